@@ -1,0 +1,5 @@
+"""Test oracle (test infrastructure only): plain FP64 CPU reference of the hot path.
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg import this package.
+"""
+from .core import *  # noqa: F401,F403

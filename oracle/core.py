@@ -1,0 +1,464 @@
+"""Test oracle for the chi^2 forward-modelling hot path (TEST INFRASTRUCTURE ONLY).
+
+A plain, slow, FP64 CPU implementation of what the HIP path computes, written from the
+paper's definitions.  Only the test suite, the smoke check and the CPU-baseline leg of
+the benchmark may import it; the product path never does.  It shares no code with the
+HIP library: it reads the same plain-dict workload spec and the same FP32-rounded
+arrays, promoted to FP64.
+
+What it computes, with the passage each step follows (section numbers of the paper):
+
+* Sersic profile with elliptical isophotes (the "sersic galaxy model" of §2.1.1;
+  parameters x, y, q, PA, n, Re, Ie as listed in §3.5, units of App. C):
+  I(R) = Ie exp(-b_n ((R/Re)^(1/n) - 1)), R = sqrt(x'^2 + (y'/q)^2), with b_n the
+  root of gamma(2n, b_n) = Gamma(2n)/2 (regularised P(2n, b_n) = 1/2).
+* Pixel integration (§2.1.2): the pixel value is the pixel area times the weighted
+  mean of the profile over s x s sub-pixel nodes (uniform midpoints, or the product
+  Gauss-Legendre rule the paper uses for its second pass); optionally s x s nodes only
+  where the pixel centre lies within k Re and the pixel centre alone elsewhere
+  (the paper's first-pass midpoint).
+* Point source (§2.1.1 "psf star model": a PSF map shifted by bilinear interpolation),
+  written as a bilinear splat of the flux onto the four surrounding pixels before the
+  convolution, which gives the same image.
+* Composite model (§2.1, §2.2): the sum of all components on the pre-convolution
+  ("extended") grid, then a true 2-D convolution with the PSF stamp (§2.1.3, direct
+  mode), then a flat sky per image.
+* Likelihood (§2.2, Eq. likelihood and Eq. chi2): chi2 = sum_i w_i (d_i - m_i)^2 with
+  w = 1/sigma^2.  The paper's Eq. (chi2) carries a factor 1/2 (it is -log L); this
+  oracle reports the conventional sum without it.
+* Derivatives (§2.3): the exact Jacobian dm/dtheta by the chain rule, J^T W J, J^T W r
+  and the gradient d chi2/d theta = -2 J^T W r.
+* Levenberg-Marquardt (§2.5): damped normal equations (A + lambda D) h = J^T W r with
+  Marquardt scaling D = diag(A), solved by Cholesky; a failed factorisation raises
+  lambda and retries, so the step never meets a singular matrix; the gain ratio decides
+  acceptance (Gavin's "update 1" form).  The constants are pinned in this module.
+
+Every sub-problem (one contiguous range of theta) is independent: its chi^2, Jacobian
+and LM run only over its own images.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Sequence
+
+import numpy as np
+import scipy.special
+
+SERSIC, POINT = 0, 1
+RULE_MIDPOINT, RULE_GAUSS_LEGENDRE = 0, 1
+MODE_UNIFORM, MODE_WITHIN_K_RE = 0, 1
+
+R_MIN = 1e-6                 # floor on the elliptical radius (cusp of n > 1 profiles)
+LN10 = math.log(10.0)
+
+# Levenberg-Marquardt constants (§2.5; the paper gives none, these are the readings)
+LM_LAMBDA0 = 1e-2
+LM_UP = 11.0
+LM_DOWN = 9.0
+LM_EPS4 = 0.1
+LM_LAMBDA_MIN = 1e-9
+LM_LAMBDA_MAX = 1e9
+LM_ATTEMPTS = 4              # Cholesky attempts per iteration before the step is dropped
+LM_DAMP_FLOOR = 1e-12        # D_kk = max(A_kk, floor * max_k A_kk)
+
+# parameter domain; a trial step outside it is rejected
+Q_MIN, Q_MAX = 0.01, 1.0
+N_MIN, N_MAX = 0.36, 10.0
+RE_MIN, RE_MAX = 0.01, 1e4
+
+
+# ----------------------------------------------------------------------------- b_n
+def sersic_b(n: float) -> float:
+    """b_n solving P(2n, b_n) = 1/2 (half the light inside Re)."""
+    return float(scipy.special.gammaincinv(2.0 * n, 0.5))
+
+
+def sersic_b_prime(n: float, h: float = 1e-5) -> float:
+    """db_n/dn by a central difference of the root (truncation ~h^2 b''')."""
+    return (sersic_b(n + h) - sersic_b(n - h)) / (2.0 * h)
+
+
+def sersic_total_flux(q, re, ie, n) -> float:
+    """Closed-form total flux of the elliptical Sersic profile (integral over the plane)."""
+    b = sersic_b(n)
+    return 2.0 * math.pi * q * re * re * ie * n * math.exp(b) * b ** (-2.0 * n) * math.gamma(2.0 * n)
+
+
+# --------------------------------------------------------------------------- nodes
+def nodes_1d(s: int, rule: int):
+    """1-D sub-pixel node offsets (pixel units, centred) and weights summing to 1."""
+    if rule == RULE_MIDPOINT:
+        o = (np.arange(s, dtype=np.float64) + 0.5) / s - 0.5
+        w = np.full(s, 1.0 / s)
+    else:
+        x, wl = np.polynomial.legendre.leggauss(s)
+        o, w = x / 2.0, wl / 2.0
+    return o, w
+
+
+def nodes_2d(s: int, rule: int):
+    o, w = nodes_1d(s, rule)
+    ox = np.tile(o, s)          # x varies fastest
+    oy = np.repeat(o, s)
+    ww = np.repeat(w, s) * np.tile(w, s)
+    return ox, oy, ww
+
+
+# ---------------------------------------------------------------------- components
+def local_params(comp: Dict, theta: np.ndarray) -> List[float]:
+    return [float(theta[p]) if p >= 0 else float(f) for p, f in zip(comp["par"], comp["fixed"])]
+
+
+def _affine(im):
+    a = np.asarray(im["affine"], dtype=np.float64)
+    return a
+
+
+def _sky_coords(a, x, y):
+    return a[0] + a[1] * x + a[2] * y, a[3] + a[4] * x + a[5] * y
+
+
+def sersic_profile(ux, uy, prm, b, with_grad=False, bp=0.0):
+    """Profile (and its 7 parameter derivatives) at sky-frame points (ux, uy)."""
+    x0, y0, q, pa, n, re, lie = prm
+    cs, sn = math.cos(pa), math.sin(pa)
+    dx, dy = ux - x0, uy - y0
+    xp = dx * cs + dy * sn
+    yp = -dx * sn + dy * cs
+    R_raw = np.sqrt(xp * xp + (yp / q) ** 2)
+    floored = R_raw < R_MIN
+    R = np.where(floored, R_MIN, R_raw)
+    ie = 10.0 ** lie
+    t = (R / re) ** (1.0 / n)
+    I = ie * np.exp(-b * (t - 1.0))
+    if not with_grad:
+        return I
+    dIdR = -I * b * t / (n * R)
+    inv = np.where(floored, 0.0, 1.0 / R)
+    dRdxp = xp * inv
+    dRdyp = yp / (q * q) * inv
+    g = np.empty((7,) + np.shape(I))
+    # x0: dx'/dx0 = -cos, dy'/dx0 = +sin ; y0: dx'/dy0 = -sin, dy'/dy0 = -cos
+    g[0] = dIdR * (-cs * dRdxp + sn * dRdyp)
+    g[1] = dIdR * (-sn * dRdxp - cs * dRdyp)
+    g[2] = dIdR * (-(yp * yp) / (q ** 3) * inv)
+    g[3] = dIdR * (xp * yp * (1.0 - 1.0 / (q * q)) * inv)
+    g[4] = I * (-bp * (t - 1.0) + b * t * np.log(R / re) / (n * n))
+    g[5] = I * b * t / (n * re)
+    g[6] = I * LN10
+    return I, g
+
+
+def _box_grid(box):
+    y0, x0, y1, x1 = box
+    yy, xx = np.meshgrid(np.arange(y0, y1, dtype=np.float64),
+                         np.arange(x0, x1, dtype=np.float64), indexing="ij")
+    return yy, xx
+
+
+def sersic_pixels(im, comp, prm, sampling, with_grad=False):
+    """Pixel-integrated Sersic (area x weighted node mean) over the component window;
+    returns the value on the window and, if asked, the 7 derivative images."""
+    a = _affine(im)
+    area = abs(a[1] * a[5] - a[2] * a[4])
+    n = prm[4]
+    b = sersic_b(n)
+    bp = sersic_b_prime(n) if with_grad else 0.0
+    yy, xx = _box_grid(comp["box"])
+    s, rule, mode = sampling["s"], sampling["rule"], sampling["mode"]
+    ox, oy, ww = nodes_2d(s, rule)
+    val = np.zeros_like(xx)
+    grad = np.zeros((7,) + xx.shape) if with_grad else None
+    for kx, ky, kw in zip(ox, oy, ww):
+        ux, uy = _sky_coords(a, xx + kx, yy + ky)
+        r = sersic_profile(ux, uy, prm, b, with_grad, bp)
+        if with_grad:
+            val += kw * r[0]
+            grad += kw * r[1]
+        else:
+            val += kw * r
+    if mode == MODE_WITHIN_K_RE:
+        # the centre alone outside k Re (pixel-centre elliptical radius, strict <)
+        ux, uy = _sky_coords(a, xx, yy)
+        x0, y0, q, pa = prm[0], prm[1], prm[2], prm[3]
+        dx, dy = ux - x0, uy - y0
+        xp = dx * math.cos(pa) + dy * math.sin(pa)
+        yp = -dx * math.sin(pa) + dy * math.cos(pa)
+        inside = np.sqrt(xp * xp + (yp / q) ** 2) < sampling["k"] * prm[5]
+        r = sersic_profile(ux, uy, prm, b, with_grad, bp)
+        if with_grad:
+            val = np.where(inside, val, r[0])
+            grad = np.where(inside[None], grad, r[1])
+        else:
+            val = np.where(inside, val, r)
+    val *= area
+    if with_grad:
+        grad *= area
+        return val, grad
+    return val
+
+
+def point_pixels(im, comp, prm, with_grad=False):
+    """Bilinear splat of a point source of flux 10^lf at sky position (x, y)."""
+    a = _affine(im)
+    A = np.array([[a[1], a[2]], [a[4], a[5]]])
+    px, py = np.linalg.solve(A, np.array([prm[0] - a[0], prm[1] - a[3]]))
+    yy, xx = _box_grid(comp["box"])
+    wgt = np.maximum(0.0, 1.0 - np.abs(xx - px)) * np.maximum(0.0, 1.0 - np.abs(yy - py))
+    F = 10.0 ** prm[2]
+    val = F * wgt
+    if with_grad:
+        g = np.zeros((7,) + xx.shape)
+        g[2] = LN10 * val
+        return val, g
+    return val
+
+
+def comp_pixels(spec, comp, theta, with_grad=False):
+    im = spec["images"][comp["image"]]
+    prm = local_params(comp, theta)
+    if comp["type"] == SERSIC:
+        return sersic_pixels(im, comp, prm, spec["sampling"], with_grad)
+    return point_pixels(im, comp, prm, with_grad)
+
+
+# ------------------------------------------------------------------- image model
+def psf_half(im) -> int:
+    return (np.asarray(im["psf"]).shape[0] - 1) // 2
+
+
+def render_ext(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
+    """Sum of all components of image k on its extended grid [-c, H+c) x [-c, W+c)."""
+    im = spec["images"][k]
+    c = psf_half(im)
+    S = np.zeros((im["H"] + 2 * c, im["W"] + 2 * c))
+    for comp in spec["comps"]:
+        if comp["image"] != k:
+            continue
+        y0, x0, y1, x1 = comp["box"]
+        if y1 <= y0 or x1 <= x0:
+            continue
+        S[y0 + c:y1 + c, x0 + c:x1 + c] += comp_pixels(spec, comp, theta)
+    return S
+
+
+def convolve_valid(S_ext: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """True 2-D convolution sampled on the image: M[i,j] = sum_uv K[c+u,c+v] S[i-u,j-v],
+    S given on the extended grid (index offset c), direct shift-and-add in FP64."""
+    K = np.asarray(K, dtype=np.float64)
+    P = K.shape[0]
+    c = (P - 1) // 2
+    H, W = S_ext.shape[0] - 2 * c, S_ext.shape[1] - 2 * c
+    M = np.zeros((H, W))
+    for U in range(P):
+        for V in range(P):
+            # S[i-u, j-v] with u = U-c lives at extended index i + c - u = i + 2c - U
+            M += K[U, V] * S_ext[2 * c - U:2 * c - U + H, 2 * c - V:2 * c - V + W]
+    return M
+
+
+def sky_value(im, theta) -> float:
+    return float(theta[im["sky_par"]]) if im["sky_par"] >= 0 else float(im["sky_fixed"])
+
+
+def model_image(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
+    """Convolved model of image k plus its flat sky (the sky is not convolved)."""
+    im = spec["images"][k]
+    return convolve_valid(render_ext(spec, theta, k), im["psf"]) + sky_value(im, theta)
+
+
+def images_of_sub(spec: Dict, sub: int) -> List[int]:
+    return [k for k, im in enumerate(spec["images"]) if im["sub"] == sub]
+
+
+def chi2_images(spec, theta, data, weight, ks: Sequence[int]) -> float:
+    """sum_i w_i (d_i - m_i)^2 over the pixels of images ks (Eq. chi2 without the 1/2)."""
+    tot = 0.0
+    for k in ks:
+        m = model_image(spec, theta, k)
+        r = np.asarray(data[k], dtype=np.float64) - m
+        tot += float(np.sum(np.asarray(weight[k], dtype=np.float64) * r * r))
+    return tot
+
+
+def chi2(spec, theta, data, weight) -> np.ndarray:
+    """chi^2 of every sub-problem."""
+    return np.array([chi2_images(spec, theta, data, weight, images_of_sub(spec, s))
+                     for s in range(len(spec["subs"]))])
+
+
+# ----------------------------------------------------------------------- Jacobian
+def jacobian_image(spec, theta, k, cols: Sequence[int] | None = None) -> np.ndarray:
+    """dm/dtheta on image k, shape (H*W, n_par) (or only the listed columns):
+    each column is the PSF convolution of the derivative of the pre-convolution image;
+    the sky column is 1; tied parameters sum their contributions."""
+    im = spec["images"][k]
+    c = psf_half(im)
+    H, W = im["H"], im["W"]
+    n_par = spec["n_par"]
+    want = set(range(n_par)) if cols is None else set(cols)
+    dS = {}
+    for comp in spec["comps"]:
+        if comp["image"] != k:
+            continue
+        y0, x0, y1, x1 = comp["box"]
+        if y1 <= y0 or x1 <= x0:
+            continue
+        if not any(p >= 0 and p in want for p in comp["par"]):
+            continue
+        _, g = comp_pixels(spec, comp, theta, with_grad=True)
+        for loc, p in enumerate(comp["par"]):
+            if p < 0 or p not in want:
+                continue
+            if p not in dS:
+                dS[p] = np.zeros((H + 2 * c, W + 2 * c))
+            dS[p][y0 + c:y1 + c, x0 + c:x1 + c] += g[loc]
+    out_cols = list(range(n_par)) if cols is None else list(cols)
+    J = np.zeros((H * W, len(out_cols)))
+    for ci, p in enumerate(out_cols):
+        if p in dS:
+            J[:, ci] = convolve_valid(dS[p], im["psf"]).ravel()
+        if im["sky_par"] == p:
+            J[:, ci] += 1.0
+    return J
+
+
+def jacobian(spec, theta, images: Sequence[int] | None = None,
+             cols: Sequence[int] | None = None) -> np.ndarray:
+    """Dense Jacobian, rows = pixels of the listed images concatenated in image order."""
+    ks = range(len(spec["images"])) if images is None else images
+    return np.concatenate([jacobian_image(spec, theta, k, cols) for k in ks], axis=0)
+
+
+def residual(spec, theta, data, weight, ks):
+    r = np.concatenate([(np.asarray(data[k], np.float64) - model_image(spec, theta, k)).ravel()
+                        for k in ks])
+    w = np.concatenate([np.asarray(weight[k], np.float64).ravel() for k in ks])
+    return r, w
+
+
+def jtwj(spec, theta, data, weight, sub: int = 0):
+    """(J^T W J, J^T W r, chi2) of one sub-problem over its own parameter range."""
+    p0, npar = spec["subs"][sub]
+    ks = images_of_sub(spec, sub)
+    cols = list(range(p0, p0 + npar))
+    J = jacobian(spec, theta, ks, cols)
+    r, w = residual(spec, theta, data, weight, ks)
+    A = J.T @ (w[:, None] * J)
+    g = J.T @ (w * r)
+    return A, g, float(np.sum(w * r * r))
+
+
+def chi2_grad(spec, theta, data, weight) -> np.ndarray:
+    """d chi2 / d theta = -2 J^T W r, from the explicit Jacobian of every sub-problem."""
+    grad = np.zeros(spec["n_par"])
+    for s, (p0, npar) in enumerate(spec["subs"]):
+        _, g, _ = jtwj(spec, theta, data, weight, s)
+        grad[p0:p0 + npar] = -2.0 * g
+    return grad
+
+
+# ------------------------------------------------------------ Levenberg-Marquardt
+def in_domain(spec, theta, sub: int) -> bool:
+    for comp in spec["comps"]:
+        if comp["type"] != SERSIC or spec["images"][comp["image"]]["sub"] != sub:
+            continue
+        x0, y0, q, pa, n, re, lie = local_params(comp, theta)
+        vals = (x0, y0, q, pa, n, re, lie)
+        if not all(math.isfinite(v) for v in vals):
+            return False
+        if not (Q_MIN <= q <= Q_MAX and N_MIN <= n <= N_MAX and RE_MIN <= re <= RE_MAX):
+            return False
+    return True
+
+
+def cholesky_or_none(M: np.ndarray):
+    """Lower Cholesky factor, or None when a pivot is not positive (or not finite)."""
+    n = M.shape[0]
+    L = np.zeros_like(M)
+    for j in range(n):
+        d = M[j, j] - L[j, :j] @ L[j, :j]
+        if not (d > 0.0) or not math.isfinite(d):
+            return None
+        L[j, j] = math.sqrt(d)
+        L[j + 1:, j] = (M[j + 1:, j] - L[j + 1:, :j] @ L[j, :j]) / L[j, j]
+    return L
+
+
+def lm_fit_sub(spec, theta0, data, weight, sub: int, n_iter: int):
+    """n_iter LM iterations on one sub-problem; returns (theta, history).
+
+    Per iteration: if the last step was accepted (or at the start) form chi2, A = J^T W J,
+    g = J^T W r at theta; try Cholesky of A + lambda D (D = diag(A) floored), raising
+    lambda by LM_UP after each failure (LM_ATTEMPTS tries); solve for h; reject an
+    out-of-domain trial; otherwise rho = (chi2 - chi2(theta + h)) / h^T (lambda D h + g);
+    accept when rho > LM_EPS4 (lambda /= LM_DOWN), else lambda *= LM_UP; lambda is
+    kept within [LM_LAMBDA_MIN, LM_LAMBDA_MAX]."""
+    theta = np.array(theta0, dtype=np.float64)
+    p0, npar = spec["subs"][sub]
+    ks = images_of_sub(spec, sub)
+    lam = LM_LAMBDA0
+    need = True
+    hist = []
+    A = g = None
+    c2 = None
+    for it in range(n_iter):
+        if need:
+            A, g, c2 = jtwj(spec, theta, data, weight, sub)
+            need = False
+        diagA = np.diag(A).copy()
+        D = np.maximum(diagA, LM_DAMP_FLOOR * np.max(diagA))
+        L = None
+        for attempt in range(LM_ATTEMPTS):
+            L = cholesky_or_none(A + lam * np.diag(D))
+            if L is not None:
+                break
+            lam = min(lam * LM_UP, LM_LAMBDA_MAX)
+        rec = dict(it=it, chi2=c2, lam=lam, accepted=False, chi2_trial=None, rho=None)
+        if L is None:
+            hist.append(rec)
+            continue
+        y = np.linalg.solve(L, g) if npar > 0 else g
+        h = np.linalg.solve(L.T, y)
+        trial = theta.copy()
+        trial[p0:p0 + npar] += h
+        pred = float(h @ (lam * D * h + g))
+        if in_domain(spec, trial, sub):
+            c2t = chi2_images(spec, trial, data, weight, ks)
+            rho = (c2 - c2t) / pred if pred != 0.0 else float("nan")
+        else:
+            c2t, rho = float("inf"), -float("inf")
+        rec.update(chi2_trial=c2t, rho=rho, pred=pred)
+        if rho > LM_EPS4:
+            theta = trial
+            c2 = c2t
+            lam = max(lam / LM_DOWN, LM_LAMBDA_MIN)
+            need = True
+            rec["accepted"] = True
+        else:
+            lam = min(lam * LM_UP, LM_LAMBDA_MAX)
+        hist.append(rec)
+    return theta, hist
+
+
+def lm_fit(spec, theta0, data, weight, n_iter: int, subs: Sequence[int] | None = None):
+    """Independent LM fits of the listed sub-problems (all by default)."""
+    theta = np.array(theta0, dtype=np.float64)
+    hists = {}
+    for s in (range(len(spec["subs"])) if subs is None else subs):
+        p0, npar = spec["subs"][s]
+        t, h = lm_fit_sub(spec, theta, data, weight, s, n_iter)
+        theta[p0:p0 + npar] = t[p0:p0 + npar]
+        hists[s] = h
+    return theta, hists
+
+
+def wrap_pa(spec, theta):
+    """Position angles reduced to [0, pi) (output convention only)."""
+    t = np.array(theta, dtype=np.float64)
+    for comp in spec["comps"]:
+        if comp["type"] == SERSIC and comp["par"][3] >= 0:
+            t[comp["par"][3]] = math.fmod(t[comp["par"][3]], math.pi)
+            if t[comp["par"][3]] < 0:
+                t[comp["par"][3]] += math.pi
+    return t
