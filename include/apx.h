@@ -1,0 +1,241 @@
+/*
+ * apx.h — C ABI of the MI355X (gfx950) chi^2 forward-modelling library.
+ *
+ * The library renders images made of elliptical Sersic profiles, point sources and a
+ * flat sky per image, integrates them over sub-pixel nodes, convolves them with a PSF,
+ * and fits them by Levenberg-Marquardt.  It implements the hot path of image
+ * modelling described in "AstroPhot: Fitting Everything Everywhere All at Once in
+ * Astronomical Images" (Stone et al. 2023):
+ *   - composite model, a sum of windowed components (§2.1, §2.1.1, §2.4 windows);
+ *   - sub-pixel integration (§2.1.2) and direct-mode PSF convolution (§2.1.3);
+ *   - chi^2 of data, model and inverse variance (§2.2, Eq. chi2);
+ *   - exact derivatives (§2.3), Levenberg-Marquardt with damped Cholesky (§2.5);
+ *   - many small fits batched together (§3.2), joint multi-image fits with shared
+ *     parameters and per-image pixel->sky maps (§3.3).
+ *
+ * Conventions (identical to the Python spec that the binding marshals):
+ *   - Pixel (i, j) of an H x W image has its centre at x = j, y = i.  Arrays are
+ *     row-major.  Data, weight and model arrays of all images are concatenated in
+ *     image order into one flat FP32 buffer ("pixel buffer", n_pix elements).
+ *   - The PSF of image k is a P x P FP32 stamp (P odd, 1 <= P <= 63), used as given
+ *     (callers normalise it); stamps are concatenated in image order.  The model is
+ *     the true convolution M[i,j] = sum_{u,v} K[c+u][c+v] S[i-u][j-v], c = (P-1)/2,
+ *     of the pre-convolution image S defined on the extended grid
+ *     [-c, H+c) x [-c, W+c), plus the image's flat sky (not convolved).
+ *   - affine[6] maps pixel to sky coordinates:
+ *       u_x = a0 + a1 x + a2 y,  u_y = a3 + a4 x + a5 y;  pixel area = |a1 a5 - a2 a4|.
+ *   - A Sersic component has local parameters (x0, y0, q, PA, n, Re, log10 Ie), centre
+ *     in the sky frame, PA in radians counter-clockwise from +x;
+ *     I(R) = Ie exp(-b_n ((R/Re)^(1/n) - 1)), R = sqrt(x'^2 + (y'/q)^2) floored at 1e-6,
+ *     gamma(2n, b_n) = Gamma(2n)/2.  A pixel holds area * sum_k w_k I(node_k).
+ *   - A point source has local parameters (x, y, log10 F) in the sky frame; its flux is
+ *     splatted bilinearly onto the four surrounding pixel centres before convolution
+ *     (the "psf star model", bilinear PSF interpolation).  Only log10 F may be free.
+ *   - par[k] is the theta index of local parameter k, or -1 (value taken from
+ *     fixed[k]).  Indices may repeat across components (tied parameters, whose
+ *     derivatives add).  Every sub-problem owns one contiguous theta range
+ *     (sub_par[2s], sub_par[2s+1]) and every parameter of its images lies inside it.
+ *   - chi^2 = sum_i w_i (d_i - m_i)^2 (the paper's Eq. chi2 is half of this plus a
+ *     constant); w = 1/sigma^2, w = 0 masks a pixel.
+ *
+ * Precision: theta, chi^2, J^T W J, J^T W r, gradients and LM state are FP64.  Images,
+ * PSFs, weights, models and Jacobian entries are stored in FP32.  The Jacobian path
+ * (derivative sampling, its convolutions) and the adjoint run in FP32 with FP64
+ * pixel->centre offsets; the objective path (model for chi^2, residual and LM trials)
+ * runs in FP64 unless APX_OBJECTIVE_FP32 is chosen.  Every reduction accumulates in
+ * FP64 in a fixed order (results are bitwise reproducible).
+ *
+ * Ownership: every pointer argument of a hot-path call is a caller-owned DEVICE
+ * pointer, except where marked "host".  The library copies descriptors at
+ * apx_problem_create, borrows the PSF pointer for the life of the problem, and keeps
+ * its scratch in one caller-provided device workspace (apx_problem_bind_workspace).
+ * After binding, hot-path calls allocate nothing and do not synchronise the host;
+ * they are enqueued on the context's stream.
+ *
+ * Errors: every call returns apx_status (0 = APX_OK).  Host-side validation failures
+ * return APX_E_INVALID / APX_E_UNSUPPORTED / APX_E_WORKSPACE before anything is
+ * enqueued; HIP runtime failures return APX_E_HIP.  apx_last_error() gives a message.
+ * Conditions found on the device (parameters outside the model's domain, non-finite
+ * values) set a sticky per-problem flag read by apx_problem_check(), which
+ * synchronises the stream.  Nothing throws across the ABI.
+ */
+#ifndef APX_H
+#define APX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t apx_status;
+
+#define APX_OK              0
+#define APX_E_INVALID      (-1)   /* bad descriptor, size, index or null pointer     */
+#define APX_E_HIP          (-2)   /* HIP runtime error                               */
+#define APX_E_NONFINITE    (-3)   /* NaN/Inf met on the device                       */
+#define APX_E_WORKSPACE    (-4)   /* no workspace bound, or too small                */
+#define APX_E_UNSUPPORTED  (-5)   /* e.g. P > 63, a free point-source position       */
+#define APX_E_DOMAIN       (-6)   /* theta outside the model domain (render/chi2)    */
+
+#define APX_SERSIC 0
+#define APX_POINT  1
+
+#define APX_RULE_MIDPOINT        0   /* offsets (k+1/2)/s - 1/2, weights 1/s^2       */
+#define APX_RULE_GAUSS_LEGENDRE  1   /* s-point Gauss-Legendre per axis (§2.1.2)     */
+
+#define APX_MODE_UNIFORM     0       /* s x s nodes in every pixel                   */
+#define APX_MODE_WITHIN_K_RE 1       /* s x s nodes where the pixel-centre R < k Re,
+                                        the pixel centre alone elsewhere (§2.1.2)     */
+
+/* Precision of the objective path (render -> convolve -> chi^2 / residual).  The
+ * Jacobian path (derivative images, their convolutions, J^T W J inputs) and the adjoint
+ * contraction always run in FP32 with FP64 accumulation. */
+#define APX_OBJECTIVE_FP64   0       /* default: FP64 profiles, convolution and chi^2;
+                                        the LM gain ratio resolves chi^2 changes far
+                                        below FP32 rounding (parameter rtol 1e-6)      */
+#define APX_OBJECTIVE_FP32   1       /* FP32 profiles and convolution (fastest render) */
+
+#define APX_MAX_PSF 63
+
+/* LM constants (§2.5 gives the method, not the constants; these are fixed here). */
+#define APX_LM_LAMBDA0     1e-2
+#define APX_LM_UP          11.0
+#define APX_LM_DOWN        9.0
+#define APX_LM_EPS4        0.1
+#define APX_LM_LAMBDA_MIN  1e-9
+#define APX_LM_LAMBDA_MAX  1e9
+#define APX_LM_ATTEMPTS    4      /* Cholesky tries per iteration (lambda *= UP between) */
+#define APX_LM_DAMP_FLOOR  1e-12  /* D_kk = max(A_kk, floor * max A_kk)                */
+
+typedef struct apx_image_desc {
+    int32_t H, W;          /* output grid                                        */
+    int32_t P;             /* PSF side, odd, 1..63                               */
+    int32_t sub;           /* sub-problem this image belongs to                  */
+    int32_t sky_par;       /* theta index of the flat sky, -1 = fixed            */
+    int32_t reserved;
+    double  sky_fixed;     /* sky value when sky_par == -1                       */
+    double  affine[6];     /* pixel -> sky map (see above)                       */
+} apx_image_desc;
+
+typedef struct apx_comp_desc {
+    int32_t type;          /* APX_SERSIC or APX_POINT                            */
+    int32_t image;         /* image index                                        */
+    int32_t box[4];        /* window (y0, x0, y1, x1), half-open, extended-grid
+                              coordinates of its image; clipped by the library     */
+    int32_t par[7];        /* theta indices of the local parameters, -1 = fixed  */
+    int32_t reserved;
+    double  fixed[7];      /* values of fixed local parameters                   */
+} apx_comp_desc;
+
+typedef struct apx_problem_desc {
+    int32_t n_images, n_comps, n_par, n_sub;
+    const apx_image_desc* images;   /* host, [n_images]                            */
+    const apx_comp_desc*  comps;    /* host, [n_comps]                             */
+    const int32_t*        sub_par;  /* host, [2*n_sub]: first theta index, count   */
+    const float*          psf;      /* device, concatenated P*P stamps (borrowed)  */
+    int32_t s;                      /* nodes per axis, 1..8                        */
+    int32_t rule;                   /* APX_RULE_*                                  */
+    int32_t mode;                   /* APX_MODE_*                                  */
+    int32_t objective;              /* APX_OBJECTIVE_* (precision of the model used
+                                       for chi^2, residuals and LM trials)          */
+    double  k_re;                   /* k of APX_MODE_WITHIN_K_RE                   */
+} apx_problem_desc;
+
+/* Per-sub-problem LM state, device memory, [n_sub] entries (apx_lm_init fills it). */
+typedef struct apx_lm_state {
+    double  lambda;        /* current damping                                     */
+    double  chi2;          /* chi^2 at the current theta                          */
+    double  chi2_trial;    /* chi^2 of the last trial (inf if out of domain)      */
+    double  pred;          /* predicted decrease h^T (lambda D h + g) of the trial */
+    double  rho;           /* gain ratio of the last trial                        */
+    int32_t need_jac;      /* 1: J^T W J must be formed at theta before the solve */
+    int32_t accepted;      /* last trial accepted                                 */
+    int32_t n_accept, n_reject;
+    int32_t n_chol_retry;  /* Cholesky failures so far (each raised lambda)       */
+    int32_t status;        /* 0, or APX_E_* found on the device                   */
+} apx_lm_state;
+
+typedef struct apx_ctx apx_ctx;
+typedef struct apx_problem apx_problem;
+
+/* --------------------------------------------------------------- lifecycle ---- */
+const char* apx_version(void);
+const char* apx_status_string(apx_status s);
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL = the
+ * default stream).  Errors: APX_E_INVALID (null out), APX_E_HIP. */
+apx_status apx_ctx_create(int device, void* hip_stream, apx_ctx** out);
+apx_status apx_ctx_set_stream(apx_ctx* ctx, void* hip_stream);
+apx_status apx_ctx_destroy(apx_ctx* ctx);
+const char* apx_last_error(const apx_ctx* ctx);
+
+/* Validate and copy the descriptor, build the launch plan (tiles, component lists,
+ * Jacobian groups, pair lists).  Host-only; nothing is enqueued.  Errors:
+ * APX_E_INVALID (inconsistent descriptor), APX_E_UNSUPPORTED. */
+apx_status apx_problem_create(apx_ctx* ctx, const apx_problem_desc* desc, apx_problem** out);
+
+/* Bytes of device workspace the problem needs (256-byte aligned base required). */
+apx_status apx_problem_workspace_bytes(const apx_problem* p, uint64_t* bytes);
+
+/* Hand the problem its workspace (caller-owned device memory, >= the queried size)
+ * and upload the plan into it (asynchronously on the context stream).  Errors:
+ * APX_E_WORKSPACE (null / too small / misaligned), APX_E_HIP. */
+apx_status apx_problem_bind_workspace(apx_problem* p, void* dev, uint64_t bytes);
+
+/* Sizes: total output pixels, total extended-grid pixels, stored Jacobian entries. */
+apx_status apx_problem_sizes(const apx_problem* p, int64_t* n_pix, int64_t* n_ext, int64_t* n_jac);
+
+/* Synchronise the stream and return the sticky device flag (APX_OK, APX_E_DOMAIN,
+ * APX_E_NONFINITE), then clear it. */
+apx_status apx_problem_check(apx_problem* p);
+apx_status apx_problem_destroy(apx_problem* p);
+
+/* ------------------------------------------------------------------ hot path ---- */
+/* model[n_pix] = PSF (x) sum of components + sky, for all images (§2.1, §2.1.2-3).
+ * theta: device [n_par] FP64.  Out-of-domain theta -> APX_E_DOMAIN via check(). */
+apx_status apx_render(apx_problem* p, const double* theta, float* model);
+
+/* chi2[n_sub] = sum w (d - m)^2 per sub-problem (§2.2, Eq. chi2 without the 1/2).
+ * data, weight: device [n_pix] FP32.  chi2: device FP64. */
+apx_status apx_chi2(apx_problem* p, const double* theta, const float* data,
+                    const float* weight, double* chi2);
+
+/* Dense Jacobian dm/dtheta (§2.3): J[k * ldJ + i] for theta index k, pixel i
+ * (ldJ >= n_pix), FP32, every entry written (zeros outside supports). */
+apx_status apx_jacobian(apx_problem* p, const double* theta, float* J, int64_t ldJ);
+
+/* Per sub-problem s (theta range [p0, p0+n)): JtWJ block n x n row-major at offset
+ * sum_{t<s} n_t^2, JtWr[p0 + k], chi2[s] (§2.5 normal equations).  FP64, device. */
+apx_status apx_jtwj(apx_problem* p, const double* theta, const float* data,
+                    const float* weight, double* JtWJ, double* JtWr, double* chi2);
+
+/* d chi2 / d theta [n_par] FP64 by the adjoint (reverse) pass: correlate -2 w r with
+ * the PSF onto the extended grid, then contract with the recomputed sub-pixel
+ * derivatives (§2.3 backpropagation); also writes chi2[n_sub]. */
+apx_status apx_chi2_grad(apx_problem* p, const double* theta, const float* data,
+                         const float* weight, double* grad, double* chi2);
+
+/* Initialise the LM state of every sub-problem at theta (lambda = LM_LAMBDA0,
+ * chi2 and residual at theta). */
+apx_status apx_lm_init(apx_problem* p, const double* theta, const float* data,
+                       const float* weight, apx_lm_state* state);
+
+/* One LM iteration on every sub-problem (§2.5): form J^T W J, J^T W r if the last
+ * step was accepted; damped Cholesky with lambda retries; trial; gain ratio;
+ * accept/reject.  theta (device, in/out) and state are updated on the device; the
+ * host never waits.  Equivalent to fitting every sub-problem on its own. */
+apx_status apx_lm_step(apx_problem* p, const float* data, const float* weight,
+                       double* theta, apx_lm_state* state);
+
+/* n_iter LM iterations.  use_graph != 0 captures one iteration into a HIP graph on
+ * first use (per data/weight/theta/state pointer set) and replays it. */
+apx_status apx_lm_run(apx_problem* p, int32_t n_iter, const float* data,
+                      const float* weight, double* theta, apx_lm_state* state,
+                      int32_t use_graph);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APX_H */

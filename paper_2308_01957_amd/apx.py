@@ -1,0 +1,378 @@
+"""Python binding of the apx C ABI (include/apx.h): argument marshalling only.
+
+Every step of the hot path runs in the HIP library; PyTorch provides device memory and
+the stream.  The binding raises if libapx.so is missing or no GPU is present -- there is
+no CPU fallback.
+
+Names follow the C entry points: render, chi2, jacobian, jtwj, chi2_grad, lm_init,
+lm_step, lm_run.  ``Chi2Fn`` exposes chi^2 as a differentiable torch function whose
+backward pass is the library's adjoint gradient.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libapx.so")
+
+APX_OK, APX_E_INVALID, APX_E_HIP, APX_E_NONFINITE, APX_E_WORKSPACE, APX_E_UNSUPPORTED, APX_E_DOMAIN = \
+    0, -1, -2, -3, -4, -5, -6
+OBJECTIVE_FP64, OBJECTIVE_FP32 = 0, 1
+
+EXPORTS = [
+    "apx_version", "apx_status_string", "apx_ctx_create", "apx_ctx_set_stream", "apx_ctx_destroy",
+    "apx_last_error", "apx_problem_create", "apx_problem_workspace_bytes",
+    "apx_problem_bind_workspace", "apx_problem_sizes", "apx_problem_check", "apx_problem_destroy",
+    "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_lm_init",
+    "apx_lm_step", "apx_lm_run",
+]
+
+
+class ImageDesc(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("P", ctypes.c_int32),
+                ("sub", ctypes.c_int32), ("sky_par", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sky_fixed", ctypes.c_double), ("affine", ctypes.c_double * 6)]
+
+
+class CompDesc(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("image", ctypes.c_int32), ("box", ctypes.c_int32 * 4),
+                ("par", ctypes.c_int32 * 7), ("reserved", ctypes.c_int32),
+                ("fixed", ctypes.c_double * 7)]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("n_images", ctypes.c_int32), ("n_comps", ctypes.c_int32),
+                ("n_par", ctypes.c_int32), ("n_sub", ctypes.c_int32),
+                ("images", ctypes.POINTER(ImageDesc)), ("comps", ctypes.POINTER(CompDesc)),
+                ("sub_par", ctypes.POINTER(ctypes.c_int32)), ("psf", ctypes.c_void_p),
+                ("s", ctypes.c_int32), ("rule", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("objective", ctypes.c_int32), ("k_re", ctypes.c_double)]
+
+
+class LMState(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("chi2", ctypes.c_double),
+                ("chi2_trial", ctypes.c_double), ("pred", ctypes.c_double),
+                ("rho", ctypes.c_double), ("need_jac", ctypes.c_int32),
+                ("accepted", ctypes.c_int32), ("n_accept", ctypes.c_int32),
+                ("n_reject", ctypes.c_int32), ("n_chol_retry", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
+
+LM_STATE_BYTES = ctypes.sizeof(LMState)
+LM_STATE_DTYPE = np.dtype([("lambda", "<f8"), ("chi2", "<f8"), ("chi2_trial", "<f8"),
+                           ("pred", "<f8"), ("rho", "<f8"), ("need_jac", "<i4"),
+                           ("accepted", "<i4"), ("n_accept", "<i4"), ("n_reject", "<i4"),
+                           ("n_chol_retry", "<i4"), ("status", "<i4")])
+assert LM_STATE_DTYPE.itemsize == LM_STATE_BYTES
+
+
+class ApxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"apx status {status}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libapx.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2308_01957_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    sig = {
+        "apx_version": ([], ctypes.c_char_p),
+        "apx_status_string": ([i32], ctypes.c_char_p),
+        "apx_ctx_create": ([ctypes.c_int, vp, ctypes.POINTER(vp)], i32),
+        "apx_ctx_set_stream": ([vp, vp], i32),
+        "apx_ctx_destroy": ([vp], i32),
+        "apx_last_error": ([vp], ctypes.c_char_p),
+        "apx_problem_create": ([vp, ctypes.POINTER(ProblemDesc), ctypes.POINTER(vp)], i32),
+        "apx_problem_workspace_bytes": ([vp, ctypes.POINTER(u64)], i32),
+        "apx_problem_bind_workspace": ([vp, vp, u64], i32),
+        "apx_problem_sizes": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
+        "apx_problem_check": ([vp], i32),
+        "apx_problem_destroy": ([vp], i32),
+        "apx_render": ([vp, vp, vp], i32),
+        "apx_chi2": ([vp, vp, vp, vp, vp], i32),
+        "apx_jacobian": ([vp, vp, vp, i64], i32),
+        "apx_jtwj": ([vp, vp, vp, vp, vp, vp, vp], i32),
+        "apx_chi2_grad": ([vp, vp, vp, vp, vp, vp], i32),
+        "apx_lm_init": ([vp, vp, vp, vp, vp], i32),
+        "apx_lm_step": ([vp, vp, vp, vp, vp], i32),
+        "apx_lm_run": ([vp, i32, vp, vp, vp, vp, i32], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _LIB = lib
+    return lib
+
+
+def _descs(spec: Dict):
+    images = spec["images"]
+    comps = spec["comps"]
+    idesc = (ImageDesc * len(images))()
+    for k, im in enumerate(images):
+        d = idesc[k]
+        d.H, d.W = int(im["H"]), int(im["W"])
+        d.P = int(np.asarray(im["psf"]).shape[0])
+        d.sub = int(im["sub"])
+        d.sky_par = int(im["sky_par"])
+        d.sky_fixed = float(im["sky_fixed"])
+        for q in range(6):
+            d.affine[q] = float(im["affine"][q])
+    cdesc = (CompDesc * max(1, len(comps)))()
+    for i, c in enumerate(comps):
+        d = cdesc[i]
+        d.type = int(c["type"])
+        d.image = int(c["image"])
+        for q in range(4):
+            d.box[q] = int(c["box"][q])
+        for q in range(7):
+            d.par[q] = int(c["par"][q])
+            d.fixed[q] = float(c["fixed"][q])
+    sp = (ctypes.c_int32 * (2 * len(spec["subs"])))()
+    for s, (p0, n) in enumerate(spec["subs"]):
+        sp[2 * s], sp[2 * s + 1] = int(p0), int(n)
+    return idesc, cdesc, sp
+
+
+class Problem:
+    """A model/fit problem bound to one GPU: descriptor, workspace and stream."""
+
+    def __init__(self, spec: Dict, device: int = 0, objective: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("apx needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.lib = load_library()
+        self.spec = spec
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.n_par = int(spec["n_par"])
+        self.n_sub = len(spec["subs"])
+        self.shapes = [(int(im["H"]), int(im["W"])) for im in spec["images"]]
+        self.offsets = np.concatenate([[0], np.cumsum([h * w for h, w in self.shapes])]).astype(np.int64)
+        self.n_pix = int(self.offsets[-1])
+        psf = np.concatenate([np.ascontiguousarray(im["psf"], dtype=np.float32).ravel()
+                              for im in spec["images"]])
+        self.psf = torch.from_numpy(psf).to(self.device)
+        self._ctx = ctypes.c_void_p()
+        self._check(self.lib.apx_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream),
+                                            ctypes.byref(self._ctx)), ctx=False)
+        idesc, cdesc, sp = _descs(spec)
+        sampling = spec["sampling"]
+        desc = ProblemDesc(len(spec["images"]), len(spec["comps"]), self.n_par, self.n_sub,
+                           idesc, cdesc, sp, ctypes.c_void_p(self.psf.data_ptr()),
+                           int(sampling["s"]), int(sampling["rule"]), int(sampling["mode"]),
+                           int(objective), float(sampling.get("k", 0.0)))
+        self._keep = (idesc, cdesc, sp, desc)
+        self._prob = ctypes.c_void_p()
+        self._check(self.lib.apx_problem_create(self._ctx, ctypes.byref(desc), ctypes.byref(self._prob)))
+        nbytes = ctypes.c_uint64()
+        self._check(self.lib.apx_problem_workspace_bytes(self._prob, ctypes.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(max(256, self.workspace_bytes), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.apx_problem_bind_workspace(self._prob, ctypes.c_void_p(self.workspace.data_ptr()),
+                                                        self.workspace.numel()))
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.apx_problem_sizes(self._prob, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        self.n_ext, self.n_jac = int(b.value), int(c.value)
+        self.par_sub = np.full(self.n_par, -1, dtype=np.int64)
+        for s, (p0, n) in enumerate(spec["subs"]):
+            self.par_sub[p0:p0 + n] = s
+        self.a_offsets = np.concatenate([[0], np.cumsum([n * n for _, n in spec["subs"]])]).astype(np.int64)
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, status: int, ctx: bool = True):
+        if status != APX_OK:
+            msg = self.lib.apx_last_error(self._ctx).decode() if ctx and self._ctx else ""
+            raise ApxError(status, msg or self.lib.apx_status_string(status).decode())
+
+    def _enter(self, *tensors):
+        cur = self.torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.stream)
+
+    def _leave(self):
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def _dev(self, x, dtype):
+        t = self.torch
+        if isinstance(x, t.Tensor):
+            if x.device != self.device or x.dtype != dtype or not x.is_contiguous():
+                x = x.to(device=self.device, dtype=dtype).contiguous()
+            return x
+        return t.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=self.device)
+
+    def pixels(self, arrays: Sequence[np.ndarray]):
+        """Concatenate per-image arrays into one FP32 device pixel buffer."""
+        flat = np.concatenate([np.ascontiguousarray(a, dtype=np.float32).ravel() for a in arrays])
+        return self.torch.from_numpy(flat).to(self.device)
+
+    def split(self, flat) -> List[np.ndarray]:
+        arr = flat.detach().cpu().numpy() if hasattr(flat, "detach") else np.asarray(flat)
+        return [arr[self.offsets[k]:self.offsets[k + 1]].reshape(h, w) for k, (h, w) in enumerate(self.shapes)]
+
+    def check(self):
+        """Synchronise and raise if the device flagged an out-of-domain or non-finite input."""
+        self._check(self.lib.apx_problem_check(self._prob))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    # ----------------------------------------------------------------- hot path
+    def render(self, theta, out=None):
+        th = self._dev(theta, self.torch.float64)
+        self._enter(th)
+        with self.torch.cuda.stream(self.stream):
+            if out is None:
+                out = self.torch.empty(self.n_pix, dtype=self.torch.float32, device=self.device)
+            self._check(self.lib.apx_render(self._prob, th.data_ptr(), out.data_ptr()))
+        self._leave()
+        return out
+
+    def chi2(self, theta, data, weight, out=None):
+        th = self._dev(theta, self.torch.float64)
+        self._enter(th, data, weight)
+        with self.torch.cuda.stream(self.stream):
+            if out is None:
+                out = self.torch.empty(self.n_sub, dtype=self.torch.float64, device=self.device)
+            self._check(self.lib.apx_chi2(self._prob, th.data_ptr(), data.data_ptr(), weight.data_ptr(),
+                                          out.data_ptr()))
+        self._leave()
+        return out
+
+    def jacobian(self, theta):
+        """Dense J as a (n_par, n_pix) FP32 tensor (row k = d model / d theta_k)."""
+        th = self._dev(theta, self.torch.float64)
+        self._enter(th)
+        with self.torch.cuda.stream(self.stream):
+            J = self.torch.empty((self.n_par, self.n_pix), dtype=self.torch.float32, device=self.device)
+            self._check(self.lib.apx_jacobian(self._prob, th.data_ptr(), J.data_ptr(), self.n_pix))
+        self._leave()
+        return J
+
+    def jtwj(self, theta, data, weight):
+        """(JtWJ flat per-sub blocks, JtWr [n_par], chi2 [n_sub]), FP64 device tensors."""
+        th = self._dev(theta, self.torch.float64)
+        self._enter(th, data, weight)
+        t = self.torch
+        with t.cuda.stream(self.stream):
+            A = t.empty(int(self.a_offsets[-1]), dtype=t.float64, device=self.device)
+            g = t.empty(self.n_par, dtype=t.float64, device=self.device)
+            c2 = t.empty(self.n_sub, dtype=t.float64, device=self.device)
+            self._check(self.lib.apx_jtwj(self._prob, th.data_ptr(), data.data_ptr(), weight.data_ptr(),
+                                          A.data_ptr(), g.data_ptr(), c2.data_ptr()))
+        self._leave()
+        return A, g, c2
+
+    def block(self, A, s: int):
+        n = self.spec["subs"][s][1]
+        return A[int(self.a_offsets[s]):int(self.a_offsets[s + 1])].reshape(n, n)
+
+    def chi2_grad(self, theta, data, weight):
+        th = self._dev(theta, self.torch.float64)
+        self._enter(th, data, weight)
+        t = self.torch
+        with t.cuda.stream(self.stream):
+            g = t.empty(self.n_par, dtype=t.float64, device=self.device)
+            c2 = t.empty(self.n_sub, dtype=t.float64, device=self.device)
+            self._check(self.lib.apx_chi2_grad(self._prob, th.data_ptr(), data.data_ptr(), weight.data_ptr(),
+                                               g.data_ptr(), c2.data_ptr()))
+        self._leave()
+        return g, c2
+
+    def lm_init(self, theta, data, weight):
+        """Returns (theta device copy, state device buffer) ready for lm_step / lm_run."""
+        t = self.torch
+        th = self._dev(theta, t.float64).clone()
+        self._enter(th, data, weight)
+        with t.cuda.stream(self.stream):
+            state = t.zeros(self.n_sub * LM_STATE_BYTES, dtype=t.uint8, device=self.device)
+            self._check(self.lib.apx_lm_init(self._prob, th.data_ptr(), data.data_ptr(), weight.data_ptr(),
+                                             state.data_ptr()))
+        self._leave()
+        return th, state
+
+    def lm_step(self, data, weight, theta, state):
+        self._enter(data, weight, theta, state)
+        with self.torch.cuda.stream(self.stream):
+            self._check(self.lib.apx_lm_step(self._prob, data.data_ptr(), weight.data_ptr(), theta.data_ptr(),
+                                             state.data_ptr()))
+        self._leave()
+
+    def lm_run(self, n_iter: int, data, weight, theta, state, use_graph: bool = False):
+        self._enter(data, weight, theta, state)
+        with self.torch.cuda.stream(self.stream):
+            self._check(self.lib.apx_lm_run(self._prob, int(n_iter), data.data_ptr(), weight.data_ptr(),
+                                            theta.data_ptr(), state.data_ptr(), 1 if use_graph else 0))
+        self._leave()
+
+    def lm_state(self, state) -> np.ndarray:
+        return np.frombuffer(state.cpu().numpy().tobytes(), dtype=LM_STATE_DTYPE)
+
+    def close(self):
+        if getattr(self, "_prob", None):
+            self.stream.synchronize()
+            self.lib.apx_problem_destroy(self._prob)
+            self._prob = None
+        if getattr(self, "_ctx", None):
+            self.lib.apx_ctx_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _chi2_fn():
+    import torch
+
+    class Chi2Fn(torch.autograd.Function):
+        """chi^2 per sub-problem as a differentiable function of theta.
+
+        forward: apx_chi2.  backward: apx_chi2_grad (the adjoint pass), each sub-problem's
+        gradient scaled by the incoming gradient of its chi^2."""
+
+        @staticmethod
+        def forward(ctx, theta, problem, data, weight):
+            ctx.problem, ctx.data, ctx.weight = problem, data, weight
+            ctx.save_for_backward(theta.detach())
+            return problem.chi2(theta.detach(), data, weight).clone()
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (theta,) = ctx.saved_tensors
+            p = ctx.problem
+            g, _ = p.chi2_grad(theta, ctx.data, ctx.weight)
+            ps = torch.as_tensor(p.par_sub, device=g.device)
+            scale = torch.where(ps >= 0, grad_out.to(g.dtype)[ps.clamp(min=0)], torch.zeros_like(g))
+            return g * scale, None, None, None
+
+    return Chi2Fn
+
+
+_CHI2_FN = []
+
+
+def chi2_autograd(theta, problem: "Problem", data, weight):
+    """Differentiable chi^2 [n_sub] of theta (backward = the library's adjoint)."""
+    if not _CHI2_FN:
+        _CHI2_FN.append(_chi2_fn())
+    return _CHI2_FN[0].apply(theta, problem, data, weight)

@@ -1,0 +1,1289 @@
+// Host side of the apx C ABI: descriptor validation, launch-plan construction
+// (tiles, component lists, Jacobian groups and pair lists, ordered-reduction tables),
+// workspace layout and the launch sequences of the hot-path entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "apx_internal.h"
+
+using namespace apx;
+
+struct apx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+namespace {
+
+struct PRange { int P, begin, count; };
+
+template <class T>
+struct DevArr {
+    const std::vector<T>* host = nullptr;
+    size_t off = 0;   // byte offset in the workspace
+};
+
+struct Layout {
+    size_t total = 0;
+    size_t take(size_t bytes) {
+        size_t o = (total + 255) & ~size_t(255);
+        total = o + ((bytes + 255) & ~size_t(255));
+        return o;
+    }
+};
+
+}  // namespace
+
+struct apx_problem {
+    apx_ctx* ctx = nullptr;
+    int n_images = 0, n_comps = 0, n_par = 0, n_sub = 0;
+    int s = 3, rule = 0, mode = 0, objective = 0;
+    double k_re = 0.0;
+    const float* psf = nullptr;
+
+    std::vector<DImage> images;
+    std::vector<DComp> comps;
+    std::vector<DGroup> groups;
+    std::vector<DCol> cols;
+    std::vector<DSub> subs;
+    std::vector<int> group_comps;
+    std::vector<RTile> rtiles, gtiles;
+    std::vector<int> rtile_off, rtile_comps;
+    std::vector<ConvJob> fwd_jobs, jcol_jobs, adj_jobs;
+    std::vector<ConvItem> fwd_items, jcol_items, adj_items;
+    std::vector<PRange> fwd_ranges, jcol_ranges, adj_ranges;
+    std::vector<DPair> pairs;
+    std::vector<PairItem> pitems64, pitems16;
+    // reduction tables
+    std::vector<int> img_seg, img_idx;            // FWD items of each image
+    std::vector<int> col_seg, col_idx;            // JCOL items of each column
+    std::vector<int> gcol_seg;                    // grad partials of each column (contiguous)
+    std::vector<int> chi_seg, chi_idx;            // img_sum entries of each sub
+    std::vector<int> g_seg, g_idx, g_sub;         // J^T W r sources per theta index
+    std::vector<double> g_w;
+    std::vector<int> gr_seg, gr_idx;              // gradient sources per theta index
+    std::vector<double> gr_w;
+    std::vector<long long> a_off_csr, a_src;      // A assembly
+    std::vector<int> a_sub, a_row, a_col;
+    std::vector<int> par_sub, par_off, par_cols, par_sky_off, par_sky;
+    std::vector<int> small_subs, large_subs;
+    std::vector<int> theta_subs;                  // sub of each theta-assembly segment
+    int nmax_small = 0;
+    std::vector<float> node_o, node_w;
+    std::vector<double> node_od, node_wd;
+
+    long long n_pix = 0, n_ext = 0, n_d = 0, n_j = 0, n_pairpart = 0, n_gradpart = 0, a_total = 0;
+    long long n_psf = 0;
+
+    // workspace
+    char* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    bool bound = false;
+    Layout L;
+    std::map<std::string, size_t> off;
+    Plan plan{};
+    double* asrc = nullptr;          // [pair_part | col_sum | grad_col | img_sum]
+    long long asrc_col = 0, asrc_gcol = 0, asrc_img = 0;
+    double* chi2_sub = nullptr;      // [n_sub]
+    double* chi2_trial = nullptr;    // [n_sub]
+
+    // graph cache for apx_lm_run
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    const void* gkey[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+// ------------------------------------------------------------------------ helpers
+static apx_status fail(apx_ctx* c, apx_status s, const std::string& m) {
+    if (c) c->err = m;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess)                                                           \
+            return fail(P->ctx, APX_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+static void gauss_legendre(int s, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(s, 0.0);
+    w.assign(s, 0.0);
+    for (int i = 0; i < s; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (s + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= s; ++j) {
+                double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            double pp = s * (z * p1 - p2) / (z * z - 1.0);
+            double z1 = z;
+            z = z1 - p1 / pp;
+            if (std::fabs(z - z1) < 1e-16) {
+                // recompute derivative at the converged node
+                p1 = 1.0; p2 = 0.0;
+                for (int j = 1; j <= s; ++j) {
+                    double p3 = p2;
+                    p2 = p1;
+                    p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+                }
+                pp = s * (z * p1 - p2) / (z * z - 1.0);
+                x[i] = z;
+                w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+                break;
+            }
+        }
+    }
+    std::sort(x.begin(), x.end());
+    // weights are symmetric; re-pair after sorting
+    std::vector<double> w2(s);
+    for (int i = 0; i < s; ++i) {
+        double z = x[i], p1 = 1.0, p2 = 0.0;
+        for (int j = 1; j <= s; ++j) {
+            double p3 = p2;
+            p2 = p1;
+            p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+        }
+        double pp = s * (z * p1 - p2) / (z * z - 1.0);
+        w2[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+    w = w2;
+}
+
+static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------ plan build
+static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
+    apx_ctx* C = P->ctx;
+    P->n_images = d->n_images;
+    P->n_comps = d->n_comps;
+    P->n_par = d->n_par;
+    P->n_sub = d->n_sub;
+    P->s = d->s;
+    P->rule = d->rule;
+    P->mode = d->mode;
+    P->k_re = d->k_re;
+    P->objective = d->objective;
+    P->psf = d->psf;
+    if (d->n_images < 1 || d->n_comps < 0 || d->n_par < 0 || d->n_sub < 1)
+        return fail(C, APX_E_INVALID, "counts: need n_images >= 1, n_sub >= 1, n_comps, n_par >= 0");
+    if (!d->images || (d->n_comps > 0 && !d->comps) || !d->sub_par || !d->psf)
+        return fail(C, APX_E_INVALID, "null descriptor pointer");
+    if (d->s < 1 || d->s > MAX_NODES_1D) return fail(C, APX_E_UNSUPPORTED, "s must be in 1..8");
+    if (d->rule != APX_RULE_MIDPOINT && d->rule != APX_RULE_GAUSS_LEGENDRE)
+        return fail(C, APX_E_INVALID, "unknown node rule");
+    if (d->mode != APX_MODE_UNIFORM && d->mode != APX_MODE_WITHIN_K_RE)
+        return fail(C, APX_E_INVALID, "unknown sampling mode");
+    if (d->mode == APX_MODE_WITHIN_K_RE && !(d->k_re > 0.0))
+        return fail(C, APX_E_INVALID, "k_re must be > 0");
+    if (d->objective != APX_OBJECTIVE_FP64 && d->objective != APX_OBJECTIVE_FP32)
+        return fail(C, APX_E_INVALID, "unknown objective precision");
+
+    // nodes
+    if (d->rule == APX_RULE_MIDPOINT) {
+        for (int k = 0; k < d->s; ++k) {
+            P->node_od.push_back((k + 0.5) / d->s - 0.5);
+            P->node_wd.push_back(1.0 / d->s);
+        }
+    } else {
+        std::vector<double> x, w;
+        gauss_legendre(d->s, x, w);
+        for (int k = 0; k < d->s; ++k) {
+            P->node_od.push_back(x[k] / 2.0);
+            P->node_wd.push_back(w[k] / 2.0);
+        }
+    }
+    for (int k = 0; k < d->s; ++k) {
+        P->node_o.push_back((float)P->node_od[k]);
+        P->node_w.push_back((float)P->node_wd[k]);
+    }
+
+    // sub-problems
+    P->subs.resize(d->n_sub);
+    P->par_sub.assign(d->n_par, -1);
+    long long aoff = 0;
+    for (int s = 0; s < d->n_sub; ++s) {
+        int p0 = d->sub_par[2 * s], n = d->sub_par[2 * s + 1];
+        if (p0 < 0 || n < 0 || (long long)p0 + n > d->n_par)
+            return fail(C, APX_E_INVALID, "sub_par range out of theta");
+        for (int k = p0; k < p0 + n; ++k) {
+            if (P->par_sub[k] >= 0) return fail(C, APX_E_INVALID, "sub-problem theta ranges overlap");
+            P->par_sub[k] = s;
+        }
+        DSub sb{};
+        sb.p0 = p0;
+        sb.n = n;
+        sb.a_off = aoff;
+        sb.large = n > SMALL_N ? 1 : 0;
+        aoff += (long long)n * n;
+        P->subs[s] = sb;
+        if (sb.large) P->large_subs.push_back(s);
+        else {
+            P->small_subs.push_back(s);
+            P->nmax_small = std::max(P->nmax_small, n);
+        }
+    }
+    P->a_total = aoff;
+    auto in_sub = [&](int par, int sub) { return par >= 0 && par < d->n_par && P->par_sub[par] == sub; };
+
+    // images
+    P->images.resize(d->n_images);
+    long long pix = 0, ext = 0, psfo = 0;
+    for (int k = 0; k < d->n_images; ++k) {
+        const apx_image_desc& id = d->images[k];
+        if (id.H < 1 || id.W < 1) return fail(C, APX_E_INVALID, "image " + std::to_string(k) + ": H, W >= 1");
+        if (id.P < 1 || id.P % 2 == 0) return fail(C, APX_E_INVALID, "image " + std::to_string(k) + ": P must be odd");
+        if (id.P > APX_MAX_PSF) return fail(C, APX_E_UNSUPPORTED, "image " + std::to_string(k) + ": P > 63");
+        if (id.sub < 0 || id.sub >= d->n_sub) return fail(C, APX_E_INVALID, "image sub out of range");
+        if (id.sky_par >= 0 && !in_sub(id.sky_par, id.sub))
+            return fail(C, APX_E_INVALID, "image " + std::to_string(k) + ": sky_par outside its sub-problem");
+        if (id.sky_par < -1) return fail(C, APX_E_INVALID, "sky_par < -1");
+        DImage im{};
+        im.H = id.H;
+        im.W = id.W;
+        im.P = id.P;
+        im.c = (id.P - 1) / 2;
+        im.EH = id.H + 2 * im.c;
+        im.EW = id.W + 2 * im.c;
+        im.sub = id.sub;
+        im.sky_par = id.sky_par;
+        im.sky_fixed = id.sky_fixed;
+        im.pix_off = pix;
+        im.ext_off = ext;
+        im.psf_off = psfo;
+        for (int q = 0; q < 6; ++q) im.aff[q] = id.affine[q];
+        const double det = id.affine[1] * id.affine[5] - id.affine[2] * id.affine[4];
+        if (!std::isfinite(det) || det == 0.0) return fail(C, APX_E_INVALID, "singular affine map");
+        im.area = std::fabs(det);
+        // inverse: p = Ainv (u - t)
+        const double i11 = id.affine[5] / det, i12 = -id.affine[2] / det;
+        const double i21 = -id.affine[4] / det, i22 = id.affine[1] / det;
+        im.inv[1] = i11;
+        im.inv[2] = i12;
+        im.inv[4] = i21;
+        im.inv[5] = i22;
+        im.inv[0] = -(i11 * id.affine[0] + i12 * id.affine[3]);
+        im.inv[3] = -(i21 * id.affine[0] + i22 * id.affine[3]);
+        P->images[k] = im;
+        pix += (long long)id.H * id.W;
+        ext += (long long)im.EH * im.EW;
+        psfo += (long long)id.P * id.P;
+    }
+    P->n_pix = pix;
+    P->n_ext = ext;
+    P->n_psf = psfo;
+
+    // components
+    P->comps.resize(d->n_comps);
+    for (int i = 0; i < d->n_comps; ++i) {
+        const apx_comp_desc& cd = d->comps[i];
+        if (cd.type != APX_SERSIC && cd.type != APX_POINT) return fail(C, APX_E_INVALID, "unknown component type");
+        if (cd.image < 0 || cd.image >= d->n_images) return fail(C, APX_E_INVALID, "component image out of range");
+        const DImage& im = P->images[cd.image];
+        DComp c{};
+        c.type = cd.type;
+        c.image = cd.image;
+        c.sub = im.sub;
+        c.group = -1;
+        for (int k = 0; k < 7; ++k) {
+            c.par[k] = cd.par[k];
+            c.fixed[k] = cd.fixed[k];
+            c.col[k] = -1;
+            if (cd.par[k] < -1 || cd.par[k] >= d->n_par)
+                return fail(C, APX_E_INVALID, "component " + std::to_string(i) + ": par index out of range");
+            if (cd.par[k] >= 0 && !in_sub(cd.par[k], im.sub))
+                return fail(C, APX_E_INVALID, "component " + std::to_string(i) + ": parameter outside its sub-problem");
+            if (cd.par[k] >= 0 && cd.par[k] == im.sky_par)
+                return fail(C, APX_E_INVALID, "component parameter shares the sky index");
+            if (cd.par[k] < 0 && !std::isfinite(cd.fixed[k]) && (cd.type == APX_SERSIC || k < 3))
+                return fail(C, APX_E_INVALID, "non-finite fixed parameter");
+        }
+        if (cd.type == APX_POINT) {
+            if (cd.par[0] >= 0 || cd.par[1] >= 0)
+                return fail(C, APX_E_UNSUPPORTED, "point-source positions must be fixed");
+            for (int k = 3; k < 7; ++k)
+                if (cd.par[k] >= 0) return fail(C, APX_E_INVALID, "point source has 3 local parameters");
+        }
+        // clip the window to the extended grid
+        int y0 = std::max(cd.box[0], -im.c), x0 = std::max(cd.box[1], -im.c);
+        int y1 = std::min(cd.box[2], im.H + im.c), x1 = std::min(cd.box[3], im.W + im.c);
+        if (y1 <= y0 || x1 <= x0) { y0 = x0 = y1 = x1 = 0; }
+        c.box[0] = y0; c.box[1] = x0; c.box[2] = y1; c.box[3] = x1;
+        P->comps[i] = c;
+    }
+
+    // render tiles (extended grid) with component lists
+    {
+        std::vector<int> tile_base(d->n_images + 1, 0);
+        for (int k = 0; k < d->n_images; ++k) {
+            const DImage& im = P->images[k];
+            const int ny = ceil_div(im.EH, RT_Y), nx = ceil_div(im.EW, RT_X);
+            tile_base[k + 1] = tile_base[k] + ny * nx;
+            for (int ty = 0; ty < ny; ++ty)
+                for (int tx = 0; tx < nx; ++tx) P->rtiles.push_back(RTile{k, -im.c + ty * RT_Y, -im.c + tx * RT_X, 0});
+        }
+        const int nt = (int)P->rtiles.size();
+        std::vector<int> cnt(nt + 1, 0);
+        auto for_tiles = [&](int ci, auto&& fn) {
+            const DComp& c = P->comps[ci];
+            if (c.box[2] <= c.box[0]) return;
+            const DImage& im = P->images[c.image];
+            const int nx = ceil_div(im.EW, RT_X);
+            const int ty0 = (c.box[0] + im.c) / RT_Y, ty1 = (c.box[2] - 1 + im.c) / RT_Y;
+            const int tx0 = (c.box[1] + im.c) / RT_X, tx1 = (c.box[3] - 1 + im.c) / RT_X;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) fn(tile_base[c.image] + ty * nx + tx);
+        };
+        for (int ci = 0; ci < d->n_comps; ++ci) for_tiles(ci, [&](int t) { cnt[t + 1]++; });
+        for (int t = 0; t < nt; ++t) cnt[t + 1] += cnt[t];
+        P->rtile_off = cnt;
+        P->rtile_comps.assign(cnt[nt], 0);
+        std::vector<int> fillp(cnt.begin(), cnt.end() - 1);
+        for (int ci = 0; ci < d->n_comps; ++ci) for_tiles(ci, [&](int t) { P->rtile_comps[fillp[t]++] = ci; });
+    }
+
+    // Jacobian groups: Sersic components with a free parameter sharing image and window
+    // merge into one group; each point source with a free flux is its own group.
+    {
+        std::map<std::tuple<int, int, int, int, int>, int> key2g;
+        std::vector<std::vector<int>> gcomps;
+        for (int ci = 0; ci < d->n_comps; ++ci) {
+            DComp& c = P->comps[ci];
+            bool anyfree = false;
+            for (int k = 0; k < 7; ++k) anyfree = anyfree || c.par[k] >= 0;
+            if (!anyfree || c.box[2] <= c.box[0]) continue;
+            int g;
+            if (c.type == APX_SERSIC) {
+                auto key = std::make_tuple(c.image, c.box[0], c.box[1], c.box[2], c.box[3]);
+                auto it = key2g.find(key);
+                if (it == key2g.end()) {
+                    g = (int)gcomps.size();
+                    key2g[key] = g;
+                    gcomps.emplace_back();
+                } else g = it->second;
+            } else {
+                g = (int)gcomps.size();
+                gcomps.emplace_back();
+            }
+            gcomps[g].push_back(ci);
+            c.group = g;
+        }
+        long long doff = 0, joff = 0, gpoff = 0;
+        for (size_t g = 0; g < gcomps.size(); ++g) {
+            const DComp& c0 = P->comps[gcomps[g][0]];
+            const DImage& im = P->images[c0.image];
+            DGroup gr{};
+            gr.image = c0.image;
+            gr.type = c0.type;
+            gr.sub = im.sub;
+            gr.iy0 = c0.box[0];
+            gr.ix0 = c0.box[1];
+            gr.ih = c0.box[2] - c0.box[0];
+            gr.iw = c0.box[3] - c0.box[1];
+            const int oy0 = std::max(0, c0.box[0] - im.c), ox0 = std::max(0, c0.box[1] - im.c);
+            const int oy1 = std::min(im.H, c0.box[2] + im.c), ox1 = std::min(im.W, c0.box[3] + im.c);
+            gr.oy0 = oy0;
+            gr.ox0 = ox0;
+            gr.oh = std::max(0, oy1 - oy0);
+            gr.ow = std::max(0, ox1 - ox0);
+            gr.comp_begin = (int)P->group_comps.size();
+            gr.col_begin = (int)P->cols.size();
+            int nc = 0;
+            for (int ci : gcomps[g]) {
+                P->group_comps.push_back(ci);
+                DComp& c = P->comps[ci];
+                for (int k = 0; k < 7; ++k) {
+                    if (c.par[k] < 0) continue;
+                    c.col[k] = nc++;
+                    P->cols.push_back(DCol{(int)g, ci, k, c.par[k]});
+                }
+            }
+            gr.comp_end = (int)P->group_comps.size();
+            gr.ncols = nc;
+            gr.d_off = doff;
+            gr.j_off = joff;
+            doff += (long long)nc * gr.ih * gr.iw;
+            joff += (long long)nc * gr.oh * gr.ow;
+            gr.tile_begin = (int)P->gtiles.size();
+            const int ny = ceil_div(gr.ih, RT_Y), nx = ceil_div(gr.iw, RT_X);
+            for (int ty = 0; ty < ny; ++ty)
+                for (int tx = 0; tx < nx; ++tx) P->gtiles.push_back(RTile{(int)g, ty * RT_Y, tx * RT_X, 0});
+            gr.ntiles = ny * nx;
+            gr.gp_off = gpoff;
+            gpoff += (long long)nc * gr.ntiles;
+            P->groups.push_back(gr);
+        }
+        P->n_d = doff;
+        P->n_j = joff;
+        P->n_gradpart = gpoff;
+    }
+    const int n_cols = (int)P->cols.size();
+    const int n_groups = (int)P->groups.size();
+
+    // convolution jobs and items (sorted by PSF size: one launch per size)
+    auto add_items = [](std::vector<ConvJob>& jobs, std::vector<ConvItem>& items,
+                        std::vector<PRange>& ranges, const std::vector<int>& jobP,
+                        const std::vector<int>& nch, std::vector<int>* job_item_begin) {
+        std::vector<int> order(jobs.size());
+        for (size_t i = 0; i < jobs.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobP[a] < jobP[b]; });
+        if (job_item_begin) job_item_begin->assign(jobs.size(), 0);
+        for (int j : order) {
+            const ConvJob& jb = jobs[j];
+            const int ny = ceil_div(jb.out_h, CV_TH), nx = ceil_div(jb.out_w, CV_TW);
+            if (job_item_begin) (*job_item_begin)[j] = (int)items.size();
+            const int b = (int)items.size();
+            for (int ch = 0; ch < nch[j]; ++ch)
+                for (int ty = 0; ty < ny; ++ty)
+                    for (int tx = 0; tx < nx; ++tx) items.push_back(ConvItem{j, ch, ty, tx});
+            const int cnt = (int)items.size() - b;
+            if (cnt == 0) continue;
+            if (!ranges.empty() && ranges.back().P == jobP[j]) ranges.back().count += cnt;
+            else ranges.push_back(PRange{jobP[j], b, cnt});
+        }
+    };
+    std::vector<int> fwd_item_begin, jcol_item_begin;
+    {
+        std::vector<int> jp, nch;
+        for (int k = 0; k < d->n_images; ++k) {
+            const DImage& im = P->images[k];
+            ConvJob jb{};
+            jb.in_off = im.ext_off;
+            jb.out_off = im.pix_off;
+            jb.in_y0 = -im.c; jb.in_x0 = -im.c; jb.in_h = im.EH; jb.in_w = im.EW;
+            jb.out_y0 = 0; jb.out_x0 = 0; jb.out_h = im.H; jb.out_w = im.W;
+            jb.image = k;
+            jb.group = -1;
+            P->fwd_jobs.push_back(jb);
+            jp.push_back(im.P);
+            nch.push_back(1);
+            ConvJob ja = jb;
+            ja.in_off = 0;                   // adjoint input is staged from the residual
+            ja.in_y0 = 0; ja.in_x0 = 0; ja.in_h = im.H; ja.in_w = im.W;
+            ja.out_off = im.ext_off;
+            ja.out_y0 = -im.c; ja.out_x0 = -im.c; ja.out_h = im.EH; ja.out_w = im.EW;
+            P->adj_jobs.push_back(ja);
+        }
+        add_items(P->fwd_jobs, P->fwd_items, P->fwd_ranges, jp, nch, &fwd_item_begin);
+        add_items(P->adj_jobs, P->adj_items, P->adj_ranges, jp, nch, nullptr);
+    }
+    {
+        std::vector<int> jp, nch;
+        for (int g = 0; g < n_groups; ++g) {
+            const DGroup& gr = P->groups[g];
+            const DImage& im = P->images[gr.image];
+            ConvJob jb{};
+            jb.in_off = gr.d_off;
+            jb.in_cs = (long long)gr.ih * gr.iw;
+            jb.out_off = gr.j_off;
+            jb.out_cs = (long long)gr.oh * gr.ow;
+            jb.in_y0 = gr.iy0; jb.in_x0 = gr.ix0; jb.in_h = gr.ih; jb.in_w = gr.iw;
+            jb.out_y0 = gr.oy0; jb.out_x0 = gr.ox0; jb.out_h = gr.oh; jb.out_w = gr.ow;
+            jb.image = gr.image;
+            jb.group = g;
+            P->jcol_jobs.push_back(jb);
+            jp.push_back(im.P);
+            nch.push_back(gr.oh > 0 && gr.ow > 0 ? gr.ncols : 0);
+        }
+        add_items(P->jcol_jobs, P->jcol_items, P->jcol_ranges, jp, nch, &jcol_item_begin);
+    }
+
+    // reduction tables: FWD items per image, JCOL items per column, grad partials per column
+    {
+        P->img_seg.assign(1, 0);
+        for (int k = 0; k < d->n_images; ++k) {
+            const DImage& im = P->images[k];
+            const int n = ceil_div(im.H, CV_TH) * ceil_div(im.W, CV_TW);
+            for (int q = 0; q < n; ++q) P->img_idx.push_back(fwd_item_begin[k] + q);
+            P->img_seg.push_back((int)P->img_idx.size());
+        }
+        P->col_seg.assign(1, 0);
+        P->gcol_seg.assign(1, 0);
+        for (int g = 0; g < n_groups; ++g) {
+            const DGroup& gr = P->groups[g];
+            const int per = (gr.oh > 0 && gr.ow > 0) ? ceil_div(gr.oh, CV_TH) * ceil_div(gr.ow, CV_TW) : 0;
+            for (int ch = 0; ch < gr.ncols; ++ch) {
+                for (int q = 0; q < per; ++q) P->col_idx.push_back(jcol_item_begin[g] + ch * per + q);
+                P->col_seg.push_back((int)P->col_idx.size());
+                P->gcol_seg.push_back((int)(gr.gp_off + (long long)(ch + 1) * gr.ntiles));
+            }
+        }
+    }
+
+    // pairs of groups on one image whose output boxes intersect
+    {
+        std::vector<std::vector<int>> by_img(d->n_images);
+        for (int g = 0; g < n_groups; ++g)
+            if (P->groups[g].oh > 0 && P->groups[g].ow > 0) by_img[P->groups[g].image].push_back(g);
+        long long outoff = 0;
+        for (int k = 0; k < d->n_images; ++k) {
+            const auto& gl = by_img[k];
+            for (size_t a = 0; a < gl.size(); ++a)
+                for (size_t b = a; b < gl.size(); ++b) {
+                    const DGroup& G = P->groups[gl[a]];
+                    const DGroup& H = P->groups[gl[b]];
+                    const int y0 = std::max(G.oy0, H.oy0), x0 = std::max(G.ox0, H.ox0);
+                    const int y1 = std::min(G.oy0 + G.oh, H.oy0 + H.oh), x1 = std::min(G.ox0 + G.ow, H.ox0 + H.ow);
+                    if (y1 <= y0 || x1 <= x0) continue;
+                    DPair pr{gl[a], gl[b], k, G.sub, y0, x0, y1, x1};
+                    const int pi = (int)P->pairs.size();
+                    P->pairs.push_back(pr);
+                    const int tm = (std::min(G.ncols, H.ncols) >= 48) ? 64 : 16;
+                    const int na = ceil_div(G.ncols, tm), nb = ceil_div(H.ncols, tm);
+                    const int rows = y1 - y0, width = x1 - x0;
+                    const int kc_w = ceil_div(width, PAIR_KC) * PAIR_KC;
+                    const int rows_per = std::max(1, ceil_div(4096, kc_w));
+                    for (int ta = 0; ta < na; ++ta)
+                        for (int tb = (gl[a] == gl[b] ? ta : 0); tb < nb; ++tb)
+                            for (int r0 = 0; r0 < rows; r0 += rows_per) {
+                                PairItem it{};
+                                it.pair = pi;
+                                it.ta = ta;
+                                it.tb = tb;
+                                it.r0 = y0 + r0;
+                                it.r1 = y0 + std::min(rows, r0 + rows_per);
+                                it.out_off = outoff;
+                                outoff += (long long)tm * tm;
+                                (tm == 64 ? P->pitems64 : P->pitems16).push_back(it);
+                            }
+                }
+        }
+        P->n_pairpart = outoff;
+    }
+    P->asrc_col = P->n_pairpart;
+    P->asrc_gcol = P->asrc_col + 2LL * n_cols;
+    P->asrc_img = P->asrc_gcol + n_cols;
+
+    // A assembly: sources per upper entry (sub, a <= b) in a fixed order
+    {
+        std::vector<long long> ent_base(d->n_sub + 1, 0);
+        for (int s = 0; s < d->n_sub; ++s) {
+            const long long n = P->subs[s].n;
+            ent_base[s + 1] = ent_base[s] + n * (n + 1) / 2;
+        }
+        const long long n_ent = ent_base[d->n_sub];
+        auto ent_id = [&](int s, int a, int b) -> long long {
+            // row-major upper triangle: row a holds entries (a, a..n-1)
+            const long long n = P->subs[s].n;
+            return ent_base[s] + (long long)a * n - (long long)a * (a - 1) / 2 + (b - a);
+        };
+        std::vector<std::pair<long long, long long>> contrib;   // (entry, src index)
+        auto add = [&](int p, int q, long long src, int mult) {
+            const int s = P->par_sub[p];
+            const int p0 = P->subs[s].p0;
+            const int a = std::min(p, q) - p0, b = std::max(p, q) - p0;
+            const long long e = ent_id(s, a, b);
+            for (int m = 0; m < mult; ++m) contrib.emplace_back(e, src);
+        };
+        auto add_items_tm = [&](const std::vector<PairItem>& items, int tm) {
+            for (const PairItem& it : items) {
+                const DPair& pr = P->pairs[it.pair];
+                const DGroup& G = P->groups[pr.g];
+                const DGroup& H = P->groups[pr.h];
+                for (int i = 0; i < tm; ++i) {
+                    const int ci = it.ta * tm + i;
+                    if (ci >= G.ncols) break;
+                    for (int j = 0; j < tm; ++j) {
+                        const int cj = it.tb * tm + j;
+                        if (cj >= H.ncols) break;
+                        if (pr.g == pr.h && ci > cj) continue;
+                        const int p = P->cols[G.col_begin + ci].par, q = P->cols[H.col_begin + cj].par;
+                        const bool diag_same_col = (pr.g == pr.h && ci == cj);
+                        add(p, q, it.out_off + (long long)i * tm + j, (p == q && !diag_same_col) ? 2 : 1);
+                    }
+                }
+            }
+        };
+        // keep item order: 64-tiles then 16-tiles, each in item order
+        add_items_tm(P->pitems64, 64);
+        add_items_tm(P->pitems16, 16);
+        for (int k = 0; k < d->n_images; ++k) {
+            const DImage& im = P->images[k];
+            if (im.sky_par < 0) continue;
+            for (int g = 0; g < n_groups; ++g) {
+                const DGroup& gr = P->groups[g];
+                if (gr.image != k || gr.oh <= 0 || gr.ow <= 0) continue;
+                for (int ch = 0; ch < gr.ncols; ++ch)
+                    add(im.sky_par, P->cols[gr.col_begin + ch].par, P->asrc_col + 2LL * (gr.col_begin + ch) + 1, 1);
+            }
+            add(im.sky_par, im.sky_par, P->asrc_img + 3LL * k + 2, 1);
+        }
+        std::stable_sort(contrib.begin(), contrib.end(),
+                         [](const std::pair<long long, long long>& x, const std::pair<long long, long long>& y) {
+                             return x.first < y.first;
+                         });
+        P->a_off_csr.assign(n_ent + 1, 0);
+        P->a_src.resize(contrib.size());
+        for (size_t i = 0; i < contrib.size(); ++i) {
+            P->a_off_csr[contrib[i].first + 1]++;
+            P->a_src[i] = contrib[i].second;
+        }
+        for (long long e = 0; e < n_ent; ++e) P->a_off_csr[e + 1] += P->a_off_csr[e];
+        P->a_sub.resize(n_ent);
+        P->a_row.resize(n_ent);
+        P->a_col.resize(n_ent);
+        for (int s = 0; s < d->n_sub; ++s) {
+            const int n = P->subs[s].n;
+            long long e = ent_base[s];
+            for (int a = 0; a < n; ++a)
+                for (int b = a; b < n; ++b, ++e) {
+                    P->a_sub[e] = s;
+                    P->a_row[e] = a;
+                    P->a_col[e] = b;
+                }
+        }
+    }
+
+    // J^T W r and gradient per theta index; chi^2 per sub; dense-J scatter lists
+    {
+        std::vector<std::vector<int>> pc(d->n_par), ps(d->n_par);
+        for (int c = 0; c < n_cols; ++c) pc[P->cols[c].par].push_back(c);
+        for (int k = 0; k < d->n_images; ++k)
+            if (P->images[k].sky_par >= 0) ps[P->images[k].sky_par].push_back(k);
+        P->g_seg.assign(1, 0);
+        P->gr_seg.assign(1, 0);
+        P->par_off.assign(1, 0);
+        P->par_sky_off.assign(1, 0);
+        for (int p = 0; p < d->n_par; ++p) {
+            for (int c : pc[p]) {
+                const DGroup& gr = P->groups[P->cols[c].group];
+                if (gr.oh > 0 && gr.ow > 0) {
+                    P->g_idx.push_back((int)(P->asrc_col + 2LL * c));
+                    P->g_w.push_back(1.0);
+                }
+                P->gr_idx.push_back((int)(P->asrc_gcol + c));
+                P->gr_w.push_back(1.0);
+                P->par_cols.push_back(c);
+            }
+            for (int k : ps[p]) {
+                P->g_idx.push_back((int)(P->asrc_img + 3LL * k + 1));
+                P->g_w.push_back(1.0);
+                P->gr_idx.push_back((int)(P->asrc_img + 3LL * k + 1));
+                P->gr_w.push_back(-2.0);
+                P->par_sky.push_back(k);
+            }
+            P->g_seg.push_back((int)P->g_idx.size());
+            P->gr_seg.push_back((int)P->gr_idx.size());
+            P->par_off.push_back((int)P->par_cols.size());
+            P->par_sky_off.push_back((int)P->par_sky.size());
+            P->g_sub.push_back(std::max(0, P->par_sub[p]));
+        }
+        P->chi_seg.assign(1, 0);
+        for (int s = 0; s < d->n_sub; ++s) {
+            for (int k = 0; k < d->n_images; ++k)
+                if (P->images[k].sub == s) P->chi_idx.push_back((int)(P->asrc_img + 3LL * k));
+            P->chi_seg.push_back((int)P->chi_idx.size());
+        }
+    }
+    if ((long long)P->asrc_img + 3LL * d->n_images >= (1LL << 31))
+        return fail(C, APX_E_UNSUPPORTED, "problem too large for 32-bit reduction indices");
+    return APX_OK;
+}
+
+// ------------------------------------------------------------------ workspace
+template <class T>
+static size_t ws_take(apx_problem* P, const char* name, size_t count) {
+    size_t o = P->L.take(count * sizeof(T) + 8);
+    P->off[name] = o;
+    return o;
+}
+
+static void layout(apx_problem* P) {
+    P->L = Layout();
+    P->off.clear();
+    const int n_cols = (int)P->cols.size();
+    ws_take<DImage>(P, "images", P->images.size());
+    ws_take<DComp>(P, "comps", P->comps.size());
+    ws_take<DGroup>(P, "groups", P->groups.size());
+    ws_take<DCol>(P, "cols", P->cols.size());
+    ws_take<DSub>(P, "subs", P->subs.size());
+    ws_take<int>(P, "group_comps", P->group_comps.size());
+    ws_take<RTile>(P, "rtiles", P->rtiles.size());
+    ws_take<int>(P, "rtile_off", P->rtile_off.size());
+    ws_take<int>(P, "rtile_comps", P->rtile_comps.size());
+    ws_take<RTile>(P, "gtiles", P->gtiles.size());
+    ws_take<ConvJob>(P, "fwd_jobs", P->fwd_jobs.size());
+    ws_take<ConvItem>(P, "fwd_items", P->fwd_items.size());
+    ws_take<ConvJob>(P, "jcol_jobs", P->jcol_jobs.size());
+    ws_take<ConvItem>(P, "jcol_items", P->jcol_items.size());
+    ws_take<ConvJob>(P, "adj_jobs", P->adj_jobs.size());
+    ws_take<ConvItem>(P, "adj_items", P->adj_items.size());
+    ws_take<DPair>(P, "pairs", P->pairs.size());
+    ws_take<PairItem>(P, "pitems64", P->pitems64.size());
+    ws_take<PairItem>(P, "pitems16", P->pitems16.size());
+    ws_take<int>(P, "img_seg", P->img_seg.size());
+    ws_take<int>(P, "img_idx", P->img_idx.size());
+    ws_take<int>(P, "col_seg", P->col_seg.size());
+    ws_take<int>(P, "col_idx", P->col_idx.size());
+    ws_take<int>(P, "gcol_seg", P->gcol_seg.size());
+    ws_take<int>(P, "chi_seg", P->chi_seg.size());
+    ws_take<int>(P, "chi_idx", P->chi_idx.size());
+    ws_take<int>(P, "g_seg", P->g_seg.size());
+    ws_take<int>(P, "g_idx", P->g_idx.size());
+    ws_take<double>(P, "g_w", P->g_w.size());
+    ws_take<int>(P, "g_sub", P->g_sub.size());
+    ws_take<int>(P, "gr_seg", P->gr_seg.size());
+    ws_take<int>(P, "gr_idx", P->gr_idx.size());
+    ws_take<double>(P, "gr_w", P->gr_w.size());
+    ws_take<long long>(P, "a_off_csr", P->a_off_csr.size());
+    ws_take<long long>(P, "a_src", P->a_src.size());
+    ws_take<int>(P, "a_sub", P->a_sub.size());
+    ws_take<int>(P, "a_row", P->a_row.size());
+    ws_take<int>(P, "a_col", P->a_col.size());
+    ws_take<int>(P, "par_sub", P->par_sub.size());
+    ws_take<int>(P, "par_off", P->par_off.size());
+    ws_take<int>(P, "par_cols", P->par_cols.size());
+    ws_take<int>(P, "par_sky_off", P->par_sky_off.size());
+    ws_take<int>(P, "par_sky", P->par_sky.size());
+    ws_take<int>(P, "small_subs", P->small_subs.size());
+    // buffers
+    ws_take<CompConst>(P, "cc", P->comps.size());
+    ws_take<float>(P, "S", P->n_ext);
+    ws_take<double>(P, "S64", P->objective == APX_OBJECTIVE_FP64 ? P->n_ext : 0);
+    ws_take<float>(P, "Abar", P->n_ext);
+    ws_take<float>(P, "rbuf", P->n_pix);
+    ws_take<float>(P, "D", P->n_d);
+    ws_take<float>(P, "J", P->n_j);
+    ws_take<float>(P, "psf_flip", P->n_psf);
+    ws_take<double>(P, "fwd_part", 3 * P->fwd_items.size());
+    ws_take<double>(P, "jcol_part", 2 * P->jcol_items.size());
+    ws_take<double>(P, "grad_part", P->n_gradpart);
+    ws_take<double>(P, "asrc", P->asrc_img + 3LL * P->n_images);
+    ws_take<double>(P, "A", P->a_total);
+    ws_take<double>(P, "M", P->a_total);
+    ws_take<double>(P, "gvec", P->n_par);
+    ws_take<double>(P, "Ddiag", P->n_par);
+    ws_take<double>(P, "hvec", P->n_par);
+    ws_take<double>(P, "theta_trial", P->n_par);
+    ws_take<LMFlags>(P, "lmf", P->n_sub);
+    ws_take<int>(P, "sticky", 1);
+    ws_take<double>(P, "sky_val", P->n_images);
+    ws_take<double>(P, "chi2_sub", P->n_sub);
+    ws_take<double>(P, "chi2_trial", P->n_sub);
+    (void)n_cols;
+}
+
+template <class T>
+static T* wsp(apx_problem* P, const char* name) {
+    return reinterpret_cast<T*>(P->ws + P->off.at(name));
+}
+
+template <class T>
+static hipError_t upload(apx_problem* P, const char* name, const std::vector<T>& v) {
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(wsp<T>(P, name), v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, P->ctx->stream);
+}
+
+// ------------------------------------------------------------------- C ABI
+extern "C" {
+
+const char* apx_version(void) { return "apx 0.1 (gfx950)"; }
+
+const char* apx_status_string(apx_status s) {
+    switch (s) {
+        case APX_OK: return "ok";
+        case APX_E_INVALID: return "invalid argument";
+        case APX_E_HIP: return "HIP runtime error";
+        case APX_E_NONFINITE: return "non-finite value";
+        case APX_E_WORKSPACE: return "workspace missing or too small";
+        case APX_E_UNSUPPORTED: return "unsupported configuration";
+        case APX_E_DOMAIN: return "parameters outside the model domain";
+        default: return "unknown status";
+    }
+}
+
+apx_status apx_ctx_create(int device, void* hip_stream, apx_ctx** out) {
+    if (!out) return APX_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return APX_E_HIP;
+    if (hipSetDevice(device) != hipSuccess) return APX_E_HIP;
+    apx_ctx* c = new apx_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return APX_OK;
+}
+
+apx_status apx_ctx_set_stream(apx_ctx* ctx, void* hip_stream) {
+    if (!ctx) return APX_E_INVALID;
+    ctx->stream = (hipStream_t)hip_stream;
+    return APX_OK;
+}
+
+apx_status apx_ctx_destroy(apx_ctx* ctx) {
+    delete ctx;
+    return APX_OK;
+}
+
+const char* apx_last_error(const apx_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+apx_status apx_problem_create(apx_ctx* ctx, const apx_problem_desc* desc, apx_problem** out) {
+    if (!ctx || !desc || !out) return APX_E_INVALID;
+    *out = nullptr;
+    apx_problem* P = new apx_problem();
+    P->ctx = ctx;
+    apx_status st;
+    try {
+        st = build_plan(P, desc);
+    } catch (const std::exception& e) {
+        st = fail(ctx, APX_E_INVALID, std::string("plan construction failed: ") + e.what());
+    }
+    if (st != APX_OK) {
+        delete P;
+        return st;
+    }
+    layout(P);
+    *out = P;
+    return APX_OK;
+}
+
+apx_status apx_problem_workspace_bytes(const apx_problem* P, uint64_t* bytes) {
+    if (!P || !bytes) return APX_E_INVALID;
+    *bytes = P->L.total;
+    return APX_OK;
+}
+
+apx_status apx_problem_sizes(const apx_problem* P, int64_t* n_pix, int64_t* n_ext, int64_t* n_jac) {
+    if (!P) return APX_E_INVALID;
+    if (n_pix) *n_pix = P->n_pix;
+    if (n_ext) *n_ext = P->n_ext;
+    if (n_jac) *n_jac = P->n_j;
+    return APX_OK;
+}
+
+apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes) {
+    if (!P) return APX_E_INVALID;
+    if (!dev || bytes < P->L.total || ((uintptr_t)dev & 255) != 0)
+        return fail(P->ctx, APX_E_WORKSPACE, "workspace null, misaligned or smaller than required");
+    P->ws = (char*)dev;
+    P->ws_bytes = bytes;
+    HIPCHK(upload(P, "images", P->images));
+    HIPCHK(upload(P, "comps", P->comps));
+    HIPCHK(upload(P, "groups", P->groups));
+    HIPCHK(upload(P, "cols", P->cols));
+    HIPCHK(upload(P, "subs", P->subs));
+    HIPCHK(upload(P, "group_comps", P->group_comps));
+    HIPCHK(upload(P, "rtiles", P->rtiles));
+    HIPCHK(upload(P, "rtile_off", P->rtile_off));
+    HIPCHK(upload(P, "rtile_comps", P->rtile_comps));
+    HIPCHK(upload(P, "gtiles", P->gtiles));
+    HIPCHK(upload(P, "fwd_jobs", P->fwd_jobs));
+    HIPCHK(upload(P, "fwd_items", P->fwd_items));
+    HIPCHK(upload(P, "jcol_jobs", P->jcol_jobs));
+    HIPCHK(upload(P, "jcol_items", P->jcol_items));
+    HIPCHK(upload(P, "adj_jobs", P->adj_jobs));
+    HIPCHK(upload(P, "adj_items", P->adj_items));
+    HIPCHK(upload(P, "pairs", P->pairs));
+    HIPCHK(upload(P, "pitems64", P->pitems64));
+    HIPCHK(upload(P, "pitems16", P->pitems16));
+    HIPCHK(upload(P, "img_seg", P->img_seg));
+    HIPCHK(upload(P, "img_idx", P->img_idx));
+    HIPCHK(upload(P, "col_seg", P->col_seg));
+    HIPCHK(upload(P, "col_idx", P->col_idx));
+    HIPCHK(upload(P, "gcol_seg", P->gcol_seg));
+    HIPCHK(upload(P, "chi_seg", P->chi_seg));
+    HIPCHK(upload(P, "chi_idx", P->chi_idx));
+    HIPCHK(upload(P, "g_seg", P->g_seg));
+    HIPCHK(upload(P, "g_idx", P->g_idx));
+    HIPCHK(upload(P, "g_w", P->g_w));
+    HIPCHK(upload(P, "g_sub", P->g_sub));
+    HIPCHK(upload(P, "gr_seg", P->gr_seg));
+    HIPCHK(upload(P, "gr_idx", P->gr_idx));
+    HIPCHK(upload(P, "gr_w", P->gr_w));
+    HIPCHK(upload(P, "a_off_csr", P->a_off_csr));
+    HIPCHK(upload(P, "a_src", P->a_src));
+    HIPCHK(upload(P, "a_sub", P->a_sub));
+    HIPCHK(upload(P, "a_row", P->a_row));
+    HIPCHK(upload(P, "a_col", P->a_col));
+    HIPCHK(upload(P, "par_sub", P->par_sub));
+    HIPCHK(upload(P, "par_off", P->par_off));
+    HIPCHK(upload(P, "par_cols", P->par_cols));
+    HIPCHK(upload(P, "par_sky_off", P->par_sky_off));
+    HIPCHK(upload(P, "par_sky", P->par_sky));
+    HIPCHK(upload(P, "small_subs", P->small_subs));
+
+    Plan& p = P->plan;
+    p = Plan{};
+    p.n_images = P->n_images;
+    p.n_comps = P->n_comps;
+    p.n_par = P->n_par;
+    p.n_sub = P->n_sub;
+    p.n_groups = (int)P->groups.size();
+    p.n_cols = (int)P->cols.size();
+    p.s = P->s;
+    p.rule = P->rule;
+    p.mode = P->mode;
+    p.objective = P->objective;
+    p.k_re = P->k_re;
+    for (int k = 0; k < MAX_NODES_1D; ++k) {
+        p.node_o[k] = k < (int)P->node_o.size() ? P->node_o[k] : 0.f;
+        p.node_w[k] = k < (int)P->node_w.size() ? P->node_w[k] : 0.f;
+        p.node_od[k] = k < (int)P->node_od.size() ? P->node_od[k] : 0.0;
+        p.node_wd[k] = k < (int)P->node_wd.size() ? P->node_wd[k] : 0.0;
+    }
+    p.images = wsp<DImage>(P, "images");
+    p.comps = wsp<DComp>(P, "comps");
+    p.groups = wsp<DGroup>(P, "groups");
+    p.cols = wsp<DCol>(P, "cols");
+    p.subs = wsp<DSub>(P, "subs");
+    p.group_comps = wsp<int>(P, "group_comps");
+    p.psf = P->psf;
+    p.psf_flip = wsp<float>(P, "psf_flip");
+    p.rtiles = wsp<RTile>(P, "rtiles");
+    p.n_rtiles = (int)P->rtiles.size();
+    p.rtile_off = wsp<int>(P, "rtile_off");
+    p.rtile_comps = wsp<int>(P, "rtile_comps");
+    p.gtiles = wsp<RTile>(P, "gtiles");
+    p.n_gtiles = (int)P->gtiles.size();
+    p.cc = wsp<CompConst>(P, "cc");
+    p.S = wsp<float>(P, "S");
+    p.S64 = wsp<double>(P, "S64");
+    p.Abar = wsp<float>(P, "Abar");
+    p.rbuf = wsp<float>(P, "rbuf");
+    p.D = wsp<float>(P, "D");
+    p.J = wsp<float>(P, "J");
+    p.fwd_part = wsp<double>(P, "fwd_part");
+    p.jcol_part = wsp<double>(P, "jcol_part");
+    p.grad_part = wsp<double>(P, "grad_part");
+    P->asrc = wsp<double>(P, "asrc");
+    p.pair_part = P->asrc;
+    p.col_sum = P->asrc + P->asrc_col;
+    p.grad_col = P->asrc + P->asrc_gcol;
+    p.img_sum = P->asrc + P->asrc_img;
+    p.A = wsp<double>(P, "A");
+    p.M = wsp<double>(P, "M");
+    p.gvec = wsp<double>(P, "gvec");
+    p.Ddiag = wsp<double>(P, "Ddiag");
+    p.hvec = wsp<double>(P, "hvec");
+    p.theta_trial = wsp<double>(P, "theta_trial");
+    p.lmf = wsp<LMFlags>(P, "lmf");
+    p.sticky = wsp<int>(P, "sticky");
+    p.sky_val = wsp<double>(P, "sky_val");
+    p.par_sub = wsp<int>(P, "par_sub");
+    p.n_pix = P->n_pix;
+    p.n_ext = P->n_ext;
+    P->chi2_sub = wsp<double>(P, "chi2_sub");
+    P->chi2_trial = wsp<double>(P, "chi2_trial");
+    HIPCHK(hipMemsetAsync(p.sticky, 0, sizeof(int), P->ctx->stream));
+    HIPCHK(hipMemsetAsync(p.lmf, 0, sizeof(LMFlags) * P->n_sub, P->ctx->stream));
+    P->bound = true;
+    return APX_OK;
+}
+
+apx_status apx_problem_check(apx_problem* P) {
+    if (!P || !P->bound) return APX_E_WORKSPACE;
+    int flags = 0;
+    HIPCHK(hipStreamSynchronize(P->ctx->stream));
+    HIPCHK(hipMemcpy(&flags, P->plan.sticky, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemset(P->plan.sticky, 0, sizeof(int)));
+    if (flags & FLAG_DOMAIN) return APX_E_DOMAIN;
+    if (flags & FLAG_NONFINITE) return APX_E_NONFINITE;
+    return APX_OK;
+}
+
+apx_status apx_problem_destroy(apx_problem* P) {
+    if (!P) return APX_OK;
+    if (P->gexec) hipGraphExecDestroy(P->gexec);
+    if (P->graph) hipGraphDestroy(P->graph);
+    delete P;
+    return APX_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ launch sequences
+static apx_status run_conv(apx_problem* P, int kind, const ConvIO& io) {
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    const std::vector<PRange>* ranges;
+    const char *jn, *inn;
+    if (kind == CONV_FWD) { ranges = &P->fwd_ranges; jn = "fwd_jobs"; inn = "fwd_items"; }
+    else if (kind == CONV_JCOL) { ranges = &P->jcol_ranges; jn = "jcol_jobs"; inn = "jcol_items"; }
+    else { ranges = &P->adj_ranges; jn = "adj_jobs"; inn = "adj_items"; }
+    for (const PRange& r : *ranges) {
+        ConvLaunch L{wsp<ConvJob>(P, jn), wsp<ConvItem>(P, inn), r.begin, r.count, r.P};
+        hipError_t e = kind == CONV_FWD ? (P->objective == APX_OBJECTIVE_FP64 ? launch_conv_fwd64(p, L, io, st)
+                                                                               : launch_conv_fwd(p, L, io, st))
+                     : kind == CONV_JCOL ? launch_conv_jcol(p, L, io, st)
+                                         : launch_conv_adj(p, L, io, st);
+        if (e != hipSuccess) return fail(P->ctx, APX_E_HIP, std::string("conv launch: ") + hipGetErrorString(e));
+    }
+    return APX_OK;
+}
+
+#define APXCHK(expr)                          \
+    do {                                      \
+        apx_status _s = (expr);               \
+        if (_s != APX_OK) return _s;          \
+    } while (0)
+
+static SegSum segsum_base() {
+    SegSum a{};
+    a.stride = 1;
+    a.ostride = 1;
+    a.scale = 1.0;
+    return a;
+}
+
+// Forward model + residual partials, reduced to img_sum (3 per image) and chi2[n_sub].
+static apx_status fwd_chi2(apx_problem* P, const double* theta, const float* data, const float* weight,
+                           float* model, double* chi2_out, int lm_trial, int skip_mode,
+                           const apx_lm_state* lm) {
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    HIPCHK(launch_prep(p, theta, lm_trial, st));
+    if (P->objective == APX_OBJECTIVE_FP64) HIPCHK(launch_render64(p, skip_mode, lm, st));
+    else HIPCHK(launch_render_mode(p, skip_mode, lm, st));
+    ConvIO io{};
+    io.in = p.S;
+    io.in64 = p.S64;
+    io.out = model;
+    io.data = data;
+    io.weight = weight;
+    io.part = p.fwd_part;
+    io.skip_mode = skip_mode;
+    io.lm = lm;
+    APXCHK(run_conv(P, CONV_FWD, io));
+    if (data) {
+        for (int q = 0; q < 3; ++q) {
+            SegSum a = segsum_base();
+            a.src = p.fwd_part;
+            a.stride = 3;
+            a.comp = q;
+            a.seg = wsp<int>(P, "img_seg");
+            a.idx = wsp<int>(P, "img_idx");
+            a.n_seg = P->n_images;
+            a.out = p.img_sum;
+            a.ostride = 3;
+            a.ocomp = q;
+            HIPCHK(launch_segsum(a, st));
+        }
+        if (chi2_out) {
+            SegSum a = segsum_base();
+            a.src = P->asrc;
+            a.seg = wsp<int>(P, "chi_seg");
+            a.idx = wsp<int>(P, "chi_idx");
+            a.n_seg = P->n_sub;
+            a.out = chi2_out;
+            HIPCHK(launch_segsum(a, st));
+        }
+    }
+    return APX_OK;
+}
+
+// Derivative images and Jacobian blocks (with sum w r J, sum w J partials if weight).
+static apx_status jac_blocks(apx_problem* P, const float* weight, const apx_lm_state* lm) {
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    HIPCHK(launch_deriv(p, lm, st));
+    ConvIO io{};
+    io.in = p.D;
+    io.out = p.J;
+    io.weight = weight;
+    io.part = p.jcol_part;
+    io.skip_mode = lm ? 2 : 0;
+    io.lm = lm;
+    APXCHK(run_conv(P, CONV_JCOL, io));
+    if (weight) {
+        for (int q = 0; q < 2; ++q) {
+            SegSum a = segsum_base();
+            a.src = p.jcol_part;
+            a.stride = 2;
+            a.comp = q;
+            a.seg = wsp<int>(P, "col_seg");
+            a.idx = wsp<int>(P, "col_idx");
+            a.n_seg = (int)P->cols.size();
+            a.out = p.col_sum;
+            a.ostride = 2;
+            a.ocomp = q;
+            HIPCHK(launch_segsum(a, st));
+        }
+    }
+    return APX_OK;
+}
+
+// J^T W J and J^T W r into A_out / g_out from the stored blocks and partials.
+static apx_status normal_eq(apx_problem* P, const float* weight, double* A_out, double* g_out,
+                            const apx_lm_state* lm) {
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    PairLaunch L64{wsp<DPair>(P, "pairs"), wsp<PairItem>(P, "pitems64"), (int)P->pitems64.size(), 64};
+    PairLaunch L16{wsp<DPair>(P, "pairs"), wsp<PairItem>(P, "pitems16"), (int)P->pitems16.size(), 16};
+    HIPCHK(launch_pairs(p, L64, weight, lm, st));
+    HIPCHK(launch_pairs(p, L16, weight, lm, st));
+    AsmA a{};
+    a.ent_off = wsp<long long>(P, "a_off_csr");
+    a.ent_sub = wsp<int>(P, "a_sub");
+    a.ent_row = wsp<int>(P, "a_row");
+    a.ent_col = wsp<int>(P, "a_col");
+    a.ent_src = wsp<long long>(P, "a_src");
+    a.n_ent = (long long)P->a_sub.size();
+    a.src = P->asrc;
+    a.subs = p.subs;
+    a.out = A_out;
+    a.lm = lm;
+    HIPCHK(launch_assemble_A(a, st));
+    SegSum g = segsum_base();
+    g.src = P->asrc;
+    g.seg = wsp<int>(P, "g_seg");
+    g.idx = wsp<int>(P, "g_idx");
+    g.wts = wsp<double>(P, "g_w");
+    g.n_seg = P->n_par;
+    g.out = g_out;
+    g.seg_sub = wsp<int>(P, "g_sub");
+    g.lm = lm;
+    HIPCHK(launch_segsum(g, st));
+    return APX_OK;
+}
+
+static apx_status ready(apx_problem* P) {
+    if (!P) return APX_E_INVALID;
+    if (!P->bound) return fail(P->ctx, APX_E_WORKSPACE, "no workspace bound");
+    return APX_OK;
+}
+
+extern "C" {
+
+apx_status apx_render(apx_problem* P, const double* theta, float* model) {
+    APXCHK(ready(P));
+    if (!theta || !model) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    return fwd_chi2(P, theta, nullptr, nullptr, model, nullptr, 0, 0, nullptr);
+}
+
+apx_status apx_chi2(apx_problem* P, const double* theta, const float* data, const float* weight,
+                    double* chi2) {
+    APXCHK(ready(P));
+    if (!theta || !data || !weight || !chi2) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
+    HIPCHK(launch_chi2_check(chi2, P->n_sub, P->plan.sticky, P->ctx->stream));
+    return APX_OK;
+}
+
+apx_status apx_jacobian(apx_problem* P, const double* theta, float* J, int64_t ldJ) {
+    APXCHK(ready(P));
+    if (!theta || !J) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (ldJ < P->n_pix) return fail(P->ctx, APX_E_INVALID, "ldJ < n_pix");
+    hipStream_t st = P->ctx->stream;
+    HIPCHK(launch_prep(P->plan, theta, 0, st));
+    APXCHK(jac_blocks(P, nullptr, nullptr));
+    HIPCHK(launch_jscatter(P->plan, wsp<int>(P, "par_off"), wsp<int>(P, "par_cols"), wsp<int>(P, "par_sky_off"),
+                           wsp<int>(P, "par_sky"), J, ldJ, st));
+    return APX_OK;
+}
+
+apx_status apx_jtwj(apx_problem* P, const double* theta, const float* data, const float* weight,
+                    double* JtWJ, double* JtWr, double* chi2) {
+    APXCHK(ready(P));
+    if (!theta || !data || !weight || !JtWJ || !JtWr || !chi2) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
+    APXCHK(jac_blocks(P, weight, nullptr));
+    APXCHK(normal_eq(P, weight, JtWJ, JtWr, nullptr));
+    HIPCHK(launch_chi2_check(chi2, P->n_sub, P->plan.sticky, P->ctx->stream));
+    return APX_OK;
+}
+
+apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data, const float* weight,
+                         double* grad, double* chi2) {
+    APXCHK(ready(P));
+    if (!theta || !data || !weight || !grad || !chi2) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
+    HIPCHK(launch_flip_psf(p, st));
+    ConvIO io{};
+    io.out = p.Abar;
+    io.weight = weight;
+    APXCHK(run_conv(P, CONV_ADJ, io));
+    HIPCHK(launch_grad_tiles(p, st));
+    SegSum a = segsum_base();
+    a.src = p.grad_part;
+    a.seg = wsp<int>(P, "gcol_seg");
+    a.n_seg = (int)P->cols.size();
+    a.out = p.grad_col;
+    HIPCHK(launch_segsum(a, st));
+    SegSum g = segsum_base();
+    g.src = P->asrc;
+    g.seg = wsp<int>(P, "gr_seg");
+    g.idx = wsp<int>(P, "gr_idx");
+    g.wts = wsp<double>(P, "gr_w");
+    g.n_seg = P->n_par;
+    g.out = grad;
+    HIPCHK(launch_segsum(g, st));
+    HIPCHK(launch_chi2_check(chi2, P->n_sub, p.sticky, st));
+    return APX_OK;
+}
+
+apx_status apx_lm_init(apx_problem* P, const double* theta, const float* data, const float* weight,
+                       apx_lm_state* state) {
+    APXCHK(ready(P));
+    if (!theta || !data || !weight || !state) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, P->chi2_sub, 0, 0, nullptr));
+    HIPCHK(launch_lm_init(P->plan, P->chi2_sub, state, P->ctx->stream));
+    return APX_OK;
+}
+
+static apx_status lm_step_enqueue(apx_problem* P, const float* data, const float* weight, double* theta,
+                                  apx_lm_state* state) {
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    HIPCHK(launch_lm_begin(p, state, st));
+    // normal equations at theta for sub-problems whose last step was accepted
+    HIPCHK(launch_prep(p, theta, 0, st));
+    APXCHK(jac_blocks(P, weight, state));
+    APXCHK(normal_eq(P, weight, p.A, p.gvec, state));
+    // damped solves
+    HIPCHK(launch_chol_small(p, wsp<int>(P, "small_subs"), (int)P->small_subs.size(), P->nmax_small, state, st));
+    for (int s : P->large_subs) HIPCHK(launch_chol_large(p, s, P->subs[s].n, state, st));
+    // trial
+    HIPCHK(launch_lm_trial(p, theta, state, st));
+    APXCHK(fwd_chi2(P, p.theta_trial, data, weight, nullptr, P->chi2_trial, 1, 1, state));
+    HIPCHK(launch_lm_accept(p, P->chi2_trial, theta, state, st));
+    return APX_OK;
+}
+
+apx_status apx_lm_step(apx_problem* P, const float* data, const float* weight, double* theta,
+                       apx_lm_state* state) {
+    APXCHK(ready(P));
+    if (!theta || !data || !weight || !state) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    return lm_step_enqueue(P, data, weight, theta, state);
+}
+
+apx_status apx_lm_run(apx_problem* P, int32_t n_iter, const float* data, const float* weight,
+                      double* theta, apx_lm_state* state, int32_t use_graph) {
+    APXCHK(ready(P));
+    if (!theta || !data || !weight || !state || n_iter < 0) return fail(P->ctx, APX_E_INVALID, "bad argument");
+    if (!use_graph) {
+        for (int i = 0; i < n_iter; ++i) APXCHK(lm_step_enqueue(P, data, weight, theta, state));
+        return APX_OK;
+    }
+    hipStream_t st = P->ctx->stream;
+    if (!st) return fail(P->ctx, APX_E_INVALID, "graph capture needs a non-default stream");
+    const void* key[4] = {data, weight, theta, state};
+    if (!P->gexec || std::memcmp(key, P->gkey, sizeof(key)) != 0) {
+        if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+        if (P->graph) { hipGraphDestroy(P->graph); P->graph = nullptr; }
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        apx_status s = lm_step_enqueue(P, data, weight, theta, state);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (s != APX_OK) { if (g) hipGraphDestroy(g); return s; }
+        if (e != hipSuccess) return fail(P->ctx, APX_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+        P->graph = g;
+        HIPCHK(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0));
+        std::memcpy(P->gkey, key, sizeof(key));
+    }
+    for (int i = 0; i < n_iter; ++i) HIPCHK(hipGraphLaunch(P->gexec, st));
+    return APX_OK;
+}
+
+}  // extern "C"

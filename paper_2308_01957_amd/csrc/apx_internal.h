@@ -1,0 +1,227 @@
+// Internal declarations of the apx library: device-side plan records, per-call
+// constants and the launchers each kernel translation unit exports to the host API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/apx.h"
+
+namespace apx {
+
+// Tile shapes --------------------------------------------------------------------
+constexpr int RT_Y = 8, RT_X = 32;            // render / derivative / gradient tiles (256 px)
+constexpr int CV_TH = 32, CV_TW = 64;         // convolution output tile per workgroup
+constexpr int CV_R = 8;                       // consecutive outputs per lane (register window)
+constexpr int PAIR_KC = 16;                   // pixels per LDS stage of the J^T W J kernel
+constexpr int CHOL_NB = 64;                   // block size of the blocked Cholesky
+constexpr int SMALL_N = 64;                   // sub-problems up to this size: one-wave solver
+constexpr int MAX_NODES_1D = 8;
+
+// Plan records (uploaded once into the workspace) -------------------------------
+struct DImage {
+    int H, W, P, c;
+    int EH, EW;               // extended grid (H+2c) x (W+2c)
+    int sub, sky_par;
+    double sky_fixed;
+    long long pix_off;        // first element in the pixel buffers
+    long long ext_off;        // first element in the extended-grid buffers
+    long long psf_off;        // first element of the stamp
+    double aff[6];            // pixel -> sky
+    double inv[6];            // sky -> pixel
+    double area;              // |det| of the linear part
+};
+
+struct DComp {
+    int type, image;
+    int box[4];               // clipped window y0, x0, y1, x1 (extended-grid coords)
+    int par[7];
+    int group;                // Jacobian group, -1 when the component has no free parameter
+    int col[7];               // column of local parameter k inside its group, -1 = fixed
+    int sub, pad;
+    double fixed[7];
+};
+
+// Per-call component constants (written by k_prep from theta)
+struct CompConst {
+    double x0, y0;            // Sersic centre (sky frame); point: pixel position
+    double cs_d, sn_d, q_d;   // FP64 copies for the within-k-Re test
+    double kre;               // k * Re
+    double h_d, A_d, B_d;     // t = exp2(g log2 R^2 - h), I = exp2(A - B t)
+    double g_d;               // 0.5 / n
+    double F64;               // point-source flux (FP64)
+    float cs, sn, iq;         // cos PA, sin PA, 1/q
+    float g;                  // 0.5 / n
+    float b, bp, n, re, q;    // b_n, db_n/dn and raw parameters (derivatives)
+    float F;                  // point-source flux
+    int valid;                // parameters inside the model domain
+    int pad;
+};
+
+struct DGroup {               // columns sharing one window on one image
+    int image, type, ncols, sub;
+    int iy0, ix0, ih, iw;     // input box (window), extended-grid coords
+    int oy0, ox0, oh, ow;     // output box (window dilated by c, clipped to the image)
+    int comp_begin, comp_end; // into group_comps
+    int col_begin;            // global id of column 0
+    int tile_begin, ntiles;   // RT tiles of the input box (deriv / grad)
+    long long d_off, j_off;   // element offsets into the D and J buffers
+    long long gp_off;         // offset of the gradient partials (ncols * ntiles)
+};
+
+struct DCol { int group, comp, local, par; };
+
+struct RTile { int a, y0, x0, pad; };         // a = image (render) or group (deriv/grad)
+
+struct ConvJob {
+    long long in_off, out_off;                // element offsets of channel 0
+    long long in_cs, out_cs;                  // channel strides
+    int in_y0, in_x0, in_h, in_w;             // input rectangle (zero outside)
+    int out_y0, out_x0, out_h, out_w;         // output rectangle
+    int image, group, ntx, pad;
+};
+struct ConvItem { int job, ch, ty, tx; };
+
+struct DPair {
+    int g, h, image, sub;
+    int y0, x0, y1, x1;       // intersection of the two output boxes
+};
+struct PairItem { int pair, ta, tb, r0, r1, pad; long long out_off; };
+
+struct DSub { int p0, n; long long a_off; int large, pad; };
+
+// Per-sub-problem LM scratch flags
+struct LMFlags {
+    int chol_done;            // factorisation succeeded this iteration
+    int chol_fail;            // current attempt failed
+    int trial_bad;            // trial parameters outside the domain
+    int skip;                 // 1: sub-problem skips the current render/phase
+};
+
+// Launch-time views of the workspace ----------------------------------------------
+struct Plan {
+    int n_images, n_comps, n_par, n_sub, n_groups, n_cols;
+    int s, rule, mode, objective;
+    double k_re;
+    float node_o[MAX_NODES_1D], node_w[MAX_NODES_1D];
+    double node_od[MAX_NODES_1D], node_wd[MAX_NODES_1D];
+
+    const DImage* images;
+    const DComp* comps;
+    const DGroup* groups;
+    const DCol* cols;
+    const DSub* subs;
+    const int* group_comps;
+    const float* psf;         // caller's stamps
+    float* psf_flip;          // flipped stamps (adjoint)
+
+    // render tiles with component CSR
+    const RTile* rtiles; int n_rtiles;
+    const int* rtile_off; const int* rtile_comps;
+    // deriv/grad tiles
+    const RTile* gtiles; int n_gtiles;
+
+    // buffers
+    CompConst* cc;
+    float* S;                 // extended grid (render, FP32 objective)
+    double* S64;              // extended grid (render, FP64 objective)
+    float* Abar;              // extended grid adjoint
+    float* rbuf;              // residual d - m (FP32)
+    float* D;                 // derivative images
+    float* J;                 // Jacobian blocks
+    double* fwd_part;         // 3 per FWD conv item: sum w r^2, sum w r, sum w
+    double* img_sum;          // 3 per image
+    double* jcol_part;        // 2 per JCOL item: sum w r J, sum w J
+    double* col_sum;          // 2 per column
+    double* pair_part;        // pair tiles
+    double* grad_part;        // gradient partials (per group: ncols x ntiles)
+    double* grad_col;         // per column
+    double* A;                // internal J^T W J blocks (per sub)
+    double* gvec;             // internal J^T W r [n_par]
+    double* M;                // Cholesky factor (per sub)
+    double* Ddiag;            // damping diagonal [n_par]
+    double* hvec;             // step [n_par]
+    double* theta_trial;      // [n_par]
+    LMFlags* lmf;             // [n_sub]
+    int* sticky;              // device error flags
+    double* sky_val;          // [n_images] sky of each image at the current theta
+    const int* par_sub;       // [n_par] sub-problem of each theta index (-1: none)
+
+    long long n_pix, n_ext;
+};
+
+// Sticky flag bits
+constexpr int FLAG_DOMAIN = 1, FLAG_NONFINITE = 2;
+
+// Launchers (each returns hipGetLastError()) ----------------------------------------
+// k_model.hip
+hipError_t launch_prep(const Plan& p, const double* theta, int lm_trial, hipStream_t st);
+// skip_mode: 0 none, 1 skip sub-problems without a valid trial, 2 skip those that keep J
+hipError_t launch_render_mode(const Plan& p, int skip_mode, const apx_lm_state* lm, hipStream_t st);
+hipError_t launch_render64(const Plan& p, int skip_mode, const apx_lm_state* lm, hipStream_t st);
+hipError_t launch_deriv(const Plan& p, const apx_lm_state* lm, hipStream_t st);
+hipError_t launch_grad_tiles(const Plan& p, hipStream_t st);
+hipError_t launch_flip_psf(const Plan& p, hipStream_t st);
+
+// k_conv_*.hip
+enum ConvKind { CONV_FWD = 0, CONV_JCOL = 1, CONV_ADJ = 2 };
+struct ConvLaunch {
+    const ConvJob* jobs;
+    const ConvItem* items;
+    int item_begin, item_count, P;
+};
+struct ConvIO {
+    const float* in;          // input buffer base (FWD, JCOL)
+    const double* in64;       // input buffer base (FWD, FP64 objective)
+    float* out;               // output buffer base (FWD: optional model)
+    const float* data;        // FWD: data (null = no residual / partials)
+    const float* weight;      // FWD, JCOL (null = no partials), ADJ
+    double* part;             // per-item partials
+    int skip_mode;            // as launch_render_mode
+    const apx_lm_state* lm;
+};
+hipError_t launch_conv_fwd(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
+hipError_t launch_conv_fwd64(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
+hipError_t launch_conv_jcol(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
+hipError_t launch_conv_adj(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
+
+// k_jtwj.hip
+struct PairLaunch { const DPair* pairs; const PairItem* items; int n_items; int tm; };
+hipError_t launch_pairs(const Plan& p, const PairLaunch& L, const float* weight,
+                        const apx_lm_state* lm, hipStream_t st);
+struct SegSum {
+    const double* src; int stride, comp;
+    const int* seg; const int* idx; const double* wts;
+    int n_seg;
+    double* out; int ostride, ocomp;
+    double scale;
+    const int* seg_sub; const apx_lm_state* lm;
+};
+hipError_t launch_segsum(const SegSum& a, hipStream_t st);
+struct AsmA {
+    const long long* ent_off; const int* ent_sub; const int* ent_row; const int* ent_col;
+    const long long* ent_src;
+    long long n_ent;
+    const double* src;
+    const DSub* subs;
+    double* out;
+    const apx_lm_state* lm;
+};
+hipError_t launch_assemble_A(const AsmA& a, hipStream_t st);
+hipError_t launch_fill(double* x, long long n, double v, hipStream_t st);
+hipError_t launch_jscatter(const Plan& p, const int* par_off, const int* par_cols,
+                           const int* par_sky_off, const int* par_sky, float* Jd, long long ldJ,
+                           hipStream_t st);
+hipError_t launch_chi2_check(const double* chi2, int n, int* sticky, hipStream_t st);
+
+// k_lm.hip
+hipError_t launch_lm_begin(const Plan& p, apx_lm_state* lm, hipStream_t st);
+hipError_t launch_lm_init(const Plan& p, const double* chi2_sub, apx_lm_state* lm, hipStream_t st);
+hipError_t launch_chol_small(const Plan& p, const int* small_subs, int n_small, int nmax,
+                             apx_lm_state* lm, hipStream_t st);
+hipError_t launch_chol_large(const Plan& p, int sub, int n, apx_lm_state* lm, hipStream_t st);
+hipError_t launch_lm_trial(const Plan& p, const double* theta, apx_lm_state* lm, hipStream_t st);
+hipError_t launch_lm_accept(const Plan& p, const double* chi2_trial, double* theta,
+                            apx_lm_state* lm, hipStream_t st);
+
+}  // namespace apx

@@ -1,0 +1,211 @@
+// Direct-mode PSF convolution (§2.1.3) for gfx950.
+//
+// out(y, x) = sum_{U,V} K[U][V] * in(y - U + c, x - V + c), in = 0 outside its rectangle.
+//
+// One workgroup (4 wave64s) owns a CV_TH x CV_TW output tile.  The input tile with its
+// (P-1) halo is staged once into LDS; each lane then produces CV_R consecutive outputs
+// of one row: per PSF row it loads a CV_R + P - 1 register window from LDS (ds_read_b128)
+// and runs P x CV_R FMAs whose PSF operand is wave-uniform (scalar loads), so the VALU
+// does useful FMAs at ~CV_R*P per (CV_R+P-1)/4 LDS instructions.  Each PSF row is summed
+// into a fresh partial before being added to the accumulator (error ~2P ulp, not P^2).
+//
+// Epilogues (template KIND):
+//   CONV_FWD  model + sky, optional model store, FP32 residual store, FP64 partials of
+//             sum w r^2, sum w r, sum w (chi^2 of Eq. chi2, sky gradient, sky-sky entry);
+//   CONV_JCOL Jacobian column store, FP64 partials of sum w r J, sum w J;
+//   CONV_ADJ  input is -2 w r staged from the residual (the adjoint seed), PSF flipped,
+//             output is dchi2/dS on the extended grid.
+#pragma once
+#include "apx_internal.h"
+
+namespace apx {
+
+__device__ __forceinline__ double conv_wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// T is the arithmetic type of the staged input and the accumulators: float for the
+// Jacobian and adjoint passes, double for the FP64 objective.
+template <int P, int KIND, typename T = float>
+__global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict__ jobs,
+                                              const ConvItem* __restrict__ items, int item_begin,
+                                              ConvIO io) {
+    constexpr int c = (P - 1) / 2;
+    constexpr int LH = CV_TH + P - 1;
+    constexpr int LW0 = CV_TW + P - 1;
+    constexpr int LW = (LW0 + 3) & ~3;
+    __shared__ __attribute__((aligned(16))) T tile[LH * LW];
+    __shared__ double red[4][3];
+
+    const int item_idx = item_begin + (int)blockIdx.x;
+    const ConvItem it = items[item_idx];
+    const ConvJob jb = jobs[it.job];
+    const DImage& im = p.images[jb.image];
+    if (io.skip_mode == 1) {
+        if (p.lmf[im.sub].chol_done == 0 || p.lmf[im.sub].trial_bad != 0) return;
+    } else if (io.skip_mode == 2) {
+        if (io.lm[im.sub].need_jac == 0) return;
+    }
+    const int oy0 = jb.out_y0 + it.ty * CV_TH;
+    const int ox0 = jb.out_x0 + it.tx * CV_TW;
+    const int iy_base = oy0 - c, ix_base = ox0 - c;
+
+    // ---- stage the input tile (zero outside the input rectangle)
+    if constexpr (KIND == CONV_ADJ) {
+        for (int e = threadIdx.x; e < LH * LW0; e += 256) {
+            const int ly = e / LW0, lx = e - ly * LW0;
+            const int y = iy_base + ly, x = ix_base + lx;
+            float v = 0.f;
+            if (y >= 0 && y < im.H && x >= 0 && x < im.W) {
+                const long long pix = im.pix_off + (long long)y * im.W + x;
+                v = -2.f * io.weight[pix] * p.rbuf[pix];
+            }
+            tile[ly * LW + lx] = v;
+        }
+    } else {
+        const T* __restrict__ in;
+        if constexpr (sizeof(T) == 8) in = io.in64 + jb.in_off + (long long)it.ch * jb.in_cs;
+        else in = io.in + jb.in_off + (long long)it.ch * jb.in_cs;
+        const int iy1 = jb.in_y0 + jb.in_h, ix1 = jb.in_x0 + jb.in_w;
+        for (int e = threadIdx.x; e < LH * LW0; e += 256) {
+            const int ly = e / LW0, lx = e - ly * LW0;
+            const int y = iy_base + ly, x = ix_base + lx;
+            T v = 0;
+            if (y >= jb.in_y0 && y < iy1 && x >= jb.in_x0 && x < ix1)
+                v = in[(long long)(y - jb.in_y0) * jb.in_w + (x - jb.in_x0)];
+            tile[ly * LW + lx] = v;
+        }
+    }
+    __syncthreads();
+
+    // ---- register-window convolution
+    const int ty = (int)threadIdx.x >> 3, tx = (int)threadIdx.x & 7;
+    const float* __restrict__ K = (KIND == CONV_ADJ ? p.psf_flip : p.psf) + im.psf_off;
+    T acc[CV_R];
+#pragma unroll
+    for (int r = 0; r < CV_R; ++r) acc[r] = 0;
+    for (int U = 0; U < P; ++U) {
+        const T* row = tile + (ty + P - 1 - U) * LW + tx * CV_R;
+        T s[CV_R + P - 1];
+#pragma unroll
+        for (int k = 0; k < CV_R + P - 1; ++k) s[k] = row[k];
+        T part[CV_R];
+#pragma unroll
+        for (int r = 0; r < CV_R; ++r) part[r] = 0;
+#pragma unroll
+        for (int V = 0; V < P; ++V) {
+            const T kv = (T)K[U * P + V];
+#pragma unroll
+            for (int r = 0; r < CV_R; ++r) part[r] = fma(kv, s[r + P - 1 - V], part[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < CV_R; ++r) acc[r] += part[r];
+    }
+
+    // ---- epilogue
+    const int y = oy0 + ty;
+    const bool yok = y < jb.out_y0 + jb.out_h;
+    const int xb = ox0 + tx * CV_R;
+    const int xend = jb.out_x0 + jb.out_w;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if constexpr (KIND == CONV_FWD) {
+        const T sky = (T)p.sky_val[jb.image];
+        double c2 = 0.0, swr = 0.0, sw = 0.0;
+        if (yok) {
+            const long long rowpix = im.pix_off + (long long)y * im.W;
+#pragma unroll
+            for (int r = 0; r < CV_R; ++r) {
+                const int x = xb + r;
+                if (x < xend) {
+                    const T m = acc[r] + sky;
+                    const long long pix = rowpix + x;
+                    if (io.out) io.out[pix] = (float)m;
+                    if (io.data) {
+                        const double w = (double)io.weight[pix];
+                        const double rr = (double)io.data[pix] - (double)m;
+                        c2 += w * rr * rr;
+                        swr += w * rr;
+                        sw += w;
+                        p.rbuf[pix] = (float)rr;
+                    }
+                }
+            }
+        }
+        if (io.data) {
+            c2 = conv_wave_sum(c2);
+            swr = conv_wave_sum(swr);
+            sw = conv_wave_sum(sw);
+            if (lane == 0) { red[wv][0] = c2; red[wv][1] = swr; red[wv][2] = sw; }
+            __syncthreads();
+            if (threadIdx.x < 3) {
+                const int q = threadIdx.x;
+                io.part[(long long)item_idx * 3 + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+            }
+        }
+    } else if constexpr (KIND == CONV_JCOL) {
+        float* __restrict__ out = io.out + jb.out_off + (long long)it.ch * jb.out_cs;
+        double s1 = 0.0, s2 = 0.0;
+        if (yok) {
+            const long long orow = (long long)(y - jb.out_y0) * jb.out_w - jb.out_x0;
+            const long long rowpix = im.pix_off + (long long)y * im.W;
+#pragma unroll
+            for (int r = 0; r < CV_R; ++r) {
+                const int x = xb + r;
+                if (x < xend) {
+                    out[orow + x] = acc[r];
+                    if (io.weight) {
+                        const double wj = (double)io.weight[rowpix + x] * (double)acc[r];
+                        s1 += wj * (double)p.rbuf[rowpix + x];
+                        s2 += wj;
+                    }
+                }
+            }
+        }
+        if (io.weight) {
+            s1 = conv_wave_sum(s1);
+            s2 = conv_wave_sum(s2);
+            if (lane == 0) { red[wv][0] = s1; red[wv][1] = s2; }
+            __syncthreads();
+            if (threadIdx.x < 2) {
+                const int q = threadIdx.x;
+                io.part[(long long)item_idx * 2 + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+            }
+        }
+    } else {
+        float* __restrict__ out = io.out + jb.out_off;
+        if (yok) {
+            const long long orow = (long long)(y - jb.out_y0) * jb.out_w - jb.out_x0;
+#pragma unroll
+            for (int r = 0; r < CV_R; ++r) {
+                const int x = xb + r;
+                if (x < xend) out[orow + x] = acc[r];
+            }
+        }
+    }
+}
+
+#define APX_FOR_EACH_P(X)                                                                     \
+    X(1) X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29)     \
+    X(31) X(33) X(35) X(37) X(39) X(41) X(43) X(45) X(47) X(49) X(51) X(53) X(55) X(57)      \
+    X(59) X(61) X(63)
+
+template <int KIND, typename T = float>
+hipError_t launch_conv_kind(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st) {
+    if (L.item_count <= 0) return hipSuccess;
+    dim3 grid(L.item_count), block(256);
+    switch (L.P) {
+#define APX_CASE(PP)                                                                         \
+    case PP:                                                                                 \
+        hipLaunchKernelGGL((k_conv<PP, KIND, T>), grid, block, 0, st, p, L.jobs, L.items,    \
+                           L.item_begin, io);                                               \
+        break;
+        APX_FOR_EACH_P(APX_CASE)
+#undef APX_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace apx

@@ -1,0 +1,233 @@
+// Normal-equation kernels: J^T W J tiles on FP64 MFMA, ordered reductions and the
+// assembly of J^T W J, J^T W r, chi^2 and the gradient from their partial sums.
+//
+// A_pq = sum_i w_i J_ip J_iq (§2.5, the Gauss-Newton Hessian of Eq. chi2).  Columns of
+// one group share an output box; the product of two groups runs over the intersection
+// of their boxes.  FP32 Jacobian entries are promoted to FP64 (w J_p is exact in FP64),
+// staged in LDS and contracted with v_mfma_f64_16x16x4_f64; every tile of every
+// K-slice is written to its own slot and summed later in a fixed order, so the result
+// does not depend on scheduling.
+#include "apx_internal.h"
+
+namespace apx {
+
+typedef double apx_d4 __attribute__((ext_vector_type(4)));
+
+// TM = 64: 4 waves as 2 x 2 blocks of 32 x 32 (2 x 2 MFMA tiles each).
+// TM = 16: 4 waves share one 16 x 16 tile and split each LDS stage along K.
+template <int TM>
+__global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ pairs,
+                                              const PairItem* __restrict__ items,
+                                              const float* __restrict__ weight,
+                                              const apx_lm_state* lm) {
+    constexpr int KC = PAIR_KC;
+    __shared__ double As[TM][KC + 1];
+    __shared__ double Bs[TM][KC + 1];
+    const PairItem it = items[blockIdx.x];
+    const DPair pr = pairs[it.pair];
+    if (lm && lm[pr.sub].need_jac == 0) return;
+    const DGroup& G = p.groups[pr.g];
+    const DGroup& Hh = p.groups[pr.h];
+    const DImage& im = p.images[pr.image];
+    const long long gs = (long long)G.oh * G.ow, hs = (long long)Hh.oh * Hh.ow;
+    const float* __restrict__ Jg = p.J + G.j_off;
+    const float* __restrict__ Jh = p.J + Hh.j_off;
+    const int a0 = it.ta * TM, b0 = it.tb * TM;
+    const int ncg = G.ncols, nch = Hh.ncols;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int NB = TM == 64 ? 2 : 1;
+    const int wr = TM == 64 ? (wv >> 1) : 0, wc = TM == 64 ? (wv & 1) : 0;
+    apx_d4 acc[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = (apx_d4){0.0, 0.0, 0.0, 0.0};
+
+    for (int row = it.r0; row < it.r1; ++row) {
+        const long long rowpix = im.pix_off + (long long)row * im.W;
+        const long long grow = (long long)(row - G.oy0) * G.ow - G.ox0;
+        const long long hrow = (long long)(row - Hh.oy0) * Hh.ow - Hh.ox0;
+        for (int xs = pr.x0; xs < pr.x1; xs += KC) {
+            for (int e = threadIdx.x; e < TM * KC; e += 256) {
+                const int i = e / KC, k = e - (e / KC) * KC;
+                const int x = xs + k;
+                double av = 0.0, bv = 0.0;
+                if (x < pr.x1) {
+                    const int ca = a0 + i, cb = b0 + i;
+                    if (ca < ncg) av = (double)Jg[ca * gs + grow + x] * (double)weight[rowpix + x];
+                    if (cb < nch) bv = (double)Jh[cb * hs + hrow + x];
+                }
+                As[i][k] = av;
+                Bs[i][k] = bv;
+            }
+            __syncthreads();
+            if constexpr (TM == 64) {
+#pragma unroll
+                for (int kk = 0; kk < KC; kk += 4) {
+                    double av[NB], bv[NB];
+#pragma unroll
+                    for (int m = 0; m < NB; ++m) av[m] = As[wr * 32 + m * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) bv[n] = Bs[wc * 32 + n * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+                    for (int m = 0; m < NB; ++m)
+#pragma unroll
+                        for (int n = 0; n < NB; ++n)
+                            acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
+                }
+            } else {
+                const int kk = 4 * wv;
+                const double av = As[lane & 15][kk + (lane >> 4)];
+                const double bv = Bs[lane & 15][kk + (lane >> 4)];
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[0][0], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+    }
+
+    double* out = p.pair_part + it.out_off;
+    if constexpr (TM == 64) {
+#pragma unroll
+        for (int m = 0; m < NB; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    // v_mfma_f64_16x16x4: D[i][j] sits in lane j + 16 (i % 4), register i / 4
+                    const int i = wr * 32 + m * 16 + (lane >> 4) + 4 * v;
+                    const int j = wc * 32 + n * 16 + (lane & 15);
+                    out[i * TM + j] = acc[m][n][v];
+                }
+    } else {
+        // reduce the four K-slices in a fixed order
+        __shared__ double red[4][256];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wv][((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[0][0][v];
+        __syncthreads();
+        const int t = threadIdx.x;
+        out[t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    }
+}
+
+hipError_t launch_pairs(const Plan& p, const PairLaunch& L, const float* weight,
+                        const apx_lm_state* lm, hipStream_t st) {
+    if (L.n_items <= 0) return hipSuccess;
+    if (L.tm == 64)
+        hipLaunchKernelGGL(k_pair<64>, dim3(L.n_items), dim3(256), 0, st, p, L.pairs, L.items, weight, lm);
+    else
+        hipLaunchKernelGGL(k_pair<16>, dim3(L.n_items), dim3(256), 0, st, p, L.pairs, L.items, weight, lm);
+    return hipGetLastError();
+}
+
+// out[s*ostride + ocomp] = sum_k wts[k] * src[(idx ? idx[k] : k) * stride + comp], k in
+// [seg[s], seg[s+1]), summed left to right.  Segments of sub-problems that do not need
+// a new Jacobian are skipped when lm is given.
+__global__ void k_segsum(SegSum a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n_seg) return;
+    if (a.lm && a.seg_sub && a.lm[a.seg_sub[s]].need_jac == 0) return;
+    double acc = 0.0;
+    for (int k = a.seg[s]; k < a.seg[s + 1]; ++k) {
+        const long long j = a.idx ? (long long)a.idx[k] : (long long)k;
+        const double v = a.src[j * a.stride + a.comp];
+        acc += a.wts ? a.wts[k] * v : v;
+    }
+    a.out[(long long)s * a.ostride + a.ocomp] = acc * a.scale;
+}
+
+hipError_t launch_segsum(const SegSum& a, hipStream_t st) {
+    if (a.n_seg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_segsum, dim3((a.n_seg + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// J^T W J assembly: every upper entry (sub, a <= b) sums its sources in list order and
+// is written to both (a, b) and (b, a) of its sub-problem's row-major block.
+__global__ void k_assemble_A(AsmA a) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.n_ent) return;
+    const int s = a.ent_sub[e];
+    if (a.lm && a.lm[s].need_jac == 0) return;
+    double acc = 0.0;
+    for (long long k = a.ent_off[e]; k < a.ent_off[e + 1]; ++k) acc += a.src[a.ent_src[k]];
+    const DSub sb = a.subs[s];
+    const int r = a.ent_row[e], c = a.ent_col[e];
+    a.out[sb.a_off + (long long)r * sb.n + c] = acc;
+    a.out[sb.a_off + (long long)c * sb.n + r] = acc;
+}
+
+hipError_t launch_assemble_A(const AsmA& a, hipStream_t st) {
+    if (a.n_ent <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_assemble_A, dim3((unsigned)((a.n_ent + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// Dense Jacobian for callers that want it: J[k * ldJ + i] = sum of the stored blocks of
+// the columns tied to theta index k (in column order) + 1 on the pixels of images whose
+// sky is theta index k.
+__global__ void k_jscatter(Plan p, const int* __restrict__ par_off, const int* __restrict__ par_cols,
+                           const int* __restrict__ par_sky_off, const int* __restrict__ par_sky,
+                           float* __restrict__ Jd, long long ldJ) {
+    const int k = blockIdx.y;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n_pix) return;
+    // image of pixel i (binary search on pix_off)
+    int lo = 0, hi = p.n_images - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p.images[mid].pix_off <= i) lo = mid; else hi = mid - 1;
+    }
+    const DImage& im = p.images[lo];
+    const long long local = i - im.pix_off;
+    const int y = (int)(local / im.W), x = (int)(local - (long long)y * im.W);
+    float v = 0.f;
+    for (int q = par_off[k]; q < par_off[k + 1]; ++q) {
+        const DCol cl = p.cols[par_cols[q]];
+        const DGroup& g = p.groups[cl.group];
+        if (g.image != lo) continue;
+        if (y < g.oy0 || y >= g.oy0 + g.oh || x < g.ox0 || x >= g.ox0 + g.ow) continue;
+        const int ci = par_cols[q] - g.col_begin;
+        v += p.J[g.j_off + (long long)ci * g.oh * g.ow + (long long)(y - g.oy0) * g.ow + (x - g.ox0)];
+    }
+    for (int q = par_sky_off[k]; q < par_sky_off[k + 1]; ++q)
+        if (par_sky[q] == lo) v += 1.f;
+    Jd[(long long)k * ldJ + i] = v;
+}
+
+hipError_t launch_jscatter(const Plan& p, const int* par_off, const int* par_cols,
+                           const int* par_sky_off, const int* par_sky, float* Jd, long long ldJ,
+                           hipStream_t st) {
+    if (p.n_par == 0 || p.n_pix == 0) return hipSuccess;
+    dim3 grid((unsigned)((p.n_pix + 255) / 256), p.n_par);
+    hipLaunchKernelGGL(k_jscatter, grid, dim3(256), 0, st, p, par_off, par_cols, par_sky_off,
+                       par_sky, Jd, ldJ);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_d(double* x, long long n, double v) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+hipError_t launch_fill(double* x, long long n, double v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    long long b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(k_fill_d, dim3((unsigned)b), dim3(256), 0, st, x, n, v);
+    return hipGetLastError();
+}
+
+// Sticky non-finite flag from per-sub chi^2 values.
+__global__ void k_chi2_check(const double* chi2, int n, int* sticky) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n && !isfinite(chi2[s])) atomicOr(sticky, FLAG_NONFINITE);
+}
+
+hipError_t launch_chi2_check(const double* chi2, int n, int* sticky, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chi2_check, dim3((n + 255) / 256), dim3(256), 0, st, chi2, n, sticky);
+    return hipGetLastError();
+}
+
+}  // namespace apx

@@ -1,0 +1,440 @@
+// Levenberg-Marquardt kernels (§2.5): Marquardt-damped normal equations solved by FP64
+// Cholesky on the device, with the damping raised and the factorisation retried when a
+// pivot is not positive (the step never meets a singular matrix), the trial step, and
+// the gain-ratio accept/reject with lambda update.  All control stays on the device so
+// an iteration can be captured in a HIP graph; every sub-problem carries its own state.
+#include "apx_internal.h"
+
+namespace apx {
+
+__device__ __forceinline__ double lm_wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double lm_wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ void k_lm_begin(Plan p) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n_sub) return;
+    LMFlags f;
+    f.chol_done = 0;
+    f.chol_fail = 0;
+    f.trial_bad = 0;
+    f.skip = 0;
+    p.lmf[s] = f;
+}
+
+hipError_t launch_lm_begin(const Plan& p, apx_lm_state* lm, hipStream_t st) {
+    (void)lm;
+    hipLaunchKernelGGL(k_lm_begin, dim3((p.n_sub + 255) / 256), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+__global__ void k_lm_init(Plan p, const double* chi2_sub, apx_lm_state* lm) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n_sub) return;
+    apx_lm_state st;
+    st.lambda = APX_LM_LAMBDA0;
+    st.chi2 = chi2_sub[s];
+    st.chi2_trial = 0.0;
+    st.pred = 0.0;
+    st.rho = 0.0;
+    st.need_jac = 1;
+    st.accepted = 0;
+    st.n_accept = 0;
+    st.n_reject = 0;
+    st.n_chol_retry = 0;
+    st.status = isfinite(st.chi2) ? APX_OK : APX_E_NONFINITE;
+    lm[s] = st;
+}
+
+hipError_t launch_lm_init(const Plan& p, const double* chi2_sub, apx_lm_state* lm, hipStream_t st) {
+    hipLaunchKernelGGL(k_lm_init, dim3((p.n_sub + 255) / 256), dim3(256), 0, st, p, chi2_sub, lm);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- small sub-problems
+// One wave64 per sub-problem (n <= 64): the damped matrix, its factor and the step
+// live in LDS; the retries happen inside the kernel.
+__global__ __launch_bounds__(64) void k_chol_small(Plan p, const int* __restrict__ small_subs,
+                                                   int nmax, apx_lm_state* lm) {
+    extern __shared__ double sm[];
+    const int s = small_subs[blockIdx.x];
+    const DSub sb = p.subs[s];
+    const int n = sb.n, ld = nmax + 1;
+    double* M = sm;
+    double* y = sm + (long long)nmax * ld;
+    const int i = threadIdx.x;
+    const double* A = p.A + sb.a_off;
+    const double* g = p.gvec + sb.p0;
+    if (n == 0) {
+        if (i == 0) { p.lmf[s].chol_done = 1; lm[s].pred = 0.0; }
+        return;
+    }
+    const double di = i < n ? A[(long long)i * n + i] : 0.0;
+    const double dmax = lm_wave_max(i < n ? di : -1e308);
+    const double Di = fmax(di, APX_LM_DAMP_FLOOR * dmax);
+    double lam = lm[s].lambda;
+    int done = 0, retries = 0;
+    for (int att = 0; att < APX_LM_ATTEMPTS; ++att) {
+        if (i < n)
+            for (int j = 0; j <= i; ++j) M[i * ld + j] = A[(long long)i * n + j] + (i == j ? lam * Di : 0.0);
+        __syncthreads();
+        bool ok = true;
+        for (int k = 0; k < n; ++k) {
+            const double piv = M[k * ld + k];
+            if (!(piv > 0.0) || !isfinite(piv)) { ok = false; break; }
+            const double lkk = sqrt(piv);
+            __syncthreads();
+            if (i == k) M[k * ld + k] = lkk;
+            if (i > k && i < n) M[i * ld + k] = M[i * ld + k] / lkk;
+            __syncthreads();
+            if (i > k && i < n) {
+                const double lik = M[i * ld + k];
+                for (int j = k + 1; j <= i; ++j) M[i * ld + j] -= lik * M[j * ld + k];
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        if (ok) { done = 1; break; }
+        lam = fmin(lam * APX_LM_UP, APX_LM_LAMBDA_MAX);
+        ++retries;
+    }
+    double h = 0.0;
+    if (done) {
+        if (i < n) y[i] = g[i];
+        __syncthreads();
+        for (int k = 0; k < n; ++k) {
+            if (i == k) y[k] = y[k] / M[k * ld + k];
+            __syncthreads();
+            if (i > k && i < n) y[i] -= M[i * ld + k] * y[k];
+            __syncthreads();
+        }
+        for (int k = n - 1; k >= 0; --k) {
+            if (i == k) y[k] = y[k] / M[k * ld + k];
+            __syncthreads();
+            if (i < k) y[i] -= M[k * ld + i] * y[k];
+            __syncthreads();
+        }
+        if (i < n) h = y[i];
+    }
+    const double pr = lm_wave_sum(i < n ? h * (lam * Di * h + g[i]) : 0.0);
+    if (i < n) {
+        p.hvec[sb.p0 + i] = h;
+        p.Ddiag[sb.p0 + i] = Di;
+    }
+    if (i == 0) {
+        lm[s].lambda = lam;
+        lm[s].pred = pr;
+        lm[s].n_chol_retry += retries;
+        p.lmf[s].chol_done = done;
+    }
+}
+
+hipError_t launch_chol_small(const Plan& p, const int* small_subs, int n_small, int nmax,
+                             apx_lm_state* lm, hipStream_t st) {
+    if (n_small <= 0) return hipSuccess;
+    const size_t lds = (size_t)nmax * (nmax + 1) * sizeof(double) + (size_t)nmax * sizeof(double);
+    hipLaunchKernelGGL(k_chol_small, dim3(n_small), dim3(64), lds, st, p, small_subs, nmax, lm);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- large sub-problems
+// Right-looking blocked Cholesky (block CHOL_NB) over a sequence of launches, each
+// attempt guarded by the sub-problem's flags so the sequence is fixed and capturable.
+__global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
+    // one block: damping diagonal D and its maximum
+    __shared__ double red[4];
+    const DSub sb = p.subs[s];
+    const int n = sb.n;
+    const double* A = p.A + sb.a_off;
+    double m = -1e308;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, A[(long long)i * n + i]);
+    m = lm_wave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        p.Ddiag[sb.p0 + i] = fmax(A[(long long)i * n + i], APX_LM_DAMP_FLOOR * dmax);
+}
+
+__global__ void k_chol_attempt_begin(Plan p, int s, int attempt, apx_lm_state* lm) {
+    if (p.lmf[s].chol_done) return;
+    if (attempt > 0) {
+        lm[s].lambda = fmin(lm[s].lambda * APX_LM_UP, APX_LM_LAMBDA_MAX);
+        lm[s].n_chol_retry += 1;
+    }
+    p.lmf[s].chol_fail = 0;
+}
+
+__global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
+    if (p.lmf[s].chol_done) return;
+    const DSub sb = p.subs[s];
+    const int n = sb.n;
+    const double lam = lm[s].lambda;
+    const long long nn = (long long)n * n;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+        double v = p.A[sb.a_off + e];
+        if (i == j) v += lam * p.Ddiag[sb.p0 + i];
+        p.M[sb.a_off + e] = v;
+    }
+}
+
+// Block k: every workgroup factors the diagonal block in LDS (redundantly); workgroup
+// 0 stores it and reports a non-positive pivot, workgroup b > 0 solves row block k+b.
+__global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
+    __shared__ double L[CHOL_NB][CHOL_NB + 1];
+    __shared__ int bad;
+    if (p.lmf[s].chol_done || p.lmf[s].chol_fail) return;
+    const DSub sb = p.subs[s];
+    const int n = sb.n;
+    double* Mg = p.M + sb.a_off;
+    const int kb = kblk * CHOL_NB;
+    const int nb = min(CHOL_NB, n - kb);
+    const int t = threadIdx.x;
+    for (int e = t; e < nb * nb; e += 256) {
+        const int i = e / nb, j = e - (e / nb) * nb;
+        L[i][j] = j <= i ? Mg[(long long)(kb + i) * n + kb + j] : 0.0;
+    }
+    if (t == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        const double piv = L[j][j];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            if (t == 0) bad = 1;
+            break;
+        }
+        const double ljj = sqrt(piv);
+        __syncthreads();
+        if (t == 0) L[j][j] = ljj;
+        for (int i = j + 1 + t; i < nb; i += 256) L[i][j] = L[i][j] / ljj;
+        __syncthreads();
+        const int m = nb - j - 1;                   // trailing lower triangle of size m
+        for (int e = t; e < m * m; e += 256) {
+            const int i = j + 1 + e / m, q = j + 1 + (e - (e / m) * m);
+            if (q <= i) L[i][q] -= L[i][j] * L[q][j];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+        if (blockIdx.x == 0 && t == 0) p.lmf[s].chol_fail = 1;
+        return;
+    }
+    if (blockIdx.x == 0) {
+        for (int e = t; e < nb * nb; e += 256) {
+            const int i = e / nb, j = e - (e / nb) * nb;
+            if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[i][j];
+        }
+        return;
+    }
+    // row block rb: X L^T = M_rk  ->  x_j = (m_j - sum_{q<j} x_q L_jq) / L_jj, rows in LDS
+    const int rb = kb + blockIdx.x * CHOL_NB;
+    if (rb >= n) return;
+    const int nr = min(CHOL_NB, n - rb);
+    __shared__ double X[CHOL_NB][CHOL_NB + 1];
+    for (int e = t; e < nr * nb; e += 256) {
+        const int i = e / nb, j = e - (e / nb) * nb;
+        X[i][j] = Mg[(long long)(rb + i) * n + kb + j];
+    }
+    __syncthreads();
+    if (t < nr) {
+        for (int j = 0; j < nb; ++j) {
+            double v = X[t][j];
+            for (int q = 0; q < j; ++q) v -= X[t][q] * L[j][q];
+            X[t][j] = v / L[j][j];
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < nr * nb; e += 256) {
+        const int i = e / nb, j = e - (e / nb) * nb;
+        Mg[(long long)(rb + i) * n + kb + j] = X[i][j];
+    }
+}
+
+// Trailing update M_ij -= L_ik L_jk^T for block pairs k < j <= i, 4 x 4 outputs per lane.
+__global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, int nblk) {
+    __shared__ double Li[CHOL_NB][17], Lj[CHOL_NB][17];
+    if (p.lmf[s].chol_done || p.lmf[s].chol_fail) return;
+    const DSub sb = p.subs[s];
+    const int n = sb.n;
+    double* Mg = p.M + sb.a_off;
+    // block index -> (bi, bj), bj <= bi, both in (kblk, nblk)
+    const int T = nblk - kblk - 1;
+    int e = blockIdx.x, bi = 0;
+    while (e >= bi + 1) { e -= bi + 1; ++bi; }
+    const int bj = e;                               // 0 <= bj <= bi < T
+    const int ri = (kblk + 1 + bi) * CHOL_NB, rj = (kblk + 1 + bj) * CHOL_NB, kc = kblk * CHOL_NB;
+    (void)T;
+    const int ni = min(CHOL_NB, n - ri), nj = min(CHOL_NB, n - rj), nk = min(CHOL_NB, n - kc);
+    const int t = threadIdx.x;
+    const int ti = (t >> 4) * 4, tj = (t & 15) * 4;
+    double acc[4][4];
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int k0 = 0; k0 < nk; k0 += 16) {
+        for (int q = t; q < CHOL_NB * 16; q += 256) {
+            const int r = q >> 4, k = q & 15;
+            Li[r][k] = (r < ni && k0 + k < nk) ? Mg[(long long)(ri + r) * n + kc + k0 + k] : 0.0;
+            Lj[r][k] = (r < nj && k0 + k < nk) ? Mg[(long long)(rj + r) * n + kc + k0 + k] : 0.0;
+        }
+        __syncthreads();
+        for (int k = 0; k < 16; ++k) {
+            double a[4], b[4];
+            for (int u = 0; u < 4; ++u) { a[u] = Li[ti + u][k]; b[u] = Lj[tj + u][k]; }
+            for (int u = 0; u < 4; ++u)
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            const int i = ti + u, j = tj + v;
+            if (i < ni && j < nj && (bi != bj || j <= i))
+                Mg[(long long)(ri + i) * n + rj + j] -= acc[u][v];
+        }
+}
+
+__global__ void k_chol_attempt_end(Plan p, int s) {
+    if (p.lmf[s].chol_done) return;
+    if (!p.lmf[s].chol_fail) p.lmf[s].chol_done = 1;
+}
+
+// Forward and back substitution with the stored factor; pred = h^T (lambda D h + g).
+__global__ __launch_bounds__(1024) void k_chol_solve(Plan p, int s, apx_lm_state* lm) {
+    extern __shared__ double y[];
+    __shared__ double red[16];
+    const DSub sb = p.subs[s];
+    const int n = sb.n;
+    const double* L = p.M + sb.a_off;
+    const double* g = p.gvec + sb.p0;
+    const int t = threadIdx.x;
+    const bool done = p.lmf[s].chol_done != 0;
+    if (!done) {
+        for (int i = t; i < n; i += blockDim.x) p.hvec[sb.p0 + i] = 0.0;
+        if (t == 0) lm[s].pred = 0.0;
+        return;
+    }
+    for (int i = t; i < n; i += blockDim.x) y[i] = g[i];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (t == 0) y[k] = y[k] / L[(long long)k * n + k];
+        __syncthreads();
+        const double yk = y[k];
+        for (int i = k + 1 + t; i < n; i += blockDim.x) y[i] -= L[(long long)i * n + k] * yk;
+        __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        if (t == 0) y[k] = y[k] / L[(long long)k * n + k];
+        __syncthreads();
+        const double yk = y[k];
+        for (int i = t; i < k; i += blockDim.x) y[i] -= L[(long long)k * n + i] * yk;
+        __syncthreads();
+    }
+    const double lam = lm[s].lambda;
+    double v = 0.0;
+    for (int i = t; i < n; i += blockDim.x) {
+        const double h = y[i];
+        p.hvec[sb.p0 + i] = h;
+        v += h * (lam * p.Ddiag[sb.p0 + i] * h + g[i]);
+    }
+    v = lm_wave_sum(v);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+        double a = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += red[w];
+        lm[s].pred = a;
+    }
+}
+
+hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipStream_t st) {
+    const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
+    hipLaunchKernelGGL(k_chol_damp, dim3(1), dim3(256), 0, st, p, s, lm);
+    const long long nn = (long long)n * n;
+    long long fb = (nn + 255) / 256;
+    if (fb > 4096) fb = 4096;
+    for (int att = 0; att < APX_LM_ATTEMPTS; ++att) {
+        hipLaunchKernelGGL(k_chol_attempt_begin, dim3(1), dim3(1), 0, st, p, s, att, lm);
+        hipLaunchKernelGGL(k_chol_fill, dim3((unsigned)fb), dim3(256), 0, st, p, s, lm);
+        for (int k = 0; k < nblk; ++k) {
+            hipLaunchKernelGGL(k_chol_panel, dim3(nblk - k), dim3(256), 0, st, p, s, k);
+            const int T = nblk - k - 1;
+            if (T > 0)
+                hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk);
+        }
+        hipLaunchKernelGGL(k_chol_attempt_end, dim3(1), dim3(1), 0, st, p, s);
+    }
+    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, p, s, lm);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------- trial/accept
+__global__ void k_lm_trial(Plan p, const double* __restrict__ theta) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= p.n_par) return;
+    const int s = p.par_sub[k];
+    double v = theta[k];
+    if (s >= 0 && p.lmf[s].chol_done) v += p.hvec[k];
+    p.theta_trial[k] = v;
+}
+
+hipError_t launch_lm_trial(const Plan& p, const double* theta, apx_lm_state* lm, hipStream_t st) {
+    (void)lm;
+    if (p.n_par == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lm_trial, dim3((p.n_par + 255) / 256), dim3(256), 0, st, p, theta);
+    return hipGetLastError();
+}
+
+__global__ void k_lm_accept(Plan p, const double* __restrict__ chi2_trial, double* theta,
+                            apx_lm_state* lm) {
+    __shared__ int acc_flag;
+    const int s = blockIdx.x;
+    const DSub sb = p.subs[s];
+    if (threadIdx.x == 0) {
+        apx_lm_state st = lm[s];
+        const LMFlags f = p.lmf[s];
+        int accept = 0;
+        if (!f.chol_done) {
+            st.chi2_trial = __builtin_nan("");
+            st.rho = __builtin_nan("");
+        } else if (f.trial_bad) {
+            st.chi2_trial = __builtin_inf();
+            st.rho = -__builtin_inf();
+            st.lambda = fmin(st.lambda * APX_LM_UP, APX_LM_LAMBDA_MAX);
+        } else {
+            const double c2t = chi2_trial[s];
+            const double rho = st.pred != 0.0 ? (st.chi2 - c2t) / st.pred : __builtin_nan("");
+            st.chi2_trial = c2t;
+            st.rho = rho;
+            if (rho > APX_LM_EPS4) {
+                accept = 1;
+                st.chi2 = c2t;
+                st.lambda = fmax(st.lambda / APX_LM_DOWN, APX_LM_LAMBDA_MIN);
+            } else {
+                st.lambda = fmin(st.lambda * APX_LM_UP, APX_LM_LAMBDA_MAX);
+            }
+        }
+        st.accepted = accept;
+        st.need_jac = accept;
+        if (accept) st.n_accept += 1; else st.n_reject += 1;
+        lm[s] = st;
+        acc_flag = accept;
+    }
+    __syncthreads();
+    if (acc_flag)
+        for (int k = threadIdx.x; k < sb.n; k += blockDim.x) theta[sb.p0 + k] = p.theta_trial[sb.p0 + k];
+}
+
+hipError_t launch_lm_accept(const Plan& p, const double* chi2_trial, double* theta,
+                            apx_lm_state* lm, hipStream_t st) {
+    hipLaunchKernelGGL(k_lm_accept, dim3(p.n_sub), dim3(64), 0, st, p, chi2_trial, theta, lm);
+    return hipGetLastError();
+}
+
+}  // namespace apx

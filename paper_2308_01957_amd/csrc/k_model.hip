@@ -1,0 +1,437 @@
+// Component evaluation kernels: parameter preparation (b_n on the device), the
+// supersampled pre-convolution render, derivative images for the Jacobian and the
+// adjoint contraction for the chi^2 gradient.
+//
+// Profile (Sersic, §2.1.1): I(R) = Ie exp(-b_n ((R/Re)^(1/n) - 1)) with elliptical
+// R = sqrt(x'^2 + (y'/q)^2), x' = dx cos PA + dy sin PA, y' = -dx sin PA + dy cos PA.
+// It is evaluated as I = 2^(A - B t), t = 2^(g log2 R^2 - h) with A = log2 Ie + b log2 e,
+// B = b log2 e, g = 1/(2n), h = log2(Re)/n: three hardware transcendentals (v_log_f32,
+// v_exp_f32) per sub-pixel node, the exponent arithmetic in FP64 (full rate on CDNA4)
+// so the FP32 result carries only the transcendentals' rounding.
+// Pixel integration (§2.1.2): area * sum_k w_k I(node_k) over s x s nodes.
+#include "apx_internal.h"
+
+namespace apx {
+
+#define LN2F 0.69314718055994531f
+#define LN10F 2.3025850929940457f
+
+// -------------------------------------------------------------------- b_n on device
+// Regularised lower incomplete gamma P(a, x) by its power series, valid and fast for
+// 0 < x < a + 1 (always the case near the half-light root).
+__device__ double gammainc_lower_series(double a, double x) {
+    if (x <= 0.0) return 0.0;
+    double sum = 1.0, term = 1.0;
+    for (int k = 1; k < 2000; ++k) {
+        term *= x / (a + (double)k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return exp(a * log(x) - x - lgamma(a + 1.0)) * sum;
+}
+
+// b solving P(2n, b) = 1/2 by bracketed Newton; the bracket [2n-1, 2n+1/2] holds the
+// median of Gamma(2n) and lies inside the series' fast region.
+__device__ double sersic_bn_device(double n) {
+    const double a = 2.0 * n;
+    double lo = fmax(a - 1.0, 1e-12), hi = a + 0.5;
+    double b = a - 1.0 / 3.0 + 4.0 / (405.0 * n) + 46.0 / (25515.0 * n * n);
+    if (!(b > lo && b < hi)) b = 0.5 * (lo + hi);
+    const double lga = lgamma(a);
+    for (int it = 0; it < 200; ++it) {
+        double f = gammainc_lower_series(a, b) - 0.5;
+        if (f > 0.0) hi = b; else lo = b;
+        double fp = exp((a - 1.0) * log(b) - b - lga);
+        double bn = b - f / fp;
+        if (!(bn > lo && bn < hi)) bn = 0.5 * (lo + hi);
+        if (fabs(bn - b) <= 1e-16 * b || hi - lo <= 4e-16 * b) { b = bn; break; }
+        b = bn;
+    }
+    return b;
+}
+
+// ------------------------------------------------------------------------- prep
+__global__ void k_prep(Plan p, const double* __restrict__ theta, int lm_trial) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.n_images) {
+        const DImage& im = p.images[i];
+        const double sky = im.sky_par >= 0 ? theta[im.sky_par] : im.sky_fixed;
+        p.sky_val[i] = sky;
+        if (!isfinite(sky)) {
+            if (lm_trial) atomicOr(&p.lmf[im.sub].trial_bad, 1);
+            else atomicOr(p.sticky, FLAG_NONFINITE);
+        }
+    }
+    if (i >= p.n_comps) return;
+    const DComp cp = p.comps[i];
+    const DImage& im = p.images[cp.image];
+    double v[7];
+    bool finite = true;
+    for (int k = 0; k < 7; ++k) {
+        v[k] = cp.par[k] >= 0 ? theta[cp.par[k]] : cp.fixed[k];
+        finite = finite && isfinite(v[k]);
+    }
+    CompConst c;
+    c.x0 = c.y0 = c.cs_d = c.sn_d = c.q_d = c.kre = c.h_d = c.A_d = c.B_d = c.g_d = 0.0;
+    c.cs = c.sn = c.iq = c.g = c.b = c.bp = c.n = c.re = c.q = c.F = 0.f;
+    c.pad = 0;
+    c.F64 = 0.0;
+    bool valid = finite;
+    if (cp.type == APX_SERSIC) {
+        const double q = v[2], pa = v[3], n = v[4], re = v[5], lie = v[6];
+        valid = valid && q >= 0.01 && q <= 1.0 && n >= 0.36 && n <= 10.0 && re >= 0.01 && re <= 1e4;
+        if (valid) {
+            const double b = sersic_bn_device(n);
+            const double hstep = 1e-5;
+            const double bp = (sersic_bn_device(n + hstep) - sersic_bn_device(n - hstep)) / (2.0 * hstep);
+            const double log2e = 1.4426950408889634;
+            c.x0 = v[0];
+            c.y0 = v[1];
+            c.cs_d = cos(pa);
+            c.sn_d = sin(pa);
+            c.q_d = q;
+            c.kre = p.k_re * re;
+            c.h_d = log2(re) / n;
+            c.A_d = lie * 3.3219280948873622 + b * log2e;
+            c.B_d = b * log2e;
+            c.g_d = 0.5 / n;
+            c.cs = (float)c.cs_d;
+            c.sn = (float)c.sn_d;
+            c.iq = (float)(1.0 / q);
+            c.g = (float)(0.5 / n);
+            c.b = (float)b;
+            c.bp = (float)bp;
+            c.n = (float)n;
+            c.re = (float)re;
+            c.q = (float)q;
+        }
+    } else {
+        // point source: sky position -> pixel position of its image
+        const double ux = v[0], uy = v[1];
+        const double px = im.inv[0] + im.inv[1] * ux + im.inv[2] * uy;
+        const double py = im.inv[3] + im.inv[4] * ux + im.inv[5] * uy;
+        c.x0 = px;
+        c.y0 = py;
+        c.F64 = exp(v[2] * 2.302585092994046);
+        c.F = (float)c.F64;
+    }
+    c.valid = valid ? 1 : 0;
+    p.cc[i] = c;
+    if (!valid) {
+        if (lm_trial) atomicOr(&p.lmf[cp.sub].trial_bad, 1);
+        else atomicOr(p.sticky, FLAG_DOMAIN);
+    }
+}
+
+hipError_t launch_prep(const Plan& p, const double* theta, int lm_trial, hipStream_t st) {
+    const int n = p.n_comps > p.n_images ? p.n_comps : p.n_images;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prep, dim3((n + 127) / 128), dim3(128), 0, st, p, theta, lm_trial);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ samples
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+__device__ __forceinline__ float sersic_I(const CompConst& c, float dx, float dy) {
+    const float xp = fmaf(dx, c.cs, dy * c.sn);
+    const float yq = fmaf(dy, c.cs, -dx * c.sn) * c.iq;
+    const float R2 = fmaxf(fmaf(xp, xp, yq * yq), 1e-12f);
+    const double lt = fma((double)c.g, (double)fast_log2(R2), -c.h_d);
+    const float t = fast_exp2((float)lt);
+    return fast_exp2((float)fma(-c.B_d, (double)t, c.A_d));
+}
+
+// Adds wgt * dI/dtheta_k (k = x0, y0, q, PA, n, Re, log10 Ie) into acc.
+__device__ __forceinline__ void sersic_dI(const CompConst& c, float dx, float dy, float wgt,
+                                          float acc[7]) {
+    const float xp = fmaf(dx, c.cs, dy * c.sn);
+    const float yp = fmaf(dy, c.cs, -dx * c.sn);
+    const float yq = yp * c.iq;
+    float R2 = fmaf(xp, xp, yq * yq);
+    const bool floored = R2 < 1e-12f;
+    R2 = floored ? 1e-12f : R2;
+    const float lt = (float)fma((double)c.g, (double)fast_log2(R2), -c.h_d);
+    const float t = fast_exp2(lt);
+    const float I = fast_exp2((float)fma(-c.B_d, (double)t, c.A_d)) * wgt;
+    const float inv_n = 2.f * c.g;
+    // dI/dR divided by R
+    const float G = floored ? 0.f : -I * c.b * t * inv_n / R2;
+    const float dxp = G * xp;                 // dI/dx'
+    const float dyp = G * yq * c.iq;          // dI/dy' = G y' / q^2
+    acc[0] += -c.cs * dxp + c.sn * dyp;
+    acc[1] += -c.sn * dxp - c.cs * dyp;
+    acc[2] += -G * yq * yq * c.iq;            // dR/dq = -y'^2 / (q^3 R)
+    acc[3] += G * xp * yp * (1.f - c.iq * c.iq);
+    acc[4] += I * (c.bp * (1.f - t) + c.b * t * lt * LN2F * inv_n);
+    acc[5] += I * c.b * t * inv_n / c.re;
+    acc[6] += I * LN10F;
+}
+
+struct NodeSet {
+    int s, rule, mode;
+    float o[MAX_NODES_1D], w[MAX_NODES_1D];
+};
+
+__device__ __forceinline__ bool within_kre(const CompConst& c, double ucx, double ucy) {
+    const double dx = ucx - c.x0, dy = ucy - c.y0;
+    const double xp = dx * c.cs_d + dy * c.sn_d;
+    const double yp = -dx * c.sn_d + dy * c.cs_d;
+    const double yq = yp / c.q_d;
+    return sqrt(xp * xp + yq * yq) < c.kre;
+}
+
+// Pixel value (before the area factor) of a Sersic component.
+__device__ __forceinline__ float sersic_pixel(const Plan& p, const CompConst& c, const DImage& im,
+                                              double ucx, double ucy) {
+    const float dxc = (float)(ucx - c.x0), dyc = (float)(ucy - c.y0);
+    if (p.mode == APX_MODE_WITHIN_K_RE && !within_kre(c, ucx, ucy)) return sersic_I(c, dxc, dyc);
+    const float a1 = (float)im.aff[1], a2 = (float)im.aff[2], a4 = (float)im.aff[4], a5 = (float)im.aff[5];
+    float sum = 0.f;
+    for (int ky = 0; ky < p.s; ++ky) {
+        const float oy = p.node_o[ky], wy = p.node_w[ky];
+        float row = 0.f;
+        for (int kx = 0; kx < p.s; ++kx) {
+            const float ox = p.node_o[kx];
+            row = fmaf(p.node_w[kx], sersic_I(c, dxc + fmaf(a1, ox, a2 * oy), dyc + fmaf(a4, ox, a5 * oy)), row);
+        }
+        sum = fmaf(wy, row, sum);
+    }
+    return sum;
+}
+
+__device__ __forceinline__ void sersic_pixel_grad(const Plan& p, const CompConst& c, const DImage& im,
+                                                  double ucx, double ucy, float acc[7]) {
+    for (int k = 0; k < 7; ++k) acc[k] = 0.f;
+    const float dxc = (float)(ucx - c.x0), dyc = (float)(ucy - c.y0);
+    if (p.mode == APX_MODE_WITHIN_K_RE && !within_kre(c, ucx, ucy)) {
+        sersic_dI(c, dxc, dyc, 1.f, acc);
+        return;
+    }
+    const float a1 = (float)im.aff[1], a2 = (float)im.aff[2], a4 = (float)im.aff[4], a5 = (float)im.aff[5];
+    for (int ky = 0; ky < p.s; ++ky) {
+        const float oy = p.node_o[ky];
+        for (int kx = 0; kx < p.s; ++kx) {
+            const float ox = p.node_o[kx];
+            sersic_dI(c, dxc + fmaf(a1, ox, a2 * oy), dyc + fmaf(a4, ox, a5 * oy),
+                      p.node_w[kx] * p.node_w[ky], acc);
+        }
+    }
+}
+
+__device__ __forceinline__ double point_weight(const CompConst& c, int y, int x) {
+    const double wx = fmax(0.0, 1.0 - fabs((double)x - c.x0));
+    const double wy = fmax(0.0, 1.0 - fabs((double)y - c.y0));
+    return wx * wy;
+}
+
+__device__ __forceinline__ bool sub_skipped(const Plan& p, int sub, int mode, const apx_lm_state* lm) {
+    if (mode == 1) return p.lmf[sub].chol_done == 0 || p.lmf[sub].trial_bad != 0;
+    if (mode == 2) return lm[sub].need_jac == 0;
+    return false;
+}
+
+// ----------------------------------------------------------------------- render
+// S (extended grid) = sum of all components whose window holds the pixel.
+__global__ __launch_bounds__(256) void k_render(Plan p, int skip_mode, const apx_lm_state* lm) {
+    const RTile t = p.rtiles[blockIdx.x];
+    const DImage& im = p.images[t.a];
+    if (sub_skipped(p, im.sub, skip_mode, lm)) return;
+    const int y = t.y0 + (int)threadIdx.x / RT_X;
+    const int x = t.x0 + (int)threadIdx.x % RT_X;
+    if (y >= im.H + im.c || x >= im.W + im.c) return;
+    const double ucx = im.aff[0] + im.aff[1] * x + im.aff[2] * y;
+    const double ucy = im.aff[3] + im.aff[4] * x + im.aff[5] * y;
+    double sum = 0.0;
+    const int kb = p.rtile_off[blockIdx.x], ke = p.rtile_off[blockIdx.x + 1];
+    for (int k = kb; k < ke; ++k) {
+        const int ci = p.rtile_comps[k];
+        const DComp& cp = p.comps[ci];
+        if (y < cp.box[0] || y >= cp.box[2] || x < cp.box[1] || x >= cp.box[3]) continue;
+        const CompConst& c = p.cc[ci];
+        if (!c.valid) { sum += __builtin_nan(""); continue; }
+        if (cp.type == APX_SERSIC) sum += (double)sersic_pixel(p, c, im, ucx, ucy) * im.area;
+        else sum += (double)c.F * point_weight(c, y, x);
+    }
+    p.S[im.ext_off + (long long)(y + im.c) * im.EW + (x + im.c)] = (float)sum;
+}
+
+hipError_t launch_render_mode(const Plan& p, int skip_mode, const apx_lm_state* lm, hipStream_t st) {
+    if (p.n_rtiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_render, dim3(p.n_rtiles), dim3(256), 0, st, p, skip_mode, lm);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- FP64 render
+// The same pixel integral in double precision throughout (FP64 log2/exp2), for the
+// objective path: chi^2 differences of the LM gain ratio are resolved far below FP32
+// rounding.
+__device__ __forceinline__ double sersic_I64(const CompConst& c, double dx, double dy) {
+    const double xp = dx * c.cs_d + dy * c.sn_d;
+    const double yq = (-dx * c.sn_d + dy * c.cs_d) / c.q_d;
+    const double R2 = fmax(xp * xp + yq * yq, 1e-12);
+    const double t = exp2(c.g_d * log2(R2) - c.h_d);
+    return exp2(c.A_d - c.B_d * t);
+}
+
+__device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst& c, const DImage& im,
+                                                 double ucx, double ucy) {
+    const double dxc = ucx - c.x0, dyc = ucy - c.y0;
+    if (p.mode == APX_MODE_WITHIN_K_RE && !within_kre(c, ucx, ucy)) return sersic_I64(c, dxc, dyc);
+    double sum = 0.0;
+    for (int ky = 0; ky < p.s; ++ky) {
+        const double oy = p.node_od[ky];
+        double row = 0.0;
+        for (int kx = 0; kx < p.s; ++kx) {
+            const double ox = p.node_od[kx];
+            row += p.node_wd[kx] * sersic_I64(c, dxc + im.aff[1] * ox + im.aff[2] * oy,
+                                              dyc + im.aff[4] * ox + im.aff[5] * oy);
+        }
+        sum += p.node_wd[ky] * row;
+    }
+    return sum;
+}
+
+__global__ __launch_bounds__(256) void k_render64(Plan p, int skip_mode, const apx_lm_state* lm) {
+    const RTile t = p.rtiles[blockIdx.x];
+    const DImage& im = p.images[t.a];
+    if (sub_skipped(p, im.sub, skip_mode, lm)) return;
+    const int y = t.y0 + (int)threadIdx.x / RT_X;
+    const int x = t.x0 + (int)threadIdx.x % RT_X;
+    if (y >= im.H + im.c || x >= im.W + im.c) return;
+    const double ucx = im.aff[0] + im.aff[1] * x + im.aff[2] * y;
+    const double ucy = im.aff[3] + im.aff[4] * x + im.aff[5] * y;
+    double sum = 0.0;
+    const int kb = p.rtile_off[blockIdx.x], ke = p.rtile_off[blockIdx.x + 1];
+    for (int k = kb; k < ke; ++k) {
+        const int ci = p.rtile_comps[k];
+        const DComp& cp = p.comps[ci];
+        if (y < cp.box[0] || y >= cp.box[2] || x < cp.box[1] || x >= cp.box[3]) continue;
+        const CompConst& c = p.cc[ci];
+        if (!c.valid) { sum += __builtin_nan(""); continue; }
+        if (cp.type == APX_SERSIC) sum += sersic_pixel64(p, c, im, ucx, ucy) * im.area;
+        else sum += (double)c.F64 * point_weight(c, y, x);
+    }
+    p.S64[im.ext_off + (long long)(y + im.c) * im.EW + (x + im.c)] = sum;
+}
+
+hipError_t launch_render64(const Plan& p, int skip_mode, const apx_lm_state* lm, hipStream_t st) {
+    if (p.n_rtiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_render64, dim3(p.n_rtiles), dim3(256), 0, st, p, skip_mode, lm);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ derivative images
+// D[col] over the group's input box: the pixel-integrated derivative of each free
+// parameter of each component of the group (pre-convolution).
+__global__ __launch_bounds__(256) void k_deriv(Plan p, const apx_lm_state* lm) {
+    const RTile t = p.gtiles[blockIdx.x];
+    const DGroup& gr = p.groups[t.a];
+    if (lm && lm[gr.sub].need_jac == 0) return;
+    const DImage& im = p.images[gr.image];
+    const int ly = t.y0 + (int)threadIdx.x / RT_X;
+    const int lx = t.x0 + (int)threadIdx.x % RT_X;
+    if (ly >= gr.ih || lx >= gr.iw) return;
+    const int y = gr.iy0 + ly, x = gr.ix0 + lx;
+    const double ucx = im.aff[0] + im.aff[1] * x + im.aff[2] * y;
+    const double ucy = im.aff[3] + im.aff[4] * x + im.aff[5] * y;
+    const long long plane = (long long)gr.ih * gr.iw;
+    float* Dg = p.D + gr.d_off + (long long)ly * gr.iw + lx;
+    for (int k = gr.comp_begin; k < gr.comp_end; ++k) {
+        const int ci = p.group_comps[k];
+        const DComp& cp = p.comps[ci];
+        const CompConst& c = p.cc[ci];
+        if (cp.type == APX_SERSIC) {
+            float acc[7];
+            sersic_pixel_grad(p, c, im, ucx, ucy, acc);
+            const float area = (float)im.area;
+            for (int q = 0; q < 7; ++q)
+                if (cp.col[q] >= 0) Dg[cp.col[q] * plane] = acc[q] * area;
+        } else {
+            if (cp.col[2] >= 0) Dg[cp.col[2] * plane] = (float)((double)c.F * point_weight(c, y, x) * 2.302585092994046);
+        }
+    }
+}
+
+hipError_t launch_deriv(const Plan& p, const apx_lm_state* lm, hipStream_t st) {
+    if (p.n_gtiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_deriv, dim3(p.n_gtiles), dim3(256), 0, st, p, lm);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- adjoint gradient
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// grad_part[col][tile] = sum over the tile of Abar * dS/dtheta_col (recomputed).
+__global__ __launch_bounds__(256) void k_grad_tiles(Plan p) {
+    __shared__ double red[4][7];
+    const RTile t = p.gtiles[blockIdx.x];
+    const DGroup& gr = p.groups[t.a];
+    const DImage& im = p.images[gr.image];
+    const int tile_local = blockIdx.x - gr.tile_begin;
+    const int ly = t.y0 + (int)threadIdx.x / RT_X;
+    const int lx = t.x0 + (int)threadIdx.x % RT_X;
+    const bool inside = ly < gr.ih && lx < gr.iw;
+    const int y = gr.iy0 + ly, x = gr.ix0 + lx;
+    const double ucx = im.aff[0] + im.aff[1] * x + im.aff[2] * y;
+    const double ucy = im.aff[3] + im.aff[4] * x + im.aff[5] * y;
+    float abar = 0.f;
+    if (inside) abar = p.Abar[im.ext_off + (long long)(y + im.c) * im.EW + (x + im.c)];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = gr.comp_begin; k < gr.comp_end; ++k) {
+        const int ci = p.group_comps[k];
+        const DComp& cp = p.comps[ci];
+        const CompConst& c = p.cc[ci];
+        double v[7];
+        if (cp.type == APX_SERSIC) {
+            float acc[7];
+            if (inside) sersic_pixel_grad(p, c, im, ucx, ucy, acc);
+            else for (int q = 0; q < 7; ++q) acc[q] = 0.f;
+            for (int q = 0; q < 7; ++q) v[q] = (double)acc[q] * im.area * (double)abar;
+        } else {
+            for (int q = 0; q < 7; ++q) v[q] = 0.0;
+            if (inside) v[2] = (double)c.F * point_weight(c, y, x) * 2.302585092994046 * (double)abar;
+        }
+        for (int q = 0; q < 7; ++q) {
+            if (cp.col[q] < 0) continue;            // uniform across the block
+            const double s = wave_sum(v[q]);
+            if (lane == 0) red[wv][q] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x < 7 && cp.col[threadIdx.x] >= 0) {
+            const int q = threadIdx.x;
+            const double s = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+            p.grad_part[gr.gp_off + (long long)cp.col[q] * gr.ntiles + tile_local] = s;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_grad_tiles(const Plan& p, hipStream_t st) {
+    if (p.n_gtiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_tiles, dim3(p.n_gtiles), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- flipped PSF
+__global__ void k_flip_psf(Plan p) {
+    const int k = blockIdx.y;
+    const DImage& im = p.images[k];
+    const int P = im.P;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < P * P; e += gridDim.x * blockDim.x) {
+        const int u = e / P, v = e % P;
+        p.psf_flip[im.psf_off + e] = p.psf[im.psf_off + (P - 1 - u) * P + (P - 1 - v)];
+    }
+}
+
+hipError_t launch_flip_psf(const Plan& p, hipStream_t st) {
+    if (p.n_images == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flip_psf, dim3(4, p.n_images), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+}  // namespace apx

@@ -145,12 +145,12 @@ def point_window(px: float, py: float, H: int, W: int, P: int):
     return (y0b, x0b, y1b, x1b)
 
 
-def _draw_sersic(rng, cx, cy):
+def _draw_sersic(rng, cx, cy, logie_range=LOGIE_RANGE):
     q = rng.uniform(*Q_RANGE)
     pa = rng.uniform(0.0, math.pi)
     n = rng.uniform(*N_RANGE)
     re = rng.uniform(*RE_RANGE)
-    lie = rng.uniform(*LOGIE_RANGE)
+    lie = rng.uniform(*logie_range)
     return [cx, cy, q, pa, n, re, lie]
 
 
@@ -242,7 +242,7 @@ def single(seed_id: int = 1, H: int = 64, W: int = 64, P: int = 11, sigma: float
 def blend(seed_id: int = 2, H: int = 512, W: int = 512, n_sersic: int = 50,
           n_point: int = 200, P: int = 25, fwhm: float = 3.0, beta: float = 2.5,
           s: int = 3, k_re: float = 2.0, mode: int = MODE_WITHIN_K_RE,
-          psf: np.ndarray | None = None) -> Dict:
+          psf: np.ndarray | None = None, logie_range=LOGIE_RANGE) -> Dict:
     """Blended field: Sersics with full-image windows + fixed-position point sources
     (free log10 flux, uniform in [0, 2]) + sky.  s x s nodes within k_re*Re of each
     Sersic centre, the pixel centre elsewhere."""
@@ -252,7 +252,7 @@ def blend(seed_id: int = 2, H: int = 512, W: int = 512, n_sersic: int = 50,
     theta, kinds, re_of, comps = [], [], [], []
     for g in range(n_sersic):
         cx, cy = rng.uniform(0, W - 1), rng.uniform(0, H - 1)
-        prm = _draw_sersic(rng, cx, cy)
+        prm = _draw_sersic(rng, cx, cy, logie_range)
         p0 = len(theta)
         theta += prm
         kinds += [K_X, K_Y, K_Q, K_PA, K_N, K_RE, K_LOGIE]
@@ -331,7 +331,8 @@ def field(seed_id: int = 3, H: int = 2048, W: int = 2048, n_sersic: int = 500,
 
 
 def cutouts(seed_id: int = 4, n_cutouts: int = 4096, side_range=(32, 256),
-            p_range=(15, 31), fwhm_range=(2.0, 5.0), max_comp: int = 5, s: int = 3) -> Dict:
+            p_range=(15, 31), fwhm_range=(2.0, 5.0), max_comp: int = 5, s: int = 3,
+            logie_range=LOGIE_RANGE) -> Dict:
     """Many independent cutouts (one sub-problem each): side log-uniform in side_range,
     1..max_comp Sersics (the first centred within 2 px, the rest uniform over the
     central 80%) + sky; per-cutout Gaussian or Moffat (beta 3) PSF of odd size
@@ -356,7 +357,7 @@ def cutouts(seed_id: int = 4, n_cutouts: int = 4096, side_range=(32, 256),
             else:
                 cx = rng.uniform(0.1 * side, 0.9 * side - 1)
                 cy = rng.uniform(0.1 * side, 0.9 * side - 1)
-            prm = _draw_sersic(rng, cx, cy)
+            prm = _draw_sersic(rng, cx, cy, logie_range)
             p0 = len(theta)
             theta += prm
             kinds += [K_X, K_Y, K_Q, K_PA, K_N, K_RE, K_LOGIE]

@@ -1,0 +1,140 @@
+"""Problem specs and data for the GPU parity tests (inputs from the seeded generator,
+noise-free models and expected values from the oracle only)."""
+import math
+
+import numpy as np
+
+import oracle
+from paper_2308_01957_amd import synth
+
+
+def with_data(spec, theta=None):
+    """Attach data/weight built from the oracle's noise-free model at theta (default truth)."""
+    th = spec["theta_true"] if theta is None else theta
+    data, weight = [], []
+    for k, im in enumerate(spec["images"]):
+        m = oracle.model_image(spec, th, k)
+        d, w = synth.make_data(m, spec["noise"][k][:im["H"], :im["W"]])
+        data.append(d)
+        weight.append(w)
+    spec["data"], spec["weight"] = data, weight
+    return spec
+
+
+def small_blend():
+    """Ragged 75x93 field: full and partial Sersic windows, point sources, sky,
+    asymmetric 9x9 PSF, s = 3 within 2 Re and the centre elsewhere."""
+    rng = np.random.default_rng(21)
+    spec = synth.blend(seed_id=102, H=75, W=93, n_sersic=3, n_point=4, P=9,
+                       psf=synth.asymmetric_psf(9, rng))
+    # give two of the Sersics partial windows
+    spec["comps"][1]["box"] = (5, -4, 60, 70)
+    spec["comps"][2]["box"] = (-4, 20, 79, 97)
+    return with_data(spec)
+
+
+def affine_pair():
+    """Two images with rotated/scaled/shifted pixel->sky maps, different PSF sizes,
+    two Sersics with tied shape parameters and per-image brightness and sky,
+    Gauss-Legendre 4 x 4 nodes."""
+    rng = np.random.default_rng(5)
+    H, W = 70, 66
+    affs = []
+    for (phi, sc, tx, ty) in [(0.3, 1.01, 0.25, 0.6), (2.1, 0.985, 0.8, 0.1)]:
+        a1, a2 = sc * math.cos(phi), -sc * math.sin(phi)
+        a4, a5 = sc * math.sin(phi), sc * math.cos(phi)
+        pcx, pcy = (W - 1) / 2, (H - 1) / 2
+        affs.append(np.array([pcx - a1 * pcx - a2 * pcy + tx, a1, a2, pcy - a4 * pcx - a5 * pcy + ty, a4, a5]))
+    psfs = [synth.moffat_psf(7, 2.5, 3.0), synth.asymmetric_psf(11, rng)]
+    gals = [[30.2, 35.7, 0.55, 0.8, 1.7, 5.0], [42.1, 25.3, 0.8, 2.0, 0.9, 3.5]]
+    theta, kinds, re_of = [], [], []
+    for g in gals:
+        theta += g + [0.3, 0.1]               # shape + two per-image log10 Ie
+        kinds += [0, 1, 2, 3, 4, 5, 6, 6]
+        re_of += [g[5]] * 8
+    theta += [0.05, 0.07]
+    kinds += [8, 8]
+    re_of += [1.0, 1.0]
+    images, comps = [], []
+    for k in range(2):
+        images.append(dict(H=H, W=W, psf=psfs[k], affine=affs[k], sky_par=16 + k, sky_fixed=0.0, sub=0))
+        for gi, g in enumerate(gals):
+            p0 = 8 * gi
+            box = synth.ellipse_window(g[0], g[1], g[2], g[3], g[5], 8.0, H, W, psfs[k].shape[0], affs[k])
+            comps.append(dict(type=0, image=k, box=box,
+                              par=[p0, p0 + 1, p0 + 2, p0 + 3, p0 + 4, p0 + 5, p0 + 6 + k], fixed=[0.0] * 7))
+    spec = {"name": "affine_pair", "images": images, "comps": comps, "subs": [(0, 18)],
+            "sampling": dict(s=4, rule=1, mode=0, k=0.0), "theta_true": theta, "kinds": kinds,
+            "re_of": re_of}
+    synth._finish(spec)
+    nr = np.random.default_rng(7)
+    spec["noise"] = [nr.standard_normal((H, W)) for _ in range(2)]
+    spec["theta_init"] = synth.perturb(spec["theta_true"], spec["kinds"], spec["re_of"], np.random.default_rng(8))
+    return with_data(spec)
+
+
+def single64():
+    return with_data(synth.single(1))
+
+
+def few_cutouts():
+    return with_data(synth.cutouts(seed_id=104, n_cutouts=6, side_range=(20, 72), p_range=(5, 17), max_comp=3))
+
+
+def large_sub():
+    """One sub-problem above the one-wave solver size (blocked Cholesky path)."""
+    return with_data(synth.blend(seed_id=105, H=96, W=110, n_sersic=11, n_point=8, P=11))
+
+
+def bright_cutouts():
+    """Six single-Sersic cutouts bright enough for the fit to converge (batched LM)."""
+    return with_data(synth.cutouts(seed_id=104, n_cutouts=6, side_range=(24, 72), p_range=(5, 17),
+                                   max_comp=1, logie_range=(0.5, 1.5)))
+
+
+def bright_large_sub():
+    """77-parameter blend (10 Sersic + 6 point sources + sky) that the LM settles."""
+    return with_data(synth.blend(seed_id=106, H=120, W=128, n_sersic=10, n_point=6, P=11,
+                                 logie_range=(0.5, 1.5)))
+
+
+def tol_pixels(m_ora):
+    return 1e-5 * np.abs(m_ora) + 1e-7 * np.max(np.abs(m_ora))
+
+
+def grid_large_sub():
+    """66 parameters in one sub-problem (blocked Cholesky path): nine bright,
+    well-separated Sersics on a 3 x 3 grid, two point sources and the sky."""
+    rng = np.random.default_rng(2024)
+    H = W = 150
+    P = 11
+    K = synth.moffat_psf(P, 3.0, 2.5)
+    theta, kinds, re_of, comps = [], [], [], []
+    for gy in range(3):
+        for gx in range(3):
+            cx, cy = 25 + 50 * gx + rng.uniform(-2, 2), 25 + 50 * gy + rng.uniform(-2, 2)
+            prm = [cx, cy, rng.uniform(0.5, 0.9), rng.uniform(0, math.pi), rng.uniform(0.8, 3.0),
+                   rng.uniform(2.5, 4.0), rng.uniform(0.5, 1.5)]
+            p0 = len(theta)
+            theta += prm
+            kinds += [0, 1, 2, 3, 4, 5, 6]
+            re_of += [prm[5]] * 7
+            comps.append(dict(type=0, image=0, box=synth.full_window(H, W, P), par=list(range(p0, p0 + 7)),
+                              fixed=[0.0] * 7))
+    for (px, py) in [(50.3, 99.6), (101.7, 48.2)]:
+        theta.append(rng.uniform(1.0, 2.0))
+        kinds.append(7)
+        re_of.append(1.0)
+        comps.append(dict(type=1, image=0, box=synth.point_window(px, py, H, W, P),
+                          par=[-1, -1, len(theta) - 1, -1, -1, -1, -1], fixed=[px, py, 0, 0, 0, 0, 0]))
+    theta.append(0.05)
+    kinds.append(8)
+    re_of.append(1.0)
+    spec = {"name": "grid66", "images": [dict(H=H, W=W, psf=K, affine=synth.IDENTITY_AFFINE.copy(),
+                                               sky_par=len(theta) - 1, sky_fixed=0.0, sub=0)],
+            "comps": comps, "subs": [(0, len(theta))], "sampling": dict(s=3, rule=0, mode=1, k=2.0),
+            "theta_true": theta, "kinds": kinds, "re_of": re_of}
+    synth._finish(spec)
+    spec["noise"] = [np.random.default_rng(2025).standard_normal((H, W))]
+    spec["theta_init"] = synth.perturb(spec["theta_true"], spec["kinds"], spec["re_of"], np.random.default_rng(2026))
+    return with_data(spec)
