@@ -191,6 +191,25 @@ apx_status apx_problem_sizes(const apx_problem* p, int64_t* n_pix, int64_t* n_ex
 apx_status apx_problem_check(apx_problem* p);
 apx_status apx_problem_destroy(apx_problem* p);
 
+/* Kernel timing (tracing aid).  When enabled, every launch group of the hot path is
+ * bracketed by HIP events recorded on the context stream; apx_problem_timing()
+ * synchronises and returns the summed duration and launch count of one class since
+ * the last enable.  Not usable while a graph is being captured (APX_E_INVALID). */
+#define APX_TIME_PREP       0
+#define APX_TIME_RENDER     1     /* pre-convolution render (objective path)   */
+#define APX_TIME_CONV_FWD   2     /* model convolution + chi^2 partials         */
+#define APX_TIME_DERIV      3     /* derivative images                          */
+#define APX_TIME_CONV_JCOL  4     /* Jacobian-column convolutions               */
+#define APX_TIME_PAIRS      5     /* J^T W J tiles (MFMA)                       */
+#define APX_TIME_REDUCE     6     /* ordered reductions and assembly            */
+#define APX_TIME_SOLVE      7     /* damped Cholesky + substitution             */
+#define APX_TIME_LM         8     /* trial, accept and state kernels            */
+#define APX_TIME_CONV_ADJ   9     /* adjoint convolution                        */
+#define APX_TIME_GRAD       10    /* adjoint contraction with recomputed samples */
+#define APX_TIME_CLASSES    11
+apx_status apx_problem_set_timing(apx_problem* p, int32_t enabled);
+apx_status apx_problem_timing(apx_problem* p, int32_t klass, double* total_ms, int64_t* launches);
+
 /* ------------------------------------------------------------------ hot path ---- */
 /* model[n_pix] = PSF (x) sum of components + sky, for all images (§2.1, §2.1.2-3).
  * theta: device [n_par] FP64.  Out-of-domain theta -> APX_E_DOMAIN via check(). */

@@ -28,8 +28,10 @@ EXPORTS = [
     "apx_last_error", "apx_problem_create", "apx_problem_workspace_bytes",
     "apx_problem_bind_workspace", "apx_problem_sizes", "apx_problem_check", "apx_problem_destroy",
     "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_lm_init",
-    "apx_lm_step", "apx_lm_run",
+    "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
 ]
+TIME_CLASSES = ["prep", "render", "conv_fwd", "deriv", "conv_jcol", "pairs", "reduce", "solve",
+                "lm", "conv_adj", "grad"]
 
 
 class ImageDesc(ctypes.Structure):
@@ -109,6 +111,8 @@ def load_library(path: str = LIB_PATH):
         "apx_lm_init": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_step": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_run": ([vp, i32, vp, vp, vp, vp, i32], i32),
+        "apx_problem_set_timing": ([vp, i32], i32),
+        "apx_problem_timing": ([vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -321,6 +325,18 @@ class Problem:
             self._check(self.lib.apx_lm_run(self._prob, int(n_iter), data.data_ptr(), weight.data_ptr(),
                                             theta.data_ptr(), state.data_ptr(), 1 if use_graph else 0))
         self._leave()
+
+    def set_timing(self, enabled: bool):
+        self._check(self.lib.apx_problem_set_timing(self._prob, 1 if enabled else 0))
+
+    def timing(self) -> Dict[str, tuple]:
+        """{class: (total_ms, launches)} since timing was enabled (synchronises)."""
+        out = {}
+        for k, name in enumerate(TIME_CLASSES):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            self._check(self.lib.apx_problem_timing(self._prob, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (float(ms.value), int(n.value))
+        return out
 
     def lm_state(self, state) -> np.ndarray:
         return np.frombuffer(state.cpu().numpy().tobytes(), dtype=LM_STATE_DTYPE)

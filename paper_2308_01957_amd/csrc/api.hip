@@ -78,6 +78,7 @@ struct apx_problem {
     int nmax_small = 0;
     std::vector<float> node_o, node_w;
     std::vector<double> node_od, node_wd;
+    std::vector<double> bn_tab;
 
     long long n_pix = 0, n_ext = 0, n_d = 0, n_j = 0, n_pairpart = 0, n_gradpart = 0, a_total = 0;
     long long n_psf = 0;
@@ -93,6 +94,13 @@ struct apx_problem {
     long long asrc_col = 0, asrc_gcol = 0, asrc_img = 0;
     double* chi2_sub = nullptr;      // [n_sub]
     double* chi2_trial = nullptr;    // [n_sub]
+
+    // kernel timing
+    bool timing = false;
+    bool capturing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_recs;   // (class, index of start event)
 
     // graph cache for apx_lm_run
     hipGraphExec_t gexec = nullptr;
@@ -161,6 +169,76 @@ static void gauss_legendre(int s, std::vector<double>& x, std::vector<double>& w
 
 static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// Regularised lower incomplete gamma P(a, x) by its power series (x < a + 1 here).
+static double gammainc_lower_series_host(double a, double x) {
+    if (x <= 0.0) return 0.0;
+    double sum = 1.0, term = 1.0;
+    for (int k = 1; k < 5000; ++k) {
+        term *= x / (a + k);
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return std::exp(a * std::log(x) - x - std::lgamma(a + 1.0)) * sum;
+}
+
+// Sersic b_n: the root of P(2n, b) = 1/2, by bracketed Newton from the asymptotic guess.
+static double sersic_bn_host(double n) {
+    const double a = 2.0 * n;
+    double lo = std::max(a - 1.0, 1e-12), hi = a + 0.5;
+    double b = a - 1.0 / 3.0 + 4.0 / (405.0 * n) + 46.0 / (25515.0 * n * n);
+    if (!(b > lo && b < hi)) b = 0.5 * (lo + hi);
+    const double lga = std::lgamma(a);
+    for (int it = 0; it < 100; ++it) {
+        const double f = gammainc_lower_series_host(a, b) - 0.5;
+        if (f > 0.0) hi = b; else lo = b;
+        const double fp = std::exp((a - 1.0) * std::log(b) - b - lga);
+        double bn = b - f / fp;
+        if (!(bn > lo && bn < hi)) bn = 0.5 * (lo + hi);
+        const double step = std::fabs(bn - b);
+        b = bn;
+        if (step <= 1e-15 * b) break;
+    }
+    return b;
+}
+
+static void build_bn_table(std::vector<double>& tab) {
+    tab.resize(2 * BN_COUNT);
+    const double hd = 1e-5;
+    for (int k = 0; k < BN_COUNT; ++k) {
+        const double n = BN_N0 + k / BN_INV_H;
+        tab[2 * k] = sersic_bn_host(n);
+        tab[2 * k + 1] = (sersic_bn_host(n + hd) - sersic_bn_host(n - hd)) / (2.0 * hd);
+    }
+}
+
+// Event pair around a launch group when timing is on (never during capture).
+struct TimeScope {
+    apx_problem* P;
+    int klass;
+    size_t idx = (size_t)-1;
+    TimeScope(apx_problem* P_, int k);
+    ~TimeScope();
+};
+
+TimeScope::TimeScope(apx_problem* P_, int k) : P(P_), klass(k) {
+    if (!P->timing || P->capturing) return;
+    while (P->ev_pool.size() < P->ev_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        P->ev_pool.push_back(e);
+    }
+    idx = P->ev_used;
+    P->ev_used += 2;
+    hipEventRecord(P->ev_pool[idx], P->ctx->stream);
+}
+TimeScope::~TimeScope() {
+    if (idx == (size_t)-1) return;
+    hipEventRecord(P->ev_pool[idx + 1], P->ctx->stream);
+    P->ev_recs.emplace_back(klass, idx);
+}
+
+
+
 // ------------------------------------------------------------------ plan build
 static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     apx_ctx* C = P->ctx;
@@ -206,6 +284,8 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         P->node_o.push_back((float)P->node_od[k]);
         P->node_w.push_back((float)P->node_wd[k]);
     }
+
+    build_bn_table(P->bn_tab);
 
     // sub-problems
     P->subs.resize(d->n_sub);
@@ -542,9 +622,10 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
                     const int rows = y1 - y0, width = x1 - x0;
                     const int kc_w = ceil_div(width, PAIR_KC) * PAIR_KC;
                     const int rows_per = std::max(1, ceil_div(4096, kc_w));
-                    for (int ta = 0; ta < na; ++ta)
-                        for (int tb = (gl[a] == gl[b] ? ta : 0); tb < nb; ++tb)
-                            for (int r0 = 0; r0 < rows; r0 += rows_per) {
+                    // K-slices outermost: the tiles that run together read the same rows of J
+                    for (int r0 = 0; r0 < rows; r0 += rows_per)
+                        for (int ta = 0; ta < na; ++ta)
+                            for (int tb = (gl[a] == gl[b] ? ta : 0); tb < nb; ++tb) {
                                 PairItem it{};
                                 it.pair = pi;
                                 it.ta = ta;
@@ -745,6 +826,7 @@ static void layout(apx_problem* P) {
     ws_take<int>(P, "par_sky_off", P->par_sky_off.size());
     ws_take<int>(P, "par_sky", P->par_sky.size());
     ws_take<int>(P, "small_subs", P->small_subs.size());
+    ws_take<double>(P, "bn_tab", P->bn_tab.size());
     // buffers
     ws_take<CompConst>(P, "cc", P->comps.size());
     ws_take<float>(P, "S", P->n_ext);
@@ -911,6 +993,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     HIPCHK(upload(P, "par_sky_off", P->par_sky_off));
     HIPCHK(upload(P, "par_sky", P->par_sky));
     HIPCHK(upload(P, "small_subs", P->small_subs));
+    HIPCHK(upload(P, "bn_tab", P->bn_tab));
 
     Plan& p = P->plan;
     p = Plan{};
@@ -970,6 +1053,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.sticky = wsp<int>(P, "sticky");
     p.sky_val = wsp<double>(P, "sky_val");
     p.par_sub = wsp<int>(P, "par_sub");
+    p.bn_tab = wsp<double>(P, "bn_tab");
     p.n_pix = P->n_pix;
     p.n_ext = P->n_ext;
     P->chi2_sub = wsp<double>(P, "chi2_sub");
@@ -991,8 +1075,35 @@ apx_status apx_problem_check(apx_problem* P) {
     return APX_OK;
 }
 
+apx_status apx_problem_set_timing(apx_problem* P, int32_t enabled) {
+    if (!P) return APX_E_INVALID;
+    if (P->capturing) return fail(P->ctx, APX_E_INVALID, "timing cannot change during capture");
+    P->timing = enabled != 0;
+    P->ev_used = 0;
+    P->ev_recs.clear();
+    return APX_OK;
+}
+
+apx_status apx_problem_timing(apx_problem* P, int32_t klass, double* total_ms, int64_t* launches) {
+    if (!P || !total_ms || !launches || klass < 0 || klass >= APX_TIME_CLASSES) return APX_E_INVALID;
+    HIPCHK(hipStreamSynchronize(P->ctx->stream));
+    double tot = 0.0;
+    int64_t n = 0;
+    for (const auto& r : P->ev_recs) {
+        if (r.first != klass) continue;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, P->ev_pool[r.second], P->ev_pool[r.second + 1]));
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *launches = n;
+    return APX_OK;
+}
+
 apx_status apx_problem_destroy(apx_problem* P) {
     if (!P) return APX_OK;
+    for (hipEvent_t e : P->ev_pool) hipEventDestroy(e);
     if (P->gexec) hipGraphExecDestroy(P->gexec);
     if (P->graph) hipGraphDestroy(P->graph);
     delete P;
@@ -1010,7 +1121,9 @@ static apx_status run_conv(apx_problem* P, int kind, const ConvIO& io) {
     if (kind == CONV_FWD) { ranges = &P->fwd_ranges; jn = "fwd_jobs"; inn = "fwd_items"; }
     else if (kind == CONV_JCOL) { ranges = &P->jcol_ranges; jn = "jcol_jobs"; inn = "jcol_items"; }
     else { ranges = &P->adj_ranges; jn = "adj_jobs"; inn = "adj_items"; }
+    const int klass = kind == CONV_FWD ? APX_TIME_CONV_FWD : kind == CONV_JCOL ? APX_TIME_CONV_JCOL : APX_TIME_CONV_ADJ;
     for (const PRange& r : *ranges) {
+        TimeScope ts(P, klass);
         ConvLaunch L{wsp<ConvJob>(P, jn), wsp<ConvItem>(P, inn), r.begin, r.count, r.P};
         hipError_t e = kind == CONV_FWD ? (P->objective == APX_OBJECTIVE_FP64 ? launch_conv_fwd64(p, L, io, st)
                                                                                : launch_conv_fwd(p, L, io, st))
@@ -1041,9 +1154,15 @@ static apx_status fwd_chi2(apx_problem* P, const double* theta, const float* dat
                            const apx_lm_state* lm) {
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
-    HIPCHK(launch_prep(p, theta, lm_trial, st));
-    if (P->objective == APX_OBJECTIVE_FP64) HIPCHK(launch_render64(p, skip_mode, lm, st));
-    else HIPCHK(launch_render_mode(p, skip_mode, lm, st));
+    {
+        TimeScope ts(P, APX_TIME_PREP);
+        HIPCHK(launch_prep(p, theta, lm_trial, st));
+    }
+    {
+        TimeScope ts(P, APX_TIME_RENDER);
+        if (P->objective == APX_OBJECTIVE_FP64) HIPCHK(launch_render64(p, skip_mode, lm, st));
+        else HIPCHK(launch_render_mode(p, skip_mode, lm, st));
+    }
     ConvIO io{};
     io.in = p.S;
     io.in64 = p.S64;
@@ -1055,6 +1174,7 @@ static apx_status fwd_chi2(apx_problem* P, const double* theta, const float* dat
     io.lm = lm;
     APXCHK(run_conv(P, CONV_FWD, io));
     if (data) {
+        TimeScope ts(P, APX_TIME_REDUCE);
         for (int q = 0; q < 3; ++q) {
             SegSum a = segsum_base();
             a.src = p.fwd_part;
@@ -1085,7 +1205,10 @@ static apx_status fwd_chi2(apx_problem* P, const double* theta, const float* dat
 static apx_status jac_blocks(apx_problem* P, const float* weight, const apx_lm_state* lm) {
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
-    HIPCHK(launch_deriv(p, lm, st));
+    {
+        TimeScope ts(P, APX_TIME_DERIV);
+        HIPCHK(launch_deriv(p, lm, st));
+    }
     ConvIO io{};
     io.in = p.D;
     io.out = p.J;
@@ -1095,6 +1218,7 @@ static apx_status jac_blocks(apx_problem* P, const float* weight, const apx_lm_s
     io.lm = lm;
     APXCHK(run_conv(P, CONV_JCOL, io));
     if (weight) {
+        TimeScope ts(P, APX_TIME_REDUCE);
         for (int q = 0; q < 2; ++q) {
             SegSum a = segsum_base();
             a.src = p.jcol_part;
@@ -1119,8 +1243,12 @@ static apx_status normal_eq(apx_problem* P, const float* weight, double* A_out, 
     hipStream_t st = P->ctx->stream;
     PairLaunch L64{wsp<DPair>(P, "pairs"), wsp<PairItem>(P, "pitems64"), (int)P->pitems64.size(), 64};
     PairLaunch L16{wsp<DPair>(P, "pairs"), wsp<PairItem>(P, "pitems16"), (int)P->pitems16.size(), 16};
-    HIPCHK(launch_pairs(p, L64, weight, lm, st));
-    HIPCHK(launch_pairs(p, L16, weight, lm, st));
+    {
+        TimeScope ts(P, APX_TIME_PAIRS);
+        HIPCHK(launch_pairs(p, L64, weight, lm, st));
+        HIPCHK(launch_pairs(p, L16, weight, lm, st));
+    }
+    TimeScope ts(P, APX_TIME_REDUCE);
     AsmA a{};
     a.ent_off = wsp<long long>(P, "a_off_csr");
     a.ent_sub = wsp<int>(P, "a_sub");
@@ -1204,7 +1332,10 @@ apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data,
     io.out = p.Abar;
     io.weight = weight;
     APXCHK(run_conv(P, CONV_ADJ, io));
-    HIPCHK(launch_grad_tiles(p, st));
+    {
+        TimeScope ts(P, APX_TIME_GRAD);
+        HIPCHK(launch_grad_tiles(p, st));
+    }
     SegSum a = segsum_base();
     a.src = p.grad_part;
     a.seg = wsp<int>(P, "gcol_seg");
@@ -1236,18 +1367,33 @@ static apx_status lm_step_enqueue(apx_problem* P, const float* data, const float
                                   apx_lm_state* state) {
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
-    HIPCHK(launch_lm_begin(p, state, st));
+    {
+        TimeScope ts(P, APX_TIME_LM);
+        HIPCHK(launch_lm_begin(p, state, st));
+    }
     // normal equations at theta for sub-problems whose last step was accepted
-    HIPCHK(launch_prep(p, theta, 0, st));
+    {
+        TimeScope ts(P, APX_TIME_PREP);
+        HIPCHK(launch_prep(p, theta, 0, st));
+    }
     APXCHK(jac_blocks(P, weight, state));
     APXCHK(normal_eq(P, weight, p.A, p.gvec, state));
     // damped solves
-    HIPCHK(launch_chol_small(p, wsp<int>(P, "small_subs"), (int)P->small_subs.size(), P->nmax_small, state, st));
-    for (int s : P->large_subs) HIPCHK(launch_chol_large(p, s, P->subs[s].n, state, st));
+    {
+        TimeScope ts(P, APX_TIME_SOLVE);
+        HIPCHK(launch_chol_small(p, wsp<int>(P, "small_subs"), (int)P->small_subs.size(), P->nmax_small, state, st));
+        for (int s : P->large_subs) HIPCHK(launch_chol_large(p, s, P->subs[s].n, state, st));
+    }
     // trial
-    HIPCHK(launch_lm_trial(p, theta, state, st));
+    {
+        TimeScope ts(P, APX_TIME_LM);
+        HIPCHK(launch_lm_trial(p, theta, state, st));
+    }
     APXCHK(fwd_chi2(P, p.theta_trial, data, weight, nullptr, P->chi2_trial, 1, 1, state));
-    HIPCHK(launch_lm_accept(p, P->chi2_trial, theta, state, st));
+    {
+        TimeScope ts(P, APX_TIME_LM);
+        HIPCHK(launch_lm_accept(p, P->chi2_trial, theta, state, st));
+    }
     return APX_OK;
 }
 
@@ -1272,8 +1418,11 @@ apx_status apx_lm_run(apx_problem* P, int32_t n_iter, const float* data, const f
     if (!P->gexec || std::memcmp(key, P->gkey, sizeof(key)) != 0) {
         if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
         if (P->graph) { hipGraphDestroy(P->graph); P->graph = nullptr; }
+        if (P->timing) return fail(P->ctx, APX_E_INVALID, "disable timing before graph capture");
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        P->capturing = true;
         apx_status s = lm_step_enqueue(P, data, weight, theta, state);
+        P->capturing = false;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(st, &g);
         if (s != APX_OK) { if (g) hipGraphDestroy(g); return s; }

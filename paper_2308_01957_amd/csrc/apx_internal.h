@@ -13,10 +13,14 @@ namespace apx {
 constexpr int RT_Y = 8, RT_X = 32;            // render / derivative / gradient tiles (256 px)
 constexpr int CV_TH = 32, CV_TW = 64;         // convolution output tile per workgroup
 constexpr int CV_R = 8;                       // consecutive outputs per lane (register window)
-constexpr int PAIR_KC = 16;                   // pixels per LDS stage of the J^T W J kernel
+constexpr int PAIR_KC = 32;                   // pixels per LDS stage of the J^T W J kernel
 constexpr int CHOL_NB = 64;                   // block size of the blocked Cholesky
 constexpr int SMALL_N = 64;                   // sub-problems up to this size: one-wave solver
 constexpr int MAX_NODES_1D = 8;
+// b_n table: cubic Hermite nodes (b, db/dn) on [BN_N0, BN_N0 + (BN_COUNT-1)/BN_INV_H]
+constexpr double BN_N0 = 0.35;
+constexpr double BN_INV_H = 256.0;
+constexpr int BN_COUNT = 2600;
 
 // Plan records (uploaded once into the workspace) -------------------------------
 struct DImage {
@@ -146,6 +150,7 @@ struct Plan {
     int* sticky;              // device error flags
     double* sky_val;          // [n_images] sky of each image at the current theta
     const int* par_sub;       // [n_par] sub-problem of each theta index (-1: none)
+    const double* bn_tab;     // [2 * BN_COUNT]: b_n, db_n/dn at the table nodes
 
     long long n_pix, n_ext;
 };

@@ -15,12 +15,15 @@ typedef double apx_d4 __attribute__((ext_vector_type(4)));
 
 // TM = 64: 4 waves as 2 x 2 blocks of 32 x 32 (2 x 2 MFMA tiles each).
 // TM = 16: 4 waves share one 16 x 16 tile and split each LDS stage along K.
+// Stages of PAIR_KC pixels (one row segment of the box intersection) are software
+// pipelined: the global loads of stage s+1 are in flight while the MFMAs consume s.
 template <int TM>
 __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ pairs,
                                               const PairItem* __restrict__ items,
                                               const float* __restrict__ weight,
                                               const apx_lm_state* lm) {
     constexpr int KC = PAIR_KC;
+    constexpr int PER = TM * KC / 256;              // elements of A (and of B) per thread
     __shared__ double As[TM][KC + 1];
     __shared__ double Bs[TM][KC + 1];
     const PairItem it = items[blockIdx.x];
@@ -43,46 +46,66 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[a][b] = (apx_d4){0.0, 0.0, 0.0, 0.0};
 
-    for (int row = it.r0; row < it.r1; ++row) {
+    const int nxs = (pr.x1 - pr.x0 + KC - 1) / KC;
+    const int n_stage = (it.r1 - it.r0) * nxs;
+    float ra[PER], rb[PER], rw[PER];
+    auto fetch = [&](int st) {
+        const int row = it.r0 + st / nxs;
+        const int xs = pr.x0 + (st - (st / nxs) * nxs) * KC;
         const long long rowpix = im.pix_off + (long long)row * im.W;
         const long long grow = (long long)(row - G.oy0) * G.ow - G.ox0;
         const long long hrow = (long long)(row - Hh.oy0) * Hh.ow - Hh.ox0;
-        for (int xs = pr.x0; xs < pr.x1; xs += KC) {
-            for (int e = threadIdx.x; e < TM * KC; e += 256) {
-                const int i = e / KC, k = e - (e / KC) * KC;
-                const int x = xs + k;
-                double av = 0.0, bv = 0.0;
-                if (x < pr.x1) {
-                    const int ca = a0 + i, cb = b0 + i;
-                    if (ca < ncg) av = (double)Jg[ca * gs + grow + x] * (double)weight[rowpix + x];
-                    if (cb < nch) bv = (double)Jh[cb * hs + hrow + x];
-                }
-                As[i][k] = av;
-                Bs[i][k] = bv;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int i = e / KC, k = e - (e / KC) * KC;
+            const int x = xs + k;
+            float av = 0.f, bv = 0.f, wv_ = 0.f;
+            if (x < pr.x1) {
+                const int ca = a0 + i, cb = b0 + i;
+                wv_ = weight[rowpix + x];
+                if (ca < ncg) av = Jg[ca * gs + grow + x];
+                if (cb < nch) bv = Jh[cb * hs + hrow + x];
             }
-            __syncthreads();
-            if constexpr (TM == 64) {
+            ra[q] = av;
+            rb[q] = bv;
+            rw[q] = wv_;
+        }
+    };
+    if (n_stage > 0) fetch(0);
+    for (int st = 0; st < n_stage; ++st) {
 #pragma unroll
-                for (int kk = 0; kk < KC; kk += 4) {
-                    double av[NB], bv[NB];
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int i = e / KC, k = e - (e / KC) * KC;
+            As[i][k] = (double)ra[q] * (double)rw[q];
+            Bs[i][k] = (double)rb[q];
+        }
+        __syncthreads();
+        if (st + 1 < n_stage) fetch(st + 1);
+        if constexpr (TM == 64) {
 #pragma unroll
-                    for (int m = 0; m < NB; ++m) av[m] = As[wr * 32 + m * 16 + (lane & 15)][kk + (lane >> 4)];
+            for (int kk = 0; kk < KC; kk += 4) {
+                double av[NB], bv[NB];
 #pragma unroll
-                    for (int n = 0; n < NB; ++n) bv[n] = Bs[wc * 32 + n * 16 + (lane & 15)][kk + (lane >> 4)];
+                for (int m = 0; m < NB; ++m) av[m] = As[wr * 32 + m * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-                    for (int m = 0; m < NB; ++m)
+                for (int n = 0; n < NB; ++n) bv[n] = Bs[wc * 32 + n * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-                        for (int n = 0; n < NB; ++n)
-                            acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
-                }
-            } else {
-                const int kk = 4 * wv;
+                for (int m = 0; m < NB; ++m)
+#pragma unroll
+                    for (int n = 0; n < NB; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 8 * wv; kk < 8 * wv + 8; kk += 4) {
                 const double av = As[lane & 15][kk + (lane >> 4)];
                 const double bv = Bs[lane & 15][kk + (lane >> 4)];
                 acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[0][0], 0, 0, 0);
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
 
     double* out = p.pair_part + it.out_off;

