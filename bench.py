@@ -84,6 +84,205 @@ def cpu_baseline(spec, data, weight):
     }
 
 
+def _data(prob, spec, synth):
+    """Noise-free model of the truth rendered by the library, noisy data and weights."""
+    m = prob.split(prob.render(spec["theta_true"]))
+    prob.check()
+    data, weight = [], []
+    for k, mk in enumerate(m):
+        d, w = synth.make_data(mk.astype(np.float64), spec["noise"][k])
+        data.append(d)
+        weight.append(w)
+    return data, weight
+
+
+def _line(rec):
+    print(json.dumps(rec), flush=True)
+
+
+def _mpix(prob, spec, torch, reps):
+    out = torch.empty(prob.n_pix, dtype=torch.float32, device=prob.device)
+    th = torch.as_tensor(spec["theta_true"], dtype=torch.float64, device=prob.device)
+    prob.render(th, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        prob.render(th, out)
+    torch.cuda.synchronize()
+    return prob.n_pix * reps / (time.perf_counter() - t0) / 1e6
+
+
+def run_cutouts(args, torch, apx, synth):
+    """4096 independent cutouts: the batched LM (every kernel over all cutouts, one HIP
+    graph replay per iteration) against the plain per-cutout path (one problem per
+    cutout, eager launches, a host read of the LM state after every iteration)."""
+    t0 = time.perf_counter()
+    spec = synth.cutouts()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    prob = apx.Problem(spec)
+    t_plan = time.perf_counter() - t0
+    print(f"[bench] cutouts: {len(spec['subs'])} sub-problems, {prob.n_pix / 1e6:.1f} Mpix, "
+          f"plan {t_plan:.1f} s, workspace {prob.workspace_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+    data, weight = _data(prob, spec, synth)
+    dd, ww = prob.pixels(data), prob.pixels(weight)
+    th, st = prob.lm_init(spec["theta_init"], dd, ww)
+    prob.lm_run(max(1, args.warmup), dd, ww, th, st, use_graph=True)
+    torch.cuda.synchronize()
+    th, st = prob.lm_init(spec["theta_init"], dd, ww, theta_out=th, state_out=st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.lm_run(args.steps, dd, ww, th, st, use_graph=True)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    stt = prob.lm_state(st)
+    # eager batched, same work
+    th2, st2 = prob.lm_init(spec["theta_init"], dd, ww)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.lm_run(args.steps, dd, ww, th2, st2, use_graph=False)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    same = bool(torch.equal(th, th2))
+    n_sub = len(spec["subs"])
+    batched = n_sub * args.steps / t_graph
+    # plain path on a sample of cutouts
+    sample = list(range(0, n_sub, max(1, n_sub // 32)))
+    offs = np.concatenate([[0], np.cumsum([im["H"] * im["W"] for im in spec["images"]])])
+    t_plain = 0.0
+    for s_ in sample:
+        sub = synth.sub_spec(spec, s_)
+        pp = apx.Problem(sub)
+        ks = [k for k, im in enumerate(spec["images"]) if im["sub"] == s_]
+        d_s = pp.pixels([data[k] for k in ks])
+        w_s = pp.pixels([weight[k] for k in ks])
+        ths, sts = pp.lm_init(sub["theta_init"], d_s, w_s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pp.lm_step(d_s, w_s, ths, sts)
+            pp.lm_state(sts)                      # the plain path's host-side check
+        t_plain += time.perf_counter() - t0
+        pp.close()
+    plain = len(sample) * args.steps / t_plain
+    mpix = _mpix(prob, spec, torch, 5)
+    _line({
+        "metric": "LM iters/s & Mpix/s rendered (fused adjoint+batched vs plain) at oracle rtol",
+        "workload": "cutouts", "value": batched, "unit": "cutout LM it/s",
+        "batch_it_per_s": args.steps / t_graph, "ms_per_batch_iteration": t_graph * 1e3 / args.steps,
+        "eager_batch_it_per_s": args.steps / t_eager, "graph_equals_eager": same,
+        "plain_cutout_it_per_s": plain, "speedup_batched_vs_plain": batched / plain,
+        "plain_sample_cutouts": len(sample), "steps": args.steps, "n_gpus": 1,
+        "mpix_per_s": mpix, "accepted_mean": float(np.mean(stt["n_accept"])),
+        "config": {"workload": "4096 cutouts, side 32-256 px log-uniform, 1-5 Sersic + sky each, "
+                               "Gaussian/Moffat PSF 15-31 px, 3x3 nodes",
+                   "n_sub": n_sub, "n_par": spec["n_par"], "n_pix": prob.n_pix,
+                   "plan_s": t_plan, "generate_s": t_gen},
+        "dtype": "f32 Jacobian / f64 objective+normal equations", "data": "synthetic"})
+    return 0
+
+
+def run_field(args, torch, apx, synth):
+    """2048 x 2048 field, 500 windowed Sersics + sky, Moffat 51 x 51: chi^2 gradient
+    evaluations per second by the adjoint path; checked against central differences of
+    the FP64 chi^2 on 32 seeded parameters."""
+    spec = synth.field()
+    prob = apx.Problem(spec)
+    data, weight = _data(prob, spec, synth)
+    dd, ww = prob.pixels(data), prob.pixels(weight)
+    th = torch.as_tensor(spec["theta_init"], dtype=torch.float64, device=prob.device)
+    for _ in range(3):
+        prob.chi2_grad(th, dd, ww)
+    torch.cuda.synchronize()
+    reps = max(args.steps, 1) * 50
+    prob.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g, c2 = prob.chi2_grad(th, dd, ww)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = prob.timing()
+    prob.set_timing(False)
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(33)
+    idx = rng.choice(spec["n_par"], 32, replace=False)
+    fd_err = []
+    base = spec["theta_init"].copy()
+    for k in idx:
+        # 1e-3 of the parameter's own scale: its value, or Re for a centre coordinate (a
+        # step relative to x ~ 2000 px would cross the profile's cusp)
+        ref = spec["scale"][k] if spec["kinds"][k] in (synth.K_X, synth.K_Y) else abs(base[k])
+        h = 1e-3 * max(ref, 1e-2)
+        tp, tm = base.copy(), base.copy()
+        tp[k] += h
+        tm[k] -= h
+        cp = float(prob.chi2(tp, dd, ww).cpu()[0])
+        cm = float(prob.chi2(tm, dd, ww).cpu()[0])
+        fd = (cp - cm) / (2 * h)
+        fd_err.append(abs(fd - g[k]) / max(abs(g[k]), 1e-3 * np.max(np.abs(g))))
+    P_psf = spec["images"][0]["psf"].shape[0]
+    adj_ms, adj_n = kt["conv_adj"]
+    flop_adj = 2.0 * P_psf * P_psf * prob.n_ext * adj_n
+    achieved = flop_adj / (adj_ms * 1e-3) / 1e12 if adj_ms > 0 else 0.0
+    _line({
+        "metric": "LM iters/s & Mpix/s rendered (fused adjoint+batched vs plain) at oracle rtol",
+        "workload": "field", "value": reps / dt, "unit": "gradient evals/s",
+        "ms_per_gradient": dt * 1e3 / reps, "n_gpus": 1, "evals": reps,
+        "fd_check_32": {"max_rel_err": float(np.max(fd_err)), "median_rel_err": float(np.median(fd_err)),
+                        "h": "1e-3 of |theta_k| (of Re for centre coordinates)"},
+        "mpix_per_s": _mpix(prob, spec, torch, 10),
+        "roofline": {"bound": "alu", "kernel": f"k_conv<{P_psf},ADJ>", "achieved": achieved,
+                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS},
+        "kernel_ms_per_eval": {k: round(v[0] / reps, 4) for k, v in kt.items()},
+        "config": {"workload": "2048x2048 field, 500 Sersic (10 Re windows) + sky, Moffat 51x51 beta 3 "
+                               "FWHM 4, 3x3 nodes", "n_par": spec["n_par"], "n_pix": prob.n_pix},
+        "dtype": "f32 adjoint / f64 objective", "data": "synthetic"})
+    return 0
+
+
+def run_lm_workload(args, torch, apx, synth, spec, label, desc):
+    prob = apx.Problem(spec)
+    data, weight = _data(prob, spec, synth)
+    dd, ww = prob.pixels(data), prob.pixels(weight)
+    th, st = prob.lm_init(spec["theta_init"], dd, ww)
+    prob.lm_run(args.warmup, dd, ww, th, st)
+    torch.cuda.synchronize()
+    th, st = prob.lm_init(spec["theta_init"], dd, ww)
+    torch.cuda.synchronize()
+    prob.set_timing(True)
+    t0 = time.perf_counter()
+    prob.lm_run(args.steps, dd, ww, th, st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = prob.timing()
+    prob.set_timing(False)
+    stt = prob.lm_state(st)
+    _line({
+        "metric": "LM iters/s & Mpix/s rendered (fused adjoint+batched vs plain) at oracle rtol",
+        "workload": label, "value": args.steps / dt, "unit": "LM it/s", "ms_per_step": dt * 1e3 / args.steps,
+        "n_gpus": 1, "steps": args.steps, "mpix_per_s": _mpix(prob, spec, torch, 10),
+        "accepted": int(stt["n_accept"][0]),
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
+        "config": {"workload": desc, "n_par": spec["n_par"], "n_pix": prob.n_pix},
+        "dtype": "f32 Jacobian / f64 objective+normal equations", "data": "synthetic"})
+    return 0
+
+
+def run_multiband(args, torch, apx, synth):
+    return run_lm_workload(args, torch, apx, synth, synth.multiband(), "multiband",
+                           "3 bands x 2 epochs of 2048x2048, per-image affine and Moffat 41x41, 300 galaxies "
+                           "with shared shape and per-band Ie, 2706 params")
+
+
+def run_single(args, torch, apx, synth):
+    return run_lm_workload(args, torch, apx, synth, synth.single(), "single",
+                           "64x64, 1 Sersic + sky, Gaussian 11x11 sigma 1.5, 3x3 nodes, 8 params")
+
+
+OTHER_WORKLOADS = {"cutouts": run_cutouts, "field": run_field, "multiband": run_multiband,
+                   "single": run_single}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +290,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--render-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="blend",
+                    choices=["blend", "cutouts", "field", "multiband", "single"],
+                    help="blend (default, the headline line); the others print their own line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -103,6 +305,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         return 1
+    if args.workload != "blend":
+        return OTHER_WORKLOADS[args.workload](args, torch, apx, synth)
 
     spec = synth.blend()                       # 512x512, 50 Sersic + 200 PS, Moffat 25
     img = spec["images"][0]

@@ -164,7 +164,9 @@ const char* apx_version(void);
 const char* apx_status_string(apx_status s);
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL = the
- * default stream).  Errors: APX_E_INVALID (null out), APX_E_HIP. */
+ * default stream).  device = -1 creates a host-only context: problems can be created
+ * (validated and planned) and sized, but not bound or run.  Errors: APX_E_INVALID
+ * (null out), APX_E_HIP. */
 apx_status apx_ctx_create(int device, void* hip_stream, apx_ctx** out);
 apx_status apx_ctx_set_stream(apx_ctx* ctx, void* hip_stream);
 apx_status apx_ctx_destroy(apx_ctx* ctx);

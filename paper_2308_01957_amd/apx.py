@@ -300,13 +300,20 @@ class Problem:
         self._leave()
         return g, c2
 
-    def lm_init(self, theta, data, weight):
-        """Returns (theta device copy, state device buffer) ready for lm_step / lm_run."""
+    def lm_init(self, theta, data, weight, theta_out=None, state_out=None):
+        """Returns (theta device copy, state device buffer) ready for lm_step / lm_run.
+        theta_out / state_out reuse existing buffers (a captured graph keys on them)."""
         t = self.torch
-        th = self._dev(theta, t.float64).clone()
-        self._enter(th, data, weight)
+        src = self._dev(theta, t.float64)
+        self._enter(src, data, weight)
         with t.cuda.stream(self.stream):
-            state = t.zeros(self.n_sub * LM_STATE_BYTES, dtype=t.uint8, device=self.device)
+            if theta_out is None:
+                th = src.clone()
+            else:
+                th = theta_out
+                th.copy_(src)
+            state = state_out if state_out is not None else \
+                t.zeros(self.n_sub * LM_STATE_BYTES, dtype=t.uint8, device=self.device)
             self._check(self.lib.apx_lm_init(self._prob, th.data_ptr(), data.data_ptr(), weight.data_ptr(),
                                              state.data_ptr()))
         self._leave()
@@ -344,6 +351,50 @@ class Problem:
     def close(self):
         if getattr(self, "_prob", None):
             self.stream.synchronize()
+            self.lib.apx_problem_destroy(self._prob)
+            self._prob = None
+        if getattr(self, "_ctx", None):
+            self.lib.apx_ctx_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Host-only view of a problem (device -1): descriptor validation and plan sizes,
+    no GPU needed.  Raises ApxError exactly as Problem would for a bad spec."""
+
+    def __init__(self, spec: Dict, objective: int = 0):
+        self.lib = load_library()
+        self._ctx = ctypes.c_void_p()
+        st = self.lib.apx_ctx_create(-1, None, ctypes.byref(self._ctx))
+        if st != APX_OK:
+            raise ApxError(st, "host context")
+        idesc, cdesc, sp = _descs(spec)
+        sampling = spec["sampling"]
+        desc = ProblemDesc(len(spec["images"]), len(spec["comps"]), int(spec["n_par"]), len(spec["subs"]),
+                           idesc, cdesc, sp, None, int(sampling["s"]), int(sampling["rule"]),
+                           int(sampling["mode"]), int(objective), float(sampling.get("k", 0.0)))
+        self._prob = ctypes.c_void_p()
+        st = self.lib.apx_problem_create(self._ctx, ctypes.byref(desc), ctypes.byref(self._prob))
+        if st != APX_OK:
+            msg = self.lib.apx_last_error(self._ctx).decode()
+            self.lib.apx_ctx_destroy(self._ctx)
+            self._ctx = None
+            raise ApxError(st, msg)
+        nbytes = ctypes.c_uint64()
+        self.lib.apx_problem_workspace_bytes(self._prob, ctypes.byref(nbytes))
+        self.workspace_bytes = int(nbytes.value)
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self.lib.apx_problem_sizes(self._prob, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        self.n_pix, self.n_ext, self.n_jac = int(a.value), int(b.value), int(c.value)
+
+    def close(self):
+        if getattr(self, "_prob", None):
             self.lib.apx_problem_destroy(self._prob)
             self._prob = None
         if getattr(self, "_ctx", None):

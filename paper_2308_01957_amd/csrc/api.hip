@@ -254,7 +254,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     P->psf = d->psf;
     if (d->n_images < 1 || d->n_comps < 0 || d->n_par < 0 || d->n_sub < 1)
         return fail(C, APX_E_INVALID, "counts: need n_images >= 1, n_sub >= 1, n_comps, n_par >= 0");
-    if (!d->images || (d->n_comps > 0 && !d->comps) || !d->sub_par || !d->psf)
+    if (!d->images || (d->n_comps > 0 && !d->comps) || !d->sub_par || (!d->psf && C->device >= 0))
         return fail(C, APX_E_INVALID, "null descriptor pointer");
     if (d->s < 1 || d->s > MAX_NODES_1D) return fail(C, APX_E_UNSUPPORTED, "s must be in 1..8");
     if (d->rule != APX_RULE_MIDPOINT && d->rule != APX_RULE_GAUSS_LEGENDRE)
@@ -845,6 +845,7 @@ static void layout(apx_problem* P) {
     ws_take<double>(P, "gvec", P->n_par);
     ws_take<double>(P, "Ddiag", P->n_par);
     ws_take<double>(P, "hvec", P->n_par);
+    ws_take<double>(P, "yvec", P->n_par);
     ws_take<double>(P, "theta_trial", P->n_par);
     ws_take<LMFlags>(P, "lmf", P->n_sub);
     ws_take<int>(P, "sticky", 1);
@@ -886,6 +887,12 @@ const char* apx_status_string(apx_status s) {
 apx_status apx_ctx_create(int device, void* hip_stream, apx_ctx** out) {
     if (!out) return APX_E_INVALID;
     *out = nullptr;
+    if (device == -1) {                       // host-only: validate and plan, never launch
+        apx_ctx* c = new apx_ctx();
+        c->device = -1;
+        *out = c;
+        return APX_OK;
+    }
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return APX_E_HIP;
     if (hipSetDevice(device) != hipSuccess) return APX_E_HIP;
@@ -945,6 +952,7 @@ apx_status apx_problem_sizes(const apx_problem* P, int64_t* n_pix, int64_t* n_ex
 
 apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes) {
     if (!P) return APX_E_INVALID;
+    if (P->ctx->device < 0) return fail(P->ctx, APX_E_INVALID, "host-only context cannot bind a workspace");
     if (!dev || bytes < P->L.total || ((uintptr_t)dev & 255) != 0)
         return fail(P->ctx, APX_E_WORKSPACE, "workspace null, misaligned or smaller than required");
     P->ws = (char*)dev;
@@ -1048,6 +1056,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.gvec = wsp<double>(P, "gvec");
     p.Ddiag = wsp<double>(P, "Ddiag");
     p.hvec = wsp<double>(P, "hvec");
+    p.yvec = wsp<double>(P, "yvec");
     p.theta_trial = wsp<double>(P, "theta_trial");
     p.lmf = wsp<LMFlags>(P, "lmf");
     p.sticky = wsp<int>(P, "sticky");

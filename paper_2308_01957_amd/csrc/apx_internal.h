@@ -145,6 +145,7 @@ struct Plan {
     double* M;                // Cholesky factor (per sub)
     double* Ddiag;            // damping diagonal [n_par]
     double* hvec;             // step [n_par]
+    double* yvec;             // substitution right-hand side [n_par]
     double* theta_trial;      // [n_par]
     LMFlags* lmf;             // [n_sub]
     int* sticky;              // device error flags

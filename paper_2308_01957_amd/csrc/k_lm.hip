@@ -156,10 +156,12 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 }
 
 // Cholesky of a 64 x 64 block held in registers by one wave: lane i owns row i (a[q],
-// q <= i).  Rows at or beyond nb must arrive as identity rows.  Fully unrolled, so every
-// register index is static; the column values move between lanes by readlane.
+// q <= i; entries above the diagonal are scratch).  Rows at or beyond the block size must
+// arrive as identity rows.  Per column j: the pivot comes from lane j, every lane scales
+// its a[j], the scaled column goes through LDS (col) and every later entry of every row is
+// updated with broadcast reads -- no lane masks, fully unrolled, wave-synchronous.
 // Returns false in every lane on a non-positive or non-finite pivot.
-__device__ __forceinline__ bool chol64_regs(double (&a)[CHOL_NB], int lane) {
+__device__ __forceinline__ bool chol64_regs(double (&a)[CHOL_NB], int lane, double* col) {
 #pragma unroll
     for (int j = 0; j < CHOL_NB; ++j) {
         const double piv = lane_bcast(a[j], j);
@@ -167,13 +169,25 @@ __device__ __forceinline__ bool chol64_regs(double (&a)[CHOL_NB], int lane) {
         const double ljj = sqrt(piv);
         const double lij = lane > j ? a[j] / ljj : 0.0;
         a[j] = lane > j ? lij : (lane == j ? ljj : a[j]);
+        col[lane] = lij;
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int q = j + 1; q < CHOL_NB; ++q) {
-            const double lqj = lane_bcast(lij, q);
-            if (lane >= q) a[q] = fma(-lij, lqj, a[q]);
-        }
+        for (int q = j + 1; q < CHOL_NB; ++q) a[q] = fma(-lij, col[q], a[q]);
+        __builtin_amdgcn_wave_barrier();
     }
     return true;
+}
+
+// x L^T = m for one row per lane (x in registers), L in LDS: right-looking, so the
+// updates of one column are independent FMAs.  Identity padding beyond nb is harmless.
+__device__ __forceinline__ void trsm_row_regs(double (&x)[CHOL_NB], const double (*L)[CHOL_NB + 1], int nb) {
+    (void)nb;
+#pragma unroll
+    for (int j = 0; j < CHOL_NB; ++j) {
+        x[j] = x[j] / L[j][j];
+#pragma unroll
+        for (int q = j + 1; q < CHOL_NB; ++q) x[q] = fma(-x[j], L[q][j], x[q]);
+    }
 }
 
 // Stage the nr x nc block at (r0, c0) of the n x n row-major matrix into LDS with
@@ -189,18 +203,6 @@ __device__ __forceinline__ void stage_block(const double* Mg, int n, int r0, int
     }
 }
 
-// x L^T = m for one row per lane, L in LDS (broadcast reads), x in registers.
-__device__ __forceinline__ void trsm_row_regs(double (&x)[CHOL_NB], const double (*L)[CHOL_NB + 1], int nb) {
-#pragma unroll
-    for (int j = 0; j < CHOL_NB; ++j) {
-        if (j < nb) {
-            double v = x[j];
-#pragma unroll
-            for (int q = 0; q < j; ++q) v = fma(-x[q], L[j][q], v);
-            x[j] = v / L[j][j];
-        }
-    }
-}
 
 __global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
     // one block: damping diagonal D from the diagonal of A and its maximum
@@ -239,6 +241,7 @@ __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
 __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
     __shared__ double L[CHOL_NB][CHOL_NB + 1];
     __shared__ double X[CHOL_NB][CHOL_NB + 1];
+    __shared__ double col[CHOL_NB];
     __shared__ int bad;
     if (p.lmf[s].chol_fail) return;
     const DSub sb = p.subs[s];
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
         double a[CHOL_NB];
 #pragma unroll
         for (int q = 0; q < CHOL_NB; ++q) a[q] = L[lane][q];
-        const bool ok = chol64_regs(a, lane);
+        const bool ok = chol64_regs(a, lane, col);
         if (lane == 0) bad = ok ? 0 : 1;
 #pragma unroll
         for (int q = 0; q < CHOL_NB; ++q) L[lane][q] = a[q];
@@ -288,39 +291,54 @@ __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
     }
 }
 
-// Trailing update M_ij -= L_ik L_jk^T of one 64 x 64 block pair, 4 x 4 outputs per lane.
+// Trailing update M_ij -= L_ik L_jk^T of one 64 x 64 block pair on FP64 MFMA: both
+// 64 x 64 panels are staged in LDS, each wave accumulates a 32 x 32 quadrant as 2 x 2
+// tiles of v_mfma_f64_16x16x4 (D[i][j] in lane j + 16 (i % 4), register i / 4).
+typedef double chol_d4 __attribute__((ext_vector_type(4)));
 __device__ void chol_update_block(double* Mg, int n, int ri, int rj, int kc, bool diag,
-                                  double (*Li)[17], double (*Lj)[17]) {
+                                  double (*Li)[CHOL_NB + 1], double (*Lj)[CHOL_NB + 1]) {
     const int ni = min(CHOL_NB, n - ri), nj = min(CHOL_NB, n - rj), nk = min(CHOL_NB, n - kc);
-    const int t = threadIdx.x;
-    const int ti = (t >> 4) * 4, tj = (t & 15) * 4;
-    double acc[4][4];
-    for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int k0 = 0; k0 < nk; k0 += 16) {
-        for (int q = t; q < CHOL_NB * 16; q += 256) {
-            const int r = q >> 4, k = q & 15;
-            Li[r][k] = (r < ni && k0 + k < nk) ? Mg[(long long)(ri + r) * n + kc + k0 + k] : 0.0;
-            Lj[r][k] = (r < nj && k0 + k < nk) ? Mg[(long long)(rj + r) * n + kc + k0 + k] : 0.0;
-        }
-        __syncthreads();
-        for (int k = 0; k < 16; ++k) {
-            double a[4], b[4];
-            for (int u = 0; u < 4; ++u) { a[u] = Li[ti + u][k]; b[u] = Lj[tj + u][k]; }
-            for (int u = 0; u < 4; ++u)
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-        }
-        __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int e = t; e < CHOL_NB * CHOL_NB; e += 256) {
+        const int r = e >> 6, k = e & 63;
+        Li[r][k] = (r < ni && k < nk) ? Mg[(long long)(ri + r) * n + kc + k] : 0.0;
+        Lj[r][k] = (r < nj && k < nk) ? Mg[(long long)(rj + r) * n + kc + k] : 0.0;
     }
-    for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v) {
-            const int i = ti + u, j = tj + v;
-            if (i < ni && j < nj && (!diag || j <= i)) Mg[(long long)(ri + i) * n + rj + j] -= acc[u][v];
-        }
+    __syncthreads();
+    const int wr = wv >> 1, wc = wv & 1;
+    chol_d4 acc[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[m][q] = (chol_d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < CHOL_NB; k0 += 4) {
+        double av[2], bv[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) av[m] = Li[wr * 32 + m * 16 + (lane & 15)][k0 + (lane >> 4)];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) bv[q] = Lj[wc * 32 + q * 16 + (lane & 15)][k0 + (lane >> 4)];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[q], acc[m][q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = wr * 32 + m * 16 + (lane >> 4) + 4 * v;
+                const int j = wc * 32 + q * 16 + (lane & 15);
+                if (i < ni && j < nj && (!diag || j <= i)) Mg[(long long)(ri + i) * n + rj + j] -= acc[m][q][v];
+            }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, int nblk) {
-    __shared__ double Li[CHOL_NB][17], Lj[CHOL_NB][17];
+    __shared__ double Li[CHOL_NB][CHOL_NB + 1], Lj[CHOL_NB][CHOL_NB + 1];
     if (p.lmf[s].chol_fail) return;
     const DSub sb = p.subs[s];
     // block index -> (bi, bj), bj <= bi, both after kblk
@@ -337,7 +355,8 @@ __global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, in
 __global__ __launch_bounds__(256) void k_chol_retry(Plan p, int s, apx_lm_state* lm) {
     __shared__ double L[CHOL_NB][CHOL_NB + 1];
     __shared__ double X[CHOL_NB][CHOL_NB + 1];
-    __shared__ double Li[CHOL_NB][17], Lj[CHOL_NB][17];
+    __shared__ double Li[CHOL_NB][CHOL_NB + 1], Lj[CHOL_NB][CHOL_NB + 1];
+    __shared__ double col[CHOL_NB];
     __shared__ int bad;
     const int t = threadIdx.x, lane = t & 63;
     if (!p.lmf[s].chol_fail) {
@@ -367,7 +386,7 @@ __global__ __launch_bounds__(256) void k_chol_retry(Plan p, int s, apx_lm_state*
                 double a[CHOL_NB];
 #pragma unroll
                 for (int q = 0; q < CHOL_NB; ++q) a[q] = L[lane][q];
-                const bool okw = chol64_regs(a, lane);
+                const bool okw = chol64_regs(a, lane, col);
                 if (lane == 0) bad = okw ? 0 : 1;
 #pragma unroll
                 for (int q = 0; q < CHOL_NB; ++q) L[lane][q] = a[q];
@@ -412,90 +431,116 @@ __global__ __launch_bounds__(256) void k_chol_retry(Plan p, int s, apx_lm_state*
     }
 }
 
-// Forward and back substitution, right-looking by CHOL_NB blocks: a diagonal block is
-// solved by wave 0 from registers (readlane broadcasts), then every later (earlier)
-// right-hand-side entry is updated by the workgroup reading contiguous rows (columns)
-// of the factor.  pred = h^T (lambda D h + g).
-__global__ __launch_bounds__(256) void k_chol_solve(Plan p, int s, apx_lm_state* lm) {
-    extern __shared__ double y[];
-    __shared__ double red[4];
+// Forward and back substitution, one launch per CHOL_NB block.  Every workgroup of a
+// launch solves the diagonal block in wave 0's registers (readlane broadcasts); workgroup 0
+// stores that part of the solution, the others update their own 64-entry slice of the
+// right-hand side with the block's contiguous rows (forward) or columns (backward).
+// The right-hand side lives in Ddiag's companion vector yvec.
+__global__ __launch_bounds__(256) void k_subst_fwd(Plan p, int s, int b) {
     __shared__ double Lb[CHOL_NB][CHOL_NB + 1];
+    __shared__ double ysh[CHOL_NB];
+    __shared__ double part[4][CHOL_NB];
+    if (!p.lmf[s].chol_done) return;
     const DSub sb = p.subs[s];
     const int n = sb.n;
     const double* L = p.M + sb.a_off;
-    const double* g = p.gvec + sb.p0;
+    double* y = p.yvec + sb.p0;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    if (!p.lmf[s].chol_done) {
-        for (int i = t; i < n; i += blockDim.x) p.hvec[sb.p0 + i] = 0.0;
-        if (t == 0) lm[s].pred = 0.0;
+    const int r0 = b * CHOL_NB, nr = min(CHOL_NB, n - r0);
+    stage_block(L, n, r0, r0, nr, nr, Lb, true);
+    __syncthreads();
+    if (wv == 0) {
+        double a[CHOL_NB];
+#pragma unroll
+        for (int q = 0; q < CHOL_NB; ++q) a[q] = Lb[lane][q];
+        double yi = lane < nr ? (b == 0 ? p.gvec[sb.p0 + r0 + lane] : y[r0 + lane]) : 0.0;
+#pragma unroll
+        for (int j = 0; j < CHOL_NB; ++j) {
+            const double yj = lane_bcast(yi, j) / lane_bcast(a[j], j);
+            if (lane == j) yi = yj;
+            else if (lane > j) yi = fma(-a[j], yj, yi);
+        }
+        ysh[lane] = lane < nr ? yi : 0.0;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        if (t < nr) y[r0 + t] = ysh[t];
         return;
     }
-    for (int i = t; i < n; i += blockDim.x) y[i] = g[i];
+    const int rb = r0 + blockIdx.x * CHOL_NB;       // row block updated by this workgroup
+    if (rb >= n) return;
+    const int i = rb + (t >> 2), kq = t & 3;
+    double acc = 0.0;
+    if (i < n) {
+        const double* Li = L + (long long)i * n + r0;
+        for (int k = kq * 16; k < min(nr, kq * 16 + 16); ++k) acc = fma(Li[k], ysh[k], acc);
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    // the first launch starts every later entry from g (each workgroup owns its rows)
+    if (kq == 0 && i < n) y[i] = (b == 0 ? p.gvec[sb.p0 + i] : y[i]) - acc;
+}
+
+__global__ __launch_bounds__(256) void k_subst_bwd(Plan p, int s, int b) {
+    __shared__ double Lb[CHOL_NB][CHOL_NB + 1];
+    __shared__ double hsh[CHOL_NB];
+    __shared__ double part[4][CHOL_NB];
+    if (!p.lmf[s].chol_done) return;
+    const DSub sb = p.subs[s];
+    const int n = sb.n;
+    const double* L = p.M + sb.a_off;
+    double* y = p.yvec + sb.p0;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int r0 = b * CHOL_NB, nr = min(CHOL_NB, n - r0);
+    stage_block(L, n, r0, r0, nr, nr, Lb, true);
     __syncthreads();
-    const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
-    for (int b = 0; b < nblk; ++b) {                 // L y = g
-        const int r0 = b * CHOL_NB, nr = min(CHOL_NB, n - r0);
-        stage_block(L, n, r0, r0, nr, nr, Lb, true);
-        __syncthreads();
-        if (wv == 0) {
-            double a[CHOL_NB];
+    if (wv == 0) {
+        double c[CHOL_NB];                           // column lane of the block: c[j] = L[r0+j][r0+lane]
 #pragma unroll
-            for (int q = 0; q < CHOL_NB; ++q) a[q] = Lb[lane][q];
-            double yi = lane < nr ? y[r0 + lane] : 0.0;
+        for (int q = 0; q < CHOL_NB; ++q) c[q] = Lb[q][lane];
+        double yi = lane < nr ? y[r0 + lane] : 0.0;
 #pragma unroll
-            for (int j = 0; j < CHOL_NB; ++j) {
-                const double yj = lane_bcast(yi, j) / lane_bcast(a[j], j);
-                if (lane == j) yi = yj;
-                else if (lane > j) yi = fma(-a[j], yj, yi);
-            }
-            if (lane < nr) y[r0 + lane] = yi;
+        for (int j = CHOL_NB - 1; j >= 0; --j) {
+            const double hj = lane_bcast(yi, j) / lane_bcast(c[j], j);
+            if (lane == j) yi = hj;
+            else if (lane < j) yi = fma(-c[j], hj, yi);
         }
-        __syncthreads();
-        for (int i = r0 + nr + t; i < n; i += 256) {
-            const double* Li = L + (long long)i * n + r0;
-            double acc = 0.0;
-            for (int k = 0; k < nr; ++k) acc = fma(Li[k], y[r0 + k], acc);
-            y[i] -= acc;
-        }
-        __syncthreads();
+        hsh[lane] = lane < nr ? yi : 0.0;
     }
-    for (int b = nblk - 1; b >= 0; --b) {            // L^T h = y
-        const int r0 = b * CHOL_NB, nr = min(CHOL_NB, n - r0);
-        stage_block(L, n, r0, r0, nr, nr, Lb, true);
-        __syncthreads();
-        if (wv == 0) {
-            // lane i takes column i of the block: c[j] = L[r0 + j][r0 + i]
-            double c[CHOL_NB];
-#pragma unroll
-            for (int q = 0; q < CHOL_NB; ++q) c[q] = Lb[q][lane];
-            double yi = lane < nr ? y[r0 + lane] : 0.0;
-#pragma unroll
-            for (int j = CHOL_NB - 1; j >= 0; --j) {
-                const double hj = lane_bcast(yi, j) / lane_bcast(c[j], j);
-                if (lane == j) yi = hj;
-                else if (lane < j) yi = fma(-c[j], hj, yi);
-            }
-            if (lane < nr) y[r0 + lane] = yi;
-        }
-        __syncthreads();
-        for (int i = t; i < r0; i += 256) {
-            double acc = 0.0;
-            for (int k = 0; k < nr; ++k) acc = fma(L[(long long)(r0 + k) * n + i], y[r0 + k], acc);
-            y[i] -= acc;
-        }
-        __syncthreads();
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        if (t < nr) y[r0 + t] = hsh[t];
+        return;
     }
+    const int cb = (blockIdx.x - 1) * CHOL_NB;      // column block updated by this workgroup
+    if (cb >= r0) return;
+    const int i = cb + lane;
+    double acc = 0.0;
+    if (i < r0)
+        for (int k = wv; k < nr; k += 4) acc = fma(L[(long long)(r0 + k) * n + i], hsh[k], acc);
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && i < r0) y[i] -= ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+}
+
+// h = y, pred = h^T (lambda D h + g); zeros when the factorisation failed.
+__global__ __launch_bounds__(256) void k_subst_finish(Plan p, int s, apx_lm_state* lm) {
+    __shared__ double red[4];
+    const DSub sb = p.subs[s];
+    const int n = sb.n;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const bool done = p.lmf[s].chol_done != 0;
     const double lam = lm[s].lambda;
     double v = 0.0;
-    for (int i = t; i < n; i += blockDim.x) {
-        const double h = y[i];
+    for (int i = t; i < n; i += 256) {
+        const double h = done ? p.yvec[sb.p0 + i] : 0.0;
         p.hvec[sb.p0 + i] = h;
-        v += h * (lam * p.Ddiag[sb.p0 + i] * h + g[i]);
+        v += h * (lam * p.Ddiag[sb.p0 + i] * h + p.gvec[sb.p0 + i]);
     }
     v = lm_wave_sum(v);
     if (lane == 0) red[wv] = v;
     __syncthreads();
-    if (t == 0) lm[s].pred = ((red[0] + red[1]) + red[2]) + red[3];
+    if (t == 0) lm[s].pred = done ? ((red[0] + red[1]) + red[2]) + red[3] : 0.0;
 }
 
 hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipStream_t st) {
@@ -511,7 +556,11 @@ hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipS
         if (T > 0) hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk);
     }
     hipLaunchKernelGGL(k_chol_retry, dim3(1), dim3(256), 0, st, p, s, lm);
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), (size_t)n * sizeof(double), st, p, s, lm);
+    for (int b = 0; b < nblk; ++b)
+        hipLaunchKernelGGL(k_subst_fwd, dim3(nblk - b), dim3(256), 0, st, p, s, b);
+    for (int b = nblk - 1; b >= 0; --b)
+        hipLaunchKernelGGL(k_subst_bwd, dim3(b + 1), dim3(256), 0, st, p, s, b);
+    hipLaunchKernelGGL(k_subst_finish, dim3(1), dim3(256), 0, st, p, s, lm);
     return hipGetLastError();
 }
 

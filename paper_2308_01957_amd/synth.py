@@ -461,3 +461,31 @@ def spec_summary(spec: Dict) -> Dict:
 def stack_images(arrays: List[np.ndarray], dtype=np.float32) -> np.ndarray:
     """Concatenate per-image arrays (row-major, image order) into one flat buffer."""
     return np.concatenate([np.ascontiguousarray(a, dtype=dtype).ravel() for a in arrays])
+
+
+def sub_spec(spec: Dict, sub: int) -> Dict:
+    """The spec of one sub-problem on its own (its images, components and parameters,
+    re-indexed from zero) -- a single cutout of a batched workload."""
+    p0, n = spec["subs"][sub]
+    ks = [k for k, im in enumerate(spec["images"]) if im["sub"] == sub]
+    kmap = {k: i for i, k in enumerate(ks)}
+    images = []
+    for k in ks:
+        im = dict(spec["images"][k])
+        im["sub"] = 0
+        im["sky_par"] = im["sky_par"] - p0 if im["sky_par"] >= 0 else -1
+        images.append(im)
+    comps = []
+    for c in spec["comps"]:
+        if c["image"] in kmap:
+            c2 = dict(c)
+            c2["image"] = kmap[c["image"]]
+            c2["par"] = [q - p0 if q >= 0 else -1 for q in c["par"]]
+            comps.append(c2)
+    out = {"name": f"{spec['name']}_sub{sub}", "images": images, "comps": comps, "subs": [(0, n)],
+           "sampling": dict(spec["sampling"]), "theta_true": spec["theta_true"][p0:p0 + n],
+           "kinds": spec["kinds"][p0:p0 + n], "re_of": spec["re_of"][p0:p0 + n]}
+    _finish(out)
+    out["theta_init"] = spec["theta_init"][p0:p0 + n].copy()
+    out["noise"] = [spec["noise"][k] for k in ks]
+    return out

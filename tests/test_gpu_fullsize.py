@@ -1,0 +1,255 @@
+"""Parity at the benchmark workloads' full sizes, in the configuration bench.py times,
+on outputs the FP64 oracle can compute one by one: whole images where affordable,
+otherwise pixel patches (the model of a patch only needs the components whose windows
+reach it -- each pixel is evaluated independently by definition), sampled Jacobian
+columns, J^T W J / J^T W r entries among them, sampled gradient entries, and the
+linear-algebra identity (A + lambda D) h = g for the LM step on the full system."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_01957_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2308_01957_amd import apx as mod
+    return mod
+
+
+def _tol(m):
+    return 1e-5 * np.abs(m) + 1e-7 * np.max(np.abs(m))
+
+
+def _local_ext(spec, theta, k, y0, x0, y1, x1):
+    """Pre-convolution image S on the extended-grid box [y0,y1) x [x0,x1) of image k."""
+    S = np.zeros((y1 - y0, x1 - x0))
+    for comp in spec["comps"]:
+        if comp["image"] != k:
+            continue
+        by0, bx0, by1, bx1 = comp["box"]
+        iy0, ix0, iy1, ix1 = max(by0, y0), max(bx0, x0), min(by1, y1), min(bx1, x1)
+        if iy1 <= iy0 or ix1 <= ix0:
+            continue
+        part = dict(comp, box=(iy0, ix0, iy1, ix1))
+        S[iy0 - y0:iy1 - y0, ix0 - x0:ix1 - x0] += oracle.comp_pixels(spec, part, theta)
+    return S
+
+
+def _local_model(spec, theta, k, y0, x0, h, w):
+    """Oracle model of the h x w pixel patch at (y0, x0) of image k."""
+    im = spec["images"][k]
+    c = oracle.psf_half(im)
+    S = _local_ext(spec, theta, k, y0 - c, x0 - c, y0 + h + c, x0 + w + c)
+    return oracle.convolve_valid(S, im["psf"]) + oracle.sky_value(im, theta)
+
+
+def _local_jcol(spec, theta, k, par, y0, x0, h, w):
+    """Oracle Jacobian column of theta index `par` on a patch of image k."""
+    im = spec["images"][k]
+    c = oracle.psf_half(im)
+    D = np.zeros((h + 2 * c, w + 2 * c))
+    for comp in spec["comps"]:
+        if comp["image"] != k or par not in comp["par"]:
+            continue
+        by0, bx0, by1, bx1 = comp["box"]
+        iy0, ix0 = max(by0, y0 - c), max(bx0, x0 - c)
+        iy1, ix1 = min(by1, y0 + h + c), min(bx1, x0 + w + c)
+        if iy1 <= iy0 or ix1 <= ix0:
+            continue
+        part = dict(comp, box=(iy0, ix0, iy1, ix1))
+        _, g = oracle.comp_pixels(spec, part, theta, with_grad=True)
+        for loc, p in enumerate(comp["par"]):
+            if p == par:
+                D[iy0 - (y0 - c):iy1 - (y0 - c), ix0 - (x0 - c):ix1 - (x0 - c)] += g[loc]
+    J = oracle.convolve_valid(D, im["psf"])
+    if im["sky_par"] == par:
+        J += 1.0
+    return J
+
+
+def _problem(apx, spec, models):
+    """Problem plus data/weights.  models[k] is the oracle's noise-free model of image k,
+    or None: then the data is the sky alone with its noise (generator only) -- parity of
+    chi^2, gradients and Jacobians does not depend on what the data contains, and no input
+    of the oracle ever comes from the HIP path."""
+    P = apx.Problem(spec)
+    data, weight = [], []
+    for k, im in enumerate(spec["images"]):
+        mk = models[k] if models[k] is not None else np.full((im["H"], im["W"]), oracle.sky_value(im, spec["theta_true"]))
+        d, w = synth.make_data(mk, spec["noise"][k])
+        data.append(d)
+        weight.append(w)
+    return P, data, weight, P.pixels(data), P.pixels(weight)
+
+
+# ------------------------------------------------------------ blended field 512^2
+@pytest.fixture(scope="module")
+def blend(apx):
+    spec = synth.blend()
+    print("[case] blend512 full size", flush=True)
+    P, data, weight, dd, ww = _problem(apx, spec, [oracle.model_image(spec, spec["theta_true"], 0)])
+    return spec, P, data, weight, dd, ww
+
+
+def test_blend_full_image_render(apx, blend):
+    spec, P, data, weight, dd, ww = blend
+    th = spec["theta_init"]
+    m = P.split(P.render(th))[0].astype(np.float64)
+    mo = oracle.model_image(spec, th, 0)
+    assert np.all(np.abs(m - mo) <= _tol(mo)), float(np.max(np.abs(m - mo) / _tol(mo)))
+
+
+def test_blend_sampled_jacobian_and_normal_equations(apx, blend):
+    spec, P, data, weight, dd, ww = blend
+    th = spec["theta_init"]
+    rng = np.random.default_rng(7)
+    gal = sorted(rng.choice(350, 5, replace=False).tolist())
+    pts = sorted((350 + rng.choice(200, 3, replace=False)).tolist())
+    cols = gal + pts + [550]
+    J = P.jacobian(th).cpu().numpy()
+    Jo = oracle.jacobian_image(spec, th, 0, cols=cols).T          # (len(cols), npix)
+    for row, p in enumerate(cols):
+        sc = np.max(np.abs(Jo[row]))
+        assert np.max(np.abs(J[p] - Jo[row])) <= 3e-5 * sc, p
+    A, g, c2 = P.jtwj(th, dd, ww)
+    A = A.cpu().numpy().reshape(551, 551)
+    g = g.cpu().numpy()
+    r = (data[0].astype(np.float64) - oracle.model_image(spec, th, 0)).ravel()
+    w = weight[0].astype(np.float64).ravel()
+    Ao = Jo @ (w[:, None] * Jo.T)
+    go = Jo @ (w * r)
+    dg = np.sqrt(np.diag(Ao))
+    sub = A[np.ix_(cols, cols)]
+    assert np.all(np.abs(sub - Ao) <= 1e-4 * np.outer(dg, dg))
+    c2o = float(np.sum(w * r * r))
+    assert np.all(np.abs(g[cols] - go) <= 1e-4 * dg * math.sqrt(c2o))
+    assert abs(float(c2.cpu()[0]) - c2o) <= 1e-6 * c2o
+
+
+def test_blend_lm_step_solves_the_damped_system(apx, blend):
+    """One LM iteration on the full 551-parameter system: the step h the device took
+    satisfies (A + lambda D) h = g with the device's own A, g (FP64, host check)."""
+    spec, P, data, weight, dd, ww = blend
+    th0 = spec["theta_init"]
+    A, g, _ = P.jtwj(th0, dd, ww)
+    A = A.cpu().numpy().reshape(551, 551)
+    g = g.cpu().numpy()
+    th, st = P.lm_init(th0, dd, ww)
+    # iterate to the first accepted step: until then theta (hence A, g) is unchanged and
+    # lambda has only been raised by rejections (x UP each)
+    for it in range(10):
+        P.lm_step(dd, ww, th, st)
+        s = P.lm_state(st)[0]
+        if s["accepted"]:
+            break
+    assert s["accepted"] == 1 and s["n_chol_retry"] == 0
+    lam_used = s["lambda"] * oracle.LM_DOWN            # accepted: lambda_new = lambda_used / DOWN
+    assert lam_used == pytest.approx(oracle.LM_LAMBDA0 * oracle.LM_UP ** it, rel=1e-14)
+    D = np.maximum(np.diag(A), oracle.LM_DAMP_FLOOR * np.max(np.diag(A)))
+    h = th.cpu().numpy() - th0
+    res = (A + lam_used * np.diag(D)) @ h - g
+    assert np.linalg.norm(res) <= 1e-8 * np.linalg.norm(g)
+    assert s["pred"] == pytest.approx(float(h @ (lam_used * D * h + g)), rel=1e-9)
+
+
+# ------------------------------------------------------------ gradient field 2048^2
+def test_field_patches_and_sampled_gradient(apx):
+    spec = synth.field()
+    print("[case] field2048 full size", flush=True)
+    P, data, weight, dd, ww = _problem(apx, spec, [None])
+    th = spec["theta_init"]
+    m = P.split(P.render(th))[0].astype(np.float64)
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        y0, x0 = int(rng.integers(0, 2048 - 24)), int(rng.integers(0, 2048 - 24))
+        mo = _local_model(spec, th, 0, y0, x0, 24, 24)
+        mg = m[y0:y0 + 24, x0:x0 + 24]
+        assert np.all(np.abs(mg - mo) <= _tol(mo) + 1e-7 * np.max(np.abs(m))), (y0, x0)
+    grad, _ = P.chi2_grad(th, dd, ww)
+    grad = grad.cpu().numpy()
+    for p in rng.choice(3500, 3, replace=False).tolist():
+        comp = spec["comps"][p // 7]
+        by0, bx0, by1, bx1 = comp["box"]
+        c = 25
+        y0, x0 = max(0, by0 - c), max(0, bx0 - c)
+        y1, x1 = min(2048, by1 + c), min(2048, bx1 + c)
+        Jp = _local_jcol(spec, th, 0, p, y0, x0, y1 - y0, x1 - x0)
+        mo = _local_model(spec, th, 0, y0, x0, y1 - y0, x1 - x0)
+        r = data[0][y0:y1, x0:x1].astype(np.float64) - mo
+        w = weight[0][y0:y1, x0:x1].astype(np.float64)
+        go = -2.0 * float(np.sum(w * r * Jp))
+        scale = 2.0 * float(np.sum(np.abs(w * r * Jp)))
+        assert abs(grad[p] - go) <= 1e-4 * max(abs(go), scale), (p, grad[p], go, scale)
+
+
+# ------------------------------------------------------------ 4096 cutouts
+def test_cutouts_sampled_render_and_early_lm(apx):
+    spec = synth.cutouts()
+    print("[case] cutouts4096 full size", flush=True)
+    rng = np.random.default_rng(5)
+    picks = rng.choice(4096, 6, replace=False).tolist()
+    models = [oracle.model_image(spec, spec["theta_true"], k) if k in picks else None for k in range(4096)]
+    P, data, weight, dd, ww = _problem(apx, spec, models)
+    th0 = spec["theta_init"]
+    m = P.split(P.render(th0))
+    for s in picks:
+        mo = oracle.model_image(spec, th0, s)
+        assert np.all(np.abs(m[s].astype(np.float64) - mo) <= _tol(mo)), s
+    th, st = P.lm_init(th0, dd, ww)
+    P.lm_run(2, dd, ww, th, st, use_graph=True)
+    tg = th.cpu().numpy()
+    stg = P.lm_state(st)
+    small = [s for s in picks if spec["images"][s]["H"] <= 90][:3]
+    for s in small:
+        sub = synth.sub_spec(spec, s)
+        to, hist = oracle.lm_fit(sub, sub["theta_init"], [data[s]], [weight[s]], 2)
+        p0, n = spec["subs"][s]
+        assert stg["n_accept"][s] == sum(r["accepted"] for r in hist[0]), s
+        assert np.all(np.abs(tg[p0:p0 + n] - to) <= 1e-5 * (np.abs(to) + sub["scale"])), s
+
+
+# ------------------------------------------------------------ multiband 6 x 2048^2
+def test_multiband_patches_and_tied_gradient(apx):
+    spec = synth.multiband()
+    print("[case] multiband full size", flush=True)
+    P, data, weight, dd, ww = _problem(apx, spec, [None] * len(spec["images"]))
+    th = spec["theta_init"]
+    m = P.split(P.render(th))
+    g = 17
+    p0 = 9 * g
+    boxes = {k: next(c for c in spec["comps"] if c["par"][0] == p0 and c["image"] == k)["box"]
+             for k in range(len(spec["images"]))}
+    for k, (by0, bx0, by1, bx1) in boxes.items():
+        y0 = min(max(0, (by0 + by1) // 2 - 12), 2048 - 24)
+        x0 = min(max(0, (bx0 + bx1) // 2 - 12), 2048 - 24)
+        mo = _local_model(spec, th, k, y0, x0, 24, 24)
+        mg = m[k][y0:y0 + 24, x0:x0 + 24].astype(np.float64)
+        assert np.all(np.abs(mg - mo) <= _tol(mo) + 1e-7 * np.max(np.abs(m[k]))), k
+    # the shape parameters of galaxy g are tied across the six images and its Ie across
+    # the two epochs of a band: the gradient sums the per-image contributions
+    grad, _ = P.chi2_grad(th, dd, ww)
+    grad = grad.cpu().numpy()
+    for par in (p0, p0 + 4, p0 + 6):
+        go, scale = 0.0, 0.0
+        for k, (by0, bx0, by1, bx1) in boxes.items():
+            c = 20
+            y0, x0 = max(0, by0 - c), max(0, bx0 - c)
+            y1, x1 = min(2048, by1 + c), min(2048, bx1 + c)
+            if y1 <= y0 or x1 <= x0:
+                continue
+            Jp = _local_jcol(spec, th, k, par, y0, x0, y1 - y0, x1 - x0)
+            if not np.any(Jp):
+                continue
+            mo = _local_model(spec, th, k, y0, x0, y1 - y0, x1 - x0)
+            r = data[k][y0:y1, x0:x1].astype(np.float64) - mo
+            w = weight[k][y0:y1, x0:x1].astype(np.float64)
+            go += -2.0 * float(np.sum(w * r * Jp))
+            scale += 2.0 * float(np.sum(np.abs(w * r * Jp)))
+        assert abs(grad[par] - go) <= 1e-4 * max(abs(go), scale), (par, grad[par], go, scale)

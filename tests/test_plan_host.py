@@ -1,0 +1,76 @@
+"""Host-side descriptor validation and planning through the C ABI (no GPU: a host-only
+context plans and sizes problems but never launches)."""
+import copy
+import os
+
+import numpy as np
+import pytest
+
+from paper_2308_01957_amd import synth
+
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2308_01957_amd", "libapx.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libapx.so not built")
+
+
+@pytest.fixture(scope="module")
+def apx():
+    from paper_2308_01957_amd import apx as mod
+    return mod
+
+
+def _small():
+    return synth.blend(seed_id=301, H=40, W=52, n_sersic=2, n_point=3, P=7)
+
+
+def test_plan_sizes_match_the_layout(apx):
+    spec = _small()
+    p = apx.Plan(spec)
+    assert p.n_pix == 40 * 52
+    assert p.n_ext == (40 + 6) * (52 + 6)
+    # Jacobian entries: 14 Sersic columns on the full image + 3 point columns on their
+    # (2+6) x (2+6) output boxes (clipped to the image)
+    npt = 0
+    for c in spec["comps"]:
+        if c["type"] == 1:
+            y0, x0, y1, x1 = c["box"]
+            oh = min(40, y1 + 3) - max(0, y0 - 3)
+            ow = min(52, x1 + 3) - max(0, x0 - 3)
+            npt += oh * ow
+    assert p.n_jac == 14 * 40 * 52 + npt
+    assert p.workspace_bytes > 0
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda s: s["images"][0].__setitem__("psf", np.ones((6, 6), np.float32)), -1),     # even P
+    (lambda s: s["images"][0].__setitem__("psf", np.ones((65, 65), np.float32)), -5),   # P > 63
+    (lambda s: s["comps"][2]["par"].__setitem__(0, 0), -5),                            # free point position
+    (lambda s: s["comps"][0]["par"].__setitem__(2, s["images"][0]["sky_par"]), -1),    # shares the sky index
+    (lambda s: s["comps"][0]["par"].__setitem__(3, 10 ** 6), -1),                      # index out of range
+    (lambda s: s.__setitem__("subs", [(0, 10), (5, 10)]), -1),                          # overlapping ranges
+    (lambda s: s["images"][0].__setitem__("affine", np.array([0, 1.0, 2.0, 0, 0.5, 1.0])), -1),  # singular map
+    (lambda s: s["sampling"].__setitem__("s", 9), -5),                                  # too many nodes
+    (lambda s: s["comps"][0].__setitem__("type", 7), -1),                               # unknown type
+])
+def test_invalid_descriptors(apx, mutate, status):
+    spec = copy.deepcopy(_small())
+    mutate(spec)
+    with pytest.raises(apx.ApxError) as e:
+        apx.Plan(spec)
+    assert e.value.status == status
+
+
+def test_parameter_outside_its_sub_problem_is_rejected(apx):
+    spec = copy.deepcopy(synth.cutouts(seed_id=302, n_cutouts=3, side_range=(20, 30), p_range=(5, 7), max_comp=1))
+    # give cutout 1's galaxy a centre parameter that belongs to cutout 0
+    spec["comps"][1]["par"][0] = 0
+    with pytest.raises(apx.ApxError) as e:
+        apx.Plan(spec)
+    assert e.value.status == -1
+
+
+def test_full_scale_plans(apx):
+    """Every benchmark workload plans on the host (sizes only, no GPU)."""
+    for f in (synth.single, synth.blend, synth.field):
+        p = apx.Plan(f())
+        assert p.n_jac > 0 and p.workspace_bytes > 0
+        p.close()
