@@ -51,30 +51,45 @@ __global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict_
     const int ox0 = jb.out_x0 + it.tx * CV_TW;
     const int iy_base = oy0 - c, ix_base = ox0 - c;
 
-    // ---- stage the input tile (zero outside the input rectangle)
+    // ---- stage the input tile (zero outside the input rectangle); every load of a thread
+    // is issued before its LDS stores so the latencies overlap
+    constexpr int NE = (LH * LW0 + 255) / 256;
+    T v[NE];
     if constexpr (KIND == CONV_ADJ) {
-        for (int e = threadIdx.x; e < LH * LW0; e += 256) {
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int e = threadIdx.x + 256 * q;
             const int ly = e / LW0, lx = e - ly * LW0;
             const int y = iy_base + ly, x = ix_base + lx;
-            float v = 0.f;
-            if (y >= 0 && y < im.H && x >= 0 && x < im.W) {
+            T val = 0;
+            if (e < LH * LW0 && y >= 0 && y < im.H && x >= 0 && x < im.W) {
                 const long long pix = im.pix_off + (long long)y * im.W + x;
-                v = -2.f * io.weight[pix] * p.rbuf[pix];
+                val = -2.f * io.weight[pix] * p.rbuf[pix];
             }
-            tile[ly * LW + lx] = v;
+            v[q] = val;
         }
     } else {
         const T* __restrict__ in;
         if constexpr (sizeof(T) == 8) in = io.in64 + jb.in_off + (long long)it.ch * jb.in_cs;
         else in = io.in + jb.in_off + (long long)it.ch * jb.in_cs;
         const int iy1 = jb.in_y0 + jb.in_h, ix1 = jb.in_x0 + jb.in_w;
-        for (int e = threadIdx.x; e < LH * LW0; e += 256) {
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int e = threadIdx.x + 256 * q;
             const int ly = e / LW0, lx = e - ly * LW0;
             const int y = iy_base + ly, x = ix_base + lx;
-            T v = 0;
-            if (y >= jb.in_y0 && y < iy1 && x >= jb.in_x0 && x < ix1)
-                v = in[(long long)(y - jb.in_y0) * jb.in_w + (x - jb.in_x0)];
-            tile[ly * LW + lx] = v;
+            T val = 0;
+            if (e < LH * LW0 && y >= jb.in_y0 && y < iy1 && x >= jb.in_x0 && x < ix1)
+                val = in[(long long)(y - jb.in_y0) * jb.in_w + (x - jb.in_x0)];
+            v[q] = val;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e < LH * LW0) {
+            const int ly = e / LW0, lx = e - ly * LW0;
+            tile[ly * LW + lx] = v[q];
         }
     }
     __syncthreads();

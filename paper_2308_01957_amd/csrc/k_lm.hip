@@ -191,18 +191,25 @@ __device__ __forceinline__ void trsm_row_regs(double (&x)[CHOL_NB], const double
 }
 
 // Stage the nr x nc block at (r0, c0) of the n x n row-major matrix into LDS with
-// coalesced loads by the whole workgroup (identity-padded to CHOL_NB x CHOL_NB when
-// pad_identity, zero-padded otherwise).  The caller synchronises.
+// coalesced loads by the whole (256-thread) workgroup, identity-padded to CHOL_NB x CHOL_NB
+// when pad_identity, zero-padded otherwise.  All 16 loads of a thread are issued before
+// any LDS store so their latencies overlap.  The caller synchronises.
 __device__ __forceinline__ void stage_block(const double* Mg, int n, int r0, int c0, int nr, int nc,
                                             double (*B)[CHOL_NB + 1], bool pad_identity) {
-    for (int e = threadIdx.x; e < CHOL_NB * CHOL_NB; e += blockDim.x) {
+    constexpr int PER = CHOL_NB * CHOL_NB / 256;
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + 256 * q;
         const int i = e >> 6, j = e & 63;
-        double v = (pad_identity && i == j) ? 1.0 : 0.0;
-        if (i < nr && j < nc) v = Mg[(long long)(r0 + i) * n + c0 + j];
-        B[i][j] = v;
+        v[q] = (i < nr && j < nc) ? Mg[(long long)(r0 + i) * n + c0 + j] : ((pad_identity && i == j) ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        B[e >> 6][e & 63] = v[q];
     }
 }
-
 
 __global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
     // one block: damping diagonal D from the diagonal of A and its maximum
@@ -299,11 +306,8 @@ __device__ void chol_update_block(double* Mg, int n, int ri, int rj, int kc, boo
                                   double (*Li)[CHOL_NB + 1], double (*Lj)[CHOL_NB + 1]) {
     const int ni = min(CHOL_NB, n - ri), nj = min(CHOL_NB, n - rj), nk = min(CHOL_NB, n - kc);
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    for (int e = t; e < CHOL_NB * CHOL_NB; e += 256) {
-        const int r = e >> 6, k = e & 63;
-        Li[r][k] = (r < ni && k < nk) ? Mg[(long long)(ri + r) * n + kc + k] : 0.0;
-        Lj[r][k] = (r < nj && k < nk) ? Mg[(long long)(rj + r) * n + kc + k] : 0.0;
-    }
+    stage_block(Mg, n, ri, kc, ni, nk, Li, false);
+    stage_block(Mg, n, rj, kc, nj, nk, Lj, false);
     __syncthreads();
     const int wr = wv >> 1, wc = wv & 1;
     chol_d4 acc[2][2];
