@@ -283,6 +283,42 @@ OTHER_WORKLOADS = {"cutouts": run_cutouts, "field": run_field, "multiband": run_
                    "single": run_single}
 
 
+def counted_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when there is none or the kernel's sources changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "conv_jcol_blend512_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("|"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel") != kernel or "sources" not in kv:
+        return None
+    h = hashlib.sha256()
+    for src in kv["sources"].split():
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != kv.get("sources_sha256"):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def copy_calibration(args, torch):
+    """Three elementwise copies y = 1 * x of a known size: a profiler's HBM byte counters
+    read on them give the factor between counted and moved bytes."""
+    if args.copy_calibration <= 0:
+        return
+    n = args.copy_calibration * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: 3 x {args.copy_calibration} MiB read + write", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +326,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--render-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also launch three plain copy kernels of MIB MiB (read MIB, write MIB) "
+                         "after the timed region, to calibrate HBM byte counters")
     ap.add_argument("--workload", default="blend",
                     choices=["blend", "cutouts", "field", "multiband", "single"],
                     help="blend (default, the headline line); the others print their own line")
@@ -306,7 +345,9 @@ def main():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         return 1
     if args.workload != "blend":
-        return OTHER_WORKLOADS[args.workload](args, torch, apx, synth)
+        rc = OTHER_WORKLOADS[args.workload](args, torch, apx, synth)
+        copy_calibration(args, torch)
+        return rc
 
     spec = synth.blend()                       # 512x512, 50 Sersic + 200 PS, Moffat 25
     img = spec["images"][0]
@@ -341,11 +382,15 @@ def main():
           f"({int(state['n_accept'])} accepted)", file=sys.stderr, flush=True)
 
     # dominant kernel: Jacobian-column convolutions, one launch per iteration
+    # (the launch also runs in iterations that follow a rejected step, where it finds no new
+    # Jacobian to compute and exits within ~12 us: those few us are kept in the total and the
+    # average is taken over the launches that computed a Jacobian)
     n_jac = prob.n_jac                        # Jacobian entries = output pixels of all columns
     flop_per_phase = 2.0 * P_psf * P_psf * n_jac
     j_phases = 1 + int(state["n_accept"]) - int(state["accepted"])
     jcol_ms, jcol_launches = kt["conv_jcol"]
-    achieved = flop_per_phase * j_phases / (jcol_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
+    avg_ms = jcol_ms / max(1, j_phases)
+    achieved = flop_per_phase / (avg_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
 
     # rendered Mpix/s: objective-path model (FP64 render + convolution) at the truth
     prob.set_timing(False)
@@ -379,11 +424,12 @@ def main():
                    "lm_accepted": int(state["n_accept"]), "jacobian_phases": j_phases},
         "mpix_per_s": mpix,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": counted_traffic(f"k_conv<{P_psf},JCOL>"), "traffic_unit": "bytes/launch",
                      "kernel": f"k_conv<{P_psf},JCOL>",
-                     "avg_launch_ms": jcol_ms / max(1, jcol_launches),
-                     "launches": jcol_launches,
-                     "flop_per_jacobian": flop_per_phase},
+                     "avg_launch_ms": avg_ms, "launches_with_work": j_phases,
+                     "launches_total": jcol_launches,
+                     "flop_per_launch": flop_per_phase},
         "kernel_ms": {k: round(v[0], 4) for k, v in kt.items()},
     }
     if not args.no_cpu_baseline:
@@ -391,6 +437,7 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(spec, [d], [w])
     print(json.dumps(rec), flush=True)
     prob.close()
+    copy_calibration(args, torch)
     return 0
 
 
