@@ -74,6 +74,7 @@ struct apx_problem {
     std::vector<int> a_sub, a_row, a_col;
     std::vector<int> par_sub, par_off, par_cols, par_sky_off, par_sky;
     std::vector<int> small_subs, large_subs;
+    int n_sflag = 0;                              // substitution hand-off flags
     std::vector<int> theta_subs;                  // sub of each theta-assembly segment
     int nmax_small = 0;
     std::vector<float> node_o, node_w;
@@ -304,6 +305,8 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         sb.n = n;
         sb.a_off = aoff;
         sb.large = n > SMALL_N ? 1 : 0;
+        sb.flag_off = P->n_sflag;
+        if (sb.large) P->n_sflag += 2 * ((n + CHOL_NB - 1) / CHOL_NB);
         aoff += (long long)n * n;
         P->subs[s] = sb;
         if (sb.large) P->large_subs.push_back(s);
@@ -848,6 +851,7 @@ static void layout(apx_problem* P) {
     ws_take<double>(P, "yvec", P->n_par);
     ws_take<double>(P, "theta_trial", P->n_par);
     ws_take<LMFlags>(P, "lmf", P->n_sub);
+    ws_take<int>(P, "sflag", std::max(1, P->n_sflag));
     ws_take<int>(P, "sticky", 1);
     ws_take<double>(P, "sky_val", P->n_images);
     ws_take<double>(P, "chi2_sub", P->n_sub);
@@ -1059,6 +1063,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.yvec = wsp<double>(P, "yvec");
     p.theta_trial = wsp<double>(P, "theta_trial");
     p.lmf = wsp<LMFlags>(P, "lmf");
+    p.sflag = wsp<int>(P, "sflag");
     p.sticky = wsp<int>(P, "sticky");
     p.sky_val = wsp<double>(P, "sky_val");
     p.par_sub = wsp<int>(P, "par_sub");
@@ -1079,6 +1084,8 @@ apx_status apx_problem_check(apx_problem* P) {
     HIPCHK(hipStreamSynchronize(P->ctx->stream));
     HIPCHK(hipMemcpy(&flags, P->plan.sticky, sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemset(P->plan.sticky, 0, sizeof(int)));
+    if (flags & FLAG_STALL)
+        return fail(P->ctx, APX_E_HIP, "a substitution hand-off wait ran out (the step was dropped)");
     if (flags & FLAG_DOMAIN) return APX_E_DOMAIN;
     if (flags & FLAG_NONFINITE) return APX_E_NONFINITE;
     return APX_OK;

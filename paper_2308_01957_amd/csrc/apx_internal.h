@@ -17,6 +17,17 @@ constexpr int PAIR_KC = 32;                   // pixels per LDS stage of the J^T
 constexpr int CHOL_NB = 64;                   // block size of the blocked Cholesky
 constexpr int SMALL_N = 64;                   // sub-problems up to this size: one-wave solver
 constexpr int MAX_NODES_1D = 8;
+constexpr int N_XCD = 8;                       // accelerator dies, each with its own L2
+
+// Workgroups of a launch are dealt to the XCDs round-robin (block b to XCD b % 8).
+// Block b takes logical item xcd_item(b, n): every XCD then owns a contiguous range of
+// items, so items that run at the same time on one XCD (neighbouring convolution tiles,
+// the tile pairs of one pixel slice) share their global reads in that XCD's L2.  The map
+// is a bijection on [0, n) for every n.
+__device__ __forceinline__ int xcd_item(int b, int n) {
+    const int x = b % N_XCD, q = n / N_XCD, r = n % N_XCD;
+    return x * q + (x < r ? x : r) + b / N_XCD;
+}
 // b_n table: cubic Hermite nodes (b, db/dn) on [BN_N0, BN_N0 + (BN_COUNT-1)/BN_INV_H]
 constexpr double BN_N0 = 0.35;
 constexpr double BN_INV_H = 256.0;
@@ -92,7 +103,7 @@ struct DPair {
 };
 struct PairItem { int pair, ta, tb, r0, r1, pad; long long out_off; };
 
-struct DSub { int p0, n; long long a_off; int large, pad; };
+struct DSub { int p0, n; long long a_off; int large, flag_off; };   // flag_off: 2 x blocks of sflag
 
 // Per-sub-problem LM scratch flags
 struct LMFlags {
@@ -100,6 +111,7 @@ struct LMFlags {
     int chol_fail;            // current attempt failed
     int trial_bad;            // trial parameters outside the domain
     int skip;                 // 1: sub-problem skips the current render/phase
+    int subst_fail;           // a substitution hand-off wait ran out this iteration
 };
 
 // Launch-time views of the workspace ----------------------------------------------
@@ -148,6 +160,7 @@ struct Plan {
     double* yvec;             // substitution right-hand side [n_par]
     double* theta_trial;      // [n_par]
     LMFlags* lmf;             // [n_sub]
+    int* sflag;               // substitution hand-off flags (per large sub: forward, backward blocks)
     int* sticky;              // device error flags
     double* sky_val;          // [n_images] sky of each image at the current theta
     const int* par_sub;       // [n_par] sub-problem of each theta index (-1: none)
@@ -157,7 +170,7 @@ struct Plan {
 };
 
 // Sticky flag bits
-constexpr int FLAG_DOMAIN = 1, FLAG_NONFINITE = 2;
+constexpr int FLAG_DOMAIN = 1, FLAG_NONFINITE = 2, FLAG_STALL = 4;
 
 // Launchers (each returns hipGetLastError()) ----------------------------------------
 // k_model.hip

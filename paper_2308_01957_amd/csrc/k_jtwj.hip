@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     constexpr int PER = TM * KC / 256;              // elements of A (and of B) per thread
     __shared__ double As[TM][KC + 1];
     __shared__ double Bs[TM][KC + 1];
-    const PairItem it = items[blockIdx.x];
+    const PairItem it = items[xcd_item((int)blockIdx.x, (int)gridDim.x)];
     const DPair pr = pairs[it.pair];
     if (lm && lm[pr.sub].need_jac == 0) return;
     const DGroup& G = p.groups[pr.g];

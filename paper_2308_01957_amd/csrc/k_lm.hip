@@ -160,34 +160,60 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // arrive as identity rows.  Per column j: the pivot comes from lane j, every lane scales
 // its a[j], the scaled column goes through LDS (col) and every later entry of every row is
 // updated with broadcast reads -- no lane masks, fully unrolled, wave-synchronous.
+// The reciprocals of the diagonal of the factor go to invd[CHOL_NB] (LDS).
 // Returns false in every lane on a non-positive or non-finite pivot.
-__device__ __forceinline__ bool chol64_regs(double (&a)[CHOL_NB], int lane, double* col) {
+__device__ __forceinline__ bool chol64_regs(double (&a)[CHOL_NB], int lane, double* col, double* invd) {
 #pragma unroll
     for (int j = 0; j < CHOL_NB; ++j) {
         const double piv = lane_bcast(a[j], j);
         if (!(piv > 0.0) || !isfinite(piv)) return false;
         const double ljj = sqrt(piv);
-        const double lij = lane > j ? a[j] / ljj : 0.0;
+        const double rj = 1.0 / ljj;
+        if (lane == 0) invd[j] = rj;
+        const double lij = lane > j ? a[j] * rj : 0.0;
         a[j] = lane > j ? lij : (lane == j ? ljj : a[j]);
         col[lane] = lij;
         __builtin_amdgcn_wave_barrier();
+        // all broadcast reads of the column first, so they are in flight together
+        double cv[CHOL_NB];
 #pragma unroll
-        for (int q = j + 1; q < CHOL_NB; ++q) a[q] = fma(-lij, col[q], a[q]);
+        for (int q = j + 1; q < CHOL_NB; ++q) cv[q] = col[q];
+#pragma unroll
+        for (int q = j + 1; q < CHOL_NB; ++q) a[q] = fma(-lij, cv[q], a[q]);
         __builtin_amdgcn_wave_barrier();
     }
     return true;
 }
 
-// x L^T = m for one row per lane (x in registers), L in LDS: right-looking, so the
-// updates of one column are independent FMAs.  Identity padding beyond nb is harmless.
-__device__ __forceinline__ void trsm_row_regs(double (&x)[CHOL_NB], const double (*L)[CHOL_NB + 1], int nb) {
-    (void)nb;
+// x L^T = m for one row per lane (x in registers), with the factor transposed in LDS
+// (Lt[j][q] = L[q][j], so column j of L is a contiguous row) and the reciprocals of its
+// diagonal in invd: right-looking, so the updates of one column are independent FMAs.
+// Identity padding beyond the block size is harmless.
+__device__ __forceinline__ void trsm_row_regs(double (&x)[CHOL_NB], const double (*Lt)[CHOL_NB + 1],
+                                              const double* invd) {
 #pragma unroll
     for (int j = 0; j < CHOL_NB; ++j) {
-        x[j] = x[j] / L[j][j];
+        x[j] = x[j] * invd[j];
+        double cv[CHOL_NB];
 #pragma unroll
-        for (int q = j + 1; q < CHOL_NB; ++q) x[q] = fma(-x[j], L[q][j], x[q]);
+        for (int q = j + 1; q < CHOL_NB; ++q) cv[q] = Lt[j][q];
+#pragma unroll
+        for (int q = j + 1; q < CHOL_NB; ++q) x[q] = fma(-x[j], cv[q], x[q]);
     }
+}
+
+// Wave 0 factors the staged diagonal block B (read as rows) and writes the factor back
+// into B transposed (B[q][i] = L[i][q]).  Returns false on a failed pivot.
+__device__ __forceinline__ bool factor_diag_block(double (*B)[CHOL_NB + 1], int lane, double* col,
+                                                  double* invd) {
+    double a[CHOL_NB];
+#pragma unroll
+    for (int q = 0; q < CHOL_NB; ++q) a[q] = B[lane][q];
+    __builtin_amdgcn_wave_barrier();
+    const bool ok = chol64_regs(a, lane, col, invd);
+#pragma unroll
+    for (int q = 0; q < CHOL_NB; ++q) B[q][lane] = a[q];
+    return ok;
 }
 
 // Stage the nr x nc block at (r0, c0) of the n x n row-major matrix into LDS with
@@ -225,7 +251,12 @@ __global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
     const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     for (int i = threadIdx.x; i < n; i += blockDim.x)
         p.Ddiag[sb.p0 + i] = fmax(A[(long long)i * n + i], APX_LM_DAMP_FLOOR * dmax);
-    if (threadIdx.x == 0) p.lmf[s].chol_fail = 0;
+    const int nflag = 2 * ((n + CHOL_NB - 1) / CHOL_NB);
+    for (int i = threadIdx.x; i < nflag; i += blockDim.x) p.sflag[sb.flag_off + i] = 0;
+    if (threadIdx.x == 0) {
+        p.lmf[s].chol_fail = 0;
+        p.lmf[s].subst_fail = 0;
+    }
 }
 
 __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
@@ -245,10 +276,11 @@ __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
 // Block column k: every workgroup factors the diagonal block in wave 0's registers
 // (redundantly); workgroup 0 stores it and reports a failed pivot, workgroup b > 0
 // solves row block k+b (X L_kk^T = M_rk, one row per lane of wave 0).
-__global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_chol_panel(Plan p, int s, int kblk) {
     __shared__ double L[CHOL_NB][CHOL_NB + 1];
     __shared__ double X[CHOL_NB][CHOL_NB + 1];
-    __shared__ double col[CHOL_NB];
+    __shared__ double col[CHOL_NB], invd[CHOL_NB];
     __shared__ int bad;
     if (p.lmf[s].chol_fail) return;
     const DSub sb = p.subs[s];
@@ -263,13 +295,8 @@ __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
     if (nr > 0) stage_block(Mg, n, rb, kb, nr, nb, X, false);
     __syncthreads();
     if (t < 64) {
-        double a[CHOL_NB];
-#pragma unroll
-        for (int q = 0; q < CHOL_NB; ++q) a[q] = L[lane][q];
-        const bool ok = chol64_regs(a, lane, col);
+        const bool ok = factor_diag_block(L, lane, col, invd);     // L now holds L^T
         if (lane == 0) bad = ok ? 0 : 1;
-#pragma unroll
-        for (int q = 0; q < CHOL_NB; ++q) L[lane][q] = a[q];
     }
     __syncthreads();
     if (bad) {
@@ -279,7 +306,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
     if (blockIdx.x == 0) {
         for (int e = t; e < nb * nb; e += 256) {
             const int i = e / nb, j = e - (e / nb) * nb;
-            if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[i][j];
+            if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[j][i];
         }
         return;
     }
@@ -287,7 +314,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
         double x[CHOL_NB];
 #pragma unroll
         for (int q = 0; q < CHOL_NB; ++q) x[q] = X[lane][q];
-        trsm_row_regs(x, L, nb);
+        trsm_row_regs(x, L, invd);
 #pragma unroll
         for (int q = 0; q < CHOL_NB; ++q) X[lane][q] = x[q];
     }
@@ -356,11 +383,12 @@ __global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, in
 
 // Retries: if the first attempt failed, raise lambda and refactor with this single
 // workgroup (up to APX_LM_ATTEMPTS - 1 more times).  Otherwise mark success and exit.
-__global__ __launch_bounds__(256) void k_chol_retry(Plan p, int s, apx_lm_state* lm) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_chol_retry(Plan p, int s, apx_lm_state* lm) {
     __shared__ double L[CHOL_NB][CHOL_NB + 1];
     __shared__ double X[CHOL_NB][CHOL_NB + 1];
     __shared__ double Li[CHOL_NB][CHOL_NB + 1], Lj[CHOL_NB][CHOL_NB + 1];
-    __shared__ double col[CHOL_NB];
+    __shared__ double col[CHOL_NB], invd[CHOL_NB];
     __shared__ int bad;
     const int t = threadIdx.x, lane = t & 63;
     if (!p.lmf[s].chol_fail) {
@@ -387,19 +415,14 @@ __global__ __launch_bounds__(256) void k_chol_retry(Plan p, int s, apx_lm_state*
             stage_block(Mg, n, kb, kb, nb, nb, L, true);
             __syncthreads();
             if (t < 64) {
-                double a[CHOL_NB];
-#pragma unroll
-                for (int q = 0; q < CHOL_NB; ++q) a[q] = L[lane][q];
-                const bool okw = chol64_regs(a, lane, col);
+                const bool okw = factor_diag_block(L, lane, col, invd);   // L now holds L^T
                 if (lane == 0) bad = okw ? 0 : 1;
-#pragma unroll
-                for (int q = 0; q < CHOL_NB; ++q) L[lane][q] = a[q];
             }
             __syncthreads();
             if (bad) { ok = false; break; }
             for (int e = t; e < nb * nb; e += 256) {
                 const int i = e / nb, j = e - (e / nb) * nb;
-                if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[i][j];
+                if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[j][i];
             }
             for (int r = k + 1; r < nblk; ++r) {
                 const int rb = r * CHOL_NB, nr = min(CHOL_NB, n - rb);
@@ -409,7 +432,7 @@ __global__ __launch_bounds__(256) void k_chol_retry(Plan p, int s, apx_lm_state*
                     double x[CHOL_NB];
 #pragma unroll
                     for (int q = 0; q < CHOL_NB; ++q) x[q] = X[lane][q];
-                    trsm_row_regs(x, L, nb);
+                    trsm_row_regs(x, L, invd);
 #pragma unroll
                     for (int q = 0; q < CHOL_NB; ++q) X[lane][q] = x[q];
                 }
@@ -435,105 +458,151 @@ __global__ __launch_bounds__(256) void k_chol_retry(Plan p, int s, apx_lm_state*
     }
 }
 
-// Forward and back substitution, one launch per CHOL_NB block.  Every workgroup of a
-// launch solves the diagonal block in wave 0's registers (readlane broadcasts); workgroup 0
-// stores that part of the solution, the others update their own 64-entry slice of the
-// right-hand side with the block's contiguous rows (forward) or columns (backward).
-// The right-hand side lives in Ddiag's companion vector yvec.
-__global__ __launch_bounds__(256) void k_subst_fwd(Plan p, int s, int b) {
+// Forward and back substitution L y = g, L^T h = y, one workgroup per CHOL_NB block in
+// one launch per direction.  Block b needs the solved blocks before it (forward) or after
+// it (backward); workgroups are numbered so that those belong to workgroups with lower
+// indices, which the hardware dispatches first, so a workgroup only ever waits on
+// workgroups that are already running or done.  A finished block is published through a
+// flag (release at device scope); a consumer prefetches the matrix block it needs, then
+// waits for the flag (acquire) and folds in that block's contribution, in a fixed order.
+// The waits are bounded: one that runs out raises FLAG_STALL and marks the iteration's
+// step as failed instead of hanging.  y and then h overwrite yvec.
+constexpr int SUBST_SPIN_MAX = 1 << 22;
+
+__device__ void subst_wait(Plan& p, int s, const int* f) {
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            if (++spins > SUBST_SPIN_MAX) {
+                atomicOr(p.sticky, FLAG_STALL);
+                p.lmf[s].subst_fail = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// wave 0: make this wave's stores visible at device scope, then raise the flag
+__device__ __forceinline__ void subst_publish(int* f, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) void k_subst_fwd(Plan p, int s) {
     __shared__ double Lb[CHOL_NB][CHOL_NB + 1];
-    __shared__ double ysh[CHOL_NB];
-    __shared__ double part[4][CHOL_NB];
+    __shared__ double rhs[CHOL_NB];
     if (!p.lmf[s].chol_done) return;
     const DSub sb = p.subs[s];
-    const int n = sb.n;
+    const int n = sb.n, b = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
+    const int r0 = b * CHOL_NB, nr = min(CHOL_NB, n - r0);
     const double* L = p.M + sb.a_off;
     double* y = p.yvec + sb.p0;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int r0 = b * CHOL_NB, nr = min(CHOL_NB, n - r0);
+    int* f = p.sflag + sb.flag_off;
     stage_block(L, n, r0, r0, nr, nr, Lb, true);
-    __syncthreads();
-    if (wv == 0) {
-        double a[CHOL_NB];
+    // thread: row il of the block, 16-column quarter kq of every earlier block
+    const int il = t >> 2, kq = t & 3;
+    const double* Lrow = L + (long long)(r0 + min(il, nr - 1)) * n + 16 * kq;
+    double lv[16], ln[16], acc = 0.0;
+    if (b > 0) {
 #pragma unroll
-        for (int q = 0; q < CHOL_NB; ++q) a[q] = Lb[lane][q];
-        double yi = lane < nr ? (b == 0 ? p.gvec[sb.p0 + r0 + lane] : y[r0 + lane]) : 0.0;
+        for (int q = 0; q < 16; ++q) lv[q] = Lrow[q];
+    }
+    for (int c = 0; c < b; ++c) {
+        if (c + 1 < b) {
 #pragma unroll
-        for (int j = 0; j < CHOL_NB; ++j) {
-            const double yj = lane_bcast(yi, j) / lane_bcast(a[j], j);
-            if (lane == j) yi = yj;
-            else if (lane > j) yi = fma(-a[j], yj, yi);
+            for (int q = 0; q < 16; ++q) ln[q] = Lrow[CHOL_NB * (c + 1) + q];
         }
-        ysh[lane] = lane < nr ? yi : 0.0;
-    }
-    __syncthreads();
-    if (blockIdx.x == 0) {
-        if (t < nr) y[r0 + t] = ysh[t];
-        return;
-    }
-    const int rb = r0 + blockIdx.x * CHOL_NB;       // row block updated by this workgroup
-    if (rb >= n) return;
-    const int i = rb + (t >> 2), kq = t & 3;
-    double acc = 0.0;
-    if (i < n) {
-        const double* Li = L + (long long)i * n + r0;
-        for (int k = kq * 16; k < min(nr, kq * 16 + 16); ++k) acc = fma(Li[k], ysh[k], acc);
+        subst_wait(p, s, f + c);
+        const double* yc = y + CHOL_NB * c + 16 * kq;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc = fma(lv[q], yc[q], acc);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) lv[q] = ln[q];
     }
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
-    // the first launch starts every later entry from g (each workgroup owns its rows)
-    if (kq == 0 && i < n) y[i] = (b == 0 ? p.gvec[sb.p0 + i] : y[i]) - acc;
+    if (kq == 0 && il < nr) rhs[il] = p.gvec[sb.p0 + r0 + il] - acc;
+    __syncthreads();
+    if (t < 64) {
+        double a[CHOL_NB];
+#pragma unroll
+        for (int q = 0; q < CHOL_NB; ++q) a[q] = Lb[lane][q];
+        const double rd = 1.0 / Lb[lane][lane];
+        double yi = lane < nr ? rhs[lane] : 0.0;
+#pragma unroll
+        for (int j = 0; j < CHOL_NB; ++j) {
+            const double yj = lane_bcast(yi, j) * lane_bcast(rd, j);
+            if (lane == j) yi = yj;
+            else if (lane > j) yi = fma(-a[j], yj, yi);
+        }
+        if (lane < nr) y[r0 + lane] = yi;
+        subst_publish(f + b, lane);
+    }
 }
 
-__global__ __launch_bounds__(256) void k_subst_bwd(Plan p, int s, int b) {
+__global__ __launch_bounds__(256) void k_subst_bwd(Plan p, int s) {
     __shared__ double Lb[CHOL_NB][CHOL_NB + 1];
-    __shared__ double hsh[CHOL_NB];
     __shared__ double part[4][CHOL_NB];
     if (!p.lmf[s].chol_done) return;
     const DSub sb = p.subs[s];
-    const int n = sb.n;
-    const double* L = p.M + sb.a_off;
-    double* y = p.yvec + sb.p0;
+    const int n = sb.n, nblk = (n + CHOL_NB - 1) / CHOL_NB;
+    const int b = nblk - 1 - (int)blockIdx.x;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int r0 = b * CHOL_NB, nr = min(CHOL_NB, n - r0);
+    const double* L = p.M + sb.a_off;
+    double* y = p.yvec + sb.p0;
+    int* f = p.sflag + sb.flag_off + nblk;
     stage_block(L, n, r0, r0, nr, nr, Lb, true);
-    __syncthreads();
-    if (wv == 0) {
-        double c[CHOL_NB];                           // column lane of the block: c[j] = L[r0+j][r0+lane]
+    // thread: column lane of this block, rows 16 wv .. 16 wv + 15 of every later block
+    const int col = r0 + min(lane, nr - 1);
+    auto load = [&](double (&v)[16], int c) {
+        const int rc = CHOL_NB * c + 16 * wv;
 #pragma unroll
-        for (int q = 0; q < CHOL_NB; ++q) c[q] = Lb[q][lane];
-        double yi = lane < nr ? y[r0 + lane] : 0.0;
+        for (int q = 0; q < 16; ++q) v[q] = rc + q < n ? L[(long long)(rc + q) * n + col] : 0.0;
+    };
+    double lv[16], ln[16], acc = 0.0;
+    if (b + 1 < nblk) load(lv, nblk - 1);
+    for (int c = nblk - 1; c > b; --c) {
+        if (c - 1 > b) load(ln, c - 1);
+        subst_wait(p, s, f + c);
+        const int rc = CHOL_NB * c + 16 * wv;
 #pragma unroll
-        for (int j = CHOL_NB - 1; j >= 0; --j) {
-            const double hj = lane_bcast(yi, j) / lane_bcast(c[j], j);
-            if (lane == j) yi = hj;
-            else if (lane < j) yi = fma(-c[j], hj, yi);
-        }
-        hsh[lane] = lane < nr ? yi : 0.0;
+        for (int q = 0; q < 16; ++q)
+            if (rc + q < n) acc = fma(lv[q], y[rc + q], acc);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) lv[q] = ln[q];
     }
-    __syncthreads();
-    if (blockIdx.x == 0) {
-        if (t < nr) y[r0 + t] = hsh[t];
-        return;
-    }
-    const int cb = (blockIdx.x - 1) * CHOL_NB;      // column block updated by this workgroup
-    if (cb >= r0) return;
-    const int i = cb + lane;
-    double acc = 0.0;
-    if (i < r0)
-        for (int k = wv; k < nr; k += 4) acc = fma(L[(long long)(r0 + k) * n + i], hsh[k], acc);
     part[wv][lane] = acc;
     __syncthreads();
-    if (wv == 0 && i < r0) y[i] -= ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    if (t < 64) {
+        double c_[CHOL_NB];                         // c_[j] = L[r0 + j][r0 + lane]
+#pragma unroll
+        for (int q = 0; q < CHOL_NB; ++q) c_[q] = Lb[q][lane];
+        const double rd = 1.0 / Lb[lane][lane];
+        const double sum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        double yi = lane < nr ? y[r0 + lane] - sum : 0.0;
+#pragma unroll
+        for (int j = CHOL_NB - 1; j >= 0; --j) {
+            const double hj = lane_bcast(yi, j) * lane_bcast(rd, j);
+            if (lane == j) yi = hj;
+            else if (lane < j) yi = fma(-c_[j], hj, yi);
+        }
+        if (lane < nr) y[r0 + lane] = yi;
+        subst_publish(f + b, lane);
+    }
 }
 
-// h = y, pred = h^T (lambda D h + g); zeros when the factorisation failed.
+// h = y, pred = h^T (lambda D h + g); zeros when the factorisation or a hand-off failed.
 __global__ __launch_bounds__(256) void k_subst_finish(Plan p, int s, apx_lm_state* lm) {
     __shared__ double red[4];
     const DSub sb = p.subs[s];
     const int n = sb.n;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const bool done = p.lmf[s].chol_done != 0;
+    const bool done = p.lmf[s].chol_done != 0 && p.lmf[s].subst_fail == 0;
     const double lam = lm[s].lambda;
     double v = 0.0;
     for (int i = t; i < n; i += 256) {
@@ -544,7 +613,10 @@ __global__ __launch_bounds__(256) void k_subst_finish(Plan p, int s, apx_lm_stat
     v = lm_wave_sum(v);
     if (lane == 0) red[wv] = v;
     __syncthreads();
-    if (t == 0) lm[s].pred = done ? ((red[0] + red[1]) + red[2]) + red[3] : 0.0;
+    if (t == 0) {
+        lm[s].pred = done ? ((red[0] + red[1]) + red[2]) + red[3] : 0.0;
+        if (!done) p.lmf[s].chol_done = 0;
+    }
 }
 
 hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipStream_t st) {
@@ -560,10 +632,8 @@ hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipS
         if (T > 0) hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk);
     }
     hipLaunchKernelGGL(k_chol_retry, dim3(1), dim3(256), 0, st, p, s, lm);
-    for (int b = 0; b < nblk; ++b)
-        hipLaunchKernelGGL(k_subst_fwd, dim3(nblk - b), dim3(256), 0, st, p, s, b);
-    for (int b = nblk - 1; b >= 0; --b)
-        hipLaunchKernelGGL(k_subst_bwd, dim3(b + 1), dim3(256), 0, st, p, s, b);
+    hipLaunchKernelGGL(k_subst_fwd, dim3(nblk), dim3(256), 0, st, p, s);
+    hipLaunchKernelGGL(k_subst_bwd, dim3(nblk), dim3(256), 0, st, p, s);
     hipLaunchKernelGGL(k_subst_finish, dim3(1), dim3(256), 0, st, p, s, lm);
     return hipGetLastError();
 }
