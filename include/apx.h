@@ -237,6 +237,16 @@ apx_status apx_jtwj(apx_problem* p, const double* theta, const float* data,
 apx_status apx_chi2_grad(apx_problem* p, const double* theta, const float* data,
                          const float* weight, double* grad, double* chi2);
 
+/* Vector-Jacobian product of the render (the reverse pass of the model of §2.3, the
+ * same adjoint as apx_chi2_grad with the caller's seed in place of -2 w r):
+ * grad_theta[k] = sum_i grad_model[i] * d model_i / d theta_k, i over every output pixel
+ * of every image in apx_render's order.  grad_model: device FP32 [n_pix], read only;
+ * grad_theta: device FP64 [n_par], overwritten.  Entries of theta that no component or
+ * sky uses get 0.  Out-of-domain theta raises the sticky APX_E_DOMAIN flag as in
+ * apx_render.  Asynchronous on the context stream. */
+apx_status apx_render_vjp(apx_problem* p, const double* theta, const float* grad_model,
+                          double* grad_theta);
+
 /* Initialise the LM state of every sub-problem at theta (lambda = LM_LAMBDA0,
  * chi2 and residual at theta). */
 apx_status apx_lm_init(apx_problem* p, const double* theta, const float* data,

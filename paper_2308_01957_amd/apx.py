@@ -27,7 +27,7 @@ EXPORTS = [
     "apx_version", "apx_status_string", "apx_ctx_create", "apx_ctx_set_stream", "apx_ctx_destroy",
     "apx_last_error", "apx_problem_create", "apx_problem_workspace_bytes",
     "apx_problem_bind_workspace", "apx_problem_sizes", "apx_problem_check", "apx_problem_destroy",
-    "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_lm_init",
+    "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_render_vjp", "apx_lm_init",
     "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
 ]
 TIME_CLASSES = ["prep", "render", "conv_fwd", "deriv", "conv_jcol", "pairs", "reduce", "solve",
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "apx_jacobian": ([vp, vp, vp, i64], i32),
         "apx_jtwj": ([vp, vp, vp, vp, vp, vp, vp], i32),
         "apx_chi2_grad": ([vp, vp, vp, vp, vp, vp], i32),
+        "apx_render_vjp": ([vp, vp, vp, vp], i32),
         "apx_lm_init": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_step": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_run": ([vp, i32, vp, vp, vp, vp, i32], i32),
@@ -288,6 +289,21 @@ class Problem:
         n = self.spec["subs"][s][1]
         return A[int(self.a_offsets[s]):int(self.a_offsets[s + 1])].reshape(n, n)
 
+    def render_vjp(self, theta, grad_model, out=None):
+        """sum_i grad_model[i] d model_i / d theta (FP64 [n_par]) by the adjoint pass."""
+        th = self._dev(theta, self.torch.float64)
+        gm = self._dev(grad_model, self.torch.float32)
+        if gm.numel() != self.n_pix:
+            raise ValueError(f"grad_model has {gm.numel()} entries, the render has {self.n_pix} pixels")
+        self._enter(th, gm)
+        t = self.torch
+        with t.cuda.stream(self.stream):
+            if out is None:
+                out = t.empty(self.n_par, dtype=t.float64, device=self.device)
+            self._check(self.lib.apx_render_vjp(self._prob, th.data_ptr(), gm.data_ptr(), out.data_ptr()))
+        self._leave()
+        return out
+
     def chi2_grad(self, theta, data, weight):
         th = self._dev(theta, self.torch.float64)
         self._enter(th, data, weight)
@@ -436,6 +452,39 @@ def _chi2_fn():
 
 
 _CHI2_FN = []
+
+
+def _render_fn():
+    import torch
+
+    class RenderFn(torch.autograd.Function):
+        """Model pixels [n_pix] (FP32) as a differentiable function of theta.
+
+        forward: apx_render.  backward: apx_render_vjp (the adjoint pass)."""
+
+        @staticmethod
+        def forward(ctx, theta, problem):
+            ctx.problem = problem
+            ctx.save_for_backward(theta.detach())
+            return problem.render(theta.detach()).clone()
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (theta,) = ctx.saved_tensors
+            g = ctx.problem.render_vjp(theta, grad_out.detach().to(torch.float32).contiguous())
+            return g.to(theta.dtype), None
+
+    return RenderFn
+
+
+_RENDER_FN = []
+
+
+def render_autograd(theta, problem: "Problem"):
+    """Differentiable model pixels [n_pix] of theta (backward = the library's adjoint)."""
+    if not _RENDER_FN:
+        _RENDER_FN.append(_render_fn())
+    return _RENDER_FN[0].apply(theta, problem)
 
 
 def chi2_autograd(theta, problem: "Problem", data, weight):

@@ -854,6 +854,7 @@ static void layout(apx_problem* P) {
     ws_take<int>(P, "sflag", std::max(1, P->n_sflag));
     ws_take<int>(P, "sticky", 1);
     ws_take<double>(P, "sky_val", P->n_images);
+    ws_take<double>(P, "seed_part", 64LL * P->n_images);
     ws_take<double>(P, "chi2_sub", P->n_sub);
     ws_take<double>(P, "chi2_trial", P->n_sub);
     (void)n_cols;
@@ -1367,6 +1368,42 @@ apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data,
     g.out = grad;
     HIPCHK(launch_segsum(g, st));
     HIPCHK(launch_chi2_check(chi2, P->n_sub, p.sticky, st));
+    return APX_OK;
+}
+
+apx_status apx_render_vjp(apx_problem* P, const double* theta, const float* grad_model, double* grad_theta) {
+    APXCHK(ready(P));
+    if (!theta || !grad_model || !grad_theta) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    {
+        TimeScope ts(P, APX_TIME_PREP);
+        HIPCHK(launch_prep(p, theta, 0, st));
+    }
+    HIPCHK(launch_flip_psf(p, st));
+    ConvIO io{};
+    io.out = p.Abar;
+    io.seed = grad_model;
+    APXCHK(run_conv(P, CONV_ADJ, io));
+    {
+        TimeScope ts(P, APX_TIME_GRAD);
+        HIPCHK(launch_grad_tiles(p, st));
+        HIPCHK(launch_seed_sums(p, grad_model, wsp<double>(P, "seed_part"), st));
+    }
+    SegSum a = segsum_base();
+    a.src = p.grad_part;
+    a.seg = wsp<int>(P, "gcol_seg");
+    a.n_seg = (int)P->cols.size();
+    a.out = p.grad_col;
+    HIPCHK(launch_segsum(a, st));
+    SegSum g = segsum_base();
+    g.src = P->asrc;
+    g.seg = wsp<int>(P, "gr_seg");
+    g.idx = wsp<int>(P, "gr_idx");
+    g.wts = wsp<double>(P, "gr_w");
+    g.n_seg = P->n_par;
+    g.out = grad_theta;
+    HIPCHK(launch_segsum(g, st));
     return APX_OK;
 }
 

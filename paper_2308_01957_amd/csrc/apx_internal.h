@@ -181,6 +181,9 @@ hipError_t launch_render64(const Plan& p, int skip_mode, const apx_lm_state* lm,
 hipError_t launch_deriv(const Plan& p, const apx_lm_state* lm, hipStream_t st);
 hipError_t launch_grad_tiles(const Plan& p, hipStream_t st);
 hipError_t launch_flip_psf(const Plan& p, hipStream_t st);
+// per image: img_sum[3 k + 1] = -sum(seed) / 2, so that the image-sum terms of the gradient
+// assembly (weight -2) give the seed's sum (the sky column of a vector-Jacobian product)
+hipError_t launch_seed_sums(const Plan& p, const float* seed, double* part, hipStream_t st);
 
 // k_conv_*.hip
 enum ConvKind { CONV_FWD = 0, CONV_JCOL = 1, CONV_ADJ = 2 };
@@ -195,6 +198,7 @@ struct ConvIO {
     float* out;               // output buffer base (FWD: optional model)
     const float* data;        // FWD: data (null = no residual / partials)
     const float* weight;      // FWD, JCOL (null = no partials), ADJ
+    const float* seed;        // ADJ: the seed itself (vector-Jacobian product) instead of -2 w r
     double* part;             // per-item partials
     int skip_mode;            // as launch_render_mode
     const apx_lm_state* lm;

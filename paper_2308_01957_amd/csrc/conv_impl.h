@@ -13,7 +13,8 @@
 //   CONV_FWD  model + sky, optional model store, FP32 residual store, FP64 partials of
 //             sum w r^2, sum w r, sum w (chi^2 of Eq. chi2, sky gradient, sky-sky entry);
 //   CONV_JCOL Jacobian column store, FP64 partials of sum w r J, sum w J;
-//   CONV_ADJ  input is -2 w r staged from the residual (the adjoint seed), PSF flipped,
+//   CONV_ADJ  input is -2 w r staged from the residual (the adjoint seed of chi^2), or a
+//             given seed (vector-Jacobian product of the render), PSF flipped,
 //             output is dchi2/dS on the extended grid.
 #pragma once
 #include "apx_internal.h"
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict_
             T val = 0;
             if (e < LH * LW0 && y >= 0 && y < im.H && x >= 0 && x < im.W) {
                 const long long pix = im.pix_off + (long long)y * im.W + x;
-                val = -2.f * io.weight[pix] * p.rbuf[pix];
+                val = io.seed ? io.seed[pix] : -2.f * io.weight[pix] * p.rbuf[pix];
             }
             v[q] = val;
         }

@@ -15,8 +15,10 @@ typedef double apx_d4 __attribute__((ext_vector_type(4)));
 
 // TM = 64: 4 waves as 2 x 2 blocks of 32 x 32 (2 x 2 MFMA tiles each).
 // TM = 16: 4 waves share one 16 x 16 tile and split each LDS stage along K.
-// Stages of PAIR_KC pixels (one row segment of the box intersection) are software
-// pipelined: the global loads of stage s+1 are in flight while the MFMAs consume s.
+// Stages of KC = PAIR_KC pixels (one row segment of the box intersection) are software
+// pipelined: the global loads of stage s+1 are in flight
+// while the MFMAs consume s.  Each thread stages the same tile columns and pixel offsets
+// in every stage, so its column offsets into J are computed once.
 template <int TM>
 __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ pairs,
                                               const PairItem* __restrict__ items,
@@ -24,6 +26,7 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
                                               const apx_lm_state* lm) {
     constexpr int KC = PAIR_KC;
     constexpr int PER = TM * KC / 256;              // elements of A (and of B) per thread
+    constexpr int NB = TM >= 64 ? TM / 32 : 1;
     __shared__ double As[TM][KC + 1];
     __shared__ double Bs[TM][KC + 1];
     const PairItem it = items[xcd_item((int)blockIdx.x, (int)gridDim.x)];
@@ -36,61 +39,56 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     const float* __restrict__ Jg = p.J + G.j_off;
     const float* __restrict__ Jh = p.J + Hh.j_off;
     const int a0 = it.ta * TM, b0 = it.tb * TM;
-    const int ncg = G.ncols, nch = Hh.ncols;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    constexpr int NB = TM == 64 ? 2 : 1;
-    const int wr = TM == 64 ? (wv >> 1) : 0, wc = TM == 64 ? (wv & 1) : 0;
+    const int wr = TM >= 64 ? (wv >> 1) : 0, wc = TM >= 64 ? (wv & 1) : 0;
     apx_d4 acc[NB][NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[a][b] = (apx_d4){0.0, 0.0, 0.0, 0.0};
 
+    // element q of this thread: tile column i0 + DI q at stage pixel kq, the same in every
+    // stage; its offset into J is colA + q * stepA (the step is uniform)
+    constexpr int DI = 256 / KC;
+    const int i0 = threadIdx.x / KC, kq = threadIdx.x % KC;
+    const long long colA = (long long)(a0 + i0) * gs - G.ox0, stepA = (long long)DI * gs;
+    const long long colB = (long long)(b0 + i0) * hs - Hh.ox0, stepB = (long long)DI * hs;
+    const int nva = G.ncols - a0 - i0, nvb = Hh.ncols - b0 - i0;   // element q valid: DI q < nv
+
     const int nxs = (pr.x1 - pr.x0 + KC - 1) / KC;
     const int n_stage = (it.r1 - it.r0) * nxs;
-    float ra[PER], rb[PER], rw[PER];
+    float ra[PER], rb[PER], rw;
     auto fetch = [&](int st) {
         const int row = it.r0 + st / nxs;
-        const int xs = pr.x0 + (st - (st / nxs) * nxs) * KC;
-        const long long rowpix = im.pix_off + (long long)row * im.W;
-        const long long grow = (long long)(row - G.oy0) * G.ow - G.ox0;
-        const long long hrow = (long long)(row - Hh.oy0) * Hh.ow - Hh.ox0;
+        const int x = pr.x0 + (st - (st / nxs) * nxs) * KC + kq;
+        const long long grow = (long long)(row - G.oy0) * G.ow + x;
+        const long long hrow = (long long)(row - Hh.oy0) * Hh.ow + x;
+        const bool in = x < pr.x1;
+        rw = in ? weight[im.pix_off + (long long)row * im.W + x] : 0.f;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = threadIdx.x + 256 * q;
-            const int i = e / KC, k = e - (e / KC) * KC;
-            const int x = xs + k;
-            float av = 0.f, bv = 0.f, wv_ = 0.f;
-            if (x < pr.x1) {
-                const int ca = a0 + i, cb = b0 + i;
-                wv_ = weight[rowpix + x];
-                if (ca < ncg) av = Jg[ca * gs + grow + x];
-                if (cb < nch) bv = Jh[cb * hs + hrow + x];
-            }
-            ra[q] = av;
-            rb[q] = bv;
-            rw[q] = wv_;
+            ra[q] = (in && DI * q < nva) ? Jg[colA + q * stepA + grow] : 0.f;
+            rb[q] = (in && DI * q < nvb) ? Jh[colB + q * stepB + hrow] : 0.f;
         }
     };
     if (n_stage > 0) fetch(0);
     for (int st = 0; st < n_stage; ++st) {
+        const double wd = (double)rw;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = threadIdx.x + 256 * q;
-            const int i = e / KC, k = e - (e / KC) * KC;
-            As[i][k] = (double)ra[q] * (double)rw[q];
-            Bs[i][k] = (double)rb[q];
+            As[i0 + DI * q][kq] = (double)ra[q] * wd;
+            Bs[i0 + DI * q][kq] = (double)rb[q];
         }
         __syncthreads();
         if (st + 1 < n_stage) fetch(st + 1);
-        if constexpr (TM == 64) {
+        if constexpr (TM >= 64) {
 #pragma unroll
             for (int kk = 0; kk < KC; kk += 4) {
                 double av[NB], bv[NB];
 #pragma unroll
-                for (int m = 0; m < NB; ++m) av[m] = As[wr * 32 + m * 16 + (lane & 15)][kk + (lane >> 4)];
+                for (int m = 0; m < NB; ++m) av[m] = As[wr * (TM / 2) + m * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-                for (int n = 0; n < NB; ++n) bv[n] = Bs[wc * 32 + n * 16 + (lane & 15)][kk + (lane >> 4)];
+                for (int n = 0; n < NB; ++n) bv[n] = Bs[wc * (TM / 2) + n * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
                 for (int m = 0; m < NB; ++m)
 #pragma unroll
@@ -109,7 +107,7 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     }
 
     double* out = p.pair_part + it.out_off;
-    if constexpr (TM == 64) {
+    if constexpr (TM >= 64) {
 #pragma unroll
         for (int m = 0; m < NB; ++m)
 #pragma unroll
@@ -117,8 +115,8 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     // v_mfma_f64_16x16x4: D[i][j] sits in lane j + 16 (i % 4), register i / 4
-                    const int i = wr * 32 + m * 16 + (lane >> 4) + 4 * v;
-                    const int j = wc * 32 + n * 16 + (lane & 15);
+                    const int i = wr * (TM / 2) + m * 16 + (lane >> 4) + 4 * v;
+                    const int j = wc * (TM / 2) + n * 16 + (lane & 15);
                     out[i * TM + j] = acc[m][n][v];
                 }
     } else {

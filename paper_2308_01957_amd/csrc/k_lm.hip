@@ -148,6 +148,17 @@ hipError_t launch_chol_small(const Plan& p, const int* small_subs, int n_small, 
 // attempt is retried (lambda *= UP) by one fallback workgroup that factors the whole
 // matrix itself -- the rare path costs one launch that exits at once when unused.
 
+// 1/sqrt(x) for positive normal x: the hardware estimate refined by two Newton steps
+// y <- y (3 - x y^2) / 2 (each roughly doubles the correct bits), a short dependent chain
+// on the factorisation's critical path.
+__device__ __forceinline__ double rsqrt_f64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
 // Value of v in lane `src` (a compile-time constant after unrolling), to every lane.
 __device__ __forceinline__ double lane_bcast(double v, int src) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -167,8 +178,8 @@ __device__ __forceinline__ bool chol64_regs(double (&a)[CHOL_NB], int lane, doub
     for (int j = 0; j < CHOL_NB; ++j) {
         const double piv = lane_bcast(a[j], j);
         if (!(piv > 0.0) || !isfinite(piv)) return false;
-        const double ljj = sqrt(piv);
-        const double rj = 1.0 / ljj;
+        const double rj = rsqrt_f64(piv);
+        const double ljj = piv * rj;
         if (lane == 0) invd[j] = rj;
         const double lij = lane > j ? a[j] * rj : 0.0;
         a[j] = lane > j ? lij : (lane == j ? ljj : a[j]);
@@ -191,9 +202,12 @@ __device__ __forceinline__ bool chol64_regs(double (&a)[CHOL_NB], int lane, doub
 // Identity padding beyond the block size is harmless.
 __device__ __forceinline__ void trsm_row_regs(double (&x)[CHOL_NB], const double (*Lt)[CHOL_NB + 1],
                                               const double* invd) {
+    double rd[CHOL_NB];
+#pragma unroll
+    for (int j = 0; j < CHOL_NB; ++j) rd[j] = invd[j];
 #pragma unroll
     for (int j = 0; j < CHOL_NB; ++j) {
-        x[j] = x[j] * invd[j];
+        x[j] = x[j] * rd[j];
         double cv[CHOL_NB];
 #pragma unroll
         for (int q = j + 1; q < CHOL_NB; ++q) cv[q] = Lt[j][q];

@@ -408,6 +408,39 @@ __global__ void k_flip_psf(Plan p) {
     }
 }
 
+// -------------------------------------------------------------- seed sums (VJP sky column)
+// Block c of image k sums pixels c*256 + t + SEED_BLOCKS*256*m in FP64 (fixed order per
+// thread, then waves in order); one wave per image folds the SEED_BLOCKS partials.
+constexpr int SEED_BLOCKS = 64;
+__global__ __launch_bounds__(256) void k_seed_part(Plan p, const float* __restrict__ seed, double* part) {
+    __shared__ double red[4];
+    const int k = blockIdx.y, c = blockIdx.x;
+    const DImage& im = p.images[k];
+    const long long npx = (long long)im.H * im.W;
+    double acc = 0.0;
+    for (long long e = (long long)c * 256 + threadIdx.x; e < npx; e += (long long)SEED_BLOCKS * 256)
+        acc += (double)seed[im.pix_off + e];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[k * SEED_BLOCKS + c] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ void k_seed_fold(Plan p, const double* __restrict__ part) {
+    const int k = blockIdx.x;
+    double v = part[k * SEED_BLOCKS + threadIdx.x];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (threadIdx.x == 0) p.img_sum[3 * k + 1] = -0.5 * v;
+}
+
+hipError_t launch_seed_sums(const Plan& p, const float* seed, double* part, hipStream_t st) {
+    static_assert(SEED_BLOCKS == 64, "one lane per partial in the fold");
+    if (p.n_images == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seed_part, dim3(SEED_BLOCKS, p.n_images), dim3(256), 0, st, p, seed, part);
+    hipLaunchKernelGGL(k_seed_fold, dim3(p.n_images), dim3(64), 0, st, p, part);
+    return hipGetLastError();
+}
+
 hipError_t launch_flip_psf(const Plan& p, hipStream_t st) {
     if (p.n_images == 0) return hipSuccess;
     hipLaunchKernelGGL(k_flip_psf, dim3(4, p.n_images), dim3(256), 0, st, p);

@@ -18,7 +18,8 @@ def declared():
 
 def test_header_declares_the_hot_path():
     names = declared()
-    for n in ["apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_lm_step", "apx_chi2_grad"]:
+    for n in ["apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_lm_step", "apx_chi2_grad",
+              "apx_render_vjp"]:
         assert n in names
 
 

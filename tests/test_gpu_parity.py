@@ -128,6 +128,38 @@ def test_gradient_parity(apx, name):
     assert np.all(np.abs(g - go) <= tol), float(np.max(np.abs(g - go) / tol))
 
 
+@pytest.mark.parametrize("name", list(SPECS))
+def test_render_vjp_parity(apx, name):
+    """apx_render_vjp against the oracle's explicit J^T seed (rtol 1e-4 of the summand
+    scale |seed|^T |J|, as for the chi^2 gradient)."""
+    spec = get(name)
+    P, _, _ = problem(apx, spec)
+    th = spec["theta_init"]
+    seed = np.random.default_rng(77).standard_normal(P.n_pix).astype(np.float32)
+    g = P.render_vjp(th, seed).cpu().numpy()
+    P.check()
+    J = oracle.jacobian(spec, th)
+    s64 = seed.astype(np.float64)
+    go = s64 @ J
+    tol = 1e-4 * np.maximum(np.abs(go), np.abs(s64) @ np.abs(J))
+    assert np.all(np.abs(g - go) <= tol), float(np.max(np.abs(g - go) / tol))
+
+
+def test_render_autograd_backward_is_the_vjp(apx):
+    """RenderFn: d/dtheta of sum(seed * model) through torch autograd equals
+    apx_render_vjp bit for bit, and its forward equals apx_render."""
+    import torch
+    spec = get("small_blend")
+    P, _, _ = problem(apx, spec)
+    th = torch.tensor(spec["theta_init"], dtype=torch.float64, device=P.device, requires_grad=True)
+    seed = torch.from_numpy(np.random.default_rng(78).standard_normal(P.n_pix).astype(np.float32)).to(P.device)
+    m = apx.render_autograd(th, P)
+    assert torch.equal(m, P.render(th.detach()))
+    (m.double() * seed.double()).sum().backward()
+    ref = P.render_vjp(th.detach(), seed)
+    assert torch.equal(th.grad, ref)
+
+
 def _lm_run(apx, spec, n_iter, use_graph=False):
     P, d, w = problem(apx, spec)
     th, st = P.lm_init(spec["theta_init"], d, w)
