@@ -166,68 +166,122 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
     return __hiloint2double(hi, lo);
 }
 
-// Cholesky of a 64 x 64 block held in registers by one wave: lane i owns row i (a[q],
-// q <= i; entries above the diagonal are scratch).  Rows at or beyond the block size must
-// arrive as identity rows.  Per column j: the pivot comes from lane j, every lane scales
-// its a[j], the scaled column goes through LDS (col) and every later entry of every row is
-// updated with broadcast reads -- no lane masks, fully unrolled, wave-synchronous.
-// The reciprocals of the diagonal of the factor go to invd[CHOL_NB] (LDS).
-// Returns false in every lane on a non-positive or non-finite pivot.
-__device__ __forceinline__ bool chol64_regs(double (&a)[CHOL_NB], int lane, double* col, double* invd) {
+// Blocked factorisation of one CHOL_NB x CHOL_NB diagonal block in LDS, by the whole
+// 256-thread workgroup (every thread must call it).  The block is taken in four 16-column
+// sub-panels.  For each, wave 0 holds one row per lane (16 entries in registers) and runs
+// the 16 column steps of a right-looking Cholesky over every row at or below the
+// sub-panel -- the 16 x 16 diagonal factor and the solve of the rows below it in one pass:
+// the pivot comes from its lane by readlane, 1/sqrt refines the hardware estimate, the
+// scaled column goes through LDS and the later entries of the row are updated with
+// independent FMAs.  The trailing rows and columns are then updated with the sub-panel
+// (a rank-16 update) on FP64 MFMA, its 16 x 16 blocks shared out over the four waves.
+// Rows at or beyond the block size must arrive as identity rows.  On return B holds the
+// factor (lower triangle, row-major) and invd the reciprocals of its diagonal; the
+// return value is false (in every thread) on a non-positive or non-finite pivot.
+typedef double chol_d4 __attribute__((ext_vector_type(4)));
+constexpr int SUBP = 16;                       // sub-panel width
+
+// D[16 di + r][16 dk + c] -= sum_{k < 16} A[16 ai + r][c0 + k] * Bm[16 bk + c][c0 + k]
+// for one 16 x 16 block, by one wave (v_mfma_f64_16x16x4: A row m = lane % 16 and B
+// column n = lane % 16 at k = lane / 16; D[i][j] sits in lane j + 16 (i % 4), register i / 4).
+__device__ __forceinline__ void rank16_block(double (*D)[CHOL_NB + 1], int di, int dk,
+                                             const double (*A)[CHOL_NB + 1], int ai,
+                                             const double (*Bm)[CHOL_NB + 1], int bk, int c0, int lane) {
+    chol_d4 acc = (chol_d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < CHOL_NB; ++j) {
-        const double piv = lane_bcast(a[j], j);
-        if (!(piv > 0.0) || !isfinite(piv)) return false;
-        const double rj = rsqrt_f64(piv);
-        const double ljj = piv * rj;
-        if (lane == 0) invd[j] = rj;
-        const double lij = lane > j ? a[j] * rj : 0.0;
-        a[j] = lane > j ? lij : (lane == j ? ljj : a[j]);
-        col[lane] = lij;
-        __builtin_amdgcn_wave_barrier();
-        // all broadcast reads of the column first, so they are in flight together
-        double cv[CHOL_NB];
+    for (int k0 = 0; k0 < SUBP; k0 += 4) {
+        const double a = A[SUBP * ai + (lane & 15)][c0 + k0 + (lane >> 4)];
+        const double b = Bm[SUBP * bk + (lane & 15)][c0 + k0 + (lane >> 4)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
 #pragma unroll
-        for (int q = j + 1; q < CHOL_NB; ++q) cv[q] = col[q];
+    for (int v = 0; v < 4; ++v) D[SUBP * di + (lane >> 4) + 4 * v][SUBP * dk + (lane & 15)] -= acc[v];
+}
+
+__device__ __forceinline__ bool factor_diag_blocked(double (*B)[CHOL_NB + 1], double* col, double* invd, int* bad) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) *bad = 0;
+    __syncthreads();
+    for (int p = 0; p < CHOL_NB / SUBP; ++p) {
+        const int c0 = SUBP * p;
+        if (wv == 0) {
+            double f[SUBP];
 #pragma unroll
-        for (int q = j + 1; q < CHOL_NB; ++q) a[q] = fma(-lij, cv[q], a[q]);
-        __builtin_amdgcn_wave_barrier();
+            for (int q = 0; q < SUBP; ++q) f[q] = B[lane][c0 + q];
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < SUBP; ++j) {
+                const int cj = c0 + j;
+                double piv = lane_bcast(f[j], cj);
+                // a failed pivot is recorded and replaced by 1 so the (discarded) factor
+                // stays finite and the loop has no exit
+                if (!(piv > 0.0) || !isfinite(piv)) { ok = false; piv = 1.0; }
+                const double rj = rsqrt_f64(piv);
+                const double l = lane > cj ? f[j] * rj : 0.0;
+                f[j] = lane > cj ? l : (lane == cj ? piv * rj : f[j]);
+                if (lane == 0) invd[cj] = rj;
+                col[lane] = l;
+                __builtin_amdgcn_wave_barrier();
+                double cv[SUBP];
+#pragma unroll
+                for (int q = j + 1; q < SUBP; ++q) cv[q] = col[c0 + q];
+#pragma unroll
+                for (int q = j + 1; q < SUBP; ++q) f[q] = fma(-l, cv[q], f[q]);
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (lane >= c0) {
+#pragma unroll
+                for (int q = 0; q < SUBP; ++q) B[lane][c0 + q] = f[q];
+            }
+            if (!ok && lane == 0) *bad = 1;
+        }
+        __syncthreads();
+        if (*bad) return false;
+        // trailing lower-triangular blocks (bi >= bk > p): 6, 3, 1 of them
+        const int first = p + 1, nt = CHOL_NB / SUBP - first;
+        for (int e = wv; e < nt * (nt + 1) / 2; e += 4) {
+            int bi = 0, r = e;
+            while (r > bi) { r -= bi + 1; ++bi; }
+            rank16_block(B, first + bi, first + r, B, first + bi, B, first + r, c0, lane);
+        }
+        __syncthreads();
     }
     return true;
 }
 
-// x L^T = m for one row per lane (x in registers), with the factor transposed in LDS
-// (Lt[j][q] = L[q][j], so column j of L is a contiguous row) and the reciprocals of its
-// diagonal in invd: right-looking, so the updates of one column are independent FMAs.
-// Identity padding beyond the block size is harmless.
-__device__ __forceinline__ void trsm_row_regs(double (&x)[CHOL_NB], const double (*Lt)[CHOL_NB + 1],
-                                              const double* invd) {
-    double rd[CHOL_NB];
+// x L^T = m for a CHOL_NB-row block X in LDS against the factored diagonal block B (the
+// whole workgroup calls it): per 16-column sub-panel, wave 0 solves its columns (one row
+// per lane, multiplications by invd, broadcast reads of B), then the later columns of
+// every row are updated on FP64 MFMA by the four waves.
+__device__ __forceinline__ void trsm_blocked(double (*X)[CHOL_NB + 1], const double (*B)[CHOL_NB + 1],
+                             const double* invd) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int p = 0; p < CHOL_NB / SUBP; ++p) {
+        const int c0 = SUBP * p;
+        if (wv == 0) {
+            double x[SUBP];
 #pragma unroll
-    for (int j = 0; j < CHOL_NB; ++j) rd[j] = invd[j];
+            for (int q = 0; q < SUBP; ++q) x[q] = X[lane][c0 + q];
 #pragma unroll
-    for (int j = 0; j < CHOL_NB; ++j) {
-        x[j] = x[j] * rd[j];
-        double cv[CHOL_NB];
+            for (int j = 0; j < SUBP; ++j) {
+                double cv[SUBP];
 #pragma unroll
-        for (int q = j + 1; q < CHOL_NB; ++q) cv[q] = Lt[j][q];
+                for (int q = j + 1; q < SUBP; ++q) cv[q] = B[c0 + q][c0 + j];
+                const double xj = x[j] * invd[c0 + j];
+                x[j] = xj;
 #pragma unroll
-        for (int q = j + 1; q < CHOL_NB; ++q) x[q] = fma(-x[j], cv[q], x[q]);
+                for (int q = j + 1; q < SUBP; ++q) x[q] = fma(-xj, cv[q], x[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < SUBP; ++q) X[lane][c0 + q] = x[q];
+        }
+        __syncthreads();
+        // X[:, later sub-panels] -= X[:, this sub-panel] L[later rows, this sub-panel]^T
+        const int first = p + 1, nt = CHOL_NB / SUBP - first;
+        for (int e = wv; e < (CHOL_NB / SUBP) * nt; e += 4)
+            rank16_block(X, e / nt, first + e % nt, X, e / nt, B, first + e % nt, c0, lane);
+        __syncthreads();
     }
-}
-
-// Wave 0 factors the staged diagonal block B (read as rows) and writes the factor back
-// into B transposed (B[q][i] = L[i][q]).  Returns false on a failed pivot.
-__device__ __forceinline__ bool factor_diag_block(double (*B)[CHOL_NB + 1], int lane, double* col,
-                                                  double* invd) {
-    double a[CHOL_NB];
-#pragma unroll
-    for (int q = 0; q < CHOL_NB; ++q) a[q] = B[lane][q];
-    __builtin_amdgcn_wave_barrier();
-    const bool ok = chol64_regs(a, lane, col, invd);
-#pragma unroll
-    for (int q = 0; q < CHOL_NB; ++q) B[q][lane] = a[q];
-    return ok;
 }
 
 // Stage the nr x nc block at (r0, c0) of the n x n row-major matrix into LDS with
@@ -287,11 +341,10 @@ __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
     }
 }
 
-// Block column k: every workgroup factors the diagonal block in wave 0's registers
-// (redundantly); workgroup 0 stores it and reports a failed pivot, workgroup b > 0
-// solves row block k+b (X L_kk^T = M_rk, one row per lane of wave 0).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void k_chol_panel(Plan p, int s, int kblk) {
+// Block column k: every workgroup factors the diagonal block (redundantly, blocked on
+// FP64 MFMA); workgroup 0 stores it and reports a failed pivot, workgroup b > 0 solves row
+// block k+b (X L_kk^T = M_rk).
+__global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
     __shared__ double L[CHOL_NB][CHOL_NB + 1];
     __shared__ double X[CHOL_NB][CHOL_NB + 1];
     __shared__ double col[CHOL_NB], invd[CHOL_NB];
@@ -302,37 +355,24 @@ void k_chol_panel(Plan p, int s, int kblk) {
     double* Mg = p.M + sb.a_off;
     const int kb = kblk * CHOL_NB;
     const int nb = min(CHOL_NB, n - kb);
-    const int t = threadIdx.x, lane = t & 63;
+    const int t = threadIdx.x;
     const int rb = kb + blockIdx.x * CHOL_NB;
     const int nr = blockIdx.x > 0 ? min(CHOL_NB, n - rb) : 0;
     stage_block(Mg, n, kb, kb, nb, nb, L, true);
     if (nr > 0) stage_block(Mg, n, rb, kb, nr, nb, X, false);
     __syncthreads();
-    if (t < 64) {
-        const bool ok = factor_diag_block(L, lane, col, invd);     // L now holds L^T
-        if (lane == 0) bad = ok ? 0 : 1;
-    }
-    __syncthreads();
-    if (bad) {
+    if (!factor_diag_blocked(L, col, invd, &bad)) {
         if (blockIdx.x == 0 && t == 0) p.lmf[s].chol_fail = 1;
         return;
     }
     if (blockIdx.x == 0) {
         for (int e = t; e < nb * nb; e += 256) {
             const int i = e / nb, j = e - (e / nb) * nb;
-            if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[j][i];
+            if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[i][j];
         }
         return;
     }
-    if (t < 64) {
-        double x[CHOL_NB];
-#pragma unroll
-        for (int q = 0; q < CHOL_NB; ++q) x[q] = X[lane][q];
-        trsm_row_regs(x, L, invd);
-#pragma unroll
-        for (int q = 0; q < CHOL_NB; ++q) X[lane][q] = x[q];
-    }
-    __syncthreads();
+    trsm_blocked(X, L, invd);
     for (int e = t; e < nr * nb; e += 256) {
         const int i = e / nb, j = e - (e / nb) * nb;
         Mg[(long long)(rb + i) * n + kb + j] = X[i][j];
@@ -342,7 +382,6 @@ void k_chol_panel(Plan p, int s, int kblk) {
 // Trailing update M_ij -= L_ik L_jk^T of one 64 x 64 block pair on FP64 MFMA: both
 // 64 x 64 panels are staged in LDS, each wave accumulates a 32 x 32 quadrant as 2 x 2
 // tiles of v_mfma_f64_16x16x4 (D[i][j] in lane j + 16 (i % 4), register i / 4).
-typedef double chol_d4 __attribute__((ext_vector_type(4)));
 __device__ void chol_update_block(double* Mg, int n, int ri, int rj, int kc, bool diag,
                                   double (*Li)[CHOL_NB + 1], double (*Lj)[CHOL_NB + 1]) {
     const int ni = min(CHOL_NB, n - ri), nj = min(CHOL_NB, n - rj), nk = min(CHOL_NB, n - kc);
@@ -404,7 +443,7 @@ void k_chol_retry(Plan p, int s, apx_lm_state* lm) {
     __shared__ double Li[CHOL_NB][CHOL_NB + 1], Lj[CHOL_NB][CHOL_NB + 1];
     __shared__ double col[CHOL_NB], invd[CHOL_NB];
     __shared__ int bad;
-    const int t = threadIdx.x, lane = t & 63;
+    const int t = threadIdx.x;
     if (!p.lmf[s].chol_fail) {
         if (t == 0) p.lmf[s].chol_done = 1;
         return;
@@ -428,29 +467,16 @@ void k_chol_retry(Plan p, int s, apx_lm_state* lm) {
             const int kb = k * CHOL_NB, nb = min(CHOL_NB, n - kb);
             stage_block(Mg, n, kb, kb, nb, nb, L, true);
             __syncthreads();
-            if (t < 64) {
-                const bool okw = factor_diag_block(L, lane, col, invd);   // L now holds L^T
-                if (lane == 0) bad = okw ? 0 : 1;
-            }
-            __syncthreads();
-            if (bad) { ok = false; break; }
+            if (!factor_diag_blocked(L, col, invd, &bad)) { ok = false; break; }
             for (int e = t; e < nb * nb; e += 256) {
                 const int i = e / nb, j = e - (e / nb) * nb;
-                if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[j][i];
+                if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[i][j];
             }
             for (int r = k + 1; r < nblk; ++r) {
                 const int rb = r * CHOL_NB, nr = min(CHOL_NB, n - rb);
                 stage_block(Mg, n, rb, kb, nr, nb, X, false);
                 __syncthreads();
-                if (t < 64) {
-                    double x[CHOL_NB];
-#pragma unroll
-                    for (int q = 0; q < CHOL_NB; ++q) x[q] = X[lane][q];
-                    trsm_row_regs(x, L, invd);
-#pragma unroll
-                    for (int q = 0; q < CHOL_NB; ++q) X[lane][q] = x[q];
-                }
-                __syncthreads();
+                trsm_blocked(X, L, invd);
                 for (int e = t; e < nr * nb; e += 256) {
                     const int i = e / nb, j = e - (e / nb) * nb;
                     Mg[(long long)(rb + i) * n + kb + j] = X[i][j];
