@@ -16,9 +16,9 @@ typedef double apx_d4 __attribute__((ext_vector_type(4)));
 // TM = 64: 4 waves as 2 x 2 blocks of 32 x 32 (2 x 2 MFMA tiles each).
 // TM = 16: 4 waves share one 16 x 16 tile and split each LDS stage along K.
 // Stages of KC = PAIR_KC pixels (one row segment of the box intersection) are software
-// pipelined: the global loads of stage s+1 are in flight
-// while the MFMAs consume s.  Each thread stages the same tile columns and pixel offsets
-// in every stage, so its column offsets into J are computed once.
+// pipelined two deep: the global loads of stages s+1 and s+2 are in flight while the
+// MFMAs consume s.  Each thread stages the same tile columns and pixel offsets in every
+// stage, so its column offsets into J are computed once.
 template <int TM>
 __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ pairs,
                                               const PairItem* __restrict__ items,
@@ -32,9 +32,12 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     const PairItem it = items[xcd_item((int)blockIdx.x, (int)gridDim.x)];
     const DPair pr = pairs[it.pair];
     if (lm && lm[pr.sub].need_jac == 0) return;
-    const DGroup& G = p.groups[pr.g];
-    const DGroup& Hh = p.groups[pr.h];
-    const DImage& im = p.images[pr.image];
+    // by value: the fields live in registers for the whole loop (no reloads through the
+    // pointers after every store)
+    const DGroup G = p.groups[pr.g];
+    const DGroup Hh = p.groups[pr.h];
+    const long long pix_off = p.images[pr.image].pix_off;
+    const int imW = p.images[pr.image].W;
     const long long gs = (long long)G.oh * G.ow, hs = (long long)Hh.oh * Hh.ow;
     const float* __restrict__ Jg = p.J + G.j_off;
     const float* __restrict__ Jh = p.J + Hh.j_off;
@@ -57,30 +60,31 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
 
     const int nxs = (pr.x1 - pr.x0 + KC - 1) / KC;
     const int n_stage = (it.r1 - it.r0) * nxs;
-    float ra[PER], rb[PER], rw;
-    auto fetch = [&](int st) {
+    // two stages of global loads in flight (register ring): the loads of stage s+2 are
+    // issued while the MFMAs consume stages s and s+1
+    float ra0[PER], rb0[PER], rw0 = 0.f, ra1[PER], rb1[PER], rw1 = 0.f;
+    auto fetch = [&](int st, float (&ra)[PER], float (&rb)[PER], float& rw) {
         const int row = it.r0 + st / nxs;
         const int x = pr.x0 + (st - (st / nxs) * nxs) * KC + kq;
         const long long grow = (long long)(row - G.oy0) * G.ow + x;
         const long long hrow = (long long)(row - Hh.oy0) * Hh.ow + x;
         const bool in = x < pr.x1;
-        rw = in ? weight[im.pix_off + (long long)row * im.W + x] : 0.f;
+        rw = in ? weight[pix_off + (long long)row * imW + x] : 0.f;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             ra[q] = (in && DI * q < nva) ? Jg[colA + q * stepA + grow] : 0.f;
             rb[q] = (in && DI * q < nvb) ? Jh[colB + q * stepB + hrow] : 0.f;
         }
     };
-    if (n_stage > 0) fetch(0);
-    for (int st = 0; st < n_stage; ++st) {
+    auto stage = [&](const float (&ra)[PER], const float (&rb)[PER], float rw) {
         const double wd = (double)rw;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             As[i0 + DI * q][kq] = (double)ra[q] * wd;
             Bs[i0 + DI * q][kq] = (double)rb[q];
         }
-        __syncthreads();
-        if (st + 1 < n_stage) fetch(st + 1);
+    };
+    auto compute = [&]() {
         if constexpr (TM >= 64) {
 #pragma unroll
             for (int kk = 0; kk < KC; kk += 4) {
@@ -103,7 +107,22 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
                 acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[0][0], 0, 0, 0);
             }
         }
+    };
+    if (n_stage > 0) fetch(0, ra0, rb0, rw0);
+    if (n_stage > 1) fetch(1, ra1, rb1, rw1);
+    for (int st = 0; st < n_stage; st += 2) {
+        stage(ra0, rb0, rw0);
         __syncthreads();
+        if (st + 2 < n_stage) fetch(st + 2, ra0, rb0, rw0);
+        compute();
+        __syncthreads();
+        if (st + 1 < n_stage) {
+            stage(ra1, rb1, rw1);
+            __syncthreads();
+            if (st + 3 < n_stage) fetch(st + 3, ra1, rb1, rw1);
+            compute();
+            __syncthreads();
+        }
     }
 
     double* out = p.pair_part + it.out_off;
