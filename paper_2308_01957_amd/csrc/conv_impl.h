@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict_
     __shared__ __attribute__((aligned(16))) T tile[LH * LW];
     __shared__ double red[4][3];
 
-    const int item_idx = item_begin + xcd_item((int)blockIdx.x, (int)gridDim.x);
+    const int item_idx = item_begin + (int)blockIdx.x;
     const ConvItem it = items[item_idx];
     const ConvJob jb = jobs[it.job];
     const DImage& im = p.images[jb.image];
