@@ -227,6 +227,21 @@ def psf_half(im) -> int:
     return (np.asarray(im["psf"]).shape[0] - 1) // 2
 
 
+def clipped(comp: Dict, im) -> Dict | None:
+    """The component with its window cut to the extended grid of its image (pixels
+    outside that grid never reach the image through the valid convolution), or None
+    when nothing is left."""
+    c = psf_half(im)
+    y0, x0, y1, x1 = comp["box"]
+    y0, x0 = max(y0, -c), max(x0, -c)
+    y1, x1 = min(y1, im["H"] + c), min(x1, im["W"] + c)
+    if y1 <= y0 or x1 <= x0:
+        return None
+    out = dict(comp)
+    out["box"] = (y0, x0, y1, x1)
+    return out
+
+
 def render_ext(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
     """Sum of all components of image k on its extended grid [-c, H+c) x [-c, W+c)."""
     im = spec["images"][k]
@@ -235,9 +250,10 @@ def render_ext(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
     for comp in spec["comps"]:
         if comp["image"] != k:
             continue
-        y0, x0, y1, x1 = comp["box"]
-        if y1 <= y0 or x1 <= x0:
+        comp = clipped(comp, im)
+        if comp is None:
             continue
+        y0, x0, y1, x1 = comp["box"]
         S[y0 + c:y1 + c, x0 + c:x1 + c] += comp_pixels(spec, comp, theta)
     return S
 
@@ -301,9 +317,10 @@ def jacobian_image(spec, theta, k, cols: Sequence[int] | None = None) -> np.ndar
     for comp in spec["comps"]:
         if comp["image"] != k:
             continue
-        y0, x0, y1, x1 = comp["box"]
-        if y1 <= y0 or x1 <= x0:
+        comp = clipped(comp, im)
+        if comp is None:
             continue
+        y0, x0, y1, x1 = comp["box"]
         if not any(p >= 0 and p in want for p in comp["par"]):
             continue
         _, g = comp_pixels(spec, comp, theta, with_grad=True)

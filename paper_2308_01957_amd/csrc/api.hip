@@ -1299,16 +1299,19 @@ static apx_status ready(apx_problem* P) {
 
 extern "C" {
 
+// Buffers sized by n_par may be null when there are no free parameters.
+static bool par_ok(const apx_problem* P, const void* ptr) { return ptr != nullptr || P->n_par == 0; }
+
 apx_status apx_render(apx_problem* P, const double* theta, float* model) {
     APXCHK(ready(P));
-    if (!theta || !model) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (!par_ok(P, theta) || !model) return fail(P->ctx, APX_E_INVALID, "null pointer");
     return fwd_chi2(P, theta, nullptr, nullptr, model, nullptr, 0, 0, nullptr);
 }
 
 apx_status apx_chi2(apx_problem* P, const double* theta, const float* data, const float* weight,
                     double* chi2) {
     APXCHK(ready(P));
-    if (!theta || !data || !weight || !chi2) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (!par_ok(P, theta) || !data || !weight || !chi2) return fail(P->ctx, APX_E_INVALID, "null pointer");
     APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
     HIPCHK(launch_chi2_check(chi2, P->n_sub, P->plan.sticky, P->ctx->stream));
     return APX_OK;
@@ -1316,7 +1319,7 @@ apx_status apx_chi2(apx_problem* P, const double* theta, const float* data, cons
 
 apx_status apx_jacobian(apx_problem* P, const double* theta, float* J, int64_t ldJ) {
     APXCHK(ready(P));
-    if (!theta || !J) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (!par_ok(P, theta) || !par_ok(P, J)) return fail(P->ctx, APX_E_INVALID, "null pointer");
     if (ldJ < P->n_pix) return fail(P->ctx, APX_E_INVALID, "ldJ < n_pix");
     hipStream_t st = P->ctx->stream;
     HIPCHK(launch_prep(P->plan, theta, 0, st));
@@ -1329,7 +1332,8 @@ apx_status apx_jacobian(apx_problem* P, const double* theta, float* J, int64_t l
 apx_status apx_jtwj(apx_problem* P, const double* theta, const float* data, const float* weight,
                     double* JtWJ, double* JtWr, double* chi2) {
     APXCHK(ready(P));
-    if (!theta || !data || !weight || !JtWJ || !JtWr || !chi2) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (!par_ok(P, theta) || !data || !weight || !par_ok(P, JtWJ) || !par_ok(P, JtWr) || !chi2)
+        return fail(P->ctx, APX_E_INVALID, "null pointer");
     APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
     APXCHK(jac_blocks(P, weight, nullptr));
     APXCHK(normal_eq(P, weight, JtWJ, JtWr, nullptr));
@@ -1340,7 +1344,8 @@ apx_status apx_jtwj(apx_problem* P, const double* theta, const float* data, cons
 apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data, const float* weight,
                          double* grad, double* chi2) {
     APXCHK(ready(P));
-    if (!theta || !data || !weight || !grad || !chi2) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (!par_ok(P, theta) || !data || !weight || !par_ok(P, grad) || !chi2)
+        return fail(P->ctx, APX_E_INVALID, "null pointer");
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
     APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
@@ -1373,7 +1378,7 @@ apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data,
 
 apx_status apx_render_vjp(apx_problem* P, const double* theta, const float* grad_model, double* grad_theta) {
     APXCHK(ready(P));
-    if (!theta || !grad_model || !grad_theta) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (!par_ok(P, theta) || !grad_model || !par_ok(P, grad_theta)) return fail(P->ctx, APX_E_INVALID, "null pointer");
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
     {
@@ -1410,7 +1415,7 @@ apx_status apx_render_vjp(apx_problem* P, const double* theta, const float* grad
 apx_status apx_lm_init(apx_problem* P, const double* theta, const float* data, const float* weight,
                        apx_lm_state* state) {
     APXCHK(ready(P));
-    if (!theta || !data || !weight || !state) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (!par_ok(P, theta) || !data || !weight || !state) return fail(P->ctx, APX_E_INVALID, "null pointer");
     APXCHK(fwd_chi2(P, theta, data, weight, nullptr, P->chi2_sub, 0, 0, nullptr));
     HIPCHK(launch_lm_init(P->plan, P->chi2_sub, state, P->ctx->stream));
     return APX_OK;
@@ -1453,14 +1458,14 @@ static apx_status lm_step_enqueue(apx_problem* P, const float* data, const float
 apx_status apx_lm_step(apx_problem* P, const float* data, const float* weight, double* theta,
                        apx_lm_state* state) {
     APXCHK(ready(P));
-    if (!theta || !data || !weight || !state) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (!par_ok(P, theta) || !data || !weight || !state) return fail(P->ctx, APX_E_INVALID, "null pointer");
     return lm_step_enqueue(P, data, weight, theta, state);
 }
 
 apx_status apx_lm_run(apx_problem* P, int32_t n_iter, const float* data, const float* weight,
                       double* theta, apx_lm_state* state, int32_t use_graph) {
     APXCHK(ready(P));
-    if (!theta || !data || !weight || !state || n_iter < 0) return fail(P->ctx, APX_E_INVALID, "bad argument");
+    if (!par_ok(P, theta) || !data || !weight || !state || n_iter < 0) return fail(P->ctx, APX_E_INVALID, "bad argument");
     if (!use_graph) {
         for (int i = 0; i < n_iter; ++i) APXCHK(lm_step_enqueue(P, data, weight, theta, state));
         return APX_OK;

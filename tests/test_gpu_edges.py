@@ -1,0 +1,188 @@
+"""Edge cases of the HIP path through the C ABI, against the FP64 oracle or a closed form:
+the smallest and largest PSF stamps, degenerate Sersic shapes at the domain bounds, a
+window entirely outside the image, fully masked pixels, a fit with only the sky free
+(closed-form weighted mean), fixed parameters only, and PSF sizes the library rejects."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_01957_amd import synth
+from tests import cases
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2308_01957_amd import apx as mod
+    return mod
+
+
+def _spec(name, H, W, psf, gals, sky=0.05, boxes=None, s=3, sky_free=True):
+    """Sersics (x0, y0, q, PA, n, Re, log10 Ie), all free, + sky (free or fixed)."""
+    P = psf.shape[0]
+    theta, kinds, re_of, comps = [], [], [], []
+    for gi, g in enumerate(gals):
+        p0 = len(theta)
+        theta += list(g)
+        kinds += [0, 1, 2, 3, 4, 5, 6]
+        re_of += [g[5]] * 7
+        box = synth.full_window(H, W, P) if boxes is None else boxes[gi]
+        comps.append(dict(type=0, image=0, box=box, par=list(range(p0, p0 + 7)), fixed=[0.0] * 7))
+    if sky_free:
+        theta.append(sky)
+        kinds.append(8)
+        re_of.append(1.0)
+    spec = {"name": name,
+            "images": [dict(H=H, W=W, psf=psf, affine=synth.IDENTITY_AFFINE.copy(),
+                            sky_par=len(theta) - 1 if sky_free else -1,
+                            sky_fixed=0.0 if sky_free else sky, sub=0)],
+            "comps": comps, "subs": [(0, len(theta))],
+            "sampling": dict(s=s, rule=0, mode=0, k=0.0),
+            "theta_true": theta, "kinds": kinds, "re_of": re_of}
+    synth._finish(spec)
+    spec["noise"] = [np.random.default_rng(hash(name) % 2**32).standard_normal((H, W))]
+    spec["theta_init"] = spec["theta_true"].copy()
+    return cases.with_data(spec)
+
+
+def _render_and_jacobian_parity(apx, spec):
+    print(f"[case] {spec['name']}", flush=True)
+    P = apx.Problem(spec)
+    th = spec["theta_init"]
+    m = P.split(P.render(th))[0].astype(np.float64)
+    P.check()
+    mo = oracle.model_image(spec, th, 0)
+    assert np.all(np.abs(m - mo) <= cases.tol_pixels(mo)), float(np.max(np.abs(m - mo) / cases.tol_pixels(mo)))
+    J = P.jacobian(th).cpu().numpy().T.astype(np.float64)
+    Jo = oracle.jacobian(spec, th)
+    for k in range(spec["n_par"]):
+        scale = max(np.max(np.abs(Jo[:, k])), 1e-30)
+        assert np.max(np.abs(J[:, k] - Jo[:, k])) <= 3e-5 * scale, k
+    return P
+
+
+def test_psf_1x1_is_the_identity(apx):
+    """P = 1: the convolution is the identity (no extended-grid margin)."""
+    psf = np.ones((1, 1), dtype=np.float32)
+    spec = _spec("psf1", 37, 41, psf, [[20.3, 17.6, 0.7, 0.4, 1.5, 4.0, 0.5]])
+    _render_and_jacobian_parity(apx, spec)
+
+
+def test_psf_63x63_largest_supported(apx):
+    """P = 63, the largest stamp: a 62-pixel margin around a 40 x 33 image."""
+    psf = synth.moffat_psf(63, 6.0, 2.5)
+    spec = _spec("psf63", 40, 33, psf, [[15.2, 21.4, 0.6, 2.0, 2.5, 5.0, 0.8]])
+    _render_and_jacobian_parity(apx, spec)
+
+
+@pytest.mark.parametrize("P", [0, 2, 64, 65])
+def test_unsupported_psf_sizes_are_rejected(apx, P):
+    """Even sizes and sizes beyond 63 are refused at problem creation."""
+    psf = np.zeros((max(P, 1), max(P, 1)), dtype=np.float32)
+    psf[psf.shape[0] // 2, psf.shape[1] // 2] = 1.0
+    spec = _spec(f"badpsf{P}", 24, 24, np.ones((3, 3), np.float32) / 9, [[11.0, 12.0, 0.7, 0.3, 1.0, 3.0, 0.0]])
+    spec["images"][0]["psf"] = psf if P > 0 else np.zeros((0, 0), np.float32)
+    with pytest.raises(apx.ApxError):
+        apx.Problem(spec)
+
+
+def test_degenerate_shapes_at_the_domain_bounds(apx):
+    """q = 1 (PA has no effect: its Jacobian column is zero), n at both domain bounds,
+    a sub-pixel Re and a Re far larger than the image, PA = 0."""
+    psf = synth.gaussian_psf(9, 1.3)
+    gals = [[14.0, 15.0, 1.0, 0.7, 2.0, 4.0, 0.3],      # circular
+            [30.5, 12.2, 0.5, 0.0, 0.36, 3.0, 0.5],     # n at the lower bound
+            [22.1, 30.7, 0.8, 1.2, 10.0, 2.5, -0.5],    # n at the upper bound (cusp)
+            [8.4, 33.3, 0.9, 2.2, 1.0, 0.05, 1.0],      # Re = 0.05 px
+            [25.0, 22.0, 0.3, 0.9, 1.0, 500.0, -2.0]]   # Re = 500 px
+    spec = _spec("degenerate", 44, 40, psf, gals)
+    P = _render_and_jacobian_parity(apx, spec)
+    J = P.jacobian(spec["theta_init"]).cpu().numpy()
+    assert np.all(J[3] == 0.0)                          # d/dPA of the circular profile
+
+
+def test_window_outside_the_image_contributes_nothing(apx):
+    """A component whose window does not meet the image adds exactly zero (and gets an
+    all-zero Jacobian column); the other component is unaffected."""
+    psf = synth.gaussian_psf(7, 1.2)
+    gals = [[12.0, 10.0, 0.7, 0.5, 1.5, 3.0, 0.4], [60.0, 70.0, 0.7, 0.5, 1.5, 3.0, 0.4]]
+    boxes = [synth.full_window(24, 28, 7), (80, 90, 100, 110)]
+    spec = _spec("outside", 24, 28, psf, gals, boxes=boxes)
+    P = _render_and_jacobian_parity(apx, spec)
+    J = P.jacobian(spec["theta_init"]).cpu().numpy()
+    assert np.all(J[7:14] == 0.0)
+
+
+def test_fully_masked_pixels(apx):
+    """w = 0 everywhere: chi^2 = 0, J^T W J = 0, J^T W r = 0 and the gradient is 0."""
+    psf = synth.gaussian_psf(7, 1.2)
+    spec = _spec("masked", 26, 30, psf, [[13.0, 12.5, 0.6, 1.0, 2.0, 3.5, 0.2]])
+    P = apx.Problem(spec)
+    d = P.pixels(spec["data"])
+    w = P.pixels([np.zeros_like(spec["weight"][0])])
+    th = spec["theta_init"]
+    assert float(P.chi2(th, d, w).cpu()[0]) == 0.0
+    A, g, c2 = P.jtwj(th, d, w)
+    assert float(A.abs().max().cpu()) == 0.0 and float(g.abs().max().cpu()) == 0.0
+    gr, _ = P.chi2_grad(th, d, w)
+    assert float(gr.abs().max().cpu()) == 0.0
+    P.check()
+
+
+def test_sky_only_fit_reaches_the_weighted_mean(apx):
+    """Only the sky is free (the galaxy is fixed): chi^2 is quadratic in the sky and its
+    minimum is sky* = sum w (d - M) / sum w, M the convolved galaxy (from the oracle)."""
+    psf = synth.moffat_psf(11, 3.0, 2.5)
+    H, W = 48, 52
+    g = [23.4, 25.1, 0.65, 0.8, 1.8, 4.5, 0.6]
+    spec = {"name": "skyonly",
+            "images": [dict(H=H, W=W, psf=psf, affine=synth.IDENTITY_AFFINE.copy(), sky_par=0,
+                            sky_fixed=0.0, sub=0)],
+            "comps": [dict(type=0, image=0, box=synth.full_window(H, W, 11), par=[-1] * 7, fixed=g)],
+            "subs": [(0, 1)], "sampling": dict(s=3, rule=0, mode=0, k=0.0),
+            "theta_true": [0.08], "kinds": [8], "re_of": [1.0]}
+    synth._finish(spec)
+    spec["noise"] = [np.random.default_rng(91).standard_normal((H, W))]
+    spec["theta_init"] = np.array([0.02])
+    cases.with_data(spec)
+    P = apx.Problem(spec)
+    d, w = P.pixels(spec["data"]), P.pixels(spec["weight"])
+    th, st = P.lm_init(spec["theta_init"], d, w)
+    P.lm_run(12, d, w, th, st)
+    P.check()
+    M = oracle.model_image(spec, np.array([0.0]), 0)
+    dd, ww = spec["data"][0].astype(np.float64), spec["weight"][0].astype(np.float64)
+    sky_star = float(np.sum(ww * (dd - M)) / np.sum(ww))
+    assert abs(float(th.cpu()[0]) - sky_star) <= 1e-7 * (abs(sky_star) + 0.1)
+
+
+def test_all_parameters_fixed(apx):
+    """n_par = 0: the render is the fixed model, chi^2 is defined and the gradient empty."""
+    psf = synth.gaussian_psf(5, 1.0)
+    H, W = 20, 22
+    g = [9.5, 10.2, 0.8, 0.3, 1.2, 3.0, 0.4]
+    spec = {"name": "fixed",
+            "images": [dict(H=H, W=W, psf=psf, affine=synth.IDENTITY_AFFINE.copy(), sky_par=-1,
+                            sky_fixed=0.25, sub=0)],
+            "comps": [dict(type=0, image=0, box=synth.full_window(H, W, 5), par=[-1] * 7, fixed=g)],
+            "subs": [(0, 0)], "sampling": dict(s=3, rule=0, mode=0, k=0.0),
+            "theta_true": [], "kinds": [], "re_of": []}
+    synth._finish(spec)
+    spec["noise"] = [np.random.default_rng(92).standard_normal((H, W))]
+    spec["theta_init"] = np.zeros(0)
+    cases.with_data(spec)
+    P = apx.Problem(spec)
+    m = P.split(P.render(np.zeros(0)))[0].astype(np.float64)
+    mo = oracle.model_image(spec, np.zeros(0), 0)
+    assert np.all(np.abs(m - mo) <= cases.tol_pixels(mo))
+    d, w = P.pixels(spec["data"]), P.pixels(spec["weight"])
+    c2 = float(P.chi2(np.zeros(0), d, w).cpu()[0])
+    c2o = oracle.chi2(spec, np.zeros(0), spec["data"], spec["weight"])
+    c2o = float(np.sum(c2o)) if np.ndim(c2o) else float(c2o)
+    assert math.isclose(c2, c2o, rel_tol=1e-6)
+    P.check()

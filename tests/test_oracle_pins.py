@@ -183,6 +183,21 @@ def test_round_profile_ignores_pa_and_integer_shift_translates():
     assert np.allclose(c[4:20, 6:20], d[6:22, 3:17], rtol=1e-12)
 
 
+def test_windows_are_cut_to_the_extended_grid():
+    """A window reaching far past the extended grid renders exactly as the full window;
+    one that misses the grid adds nothing (pixels beyond the grid never reach the image
+    through the valid convolution)."""
+    spec = synth.single(1, H=20, W=24, P=7)
+    th = spec["theta_true"]
+    m_full = oracle.model_image(spec, th, 0)
+    spec["comps"][0]["box"] = (-40, -50, 90, 80)
+    assert np.array_equal(oracle.model_image(spec, th, 0), m_full)
+    spec["comps"][0]["box"] = (30, 40, 35, 45)
+    assert np.array_equal(oracle.model_image(spec, th, 0), np.full((20, 24), th[7]))
+    J = oracle.jacobian(spec, th)
+    assert np.all(J[:, :7] == 0.0) and np.all(J[:, 7] == 1.0)
+
+
 def test_affine_rotation_and_area():
     """An image whose pixel->sky map is a 90-degree rotation sees the rot90 of the
     identity render; a scaled map multiplies pixel values by the area |det A|."""
