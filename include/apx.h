@@ -169,6 +169,30 @@ const char* apx_status_string(apx_status s);
  * (null out), APX_E_HIP. */
 apx_status apx_ctx_create(int device, void* hip_stream, apx_ctx** out);
 apx_status apx_ctx_set_stream(apx_ctx* ctx, void* hip_stream);
+
+/* Output tile shapes of the direct convolution (§2.1.3).  Every convolution job (an image,
+ * or the Jacobian columns of one window) is cut into workgroup tiles of one of four shapes:
+ * 0 = 32 x 64, 1 = 16 x 64, 2 = 32 x 32, 3 = 16 x 32 output pixels; a job takes the shape of
+ * least estimated cost (tiles needed x cost of one tile) for its output size.  The policy
+ * holds for problems created after the call:
+ *   APX_TILES_AUTOTUNE (default): on a device context, the first problem that needs a
+ *     convolution kernel at a PSF size times all four shapes of it on a synthetic
+ *     256 x 256 job of 32 channels (a few ms, synchronous on the context stream, in scratch
+ *     memory the context allocates once and frees in apx_ctx_destroy) and the context keeps
+ *     the table; host-only contexts use the model;
+ *   APX_TILES_MODEL: an operation-count model, no timing;
+ *   APX_TILES_FIXED + s (s = 0..3): shape s for every job.
+ * The shape changes nothing but the order in which the FP64 per-tile partial sums of chi^2,
+ * J^T W r and the gradient are added.  APX_E_INVALID for an unknown policy. */
+#define APX_TILES_AUTOTUNE  0
+#define APX_TILES_MODEL     1
+#define APX_TILES_FIXED     2
+apx_status apx_ctx_set_tiles(apx_ctx* ctx, int32_t policy);
+
+/* Measured cost of one tile, in microseconds, of each shape (us[4]) of convolution kernel
+ * `kernel` (0 model FP32, 1 Jacobian columns, 2 adjoint, 3 model FP64) at PSF size P, as
+ * timed by the autotuner; APX_E_INVALID when that pair has not been timed. */
+apx_status apx_ctx_tile_cost(const apx_ctx* ctx, int32_t kernel, int32_t P, double* us);
 apx_status apx_ctx_destroy(apx_ctx* ctx);
 const char* apx_last_error(const apx_ctx* ctx);
 
@@ -188,8 +212,13 @@ apx_status apx_problem_bind_workspace(apx_problem* p, void* dev, uint64_t bytes)
 /* Sizes: total output pixels, total extended-grid pixels, stored Jacobian entries. */
 apx_status apx_problem_sizes(const apx_problem* p, int64_t* n_pix, int64_t* n_ext, int64_t* n_jac);
 
-/* Synchronise the stream and return the sticky device flag (APX_OK, APX_E_DOMAIN,
- * APX_E_NONFINITE), then clear it. */
+/* Convolution jobs of `kind` (0 model, 1 Jacobian columns, 2 adjoint) per tile shape:
+ * counts[s] for s = 0..3 (see apx_ctx_set_tiles). */
+apx_status apx_problem_tile_shapes(const apx_problem* p, int32_t kind, int32_t* counts);
+
+/* Synchronise the stream and return the sticky device flag, then clear it: APX_OK,
+ * APX_E_DOMAIN, APX_E_NONFINITE, or APX_E_HIP when a substitution hand-off wait of the
+ * damped solve ran out (that iteration's step was dropped). */
 apx_status apx_problem_check(apx_problem* p);
 apx_status apx_problem_destroy(apx_problem* p);
 

@@ -29,7 +29,10 @@ EXPORTS = [
     "apx_problem_bind_workspace", "apx_problem_sizes", "apx_problem_check", "apx_problem_destroy",
     "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_render_vjp", "apx_lm_init",
     "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
+    "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_problem_tile_shapes",
 ]
+TILES_AUTOTUNE, TILES_MODEL, TILES_FIXED = 0, 1, 2
+TILE_SHAPES = [(32, 64), (16, 64), (32, 32), (16, 32)]       # output rows x cols per workgroup
 TIME_CLASSES = ["prep", "render", "conv_fwd", "deriv", "conv_jcol", "pairs", "reduce", "solve",
                 "lm", "conv_adj", "grad"]
 
@@ -114,6 +117,9 @@ def load_library(path: str = LIB_PATH):
         "apx_lm_run": ([vp, i32, vp, vp, vp, vp, i32], i32),
         "apx_problem_set_timing": ([vp, i32], i32),
         "apx_problem_timing": ([vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], i32),
+        "apx_ctx_set_tiles": ([vp, i32], i32),
+        "apx_ctx_tile_cost": ([vp, i32, i32, ctypes.POINTER(ctypes.c_double)], i32),
+        "apx_problem_tile_shapes": ([vp, i32, ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -155,7 +161,7 @@ def _descs(spec: Dict):
 class Problem:
     """A model/fit problem bound to one GPU: descriptor, workspace and stream."""
 
-    def __init__(self, spec: Dict, device: int = 0, objective: int = 0):
+    def __init__(self, spec: Dict, device: int = 0, objective: int = 0, tiles: int = TILES_AUTOTUNE):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("apx needs a ROCm GPU; none is visible")
@@ -175,6 +181,7 @@ class Problem:
         self._ctx = ctypes.c_void_p()
         self._check(self.lib.apx_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream),
                                             ctypes.byref(self._ctx)), ctx=False)
+        self._check(self.lib.apx_ctx_set_tiles(self._ctx, int(tiles)))
         idesc, cdesc, sp = _descs(spec)
         sampling = spec["sampling"]
         desc = ProblemDesc(len(spec["images"]), len(spec["comps"]), self.n_par, self.n_sub,
@@ -198,6 +205,19 @@ class Problem:
         for s, (p0, n) in enumerate(spec["subs"]):
             self.par_sub[p0:p0 + n] = s
         self.a_offsets = np.concatenate([[0], np.cumsum([n * n for _, n in spec["subs"]])]).astype(np.int64)
+
+    def tile_shapes(self, kind: int) -> List[int]:
+        """Convolution jobs of kind (0 model, 1 Jacobian columns, 2 adjoint) per tile shape."""
+        counts = (ctypes.c_int32 * 4)()
+        self._check(self.lib.apx_problem_tile_shapes(self._prob, int(kind), counts))
+        return list(counts)
+
+    def tile_cost(self, kernel: int, P: int):
+        """Autotuner's microseconds per tile of each shape, or None if not timed."""
+        us = (ctypes.c_double * 4)()
+        if self.lib.apx_ctx_tile_cost(self._ctx, int(kernel), int(P), us) != APX_OK:
+            return None
+        return list(us)
 
     # ------------------------------------------------------------------ helpers
     def _check(self, status: int, ctx: bool = True):
@@ -384,12 +404,17 @@ class Plan:
     """Host-only view of a problem (device -1): descriptor validation and plan sizes,
     no GPU needed.  Raises ApxError exactly as Problem would for a bad spec."""
 
-    def __init__(self, spec: Dict, objective: int = 0):
+    def __init__(self, spec: Dict, objective: int = 0, tiles: int = TILES_MODEL):
         self.lib = load_library()
         self._ctx = ctypes.c_void_p()
         st = self.lib.apx_ctx_create(-1, None, ctypes.byref(self._ctx))
         if st != APX_OK:
             raise ApxError(st, "host context")
+        st = self.lib.apx_ctx_set_tiles(self._ctx, int(tiles))
+        if st != APX_OK:
+            self.lib.apx_ctx_destroy(self._ctx)
+            self._ctx = None
+            raise ApxError(st, "tile policy")
         idesc, cdesc, sp = _descs(spec)
         sampling = spec["sampling"]
         desc = ProblemDesc(len(spec["images"]), len(spec["comps"]), int(spec["n_par"]), len(spec["subs"]),
@@ -408,6 +433,14 @@ class Plan:
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         self.lib.apx_problem_sizes(self._prob, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
         self.n_pix, self.n_ext, self.n_jac = int(a.value), int(b.value), int(c.value)
+
+    def tile_shapes(self, kind: int) -> List[int]:
+        """Convolution jobs of kind (0 model, 1 Jacobian columns, 2 adjoint) per tile shape."""
+        counts = (ctypes.c_int32 * 4)()
+        st = self.lib.apx_problem_tile_shapes(self._prob, int(kind), counts)
+        if st != APX_OK:
+            raise ApxError(st, "tile shapes")
+        return list(counts)
 
     def close(self):
         if getattr(self, "_prob", None):

@@ -2,6 +2,7 @@
 // (tiles, component lists, Jacobian groups and pair lists, ordered-reduction tables),
 // workspace layout and the launch sequences of the hot-path entry points.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -18,11 +19,15 @@ struct apx_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    int tiles = APX_TILES_AUTOTUNE;                     // tile-shape policy for new problems
+    std::map<int, std::array<double, 4>> tile_us;       // (kernel, P) -> measured us per tile
+    void* tune_mem = nullptr;                           // autotuner scratch (allocated once)
+    size_t tune_bytes = 0;
 };
 
 namespace {
 
-struct PRange { int P, begin, count; };
+struct PRange { int P, shape, begin, count; };
 
 template <class T>
 struct DevArr {
@@ -169,6 +174,145 @@ static void gauss_legendre(int s, std::vector<double>& x, std::vector<double>& w
 }
 
 static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------- tile-shape choice
+// Kernel keys of the cost table: the three convolution epilogues, FWD split by precision.
+enum { TUNE_FWD32 = 0, TUNE_JCOL = 1, TUNE_ADJ = 2, TUNE_FWD64 = 3 };
+
+// Operation-count model of one tile: P^2 FMAs and an epilogue per output, the staged input
+// tile with its halo, and a fixed per-workgroup cost (in FMA-lane units).
+static double tile_model(int P, int shape) {
+    const double th = tile_th(shape), tw = tile_tw(shape);
+    return th * tw * ((double)P * P + 10.0) + 8.0 * (th + P - 1) * (tw + P - 1) + 3000.0;
+}
+
+// The autotuner: time every tile shape of one convolution kernel at PSF size P on a
+// synthetic 256 x 256 job of 32 channels (zero data, so timings do not depend on values),
+// in scratch memory of the context, and keep microseconds per tile (best of 3 timed pairs
+// of launches after 2 warm-up launches).  Synchronous on the context stream.
+static constexpr int TUNE_H = 256, TUNE_CH = 32, TUNE_MAXP = 63;
+static bool tune_kernel(apx_ctx* C, int key, int P, std::array<double, 4>& us) {
+    const int c = (P - 1) / 2, EH = TUNE_H + 2 * c;
+    const int EMAX = TUNE_H + TUNE_MAXP - 1;
+    const long long npx = (long long)TUNE_H * TUNE_H, next = (long long)EMAX * EMAX;
+    const int max_items = ceil_div(EMAX, 16) * ceil_div(EMAX, 32) * TUNE_CH;   // smallest tile, widest output
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+    const size_t o_img = take(sizeof(DImage)), o_job = take(sizeof(ConvJob));
+    const size_t o_items = take(sizeof(ConvItem) * max_items), o_psf = take(sizeof(float) * TUNE_MAXP * TUNE_MAXP);
+    const size_t o_sky = take(sizeof(double)), o_r = take(sizeof(float) * npx), o_w = take(sizeof(float) * npx);
+    const size_t o_d = take(sizeof(float) * npx), o_in = take(sizeof(float) * next * TUNE_CH);
+    const size_t o_in64 = take(sizeof(double) * next), o_out = take(sizeof(float) * (size_t)TUNE_CH * next);
+    const size_t o_part = take(sizeof(double) * 3 * max_items);
+    if (!C->tune_mem) {
+        if (hipMalloc(&C->tune_mem, off) != hipSuccess) { C->tune_mem = nullptr; return false; }
+        C->tune_bytes = off;
+        if (hipMemset(C->tune_mem, 0, off) != hipSuccess) return false;
+    }
+    char* base = (char*)C->tune_mem;
+    hipStream_t st = C->stream;
+    DImage im{};
+    im.H = im.W = TUNE_H; im.P = P; im.c = c; im.EH = im.EW = EH;
+    im.area = 1.0;
+    if (hipMemcpy(base + o_img, &im, sizeof im, hipMemcpyHostToDevice) != hipSuccess) return false;
+    Plan p{};
+    p.n_images = 1;
+    p.images = (const DImage*)(base + o_img);
+    p.psf = (const float*)(base + o_psf);
+    p.psf_flip = (float*)(base + o_psf);
+    p.sky_val = (double*)(base + o_sky);
+    p.rbuf = (float*)(base + o_r);
+    ConvIO io{};
+    io.in = (const float*)(base + o_in);
+    io.in64 = (const double*)(base + o_in64);
+    io.out = (float*)(base + o_out);
+    io.weight = (const float*)(base + o_w);
+    io.part = (double*)(base + o_part);
+    const bool fwd = key == TUNE_FWD32 || key == TUNE_FWD64;
+    if (fwd) { io.data = (const float*)(base + o_d); io.out = nullptr; }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return false;
+    bool ok = true;
+    for (int shape = 0; shape < N_TILE_SHAPES && ok; ++shape) {
+        ConvJob jb{};
+        if (key == TUNE_ADJ) {
+            jb.in_y0 = 0; jb.in_x0 = 0; jb.in_h = TUNE_H; jb.in_w = TUNE_H;
+            jb.out_y0 = -c; jb.out_x0 = -c; jb.out_h = EH; jb.out_w = EH;
+        } else {
+            jb.in_y0 = -c; jb.in_x0 = -c; jb.in_h = EH; jb.in_w = EH;
+            jb.out_y0 = 0; jb.out_x0 = 0; jb.out_h = TUNE_H; jb.out_w = TUNE_H;
+            if (key == TUNE_JCOL) { jb.in_cs = next; jb.out_cs = npx; }
+        }
+        jb.shape = shape;
+        std::vector<ConvItem> items;
+        const int ny = ceil_div(jb.out_h, tile_th(shape)), nx = ceil_div(jb.out_w, tile_tw(shape));
+        for (int ch = 0; ch < TUNE_CH; ++ch)
+            for (int ty = 0; ty < ny; ++ty)
+                for (int tx = 0; tx < nx; ++tx) items.push_back(ConvItem{0, ch, ty, tx});
+        if ((int)items.size() > max_items ||
+            hipMemcpy(base + o_job, &jb, sizeof jb, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(base + o_items, items.data(), sizeof(ConvItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            ok = false;
+            break;
+        }
+        ConvLaunch L{(const ConvJob*)(base + o_job), (const ConvItem*)(base + o_items), 0, (int)items.size(), P, shape};
+        auto launch = [&]() {
+            switch (key) {
+                case TUNE_FWD32: return launch_conv_fwd(p, L, io, st);
+                case TUNE_FWD64: return launch_conv_fwd64(p, L, io, st);
+                case TUNE_JCOL: return launch_conv_jcol(p, L, io, st);
+                default: return launch_conv_adj(p, L, io, st);
+            }
+        };
+        double best = 1e300;
+        for (int rep = 0; rep < 5 && ok; ++rep) {
+            if (rep >= 2) ok = hipEventRecord(e0, st) == hipSuccess;
+            ok = ok && launch() == hipSuccess && launch() == hipSuccess;
+            if (rep >= 2 && ok) {
+                float ms = 0.f;
+                ok = hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                     hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                best = std::min(best, (double)ms * 1e3 / (2.0 * items.size()));
+            }
+        }
+        us[shape] = best;
+    }
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return ok;
+}
+
+// Cost of one tile of each shape for kernel `key` at PSF size P under the context's policy.
+static std::array<double, 4> tile_costs(apx_ctx* C, int key, int P) {
+    std::array<double, 4> cost;
+    if (C->tiles == APX_TILES_AUTOTUNE && C->device >= 0) {
+        const int k = key * 64 + P;
+        auto it = C->tile_us.find(k);
+        if (it != C->tile_us.end()) return it->second;
+        if (tune_kernel(C, key, P, cost)) {
+            C->tile_us[k] = cost;
+            return cost;
+        }
+        (void)hipGetLastError();                        // fall back to the model
+    }
+    for (int s = 0; s < N_TILE_SHAPES; ++s) cost[s] = tile_model(P, s);
+    return cost;
+}
+
+// Tile shape of least estimated cost for an out_h x out_w output (ties: the lower index).
+static int choose_shape(apx_ctx* C, int key, int P, int out_h, int out_w) {
+    if (C->tiles >= APX_TILES_FIXED && C->tiles < APX_TILES_FIXED + N_TILE_SHAPES) return C->tiles - APX_TILES_FIXED;
+    if (out_h <= 0 || out_w <= 0) return 0;
+    const std::array<double, 4> cost = tile_costs(C, key, P);
+    int best = 0;
+    double bc = 1e300;
+    for (int s = 0; s < N_TILE_SHAPES; ++s) {
+        const double v = (double)ceil_div(out_h, tile_th(s)) * ceil_div(out_w, tile_tw(s)) * cost[s];
+        if (v < bc) { bc = v; best = s; }
+    }
+    return best;
+}
 
 // Regularised lower incomplete gamma P(a, x) by its power series (x < a + 1 here).
 static double gammainc_lower_series_host(double a, double x) {
@@ -512,17 +656,24 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     const int n_cols = (int)P->cols.size();
     const int n_groups = (int)P->groups.size();
 
-    // convolution jobs and items (sorted by PSF size: one launch per size)
-    auto add_items = [](std::vector<ConvJob>& jobs, std::vector<ConvItem>& items,
-                        std::vector<PRange>& ranges, const std::vector<int>& jobP,
-                        const std::vector<int>& nch, std::vector<int>* job_item_begin) {
+    // convolution jobs and items, sorted by (PSF size, tile shape): one launch per pair.
+    // Each job takes the tile shape of least estimated cost (choose_shape).
+    auto add_items = [&](int kind, std::vector<ConvJob>& jobs, std::vector<ConvItem>& items,
+                         std::vector<PRange>& ranges, const std::vector<int>& jobP,
+                         const std::vector<int>& nch, std::vector<int>* job_item_begin) {
+        const int key = kind == CONV_JCOL ? TUNE_JCOL : kind == CONV_ADJ ? TUNE_ADJ
+                      : P->objective == APX_OBJECTIVE_FP64 ? TUNE_FWD64 : TUNE_FWD32;
+        for (size_t j = 0; j < jobs.size(); ++j)
+            jobs[j].shape = choose_shape(C, key, jobP[j], jobs[j].out_h, jobs[j].out_w);
         std::vector<int> order(jobs.size());
         for (size_t i = 0; i < jobs.size(); ++i) order[i] = (int)i;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobP[a] < jobP[b]; });
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return jobP[a] != jobP[b] ? jobP[a] < jobP[b] : jobs[a].shape < jobs[b].shape;
+        });
         if (job_item_begin) job_item_begin->assign(jobs.size(), 0);
         for (int j : order) {
             const ConvJob& jb = jobs[j];
-            const int ny = ceil_div(jb.out_h, CV_TH), nx = ceil_div(jb.out_w, CV_TW);
+            const int ny = ceil_div(jb.out_h, tile_th(jb.shape)), nx = ceil_div(jb.out_w, tile_tw(jb.shape));
             if (job_item_begin) (*job_item_begin)[j] = (int)items.size();
             const int b = (int)items.size();
             for (int ch = 0; ch < nch[j]; ++ch)
@@ -530,9 +681,14 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
                     for (int tx = 0; tx < nx; ++tx) items.push_back(ConvItem{j, ch, ty, tx});
             const int cnt = (int)items.size() - b;
             if (cnt == 0) continue;
-            if (!ranges.empty() && ranges.back().P == jobP[j]) ranges.back().count += cnt;
-            else ranges.push_back(PRange{jobP[j], b, cnt});
+            if (!ranges.empty() && ranges.back().P == jobP[j] && ranges.back().shape == jb.shape)
+                ranges.back().count += cnt;
+            else
+                ranges.push_back(PRange{jobP[j], jb.shape, b, cnt});
         }
+    };
+    auto job_tiles = [](const ConvJob& jb) {
+        return ceil_div(jb.out_h, tile_th(jb.shape)) * ceil_div(jb.out_w, tile_tw(jb.shape));
     };
     std::vector<int> fwd_item_begin, jcol_item_begin;
     {
@@ -556,8 +712,8 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             ja.out_y0 = -im.c; ja.out_x0 = -im.c; ja.out_h = im.EH; ja.out_w = im.EW;
             P->adj_jobs.push_back(ja);
         }
-        add_items(P->fwd_jobs, P->fwd_items, P->fwd_ranges, jp, nch, &fwd_item_begin);
-        add_items(P->adj_jobs, P->adj_items, P->adj_ranges, jp, nch, nullptr);
+        add_items(CONV_FWD, P->fwd_jobs, P->fwd_items, P->fwd_ranges, jp, nch, &fwd_item_begin);
+        add_items(CONV_ADJ, P->adj_jobs, P->adj_items, P->adj_ranges, jp, nch, nullptr);
     }
     {
         std::vector<int> jp, nch;
@@ -577,7 +733,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             jp.push_back(im.P);
             nch.push_back(gr.oh > 0 && gr.ow > 0 ? gr.ncols : 0);
         }
-        add_items(P->jcol_jobs, P->jcol_items, P->jcol_ranges, jp, nch, &jcol_item_begin);
+        add_items(CONV_JCOL, P->jcol_jobs, P->jcol_items, P->jcol_ranges, jp, nch, &jcol_item_begin);
     }
 
     // reduction tables: FWD items per image, JCOL items per column, grad partials per column
@@ -585,7 +741,8 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         P->img_seg.assign(1, 0);
         for (int k = 0; k < d->n_images; ++k) {
             const DImage& im = P->images[k];
-            const int n = ceil_div(im.H, CV_TH) * ceil_div(im.W, CV_TW);
+            (void)im;
+            const int n = job_tiles(P->fwd_jobs[k]);
             for (int q = 0; q < n; ++q) P->img_idx.push_back(fwd_item_begin[k] + q);
             P->img_seg.push_back((int)P->img_idx.size());
         }
@@ -593,7 +750,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         P->gcol_seg.assign(1, 0);
         for (int g = 0; g < n_groups; ++g) {
             const DGroup& gr = P->groups[g];
-            const int per = (gr.oh > 0 && gr.ow > 0) ? ceil_div(gr.oh, CV_TH) * ceil_div(gr.ow, CV_TW) : 0;
+            const int per = (gr.oh > 0 && gr.ow > 0) ? job_tiles(P->jcol_jobs[g]) : 0;
             for (int ch = 0; ch < gr.ncols; ++ch) {
                 for (int q = 0; q < per; ++q) P->col_idx.push_back(jcol_item_begin[g] + ch * per + q);
                 P->col_seg.push_back((int)P->col_idx.size());
@@ -915,7 +1072,25 @@ apx_status apx_ctx_set_stream(apx_ctx* ctx, void* hip_stream) {
 }
 
 apx_status apx_ctx_destroy(apx_ctx* ctx) {
+    if (ctx && ctx->tune_mem) (void)hipFree(ctx->tune_mem);
     delete ctx;
+    return APX_OK;
+}
+
+apx_status apx_ctx_set_tiles(apx_ctx* ctx, int32_t policy) {
+    if (!ctx) return APX_E_INVALID;
+    if (policy != APX_TILES_AUTOTUNE && policy != APX_TILES_MODEL &&
+        !(policy >= APX_TILES_FIXED && policy < APX_TILES_FIXED + N_TILE_SHAPES))
+        return fail(ctx, APX_E_INVALID, "unknown tile policy");
+    ctx->tiles = policy;
+    return APX_OK;
+}
+
+apx_status apx_ctx_tile_cost(const apx_ctx* ctx, int32_t kernel, int32_t P, double* us) {
+    if (!ctx || !us || kernel < 0 || kernel > 3) return APX_E_INVALID;
+    auto it = ctx->tile_us.find(kernel * 64 + P);
+    if (it == ctx->tile_us.end()) return APX_E_INVALID;
+    for (int s = 0; s < N_TILE_SHAPES; ++s) us[s] = it->second[s];
     return APX_OK;
 }
 
@@ -1079,6 +1254,15 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     return APX_OK;
 }
 
+apx_status apx_problem_tile_shapes(const apx_problem* P, int32_t kind, int32_t* counts) {
+    if (!P || !counts || kind < 0 || kind > 2) return APX_E_INVALID;
+    const std::vector<ConvJob>& jobs = kind == 0 ? P->fwd_jobs : kind == 1 ? P->jcol_jobs : P->adj_jobs;
+    for (int s = 0; s < N_TILE_SHAPES; ++s) counts[s] = 0;
+    for (const ConvJob& jb : jobs)
+        if (jb.out_h > 0 && jb.out_w > 0) counts[jb.shape] += 1;
+    return APX_OK;
+}
+
 apx_status apx_problem_check(apx_problem* P) {
     if (!P || !P->bound) return APX_E_WORKSPACE;
     int flags = 0;
@@ -1141,7 +1325,7 @@ static apx_status run_conv(apx_problem* P, int kind, const ConvIO& io) {
     const int klass = kind == CONV_FWD ? APX_TIME_CONV_FWD : kind == CONV_JCOL ? APX_TIME_CONV_JCOL : APX_TIME_CONV_ADJ;
     for (const PRange& r : *ranges) {
         TimeScope ts(P, klass);
-        ConvLaunch L{wsp<ConvJob>(P, jn), wsp<ConvItem>(P, inn), r.begin, r.count, r.P};
+        ConvLaunch L{wsp<ConvJob>(P, jn), wsp<ConvItem>(P, inn), r.begin, r.count, r.P, r.shape};
         hipError_t e = kind == CONV_FWD ? (P->objective == APX_OBJECTIVE_FP64 ? launch_conv_fwd64(p, L, io, st)
                                                                                : launch_conv_fwd(p, L, io, st))
                      : kind == CONV_JCOL ? launch_conv_jcol(p, L, io, st)

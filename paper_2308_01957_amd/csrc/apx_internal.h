@@ -11,7 +11,12 @@ namespace apx {
 
 // Tile shapes --------------------------------------------------------------------
 constexpr int RT_Y = 8, RT_X = 32;            // render / derivative / gradient tiles (256 px)
-constexpr int CV_TH = 32, CV_TW = 64;         // convolution output tile per workgroup
+// Convolution output tiles a workgroup can own (rows x cols).  Every lane computes CV_R
+// consecutive outputs of one row, so shape s runs tile_th(s) * tile_tw(s) / CV_R threads.
+// The tile shape of each convolution job is chosen per job (apx_ctx_set_tiles).
+constexpr int N_TILE_SHAPES = 4;
+__host__ __device__ constexpr int tile_th(int s) { return (s & 1) ? 16 : 32; }
+__host__ __device__ constexpr int tile_tw(int s) { return s < 2 ? 64 : 32; }
 constexpr int CV_R = 8;                       // consecutive outputs per lane (register window)
 constexpr int PAIR_KC = 32;                   // pixels per LDS stage of the J^T W J kernel
 constexpr int CHOL_NB = 64;                   // block size of the blocked Cholesky
@@ -93,7 +98,7 @@ struct ConvJob {
     long long in_cs, out_cs;                  // channel strides
     int in_y0, in_x0, in_h, in_w;             // input rectangle (zero outside)
     int out_y0, out_x0, out_h, out_w;         // output rectangle
-    int image, group, ntx, pad;
+    int image, group, ntx, shape;             // shape: output tile shape (tile_th/tile_tw)
 };
 struct ConvItem { int job, ch, ty, tx; };
 
@@ -190,7 +195,7 @@ enum ConvKind { CONV_FWD = 0, CONV_JCOL = 1, CONV_ADJ = 2 };
 struct ConvLaunch {
     const ConvJob* jobs;
     const ConvItem* items;
-    int item_begin, item_count, P;
+    int item_begin, item_count, P, shape;
 };
 struct ConvIO {
     const float* in;          // input buffer base (FWD, JCOL)

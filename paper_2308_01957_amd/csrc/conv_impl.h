@@ -2,7 +2,7 @@
 //
 // out(y, x) = sum_{U,V} K[U][V] * in(y - U + c, x - V + c), in = 0 outside its rectangle.
 //
-// One workgroup (4 wave64s) owns a CV_TH x CV_TW output tile.  The input tile with its
+// One workgroup owns a TH x TW output tile (TH * TW / CV_R threads).  The input tile with its
 // (P-1) halo is staged once into LDS; each lane then produces CV_R consecutive outputs
 // of one row: per PSF row it loads a CV_R + P - 1 register window from LDS (ds_read_b128)
 // and runs P x CV_R FMAs whose PSF operand is wave-uniform (scalar loads), so the VALU
@@ -28,16 +28,20 @@ __device__ __forceinline__ double conv_wave_sum(double v) {
 
 // T is the arithmetic type of the staged input and the accumulators: float for the
 // Jacobian and adjoint passes, double for the FP64 objective.
-template <int P, int KIND, typename T = float>
-__global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict__ jobs,
-                                              const ConvItem* __restrict__ items, int item_begin,
-                                              ConvIO io) {
+template <int P, int KIND, typename T, int TH, int TW>
+__global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* __restrict__ jobs,
+                                                         const ConvItem* __restrict__ items, int item_begin,
+                                                         ConvIO io) {
     constexpr int c = (P - 1) / 2;
-    constexpr int LH = CV_TH + P - 1;
-    constexpr int LW0 = CV_TW + P - 1;
+    constexpr int NT = TH * TW / CV_R;              // threads
+    constexpr int LPR = TW / CV_R;                  // lanes per output row
+    constexpr int NW = NT / 64;                     // waves
+    static_assert(NW >= 1 && NT % 64 == 0, "whole waves");
+    constexpr int LH = TH + P - 1;
+    constexpr int LW0 = TW + P - 1;
     constexpr int LW = (LW0 + 3) & ~3;
     __shared__ __attribute__((aligned(16))) T tile[LH * LW];
-    __shared__ double red[4][3];
+    __shared__ double red[NW][3];
 
     const int item_idx = item_begin + (int)blockIdx.x;
     const ConvItem it = items[item_idx];
@@ -48,18 +52,18 @@ __global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict_
     } else if (io.skip_mode == 2) {
         if (io.lm[im.sub].need_jac == 0) return;
     }
-    const int oy0 = jb.out_y0 + it.ty * CV_TH;
-    const int ox0 = jb.out_x0 + it.tx * CV_TW;
+    const int oy0 = jb.out_y0 + it.ty * TH;
+    const int ox0 = jb.out_x0 + it.tx * TW;
     const int iy_base = oy0 - c, ix_base = ox0 - c;
 
     // ---- stage the input tile (zero outside the input rectangle); every load of a thread
     // is issued before its LDS stores so the latencies overlap
-    constexpr int NE = (LH * LW0 + 255) / 256;
+    constexpr int NE = (LH * LW0 + NT - 1) / NT;
     T v[NE];
     if constexpr (KIND == CONV_ADJ) {
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
-            const int e = threadIdx.x + 256 * q;
+            const int e = threadIdx.x + NT * q;
             const int ly = e / LW0, lx = e - ly * LW0;
             const int y = iy_base + ly, x = ix_base + lx;
             T val = 0;
@@ -76,7 +80,7 @@ __global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict_
         const int iy1 = jb.in_y0 + jb.in_h, ix1 = jb.in_x0 + jb.in_w;
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
-            const int e = threadIdx.x + 256 * q;
+            const int e = threadIdx.x + NT * q;
             const int ly = e / LW0, lx = e - ly * LW0;
             const int y = iy_base + ly, x = ix_base + lx;
             T val = 0;
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict_
     }
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
-        const int e = threadIdx.x + 256 * q;
+        const int e = threadIdx.x + NT * q;
         if (e < LH * LW0) {
             const int ly = e / LW0, lx = e - ly * LW0;
             tile[ly * LW + lx] = v[q];
@@ -96,7 +100,7 @@ __global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict_
     __syncthreads();
 
     // ---- register-window convolution
-    const int ty = (int)threadIdx.x >> 3, tx = (int)threadIdx.x & 7;
+    const int ty = (int)threadIdx.x / LPR, tx = (int)threadIdx.x % LPR;
     const float* __restrict__ K = (KIND == CONV_ADJ ? p.psf_flip : p.psf) + im.psf_off;
     T acc[CV_R];
 #pragma unroll
@@ -156,7 +160,10 @@ __global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict_
             __syncthreads();
             if (threadIdx.x < 3) {
                 const int q = threadIdx.x;
-                io.part[(long long)item_idx * 3 + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+                double sum = red[0][q];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) sum += red[w][q];
+                io.part[(long long)item_idx * 3 + q] = sum;
             }
         }
     } else if constexpr (KIND == CONV_JCOL) {
@@ -185,7 +192,10 @@ __global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict_
             __syncthreads();
             if (threadIdx.x < 2) {
                 const int q = threadIdx.x;
-                io.part[(long long)item_idx * 2 + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+                double sum = red[0][q];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) sum += red[w][q];
+                io.part[(long long)item_idx * 2 + q] = sum;
             }
         }
     } else {
@@ -206,15 +216,14 @@ __global__ __launch_bounds__(256) void k_conv(Plan p, const ConvJob* __restrict_
     X(31) X(33) X(35) X(37) X(39) X(41) X(43) X(45) X(47) X(49) X(51) X(53) X(55) X(57)      \
     X(59) X(61) X(63)
 
-template <int KIND, typename T = float>
-hipError_t launch_conv_kind(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st) {
-    if (L.item_count <= 0) return hipSuccess;
-    dim3 grid(L.item_count), block(256);
+template <int KIND, typename T, int TH, int TW>
+hipError_t launch_conv_shape(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st) {
+    dim3 grid(L.item_count), block(TH * TW / CV_R);
     switch (L.P) {
 #define APX_CASE(PP)                                                                         \
     case PP:                                                                                 \
-        hipLaunchKernelGGL((k_conv<PP, KIND, T>), grid, block, 0, st, p, L.jobs, L.items,    \
-                           L.item_begin, io);                                               \
+        hipLaunchKernelGGL((k_conv<PP, KIND, T, TH, TW>), grid, block, 0, st, p, L.jobs,     \
+                           L.items, L.item_begin, io);                                      \
         break;
         APX_FOR_EACH_P(APX_CASE)
 #undef APX_CASE
@@ -222,6 +231,19 @@ hipError_t launch_conv_kind(const Plan& p, const ConvLaunch& L, const ConvIO& io
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int KIND, typename T = float>
+hipError_t launch_conv_kind(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st) {
+    if (L.item_count <= 0) return hipSuccess;
+    static_assert(N_TILE_SHAPES == 4, "one case per tile shape");
+    switch (L.shape) {
+        case 0: return launch_conv_shape<KIND, T, tile_th(0), tile_tw(0)>(p, L, io, st);
+        case 1: return launch_conv_shape<KIND, T, tile_th(1), tile_tw(1)>(p, L, io, st);
+        case 2: return launch_conv_shape<KIND, T, tile_th(2), tile_tw(2)>(p, L, io, st);
+        case 3: return launch_conv_shape<KIND, T, tile_th(3), tile_tw(3)>(p, L, io, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace apx

@@ -37,9 +37,9 @@ def get(name):
     return _CACHE[name]
 
 
-def problem(apx, spec):
-    print(f"[case] {spec['name']}", flush=True)
-    P = apx.Problem(spec)
+def problem(apx, spec, tiles=None):
+    print(f"[case] {spec['name']} tiles={tiles}", flush=True)
+    P = apx.Problem(spec) if tiles is None else apx.Problem(spec, tiles=tiles)
     d = P.pixels(spec["data"])
     w = P.pixels(spec["weight"])
     return P, d, w
@@ -158,6 +158,47 @@ def test_render_autograd_backward_is_the_vjp(apx):
     (m.double() * seed.double()).sum().backward()
     ref = P.render_vjp(th.detach(), seed)
     assert torch.equal(th.grad, ref)
+
+
+@pytest.mark.parametrize("shape", range(4))
+@pytest.mark.parametrize("name", ["small_blend", "affine_pair"])
+def test_every_tile_shape_keeps_parity(apx, name, shape):
+    """Each of the four convolution tile shapes, forced for every job, gives the oracle's
+    model, chi^2, Jacobian and gradient (ragged 75 x 93 and rotated 70 x 66 images)."""
+    spec = get(name)
+    P, d, w = problem(apx, spec, tiles=apx.TILES_FIXED + shape)
+    assert P.tile_shapes(1)[shape] == sum(P.tile_shapes(1)) > 0
+    th = spec["theta_init"]
+    m = P.split(P.render(th))
+    ks = range(len(spec["images"]))
+    for k in ks:
+        mo = oracle.model_image(spec, th, k)
+        assert np.all(np.abs(m[k].astype(np.float64) - mo) <= cases.tol_pixels(mo)), k
+    c2 = P.chi2(th, d, w).cpu().numpy()
+    c2o = oracle.chi2(spec, th, spec["data"], spec["weight"])
+    assert np.allclose(c2, c2o, rtol=1e-5)
+    J = P.jacobian(th).cpu().numpy().T.astype(np.float64)
+    Jo = oracle.jacobian(spec, th)
+    assert np.all(np.abs(J - Jo) <= 3e-5 * np.maximum(np.max(np.abs(Jo), axis=0), 1e-30))
+    g, _ = P.chi2_grad(th, d, w)
+    go = oracle.chi2_grad(spec, th, spec["data"], spec["weight"])
+    r, wv = oracle.residual(spec, th, spec["data"], spec["weight"], ks)
+    tol = 1e-4 * np.maximum(np.abs(go), 2.0 * (np.abs(wv * r) @ np.abs(Jo)))
+    assert np.all(np.abs(g.cpu().numpy() - go) <= tol)
+    P.check()
+
+
+def test_autotuner_times_every_shape(apx):
+    """The default policy times the four shapes of each convolution kernel the problem
+    needs and the planner's choice is the cheapest estimate for each job."""
+    spec = get("few_cutouts")
+    P, _, _ = problem(apx, spec)
+    Ps = sorted({int(im["psf"].shape[0]) for im in spec["images"]})
+    for Pk in Ps:
+        for kernel in (1, 3):                   # Jacobian columns, FP64 model
+            us = P.tile_cost(kernel, Pk)
+            assert us is not None and all(u > 0 and math.isfinite(u) for u in us), (kernel, Pk)
+    assert sum(P.tile_shapes(1)) >= 1
 
 
 def _lm_run(apx, spec, n_iter, use_graph=False):

@@ -74,3 +74,31 @@ def test_full_scale_plans(apx):
         p = apx.Plan(f())
         assert p.n_jac > 0 and p.workspace_bytes > 0
         p.close()
+
+
+@pytest.mark.parametrize("shape", range(4))
+def test_fixed_tile_policy_gives_every_job_that_shape(apx, shape):
+    spec = _small()
+    pl = apx.Plan(spec, tiles=apx.TILES_FIXED + shape)
+    for kind in range(3):
+        counts = pl.tile_shapes(kind)
+        assert sum(counts) > 0 and counts[shape] == sum(counts)
+    pl.close()
+
+
+def test_model_tile_policy_prefers_tiles_that_fit_the_output(apx):
+    """The operation-count model keeps 32 x 64 tiles on a 512 x 512 image and takes
+    narrower tiles where they cut the padding of a 40-pixel-wide window."""
+    big = synth.single(1, H=512, W=512, P=11)
+    pl = apx.Plan(big, tiles=apx.TILES_MODEL)
+    assert pl.tile_shapes(0) == [1, 0, 0, 0]
+    pl.close()
+    small = synth.single(1, H=40, W=40, P=11)
+    pl = apx.Plan(small, tiles=apx.TILES_MODEL)
+    assert pl.tile_shapes(0)[0] == 0
+    pl.close()
+
+
+def test_unknown_tile_policy_is_rejected(apx):
+    with pytest.raises(apx.ApxError):
+        apx.Plan(_small(), tiles=99)
