@@ -174,6 +174,7 @@ def run_cutouts(args, torch, apx, synth):
         "plain_cutout_it_per_s": plain, "speedup_batched_vs_plain": batched / plain,
         "plain_sample_cutouts": len(sample), "steps": args.steps, "n_gpus": 1,
         "mpix_per_s": mpix, "accepted_mean": float(np.mean(stt["n_accept"])),
+        "tile_shapes": tile_choice(prob),
         "config": {"workload": "4096 cutouts, side 32-256 px log-uniform, 1-5 Sersic + sky each, "
                                "Gaussian/Moffat PSF 15-31 px, 3x3 nodes",
                    "n_sub": n_sub, "n_par": spec["n_par"], "n_pix": prob.n_pix,
@@ -234,6 +235,7 @@ def run_field(args, torch, apx, synth):
         "roofline": {"bound": "alu", "kernel": f"k_conv<{P_psf},ADJ>", "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS},
         "kernel_ms_per_eval": {k: round(v[0] / reps, 4) for k, v in kt.items()},
+        "tile_shapes": tile_choice(prob),
         "config": {"workload": "2048x2048 field, 500 Sersic (10 Re windows) + sky, Moffat 51x51 beta 3 "
                                "FWHM 4, 3x3 nodes", "n_par": spec["n_par"], "n_pix": prob.n_pix},
         "dtype": "f32 adjoint / f64 objective", "data": "synthetic"})
@@ -263,6 +265,7 @@ def run_lm_workload(args, torch, apx, synth, spec, label, desc):
         "n_gpus": 1, "steps": args.steps, "mpix_per_s": _mpix(prob, spec, torch, 10),
         "accepted": int(stt["n_accept"][0]),
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
+        "tile_shapes": tile_choice(prob),
         "config": {"workload": desc, "n_par": spec["n_par"], "n_pix": prob.n_pix},
         "dtype": "f32 Jacobian / f64 objective+normal equations", "data": "synthetic"})
     return 0
@@ -281,6 +284,17 @@ def run_single(args, torch, apx, synth):
 
 OTHER_WORKLOADS = {"cutouts": run_cutouts, "field": run_field, "multiband": run_multiband,
                    "single": run_single}
+
+
+def tile_choice(prob):
+    """Convolution jobs per tile shape (rows x cols) as the autotuner chose them."""
+    names = ["%dx%d" % t for t in prob_tile_shapes()]
+    return {kind: dict(zip(names, prob.tile_shapes(k))) for k, kind in enumerate(["model", "jacobian", "adjoint"])}
+
+
+def prob_tile_shapes():
+    from paper_2308_01957_amd import apx
+    return apx.TILE_SHAPES
 
 
 def counted_traffic(kernel):
@@ -418,6 +432,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 Jacobian / f64 objective+normal equations",
         "data": "synthetic (seeded; noise-free model rendered by the library, Gaussian noise)",
+        "tile_shapes": tile_choice(prob),
         "config": {"workload": "blended field 512x512: 50 Sersic + 200 point sources + sky, "
                                "Moffat 25x25 beta 2.5 FWHM 3, 3x3 nodes within 2 Re, 551 params",
                    "n_par": spec["n_par"], "n_pix": prob.n_pix, "psf": P_psf,
