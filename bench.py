@@ -173,7 +173,8 @@ def run_cutouts(args, torch, apx, synth):
         "eager_batch_it_per_s": args.steps / t_eager, "graph_equals_eager": same,
         "plain_cutout_it_per_s": plain, "speedup_batched_vs_plain": batched / plain,
         "plain_sample_cutouts": len(sample), "steps": args.steps, "n_gpus": 1,
-        "mpix_per_s": mpix, "accepted_mean": float(np.mean(stt["n_accept"])),
+        "mpix_per_s": mpix,
+        "covariance_ms": cov_ms, "accepted_mean": float(np.mean(stt["n_accept"])),
         "tile_shapes": tile_choice(prob),
         "config": {"workload": "4096 cutouts, side 32-256 px log-uniform, 1-5 Sersic + sky each, "
                                "Gaussian/Moffat PSF 15-31 px, 3x3 nodes",
@@ -405,6 +406,13 @@ def main():
     jcol_ms, jcol_launches = kt["conv_jcol"]
     avg_ms = jcol_ms / max(1, j_phases)
     achieved = flop_per_phase / (avg_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
+
+    # parameter covariance at the last iterate: (J^T W J)^-1 of the 551-parameter system
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.covariance(th, dd, ww)
+    torch.cuda.synchronize()
+    cov_ms = (time.perf_counter() - t0) * 1e3
 
     # rendered Mpix/s: objective-path model (FP64 render + convolution) at the truth
     prob.set_timing(False)

@@ -266,6 +266,17 @@ apx_status apx_jtwj(apx_problem* p, const double* theta, const float* data,
 apx_status apx_chi2_grad(apx_problem* p, const double* theta, const float* data,
                          const float* weight, double* grad, double* chi2);
 
+/* Parameter covariance at theta (§2.5: the inverse of the Hessian the LM approximates
+ * gives the uncertainties and the full covariance of the parameters): for each
+ * sub-problem s, cov_s = (J^T W J)^{-1} in FP64, an n_s x n_s row-major block at offset
+ * sum_{t<s} n_t^2 (the layout of apx_jtwj's JtWJ); also chi2[n_sub].  J^T W J is formed
+ * as in apx_jtwj, factored by Cholesky without damping and inverted column block by
+ * column block.  For chi^2 = sum w r^2 this is the usual 1-sigma covariance (the inverse
+ * of half the chi^2 Hessian).  A block whose J^T W J is not positive definite is filled
+ * with NaN.  cov: device FP64, overwritten; asynchronous on the context stream. */
+apx_status apx_covariance(apx_problem* p, const double* theta, const float* data,
+                          const float* weight, double* cov, double* chi2);
+
 /* Vector-Jacobian product of the render (the reverse pass of the model of §2.3, the
  * same adjoint as apx_chi2_grad with the caller's seed in place of -2 w r):
  * grad_theta[k] = sum_i grad_model[i] * d model_i / d theta_k, i over every output pixel

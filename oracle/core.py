@@ -375,6 +375,14 @@ def chi2_grad(spec, theta, data, weight) -> np.ndarray:
     return grad
 
 
+def covariance(spec, theta, data, weight, sub: int = 0) -> np.ndarray:
+    """Parameter covariance of one sub-problem: the inverse of the Gauss-Newton Hessian
+    J^T W J (section 2.5: the inverse of the Hessian the LM approximates gives the
+    uncertainties and the full covariance of the parameters)."""
+    A, _, _ = jtwj(spec, theta, data, weight, sub)
+    return np.linalg.inv(A)
+
+
 # ------------------------------------------------------------ Levenberg-Marquardt
 def in_domain(spec, theta, sub: int) -> bool:
     for comp in spec["comps"]:

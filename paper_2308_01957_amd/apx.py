@@ -29,7 +29,7 @@ EXPORTS = [
     "apx_problem_bind_workspace", "apx_problem_sizes", "apx_problem_check", "apx_problem_destroy",
     "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_render_vjp", "apx_lm_init",
     "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
-    "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_problem_tile_shapes",
+    "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_problem_tile_shapes", "apx_covariance",
 ]
 TILES_AUTOTUNE, TILES_MODEL, TILES_FIXED = 0, 1, 2
 TILE_SHAPES = [(32, 64), (16, 64), (32, 32), (16, 32)]       # output rows x cols per workgroup
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
         "apx_jtwj": ([vp, vp, vp, vp, vp, vp, vp], i32),
         "apx_chi2_grad": ([vp, vp, vp, vp, vp, vp], i32),
         "apx_render_vjp": ([vp, vp, vp, vp], i32),
+        "apx_covariance": ([vp, vp, vp, vp, vp, vp], i32),
         "apx_lm_init": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_step": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_run": ([vp, i32, vp, vp, vp, vp, i32], i32),
@@ -308,6 +309,19 @@ class Problem:
     def block(self, A, s: int):
         n = self.spec["subs"][s][1]
         return A[int(self.a_offsets[s]):int(self.a_offsets[s + 1])].reshape(n, n)
+
+    def covariance(self, theta, data, weight):
+        """((J^T W J)^{-1} flat per-sub blocks, chi2 [n_sub]), FP64 device tensors."""
+        th = self._dev(theta, self.torch.float64)
+        self._enter(th, data, weight)
+        t = self.torch
+        with t.cuda.stream(self.stream):
+            C = t.empty(max(1, int(self.a_offsets[-1])), dtype=t.float64, device=self.device)
+            c2 = t.empty(self.n_sub, dtype=t.float64, device=self.device)
+            self._check(self.lib.apx_covariance(self._prob, th.data_ptr(), data.data_ptr(), weight.data_ptr(),
+                                                C.data_ptr(), c2.data_ptr()))
+        self._leave()
+        return C, c2
 
     def render_vjp(self, theta, grad_model, out=None):
         """sum_i grad_model[i] d model_i / d theta (FP64 [n_par]) by the adjoint pass."""

@@ -1525,6 +1525,31 @@ apx_status apx_jtwj(apx_problem* P, const double* theta, const float* data, cons
     return APX_OK;
 }
 
+apx_status apx_covariance(apx_problem* P, const double* theta, const float* data, const float* weight,
+                          double* cov, double* chi2) {
+    APXCHK(ready(P));
+    if (!par_ok(P, theta) || !data || !weight || !par_ok(P, cov) || !chi2)
+        return fail(P->ctx, APX_E_INVALID, "null pointer");
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
+    APXCHK(jac_blocks(P, weight, nullptr));
+    APXCHK(normal_eq(P, weight, p.A, p.gvec, nullptr));
+    {
+        TimeScope ts(P, APX_TIME_SOLVE);
+        HIPCHK(launch_cov_small(p, wsp<int>(P, "small_subs"), (int)P->small_subs.size(), P->nmax_small, cov, st));
+        for (int s : P->large_subs) {
+            const int n = P->subs[s].n;
+            HIPCHK(launch_chol_reset(p, s, st));
+            HIPCHK(launch_cov_fill(p, s, n, st));
+            HIPCHK(launch_chol_blocks(p, s, n, st));
+            HIPCHK(launch_cov_cols(p, s, n, cov, st));
+        }
+    }
+    HIPCHK(launch_chi2_check(chi2, P->n_sub, p.sticky, st));
+    return APX_OK;
+}
+
 apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data, const float* weight,
                          double* grad, double* chi2) {
     APXCHK(ready(P));

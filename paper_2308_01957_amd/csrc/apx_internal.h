@@ -248,8 +248,16 @@ hipError_t launch_lm_init(const Plan& p, const double* chi2_sub, apx_lm_state* l
 hipError_t launch_chol_small(const Plan& p, const int* small_subs, int n_small, int nmax,
                              apx_lm_state* lm, hipStream_t st);
 hipError_t launch_chol_large(const Plan& p, int sub, int n, apx_lm_state* lm, hipStream_t st);
+hipError_t launch_chol_reset(const Plan& p, int sub, hipStream_t st);
+hipError_t launch_chol_blocks(const Plan& p, int sub, int n, hipStream_t st);
 hipError_t launch_lm_trial(const Plan& p, const double* theta, apx_lm_state* lm, hipStream_t st);
 hipError_t launch_lm_accept(const Plan& p, const double* chi2_trial, double* theta,
                             apx_lm_state* lm, hipStream_t st);
+
+// k_cov.hip
+hipError_t launch_cov_small(const Plan& p, const int* small_subs, int n_small, int nmax, double* cov,
+                            hipStream_t st);
+hipError_t launch_cov_fill(const Plan& p, int sub, int n, hipStream_t st);
+hipError_t launch_cov_cols(const Plan& p, int sub, int n, double* cov, hipStream_t st);
 
 }  // namespace apx

@@ -659,6 +659,24 @@ __global__ __launch_bounds__(256) void k_subst_finish(Plan p, int s, apx_lm_stat
     }
 }
 
+// For the covariance: clear the factorisation flags of sub-problem s, and factor its M
+// (filled by the caller) with the blocked kernels, no damping and no retry; a failed pivot
+// leaves lmf[s].chol_fail set.
+hipError_t launch_chol_reset(const Plan& p, int s, hipStream_t st) {
+    hipLaunchKernelGGL(k_chol_damp, dim3(1), dim3(256), 0, st, p, s, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_blocks(const Plan& p, int s, int n, hipStream_t st) {
+    const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
+    for (int k = 0; k < nblk; ++k) {
+        hipLaunchKernelGGL(k_chol_panel, dim3(nblk - k), dim3(256), 0, st, p, s, k);
+        const int T = nblk - k - 1;
+        if (T > 0) hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipStream_t st) {
     const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
     hipLaunchKernelGGL(k_chol_damp, dim3(1), dim3(256), 0, st, p, s, lm);

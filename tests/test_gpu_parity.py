@@ -201,6 +201,50 @@ def test_autotuner_times_every_shape(apx):
     assert sum(P.tile_shapes(1)) >= 1
 
 
+@pytest.mark.parametrize("name", ["single64", "few_cutouts", "grid_large_sub", "large_sub"])
+def test_covariance_parity(apx, name):
+    """apx_covariance against the oracle's inverse of J^T W J per sub-problem (one-wave and
+    blocked paths).  Tolerance from first-order perturbation of the inverse: with the GPU's
+    J^T W J within eps sqrt(A_kk A_ll) of the oracle's, |d C| <= |C| E |C| (E_kl = eps
+    sqrt(A_kk A_ll)), eps = 2e-5 (FP32 Jacobian entries)."""
+    spec = get(name)
+    P, d, w = problem(apx, spec)
+    th = spec["theta_init"]
+    C, _ = P.covariance(th, d, w)
+    C = C.cpu().numpy()
+    P.check()
+    for s, (p0, n) in enumerate(spec["subs"]):
+        A, _, _ = oracle.jtwj(spec, th, spec["data"], spec["weight"], s)
+        Co = np.linalg.inv(A)
+        Cg = C[int(P.a_offsets[s]):int(P.a_offsets[s + 1])].reshape(n, n)
+        sd = np.sqrt(np.diag(A))
+        E = 2e-5 * np.outer(sd, sd)
+        tol = np.abs(Co) @ E @ np.abs(Co) + 1e-12 * np.abs(Co)
+        assert np.all(np.abs(Cg - Co) <= tol), (s, float(np.max(np.abs(Cg - Co) / tol)))
+
+
+def test_covariance_of_the_sky_alone_is_one_over_sum_w(apx):
+    """Only the sky free: its variance is 1 / sum w (closed form, no oracle)."""
+    H, W = 30, 34
+    from paper_2308_01957_amd import synth
+    psf = synth.moffat_psf(9, 3.0, 2.5)
+    g = [15.2, 16.9, 0.7, 0.6, 1.6, 4.0, 0.5]
+    spec = {"name": "skycov",
+            "images": [dict(H=H, W=W, psf=psf, affine=synth.IDENTITY_AFFINE.copy(), sky_par=0,
+                            sky_fixed=0.0, sub=0)],
+            "comps": [dict(type=0, image=0, box=synth.full_window(H, W, 9), par=[-1] * 7, fixed=g)],
+            "subs": [(0, 1)], "sampling": dict(s=3, rule=0, mode=0, k=0.0),
+            "theta_true": [0.05], "kinds": [8], "re_of": [1.0]}
+    synth._finish(spec)
+    spec["noise"] = [np.random.default_rng(93).standard_normal((H, W))]
+    spec["theta_init"] = np.array([0.05])
+    cases.with_data(spec)
+    P, d, w = problem(apx, spec)
+    C, _ = P.covariance(spec["theta_init"], d, w)
+    ref = 1.0 / np.sum(spec["weight"][0].astype(np.float64))
+    assert abs(float(C.cpu()[0]) - ref) <= 1e-12 * ref
+
+
 def _lm_run(apx, spec, n_iter, use_graph=False):
     P, d, w = problem(apx, spec)
     th, st = P.lm_init(spec["theta_init"], d, w)

@@ -403,6 +403,30 @@ def test_lm_sky_only_closed_form():
     assert tn[15] == pytest.approx(target, rel=1e-12)
 
 
+def test_covariance_of_a_linear_fit_is_the_closed_form():
+    """With only the sky free the model is linear: the variance of the fitted sky is
+    1 / sum w, and for sky plus the brightness of a fixed-shape galaxy the covariance is the
+    inverse of the 2 x 2 weighted Gram matrix of the two templates (built here by hand)."""
+    spec = synth.single(1, H=24, W=26, P=7)
+    g = list(spec["theta_true"][:7])
+    th = spec["theta_true"]
+    d, w = synth.make_data(oracle.model_image(spec, th, 0), spec["noise"][0][:24, :26])
+    sky_only = dict(spec, comps=[dict(spec["comps"][0], par=[-1] * 7, fixed=g)],
+                    images=[dict(spec["images"][0], sky_par=0)], subs=[(0, 1)], n_par=1)
+    C = oracle.covariance(sky_only, np.array([th[7]]), [d], [w])
+    assert C.shape == (1, 1) and abs(C[0, 0] - 1.0 / np.sum(w.astype(np.float64))) <= 1e-12 * C[0, 0]
+    # sky + log10 Ie: d m / d log10 Ie = ln10 * m_gal, d m / d sky = 1
+    two = dict(spec, comps=[dict(spec["comps"][0], par=[-1] * 6 + [0], fixed=g)],
+               images=[dict(spec["images"][0], sky_par=1)], subs=[(0, 2)], n_par=2)
+    th2 = np.array([th[6], th[7]])
+    mg = oracle.model_image(two, th2, 0) - th[7]
+    T = np.stack([math.log(10.0) * mg.ravel(), np.ones(mg.size)], axis=1)
+    ww = w.astype(np.float64).ravel()
+    G = T.T @ (ww[:, None] * T)
+    C2 = oracle.covariance(two, th2, [d], [w])
+    assert np.allclose(C2, np.linalg.inv(G), rtol=1e-9, atol=0)
+
+
 def test_lm_reaches_least_squares_minimum():
     """The LM minimum is a stationary point that MINPACK's LM (scipy) does not move,
     and MINPACK started from the same initial point finds the same minimum."""
