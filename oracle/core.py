@@ -65,6 +65,9 @@ LM_DAMP_FLOOR = 1e-12        # D_kk = max(A_kk, floor * max_k A_kk)
 Q_MIN, Q_MAX = 0.01, 1.0
 N_MIN, N_MAX = 0.36, 10.0
 RE_MIN, RE_MAX = 0.01, 1e4
+# live Moffat PSF (power n, scale R_d in pixels)
+PSF_N_MIN, PSF_N_MAX = 0.2, 20.0
+PSF_RD_MIN, PSF_RD_MAX = 0.05, 1e3
 
 
 # ----------------------------------------------------------------------------- b_n
@@ -277,10 +280,55 @@ def sky_value(im, theta) -> float:
     return float(theta[im["sky_par"]]) if im["sky_par"] >= 0 else float(im["sky_fixed"])
 
 
+# ------------------------------------------------------------------ live PSF
+def psf_model_of(spec: Dict, k: int) -> Dict | None:
+    """The live PSF model of image k (its parameters fitted with everything else, §2.1.3
+    and §3.4), or None when the image has a fixed stamp."""
+    for pm in spec.get("psf_models", []):
+        if pm["image"] == k:
+            return pm
+    return None
+
+
+def psf_params(pm: Dict, theta: np.ndarray):
+    return [float(theta[p]) if p >= 0 else float(f) for p, f in zip(pm["par"], pm["fixed"])]
+
+
+def moffat_stamp(n: float, rd: float, P: int, with_grad: bool = False):
+    """Moffat PSF stamp: f = (1 + r^2/R_d^2)^(-n) point-sampled at the integer offsets of
+    a P x P grid, normalised to unit sum (the stamp is normalised before convolution,
+    §3.4).  With with_grad also d stamp / d n and d stamp / d R_d of the normalised
+    stamp (quotient rule: dK = (df - K sum df) / sum f)."""
+    c = (P - 1) // 2
+    v, u = np.meshgrid(np.arange(-c, c + 1, dtype=np.float64), np.arange(-c, c + 1, dtype=np.float64))
+    x = 1.0 + (u * u + v * v) / (rd * rd)
+    f = x ** (-n)
+    S = f.sum()
+    K = f / S
+    if not with_grad:
+        return K
+    df_dn = -np.log(x) * f
+    df_drd = f * (-n) / x * (-2.0 * (u * u + v * v) / rd ** 3)
+    dK_dn = (df_dn - K * df_dn.sum()) / S
+    dK_drd = (df_drd - K * df_drd.sum()) / S
+    return K, dK_dn, dK_drd
+
+
+def psf_of(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
+    """The stamp image k is convolved with: its fixed stamp (FP32 values in FP64) or the
+    live Moffat model at theta."""
+    im = spec["images"][k]
+    pm = psf_model_of(spec, k)
+    if pm is None:
+        return np.asarray(im["psf"], dtype=np.float64)
+    n, rd = psf_params(pm, theta)
+    return moffat_stamp(n, rd, np.asarray(im["psf"]).shape[0])
+
+
 def model_image(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
     """Convolved model of image k plus its flat sky (the sky is not convolved)."""
     im = spec["images"][k]
-    return convolve_valid(render_ext(spec, theta, k), im["psf"]) + sky_value(im, theta)
+    return convolve_valid(render_ext(spec, theta, k), psf_of(spec, theta, k)) + sky_value(im, theta)
 
 
 def images_of_sub(spec: Dict, sub: int) -> List[int]:
@@ -332,11 +380,21 @@ def jacobian_image(spec, theta, k, cols: Sequence[int] | None = None) -> np.ndar
             dS[p][y0 + c:y1 + c, x0 + c:x1 + c] += g[loc]
     out_cols = list(range(n_par)) if cols is None else list(cols)
     J = np.zeros((H * W, len(out_cols)))
+    K = psf_of(spec, theta, k)
     for ci, p in enumerate(out_cols):
         if p in dS:
-            J[:, ci] = convolve_valid(dS[p], im["psf"]).ravel()
+            J[:, ci] = convolve_valid(dS[p], K).ravel()
         if im["sky_par"] == p:
             J[:, ci] += 1.0
+    # live PSF: m = K(phi) * S + sky, so dm/dphi = (dK/dphi) * S
+    pm = psf_model_of(spec, k)
+    if pm is not None and any(p >= 0 and p in want for p in pm["par"]):
+        n, rd = psf_params(pm, theta)
+        _, dK_dn, dK_drd = moffat_stamp(n, rd, np.asarray(im["psf"]).shape[0], with_grad=True)
+        S = render_ext(spec, theta, k)
+        for p, dK in zip(pm["par"], (dK_dn, dK_drd)):
+            if p >= 0 and p in want:
+                J[:, out_cols.index(p)] += convolve_valid(S, dK).ravel()
     return J
 
 
@@ -393,6 +451,13 @@ def in_domain(spec, theta, sub: int) -> bool:
         if not all(math.isfinite(v) for v in vals):
             return False
         if not (Q_MIN <= q <= Q_MAX and N_MIN <= n <= N_MAX and RE_MIN <= re <= RE_MAX):
+            return False
+    for pm in spec.get("psf_models", []):
+        if spec["images"][pm["image"]]["sub"] != sub:
+            continue
+        n, rd = psf_params(pm, theta)
+        if not (math.isfinite(n) and math.isfinite(rd) and PSF_N_MIN <= n <= PSF_N_MAX
+                and PSF_RD_MIN <= rd <= PSF_RD_MAX):
             return False
     return True
 

@@ -427,6 +427,56 @@ def test_covariance_of_a_linear_fit_is_the_closed_form():
     assert np.allclose(C2, np.linalg.inv(G), rtol=1e-9, atol=0)
 
 
+def _live_psf_spec(n=2.2, rd=2.5, P=13, H=40, W=44):
+    """Stars and one galaxy on a small image whose PSF is a live Moffat (n, R_d free)."""
+    theta = [1.3, 1.0, 1.6, 0.4, 0.05, n, rd, 19.3, 21.7, 0.6, 1.0, 1.5, 4.0, 0.5]
+    stars = [(10.0, 12.0), (30.4, 8.7), (12.6, 31.2), (33.0, 30.0)]
+    comps = [dict(type=1, image=0, box=synth.point_window(x, y, H, W, P), par=[-1, -1, i, -1, -1, -1, -1],
+                  fixed=[x, y, 0, 0, 0, 0, 0]) for i, (x, y) in enumerate(stars)]
+    comps.append(dict(type=0, image=0, box=synth.full_window(H, W, P), par=list(range(7, 14)), fixed=[0.0] * 7))
+    spec = {"name": "livepsf", "images": [dict(H=H, W=W, psf=np.zeros((P, P), np.float32),
+                                                affine=synth.IDENTITY_AFFINE.copy(), sky_par=4,
+                                                sky_fixed=0.0, sub=0)],
+            "comps": comps, "subs": [(0, len(theta))], "sampling": dict(s=3, rule=0, mode=0, k=0.0),
+            "psf_models": [dict(image=0, par=[5, 6], fixed=[0.0, 0.0])],
+            "theta_true": theta, "kinds": [7, 7, 7, 7, 8, 9, 10, 0, 1, 2, 3, 4, 5, 6],
+            "re_of": [1.0] * 7 + [4.0] * 7}
+    return synth._finish(spec)
+
+
+def test_moffat_stamp_half_width_and_normalisation():
+    """Half maximum of (1 + r^2/R_d^2)^-n sits at r = R_d sqrt(2^(1/n) - 1): pick R_d so
+    that r is an on-axis pixel, for two powers; the stamp sums to 1 and its parameter
+    derivatives to 0 (normalisation)."""
+    for n, r in ((1.0, 3), (2.0, 4)):
+        rd = r / math.sqrt(2.0 ** (1.0 / n) - 1.0)
+        K, dn, drd = oracle.moffat_stamp(n, rd, 13, with_grad=True)
+        assert abs(K[6, 6 + r] / K[6, 6] - 0.5) <= 1e-14
+        assert abs(K.sum() - 1.0) <= 1e-14
+        assert abs(dn.sum()) <= 1e-14 and abs(drd.sum()) <= 1e-14
+
+
+def test_live_psf_star_is_the_stamp_and_jacobian_matches_fd():
+    """A star at an integer position renders as flux x the live stamp (+ sky); the PSF
+    Jacobian columns match central differences of the model."""
+    spec = _live_psf_spec()
+    th = np.asarray(spec["theta_true"], dtype=np.float64)
+    one = dict(spec, comps=[spec["comps"][0]])
+    m = oracle.model_image(one, th, 0)
+    K = oracle.moffat_stamp(th[5], th[6], 13)
+    ref = np.full((40, 44), th[4])
+    ref[12 - 6:12 + 7, 10 - 6:10 + 7] += 10 ** th[0] * K
+    assert np.allclose(m, ref, rtol=1e-13, atol=1e-13)
+    J = oracle.jacobian(spec, th)
+    for p in (5, 6):
+        h = 1e-6 * abs(th[p])
+        tp, tm = th.copy(), th.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = (oracle.model_image(spec, tp, 0) - oracle.model_image(spec, tm, 0)).ravel() / (2 * h)
+        assert np.max(np.abs(J[:, p] - fd)) <= 1e-6 * np.max(np.abs(fd)), p
+
+
 def test_lm_reaches_least_squares_minimum():
     """The LM minimum is a stationary point that MINPACK's LM (scipy) does not move,
     and MINPACK started from the same initial point finds the same minimum."""
