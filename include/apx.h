@@ -128,6 +128,21 @@ typedef struct apx_comp_desc {
     double  fixed[7];      /* values of fixed local parameters                   */
 } apx_comp_desc;
 
+/* Live PSF model of one image (§2.1.3: the PSF may itself be a model with parameters
+ * optimised in the fit; §3.4).  APX_PSF_MOFFAT: f(r) = (1 + r^2 / R_d^2)^(-n) with power n
+ * and scale R_d in pixels, point-sampled at the integer offsets of the image's P x P stamp
+ * grid and normalised to unit sum before the convolution.  The image's stamp in `psf` only
+ * fixes P.  Its parameters may be free theta indices of the image's sub-problem (they add
+ * Jacobian columns (dK/dphi) * S, S the pre-convolution model) or fixed.  Domain, checked
+ * like the Sersic one: n in [0.2, 20], R_d in [0.05, 1e3]. */
+#define APX_PSF_MOFFAT 0
+typedef struct apx_psf_model_desc {
+    int32_t image;         /* image index (at most one model per image)          */
+    int32_t type;          /* APX_PSF_MOFFAT                                     */
+    int32_t par[2];        /* theta indices of (n, R_d), -1 = fixed              */
+    double  fixed[2];      /* values of fixed parameters                         */
+} apx_psf_model_desc;
+
 typedef struct apx_problem_desc {
     int32_t n_images, n_comps, n_par, n_sub;
     const apx_image_desc* images;   /* host, [n_images]                            */
@@ -140,6 +155,9 @@ typedef struct apx_problem_desc {
     int32_t objective;              /* APX_OBJECTIVE_* (precision of the model used
                                        for chi^2, residuals and LM trials)          */
     double  k_re;                   /* k of APX_MODE_WITHIN_K_RE                   */
+    int32_t n_psf_models;           /* live PSF models (0: every stamp is fixed)     */
+    int32_t reserved;
+    const apx_psf_model_desc* psf_models;   /* host, [n_psf_models]                 */
 } apx_problem_desc;
 
 /* Per-sub-problem LM state, device memory, [n_sub] entries (apx_lm_init fills it). */

@@ -49,13 +49,36 @@ class CompDesc(ctypes.Structure):
                 ("fixed", ctypes.c_double * 7)]
 
 
+class PsfModelDesc(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_int32), ("type", ctypes.c_int32), ("par", ctypes.c_int32 * 2),
+                ("fixed", ctypes.c_double * 2)]
+
+
 class ProblemDesc(ctypes.Structure):
     _fields_ = [("n_images", ctypes.c_int32), ("n_comps", ctypes.c_int32),
                 ("n_par", ctypes.c_int32), ("n_sub", ctypes.c_int32),
                 ("images", ctypes.POINTER(ImageDesc)), ("comps", ctypes.POINTER(CompDesc)),
                 ("sub_par", ctypes.POINTER(ctypes.c_int32)), ("psf", ctypes.c_void_p),
                 ("s", ctypes.c_int32), ("rule", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("objective", ctypes.c_int32), ("k_re", ctypes.c_double)]
+                ("objective", ctypes.c_int32), ("k_re", ctypes.c_double),
+                ("n_psf_models", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("psf_models", ctypes.POINTER(PsfModelDesc))]
+
+
+PSF_MOFFAT = 0
+
+
+def _psf_models(spec: Dict):
+    """Live PSF models of the spec: entries dict(image, par=[n, R_d indices], fixed=[n, R_d])."""
+    models = spec.get("psf_models", [])
+    arr = (PsfModelDesc * max(1, len(models)))()
+    for m, pm in enumerate(models):
+        arr[m].image = int(pm["image"])
+        arr[m].type = int(pm.get("type", PSF_MOFFAT))
+        for q in range(2):
+            arr[m].par[q] = int(pm["par"][q])
+            arr[m].fixed[q] = float(pm["fixed"][q])
+    return len(models), arr
 
 
 class LMState(ctypes.Structure):
@@ -185,11 +208,12 @@ class Problem:
         self._check(self.lib.apx_ctx_set_tiles(self._ctx, int(tiles)))
         idesc, cdesc, sp = _descs(spec)
         sampling = spec["sampling"]
+        npm, pms = _psf_models(spec)
         desc = ProblemDesc(len(spec["images"]), len(spec["comps"]), self.n_par, self.n_sub,
                            idesc, cdesc, sp, ctypes.c_void_p(self.psf.data_ptr()),
                            int(sampling["s"]), int(sampling["rule"]), int(sampling["mode"]),
-                           int(objective), float(sampling.get("k", 0.0)))
-        self._keep = (idesc, cdesc, sp, desc)
+                           int(objective), float(sampling.get("k", 0.0)), npm, 0, pms)
+        self._keep = (idesc, cdesc, sp, desc, pms)
         self._prob = ctypes.c_void_p()
         self._check(self.lib.apx_problem_create(self._ctx, ctypes.byref(desc), ctypes.byref(self._prob)))
         nbytes = ctypes.c_uint64()
@@ -431,9 +455,11 @@ class Plan:
             raise ApxError(st, "tile policy")
         idesc, cdesc, sp = _descs(spec)
         sampling = spec["sampling"]
+        npm, pms = _psf_models(spec)
         desc = ProblemDesc(len(spec["images"]), len(spec["comps"]), int(spec["n_par"]), len(spec["subs"]),
                            idesc, cdesc, sp, None, int(sampling["s"]), int(sampling["rule"]),
-                           int(sampling["mode"]), int(objective), float(sampling.get("k", 0.0)))
+                           int(sampling["mode"]), int(objective), float(sampling.get("k", 0.0)), npm, 0, pms)
+        self._keep = (idesc, cdesc, sp, desc, pms)
         self._prob = ctypes.c_void_p()
         st = self.lib.apx_problem_create(self._ctx, ctypes.byref(desc), ctypes.byref(self._prob))
         if st != APX_OK:

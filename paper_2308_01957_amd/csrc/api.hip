@@ -61,9 +61,11 @@ struct apx_problem {
     std::vector<int> group_comps;
     std::vector<RTile> rtiles, gtiles;
     std::vector<int> rtile_off, rtile_comps;
-    std::vector<ConvJob> fwd_jobs, jcol_jobs, adj_jobs;
-    std::vector<ConvItem> fwd_items, jcol_items, adj_items;
-    std::vector<PRange> fwd_ranges, jcol_ranges, adj_ranges;
+    std::vector<ConvJob> fwd_jobs, jcol_jobs, adj_jobs, psf_jobs;
+    std::vector<ConvItem> fwd_items, jcol_items, adj_items, psf_items;
+    std::vector<PRange> fwd_ranges, jcol_ranges, adj_ranges, psf_ranges;
+    long long n_live = 0;                         // floats of live-PSF stamps (3 P^2 each)
+    bool has_live_cols = false;                   // some live PSF has a free parameter
     std::vector<DPair> pairs;
     std::vector<PairItem> pitems64, pitems16;
     // reduction tables
@@ -200,6 +202,7 @@ static bool tune_kernel(apx_ctx* C, int key, int P, std::array<double, 4>& us) {
     auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
     const size_t o_img = take(sizeof(DImage)), o_job = take(sizeof(ConvJob));
     const size_t o_items = take(sizeof(ConvItem) * max_items), o_psf = take(sizeof(float) * TUNE_MAXP * TUNE_MAXP);
+    const size_t o_psf64 = take(sizeof(double) * TUNE_MAXP * TUNE_MAXP);
     const size_t o_sky = take(sizeof(double)), o_r = take(sizeof(float) * npx), o_w = take(sizeof(float) * npx);
     const size_t o_d = take(sizeof(float) * npx), o_in = take(sizeof(float) * next * TUNE_CH);
     const size_t o_in64 = take(sizeof(double) * next), o_out = take(sizeof(float) * (size_t)TUNE_CH * next);
@@ -218,8 +221,11 @@ static bool tune_kernel(apx_ctx* C, int key, int P, std::array<double, 4>& us) {
     Plan p{};
     p.n_images = 1;
     p.images = (const DImage*)(base + o_img);
+    // every stamp pointer a kernel may read (FP32, flipped, FP64) points at zeroed scratch
     p.psf = (const float*)(base + o_psf);
     p.psf_flip = (float*)(base + o_psf);
+    p.psf_live = (float*)(base + o_psf);
+    p.psf64 = (double*)(base + o_psf64);
     p.sky_val = (double*)(base + o_sky);
     p.rbuf = (float*)(base + o_r);
     ConvIO io{};
@@ -509,6 +515,30 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     P->n_ext = ext;
     P->n_psf = psfo;
 
+    // live PSF models
+    if (d->n_psf_models < 0 || (d->n_psf_models > 0 && !d->psf_models))
+        return fail(C, APX_E_INVALID, "psf_models: bad count or null pointer");
+    for (int m = 0; m < d->n_psf_models; ++m) {
+        const apx_psf_model_desc& md = d->psf_models[m];
+        if (md.type != APX_PSF_MOFFAT) return fail(C, APX_E_UNSUPPORTED, "unknown PSF model type");
+        if (md.image < 0 || md.image >= d->n_images) return fail(C, APX_E_INVALID, "PSF model image out of range");
+        DImage& im = P->images[md.image];
+        if (im.live) return fail(C, APX_E_INVALID, "two PSF models for one image");
+        for (int q = 0; q < 2; ++q) {
+            if (md.par[q] < -1 || (md.par[q] >= 0 && !in_sub(md.par[q], im.sub)))
+                return fail(C, APX_E_INVALID, "PSF model parameter outside its image's sub-problem");
+            if (md.par[q] >= 0 && md.par[q] == im.sky_par)
+                return fail(C, APX_E_INVALID, "PSF model parameter shares the sky index");
+            if (md.par[q] < 0 && !std::isfinite(md.fixed[q]))
+                return fail(C, APX_E_INVALID, "non-finite fixed PSF parameter");
+            im.live_par[q] = md.par[q];
+            im.live_fixed[q] = md.fixed[q];
+        }
+        im.live = 1;
+        im.live_off = P->n_live;
+        P->n_live += 3LL * im.P * im.P;
+    }
+
     // components
     P->comps.resize(d->n_comps);
     for (int i = 0; i < d->n_comps; ++i) {
@@ -649,6 +679,35 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             gpoff += (long long)nc * gr.ntiles;
             P->groups.push_back(gr);
         }
+        // live-PSF columns of each image: input the pre-convolution model S on the
+        // extended grid, output the whole image, no derivative images and no tiles
+        for (int k = 0; k < d->n_images; ++k) {
+            const DImage& im = P->images[k];
+            if (!im.live || (im.live_par[0] < 0 && im.live_par[1] < 0)) continue;
+            DGroup gr{};
+            gr.image = k;
+            gr.type = GROUP_PSF;
+            gr.sub = im.sub;
+            gr.iy0 = -im.c; gr.ix0 = -im.c; gr.ih = im.EH; gr.iw = im.EW;
+            gr.oy0 = 0; gr.ox0 = 0; gr.oh = im.H; gr.ow = im.W;
+            gr.comp_begin = gr.comp_end = (int)P->group_comps.size();
+            gr.col_begin = (int)P->cols.size();
+            int nc = 0;
+            for (int q = 0; q < 2; ++q)
+                if (im.live_par[q] >= 0) {
+                    P->cols.push_back(DCol{(int)P->groups.size(), -1, q, im.live_par[q]});
+                    ++nc;
+                }
+            gr.ncols = nc;
+            gr.d_off = doff;
+            gr.j_off = joff;
+            joff += (long long)nc * gr.oh * gr.ow;
+            gr.tile_begin = (int)P->gtiles.size();
+            gr.ntiles = 0;
+            gr.gp_off = gpoff;
+            P->groups.push_back(gr);
+            P->has_live_cols = true;
+        }
         P->n_d = doff;
         P->n_j = joff;
         P->n_gradpart = gpoff;
@@ -715,8 +774,11 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         add_items(CONV_FWD, P->fwd_jobs, P->fwd_items, P->fwd_ranges, jp, nch, &fwd_item_begin);
         add_items(CONV_ADJ, P->adj_jobs, P->adj_items, P->adj_ranges, jp, nch, nullptr);
     }
+    std::vector<int> psf_job_of(n_groups, -1), psf_item_begin;
     {
-        std::vector<int> jp, nch;
+        // one job per group (index = group); live-PSF groups get no items here and a job
+        // of their own in the PSF list (input S, derivative stamps)
+        std::vector<int> jp, nch, pjp, pnch;
         for (int g = 0; g < n_groups; ++g) {
             const DGroup& gr = P->groups[g];
             const DImage& im = P->images[gr.image];
@@ -729,11 +791,24 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             jb.out_y0 = gr.oy0; jb.out_x0 = gr.ox0; jb.out_h = gr.oh; jb.out_w = gr.ow;
             jb.image = gr.image;
             jb.group = g;
+            const bool psfg = gr.type == GROUP_PSF;
             P->jcol_jobs.push_back(jb);
             jp.push_back(im.P);
-            nch.push_back(gr.oh > 0 && gr.ow > 0 ? gr.ncols : 0);
+            nch.push_back(!psfg && gr.oh > 0 && gr.ow > 0 ? gr.ncols : 0);
+            if (psfg) {
+                ConvJob pj = jb;
+                pj.in_src = 1;
+                pj.in_off = im.ext_off;
+                pj.in_cs = 0;                      // every PSF column convolves the same S
+                for (int ch = 0; ch < gr.ncols && ch < 2; ++ch) pj.kslot[ch] = 1 + P->cols[gr.col_begin + ch].local;
+                psf_job_of[g] = (int)P->psf_jobs.size();
+                P->psf_jobs.push_back(pj);
+                pjp.push_back(im.P);
+                pnch.push_back(gr.ncols);
+            }
         }
         add_items(CONV_JCOL, P->jcol_jobs, P->jcol_items, P->jcol_ranges, jp, nch, &jcol_item_begin);
+        add_items(CONV_JCOL, P->psf_jobs, P->psf_items, P->psf_ranges, pjp, pnch, &psf_item_begin);
     }
 
     // reduction tables: FWD items per image, JCOL items per column, grad partials per column
@@ -748,11 +823,16 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         }
         P->col_seg.assign(1, 0);
         P->gcol_seg.assign(1, 0);
+        const int n_main_items = (int)P->jcol_items.size();
         for (int g = 0; g < n_groups; ++g) {
             const DGroup& gr = P->groups[g];
-            const int per = (gr.oh > 0 && gr.ow > 0) ? job_tiles(P->jcol_jobs[g]) : 0;
+            const int pj = psf_job_of[g];
+            const ConvJob& job = pj >= 0 ? P->psf_jobs[pj] : P->jcol_jobs[g];
+            const int per = (gr.oh > 0 && gr.ow > 0) ? job_tiles(job) : 0;
+            // partials of the PSF list follow those of the main list in jcol_part
+            const int first = pj >= 0 ? n_main_items + psf_item_begin[pj] : jcol_item_begin[g];
             for (int ch = 0; ch < gr.ncols; ++ch) {
-                for (int q = 0; q < per; ++q) P->col_idx.push_back(jcol_item_begin[g] + ch * per + q);
+                for (int q = 0; q < per; ++q) P->col_idx.push_back(first + ch * per + q);
                 P->col_seg.push_back((int)P->col_idx.size());
                 P->gcol_seg.push_back((int)(gr.gp_off + (long long)(ch + 1) * gr.ntiles));
             }
@@ -901,8 +981,14 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
                     P->g_idx.push_back((int)(P->asrc_col + 2LL * c));
                     P->g_w.push_back(1.0);
                 }
-                P->gr_idx.push_back((int)(P->asrc_gcol + c));
-                P->gr_w.push_back(1.0);
+                if (gr.type == GROUP_PSF) {
+                    // d chi2 / d phi = -2 sum w r J_phi, from the column's JCOL partials
+                    P->gr_idx.push_back((int)(P->asrc_col + 2LL * c));
+                    P->gr_w.push_back(-2.0);
+                } else {
+                    P->gr_idx.push_back((int)(P->asrc_gcol + c));
+                    P->gr_w.push_back(1.0);
+                }
                 P->par_cols.push_back(c);
             }
             for (int k : ps[p]) {
@@ -956,6 +1042,8 @@ static void layout(apx_problem* P) {
     ws_take<ConvItem>(P, "fwd_items", P->fwd_items.size());
     ws_take<ConvJob>(P, "jcol_jobs", P->jcol_jobs.size());
     ws_take<ConvItem>(P, "jcol_items", P->jcol_items.size());
+    ws_take<ConvJob>(P, "psf_jobs", P->psf_jobs.size());
+    ws_take<ConvItem>(P, "psf_items", P->psf_items.size());
     ws_take<ConvJob>(P, "adj_jobs", P->adj_jobs.size());
     ws_take<ConvItem>(P, "adj_items", P->adj_items.size());
     ws_take<DPair>(P, "pairs", P->pairs.size());
@@ -997,7 +1085,9 @@ static void layout(apx_problem* P) {
     ws_take<float>(P, "J", P->n_j);
     ws_take<float>(P, "psf_flip", P->n_psf);
     ws_take<double>(P, "fwd_part", 3 * P->fwd_items.size());
-    ws_take<double>(P, "jcol_part", 2 * P->jcol_items.size());
+    ws_take<double>(P, "jcol_part", 2 * (P->jcol_items.size() + P->psf_items.size()));
+    ws_take<float>(P, "psf_live", P->n_live);
+    ws_take<double>(P, "psf64", P->n_psf);
     ws_take<double>(P, "grad_part", P->n_gradpart);
     ws_take<double>(P, "asrc", P->asrc_img + 3LL * P->n_images);
     ws_take<double>(P, "A", P->a_total);
@@ -1151,6 +1241,8 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     HIPCHK(upload(P, "fwd_items", P->fwd_items));
     HIPCHK(upload(P, "jcol_jobs", P->jcol_jobs));
     HIPCHK(upload(P, "jcol_items", P->jcol_items));
+    HIPCHK(upload(P, "psf_jobs", P->psf_jobs));
+    HIPCHK(upload(P, "psf_items", P->psf_items));
     HIPCHK(upload(P, "adj_jobs", P->adj_jobs));
     HIPCHK(upload(P, "adj_items", P->adj_items));
     HIPCHK(upload(P, "pairs", P->pairs));
@@ -1225,6 +1317,8 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.J = wsp<float>(P, "J");
     p.fwd_part = wsp<double>(P, "fwd_part");
     p.jcol_part = wsp<double>(P, "jcol_part");
+    p.psf_live = wsp<float>(P, "psf_live");
+    p.psf64 = wsp<double>(P, "psf64");
     p.grad_part = wsp<double>(P, "grad_part");
     P->asrc = wsp<double>(P, "asrc");
     p.pair_part = P->asrc;
@@ -1321,14 +1415,16 @@ static apx_status run_conv(apx_problem* P, int kind, const ConvIO& io) {
     const char *jn, *inn;
     if (kind == CONV_FWD) { ranges = &P->fwd_ranges; jn = "fwd_jobs"; inn = "fwd_items"; }
     else if (kind == CONV_JCOL) { ranges = &P->jcol_ranges; jn = "jcol_jobs"; inn = "jcol_items"; }
+    else if (kind == CONV_JCOL_PSF) { ranges = &P->psf_ranges; jn = "psf_jobs"; inn = "psf_items"; }
     else { ranges = &P->adj_ranges; jn = "adj_jobs"; inn = "adj_items"; }
-    const int klass = kind == CONV_FWD ? APX_TIME_CONV_FWD : kind == CONV_JCOL ? APX_TIME_CONV_JCOL : APX_TIME_CONV_ADJ;
+    const int klass = kind == CONV_FWD ? APX_TIME_CONV_FWD
+                    : (kind == CONV_JCOL || kind == CONV_JCOL_PSF) ? APX_TIME_CONV_JCOL : APX_TIME_CONV_ADJ;
     for (const PRange& r : *ranges) {
         TimeScope ts(P, klass);
         ConvLaunch L{wsp<ConvJob>(P, jn), wsp<ConvItem>(P, inn), r.begin, r.count, r.P, r.shape};
         hipError_t e = kind == CONV_FWD ? (P->objective == APX_OBJECTIVE_FP64 ? launch_conv_fwd64(p, L, io, st)
                                                                                : launch_conv_fwd(p, L, io, st))
-                     : kind == CONV_JCOL ? launch_conv_jcol(p, L, io, st)
+                     : (kind == CONV_JCOL || kind == CONV_JCOL_PSF) ? launch_conv_jcol(p, L, io, st)
                                          : launch_conv_adj(p, L, io, st);
         if (e != hipSuccess) return fail(P->ctx, APX_E_HIP, std::string("conv launch: ") + hipGetErrorString(e));
     }
@@ -1403,6 +1499,45 @@ static apx_status fwd_chi2(apx_problem* P, const double* theta, const float* dat
 }
 
 // Derivative images and Jacobian blocks (with sum w r J, sum w J partials if weight).
+// Live-PSF Jacobian columns (dK/dphi) * S: the FP32 pre-convolution model S at theta,
+// then its convolutions with the derivative stamps, with Sigma w r J, Sigma w J partials
+// after those of the main Jacobian list.
+static apx_status psf_columns(apx_problem* P, const float* weight, int skip_mode, const apx_lm_state* lm) {
+    if (!P->has_live_cols) return APX_OK;
+    const Plan& p = P->plan;
+    {
+        TimeScope ts(P, APX_TIME_RENDER);
+        HIPCHK(launch_render_mode(p, skip_mode, lm, P->ctx->stream));
+    }
+    ConvIO io{};
+    io.in_s = p.S;
+    io.out = p.J;
+    io.weight = weight;
+    io.part = p.jcol_part + 2 * P->jcol_items.size();
+    io.skip_mode = skip_mode;
+    io.lm = lm;
+    return run_conv(P, CONV_JCOL_PSF, io);
+}
+
+static apx_status col_sums(apx_problem* P) {
+    const Plan& p = P->plan;
+    TimeScope ts(P, APX_TIME_REDUCE);
+    for (int q = 0; q < 2; ++q) {
+        SegSum a = segsum_base();
+        a.src = p.jcol_part;
+        a.stride = 2;
+        a.comp = q;
+        a.seg = wsp<int>(P, "col_seg");
+        a.idx = wsp<int>(P, "col_idx");
+        a.n_seg = (int)P->cols.size();
+        a.out = p.col_sum;
+        a.ostride = 2;
+        a.ocomp = q;
+        HIPCHK(launch_segsum(a, P->ctx->stream));
+    }
+    return APX_OK;
+}
+
 static apx_status jac_blocks(apx_problem* P, const float* weight, const apx_lm_state* lm) {
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
@@ -1418,22 +1553,8 @@ static apx_status jac_blocks(apx_problem* P, const float* weight, const apx_lm_s
     io.skip_mode = lm ? 2 : 0;
     io.lm = lm;
     APXCHK(run_conv(P, CONV_JCOL, io));
-    if (weight) {
-        TimeScope ts(P, APX_TIME_REDUCE);
-        for (int q = 0; q < 2; ++q) {
-            SegSum a = segsum_base();
-            a.src = p.jcol_part;
-            a.stride = 2;
-            a.comp = q;
-            a.seg = wsp<int>(P, "col_seg");
-            a.idx = wsp<int>(P, "col_idx");
-            a.n_seg = (int)P->cols.size();
-            a.out = p.col_sum;
-            a.ostride = 2;
-            a.ocomp = q;
-            HIPCHK(launch_segsum(a, st));
-        }
-    }
+    APXCHK(psf_columns(P, weight, lm ? 2 : 0, lm));
+    if (weight) APXCHK(col_sums(P));
     return APX_OK;
 }
 
@@ -1573,6 +1694,10 @@ apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data,
     a.n_seg = (int)P->cols.size();
     a.out = p.grad_col;
     HIPCHK(launch_segsum(a, st));
+    if (P->has_live_cols) {                 // live-PSF columns: -2 sum w r J from their convolutions
+        APXCHK(psf_columns(P, weight, 0, nullptr));
+        APXCHK(col_sums(P));
+    }
     SegSum g = segsum_base();
     g.src = P->asrc;
     g.seg = wsp<int>(P, "gr_seg");
@@ -1610,6 +1735,13 @@ apx_status apx_render_vjp(apx_problem* P, const double* theta, const float* grad
     a.n_seg = (int)P->cols.size();
     a.out = p.grad_col;
     HIPCHK(launch_segsum(a, st));
+    if (P->has_live_cols) {
+        // live-PSF columns: sum seed J from their convolutions, with the residual buffer set
+        // to -1/2 so that the gradient tables' weight -2 on sum w r J gives sum seed J
+        HIPCHK(launch_fill_f(p.rbuf, P->n_pix, -0.5f, st));
+        APXCHK(psf_columns(P, grad_model, 0, nullptr));
+        APXCHK(col_sums(P));
+    }
     SegSum g = segsum_base();
     g.src = P->asrc;
     g.seg = wsp<int>(P, "gr_seg");

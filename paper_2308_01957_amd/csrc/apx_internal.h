@@ -50,6 +50,11 @@ struct DImage {
     double aff[6];            // pixel -> sky
     double inv[6];            // sky -> pixel
     double area;              // |det| of the linear part
+    int live;                 // 1: the stamp is a live Moffat model rendered from theta
+    int live_par[2];          // theta indices of (n, R_d), -1 = fixed
+    int pad_live;
+    double live_fixed[2];
+    long long live_off;       // into psf_live: K, dK/dn, dK/dR_d (3 P^2 floats)
 };
 
 struct DComp {
@@ -99,6 +104,10 @@ struct ConvJob {
     int in_y0, in_x0, in_h, in_w;             // input rectangle (zero outside)
     int out_y0, out_x0, out_h, out_w;         // output rectangle
     int image, group, ntx, shape;             // shape: output tile shape (tile_th/tile_tw)
+    int in_src;                               // input: 0 derivative images, 1 the model S
+    int kslot[2];                             // stamp of channel 0 / 1 on live-PSF images:
+                                              // 0 K, 1 dK/dn, 2 dK/dR_d
+    int pad_job;
 };
 struct ConvItem { int job, ch, ty, tx; };
 
@@ -135,6 +144,8 @@ struct Plan {
     const int* group_comps;
     const float* psf;         // caller's stamps
     float* psf_flip;          // flipped stamps (adjoint)
+    float* psf_live;          // live-PSF stamps and their derivatives (3 P^2 per live image)
+    double* psf64;            // every stamp in FP64 (objective convolution)
 
     // render tiles with component CSR
     const RTile* rtiles; int n_rtiles;
@@ -176,6 +187,9 @@ struct Plan {
 
 // Sticky flag bits
 constexpr int FLAG_DOMAIN = 1, FLAG_NONFINITE = 2, FLAG_STALL = 4;
+// live Moffat PSF domain
+constexpr double PSF_N_MIN = 0.2, PSF_N_MAX = 20.0, PSF_RD_MIN = 0.05, PSF_RD_MAX = 1e3;
+constexpr int GROUP_PSF = 2;                   // DGroup.type of the live-PSF columns of an image
 
 // Launchers (each returns hipGetLastError()) ----------------------------------------
 // k_model.hip
@@ -191,7 +205,7 @@ hipError_t launch_flip_psf(const Plan& p, hipStream_t st);
 hipError_t launch_seed_sums(const Plan& p, const float* seed, double* part, hipStream_t st);
 
 // k_conv_*.hip
-enum ConvKind { CONV_FWD = 0, CONV_JCOL = 1, CONV_ADJ = 2 };
+enum ConvKind { CONV_FWD = 0, CONV_JCOL = 1, CONV_ADJ = 2, CONV_JCOL_PSF = 3 };   // PSF: live-PSF columns
 struct ConvLaunch {
     const ConvJob* jobs;
     const ConvItem* items;
@@ -199,6 +213,7 @@ struct ConvLaunch {
 };
 struct ConvIO {
     const float* in;          // input buffer base (FWD, JCOL)
+    const float* in_s;        // JCOL jobs with in_src = 1: the pre-convolution model S
     const double* in64;       // input buffer base (FWD, FP64 objective)
     float* out;               // output buffer base (FWD: optional model)
     const float* data;        // FWD: data (null = no residual / partials)
@@ -237,6 +252,7 @@ struct AsmA {
 };
 hipError_t launch_assemble_A(const AsmA& a, hipStream_t st);
 hipError_t launch_fill(double* x, long long n, double v, hipStream_t st);
+hipError_t launch_fill_f(float* x, long long n, float v, hipStream_t st);
 hipError_t launch_jscatter(const Plan& p, const int* par_off, const int* par_cols,
                            const int* par_sky_off, const int* par_sky, float* Jd, long long ldJ,
                            hipStream_t st);

@@ -17,6 +17,8 @@
 //             given seed (vector-Jacobian product of the render), PSF flipped,
 //             output is dchi2/dS on the extended grid.
 #pragma once
+#include <type_traits>
+
 #include "apx_internal.h"
 
 namespace apx {
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
     } else {
         const T* __restrict__ in;
         if constexpr (sizeof(T) == 8) in = io.in64 + jb.in_off + (long long)it.ch * jb.in_cs;
-        else in = io.in + jb.in_off + (long long)it.ch * jb.in_cs;
+        else in = (jb.in_src ? io.in_s : io.in) + jb.in_off + (long long)it.ch * jb.in_cs;
         const int iy1 = jb.in_y0 + jb.in_h, ix1 = jb.in_x0 + jb.in_w;
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
@@ -101,7 +103,14 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
 
     // ---- register-window convolution
     const int ty = (int)threadIdx.x / LPR, tx = (int)threadIdx.x % LPR;
-    const float* __restrict__ K = (KIND == CONV_ADJ ? p.psf_flip : p.psf) + im.psf_off;
+    // the stamp: FP64 copies for the FP64 objective; the flipped stamp for the adjoint;
+    // on a live-PSF image the rendered stamp, or for its PSF columns a derivative stamp
+    using KT = typename std::conditional<sizeof(T) == 8, double, float>::type;
+    const KT* __restrict__ K;
+    if constexpr (sizeof(T) == 8) K = p.psf64 + im.psf_off;
+    else if constexpr (KIND == CONV_ADJ) K = p.psf_flip + im.psf_off;
+    else K = im.live ? p.psf_live + im.live_off + (long long)jb.kslot[it.ch < 1 ? 0 : 1] * P * P
+                     : p.psf + im.psf_off;
     T acc[CV_R];
 #pragma unroll
     for (int r = 0; r < CV_R; ++r) acc[r] = 0;

@@ -253,6 +253,20 @@ __global__ void k_fill_d(double* x, long long n, double v) {
         x[i] = v;
 }
 
+__global__ void k_fill_f(float* x, long long n, float v) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+hipError_t launch_fill_f(float* x, long long n, float v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    long long b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(k_fill_f, dim3((unsigned)b), dim3(256), 0, st, x, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(double* x, long long n, double v, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     long long b = (n + 255) / 256;

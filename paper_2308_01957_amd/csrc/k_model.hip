@@ -103,10 +103,79 @@ __global__ void k_prep(Plan p, const double* __restrict__ theta, int lm_trial) {
     }
 }
 
+// Stamps of every image for this theta: fixed stamps promoted to FP64 (objective
+// convolution); live Moffat stamps (§2.1.3, §3.4) rendered at the integer offsets,
+// normalised, with d/dn and d/dR_d of the normalised stamp (quotient rule), in FP64 and
+// as FP32 copies for the FP32 kernels.  One workgroup per image; the sums are ordered.
+__global__ __launch_bounds__(256) void k_psf_prep(Plan p, const double* __restrict__ theta, int lm_trial) {
+    __shared__ double red[4][3];
+    const int k = blockIdx.x;
+    const DImage& im = p.images[k];
+    const int P = im.P, c = im.c, P2 = P * P;
+    double* K64 = p.psf64 + im.psf_off;
+    if (!im.live) {
+        for (int e = threadIdx.x; e < P2; e += blockDim.x) K64[e] = (double)p.psf[im.psf_off + e];
+        return;
+    }
+    double n = im.live_par[0] >= 0 ? theta[im.live_par[0]] : im.live_fixed[0];
+    double rd = im.live_par[1] >= 0 ? theta[im.live_par[1]] : im.live_fixed[1];
+    const bool valid = isfinite(n) && isfinite(rd) && n >= PSF_N_MIN && n <= PSF_N_MAX &&
+                       rd >= PSF_RD_MIN && rd <= PSF_RD_MAX;
+    if (!valid) {
+        if (threadIdx.x == 0) {
+            if (lm_trial) atomicOr(&p.lmf[im.sub].trial_bad, 1);
+            else atomicOr(p.sticky, FLAG_DOMAIN);
+        }
+        n = 1.0;                                   // keeps the (unused) stamp finite
+        rd = 1.0;
+    }
+    const double ird2 = 1.0 / (rd * rd);
+    double sf = 0.0, sdn = 0.0, sdr = 0.0;
+    for (int e = threadIdx.x; e < P2; e += blockDim.x) {
+        const double u = (double)(e / P - c), v = (double)(e % P - c);
+        const double r2 = u * u + v * v;
+        const double x = 1.0 + r2 * ird2;
+        const double f = exp(-n * log(x));
+        sf += f;
+        sdn += -log(x) * f;
+        sdr += f * (-n) / x * (-2.0 * r2 * ird2 / rd);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sf += __shfl_xor(sf, o, 64);
+        sdn += __shfl_xor(sdn, o, 64);
+        sdr += __shfl_xor(sdr, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = sf;
+        red[threadIdx.x >> 6][1] = sdn;
+        red[threadIdx.x >> 6][2] = sdr;
+    }
+    __syncthreads();
+    const double S = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+    const double Sdn = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+    const double Sdr = ((red[0][2] + red[1][2]) + red[2][2]) + red[3][2];
+    const double iS = 1.0 / S;
+    float* K32 = p.psf_live + im.live_off;
+    for (int e = threadIdx.x; e < P2; e += blockDim.x) {
+        const double u = (double)(e / P - c), v = (double)(e % P - c);
+        const double r2 = u * u + v * v;
+        const double x = 1.0 + r2 * ird2;
+        const double f = exp(-n * log(x));
+        const double Kv = f * iS;
+        const double dn = (-log(x) * f - Kv * Sdn) * iS;
+        const double dr = (f * (-n) / x * (-2.0 * r2 * ird2 / rd) - Kv * Sdr) * iS;
+        K64[e] = Kv;
+        K32[e] = (float)Kv;
+        K32[P2 + e] = (float)dn;
+        K32[2 * P2 + e] = (float)dr;
+    }
+}
+
 hipError_t launch_prep(const Plan& p, const double* theta, int lm_trial, hipStream_t st) {
     const int n = p.n_comps > p.n_images ? p.n_comps : p.n_images;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_prep, dim3((n + 127) / 128), dim3(128), 0, st, p, theta, lm_trial);
+    if (p.n_images > 0) hipLaunchKernelGGL(k_psf_prep, dim3(p.n_images), dim3(256), 0, st, p, theta, lm_trial);
     return hipGetLastError();
 }
 
@@ -404,7 +473,8 @@ __global__ void k_flip_psf(Plan p) {
     const int P = im.P;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < P * P; e += gridDim.x * blockDim.x) {
         const int u = e / P, v = e % P;
-        p.psf_flip[im.psf_off + e] = p.psf[im.psf_off + (P - 1 - u) * P + (P - 1 - v)];
+        const float* K = im.live ? p.psf_live + im.live_off : p.psf + im.psf_off;
+        p.psf_flip[im.psf_off + e] = K[(P - 1 - u) * P + (P - 1 - v)];
     }
 }
 

@@ -49,7 +49,7 @@ MODE_UNIFORM = 0
 MODE_WITHIN_K_RE = 1
 
 # parameter kinds (used for tolerances, perturbation and domain checks)
-K_X, K_Y, K_Q, K_PA, K_N, K_RE, K_LOGIE, K_LOGF, K_SKY = range(9)
+K_X, K_Y, K_Q, K_PA, K_N, K_RE, K_LOGIE, K_LOGF, K_SKY, K_PSF_N, K_PSF_RD = range(11)
 
 Q_RANGE = (0.4, 0.9)
 N_RANGE = (0.8, 4.0)
@@ -166,7 +166,7 @@ def perturb(theta: np.ndarray, kinds: np.ndarray, re_of: np.ndarray, rng) -> np.
             t[k] += 0.1 * re_of[k] * z[k]
         elif kd == K_PA:
             t[k] += 0.1 * z[k]
-        elif kd in (K_Q, K_N, K_RE, K_SKY):
+        elif kd in (K_Q, K_N, K_RE, K_SKY, K_PSF_N, K_PSF_RD):
             t[k] *= 1.0 + 0.1 * z[k]
             if kd == K_Q:
                 t[k] = min(max(t[k], Q_RANGE[0]), Q_RANGE[1])
@@ -382,6 +382,51 @@ def cutouts(seed_id: int = 4, n_cutouts: int = 4096, side_range=(32, 256),
     spec["noise"] = [rng_n.standard_normal((im["H"], im["W"])) for im in images]
     rng_i = np.random.Generator(np.random.PCG64(si))
     spec["theta_init"] = perturb(spec["theta_true"], spec["kinds"], spec["re_of"], rng_i)
+    return spec
+
+
+def live_psf(seed_id: int = 6, H: int = 512, W: int = 512, n_star: int = 100, n_sersic: int = 20,
+             P: int = 25, psf_n: float = 2.5, psf_rd: float = 2.6, s: int = 3,
+             logf_range=(1.0, 2.5), logie_range=LOGIE_RANGE) -> Dict:
+    """Stars (fixed positions, free log10 flux) and Sersic galaxies on one image whose PSF is
+    a live Moffat model with free power n and scale R_d (its stamp in `psf` only sets P)
+    + sky; all fitted jointly.  Galaxies have full-image windows, stars PSF-sized ones."""
+    st, sn, si = seeds(seed_id)
+    rng = np.random.Generator(np.random.PCG64(st))
+    theta, kinds, re_of, comps = [], [], [], []
+    for _ in range(n_star):
+        px, py = rng.uniform(P / 2, W - 1 - P / 2), rng.uniform(P / 2, H - 1 - P / 2)
+        theta.append(rng.uniform(*logf_range))
+        kinds.append(K_LOGF)
+        re_of.append(1.0)
+        comps.append(dict(type=POINT, image=0, box=point_window(px, py, H, W, P),
+                          par=[-1, -1, len(theta) - 1, -1, -1, -1, -1], fixed=[px, py, 0, 0, 0, 0, 0]))
+    for _ in range(n_sersic):
+        prm = _draw_sersic(rng, rng.uniform(0.1 * W, 0.9 * W), rng.uniform(0.1 * H, 0.9 * H), logie_range)
+        p0 = len(theta)
+        theta += prm
+        kinds += [K_X, K_Y, K_Q, K_PA, K_N, K_RE, K_LOGIE]
+        re_of += [prm[5]] * 7
+        comps.append(dict(type=SERSIC, image=0, box=full_window(H, W, P), par=list(range(p0, p0 + 7)),
+                          fixed=[0.0] * 7))
+    theta.append(rng.uniform(*SKY_RANGE))
+    kinds.append(K_SKY)
+    re_of.append(1.0)
+    sky = len(theta) - 1
+    theta += [psf_n, psf_rd]
+    kinds += [K_PSF_N, K_PSF_RD]
+    re_of += [1.0, 1.0]
+    spec = {"name": f"livepsf{H}x{W}_{n_star}st{n_sersic}s_P{P}",
+            "images": [dict(H=H, W=W, psf=np.zeros((P, P), dtype=np.float32), affine=IDENTITY_AFFINE.copy(),
+                            sky_par=sky, sky_fixed=0.0, sub=0)],
+            "comps": comps, "subs": [(0, len(theta))],
+            "psf_models": [dict(image=0, par=[len(theta) - 2, len(theta) - 1], fixed=[0.0, 0.0])],
+            "sampling": dict(s=s, rule=RULE_MIDPOINT, mode=MODE_UNIFORM, k=0.0),
+            "theta_true": theta, "kinds": kinds, "re_of": re_of}
+    _finish(spec)
+    spec["noise"] = [np.random.Generator(np.random.PCG64(sn)).standard_normal((H, W))]
+    spec["theta_init"] = perturb(spec["theta_true"], spec["kinds"], spec["re_of"],
+                                 np.random.Generator(np.random.PCG64(si)))
     return spec
 
 

@@ -138,3 +138,11 @@ def grid_large_sub():
     spec["noise"] = [np.random.default_rng(2025).standard_normal((H, W))]
     spec["theta_init"] = synth.perturb(spec["theta_true"], spec["kinds"], spec["re_of"], np.random.default_rng(2026))
     return with_data(spec)
+
+
+def live_psf_small():
+    """Live Moffat PSF (n, R_d free) fitted with 6 bright stars, 2 galaxies and the sky on a
+    ragged 70 x 76 image, P = 15."""
+    spec = synth.live_psf(seed_id=107, H=70, W=76, n_star=6, n_sersic=2, P=15, psf_n=2.2, psf_rd=2.4,
+                          logf_range=(2.0, 3.0), logie_range=(0.5, 1.5))
+    return with_data(spec)

@@ -1,0 +1,102 @@
+"""Live PSF fitting (a Moffat PSF whose power n and scale R_d are fitted with the rest of
+the model) through the C ABI against the FP64 oracle: model, Jacobian (including the
+PSF columns (dK/dphi) * S), J^T W J, gradient, render VJP, covariance and a converged
+LM fit; an out-of-domain PSF parameter is reported."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import cases
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2308_01957_amd import apx as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def spec():
+    return cases.live_psf_small()
+
+
+def _problem(apx, spec):
+    print(f"[case] {spec['name']}", flush=True)
+    P = apx.Problem(spec)
+    return P, P.pixels(spec["data"]), P.pixels(spec["weight"])
+
+
+def test_live_psf_model_and_jacobian(apx, spec):
+    P, d, w = _problem(apx, spec)
+    th = spec["theta_init"]
+    m = P.split(P.render(th))[0].astype(np.float64)
+    mo = oracle.model_image(spec, th, 0)
+    assert np.all(np.abs(m - mo) <= cases.tol_pixels(mo)), float(np.max(np.abs(m - mo) / cases.tol_pixels(mo)))
+    J = P.jacobian(th).cpu().numpy().T.astype(np.float64)
+    Jo = oracle.jacobian(spec, th)
+    scale = np.maximum(np.max(np.abs(Jo), axis=0), 1e-30)
+    err = np.max(np.abs(J - Jo), axis=0) / scale
+    assert np.all(err <= 3e-5), (np.argmax(err), float(np.max(err)))
+    c2 = float(P.chi2(th, d, w).cpu()[0])
+    assert math.isclose(c2, float(oracle.chi2(spec, th, spec["data"], spec["weight"])[0]), rel_tol=1e-6)
+    P.check()
+
+
+def test_live_psf_normal_equations_gradient_vjp(apx, spec):
+    P, d, w = _problem(apx, spec)
+    th = spec["theta_init"]
+    A, g, _ = P.jtwj(th, d, w)
+    n = spec["n_par"]
+    A = A.cpu().numpy().reshape(n, n)
+    Ao, go, c2o = oracle.jtwj(spec, th, spec["data"], spec["weight"], 0)
+    sd = np.sqrt(np.diag(Ao))
+    assert np.all(np.abs(A - Ao) <= 1e-4 * np.outer(sd, sd))
+    assert np.all(np.abs(g.cpu().numpy() - go) <= 1e-4 * sd * math.sqrt(c2o))
+    gr, _ = P.chi2_grad(th, d, w)
+    gro = oracle.chi2_grad(spec, th, spec["data"], spec["weight"])
+    Jo = oracle.jacobian(spec, th)
+    r, wv = oracle.residual(spec, th, spec["data"], spec["weight"], [0])
+    tol = 1e-4 * np.maximum(np.abs(gro), 2.0 * (np.abs(wv * r) @ np.abs(Jo)))
+    assert np.all(np.abs(gr.cpu().numpy() - gro) <= tol), float(np.max(np.abs(gr.cpu().numpy() - gro) / tol))
+    seed = np.random.default_rng(79).standard_normal(P.n_pix).astype(np.float32)
+    v = P.render_vjp(th, seed).cpu().numpy()
+    s64 = seed.astype(np.float64)
+    vo = s64 @ Jo
+    tolv = 1e-4 * np.maximum(np.abs(vo), np.abs(s64) @ np.abs(Jo))
+    assert np.all(np.abs(v - vo) <= tolv), float(np.max(np.abs(v - vo) / tolv))
+    C, _ = P.covariance(th, d, w)
+    Co = np.linalg.inv(Ao)
+    E = 2e-5 * np.outer(sd, sd)
+    tolc = np.abs(Co) @ E @ np.abs(Co) + 1e-12 * np.abs(Co)
+    assert np.all(np.abs(C.cpu().numpy().reshape(n, n) - Co) <= tolc)
+    P.check()
+
+
+def test_live_psf_lm_converges_to_the_oracle_fit(apx, spec):
+    """Both fits converge (oracle Newton decrement < 1e-6) from the perturbed start and the
+    fitted parameters, the PSF's n and R_d among them, agree to 1e-6 (|theta| + scale)."""
+    P, d, w = _problem(apx, spec)
+    th, st = P.lm_init(spec["theta_init"], d, w)
+    P.lm_run(40, d, w, th, st)
+    P.check()
+    tg = th.cpu().numpy()
+    to, _ = oracle.lm_fit(spec, spec["theta_init"], spec["data"], spec["weight"], 40)
+    A, g, _ = oracle.jtwj(spec, to, spec["data"], spec["weight"], 0)
+    assert float(g @ np.linalg.solve(A, g)) < 1e-6
+    bad = np.abs(tg - to) > 1e-6 * (np.abs(to) + spec["scale"])
+    assert not bad.any(), (np.nonzero(bad), tg[bad], to[bad])
+
+
+def test_live_psf_out_of_domain_is_reported(apx, spec):
+    P, _, _ = _problem(apx, spec)
+    th = np.array(spec["theta_init"])
+    th[-2] = 50.0                      # Moffat power beyond 20
+    P.render(th)
+    with pytest.raises(apx.ApxError):
+        P.check()
