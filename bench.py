@@ -283,8 +283,14 @@ def run_single(args, torch, apx, synth):
                            "64x64, 1 Sersic + sky, Gaussian 11x11 sigma 1.5, 3x3 nodes, 8 params")
 
 
+def run_livepsf(args, torch, apx, synth):
+    return run_lm_workload(args, torch, apx, synth, synth.live_psf(), "livepsf",
+                           "512x512, 100 stars + 20 Sersic + sky, live Moffat PSF 25x25 with free power "
+                           "and scale, 243 params")
+
+
 OTHER_WORKLOADS = {"cutouts": run_cutouts, "field": run_field, "multiband": run_multiband,
-                   "single": run_single}
+                   "single": run_single, "livepsf": run_livepsf}
 
 
 def tile_choice(prob):
@@ -345,7 +351,7 @@ def main():
                     help="also launch three plain copy kernels of MIB MiB (read MIB, write MIB) "
                          "after the timed region, to calibrate HBM byte counters")
     ap.add_argument("--workload", default="blend",
-                    choices=["blend", "cutouts", "field", "multiband", "single"],
+                    choices=["blend", "cutouts", "field", "multiband", "single", "livepsf"],
                     help="blend (default, the headline line); the others print their own line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
