@@ -123,6 +123,52 @@ def test_gaussian_special_case_exact_pixel_integrals():
     assert 1e-5 * exact.max() < np.max(np.abs(mid - exact)) < 1e-2 * exact.max()
 
 
+def test_adaptive_integration_gaussian_within_budget():
+    """Adaptive mode (§2.1.2) on the circular Gaussian (n = 1/2, q = 1): every pixel within
+    its budget e = tol F / N of the exact erf integral, the image within tol F."""
+    x0, y0, re, lie = 7.3, 6.6, 2.2, 0.1
+    prm = [x0, y0, 1.0, 0.4, 0.5, re, lie]
+    sig = re / math.sqrt(2 * math.log(2))
+    H = W = 14
+    Phi = scipy.special.ndtr
+    px = Phi((np.arange(W) + 0.5 - x0) / sig) - Phi((np.arange(W) - 0.5 - x0) / sig)
+    py = Phi((np.arange(H) + 0.5 - y0) / sig) - Phi((np.arange(H) - 0.5 - y0) / sig)
+    exact = 2.0 * 10 ** lie * 2 * math.pi * sig * sig * np.outer(py, px)
+    spec = _render_spec(H, W, 1, [_sersic_comp(prm, (0, 0, H, W))], mode=oracle.MODE_ADAPTIVE, k=0.01)
+    v = oracle.render_ext(spec, None, 0)
+    e = 0.01 * v.sum() / (H * W)
+    assert np.max(np.abs(v - exact)) <= e
+    assert np.sum(np.abs(v - exact)) <= 0.01 * v.sum()
+    mid = oracle.render_ext(_render_spec(H, W, 1, [_sersic_comp(prm, (0, 0, H, W))], s=1), None, 0)
+    assert np.sum(np.abs(mid - exact)) > np.sum(np.abs(v - exact))      # the refinement helped
+
+
+def test_adaptive_integration_cusp_flux_and_flat_profile():
+    """n = 4 with Re = 1.5 px (a cusp): the image sum within tol F of a dense
+    Gauss-Legendre reference (25 x 25 sub-pixels of 8 x 8 nodes per pixel); a faint,
+    broad n = 1 profile needs no refinement and equals the centre sampling exactly."""
+    prm = [7.3, 8.2, 0.7, 0.5, 4.0, 1.5, 0.5]
+    H = W = 16
+    v = oracle.render_ext(_render_spec(H, W, 1, [_sersic_comp(prm, (0, 0, H, W))], mode=oracle.MODE_ADAPTIVE,
+                                       k=0.01), None, 0)
+    b = oracle.sersic_b(4.0)
+    o, w = oracle.nodes_1d(8, oracle.RULE_GAUSS_LEGENDRE)
+    sub = (np.arange(25) + 0.5) / 25 - 0.5
+    offs = (sub[:, None] + o[None, :] / 25).ravel()
+    wts = (np.ones(25)[:, None] * w[None, :] / 25).ravel()
+    yy, xx = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64), indexing="ij")
+    ref = np.zeros((H, W))
+    for ky, wy in zip(offs, wts):
+        r = oracle.sersic_profile(xx[..., None] + offs, yy[..., None] + ky, prm, b)
+        ref += wy * (r * wts).sum(-1)
+    assert abs(v.sum() - ref.sum()) <= 0.01 * v.sum()
+    flat = [20.0, 21.0, 0.8, 0.3, 0.5, 30.0, -1.0]
+    a = oracle.render_ext(_render_spec(40, 40, 1, [_sersic_comp(flat, (0, 0, 40, 40))], mode=oracle.MODE_ADAPTIVE,
+                                       k=0.01), None, 0)
+    c = oracle.render_ext(_render_spec(40, 40, 1, [_sersic_comp(flat, (0, 0, 40, 40))], s=1), None, 0)
+    assert np.array_equal(a, c)
+
+
 def test_general_sersic_pixel_vs_dblquad():
     """Brute-force 2-D quadrature of the profile over single pixels away from the cusp."""
     prm = [3.2, 2.7, 0.55, 0.9, 2.3, 2.5, -0.3]
@@ -345,6 +391,23 @@ def test_jacobian_matches_central_differences(aff):
         fd = (oracle.model_image(spec, tp, 0) - oracle.model_image(spec, tm, 0)).ravel() / (2 * h)
         scale = np.max(np.abs(J[:, p]))
         assert scale > 0
+        assert np.max(np.abs(fd - J[:, p])) < 1e-7 * scale, p
+
+
+def test_adaptive_jacobian_matches_central_differences():
+    """Adaptive mode: with the refinement choices held (the steps of the FD are far too
+    small to move a pixel across its budget), the analytic columns match central
+    differences."""
+    spec, theta = _small_problem(mode=oracle.MODE_ADAPTIVE)
+    spec["sampling"]["k"] = 0.01
+    J = oracle.jacobian(spec, theta)
+    for p in range(spec["n_par"]):
+        h = 1e-6 * max(abs(theta[p]), 0.1)
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = (oracle.model_image(spec, tp, 0) - oracle.model_image(spec, tm, 0)).ravel() / (2 * h)
+        scale = np.max(np.abs(J[:, p]))
         assert np.max(np.abs(fd - J[:, p])) < 1e-7 * scale, p
 
 
