@@ -87,6 +87,22 @@ typedef int32_t apx_status;
 #define APX_MODE_UNIFORM     0       /* s x s nodes in every pixel                   */
 #define APX_MODE_WITHIN_K_RE 1       /* s x s nodes where the pixel-centre R < k Re,
                                         the pixel centre alone elsewhere (§2.1.2)     */
+#define APX_MODE_ADAPTIVE    2       /* two-pass adaptive integration (§2.1.2), k_re is
+                                        the relative tolerance tol > 0; s and rule are
+                                        not used.  Per Sersic component: the pixel
+                                        centres give the window flux F and the error
+                                        budget e = tol F / N (N window pixels); a pixel
+                                        keeps its centre value when the second-difference
+                                        estimate of the midpoint error, area (|I(x+1) +
+                                        I(x-1) - 2 I| + |I(y+1) + I(y-1) - 2 I|) / 24, is
+                                        at most e, else takes 3 x 3 Gauss-Legendre when
+                                        that moves it by at most e, else is cut into
+                                        5 x 5 sub-pixels, each at 5 x 5 Gauss-Legendre
+                                        when within e of its 3 x 3 value, else the mean
+                                        of its 5 x 5 sub-sub-pixels at 7 x 7.  The choices
+                                        are made in FP64 at each theta; the derivatives
+                                        are those of the chosen rule (choices held
+                                        fixed).                                         */
 
 /* Precision of the objective path (render -> convolve -> chi^2 / residual).  The
  * Jacobian path (derivative images, their convolutions, J^T W J inputs) and the adjoint
@@ -154,7 +170,8 @@ typedef struct apx_problem_desc {
     int32_t mode;                   /* APX_MODE_*                                  */
     int32_t objective;              /* APX_OBJECTIVE_* (precision of the model used
                                        for chi^2, residuals and LM trials)          */
-    double  k_re;                   /* k of APX_MODE_WITHIN_K_RE                   */
+    double  k_re;                   /* k of APX_MODE_WITHIN_K_RE; tol of
+                                       APX_MODE_ADAPTIVE                             */
     int32_t n_psf_models;           /* live PSF models (0: every stamp is fixed)     */
     int32_t reserved;
     const apx_psf_model_desc* psf_models;   /* host, [n_psf_models]                 */

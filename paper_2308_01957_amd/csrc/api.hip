@@ -87,6 +87,10 @@ struct apx_problem {
     std::vector<float> node_o, node_w;
     std::vector<double> node_od, node_wd;
     std::vector<double> bn_tab;
+    std::vector<double> agl;                      // adaptive: GL 3/5/7 offsets and weights
+    std::vector<AChunk> achunks;
+    std::vector<int> acomp_chunk;
+    long long n_apix = 0;
 
     long long n_pix = 0, n_ext = 0, n_d = 0, n_j = 0, n_pairpart = 0, n_gradpart = 0, a_total = 0;
     long long n_psf = 0;
@@ -410,15 +414,35 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     if (d->s < 1 || d->s > MAX_NODES_1D) return fail(C, APX_E_UNSUPPORTED, "s must be in 1..8");
     if (d->rule != APX_RULE_MIDPOINT && d->rule != APX_RULE_GAUSS_LEGENDRE)
         return fail(C, APX_E_INVALID, "unknown node rule");
-    if (d->mode != APX_MODE_UNIFORM && d->mode != APX_MODE_WITHIN_K_RE)
+    if (d->mode != APX_MODE_UNIFORM && d->mode != APX_MODE_WITHIN_K_RE && d->mode != APX_MODE_ADAPTIVE)
         return fail(C, APX_E_INVALID, "unknown sampling mode");
-    if (d->mode == APX_MODE_WITHIN_K_RE && !(d->k_re > 0.0))
+    if (d->mode == APX_MODE_WITHIN_K_RE && !(d->k_re > 0.0 && std::isfinite(d->k_re)))
         return fail(C, APX_E_INVALID, "k_re must be > 0");
+    if (d->mode == APX_MODE_ADAPTIVE && !(d->k_re > 0.0 && std::isfinite(d->k_re)))
+        return fail(C, APX_E_INVALID, "adaptive tolerance (k_re) must be > 0");
     if (d->objective != APX_OBJECTIVE_FP64 && d->objective != APX_OBJECTIVE_FP32)
         return fail(C, APX_E_INVALID, "unknown objective precision");
 
-    // nodes
-    if (d->rule == APX_RULE_MIDPOINT) {
+    // nodes (adaptive mode: its 3 x 3 Gauss-Legendre level; the other levels use agl)
+    if (d->mode == APX_MODE_ADAPTIVE) {
+        P->s = 3;
+        P->rule = APX_RULE_GAUSS_LEGENDRE;
+        for (int order : {3, 5, 7}) {
+            std::vector<double> x, w;
+            gauss_legendre(order, x, w);
+            for (int k = 0; k < order; ++k) P->agl.push_back(x[k] / 2.0);
+            for (int k = 0; k < order; ++k) P->agl.push_back(w[k] / 2.0);
+        }
+    }
+    const int s_nodes = P->s;
+    if (d->mode == APX_MODE_ADAPTIVE) {
+        std::vector<double> x, w;
+        gauss_legendre(3, x, w);
+        for (int k = 0; k < 3; ++k) {
+            P->node_od.push_back(x[k] / 2.0);
+            P->node_wd.push_back(w[k] / 2.0);
+        }
+    } else if (d->rule == APX_RULE_MIDPOINT) {
         for (int k = 0; k < d->s; ++k) {
             P->node_od.push_back((k + 0.5) / d->s - 0.5);
             P->node_wd.push_back(1.0 / d->s);
@@ -431,7 +455,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             P->node_wd.push_back(w[k] / 2.0);
         }
     }
-    for (int k = 0; k < d->s; ++k) {
+    for (int k = 0; k < s_nodes; ++k) {
         P->node_o.push_back((float)P->node_od[k]);
         P->node_w.push_back((float)P->node_wd[k]);
     }
@@ -576,6 +600,23 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         if (y1 <= y0 || x1 <= x0) { y0 = x0 = y1 = x1 = 0; }
         c.box[0] = y0; c.box[1] = x0; c.box[2] = y1; c.box[3] = x1;
         P->comps[i] = c;
+    }
+
+    // adaptive integration: per-pixel arrays of the Sersic windows, cut into chunks
+    if (d->mode == APX_MODE_ADAPTIVE) {
+        P->acomp_chunk.assign(1, 0);
+        for (int i = 0; i < d->n_comps; ++i) {
+            DComp& c = P->comps[i];
+            const long long npx = (long long)(c.box[2] - c.box[0]) * (c.box[3] - c.box[1]);
+            c.aoff = P->n_apix;
+            if (c.type == APX_SERSIC) {
+                for (long long e = 0; e < npx; e += ADAPT_CHUNK) P->achunks.push_back(AChunk{i, (int)e});
+                P->n_apix += npx;
+            }
+            P->acomp_chunk.push_back((int)P->achunks.size());
+        }
+        if (P->n_apix >= (1LL << 31) || P->achunks.size() >= (size_t)INT32_MAX)
+            return fail(C, APX_E_UNSUPPORTED, "adaptive integration: too many window pixels");
     }
 
     // render tiles (extended grid) with component lists
@@ -1075,6 +1116,16 @@ static void layout(apx_problem* P) {
     ws_take<int>(P, "par_sky", P->par_sky.size());
     ws_take<int>(P, "small_subs", P->small_subs.size());
     ws_take<double>(P, "bn_tab", P->bn_tab.size());
+    ws_take<double>(P, "agl", P->agl.size());
+    ws_take<AChunk>(P, "achunks", P->achunks.size());
+    ws_take<int>(P, "acomp_chunk", P->acomp_chunk.size());
+    ws_take<double>(P, "apart", P->achunks.size());
+    ws_take<double>(P, "ae", P->agl.empty() ? 0 : P->comps.size());
+    ws_take<double>(P, "aval", P->n_apix);
+    ws_take<int>(P, "acode", P->n_apix);
+    ws_take<ARef>(P, "aref", P->n_apix);
+    ws_take<float>(P, "adval", 7 * P->n_apix);
+    ws_take<int>(P, "acount", 1);
     // buffers
     ws_take<CompConst>(P, "cc", P->comps.size());
     ws_take<float>(P, "S", P->n_ext);
@@ -1274,6 +1325,9 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     HIPCHK(upload(P, "par_sky", P->par_sky));
     HIPCHK(upload(P, "small_subs", P->small_subs));
     HIPCHK(upload(P, "bn_tab", P->bn_tab));
+    HIPCHK(upload(P, "agl", P->agl));
+    HIPCHK(upload(P, "achunks", P->achunks));
+    HIPCHK(upload(P, "acomp_chunk", P->acomp_chunk));
 
     Plan& p = P->plan;
     p = Plan{};
@@ -1338,6 +1392,18 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.sky_val = wsp<double>(P, "sky_val");
     p.par_sub = wsp<int>(P, "par_sub");
     p.bn_tab = wsp<double>(P, "bn_tab");
+    p.agl = wsp<double>(P, "agl");
+    p.achunks = wsp<AChunk>(P, "achunks");
+    p.n_achunks = (int)P->achunks.size();
+    p.acomp_chunk = wsp<int>(P, "acomp_chunk");
+    p.apart = wsp<double>(P, "apart");
+    p.ae = wsp<double>(P, "ae");
+    p.aval = wsp<double>(P, "aval");
+    p.acode = wsp<int>(P, "acode");
+    p.aref = wsp<ARef>(P, "aref");
+    p.adval = wsp<float>(P, "adval");
+    p.acount = wsp<int>(P, "acount");
+    p.n_apix = P->n_apix;
     p.n_pix = P->n_pix;
     p.n_ext = P->n_ext;
     P->chi2_sub = wsp<double>(P, "chi2_sub");
@@ -1445,16 +1511,30 @@ static SegSum segsum_base() {
     return a;
 }
 
-// Forward model + residual partials, reduced to img_sum (3 per image) and chi2[n_sub].
-static apx_status fwd_chi2(apx_problem* P, const double* theta, const float* data, const float* weight,
-                           float* model, double* chi2_out, int lm_trial, int skip_mode,
-                           const apx_lm_state* lm) {
+// Per-theta constants (component constants, stamps) and, in adaptive mode, the
+// integration choices and values; want_grad: the refined pixels' derivatives too.
+static apx_status prep(apx_problem* P, const double* theta, int lm_trial, int skip_mode,
+                       const apx_lm_state* lm, int want_grad) {
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
     {
         TimeScope ts(P, APX_TIME_PREP);
         HIPCHK(launch_prep(p, theta, lm_trial, st));
     }
+    if (P->mode == APX_MODE_ADAPTIVE) {
+        TimeScope ts(P, APX_TIME_RENDER);
+        HIPCHK(launch_adapt(p, skip_mode, lm, want_grad, st));
+    }
+    return APX_OK;
+}
+
+// Forward model + residual partials, reduced to img_sum (3 per image) and chi2[n_sub].
+static apx_status fwd_chi2(apx_problem* P, const double* theta, const float* data, const float* weight,
+                           float* model, double* chi2_out, int lm_trial, int skip_mode,
+                           const apx_lm_state* lm, int want_grad) {
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    APXCHK(prep(P, theta, lm_trial, skip_mode, lm, want_grad));
     {
         TimeScope ts(P, APX_TIME_RENDER);
         if (P->objective == APX_OBJECTIVE_FP64) HIPCHK(launch_render64(p, skip_mode, lm, st));
@@ -1610,14 +1690,14 @@ static bool par_ok(const apx_problem* P, const void* ptr) { return ptr != nullpt
 apx_status apx_render(apx_problem* P, const double* theta, float* model) {
     APXCHK(ready(P));
     if (!par_ok(P, theta) || !model) return fail(P->ctx, APX_E_INVALID, "null pointer");
-    return fwd_chi2(P, theta, nullptr, nullptr, model, nullptr, 0, 0, nullptr);
+    return fwd_chi2(P, theta, nullptr, nullptr, model, nullptr, 0, 0, nullptr, 0);
 }
 
 apx_status apx_chi2(apx_problem* P, const double* theta, const float* data, const float* weight,
                     double* chi2) {
     APXCHK(ready(P));
     if (!par_ok(P, theta) || !data || !weight || !chi2) return fail(P->ctx, APX_E_INVALID, "null pointer");
-    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr, 0));
     HIPCHK(launch_chi2_check(chi2, P->n_sub, P->plan.sticky, P->ctx->stream));
     return APX_OK;
 }
@@ -1627,7 +1707,7 @@ apx_status apx_jacobian(apx_problem* P, const double* theta, float* J, int64_t l
     if (!par_ok(P, theta) || !par_ok(P, J)) return fail(P->ctx, APX_E_INVALID, "null pointer");
     if (ldJ < P->n_pix) return fail(P->ctx, APX_E_INVALID, "ldJ < n_pix");
     hipStream_t st = P->ctx->stream;
-    HIPCHK(launch_prep(P->plan, theta, 0, st));
+    APXCHK(prep(P, theta, 0, 0, nullptr, 1));
     APXCHK(jac_blocks(P, nullptr, nullptr));
     HIPCHK(launch_jscatter(P->plan, wsp<int>(P, "par_off"), wsp<int>(P, "par_cols"), wsp<int>(P, "par_sky_off"),
                            wsp<int>(P, "par_sky"), J, ldJ, st));
@@ -1639,7 +1719,7 @@ apx_status apx_jtwj(apx_problem* P, const double* theta, const float* data, cons
     APXCHK(ready(P));
     if (!par_ok(P, theta) || !data || !weight || !par_ok(P, JtWJ) || !par_ok(P, JtWr) || !chi2)
         return fail(P->ctx, APX_E_INVALID, "null pointer");
-    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr, 1));
     APXCHK(jac_blocks(P, weight, nullptr));
     APXCHK(normal_eq(P, weight, JtWJ, JtWr, nullptr));
     HIPCHK(launch_chi2_check(chi2, P->n_sub, P->plan.sticky, P->ctx->stream));
@@ -1653,7 +1733,7 @@ apx_status apx_covariance(apx_problem* P, const double* theta, const float* data
         return fail(P->ctx, APX_E_INVALID, "null pointer");
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
-    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr, 1));
     APXCHK(jac_blocks(P, weight, nullptr));
     APXCHK(normal_eq(P, weight, p.A, p.gvec, nullptr));
     {
@@ -1678,7 +1758,7 @@ apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data,
         return fail(P->ctx, APX_E_INVALID, "null pointer");
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
-    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr));
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr, 1));
     HIPCHK(launch_flip_psf(p, st));
     ConvIO io{};
     io.out = p.Abar;
@@ -1715,10 +1795,7 @@ apx_status apx_render_vjp(apx_problem* P, const double* theta, const float* grad
     if (!par_ok(P, theta) || !grad_model || !par_ok(P, grad_theta)) return fail(P->ctx, APX_E_INVALID, "null pointer");
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
-    {
-        TimeScope ts(P, APX_TIME_PREP);
-        HIPCHK(launch_prep(p, theta, 0, st));
-    }
+    APXCHK(prep(P, theta, 0, 0, nullptr, 1));
     HIPCHK(launch_flip_psf(p, st));
     ConvIO io{};
     io.out = p.Abar;
@@ -1757,7 +1834,7 @@ apx_status apx_lm_init(apx_problem* P, const double* theta, const float* data, c
                        apx_lm_state* state) {
     APXCHK(ready(P));
     if (!par_ok(P, theta) || !data || !weight || !state) return fail(P->ctx, APX_E_INVALID, "null pointer");
-    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, P->chi2_sub, 0, 0, nullptr));
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, P->chi2_sub, 0, 0, nullptr, 0));
     HIPCHK(launch_lm_init(P->plan, P->chi2_sub, state, P->ctx->stream));
     return APX_OK;
 }
@@ -1771,10 +1848,7 @@ static apx_status lm_step_enqueue(apx_problem* P, const float* data, const float
         HIPCHK(launch_lm_begin(p, state, st));
     }
     // normal equations at theta for sub-problems whose last step was accepted
-    {
-        TimeScope ts(P, APX_TIME_PREP);
-        HIPCHK(launch_prep(p, theta, 0, st));
-    }
+    APXCHK(prep(P, theta, 0, 2, state, 1));
     APXCHK(jac_blocks(P, weight, state));
     APXCHK(normal_eq(P, weight, p.A, p.gvec, state));
     // damped solves
@@ -1788,7 +1862,7 @@ static apx_status lm_step_enqueue(apx_problem* P, const float* data, const float
         TimeScope ts(P, APX_TIME_LM);
         HIPCHK(launch_lm_trial(p, theta, state, st));
     }
-    APXCHK(fwd_chi2(P, p.theta_trial, data, weight, nullptr, P->chi2_trial, 1, 1, state));
+    APXCHK(fwd_chi2(P, p.theta_trial, data, weight, nullptr, P->chi2_trial, 1, 1, state, 0));
     {
         TimeScope ts(P, APX_TIME_LM);
         HIPCHK(launch_lm_accept(p, P->chi2_trial, theta, state, st));

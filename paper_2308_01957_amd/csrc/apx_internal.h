@@ -64,6 +64,7 @@ struct DComp {
     int group;                // Jacobian group, -1 when the component has no free parameter
     int col[7];               // column of local parameter k inside its group, -1 = fixed
     int sub, pad;
+    long long aoff;           // adaptive mode: first entry of the window in the per-pixel arrays
     double fixed[7];
 };
 
@@ -116,6 +117,12 @@ struct DPair {
     int y0, x0, y1, x1;       // intersection of the two output boxes
 };
 struct PairItem { int pair, ta, tb, r0, r1, pad; long long out_off; };
+
+// Adaptive integration: the Sersic windows cut into chunks of up to ADAPT_CHUNK pixels
+// (row-major window order); a pixel that needs sub-pixels is appended to the refine list.
+constexpr int ADAPT_CHUNK = 256;
+struct AChunk { int comp, start; };
+struct ARef { int comp, idx; };
 
 struct DSub { int p0, n; long long a_off; int large, flag_off; };   // flag_off: 2 x blocks of sflag
 
@@ -182,6 +189,19 @@ struct Plan {
     const int* par_sub;       // [n_par] sub-problem of each theta index (-1: none)
     const double* bn_tab;     // [2 * BN_COUNT]: b_n, db_n/dn at the table nodes
 
+    // adaptive integration (mode APX_MODE_ADAPTIVE, tolerance k_re)
+    const double* agl;        // Gauss-Legendre offsets / weights on [-1/2, 1/2]: o3 w3 o5 w5 o7 w7
+    const AChunk* achunks; int n_achunks;
+    const int* acomp_chunk;   // [n_comps + 1]: chunks of each component (CSR)
+    double* apart;            // [n_achunks] window-flux partials
+    double* ae;               // [n_comps] error budget e = tol F / N
+    double* aval;             // [n_apix] pixel value (mean of the profile, before the area)
+    int* acode;               // [n_apix] 0 centre, 1 3 x 3, -1 - r: refine entry r
+    ARef* aref;               // [n_apix] refine list
+    float* adval;             // [7 n_apix] derivatives of refined pixels (before the area)
+    int* acount;              // refine-list length
+    long long n_apix;
+
     long long n_pix, n_ext;
 };
 
@@ -190,6 +210,14 @@ constexpr int FLAG_DOMAIN = 1, FLAG_NONFINITE = 2, FLAG_STALL = 4;
 // live Moffat PSF domain
 constexpr double PSF_N_MIN = 0.2, PSF_N_MAX = 20.0, PSF_RD_MIN = 0.05, PSF_RD_MAX = 1e3;
 constexpr int GROUP_PSF = 2;                   // DGroup.type of the live-PSF columns of an image
+
+// skip_mode of the launchers: 0 none, 1 sub-problems without a valid trial (the trial
+// render), 2 sub-problems that keep their Jacobian (lm[sub].need_jac == 0)
+__device__ __forceinline__ bool sub_skipped(const Plan& p, int sub, int mode, const apx_lm_state* lm) {
+    if (mode == 1) return p.lmf[sub].chol_done == 0 || p.lmf[sub].trial_bad != 0;
+    if (mode == 2) return lm[sub].need_jac == 0;
+    return false;
+}
 
 // Launchers (each returns hipGetLastError()) ----------------------------------------
 // k_model.hip
@@ -200,6 +228,10 @@ hipError_t launch_render64(const Plan& p, int skip_mode, const apx_lm_state* lm,
 hipError_t launch_deriv(const Plan& p, const apx_lm_state* lm, hipStream_t st);
 hipError_t launch_grad_tiles(const Plan& p, hipStream_t st);
 hipError_t launch_flip_psf(const Plan& p, hipStream_t st);
+
+// k_adapt.hip: error budgets, choices and values of the adaptive integration at the
+// current theta (after launch_prep); want_grad also forms the refined pixels' derivatives
+hipError_t launch_adapt(const Plan& p, int skip_mode, const apx_lm_state* lm, int want_grad, hipStream_t st);
 // per image: img_sum[3 k + 1] = -sum(seed) / 2, so that the image-sum terms of the gradient
 // assembly (weight -2) give the seed's sum (the sky column of a vector-Jacobian product)
 hipError_t launch_seed_sums(const Plan& p, const float* seed, double* part, hipStream_t st);

@@ -10,6 +10,7 @@
 // so the FP32 result carries only the transcendentals' rounding.
 // Pixel integration (§2.1.2): area * sum_k w_k I(node_k) over s x s nodes.
 #include "apx_internal.h"
+#include "sersic64.h"
 
 namespace apx {
 
@@ -250,13 +251,33 @@ __device__ __forceinline__ float sersic_pixel(const Plan& p, const CompConst& c,
     return sum;
 }
 
+// Window-pixel index of (y, x) in the adaptive-integration arrays.
+__device__ __forceinline__ long long adapt_index(const DComp& cp, int y, int x) {
+    return cp.aoff + (long long)(y - cp.box[0]) * (cp.box[3] - cp.box[1]) + (x - cp.box[1]);
+}
+
 __device__ __forceinline__ void sersic_pixel_grad(const Plan& p, const CompConst& c, const DImage& im,
-                                                  double ucx, double ucy, float acc[7]) {
+                                                  const DComp& cp, int y, int x, double ucx, double ucy,
+                                                  float acc[7]) {
     for (int k = 0; k < 7; ++k) acc[k] = 0.f;
     const float dxc = (float)(ucx - c.x0), dyc = (float)(ucy - c.y0);
     if (p.mode == APX_MODE_WITHIN_K_RE && !within_kre(c, ucx, ucy)) {
         sersic_dI(c, dxc, dyc, 1.f, acc);
         return;
+    }
+    if (p.mode == APX_MODE_ADAPTIVE) {
+        // the rule chosen at this theta: centre, 3 x 3 (the s x s nodes below), or refined
+        const int code = p.acode[adapt_index(cp, y, x)];
+        if (code == 0) {
+            sersic_dI(c, dxc, dyc, 1.f, acc);
+            return;
+        }
+        if (code < 0) {
+            const long long r = -1LL - code;          // refine entry (always < n_apix)
+            const float* dv = p.adval + 7LL * (r < p.n_apix ? r : 0);
+            for (int k = 0; k < 7; ++k) acc[k] = r < p.n_apix ? dv[k] : __builtin_nanf("");
+            return;
+        }
     }
     const float a1 = (float)im.aff[1], a2 = (float)im.aff[2], a4 = (float)im.aff[4], a5 = (float)im.aff[5];
     for (int ky = 0; ky < p.s; ++ky) {
@@ -273,12 +294,6 @@ __device__ __forceinline__ double point_weight(const CompConst& c, int y, int x)
     const double wx = fmax(0.0, 1.0 - fabs((double)x - c.x0));
     const double wy = fmax(0.0, 1.0 - fabs((double)y - c.y0));
     return wx * wy;
-}
-
-__device__ __forceinline__ bool sub_skipped(const Plan& p, int sub, int mode, const apx_lm_state* lm) {
-    if (mode == 1) return p.lmf[sub].chol_done == 0 || p.lmf[sub].trial_bad != 0;
-    if (mode == 2) return lm[sub].need_jac == 0;
-    return false;
 }
 
 // ----------------------------------------------------------------------- render
@@ -300,7 +315,9 @@ __global__ __launch_bounds__(256) void k_render(Plan p, int skip_mode, const apx
         if (y < cp.box[0] || y >= cp.box[2] || x < cp.box[1] || x >= cp.box[3]) continue;
         const CompConst& c = p.cc[ci];
         if (!c.valid) { sum += __builtin_nan(""); continue; }
-        if (cp.type == APX_SERSIC) sum += (double)sersic_pixel(p, c, im, ucx, ucy) * im.area;
+        if (cp.type == APX_SERSIC)
+            sum += (p.mode == APX_MODE_ADAPTIVE ? p.aval[adapt_index(cp, y, x)]
+                                                : (double)sersic_pixel(p, c, im, ucx, ucy)) * im.area;
         else sum += (double)c.F * point_weight(c, y, x);
     }
     p.S[im.ext_off + (long long)(y + im.c) * im.EW + (x + im.c)] = (float)sum;
@@ -316,14 +333,6 @@ hipError_t launch_render_mode(const Plan& p, int skip_mode, const apx_lm_state* 
 // The same pixel integral in double precision throughout (FP64 log2/exp2), for the
 // objective path: chi^2 differences of the LM gain ratio are resolved far below FP32
 // rounding.
-__device__ __forceinline__ double sersic_I64(const CompConst& c, double dx, double dy) {
-    const double xp = dx * c.cs_d + dy * c.sn_d;
-    const double yq = (-dx * c.sn_d + dy * c.cs_d) / c.q_d;
-    const double R2 = fmax(xp * xp + yq * yq, 1e-12);
-    const double t = exp2(c.g_d * log2(R2) - c.h_d);
-    return exp2(c.A_d - c.B_d * t);
-}
-
 __device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst& c, const DImage& im,
                                                  double ucx, double ucy) {
     const double dxc = ucx - c.x0, dyc = ucy - c.y0;
@@ -359,7 +368,9 @@ __global__ __launch_bounds__(256) void k_render64(Plan p, int skip_mode, const a
         if (y < cp.box[0] || y >= cp.box[2] || x < cp.box[1] || x >= cp.box[3]) continue;
         const CompConst& c = p.cc[ci];
         if (!c.valid) { sum += __builtin_nan(""); continue; }
-        if (cp.type == APX_SERSIC) sum += sersic_pixel64(p, c, im, ucx, ucy) * im.area;
+        if (cp.type == APX_SERSIC)
+            sum += (p.mode == APX_MODE_ADAPTIVE ? p.aval[adapt_index(cp, y, x)]
+                                                : sersic_pixel64(p, c, im, ucx, ucy)) * im.area;
         else sum += (double)c.F64 * point_weight(c, y, x);
     }
     p.S64[im.ext_off + (long long)(y + im.c) * im.EW + (x + im.c)] = sum;
@@ -393,7 +404,7 @@ __global__ __launch_bounds__(256) void k_deriv(Plan p, const apx_lm_state* lm) {
         const CompConst& c = p.cc[ci];
         if (cp.type == APX_SERSIC) {
             float acc[7];
-            sersic_pixel_grad(p, c, im, ucx, ucy, acc);
+            sersic_pixel_grad(p, c, im, cp, y, x, ucx, ucy, acc);
             const float area = (float)im.area;
             for (int q = 0; q < 7; ++q)
                 if (cp.col[q] >= 0) Dg[cp.col[q] * plane] = acc[q] * area;
@@ -438,7 +449,7 @@ __global__ __launch_bounds__(256) void k_grad_tiles(Plan p) {
         double v[7];
         if (cp.type == APX_SERSIC) {
             float acc[7];
-            if (inside) sersic_pixel_grad(p, c, im, ucx, ucy, acc);
+            if (inside) sersic_pixel_grad(p, c, im, cp, y, x, ucx, ucy, acc);
             else for (int q = 0; q < 7; ++q) acc[q] = 0.f;
             for (int q = 0; q < 7; ++q) v[q] = (double)acc[q] * im.area * (double)abar;
         } else {

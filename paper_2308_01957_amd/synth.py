@@ -47,6 +47,7 @@ RULE_GAUSS_LEGENDRE = 1
 
 MODE_UNIFORM = 0
 MODE_WITHIN_K_RE = 1
+MODE_ADAPTIVE = 2            # two-pass adaptive integration, k = tolerance
 
 # parameter kinds (used for tolerances, perturbation and domain checks)
 K_X, K_Y, K_Q, K_PA, K_N, K_RE, K_LOGIE, K_LOGF, K_SKY, K_PSF_N, K_PSF_RD = range(11)

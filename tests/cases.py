@@ -146,3 +146,23 @@ def live_psf_small():
     spec = synth.live_psf(seed_id=107, H=70, W=76, n_star=6, n_sersic=2, P=15, psf_n=2.2, psf_rd=2.4,
                           logf_range=(2.0, 3.0), logie_range=(0.5, 1.5))
     return with_data(spec)
+
+
+def adaptive_small(tol=1e-3):
+    """Adaptive integration (tolerance tol) on a ragged 64 x 72 blend: a steep n ~ 5.9
+    Sersic at the image edge, two more Sersics (one with a window cut by the extended
+    grid), three point sources and the sky; P = 9."""
+    spec = synth.blend(seed_id=108, H=64, W=72, n_sersic=3, n_point=3, P=9, mode=synth.MODE_ADAPTIVE,
+                       k_re=tol)
+    spec["comps"][1]["box"] = (-4, 10, 50, 80)
+    spec["name"] = f"adaptive64x72_tol{tol:g}"
+    return with_data(spec)
+
+
+def adaptive_fit():
+    """Adaptive integration, tol = 1e-2, on a 56 x 60 blend of two bright Sersics, two point
+    sources and the sky that the LM settles from the perturbed start; P = 9."""
+    spec = synth.blend(seed_id=110, H=56, W=60, n_sersic=2, n_point=2, P=9, mode=synth.MODE_ADAPTIVE,
+                       k_re=1e-2, logie_range=(0.5, 1.5))
+    spec["name"] = "adaptive56x60_fit"
+    return with_data(spec)

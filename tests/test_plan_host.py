@@ -50,6 +50,9 @@ def test_plan_sizes_match_the_layout(apx):
     (lambda s: s["images"][0].__setitem__("affine", np.array([0, 1.0, 2.0, 0, 0.5, 1.0])), -1),  # singular map
     (lambda s: s["sampling"].__setitem__("s", 9), -5),                                  # too many nodes
     (lambda s: s["comps"][0].__setitem__("type", 7), -1),                               # unknown type
+    (lambda s: s.__setitem__("sampling", dict(s=3, rule=0, mode=2, k=0.0)), -1),         # adaptive tol 0
+    (lambda s: s.__setitem__("sampling", dict(s=3, rule=0, mode=2, k=float("nan"))), -1),  # adaptive tol NaN
+    (lambda s: s.__setitem__("sampling", dict(s=3, rule=0, mode=3, k=1.0)), -1),         # unknown mode
 ])
 def test_invalid_descriptors(apx, mutate, status):
     spec = copy.deepcopy(_small())
@@ -102,3 +105,16 @@ def test_model_tile_policy_prefers_tiles_that_fit_the_output(apx):
 def test_unknown_tile_policy_is_rejected(apx):
     with pytest.raises(apx.ApxError):
         apx.Plan(_small(), tiles=99)
+
+
+def test_adaptive_mode_sizes_its_per_pixel_arrays(apx):
+    """Adaptive integration keeps, per Sersic window pixel, a value, a choice code and room
+    for a refine entry and its 7 derivatives: the workspace grows by at least 48 bytes per
+    window pixel over the uniform plan of the same problem."""
+    spec = _small()
+    base = apx.Plan(spec).workspace_bytes
+    spec["sampling"] = dict(s=3, rule=0, mode=synth.MODE_ADAPTIVE, k=1e-3)
+    ad = apx.Plan(spec).workspace_bytes
+    npx = sum((c["box"][2] - c["box"][0]) * (c["box"][3] - c["box"][1])
+              for c in spec["comps"] if c["type"] == 0)
+    assert npx > 0 and ad - base >= 48 * npx - 16 * 256       # less the empty arrays of the base plan
