@@ -289,8 +289,15 @@ def run_livepsf(args, torch, apx, synth):
                            "and scale, 243 params")
 
 
+def run_adaptive(args, torch, apx, synth):
+    spec = synth.blend(mode=synth.MODE_ADAPTIVE, k_re=1e-2)
+    return run_lm_workload(args, torch, apx, synth, spec, "adaptive",
+                           "512x512, 50 Sersic + 200 point sources + sky, Moffat 25x25, adaptive "
+                           "integration with budget 0.01 F / N, 551 params")
+
+
 OTHER_WORKLOADS = {"cutouts": run_cutouts, "field": run_field, "multiband": run_multiband,
-                   "single": run_single, "livepsf": run_livepsf}
+                   "single": run_single, "livepsf": run_livepsf, "adaptive": run_adaptive}
 
 
 def tile_choice(prob):
@@ -351,7 +358,7 @@ def main():
                     help="also launch three plain copy kernels of MIB MiB (read MIB, write MIB) "
                          "after the timed region, to calibrate HBM byte counters")
     ap.add_argument("--workload", default="blend",
-                    choices=["blend", "cutouts", "field", "multiband", "single", "livepsf"],
+                    choices=["blend", "cutouts", "field", "multiband", "single", "livepsf", "adaptive"],
                     help="blend (default, the headline line); the others print their own line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -1121,7 +1121,9 @@ static void layout(apx_problem* P) {
     ws_take<int>(P, "acomp_chunk", P->acomp_chunk.size());
     ws_take<double>(P, "apart", P->achunks.size());
     ws_take<double>(P, "ae", P->agl.empty() ? 0 : P->comps.size());
+    ws_take<double>(P, "av0", P->n_apix);
     ws_take<double>(P, "aval", P->n_apix);
+    ws_take<int>(P, "aneed", P->n_apix);
     ws_take<int>(P, "acode", P->n_apix);
     ws_take<ARef>(P, "aref", P->n_apix);
     ws_take<float>(P, "adval", 7 * P->n_apix);
@@ -1398,7 +1400,9 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.acomp_chunk = wsp<int>(P, "acomp_chunk");
     p.apart = wsp<double>(P, "apart");
     p.ae = wsp<double>(P, "ae");
+    p.av0 = wsp<double>(P, "av0");
     p.aval = wsp<double>(P, "aval");
+    p.aneed = wsp<int>(P, "aneed");
     p.acode = wsp<int>(P, "acode");
     p.aref = wsp<ARef>(P, "aref");
     p.adval = wsp<float>(P, "adval");

@@ -195,7 +195,9 @@ struct Plan {
     const int* acomp_chunk;   // [n_comps + 1]: chunks of each component (CSR)
     double* apart;            // [n_achunks] window-flux partials
     double* ae;               // [n_comps] error budget e = tol F / N
+    double* av0;              // [n_apix] profile at the pixel centre
     double* aval;             // [n_apix] pixel value (mean of the profile, before the area)
+    int* aneed;               // [n_apix] per refine entry: mask of the sub-pixels taken at 7 x 7
     int* acode;               // [n_apix] 0 centre, 1 3 x 3, -1 - r: refine entry r
     ARef* aref;               // [n_apix] refine list
     float* adval;             // [7 n_apix] derivatives of refined pixels (before the area)

@@ -6,17 +6,19 @@
 // and FP32 renders, derivative images, adjoint contraction) reads them, so the model and
 // its derivatives always use the same rule (the derivatives are those of the chosen rule).
 //
-//   k_adapt_flux / k_adapt_fold  F = area * sum of centre values over the window (ordered
-//                                 chunk sums), e = tol F / N
-//   k_adapt_pix                  one thread per window pixel: centre value; the midpoint
-//                                 error estimate area * (|I(x+1) + I(x-1) - 2 I| +
-//                                 |I(y+1) + I(y-1) - 2 I|) / 24 against e; 3 x 3
+//   k_adapt_flux / k_adapt_fold  centre values of the window (stored), F = area * their
+//                                 sum (ordered chunk sums), e = tol F / N
+//   k_adapt_pix                  one thread per window pixel: the midpoint error estimate
+//                                 area * (|I(x+1) + I(x-1) - 2 I| + |I(y+1) + I(y-1) - 2 I|)
+//                                 / 24 against e (neighbours inside the window read from the
+//                                 stored centre values, the same numbers); 3 x 3
 //                                 Gauss-Legendre if it moves the value by at most e;
 //                                 otherwise the pixel joins the refine list
 //   k_adapt_refine               one workgroup per listed pixel: its 5 x 5 sub-pixels take
 //                                 5 x 5 Gauss-Legendre when within e of their 3 x 3 value,
-//                                 the others the mean of their 5 x 5 sub-sub-pixels at 7 x 7;
-//                                 optionally the 7 parameter derivatives of that rule
+//                                 the others the mean of their 5 x 5 sub-sub-pixels at 7 x 7
+//   k_adapt_refine_grad          the 7 parameter derivatives of the rule each listed pixel
+//                                 took (only where derivatives are wanted)
 //
 // Values and derivatives are stored before the pixel-area factor.  The refine list is
 // filled by an atomic counter, so its order varies between runs, but each entry's result
@@ -66,7 +68,10 @@ __global__ __launch_bounds__(ADAPT_CHUNK) void k_adapt_flux(Plan p, int skip_mod
     const int npx = (cp.box[2] - cp.box[0]) * bw;
     const int e = ch.start + (int)threadIdx.x;
     double v = 0.0;
-    if (e < npx) v = prof_at(c, im, (double)(cp.box[1] + e % bw), (double)(cp.box[0] + e / bw));
+    if (e < npx) {
+        v = prof_at(c, im, (double)(cp.box[1] + e % bw), (double)(cp.box[0] + e / bw));
+        p.av0[cp.aoff + e] = v;
+    }
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -110,12 +115,17 @@ __global__ __launch_bounds__(ADAPT_CHUNK) void k_adapt_pix(Plan p, int skip_mode
         p.acode[cp.aoff + e] = 0;
         return;
     }
-    const double x = (double)(cp.box[1] + e % bw), y = (double)(cp.box[0] + e / bw);
+    const int ix = e % bw, iy = e / bw, bh = cp.box[2] - cp.box[0];
+    const double x = (double)(cp.box[1] + ix), y = (double)(cp.box[0] + iy);
     const double area = im.area, budget = p.ae[ch.comp];
     const long long gi = cp.aoff + e;
-    const double v0 = prof_at(c, im, x, y);
-    const double est = area * (fabs(prof_at(c, im, x + 1.0, y) + prof_at(c, im, x - 1.0, y) - 2.0 * v0) +
-                               fabs(prof_at(c, im, x, y + 1.0) + prof_at(c, im, x, y - 1.0) - 2.0 * v0)) / 24.0;
+    const double* c0 = p.av0 + gi;
+    const double v0 = c0[0];
+    const double xp1 = ix + 1 < bw ? c0[1] : prof_at(c, im, x + 1.0, y);
+    const double xm1 = ix > 0 ? c0[-1] : prof_at(c, im, x - 1.0, y);
+    const double yp1 = iy + 1 < bh ? c0[bw] : prof_at(c, im, x, y + 1.0);
+    const double ym1 = iy > 0 ? c0[-bw] : prof_at(c, im, x, y - 1.0);
+    const double est = area * (fabs(xp1 + xm1 - 2.0 * v0) + fabs(yp1 + ym1 - 2.0 * v0)) / 24.0;
     if (est <= budget) {
         p.aval[gi] = v0;
         p.acode[gi] = 0;
@@ -159,7 +169,7 @@ __device__ __forceinline__ void node7(const Plan& p, const int* need_list, doubl
     wgt = (w7[k % 7] * w7[k / 7]) * 0.04;              // sub-sub-pixel mean over 25
 }
 
-__global__ __launch_bounds__(REFINE_THREADS) void k_adapt_refine(Plan p, int want_grad) {
+__global__ __launch_bounds__(REFINE_THREADS) void k_adapt_refine(Plan p) {
     __shared__ double nv[N_G3 + N_G5];
     __shared__ double g5s[25];
     __shared__ int need_list[25];
@@ -203,10 +213,14 @@ __global__ __launch_bounds__(REFINE_THREADS) void k_adapt_refine(Plan p, int wan
         }
         __syncthreads();
         if (t == 0) {
-            int k = 0;
+            int k = 0, mask = 0;
             for (int j = 0; j < 25; ++j)
-                if (flags[j]) need_list[k++] = j;
+                if (flags[j]) {
+                    need_list[k++] = j;
+                    mask |= 1 << j;
+                }
             n_need = k;
+            p.aneed[r] = mask;
         }
         __syncthreads();
         const int T7 = n_need * N_G7;
@@ -224,26 +238,62 @@ __global__ __launch_bounds__(REFINE_THREADS) void k_adapt_refine(Plan p, int wan
                 if (!flags[j]) s5 += g5s[j];
             p.aval[cp.aoff + ar.idx] = (s5 + s7) / 25.0;
         }
-        // phase 3: the derivatives of the same rule
-        if (want_grad) {
-            double acc[7] = {0, 0, 0, 0, 0, 0, 0}, vv = 0.0;
-            for (int q = t; q < T7; q += REFINE_THREADS) {
-                double px, py, wgt, ux, uy;
+        __syncthreads();                    // LDS reuse by the next entry
+    }
+}
+
+// The derivatives of the rule each listed pixel took: 7 x 7 nodes of its refined
+// sub-pixels, 5 x 5 nodes of the others, all in one strided node range.
+__global__ __launch_bounds__(REFINE_THREADS) void k_adapt_refine_grad(Plan p) {
+    __shared__ int need_list[25], keep_list[25];
+    __shared__ int n_need;
+    __shared__ double red[REFINE_THREADS / 64][7];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int count = p.acount[0];
+    const double* o5 = p.agl + 6;
+    const double* w5 = p.agl + 11;
+    for (int r = blockIdx.x; r < count; r += gridDim.x) {
+        const ARef ar = p.aref[r];
+        const DComp& cp = p.comps[ar.comp];
+        const CompConst& c = p.cc[ar.comp];
+        const DImage& im = p.images[cp.image];
+        const int bw = cp.box[3] - cp.box[1];
+        const double x = (double)(cp.box[1] + ar.idx % bw), y = (double)(cp.box[0] + ar.idx / bw);
+        if (t == 0) {
+            const int mask = p.aneed[r];
+            int a = 0, b = 0;
+            for (int j = 0; j < 25; ++j) {
+                if ((mask >> j) & 1) need_list[a++] = j;
+                else keep_list[b++] = j;
+            }
+            n_need = a;
+        }
+        __syncthreads();
+        const int T7 = n_need * N_G7, T = T7 + (25 - n_need) * 25;
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0}, vv = 0.0;
+        for (int q = t; q < T; q += REFINE_THREADS) {
+            double px, py, wgt, ux, uy;
+            if (q < T7) {
                 node7(p, need_list, x, y, q, px, py, wgt);
-                to_sky(im, px, py, ux, uy);
-                sersic_dI64(c, ux - c.x0, uy - c.y0, wgt, vv, acc);
+            } else {
+                const int j = keep_list[(q - T7) / 25], k = (q - T7) % 25;
+                px = x + sub_off(j % 5) + 0.2 * o5[k % 5];
+                py = y + sub_off(j / 5) + 0.2 * o5[k / 5];
+                wgt = w5[k % 5] * w5[k / 5];
             }
-            for (int q = t; q < 25 * 25; q += REFINE_THREADS) {
-                const int j = q / 25, k = q % 25;
-                if (flags[j]) continue;
-                double ux, uy;
-                to_sky(im, x + sub_off(j % 5) + 0.2 * o5[k % 5], y + sub_off(j / 5) + 0.2 * o5[k / 5], ux, uy);
-                sersic_dI64(c, ux - c.x0, uy - c.y0, w5[k % 5] * w5[k / 5], vv, acc);
-            }
-            for (int k = 0; k < 7; ++k) {
-                const double s = block_sum(acc[k], red);
-                if (t == 0) p.adval[7LL * r + k] = (float)(s / 25.0);
-            }
+            to_sky(im, px, py, ux, uy);
+            sersic_dI64(c, ux - c.x0, uy - c.y0, wgt, vv, acc);
+        }
+        for (int k = 0; k < 7; ++k) {
+            double s = acc[k];
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            if (lane == 0) red[wv][k] = s;
+        }
+        __syncthreads();
+        if (t < 7) {
+            double s = red[0][t];
+            for (int w = 1; w < REFINE_THREADS / 64; ++w) s += red[w][t];
+            p.adval[7LL * r + t] = (float)(s / 25.0);
         }
         __syncthreads();                    // LDS reuse by the next entry
     }
@@ -255,8 +305,9 @@ hipError_t launch_adapt(const Plan& p, int skip_mode, const apx_lm_state* lm, in
     hipLaunchKernelGGL(k_adapt_flux, dim3(p.n_achunks), dim3(ADAPT_CHUNK), 0, st, p, skip_mode, lm);
     hipLaunchKernelGGL(k_adapt_fold, dim3(p.n_comps), dim3(64), 0, st, p, skip_mode, lm);
     hipLaunchKernelGGL(k_adapt_pix, dim3(p.n_achunks), dim3(ADAPT_CHUNK), 0, st, p, skip_mode, lm);
-    const long long g = p.n_apix < 2048 ? p.n_apix : 2048;
-    hipLaunchKernelGGL(k_adapt_refine, dim3((unsigned)g), dim3(REFINE_THREADS), 0, st, p, want_grad);
+    const long long g = p.n_apix < 4096 ? p.n_apix : 4096;
+    hipLaunchKernelGGL(k_adapt_refine, dim3((unsigned)g), dim3(REFINE_THREADS), 0, st, p);
+    if (want_grad) hipLaunchKernelGGL(k_adapt_refine_grad, dim3((unsigned)g), dim3(REFINE_THREADS), 0, st, p);
     return hipGetLastError();
 }
 
