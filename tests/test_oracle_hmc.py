@@ -1,0 +1,133 @@
+"""Pins of the HMC oracle against closed forms (CPU only).
+
+For a quadratic potential U = |phi|^2 / 2 in whitened coordinates the leapfrog step of size
+eps is the linear map (phi, r) -> (a phi + eps r, -eps (1 - eps^2/4) phi + a r) with
+a = 1 - eps^2/2 (kick-drift-kick solved by hand), so L steps are its L-th power.  A
+correlated Gaussian target, a sky-only image fit (chi^2 exactly quadratic in the sky, with
+variance 1 / sum w) and the model domain fix what the sampler must do; planted mistakes
+(a transposed factor, a missing factor 1/2 in U) must fail them."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.hmc
+from paper_2308_01957_amd import synth
+
+
+def _osc(eps, L):
+    a = 1.0 - 0.5 * eps * eps
+    M = np.array([[a, eps], [-eps * (1.0 - 0.25 * eps * eps), a]])
+    return np.linalg.matrix_power(M, L)
+
+
+def test_leapfrog_on_a_correlated_gaussian_is_the_oscillator_map():
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((3, 3))
+    Sigma = B @ B.T + 0.5 * np.eye(3)
+    mu = rng.standard_normal(3)
+    P = np.linalg.inv(Sigma)
+    F = np.linalg.cholesky(Sigma) @ np.linalg.qr(rng.standard_normal((3, 3)))[0]   # any F F^T = Sigma
+    assert np.allclose(F @ F.T, Sigma)
+    theta0, r0 = rng.standard_normal(3), rng.standard_normal(3)
+    eps, L = 0.37, 9
+    tL, rL, _ = oracle.leapfrog(theta0, r0, F, lambda t: P @ (t - mu), eps, L)
+    phi0 = np.linalg.solve(F, theta0 - mu)
+    M = _osc(eps, L)
+    phiL = M[0, 0] * phi0 + M[0, 1] * r0
+    rLc = M[1, 0] * phi0 + M[1, 1] * r0
+    assert np.allclose(tL, mu + F @ phiL, rtol=0, atol=1e-12)
+    assert np.allclose(rL, rLc, rtol=0, atol=1e-12)
+
+
+def _sky_only(H=14, W=16):
+    P = 5
+    psf = synth.gaussian_psf(P, 1.0)
+    g = [7.3, 8.1, 0.7, 0.5, 1.5, 2.5, 0.8]
+    spec = {"name": "hmc_sky", "images": [dict(H=H, W=W, psf=psf, affine=synth.IDENTITY_AFFINE.copy(),
+                                               sky_par=0, sky_fixed=0.0, sub=0)],
+            "comps": [dict(type=0, image=0, box=synth.full_window(H, W, P), par=[-1] * 7, fixed=g)],
+            "subs": [(0, 1)], "sampling": dict(s=3, rule=0, mode=0, k=0.0),
+            "theta_true": [0.08], "kinds": [8], "re_of": [1.0]}
+    synth._finish(spec)
+    m = oracle.model_image(spec, np.array(spec["theta_true"]), 0)
+    d, w = synth.make_data(m, np.random.default_rng(5).standard_normal((H, W)))
+    spec["data"], spec["weight"] = [d], [w]
+    M0 = oracle.model_image(spec, np.array([0.0]), 0)
+    dd, ww = d.astype(np.float64), w.astype(np.float64)
+    return spec, float(np.sum(ww * (dd - M0)) / np.sum(ww)), 1.0 / math.sqrt(float(np.sum(ww)))
+
+
+def test_hmc_on_the_sky_only_fit_follows_the_closed_form():
+    """U(s) = (s - s*)^2 / (2 sigma^2) + U*: with F = sigma every transition is the
+    oscillator map, H1 - H0 is known exactly, and the Metropolis test follows u."""
+    spec, s_star, sigma = _sky_only()
+    F = oracle.covariance_factor(spec, np.array([0.0]), spec["data"], spec["weight"])
+    assert F.shape == (1, 1) and math.isclose(F[0, 0], sigma, rel_tol=1e-10)
+    eps, L, n = 1.3, 3, 12
+    rng = np.random.default_rng(7)
+    z = rng.standard_normal((n, 1))
+    u = rng.uniform(size=(n, 1))
+    theta0 = np.array([s_star + 2.5 * sigma])
+    samples, stats = oracle.hmc_chain(spec, theta0, spec["data"], spec["weight"], [F], eps, L, z, u)
+    M = _osc(eps, L)
+    s = float(theta0[0])
+    n_acc = 0
+    for i in range(n):
+        phi0, r0 = (s - s_star) / sigma, z[i, 0]
+        phiL, rL = M[0, 0] * phi0 + M[0, 1] * r0, M[1, 0] * phi0 + M[1, 1] * r0
+        dH = 0.5 * (phiL ** 2 + rL ** 2) - 0.5 * (phi0 ** 2 + r0 ** 2)
+        assert math.isclose(stats[i, 0, 2] - stats[i, 0, 1], dH, rel_tol=1e-7, abs_tol=1e-9)
+        acc = math.log(u[i, 0]) < -dH
+        assert bool(stats[i, 0, 0]) == acc
+        if acc:
+            s = s_star + sigma * phiL
+            n_acc += 1
+        assert math.isclose(samples[i, 0], s, rel_tol=0, abs_tol=1e-10 * sigma + 1e-12)
+    assert 0 < n_acc < n                 # both outcomes exercised
+
+
+def test_hmc_rejects_a_trajectory_that_leaves_the_domain():
+    """q driven beyond 1 by a large step: the transition is rejected and theta stays."""
+    spec = synth.blend(seed_id=120, H=20, W=22, n_sersic=1, n_point=0, P=5, mode=synth.MODE_UNIFORM)
+    m = oracle.model_image(spec, np.array(spec["theta_true"]), 0)
+    d, w = synth.make_data(m, np.random.default_rng(3).standard_normal((20, 22)))
+    spec["data"], spec["weight"] = [d], [w]
+    th = np.array(spec["theta_true"])
+    n = spec["n_par"]
+    F = np.zeros((n, n))
+    F[2, 2] = 1.0                        # move only q
+    z = np.zeros((1, n))
+    z[0, 2] = 5.0
+    samples, stats = oracle.hmc_chain(spec, th, spec["data"], spec["weight"], [F], 1.0, 2, z, np.array([[1e-300]]))
+    assert stats[0, 0, 0] == 0.0 and math.isinf(stats[0, 0, 2])
+    assert np.array_equal(samples[0], th)
+
+
+def test_planted_transposed_factor_fails_the_oscillator_pin(monkeypatch):
+    def transposed_drift(theta, r, F, grad_U, step, n_steps):
+        theta = np.array(theta, dtype=np.float64)
+        r = np.array(r, dtype=np.float64)
+        g = grad_U(theta)
+        for _ in range(n_steps):
+            r = r - 0.5 * step * (F.T @ g)
+            theta = theta + step * (F.T @ r)          # planted: F^T in the drift
+            g = grad_U(theta)
+            r = r - 0.5 * step * (F.T @ g)
+        return theta, r, []
+    monkeypatch.setattr(oracle, "leapfrog", transposed_drift)
+    with pytest.raises(AssertionError):
+        test_leapfrog_on_a_correlated_gaussian_is_the_oscillator_map()
+
+
+def test_planted_missing_half_in_the_potential_fails_the_sky_pin(monkeypatch):
+    """U = chi^2 instead of chi^2 / 2 doubles the force: the sky transitions stop matching."""
+    orig = oracle.hmc.jtwj
+
+    def doubled(spec, theta, data, weight, sub=0):
+        A, g, c = orig(spec, theta, data, weight, sub)
+        return A, 2.0 * g, c
+    monkeypatch.setattr(oracle.hmc, "jtwj", doubled)
+    with pytest.raises(AssertionError):
+        test_hmc_on_the_sky_only_fit_follows_the_closed_form()
