@@ -312,6 +312,39 @@ apx_status apx_chi2_grad(apx_problem* p, const double* theta, const float* data,
 apx_status apx_covariance(apx_problem* p, const double* theta, const float* data,
                           const float* weight, double* cov, double* chi2);
 
+/* Factor of the parameter covariance, for use as the sampler's mass matrix: for each
+ * sub-problem s, F_s = L^{-T} where J^T W J = L L^T (lower Cholesky factor, no damping),
+ * so that F_s F_s^T = (J^T W J)^{-1} = cov_s of apx_covariance.  F_s is upper triangular,
+ * written in full (zeros below the diagonal) as an n_s x n_s row-major block at offset
+ * sum_{t<s} n_t^2; also chi2[n_sub].  A block whose J^T W J is not positive definite is
+ * filled with NaN.  F: device FP64, overwritten; asynchronous on the context stream. */
+apx_status apx_covariance_factor(apx_problem* p, const double* theta, const float* data,
+                                 const float* weight, double* F, double* chi2);
+
+/* Hamiltonian Monte Carlo (§2.5; §3.5 starts it at the LM fit with the LM covariance as the
+ * inverse mass matrix; the method is the hybrid Monte Carlo of Duane et al. 1987).  Target
+ * of each sub-problem s: U_s = chi2_s / 2 (flat priors), sampled as its own chain.
+ * F: device FP64 per-sub blocks in the layout of apx_covariance with F_s F_s^T = Sigma_s,
+ * the inverse mass matrix (apx_covariance_factor gives one; any factor is accepted).  The
+ * momenta are whitened, r = F^T p ~ N(0, I), K = |r|^2 / 2, and a leapfrog step of size
+ * `step` is r -= (step/2) F^T grad U; theta += step F r; r -= (step/2) F^T grad U.
+ * Sample i: r = z[i * n_par + j] (j over the sub-problem's range), n_leapfrog steps
+ * (n_leapfrog gradient passes; the gradient at the start of a trajectory is carried over),
+ * then per sub-problem: accepted iff every leapfrog point stayed in the model domain and
+ * log(u[i * n_sub + s]) < H0 - H1, H = U + K; a rejected sub-problem returns to its start.
+ * theta: device [n_par] FP64, in: start, out: the chain's last state.  z: device FP64
+ * [n_samples * n_par] standard normals; u: device FP64 [n_samples * n_sub] uniforms in
+ * (0, 1] (the caller draws both).  samples: device FP64 [n_samples * n_par], theta after
+ * each transition (entries outside every sub-problem copied).  stats: device FP64
+ * [n_samples * n_sub * 3] = (accepted 0/1, H0, H1).  An out-of-domain start raises
+ * APX_E_DOMAIN via apx_problem_check; out-of-domain points inside trajectories only reject.
+ * n_leapfrog >= 1, step > 0 finite, n_samples >= 0, else APX_E_INVALID.  Uses the LM's
+ * Cholesky scratch (do not interleave with apx_lm_* calls of the same problem).
+ * Asynchronous on the context stream. */
+apx_status apx_hmc_run(apx_problem* p, const float* data, const float* weight, double* theta,
+                       const double* F, double step, int32_t n_leapfrog, int32_t n_samples,
+                       const double* z, const double* u, double* samples, double* stats);
+
 /* Vector-Jacobian product of the render (the reverse pass of the model of §2.3, the
  * same adjoint as apx_chi2_grad with the caller's seed in place of -2 w r):
  * grad_theta[k] = sum_i grad_model[i] * d model_i / d theta_k, i over every output pixel

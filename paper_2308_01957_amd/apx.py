@@ -30,6 +30,7 @@ EXPORTS = [
     "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_render_vjp", "apx_lm_init",
     "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
     "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_problem_tile_shapes", "apx_covariance",
+    "apx_covariance_factor", "apx_hmc_run",
 ]
 TILES_AUTOTUNE, TILES_MODEL, TILES_FIXED = 0, 1, 2
 TILE_SHAPES = [(32, 64), (16, 64), (32, 32), (16, 32)]       # output rows x cols per workgroup
@@ -136,6 +137,8 @@ def load_library(path: str = LIB_PATH):
         "apx_chi2_grad": ([vp, vp, vp, vp, vp, vp], i32),
         "apx_render_vjp": ([vp, vp, vp, vp], i32),
         "apx_covariance": ([vp, vp, vp, vp, vp, vp], i32),
+        "apx_covariance_factor": ([vp, vp, vp, vp, vp, vp], i32),
+        "apx_hmc_run": ([vp, vp, vp, vp, vp, ctypes.c_double, i32, i32, vp, vp, vp, vp], i32),
         "apx_lm_init": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_step": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_run": ([vp, i32, vp, vp, vp, vp, i32], i32),
@@ -346,6 +349,43 @@ class Problem:
                                                 C.data_ptr(), c2.data_ptr()))
         self._leave()
         return C, c2
+
+    def covariance_factor(self, theta, data, weight):
+        """(F flat per-sub blocks with F F^T = (J^T W J)^{-1}, chi2 [n_sub]), FP64 device tensors."""
+        th = self._dev(theta, self.torch.float64)
+        self._enter(th, data, weight)
+        t = self.torch
+        with t.cuda.stream(self.stream):
+            F = t.empty(max(1, int(self.a_offsets[-1])), dtype=t.float64, device=self.device)
+            c2 = t.empty(self.n_sub, dtype=t.float64, device=self.device)
+            self._check(self.lib.apx_covariance_factor(self._prob, th.data_ptr(), data.data_ptr(),
+                                                       weight.data_ptr(), F.data_ptr(), c2.data_ptr()))
+        self._leave()
+        return F, c2
+
+    def hmc(self, theta, data, weight, F, step: float, n_leapfrog: int, z, u):
+        """Hamiltonian Monte Carlo from theta (device FP64 [n_par], updated in place to the
+        chain's last state) with inverse-mass factor F (flat per-sub blocks); z: [n_samples,
+        n_par] standard normals, u: [n_samples, n_sub] uniforms.  Returns (samples
+        [n_samples, n_par], stats [n_samples, n_sub, 3] = accepted, H0, H1)."""
+        t = self.torch
+        z = self._dev(z, t.float64)
+        u = self._dev(u, t.float64)
+        F = self._dev(F, t.float64)
+        n_samples = int(z.numel() // max(1, self.n_par)) if self.n_par else int(u.numel() // max(1, self.n_sub))
+        if z.numel() != n_samples * self.n_par or u.numel() != n_samples * self.n_sub:
+            raise ValueError("z must hold n_samples x n_par and u n_samples x n_sub entries")
+        if F.numel() < int(self.a_offsets[-1]):
+            raise ValueError("F must hold the per-sub blocks (sum of n_s^2 entries)")
+        self._enter(theta, data, weight, F, z, u)
+        with t.cuda.stream(self.stream):
+            samples = t.empty((n_samples, self.n_par), dtype=t.float64, device=self.device)
+            stats = t.empty((n_samples, self.n_sub, 3), dtype=t.float64, device=self.device)
+            self._check(self.lib.apx_hmc_run(self._prob, data.data_ptr(), weight.data_ptr(), theta.data_ptr(),
+                                             F.data_ptr(), float(step), int(n_leapfrog), n_samples,
+                                             z.data_ptr(), u.data_ptr(), samples.data_ptr(), stats.data_ptr()))
+        self._leave()
+        return samples, stats
 
     def render_vjp(self, theta, grad_model, out=None):
         """sum_i grad_model[i] d model_i / d theta (FP64 [n_par]) by the adjoint pass."""

@@ -1157,6 +1157,13 @@ static void layout(apx_problem* P) {
     ws_take<double>(P, "seed_part", 64LL * P->n_images);
     ws_take<double>(P, "chi2_sub", P->n_sub);
     ws_take<double>(P, "chi2_trial", P->n_sub);
+    ws_take<double>(P, "hmc_t0", P->n_par);
+    ws_take<double>(P, "hmc_r", P->n_par);
+    ws_take<double>(P, "hmc_g0", P->n_par);
+    ws_take<double>(P, "hmc_g1", P->n_par);
+    ws_take<double>(P, "hmc_c0", P->n_sub);
+    ws_take<double>(P, "hmc_c1", P->n_sub);
+    ws_take<double>(P, "hmc_h0", P->n_sub);
     (void)n_cols;
 }
 
@@ -1730,10 +1737,14 @@ apx_status apx_jtwj(apx_problem* P, const double* theta, const float* data, cons
     return APX_OK;
 }
 
-apx_status apx_covariance(apx_problem* P, const double* theta, const float* data, const float* weight,
-                          double* cov, double* chi2) {
+}  // extern "C"
+
+// A^{-1} (factor = 0) or F = L^{-T} with A = L L^T (factor = 1) of every sub-problem's
+// J^T W J at theta, into out (per-sub blocks at a_off).
+static apx_status cov_core(apx_problem* P, const double* theta, const float* data, const float* weight,
+                           double* out, double* chi2, int factor) {
     APXCHK(ready(P));
-    if (!par_ok(P, theta) || !data || !weight || !par_ok(P, cov) || !chi2)
+    if (!par_ok(P, theta) || !data || !weight || !par_ok(P, out) || !chi2)
         return fail(P->ctx, APX_E_INVALID, "null pointer");
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
@@ -1742,27 +1753,42 @@ apx_status apx_covariance(apx_problem* P, const double* theta, const float* data
     APXCHK(normal_eq(P, weight, p.A, p.gvec, nullptr));
     {
         TimeScope ts(P, APX_TIME_SOLVE);
-        HIPCHK(launch_cov_small(p, wsp<int>(P, "small_subs"), (int)P->small_subs.size(), P->nmax_small, cov, st));
+        HIPCHK(launch_cov_small(p, wsp<int>(P, "small_subs"), (int)P->small_subs.size(), P->nmax_small, out,
+                                factor, st));
         for (int s : P->large_subs) {
             const int n = P->subs[s].n;
             HIPCHK(launch_chol_reset(p, s, st));
             HIPCHK(launch_cov_fill(p, s, n, st));
             HIPCHK(launch_chol_blocks(p, s, n, st));
-            HIPCHK(launch_cov_cols(p, s, n, cov, st));
+            HIPCHK(launch_cov_cols(p, s, n, out, factor, st));
+            if (factor) HIPCHK(launch_cov_transpose(p, s, n, out, st));
         }
     }
     HIPCHK(launch_chi2_check(chi2, P->n_sub, p.sticky, st));
     return APX_OK;
 }
 
-apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data, const float* weight,
-                         double* grad, double* chi2) {
-    APXCHK(ready(P));
-    if (!par_ok(P, theta) || !data || !weight || !par_ok(P, grad) || !chi2)
-        return fail(P->ctx, APX_E_INVALID, "null pointer");
+extern "C" {
+
+apx_status apx_covariance(apx_problem* P, const double* theta, const float* data, const float* weight,
+                          double* cov, double* chi2) {
+    return cov_core(P, theta, data, weight, cov, chi2, 0);
+}
+
+apx_status apx_covariance_factor(apx_problem* P, const double* theta, const float* data, const float* weight,
+                                 double* F, double* chi2) {
+    return cov_core(P, theta, data, weight, F, chi2, 1);
+}
+
+}  // extern "C"
+
+// chi2 and d chi2 / d theta at theta; lm_trial = 1 marks out-of-domain sub-problems in their
+// trial flags instead of the sticky error flags (sampler trajectories).
+static apx_status grad_core(apx_problem* P, const double* theta, const float* data, const float* weight,
+                            double* grad, double* chi2, int lm_trial) {
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
-    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, 0, 0, nullptr, 1));
+    APXCHK(fwd_chi2(P, theta, data, weight, nullptr, chi2, lm_trial, 0, nullptr, 1));
     HIPCHK(launch_flip_psf(p, st));
     ConvIO io{};
     io.out = p.Abar;
@@ -1790,7 +1816,60 @@ apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data,
     g.n_seg = P->n_par;
     g.out = grad;
     HIPCHK(launch_segsum(g, st));
-    HIPCHK(launch_chi2_check(chi2, P->n_sub, p.sticky, st));
+    return APX_OK;
+}
+
+extern "C" {
+
+apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data, const float* weight,
+                         double* grad, double* chi2) {
+    APXCHK(ready(P));
+    if (!par_ok(P, theta) || !data || !weight || !par_ok(P, grad) || !chi2)
+        return fail(P->ctx, APX_E_INVALID, "null pointer");
+    APXCHK(grad_core(P, theta, data, weight, grad, chi2, 0));
+    HIPCHK(launch_chi2_check(chi2, P->n_sub, P->plan.sticky, P->ctx->stream));
+    return APX_OK;
+}
+
+apx_status apx_hmc_run(apx_problem* P, const float* data, const float* weight, double* theta, const double* F,
+                       double step, int32_t n_leapfrog, int32_t n_samples, const double* z, const double* u,
+                       double* samples, double* stats) {
+    APXCHK(ready(P));
+    if (!data || !weight || !par_ok(P, theta) || !par_ok(P, F) || (n_samples > 0 && (!par_ok(P, z) || !u)) ||
+        (n_samples > 0 && (!par_ok(P, samples) || !stats)))
+        return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (n_leapfrog < 1 || n_samples < 0 || !(step > 0.0) || !std::isfinite(step))
+        return fail(P->ctx, APX_E_INVALID, "need n_leapfrog >= 1, n_samples >= 0 and a finite step > 0");
+    if (n_samples == 0) return APX_OK;
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    HmcIO h{};
+    h.theta = theta;
+    h.theta0 = wsp<double>(P, "hmc_t0");
+    h.r = wsp<double>(P, "hmc_r");
+    h.grad_cur = wsp<double>(P, "hmc_g0");
+    h.grad_new = wsp<double>(P, "hmc_g1");
+    h.chi2_cur = wsp<double>(P, "hmc_c0");
+    h.chi2_new = wsp<double>(P, "hmc_c1");
+    h.H0 = wsp<double>(P, "hmc_h0");
+    h.z = z;
+    h.u = u;
+    h.samples = samples;
+    h.stats = stats;
+    double* Ft = p.M;                              // F^T (the Cholesky scratch is free here)
+    HIPCHK(launch_hmc_transpose(p, F, Ft, st));
+    // gradient at the start (an out-of-domain start raises the sticky flag)
+    APXCHK(grad_core(P, theta, data, weight, h.grad_cur, h.chi2_cur, 0));
+    for (long long i = 0; i < n_samples; ++i) {
+        HIPCHK(launch_hmc_begin(p, h, i, st));
+        for (int l = 0; l < n_leapfrog; ++l) {
+            HIPCHK(launch_hmc_matvec(p, F, l == 0 ? h.grad_cur : h.grad_new, h.r, -0.25 * step, st));
+            HIPCHK(launch_hmc_matvec(p, Ft, h.r, h.theta, step, st));
+            APXCHK(grad_core(P, theta, data, weight, h.grad_new, h.chi2_new, 1));
+            HIPCHK(launch_hmc_matvec(p, F, h.grad_new, h.r, -0.25 * step, st));
+        }
+        HIPCHK(launch_hmc_accept(p, h, i, st));
+    }
     return APX_OK;
 }
 

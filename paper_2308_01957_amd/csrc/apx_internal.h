@@ -305,9 +305,33 @@ hipError_t launch_lm_accept(const Plan& p, const double* chi2_trial, double* the
                             apx_lm_state* lm, hipStream_t st);
 
 // k_cov.hip
+// factor / forward_only: F = L^{-T} (A = L L^T) instead of A^{-1}, so that F F^T = A^{-1}
 hipError_t launch_cov_small(const Plan& p, const int* small_subs, int n_small, int nmax, double* cov,
-                            hipStream_t st);
+                            int factor, hipStream_t st);
 hipError_t launch_cov_fill(const Plan& p, int sub, int n, hipStream_t st);
-hipError_t launch_cov_cols(const Plan& p, int sub, int n, double* cov, hipStream_t st);
+hipError_t launch_cov_cols(const Plan& p, int sub, int n, double* cov, int forward_only, hipStream_t st);
+hipError_t launch_cov_transpose(const Plan& p, int sub, int n, double* X, hipStream_t st);
+
+// k_hmc.hip: the vector steps of Hamiltonian Monte Carlo around the gradient passes
+struct HmcIO {
+    double* theta;            // [n_par] current point (in/out)
+    double* theta0;           // [n_par] start of the trajectory
+    double* r;                // [n_par] whitened momenta
+    double* grad_cur;         // [n_par] d chi2 / d theta at theta0 (start of the next trajectory)
+    double* grad_new;         // [n_par] d chi2 / d theta at the latest leapfrog point
+    double* chi2_cur;         // [n_sub]
+    double* chi2_new;         // [n_sub]
+    double* H0;               // [n_sub]
+    const double* z;          // [n_samples * n_par] standard normals
+    const double* u;          // [n_samples * n_sub] uniforms
+    double* samples;          // [n_samples * n_par]
+    double* stats;            // [n_samples * n_sub * 3]: accepted, H0, H1
+};
+hipError_t launch_hmc_transpose(const Plan& p, const double* F, double* Ft, hipStream_t st);
+// out[j] += coef * (M_s^T v_s)[j - p0_s] for every theta index j of sub-problem s
+hipError_t launch_hmc_matvec(const Plan& p, const double* M, const double* v, double* out, double coef,
+                             hipStream_t st);
+hipError_t launch_hmc_begin(const Plan& p, const HmcIO& h, long long i, hipStream_t st);
+hipError_t launch_hmc_accept(const Plan& p, const HmcIO& h, long long i, hipStream_t st);
 
 }  // namespace apx

@@ -9,12 +9,15 @@
 // the CHOL_NB columns of block j, with the off-diagonal products on FP64 MFMA and the
 // triangular 64 x 64 solves one column per lane.  A matrix that is not positive definite
 // yields NaN in its whole block.
+//
+// Factor mode (the mass-matrix factor of the sampler): only the forward solves, Y = L^{-1},
+// stored transposed, F = L^{-T}, so that F F^T = L^{-T} L^{-1} = A^{-1}.
 #include "apx_internal.h"
 
 namespace apx {
 
 __global__ __launch_bounds__(64) void k_cov_small(Plan p, const int* __restrict__ small_subs, int nmax,
-                                                  double* __restrict__ cov) {
+                                                  double* __restrict__ cov, int factor) {
     extern __shared__ double sm[];
     const int s = small_subs[blockIdx.x];
     const DSub sb = p.subs[s];
@@ -56,6 +59,10 @@ __global__ __launch_bounds__(64) void k_cov_small(Plan p, const int* __restrict_
         for (int m = c; m < i; ++m) t -= L[i * ld + m] * Y[m * ld + c];
         Y[i * ld + c] = t / L[i * ld + i];
     }
+    if (factor) {                                    // row c of F = L^{-T}
+        for (int i = 0; i < n; ++i) out[(long long)c * n + i] = Y[i * ld + c];
+        return;
+    }
     for (int i = n - 1; i >= 0; --i) {
         double t = Y[i * ld + c];
         for (int m = i + 1; m < n; ++m) t -= L[m * ld + i] * Y[m * ld + c];
@@ -65,10 +72,10 @@ __global__ __launch_bounds__(64) void k_cov_small(Plan p, const int* __restrict_
 }
 
 hipError_t launch_cov_small(const Plan& p, const int* small_subs, int n_small, int nmax, double* cov,
-                            hipStream_t st) {
+                            int factor, hipStream_t st) {
     if (n_small <= 0 || nmax <= 0) return hipSuccess;
     const size_t lds = 2 * (size_t)nmax * (nmax + 1) * sizeof(double);
-    hipLaunchKernelGGL(k_cov_small, dim3(n_small), dim3(64), lds, st, p, small_subs, nmax, cov);
+    hipLaunchKernelGGL(k_cov_small, dim3(n_small), dim3(64), lds, st, p, small_subs, nmax, cov, factor);
     return hipGetLastError();
 }
 
@@ -126,7 +133,7 @@ __device__ __forceinline__ void cov_gemm(const double (*Lb)[CHOL_NB + 1], const 
 // Workgroup j: block column j of A^{-1}.  Forward L Y = E_j over row blocks b >= j (Y is
 // zero above block j), then backward L^T X = Y over every row block from the last; Y and
 // then X live in the output block column.
-__global__ __launch_bounds__(256) void k_cov_cols(Plan p, int s, double* __restrict__ cov) {
+__global__ __launch_bounds__(256) void k_cov_cols(Plan p, int s, double* __restrict__ cov, int forward_only) {
     __shared__ double Lb[CHOL_NB][CHOL_NB + 1];
     __shared__ double Yb[CHOL_NB][CHOL_NB + 1];
     __shared__ double T[CHOL_NB][CHOL_NB + 1];
@@ -152,7 +159,7 @@ __global__ __launch_bounds__(256) void k_cov_cols(Plan p, int s, double* __restr
                 for (int v = 0; v < 4; ++v)
                     T[wr * 32 + m * 16 + (lane >> 4) + 4 * v][wc * 32 + q * 16 + (lane & 15)] -= acc[m][q][v];
     };
-    for (int dir = 0; dir < 2; ++dir) {
+    for (int dir = 0; dir < (forward_only ? 1 : 2); ++dir) {
         const int b_first = dir == 0 ? j : nblk - 1, b_last = dir == 0 ? nblk : -1, step = dir == 0 ? 1 : -1;
         for (int b = b_first; b != b_last; b += step) {
             const int r0 = b * CHOL_NB, nr = min(CHOL_NB, n - r0);
@@ -217,9 +224,34 @@ __global__ __launch_bounds__(256) void k_cov_cols(Plan p, int s, double* __restr
     }
 }
 
-hipError_t launch_cov_cols(const Plan& p, int s, int n, double* cov, hipStream_t st) {
+hipError_t launch_cov_cols(const Plan& p, int s, int n, double* cov, int forward_only, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cov_cols, dim3((n + CHOL_NB - 1) / CHOL_NB), dim3(256), 0, st, p, s, cov);
+    hipLaunchKernelGGL(k_cov_cols, dim3((n + CHOL_NB - 1) / CHOL_NB), dim3(256), 0, st, p, s, cov, forward_only);
+    return hipGetLastError();
+}
+
+// X <- X^T in place for the n x n block of sub-problem s (each pair swapped by one thread).
+__global__ void k_cov_transpose(Plan p, int s, double* __restrict__ X) {
+    const DSub sb = p.subs[s];
+    const long long n = sb.n, nn = n * n;
+    double* B = X + sb.a_off;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long i = e / n, j = e - i * n;
+        if (i < j) {
+            const double a = B[i * n + j], b = B[j * n + i];
+            B[i * n + j] = b;
+            B[j * n + i] = a;
+        }
+    }
+}
+
+hipError_t launch_cov_transpose(const Plan& p, int s, int n, double* X, hipStream_t st) {
+    const long long nn = (long long)n * n;
+    long long fb = (nn + 255) / 256;
+    if (fb > 4096) fb = 4096;
+    if (fb < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_cov_transpose, dim3((unsigned)fb), dim3(256), 0, st, p, s, X);
     return hipGetLastError();
 }
 
