@@ -296,8 +296,51 @@ def run_adaptive(args, torch, apx, synth):
                            "integration with budget 0.01 F / N, 551 params")
 
 
+def run_hmc(args, torch, apx, synth):
+    """The Bayesian mock of the paper's HMC example: one Sersic galaxy, one star and the sky
+    under a live Moffat PSF (11 free parameters), fitted by LM, then sampled by HMC with the
+    LM covariance as the inverse mass matrix: 20 untimed warm-up transitions, then
+    `steps` x 25 timed transitions of 10 leapfrog steps each."""
+    spec = synth.live_psf(seed_id=9, H=128, W=128, n_star=1, n_sersic=1, P=25, logf_range=(2.0, 2.5),
+                          logie_range=(0.0, 0.5))
+    prob = apx.Problem(spec)
+    data, weight = _data(prob, spec, synth)
+    dd, ww = prob.pixels(data), prob.pixels(weight)
+    th, st = prob.lm_init(spec["theta_init"], dd, ww)
+    prob.lm_run(60, dd, ww, th, st, use_graph=True)
+    F, _ = prob.covariance_factor(th, dd, ww)
+    n_leap, eps = 10, 0.3
+    rng = np.random.default_rng(20230801)
+    n_warm, n_samp = 20, 25 * args.steps
+    z = torch.tensor(rng.standard_normal((n_warm + n_samp, spec["n_par"])), device=prob.device)
+    u = torch.tensor(rng.uniform(size=(n_warm + n_samp, 1)), device=prob.device)
+    prob.hmc(th, dd, ww, F, eps, n_leap, z[:n_warm], u[:n_warm])
+    torch.cuda.synchronize()
+    prob.set_timing(True)
+    t0 = time.perf_counter()
+    samples, stats = prob.hmc(th, dd, ww, F, eps, n_leap, z[n_warm:], u[n_warm:])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = prob.timing()
+    prob.set_timing(False)
+    prob.check()
+    acc = float(stats[:, 0, 0].mean().cpu())
+    _line({
+        "metric": "HMC transitions/s (10 leapfrog steps each, LM covariance mass matrix)",
+        "workload": "hmc", "value": n_samp / dt, "unit": "HMC samples/s", "ms_per_step": dt * 1e3 / n_samp,
+        "n_gpus": 1, "steps": n_samp, "gradient_passes_per_s": n_samp * n_leap / dt, "accept_rate": acc,
+        "kernel_ms_per_sample": {k: round(v[0] / n_samp, 4) for k, v in kt.items()},
+        "paper_context": "NUTS, 20 warm-up + 250 samples of a 13-parameter mock in 738.5 s, hardware unstated",
+        "config": {"workload": "128x128, 1 Sersic + 1 star + sky, live Moffat PSF 25x25 (n, R_d fitted), "
+                               "11 params; step 0.3, 10 leapfrog steps", "n_par": spec["n_par"],
+                   "n_pix": prob.n_pix},
+        "dtype": "f64 objective / f32 adjoint gradient", "data": "synthetic"})
+    return 0
+
+
 OTHER_WORKLOADS = {"cutouts": run_cutouts, "field": run_field, "multiband": run_multiband,
-                   "single": run_single, "livepsf": run_livepsf, "adaptive": run_adaptive}
+                   "single": run_single, "livepsf": run_livepsf, "adaptive": run_adaptive,
+                   "hmc": run_hmc}
 
 
 def tile_choice(prob):
@@ -358,7 +401,7 @@ def main():
                     help="also launch three plain copy kernels of MIB MiB (read MIB, write MIB) "
                          "after the timed region, to calibrate HBM byte counters")
     ap.add_argument("--workload", default="blend",
-                    choices=["blend", "cutouts", "field", "multiband", "single", "livepsf", "adaptive"],
+                    choices=["blend", "cutouts", "field", "multiband", "single", "livepsf", "adaptive", "hmc"],
                     help="blend (default, the headline line); the others print their own line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
