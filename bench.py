@@ -345,7 +345,7 @@ OTHER_WORKLOADS = {"cutouts": run_cutouts, "field": run_field, "multiband": run_
 
 def tile_choice(prob):
     """Convolution jobs per tile shape (rows x cols) as the autotuner chose them."""
-    names = ["%dx%d" % t for t in prob_tile_shapes()]
+    names = ["%dx%d" % t for t in prob_tile_shapes()] + ["fft"]
     return {kind: dict(zip(names, prob.tile_shapes(k))) for k, kind in enumerate(["model", "jacobian", "adjoint"])}
 
 

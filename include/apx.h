@@ -114,6 +114,17 @@ typedef int32_t apx_status;
 
 #define APX_MAX_PSF 63
 
+/* Convolution mode (§2.1.3: direct convolution, efficient for small stamps, or FFT
+ * convolution, efficient for large ones).  APX_CONV_FFT applies to images with P >=
+ * APX_FFT_MIN_P: their Jacobian-column and adjoint convolutions, and the model convolution
+ * when the objective is FP32, whose output box is at least 32 x 32 run as overlap-save
+ * 128 x 128 FFTs in FP32 (two output blocks per complex transform); the rest stays direct,
+ * as does the FP64 objective convolution.  Results equal the direct ones to FP32 rounding
+ * relative to each tile's largest values. */
+#define APX_CONV_DIRECT 0
+#define APX_CONV_FFT    1
+#define APX_FFT_MIN_P   15
+
 /* LM constants (§2.5 gives the method, not the constants; these are fixed here). */
 #define APX_LM_LAMBDA0     1e-2
 #define APX_LM_UP          11.0
@@ -173,7 +184,7 @@ typedef struct apx_problem_desc {
     double  k_re;                   /* k of APX_MODE_WITHIN_K_RE; tol of
                                        APX_MODE_ADAPTIVE                             */
     int32_t n_psf_models;           /* live PSF models (0: every stamp is fixed)     */
-    int32_t reserved;
+    int32_t conv_mode;              /* APX_CONV_DIRECT (default) or APX_CONV_FFT     */
     const apx_psf_model_desc* psf_models;   /* host, [n_psf_models]                 */
 } apx_problem_desc;
 
@@ -248,7 +259,8 @@ apx_status apx_problem_bind_workspace(apx_problem* p, void* dev, uint64_t bytes)
 apx_status apx_problem_sizes(const apx_problem* p, int64_t* n_pix, int64_t* n_ext, int64_t* n_jac);
 
 /* Convolution jobs of `kind` (0 model, 1 Jacobian columns, 2 adjoint) per tile shape:
- * counts[s] for s = 0..3 (see apx_ctx_set_tiles). */
+ * counts[s] for s = 0..3 (see apx_ctx_set_tiles), counts[4] = jobs in FFT mode.  counts
+ * must hold 5 entries. */
 apx_status apx_problem_tile_shapes(const apx_problem* p, int32_t kind, int32_t* counts);
 
 /* Synchronise the stream and return the sticky device flag, then clear it: APX_OK,

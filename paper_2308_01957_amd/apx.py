@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libapx.so")
 APX_OK, APX_E_INVALID, APX_E_HIP, APX_E_NONFINITE, APX_E_WORKSPACE, APX_E_UNSUPPORTED, APX_E_DOMAIN = \
     0, -1, -2, -3, -4, -5, -6
 OBJECTIVE_FP64, OBJECTIVE_FP32 = 0, 1
+CONV_DIRECT, CONV_FFT = 0, 1            # spec["conv_mode"]
 
 EXPORTS = [
     "apx_version", "apx_status_string", "apx_ctx_create", "apx_ctx_set_stream", "apx_ctx_destroy",
@@ -62,7 +63,7 @@ class ProblemDesc(ctypes.Structure):
                 ("sub_par", ctypes.POINTER(ctypes.c_int32)), ("psf", ctypes.c_void_p),
                 ("s", ctypes.c_int32), ("rule", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("objective", ctypes.c_int32), ("k_re", ctypes.c_double),
-                ("n_psf_models", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_psf_models", ctypes.c_int32), ("conv_mode", ctypes.c_int32),
                 ("psf_models", ctypes.POINTER(PsfModelDesc))]
 
 
@@ -215,7 +216,8 @@ class Problem:
         desc = ProblemDesc(len(spec["images"]), len(spec["comps"]), self.n_par, self.n_sub,
                            idesc, cdesc, sp, ctypes.c_void_p(self.psf.data_ptr()),
                            int(sampling["s"]), int(sampling["rule"]), int(sampling["mode"]),
-                           int(objective), float(sampling.get("k", 0.0)), npm, 0, pms)
+                           int(objective), float(sampling.get("k", 0.0)), npm,
+                           int(spec.get("conv_mode", CONV_DIRECT)), pms)
         self._keep = (idesc, cdesc, sp, desc, pms)
         self._prob = ctypes.c_void_p()
         self._check(self.lib.apx_problem_create(self._ctx, ctypes.byref(desc), ctypes.byref(self._prob)))
@@ -235,8 +237,9 @@ class Problem:
         self.a_offsets = np.concatenate([[0], np.cumsum([n * n for _, n in spec["subs"]])]).astype(np.int64)
 
     def tile_shapes(self, kind: int) -> List[int]:
-        """Convolution jobs of kind (0 model, 1 Jacobian columns, 2 adjoint) per tile shape."""
-        counts = (ctypes.c_int32 * 4)()
+        """Convolution jobs of kind (0 model, 1 Jacobian columns, 2 adjoint) per tile shape
+        (TILE_SHAPES order), then the jobs in FFT mode."""
+        counts = (ctypes.c_int32 * 5)()
         self._check(self.lib.apx_problem_tile_shapes(self._prob, int(kind), counts))
         return list(counts)
 
@@ -498,7 +501,8 @@ class Plan:
         npm, pms = _psf_models(spec)
         desc = ProblemDesc(len(spec["images"]), len(spec["comps"]), int(spec["n_par"]), len(spec["subs"]),
                            idesc, cdesc, sp, None, int(sampling["s"]), int(sampling["rule"]),
-                           int(sampling["mode"]), int(objective), float(sampling.get("k", 0.0)), npm, 0, pms)
+                           int(sampling["mode"]), int(objective), float(sampling.get("k", 0.0)), npm,
+                           int(spec.get("conv_mode", CONV_DIRECT)), pms)
         self._keep = (idesc, cdesc, sp, desc, pms)
         self._prob = ctypes.c_void_p()
         st = self.lib.apx_problem_create(self._ctx, ctypes.byref(desc), ctypes.byref(self._prob))
@@ -515,8 +519,9 @@ class Plan:
         self.n_pix, self.n_ext, self.n_jac = int(a.value), int(b.value), int(c.value)
 
     def tile_shapes(self, kind: int) -> List[int]:
-        """Convolution jobs of kind (0 model, 1 Jacobian columns, 2 adjoint) per tile shape."""
-        counts = (ctypes.c_int32 * 4)()
+        """Convolution jobs of kind (0 model, 1 Jacobian columns, 2 adjoint) per tile shape
+        (TILE_SHAPES order), then the jobs in FFT mode."""
+        counts = (ctypes.c_int32 * 5)()
         st = self.lib.apx_problem_tile_shapes(self._prob, int(kind), counts)
         if st != APX_OK:
             raise ApxError(st, "tile shapes")

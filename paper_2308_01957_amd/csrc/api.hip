@@ -27,7 +27,7 @@ struct apx_ctx {
 
 namespace {
 
-struct PRange { int P, shape, begin, count; };
+struct PRange { int P, shape, begin, count, pair_begin, pair_count; };
 
 template <class T>
 struct DevArr {
@@ -49,7 +49,7 @@ struct Layout {
 struct apx_problem {
     apx_ctx* ctx = nullptr;
     int n_images = 0, n_comps = 0, n_par = 0, n_sub = 0;
-    int s = 3, rule = 0, mode = 0, objective = 0;
+    int s = 3, rule = 0, mode = 0, objective = 0, conv_mode = 0;
     double k_re = 0.0;
     const float* psf = nullptr;
 
@@ -64,6 +64,11 @@ struct apx_problem {
     std::vector<ConvJob> fwd_jobs, jcol_jobs, adj_jobs, psf_jobs;
     std::vector<ConvItem> fwd_items, jcol_items, adj_items, psf_items;
     std::vector<PRange> fwd_ranges, jcol_ranges, adj_ranges, psf_ranges;
+    std::vector<int2> fwd_pairs, jcol_pairs, adj_pairs;    // FFT mode: items per transform
+    long long n_fft_spec = 0;                     // FFT mode: stamp spectra (complex entries)
+    int n_fft_images = 0;
+    bool fft_fixed_ready = false;                 // spectra of fixed stamps computed
+    std::vector<float> fft_tw;                    // exp(-2 pi i m / FFT_T) as (re, im)
     long long n_live = 0;                         // floats of live-PSF stamps (3 P^2 each)
     bool has_live_cols = false;                   // some live PSF has a free parameter
     std::vector<DPair> pairs;
@@ -406,6 +411,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     P->mode = d->mode;
     P->k_re = d->k_re;
     P->objective = d->objective;
+    P->conv_mode = d->conv_mode;
     P->psf = d->psf;
     if (d->n_images < 1 || d->n_comps < 0 || d->n_par < 0 || d->n_sub < 1)
         return fail(C, APX_E_INVALID, "counts: need n_images >= 1, n_sub >= 1, n_comps, n_par >= 0");
@@ -422,6 +428,8 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         return fail(C, APX_E_INVALID, "adaptive tolerance (k_re) must be > 0");
     if (d->objective != APX_OBJECTIVE_FP64 && d->objective != APX_OBJECTIVE_FP32)
         return fail(C, APX_E_INVALID, "unknown objective precision");
+    if (d->conv_mode != APX_CONV_DIRECT && d->conv_mode != APX_CONV_FFT)
+        return fail(C, APX_E_INVALID, "unknown convolution mode");
 
     // nodes (adaptive mode: its 3 x 3 Gauss-Legendre level; the other levels use agl)
     if (d->mode == APX_MODE_ADAPTIVE) {
@@ -461,6 +469,12 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     }
 
     build_bn_table(P->bn_tab);
+    if (d->conv_mode == APX_CONV_FFT)
+        for (int m = 0; m < FFT_T; ++m) {
+            const double a = -2.0 * M_PI * m / FFT_T;
+            P->fft_tw.push_back((float)std::cos(a));
+            P->fft_tw.push_back((float)std::sin(a));
+        }
 
     // sub-problems
     P->subs.resize(d->n_sub);
@@ -517,6 +531,12 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         im.pix_off = pix;
         im.ext_off = ext;
         im.psf_off = psfo;
+        im.fft_off = -1;
+        if (d->conv_mode == APX_CONV_FFT && id.P >= APX_FFT_MIN_P) {
+            im.fft_off = P->n_fft_spec;
+            P->n_fft_spec += 2LL * FFT_T * FFT_T;
+            ++P->n_fft_images;
+        }
         for (int q = 0; q < 6; ++q) im.aff[q] = id.affine[q];
         const double det = id.affine[1] * id.affine[5] - id.affine[2] * id.affine[4];
         if (!std::isfinite(det) || det == 0.0) return fail(C, APX_E_INVALID, "singular affine map");
@@ -758,13 +778,20 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
 
     // convolution jobs and items, sorted by (PSF size, tile shape): one launch per pair.
     // Each job takes the tile shape of least estimated cost (choose_shape).
+    // In FFT mode, jobs of the FP32 kinds on images with spectra and outputs of at least
+    // 32 x 32 take the FFT shape; the items of each FFT range are paired (two per complex
+    // transform) when they share the image, and so the stamp.
     auto add_items = [&](int kind, std::vector<ConvJob>& jobs, std::vector<ConvItem>& items,
                          std::vector<PRange>& ranges, const std::vector<int>& jobP,
-                         const std::vector<int>& nch, std::vector<int>* job_item_begin) {
+                         const std::vector<int>& nch, std::vector<int>* job_item_begin,
+                         std::vector<int2>* pairs) {
         const int key = kind == CONV_JCOL ? TUNE_JCOL : kind == CONV_ADJ ? TUNE_ADJ
                       : P->objective == APX_OBJECTIVE_FP64 ? TUNE_FWD64 : TUNE_FWD32;
-        for (size_t j = 0; j < jobs.size(); ++j)
-            jobs[j].shape = choose_shape(C, key, jobP[j], jobs[j].out_h, jobs[j].out_w);
+        for (size_t j = 0; j < jobs.size(); ++j) {
+            const bool fft = pairs && P->images[jobs[j].image].fft_off >= 0 && jobs[j].out_h >= 32 &&
+                             jobs[j].out_w >= 32;
+            jobs[j].shape = fft ? SHAPE_FFT : choose_shape(C, key, jobP[j], jobs[j].out_h, jobs[j].out_w);
+        }
         std::vector<int> order(jobs.size());
         for (size_t i = 0; i < jobs.size(); ++i) order[i] = (int)i;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -773,7 +800,8 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         if (job_item_begin) job_item_begin->assign(jobs.size(), 0);
         for (int j : order) {
             const ConvJob& jb = jobs[j];
-            const int ny = ceil_div(jb.out_h, tile_th(jb.shape)), nx = ceil_div(jb.out_w, tile_tw(jb.shape));
+            const int ny = ceil_div(jb.out_h, shape_th(jb.shape, jobP[j]));
+            const int nx = ceil_div(jb.out_w, shape_tw(jb.shape, jobP[j]));
             if (job_item_begin) (*job_item_begin)[j] = (int)items.size();
             const int b = (int)items.size();
             for (int ch = 0; ch < nch[j]; ++ch)
@@ -784,11 +812,24 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             if (!ranges.empty() && ranges.back().P == jobP[j] && ranges.back().shape == jb.shape)
                 ranges.back().count += cnt;
             else
-                ranges.push_back(PRange{jobP[j], jb.shape, b, cnt});
+                ranges.push_back(PRange{jobP[j], jb.shape, b, cnt, 0, 0});
+        }
+        if (!pairs) return;
+        for (PRange& r : ranges) {
+            if (r.shape != SHAPE_FFT) continue;
+            r.pair_begin = (int)pairs->size();
+            for (int i = r.begin; i < r.begin + r.count;) {
+                const bool two = i + 1 < r.begin + r.count &&
+                                 jobs[items[i].job].image == jobs[items[i + 1].job].image;
+                pairs->push_back(make_int2(i, two ? i + 1 : -1));
+                i += two ? 2 : 1;
+            }
+            r.pair_count = (int)pairs->size() - r.pair_begin;
         }
     };
-    auto job_tiles = [](const ConvJob& jb) {
-        return ceil_div(jb.out_h, tile_th(jb.shape)) * ceil_div(jb.out_w, tile_tw(jb.shape));
+    auto job_tiles = [&](const ConvJob& jb) {
+        const int Pj = P->images[jb.image].P;
+        return ceil_div(jb.out_h, shape_th(jb.shape, Pj)) * ceil_div(jb.out_w, shape_tw(jb.shape, Pj));
     };
     std::vector<int> fwd_item_begin, jcol_item_begin;
     {
@@ -812,8 +853,9 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             ja.out_y0 = -im.c; ja.out_x0 = -im.c; ja.out_h = im.EH; ja.out_w = im.EW;
             P->adj_jobs.push_back(ja);
         }
-        add_items(CONV_FWD, P->fwd_jobs, P->fwd_items, P->fwd_ranges, jp, nch, &fwd_item_begin);
-        add_items(CONV_ADJ, P->adj_jobs, P->adj_items, P->adj_ranges, jp, nch, nullptr);
+        add_items(CONV_FWD, P->fwd_jobs, P->fwd_items, P->fwd_ranges, jp, nch, &fwd_item_begin,
+                  P->objective == APX_OBJECTIVE_FP32 ? &P->fwd_pairs : nullptr);
+        add_items(CONV_ADJ, P->adj_jobs, P->adj_items, P->adj_ranges, jp, nch, nullptr, &P->adj_pairs);
     }
     std::vector<int> psf_job_of(n_groups, -1), psf_item_begin;
     {
@@ -848,8 +890,9 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
                 pnch.push_back(gr.ncols);
             }
         }
-        add_items(CONV_JCOL, P->jcol_jobs, P->jcol_items, P->jcol_ranges, jp, nch, &jcol_item_begin);
-        add_items(CONV_JCOL, P->psf_jobs, P->psf_items, P->psf_ranges, pjp, pnch, &psf_item_begin);
+        add_items(CONV_JCOL, P->jcol_jobs, P->jcol_items, P->jcol_ranges, jp, nch, &jcol_item_begin,
+                  &P->jcol_pairs);
+        add_items(CONV_JCOL, P->psf_jobs, P->psf_items, P->psf_ranges, pjp, pnch, &psf_item_begin, nullptr);
     }
 
     // reduction tables: FWD items per image, JCOL items per column, grad partials per column
@@ -1141,6 +1184,11 @@ static void layout(apx_problem* P) {
     ws_take<double>(P, "jcol_part", 2 * (P->jcol_items.size() + P->psf_items.size()));
     ws_take<float>(P, "psf_live", P->n_live);
     ws_take<double>(P, "psf64", P->n_psf);
+    ws_take<float2>(P, "fft_spec", P->n_fft_spec);
+    ws_take<float>(P, "fft_tw", P->fft_tw.size());
+    ws_take<int2>(P, "fwd_pairs", P->fwd_pairs.size());
+    ws_take<int2>(P, "jcol_pairs", P->jcol_pairs.size());
+    ws_take<int2>(P, "adj_pairs", P->adj_pairs.size());
     ws_take<double>(P, "grad_part", P->n_gradpart);
     ws_take<double>(P, "asrc", P->asrc_img + 3LL * P->n_images);
     ws_take<double>(P, "A", P->a_total);
@@ -1335,6 +1383,11 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     HIPCHK(upload(P, "small_subs", P->small_subs));
     HIPCHK(upload(P, "bn_tab", P->bn_tab));
     HIPCHK(upload(P, "agl", P->agl));
+    HIPCHK(upload(P, "fft_tw", P->fft_tw));
+    HIPCHK(upload(P, "fwd_pairs", P->fwd_pairs));
+    HIPCHK(upload(P, "jcol_pairs", P->jcol_pairs));
+    HIPCHK(upload(P, "adj_pairs", P->adj_pairs));
+    P->fft_fixed_ready = false;
     HIPCHK(upload(P, "achunks", P->achunks));
     HIPCHK(upload(P, "acomp_chunk", P->acomp_chunk));
 
@@ -1382,6 +1435,8 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.jcol_part = wsp<double>(P, "jcol_part");
     p.psf_live = wsp<float>(P, "psf_live");
     p.psf64 = wsp<double>(P, "psf64");
+    p.fft_spec = wsp<float2>(P, "fft_spec");
+    p.fft_tw = reinterpret_cast<const float2*>(wsp<float>(P, "fft_tw"));
     p.grad_part = wsp<double>(P, "grad_part");
     P->asrc = wsp<double>(P, "asrc");
     p.pair_part = P->asrc;
@@ -1428,7 +1483,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
 apx_status apx_problem_tile_shapes(const apx_problem* P, int32_t kind, int32_t* counts) {
     if (!P || !counts || kind < 0 || kind > 2) return APX_E_INVALID;
     const std::vector<ConvJob>& jobs = kind == 0 ? P->fwd_jobs : kind == 1 ? P->jcol_jobs : P->adj_jobs;
-    for (int s = 0; s < N_TILE_SHAPES; ++s) counts[s] = 0;
+    for (int s = 0; s <= SHAPE_FFT; ++s) counts[s] = 0;
     for (const ConvJob& jb : jobs)
         if (jb.out_h > 0 && jb.out_w > 0) counts[jb.shape] += 1;
     return APX_OK;
@@ -1496,9 +1551,17 @@ static apx_status run_conv(apx_problem* P, int kind, const ConvIO& io) {
     else { ranges = &P->adj_ranges; jn = "adj_jobs"; inn = "adj_items"; }
     const int klass = kind == CONV_FWD ? APX_TIME_CONV_FWD
                     : (kind == CONV_JCOL || kind == CONV_JCOL_PSF) ? APX_TIME_CONV_JCOL : APX_TIME_CONV_ADJ;
+    const char* pn = kind == CONV_FWD ? "fwd_pairs" : kind == CONV_JCOL ? "jcol_pairs" : "adj_pairs";
     for (const PRange& r : *ranges) {
         TimeScope ts(P, klass);
-        ConvLaunch L{wsp<ConvJob>(P, jn), wsp<ConvItem>(P, inn), r.begin, r.count, r.P, r.shape};
+        ConvLaunch L{wsp<ConvJob>(P, jn), wsp<ConvItem>(P, inn), r.begin, r.count, r.P, r.shape, nullptr,
+                     r.pair_begin, r.pair_count};
+        if (r.shape == SHAPE_FFT) {
+            L.pairs = wsp<int2>(P, pn);
+            hipError_t e = launch_conv_fft(p, kind, L, io, st);
+            if (e != hipSuccess) return fail(P->ctx, APX_E_HIP, std::string("FFT conv launch: ") + hipGetErrorString(e));
+            continue;
+        }
         hipError_t e = kind == CONV_FWD ? (P->objective == APX_OBJECTIVE_FP64 ? launch_conv_fwd64(p, L, io, st)
                                                                                : launch_conv_fwd(p, L, io, st))
                      : (kind == CONV_JCOL || kind == CONV_JCOL_PSF) ? launch_conv_jcol(p, L, io, st)
@@ -1531,6 +1594,10 @@ static apx_status prep(apx_problem* P, const double* theta, int lm_trial, int sk
     {
         TimeScope ts(P, APX_TIME_PREP);
         HIPCHK(launch_prep(p, theta, lm_trial, st));
+        if (P->n_fft_images > 0) {               // stamp spectra: live stamps per theta, fixed once
+            HIPCHK(launch_fft_stamps(p, P->fft_fixed_ready ? 1 : 0, st));
+            P->fft_fixed_ready = true;
+        }
     }
     if (P->mode == APX_MODE_ADAPTIVE) {
         TimeScope ts(P, APX_TIME_RENDER);

@@ -23,6 +23,12 @@ constexpr int CHOL_NB = 64;                   // block size of the blocked Chole
 constexpr int SMALL_N = 64;                   // sub-problems up to this size: one-wave solver
 constexpr int MAX_NODES_1D = 8;
 constexpr int N_XCD = 8;                       // accelerator dies, each with its own L2
+// FFT-mode convolution: 128 x 128 transform tiles; a job in FFT mode has tile shape
+// SHAPE_FFT, whose output blocks are (FFT_T - P + 1)^2
+constexpr int FFT_T = 128;
+constexpr int SHAPE_FFT = N_TILE_SHAPES;
+__host__ __device__ constexpr int shape_th(int s, int P) { return s == SHAPE_FFT ? FFT_T - P + 1 : tile_th(s); }
+__host__ __device__ constexpr int shape_tw(int s, int P) { return s == SHAPE_FFT ? FFT_T - P + 1 : tile_tw(s); }
 
 // Workgroups of a launch are dealt to the XCDs round-robin (block b to XCD b % 8).
 // Block b takes logical item xcd_item(b, n): every XCD then owns a contiguous range of
@@ -55,6 +61,7 @@ struct DImage {
     int pad_live;
     double live_fixed[2];
     long long live_off;       // into psf_live: K, dK/dn, dK/dR_d (3 P^2 floats)
+    long long fft_off;        // FFT mode: into fft_spec (2 slots of FFT_T^2), -1 = none
 };
 
 struct DComp {
@@ -153,6 +160,8 @@ struct Plan {
     float* psf_flip;          // flipped stamps (adjoint)
     float* psf_live;          // live-PSF stamps and their derivatives (3 P^2 per live image)
     double* psf64;            // every stamp in FP64 (objective convolution)
+    float2* fft_spec;         // FFT mode: stamp spectra (K, flipped K) per image
+    const float2* fft_tw;     // [FFT_T]: exp(-2 pi i m / FFT_T)
 
     // render tiles with component CSR
     const RTile* rtiles; int n_rtiles;
@@ -244,6 +253,8 @@ struct ConvLaunch {
     const ConvJob* jobs;
     const ConvItem* items;
     int item_begin, item_count, P, shape;
+    const int2* pairs;        // FFT mode: items sharing one transform (second -1 = none)
+    int pair_begin, pair_count;
 };
 struct ConvIO {
     const float* in;          // input buffer base (FWD, JCOL)
@@ -261,6 +272,9 @@ hipError_t launch_conv_fwd(const Plan& p, const ConvLaunch& L, const ConvIO& io,
 hipError_t launch_conv_fwd64(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
 hipError_t launch_conv_jcol(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
 hipError_t launch_conv_adj(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
+// k_conv_fft.hip: FFT mode (kinds FWD with the FP32 objective, JCOL, ADJ)
+hipError_t launch_conv_fft(const Plan& p, int kind, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
+hipError_t launch_fft_stamps(const Plan& p, int live_only, hipStream_t st);
 
 // k_jtwj.hip
 struct PairLaunch { const DPair* pairs; const PairItem* items; int n_items; int tm; };

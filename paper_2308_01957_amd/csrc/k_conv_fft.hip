@@ -1,0 +1,322 @@
+// FFT-mode PSF convolution (§2.1.3: besides direct convolution the paper offers an FFT mode
+// for large PSFs).  Overlap-save on 128 x 128 tiles held in LDS: a workgroup stages a
+// 128 x 128 input tile (zero outside the input rectangle), takes its 2-D FFT, multiplies
+// by the stamp's spectrum (computed once per stamp and theta), transforms back and keeps
+// the (129 - P)^2 outputs that the circular wrap does not touch.  Two output blocks that
+// use the same stamp ride in one complex transform (one in the real part, one in the
+// imaginary part: the stamp is real, so the two convolutions separate exactly).
+//
+// The 128-point transforms run as 16 x 8 Cooley-Tukey: a 16-point DFT in registers per
+// stride-8 subsequence, the 128th-root twiddles, then an 8-point DFT in registers; rows,
+// then columns, with LDS rows padded by one element.  The inverse uses conj(FFT(conj(.))).
+// FP32 throughout (the objective's FP64 convolution stays direct); the error is a few ulp
+// of the tile's largest values times log2 of the transform size.
+//
+// Same epilogues as the direct kernel: model + chi^2 partials (FP32 objective), Jacobian
+// columns + partials, adjoint.
+#include "apx_internal.h"
+
+namespace apx {
+
+constexpr int FT = FFT_T;                 // 128
+constexpr int FTP = FT + 1;               // padded LDS row
+constexpr int FFT_THREADS = 1024;
+static_assert(FT == 128, "the 16 x 8 decomposition below is for 128-point transforms");
+
+struct cf { float x, y; };
+__device__ __forceinline__ cf cadd(cf a, cf b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cf csub(cf a, cf b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cf cmul(cf a, cf b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
+// exp(-2 pi i m / 16), m = 0..15
+__device__ __forceinline__ cf w16(int m) {
+    constexpr float C1 = 0.92387953251128674f, S1 = 0.38268343236508978f, R2 = 0.70710678118654752f;
+    const float cs[16] = {1.f, C1, R2, S1, 0.f, -S1, -R2, -C1, -1.f, -C1, -R2, -S1, 0.f, S1, R2, C1};
+    const float sn[16] = {0.f, S1, R2, C1, 1.f, C1, R2, S1, 0.f, -S1, -R2, -C1, -1.f, -C1, -R2, -S1};
+    return {cs[m & 15], -sn[m & 15]};
+}
+
+__host__ __device__ constexpr int bitrev(int v, int bits) {
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((v >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+
+// In-register DFT of N = 8 or 16 points, natural order in and out (radix-2, decimation in
+// time; every index and twiddle is a compile-time constant after unrolling).
+template <int N>
+__device__ __forceinline__ void dft_reg(cf (&x)[N]) {
+    constexpr int LOG = N == 16 ? 4 : 3;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int j = bitrev(i, LOG);
+        if (i < j) { const cf t = x[i]; x[i] = x[j]; x[j] = t; }
+    }
+#pragma unroll
+    for (int len = 2; len <= N; len <<= 1) {
+#pragma unroll
+        for (int i = 0; i < N; i += len) {
+#pragma unroll
+            for (int k = 0; k < len / 2; ++k) {
+                const cf w = w16(k * (16 / len));
+                const cf u = x[i + k], v = cmul(x[i + k + len / 2], w);
+                x[i + k] = cadd(u, v);
+                x[i + k + len / 2] = csub(u, v);
+            }
+        }
+    }
+}
+
+// 128-point forward FFTs of all 128 lines of the LDS tile; rows (dir 0: element e of line
+// l at l * FTP + e) or columns (dir 1: at e * FTP + l).  tw[m] = exp(-2 pi i m / 128).
+__device__ __forceinline__ void fft_lines(cf* sm, const cf* tw, int dir) {
+    const int t = threadIdx.x;
+    const int ls = dir == 0 ? FTP : 1, es = dir == 0 ? 1 : FTP;
+    {   // pass A: thread (line, n2), n2 < 8: 16-point DFT over n1 of x[n2 + 8 n1], times W^(n2 k1)
+        const int line = dir == 0 ? t >> 3 : t & 127;
+        const int n2 = dir == 0 ? t & 7 : t >> 7;
+        cf* base = sm + line * ls;
+        cf x[16];
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) x[n1] = base[(n2 + 8 * n1) * es];
+        dft_reg<16>(x);
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) base[(n2 + 8 * k1) * es] = cmul(x[k1], tw[(n2 * k1) & 127]);
+    }
+    __syncthreads();
+    {   // pass B: thread (line, k1) for two k1: 8-point DFT over n2 -> X[k1 + 16 k2]
+        cf x[2][8];
+        int line[2], k1[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int u = t + FFT_THREADS * h;                 // 0 .. 2047
+            line[h] = dir == 0 ? u >> 4 : u & 127;
+            k1[h] = dir == 0 ? u & 15 : u >> 7;
+            const cf* base = sm + line[h] * ls;
+#pragma unroll
+            for (int n2 = 0; n2 < 8; ++n2) x[h][n2] = base[(n2 + 8 * k1[h]) * es];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            dft_reg<8>(x[h]);
+            cf* base = sm + line[h] * ls;
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) base[(k1[h] + 16 * k2) * es] = x[h][k2];
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void fft2d(cf* sm, const cf* tw) {
+    fft_lines(sm, tw, 0);
+    fft_lines(sm, tw, 1);
+}
+
+__device__ __forceinline__ void load_twiddles(const Plan& p, cf* tw) {
+    if (threadIdx.x < FT) {
+        const float2 v = p.fft_tw[threadIdx.x];
+        tw[threadIdx.x] = {v.x, v.y};
+    }
+}
+
+// Spectrum of one stamp slot of one image, zero-padded to 128 x 128 at the origin: K
+// (slot 0, the model and Jacobian convolutions) and K flipped (slot 1, the adjoint).  On a
+// live-PSF image K is the stamp rendered for the current theta.
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_stamp(Plan p, int live_only) {
+    __shared__ cf sm[FT * FTP];
+    __shared__ cf tw[FT];
+    const int k = blockIdx.y, slot = blockIdx.x;
+    const DImage& im = p.images[k];
+    if (im.fft_off < 0 || (live_only && !im.live)) return;
+
+    load_twiddles(p, tw);
+    const int P = im.P;
+    const float* K = im.live ? p.psf_live + im.live_off : p.psf + im.psf_off;
+    for (int e = threadIdx.x; e < FT * FT; e += FFT_THREADS) {
+        const int u = e >> 7, v = e & 127;
+        float val = 0.f;
+        if (u < P && v < P) val = slot == 1 ? K[(P - 1 - u) * P + (P - 1 - v)] : K[u * P + v];
+        sm[u * FTP + v] = {val, 0.f};
+    }
+    __syncthreads();
+    fft2d(sm, tw);
+    float2* out = p.fft_spec + im.fft_off + (long long)slot * FT * FT;
+    for (int e = threadIdx.x; e < FT * FT; e += FFT_THREADS) {
+        const cf v = sm[(e >> 7) * FTP + (e & 127)];
+        out[e] = make_float2(v.x, v.y);
+    }
+}
+
+hipError_t launch_fft_stamps(const Plan& p, int live_only, hipStream_t st) {
+    if (p.n_images == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fft_stamp, dim3(2, p.n_images), dim3(FFT_THREADS), 0, st, p, live_only);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ double fft_block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        s = red[0];
+        for (int w = 1; w < FFT_THREADS / 64; ++w) s += red[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob* __restrict__ jobs,
+                                                          const ConvItem* __restrict__ items,
+                                                          const int2* __restrict__ pairs, int pair_begin,
+                                                          ConvIO io) {
+    __shared__ cf sm[FT * FTP];
+    __shared__ cf tw[FT];
+    __shared__ double red[FFT_THREADS / 64];
+    const int2 pr = pairs[pair_begin + blockIdx.x];
+    const int half_item[2] = {pr.x, pr.y};
+    const ConvJob jb0 = jobs[items[pr.x].job];
+    const DImage& im = p.images[jb0.image];
+    if (io.skip_mode == 1) {
+        if (p.lmf[im.sub].chol_done == 0 || p.lmf[im.sub].trial_bad != 0) return;
+    } else if (io.skip_mode == 2) {
+        if (io.lm[im.sub].need_jac == 0) return;
+    }
+    load_twiddles(p, tw);
+    const int P = im.P, c = (P - 1) / 2, V = FT - P + 1;
+
+    // ---- stage both halves: element (ly, lx) = input (oy - c + ly, ox - c + lx)
+    for (int h = 0; h < 2; ++h) {
+        const int itx = half_item[h];
+        const ConvItem it = items[itx < 0 ? pr.x : itx];
+        const ConvJob jb = jobs[it.job];
+        const int iy_base = jb.out_y0 + it.ty * V - c, ix_base = jb.out_x0 + it.tx * V - c;
+        const float* in = nullptr;
+        if constexpr (KIND != CONV_ADJ) in = io.in + jb.in_off + (long long)it.ch * jb.in_cs;
+        const int iy1 = jb.in_y0 + jb.in_h, ix1 = jb.in_x0 + jb.in_w;
+        for (int e = threadIdx.x; e < FT * FT; e += FFT_THREADS) {
+            const int ly = e >> 7, lx = e & 127;
+            const int y = iy_base + ly, x = ix_base + lx;
+            float val = 0.f;
+            if (itx >= 0) {
+                if constexpr (KIND == CONV_ADJ) {
+                    if (y >= 0 && y < im.H && x >= 0 && x < im.W) {
+                        const long long pix = im.pix_off + (long long)y * im.W + x;
+                        val = io.seed ? io.seed[pix] : -2.f * io.weight[pix] * p.rbuf[pix];
+                    }
+                } else {
+                    if (y >= jb.in_y0 && y < iy1 && x >= jb.in_x0 && x < ix1)
+                        val = in[(long long)(y - jb.in_y0) * jb.in_w + (x - jb.in_x0)];
+                }
+            }
+            cf& s = sm[ly * FTP + lx];
+            if (h == 0) s.x = val;
+            else s.y = val;
+        }
+    }
+    __syncthreads();
+    fft2d(sm, tw);
+
+    // ---- times the stamp spectrum, conjugated for the inverse
+    const int slot = KIND == CONV_ADJ ? 1 : 0;
+    const float2* Kf = p.fft_spec + im.fft_off + (long long)slot * FT * FT;
+    for (int e = threadIdx.x; e < FT * FT; e += FFT_THREADS) {
+        const float2 kv = Kf[e];
+        cf& s = sm[(e >> 7) * FTP + (e & 127)];
+        const cf m = cmul(s, {kv.x, kv.y});
+        s = {m.x, -m.y};
+    }
+    __syncthreads();
+    fft2d(sm, tw);
+    const float scale = 1.f / (float)(FT * FT);     // real part of the inverse: x / N, imaginary: -y / N
+
+    // ---- epilogues, one half at a time
+    for (int h = 0; h < 2; ++h) {
+        const int itx = half_item[h];
+        if (itx < 0) break;                          // uniform across the block
+        const ConvItem it = items[itx];
+        const ConvJob jb = jobs[it.job];
+        const int oy = jb.out_y0 + it.ty * V, ox = jb.out_x0 + it.tx * V;
+        const int yend = min(oy + V, jb.out_y0 + jb.out_h), xend = min(ox + V, jb.out_x0 + jb.out_w);
+        const int bh = yend - oy, bw = xend - ox;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        if constexpr (KIND == CONV_FWD) {
+            const float sky = (float)p.sky_val[jb.image];
+            for (int e = threadIdx.x; e < bh * bw; e += FFT_THREADS) {
+                const int dy = e / bw, dx = e - dy * bw;
+                const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
+                const float m = (h == 0 ? s.x : -s.y) * scale + sky;
+                const long long pix = im.pix_off + (long long)(oy + dy) * im.W + (ox + dx);
+                if (io.out) io.out[pix] = m;
+                if (io.data) {
+                    const double w = (double)io.weight[pix];
+                    const double rr = (double)io.data[pix] - (double)m;
+                    a0 += w * rr * rr;
+                    a1 += w * rr;
+                    a2 += w;
+                    p.rbuf[pix] = (float)rr;
+                }
+            }
+            if (io.data) {
+                a0 = fft_block_sum(a0, red);
+                a1 = fft_block_sum(a1, red);
+                a2 = fft_block_sum(a2, red);
+                if (threadIdx.x == 0) {
+                    io.part[(long long)itx * 3 + 0] = a0;
+                    io.part[(long long)itx * 3 + 1] = a1;
+                    io.part[(long long)itx * 3 + 2] = a2;
+                }
+            }
+        } else if constexpr (KIND == CONV_JCOL) {
+            float* __restrict__ out = io.out + jb.out_off + (long long)it.ch * jb.out_cs;
+            for (int e = threadIdx.x; e < bh * bw; e += FFT_THREADS) {
+                const int dy = e / bw, dx = e - dy * bw;
+                const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
+                const float v = (h == 0 ? s.x : -s.y) * scale;
+                const int y = oy + dy, x = ox + dx;
+                out[(long long)(y - jb.out_y0) * jb.out_w + (x - jb.out_x0)] = v;
+                if (io.weight) {
+                    const long long pix = im.pix_off + (long long)y * im.W + x;
+                    const double wj = (double)io.weight[pix] * (double)v;
+                    a0 += wj * (double)p.rbuf[pix];
+                    a1 += wj;
+                }
+            }
+            if (io.weight) {
+                a0 = fft_block_sum(a0, red);
+                a1 = fft_block_sum(a1, red);
+                if (threadIdx.x == 0) {
+                    io.part[(long long)itx * 2 + 0] = a0;
+                    io.part[(long long)itx * 2 + 1] = a1;
+                }
+            }
+        } else {
+            float* __restrict__ out = io.out + jb.out_off;
+            for (int e = threadIdx.x; e < bh * bw; e += FFT_THREADS) {
+                const int dy = e / bw, dx = e - dy * bw;
+                const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
+                out[(long long)(oy + dy - jb.out_y0) * jb.out_w + (ox + dx - jb.out_x0)] =
+                    (h == 0 ? s.x : -s.y) * scale;
+            }
+        }
+    }
+}
+
+template <int KIND>
+static hipError_t launch_fft_kind(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st) {
+    if (L.pair_count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_conv_fft<KIND>, dim3(L.pair_count), dim3(FFT_THREADS), 0, st, p, L.jobs, L.items,
+                       L.pairs, L.pair_begin, io);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_fft(const Plan& p, int kind, const ConvLaunch& L, const ConvIO& io, hipStream_t st) {
+    if (kind == CONV_FWD) return launch_fft_kind<CONV_FWD>(p, L, io, st);
+    if (kind == CONV_JCOL) return launch_fft_kind<CONV_JCOL>(p, L, io, st);
+    if (kind == CONV_ADJ) return launch_fft_kind<CONV_ADJ>(p, L, io, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace apx

@@ -166,3 +166,22 @@ def adaptive_fit():
                        k_re=1e-2, logie_range=(0.5, 1.5))
     spec["name"] = "adaptive56x60_fit"
     return with_data(spec)
+
+
+def fft_blend():
+    """FFT-mode convolution on a ragged 150 x 170 blend, P = 25: four Sersics (one with a
+    window cut by the extended grid) on FFT tiles, five point sources on direct tiles."""
+    spec = synth.blend(seed_id=130, H=150, W=170, n_sersic=4, n_point=5, P=25, logie_range=(0.0, 1.0))
+    spec["comps"][1]["box"] = (-12, 30, 120, 182)
+    spec["conv_mode"] = 1
+    spec["name"] = "fft_blend150x170_P25"
+    return with_data(spec)
+
+
+def fft_fit():
+    """A 110 x 120 blend (3 bright Sersics, 2 point sources, sky; P = 25) that the LM
+    settles, with FFT-mode convolution."""
+    spec = synth.blend(seed_id=132, H=110, W=120, n_sersic=3, n_point=2, P=25, logie_range=(0.5, 1.5))
+    spec["conv_mode"] = 1
+    spec["name"] = "fft_fit110x120_P25"
+    return with_data(spec)

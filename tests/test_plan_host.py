@@ -94,7 +94,7 @@ def test_model_tile_policy_prefers_tiles_that_fit_the_output(apx):
     narrower tiles where they cut the padding of a 40-pixel-wide window."""
     big = synth.single(1, H=512, W=512, P=11)
     pl = apx.Plan(big, tiles=apx.TILES_MODEL)
-    assert pl.tile_shapes(0) == [1, 0, 0, 0]
+    assert pl.tile_shapes(0) == [1, 0, 0, 0, 0]
     pl.close()
     small = synth.single(1, H=40, W=40, P=11)
     pl = apx.Plan(small, tiles=apx.TILES_MODEL)
@@ -118,3 +118,31 @@ def test_adaptive_mode_sizes_its_per_pixel_arrays(apx):
     npx = sum((c["box"][2] - c["box"][0]) * (c["box"][3] - c["box"][1])
               for c in spec["comps"] if c["type"] == 0)
     assert npx > 0 and ad - base >= 48 * npx - 16 * 256       # less the empty arrays of the base plan
+
+
+def test_fft_mode_takes_the_large_outputs_of_large_stamps(apx):
+    """conv_mode FFT: on a P = 25 image the Jacobian columns of the full-image windows and
+    the adjoint go to FFT tiles, the small point-source windows stay direct, and the model
+    convolution stays direct under the FP64 objective but not under the FP32 one."""
+    spec = synth.blend(seed_id=302, H=120, W=130, n_sersic=3, n_point=4, P=25)
+    spec["conv_mode"] = apx.CONV_FFT
+    pl = apx.Plan(spec)
+    assert pl.tile_shapes(0)[4] == 0
+    assert pl.tile_shapes(1)[4] == 1 and sum(pl.tile_shapes(1)[:4]) == 4
+    assert pl.tile_shapes(2)[4] == 1
+    pl.close()
+    pl = apx.Plan(spec, objective=1)
+    assert pl.tile_shapes(0)[4] == 1
+    pl.close()
+    small = synth.blend(seed_id=303, H=120, W=130, n_sersic=3, n_point=4, P=11)
+    small["conv_mode"] = apx.CONV_FFT
+    pl = apx.Plan(small)
+    assert all(pl.tile_shapes(k)[4] == 0 for k in range(3))       # P below the FFT threshold
+    pl.close()
+
+
+def test_unknown_conv_mode_is_rejected(apx):
+    spec = _small()
+    spec["conv_mode"] = 7
+    with pytest.raises(apx.ApxError):
+        apx.Plan(spec)
