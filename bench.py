@@ -84,6 +84,14 @@ def cpu_baseline(spec, data, weight):
     }
 
 
+def _conv(args, spec):
+    """The workload spec with the convolution mode asked for on the command line."""
+    if args.conv == "fft":
+        spec = dict(spec)
+        spec["conv_mode"] = 1
+    return spec
+
+
 def _data(prob, spec, synth):
     """Noise-free model of the truth rendered by the library, noisy data and weights."""
     m = prob.split(prob.render(spec["theta_true"]))
@@ -96,7 +104,12 @@ def _data(prob, spec, synth):
     return data, weight
 
 
+CONV_MODE = ["direct"]                # set from --conv; recorded in every line's config
+
+
 def _line(rec):
+    if isinstance(rec.get("config"), dict):
+        rec["config"]["conv"] = CONV_MODE[0]
     print(json.dumps(rec), flush=True)
 
 
@@ -120,7 +133,7 @@ def run_cutouts(args, torch, apx, synth):
     spec = synth.cutouts()
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    prob = apx.Problem(spec)
+    prob = apx.Problem(_conv(args, spec))
     t_plan = time.perf_counter() - t0
     print(f"[bench] cutouts: {len(spec['subs'])} sub-problems, {prob.n_pix / 1e6:.1f} Mpix, "
           f"plan {t_plan:.1f} s, workspace {prob.workspace_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
@@ -152,7 +165,7 @@ def run_cutouts(args, torch, apx, synth):
     t_plain = 0.0
     for s_ in sample:
         sub = synth.sub_spec(spec, s_)
-        pp = apx.Problem(sub)
+        pp = apx.Problem(_conv(args, sub))
         ks = [k for k, im in enumerate(spec["images"]) if im["sub"] == s_]
         d_s = pp.pixels([data[k] for k in ks])
         w_s = pp.pixels([weight[k] for k in ks])
@@ -189,7 +202,7 @@ def run_field(args, torch, apx, synth):
     evaluations per second by the adjoint path; checked against central differences of
     the FP64 chi^2 on 32 seeded parameters."""
     spec = synth.field()
-    prob = apx.Problem(spec)
+    prob = apx.Problem(_conv(args, spec))
     data, weight = _data(prob, spec, synth)
     dd, ww = prob.pixels(data), prob.pixels(weight)
     th = torch.as_tensor(spec["theta_init"], dtype=torch.float64, device=prob.device)
@@ -244,7 +257,7 @@ def run_field(args, torch, apx, synth):
 
 
 def run_lm_workload(args, torch, apx, synth, spec, label, desc):
-    prob = apx.Problem(spec)
+    prob = apx.Problem(_conv(args, spec))
     data, weight = _data(prob, spec, synth)
     dd, ww = prob.pixels(data), prob.pixels(weight)
     th, st = prob.lm_init(spec["theta_init"], dd, ww)
@@ -303,7 +316,7 @@ def run_hmc(args, torch, apx, synth):
     `steps` x 25 timed transitions of 10 leapfrog steps each."""
     spec = synth.live_psf(seed_id=9, H=128, W=128, n_star=1, n_sersic=1, P=25, logf_range=(2.0, 2.5),
                           logie_range=(0.0, 0.5))
-    prob = apx.Problem(spec)
+    prob = apx.Problem(_conv(args, spec))
     data, weight = _data(prob, spec, synth)
     dd, ww = prob.pixels(data), prob.pixels(weight)
     th, st = prob.lm_init(spec["theta_init"], dd, ww)
@@ -400,10 +413,13 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also launch three plain copy kernels of MIB MiB (read MIB, write MIB) "
                          "after the timed region, to calibrate HBM byte counters")
+    ap.add_argument("--conv", default="direct", choices=["direct", "fft"],
+                    help="PSF convolution mode: direct (default) or FFT tiles for P >= 15")
     ap.add_argument("--workload", default="blend",
                     choices=["blend", "cutouts", "field", "multiband", "single", "livepsf", "adaptive", "hmc"],
                     help="blend (default, the headline line); the others print their own line")
     args = ap.parse_args()
+    CONV_MODE[0] = args.conv
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -424,7 +440,7 @@ def main():
     img = spec["images"][0]
     P_psf = img["psf"].shape[0]
     print(f"[bench] workload {spec['name']}: {spec['n_par']} parameters", file=sys.stderr, flush=True)
-    prob = apx.Problem(spec)
+    prob = apx.Problem(_conv(args, spec))
     m_true = prob.split(prob.render(spec["theta_true"]))[0].astype(np.float64)
     prob.check()
     d, w = synth.make_data(m_true, spec["noise"][0])

@@ -72,9 +72,12 @@ __device__ __forceinline__ void dft_reg(cf (&x)[N]) {
 __device__ __forceinline__ void fft_lines(cf* sm, const cf* tw, int dir) {
     const int t = threadIdx.x;
     const int ls = dir == 0 ? FTP : 1, es = dir == 0 ? 1 : FTP;
+    // Lanes of a wave take 64 consecutive lines at one position: with the odd row pitch FTP
+    // the 64 addresses of every LDS access fall in distinct banks (two per bank for 8-byte
+    // elements), for rows and columns alike.
     {   // pass A: thread (line, n2), n2 < 8: 16-point DFT over n1 of x[n2 + 8 n1], times W^(n2 k1)
-        const int line = dir == 0 ? t >> 3 : t & 127;
-        const int n2 = dir == 0 ? t & 7 : t >> 7;
+        const int line = t & 127;
+        const int n2 = t >> 7;
         cf* base = sm + line * ls;
         cf x[16];
 #pragma unroll
@@ -90,8 +93,8 @@ __device__ __forceinline__ void fft_lines(cf* sm, const cf* tw, int dir) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int u = t + FFT_THREADS * h;                 // 0 .. 2047
-            line[h] = dir == 0 ? u >> 4 : u & 127;
-            k1[h] = dir == 0 ? u & 15 : u >> 7;
+            line[h] = u & 127;
+            k1[h] = u >> 7;
             const cf* base = sm + line[h] * ls;
 #pragma unroll
             for (int n2 = 0; n2 < 8; ++n2) x[h][n2] = base[(n2 + 8 * k1[h]) * es];
