@@ -14,7 +14,10 @@ import it.  What it computes, with the passages it follows:
   momenta r = F^T p (r ~ N(0, I) exactly when p ~ N(0, M)), the kinetic energy is
   K = |r|^2 / 2 and the leapfrog step of size eps reads
       r <- r - (eps/2) F^T grad U(theta);  theta <- theta + eps F r;  r <- r - (eps/2) F^T grad U(theta).
-* Every sub-problem is its own chain (its chi^2 involves only its parameters): its own
+* No-U-Turn sampling (§2.5, §3.5: the paper's example runs NUTS with the LM covariance
+  as mass matrix): the slice-sampling NUTS of Hoffman & Gelman in the same whitened
+  coordinates, one joint chain over all sub-problems (`nuts_transition`, `nuts_chain`).
+* Every HMC sub-problem is its own chain (its chi^2 involves only its parameters): its own
   energy, its own accept test, its own uniform draw.  The random numbers are inputs
   (standard normals z for the momenta, uniforms u for the tests).  A trajectory that
   leaves the model domain at any leapfrog step is rejected (its energy is infinite).
@@ -97,4 +100,141 @@ def hmc_chain(spec, theta0, data, weight, F_blocks, step: float, n_leapfrog: int
                 theta[sl] = tL
             samples[i, sl] = theta[sl]
             stats[i, s] = (1.0 if acc else 0.0, H0, H1)
+    return samples, stats
+
+
+# --------------------------------------------------------------------------- NUTS
+NUTS_DELTA_MAX = 1000.0          # energy error that ends a trajectory as divergent
+
+
+class _Draws:
+    """The uniforms of one NUTS transition, taken strictly in the order the algorithm asks
+    for them: the slice variable first, then one per doubling direction and one per merge
+    of a subtree or of a doubling, as they occur."""
+
+    def __init__(self, u):
+        self.u = u
+        self.k = 0
+
+    def next(self):
+        v = float(self.u[self.k])
+        self.k += 1
+        return v
+
+
+def nuts_draws_per_sample(max_depth: int) -> int:
+    """Uniforms a transition may consume: slice + directions + at most one per tree node."""
+    return 1 + max_depth + (1 << (max_depth + 1))
+
+
+def nuts_transition(theta0, r0, F, U, grad_U, step, max_depth, u):
+    """One No-U-Turn transition (the "efficient" slice-sampling NUTS of Hoffman & Gelman,
+    which the paper's Bayesian example (§3.5) runs through an external package) in whitened
+    momenta: energy H = U(theta) + |r|^2 / 2, leapfrog as `leapfrog`, velocity F r.
+
+    The trajectory doubles in a random direction per step (v = -1 if the draw < 1/2); a
+    point is in the slice when log(slice) <= -H, i.e. log(u0) - H0 <= -H; a subtree stops
+    when -H < log(slice) - NUTS_DELTA_MAX (divergence) or when its ends make a U-turn,
+    (theta+ - theta-) . F r- < 0 or (theta+ - theta-) . F r+ < 0.  The proposal of a subtree
+    is replaced by that of its second half with probability n'' / (n' + n''); that of the
+    chain by a new doubling's with probability min(1, n' / n).  Returns (theta, stats) with
+    stats = (depth, leapfrog steps, points in the slice, divergent)."""
+    d = _Draws(u)
+    theta0 = np.asarray(theta0, dtype=np.float64)
+    r0 = np.asarray(r0, dtype=np.float64)
+
+    def H(t, r):
+        e = U(t)
+        return math.inf if not math.isfinite(e) else e + 0.5 * float(r @ r)
+
+    H0 = H(theta0, r0)
+    log_slice = math.log(d.next()) - H0
+    counters = {"steps": 0, "divergent": 0}
+
+    def step1(t, r, g, v):
+        r = r - 0.5 * v * step * (F.T @ g)
+        t = t + v * step * (F @ r)
+        g = grad_U(t)
+        r = r - 0.5 * v * step * (F.T @ g)
+        counters["steps"] += 1
+        return t, r, g
+
+    def no_uturn(tm, rm, tp, rp):
+        dt = tp - tm
+        return float(dt @ (F @ rm)) >= 0.0 and float(dt @ (F @ rp)) >= 0.0
+
+    def build(t, r, g, v, j):
+        """(t-, r-, g-, t+, r+, g+, proposal, n, s) of a subtree of 2^j leapfrog steps."""
+        if j == 0:
+            t1, r1, g1 = step1(t, r, g, v)
+            h = H(t1, r1)
+            n = 1 if log_slice <= -h else 0
+            s = 1 if log_slice < -h + NUTS_DELTA_MAX else 0
+            if not s:
+                counters["divergent"] = 1
+            return t1, r1, g1, t1, r1, g1, t1, n, s
+        tm, rm, gm, tp, rp, gp, prop, n1, s1 = build(t, r, g, v, j - 1)
+        if s1:
+            if v < 0:
+                tm, rm, gm, _, _, _, prop2, n2, s2 = build(tm, rm, gm, v, j - 1)
+            else:
+                _, _, _, tp, rp, gp, prop2, n2, s2 = build(tp, rp, gp, v, j - 1)
+            if d.next() * (n1 + n2) < n2:
+                prop = prop2
+            s1 = s2 if no_uturn(tm, rm, tp, rp) else 0
+            n1 = n1 + n2
+        return tm, rm, gm, tp, rp, gp, prop, n1, s1
+
+    g0 = grad_U(theta0)
+    tm = tp = theta0
+    rm = rp = r0
+    gm = gp = g0
+    theta = theta0
+    n, s, depth = 1, 1, 0
+    while s and depth < max_depth:
+        v = -1.0 if d.next() < 0.5 else 1.0
+        if v < 0:
+            tm, rm, gm, _, _, _, prop, n1, s1 = build(tm, rm, gm, v, depth)
+        else:
+            _, _, _, tp, rp, gp, prop, n1, s1 = build(tp, rp, gp, v, depth)
+        if s1 and d.next() * n < n1:
+            theta = prop
+        n += n1
+        s = s1 if no_uturn(tm, rm, tp, rp) else 0
+        depth += 1
+    return theta, (depth, counters["steps"], n, counters["divergent"])
+
+
+def nuts_chain(spec, theta0, data, weight, F, step: float, max_depth: int, z, u):
+    """NUTS on the joint posterior of every sub-problem (one chain; U = sum chi^2 / 2) with
+    the inverse-mass factor F (n_par x n_par, block diagonal per sub-problem).  z:
+    [n_samples, n_par] standard normals (the momenta), u: [n_samples,
+    nuts_draws_per_sample(max_depth)] uniforms.  Returns (samples, stats [n_samples, 4])."""
+    from .core import chi2 as chi2_all
+
+    theta = np.array(theta0, dtype=np.float64)
+    subs = spec["subs"]
+
+    def U(t):
+        if not all(in_domain(spec, t, s) for s in range(len(subs))):
+            return math.inf
+        return 0.5 * float(np.sum(chi2_all(spec, t, data, weight)))
+
+    def grad_U(t):
+        if not all(in_domain(spec, t, s) for s in range(len(subs))):
+            return np.full(t.size, np.nan)
+        g = np.zeros(t.size)
+        for s, (p0, npar) in enumerate(subs):
+            _, gs, _ = jtwj(spec, t, data, weight, s)
+            g[p0:p0 + npar] = -gs
+        return g
+
+    z = np.asarray(z, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    samples = np.zeros((z.shape[0], theta.size))
+    stats = np.zeros((z.shape[0], 4))
+    for i in range(z.shape[0]):
+        theta, st = nuts_transition(theta, z[i], F, U, grad_U, step, max_depth, u[i])
+        samples[i] = theta
+        stats[i] = st
     return samples, stats

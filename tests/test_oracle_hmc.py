@@ -131,3 +131,74 @@ def test_planted_missing_half_in_the_potential_fails_the_sky_pin(monkeypatch):
     monkeypatch.setattr(oracle.hmc, "jtwj", doubled)
     with pytest.raises(AssertionError):
         test_hmc_on_the_sky_only_fit_follows_the_closed_form()
+
+
+# ------------------------------------------------------------------------------ NUTS
+def _gauss2(rng=None):
+    Sigma = np.array([[2.0, 1.2], [1.2, 1.5]])
+    mu = np.array([0.7, -1.3])
+    P = np.linalg.inv(Sigma)
+    U = lambda t: 0.5 * float((t - mu) @ P @ (t - mu))
+    G = lambda t: P @ (t - mu)
+    return Sigma, mu, U, G
+
+
+def _nuts_run(F, U, G, step, n, max_depth=8, seed=3, theta0=None):
+    rng = np.random.default_rng(seed)
+    th = np.zeros(F.shape[0]) if theta0 is None else np.array(theta0, float)
+    nd = oracle.nuts_draws_per_sample(max_depth)
+    out, st = [], []
+    for _ in range(n):
+        th, s = oracle.nuts_transition(th, rng.standard_normal(F.shape[0]), F, U, G, step, max_depth,
+                                       rng.uniform(size=nd))
+        out.append(th)
+        st.append(s)
+    return np.array(out), np.array(st)
+
+
+def test_nuts_samples_a_correlated_gaussian():
+    """Stationary mean and covariance of 3000 NUTS draws within 4 standard errors."""
+    Sigma, mu, U, G = _gauss2()
+    F = np.linalg.cholesky(Sigma)
+    x, st = _nuts_run(F, U, G, 0.4, 3000)
+    n = x.shape[0]
+    se_mean = np.sqrt(np.diag(Sigma) / n)
+    assert np.all(np.abs(x.mean(0) - mu) < 4 * se_mean), (x.mean(0), mu)
+    C = np.cov(x.T)
+    se_cov = np.sqrt((Sigma ** 2 + np.outer(np.diag(Sigma), np.diag(Sigma))) / n)
+    assert np.all(np.abs(C - Sigma) < 4 * se_cov), (C, Sigma)
+    assert np.all(st[:, 3] == 0)
+
+
+def test_nuts_tree_sizes_follow_the_half_period():
+    """Unit Gaussian, step 0.1: in phase space the leapfrog turns by ~0.1 rad per step, and
+    the ends make a U-turn within half a period (pi, ~31 steps), so no tree is deeper than
+    6 (63 steps); every doubling but the last is complete."""
+    F = np.eye(1)
+    x, st = _nuts_run(F, lambda t: 0.5 * float(t @ t), lambda t: t.copy(), 0.1, 300)
+    depth, steps = st[:, 0], st[:, 1]
+    assert depth.max() == 6 and depth.min() >= 1
+    assert np.all(steps >= 2 ** (depth - 1)) and np.all(steps <= 2 ** depth - 1)
+    assert np.all(st[:, 2] >= 1)
+
+
+def test_nuts_divergence_keeps_the_start():
+    """A step so large that the energy error passes the divergence threshold: the
+    transition stops at once, is flagged divergent and returns its start."""
+    F = np.eye(1)
+    th0 = np.array([0.3])
+    th, st = oracle.nuts_transition(th0, np.array([0.5]), F, lambda t: 0.5 * float(t @ t) * 1e8,
+                                    lambda t: 1e8 * t, 1.0, 8, np.full(oracle.nuts_draws_per_sample(8), 0.9))
+    assert st[3] == 1 and st[0] == 1 and np.array_equal(th, th0)
+
+
+def test_planted_inverted_merge_test_fails_the_gaussian_pin(monkeypatch):
+    """A merge test that never takes the new half (an inverted comparison) breaks detailed
+    balance: the chain stays near its start and the moments pin fails."""
+    class Stuck(oracle.hmc._Draws):
+        def next(self):
+            v = super().next()
+            return v if self.k == 1 else 0.999
+    monkeypatch.setattr(oracle.hmc, "_Draws", Stuck)
+    with pytest.raises(AssertionError):
+        test_nuts_samples_a_correlated_gaussian()
