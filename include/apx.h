@@ -357,6 +357,29 @@ apx_status apx_hmc_run(apx_problem* p, const float* data, const float* weight, d
                        const double* F, double step, int32_t n_leapfrog, int32_t n_samples,
                        const double* z, const double* u, double* samples, double* stats);
 
+/* No-U-Turn sampling (§2.5; §3.5 runs NUTS from the LM fit with the LM covariance as the
+ * inverse mass matrix): the slice-sampling NUTS of Hoffman & Gelman in the whitened
+ * momenta of apx_hmc_run (same F, leapfrog and energy H = sum_s chi2_s / 2 + |r|^2 / 2),
+ * one joint chain over all sub-problems.  Per transition i: r = z[i * n_par ...]; the
+ * uniforms u[i * D ...], D = 1 + max_depth + 2^(max_depth + 1), are taken strictly in
+ * the order the algorithm asks for them: the slice variable (log slice = log(u) - H0),
+ * then per doubling a direction (-1 if < 1/2) and, as they occur, one per merge of a
+ * subtree (the second half's proposal replaces the first's with probability
+ * n'' / (n' + n'')) and one per doubling whose subtree continued (its proposal becomes the
+ * sample with probability min(1, n' / n)).  A subtree stops when -H < log slice -
+ * APX_NUTS_DELTA_MAX (divergent; also when a point leaves the model domain) or its ends
+ * make a U-turn: (theta+ - theta-) . F r- < 0 or (theta+ - theta-) . F r+ < 0.  The tree
+ * stops at max_depth doublings (1..APX_NUTS_MAX_DEPTH).  theta: device [n_par], in: start,
+ * out: last sample.  samples: device FP64 [n_samples * n_par].  stats: device FP64
+ * [n_samples * 4] = (depth, leapfrog steps, points in the slice, divergent).  The tree
+ * logic runs on the host between device reductions (one synchronisation per leapfrog step
+ * and per U-turn test); returns after the last transition.  Uses the LM's Cholesky scratch. */
+#define APX_NUTS_MAX_DEPTH 10
+#define APX_NUTS_DELTA_MAX 1000.0
+apx_status apx_nuts_run(apx_problem* p, const float* data, const float* weight, double* theta,
+                        const double* F, double step, int32_t max_depth, int32_t n_samples,
+                        const double* z, const double* u, double* samples, double* stats);
+
 /* Vector-Jacobian product of the render (the reverse pass of the model of §2.3, the
  * same adjoint as apx_chi2_grad with the caller's seed in place of -2 w r):
  * grad_theta[k] = sum_i grad_model[i] * d model_i / d theta_k, i over every output pixel

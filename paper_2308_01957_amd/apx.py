@@ -31,7 +31,7 @@ EXPORTS = [
     "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_render_vjp", "apx_lm_init",
     "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
     "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_problem_tile_shapes", "apx_covariance",
-    "apx_covariance_factor", "apx_hmc_run",
+    "apx_covariance_factor", "apx_hmc_run", "apx_nuts_run",
 ]
 TILES_AUTOTUNE, TILES_MODEL, TILES_FIXED = 0, 1, 2
 TILE_SHAPES = [(32, 64), (16, 64), (32, 32), (16, 32)]       # output rows x cols per workgroup
@@ -140,6 +140,7 @@ def load_library(path: str = LIB_PATH):
         "apx_covariance": ([vp, vp, vp, vp, vp, vp], i32),
         "apx_covariance_factor": ([vp, vp, vp, vp, vp, vp], i32),
         "apx_hmc_run": ([vp, vp, vp, vp, vp, ctypes.c_double, i32, i32, vp, vp, vp, vp], i32),
+        "apx_nuts_run": ([vp, vp, vp, vp, vp, ctypes.c_double, i32, i32, vp, vp, vp, vp], i32),
         "apx_lm_init": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_step": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_run": ([vp, i32, vp, vp, vp, vp, i32], i32),
@@ -387,6 +388,32 @@ class Problem:
             self._check(self.lib.apx_hmc_run(self._prob, data.data_ptr(), weight.data_ptr(), theta.data_ptr(),
                                              F.data_ptr(), float(step), int(n_leapfrog), n_samples,
                                              z.data_ptr(), u.data_ptr(), samples.data_ptr(), stats.data_ptr()))
+        self._leave()
+        return samples, stats
+
+    def nuts(self, theta, data, weight, F, step: float, max_depth: int, z, u):
+        """No-U-Turn sampling from theta (device FP64 [n_par], updated in place to the last
+        sample) with inverse-mass factor F (flat per-sub blocks); z: [n_samples, n_par]
+        standard normals, u: [n_samples, 1 + max_depth + 2^(max_depth+1)] uniforms.  Returns
+        (samples [n_samples, n_par], stats [n_samples, 4] = depth, leapfrog steps, points in
+        the slice, divergent)."""
+        t = self.torch
+        z = self._dev(z, t.float64)
+        u = self._dev(u, t.float64)
+        F = self._dev(F, t.float64)
+        nd = 1 + int(max_depth) + (1 << (int(max_depth) + 1))
+        n_samples = int(u.numel() // nd)
+        if u.numel() != n_samples * nd or z.numel() != n_samples * self.n_par:
+            raise ValueError("z must hold n_samples x n_par and u n_samples x (1 + d + 2^(d+1)) entries")
+        if F.numel() < int(self.a_offsets[-1]):
+            raise ValueError("F must hold the per-sub blocks (sum of n_s^2 entries)")
+        self._enter(theta, data, weight, F, z, u)
+        with t.cuda.stream(self.stream):
+            samples = t.empty((n_samples, self.n_par), dtype=t.float64, device=self.device)
+            stats = t.empty((n_samples, 4), dtype=t.float64, device=self.device)
+            self._check(self.lib.apx_nuts_run(self._prob, data.data_ptr(), weight.data_ptr(), theta.data_ptr(),
+                                              F.data_ptr(), float(step), int(max_depth), n_samples,
+                                              z.data_ptr(), u.data_ptr(), samples.data_ptr(), stats.data_ptr()))
         self._leave()
         return samples, stats
 

@@ -1212,6 +1212,12 @@ static void layout(apx_problem* P) {
     ws_take<double>(P, "hmc_c0", P->n_sub);
     ws_take<double>(P, "hmc_c1", P->n_sub);
     ws_take<double>(P, "hmc_h0", P->n_sub);
+    // NUTS: per tree level an outer end, an inner end (theta, r, grad each) and a proposal;
+    // the two trajectory edges; two velocities; reduction results
+    ws_take<double>(P, "nuts_lvl", (size_t)(APX_NUTS_MAX_DEPTH + 1) * 7 * P->n_par);
+    ws_take<double>(P, "nuts_edge", 6 * (size_t)P->n_par);
+    ws_take<double>(P, "nuts_vel", 2 * (size_t)P->n_par);
+    ws_take<double>(P, "nuts_scal", 4);
     (void)n_cols;
 }
 
@@ -1895,6 +1901,202 @@ apx_status apx_chi2_grad(apx_problem* P, const double* theta, const float* data,
         return fail(P->ctx, APX_E_INVALID, "null pointer");
     APXCHK(grad_core(P, theta, data, weight, grad, chi2, 0));
     HIPCHK(launch_chi2_check(chi2, P->n_sub, P->plan.sticky, P->ctx->stream));
+    return APX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// A point of a NUTS trajectory: theta, whitened momentum, d chi2 / d theta (device vectors).
+struct NPoint { double *t, *r, *g; };
+
+struct Nuts {
+    apx_problem* P;
+    const float *data, *weight;
+    const double *F, *Ft;
+    double step;
+    const double* u;          // this transition's uniforms (host)
+    int k;                    // next uniform
+    double log_slice;
+    int steps, divergent;
+    NPoint outer[APX_NUTS_MAX_DEPTH + 1], inner[APX_NUTS_MAX_DEPTH + 1];
+    double* prop[APX_NUTS_MAX_DEPTH + 1];
+    double *vel_m, *vel_p, *scal, *chi2;
+    long long n;
+
+    double draw() { return u[k++]; }
+
+    apx_status copy(double* dst, const double* src) {
+        if (dst == src || n == 0) return APX_OK;
+        hipError_t e = hipMemcpyAsync(dst, src, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, P->ctx->stream);
+        return e == hipSuccess ? APX_OK : fail(P->ctx, APX_E_HIP, "NUTS copy");
+    }
+    apx_status copy(const NPoint& d, const NPoint& s) {
+        APXCHK(copy(d.t, s.t));
+        APXCHK(copy(d.r, s.r));
+        return copy(d.g, s.g);
+    }
+    apx_status read(double* host, int count) {
+        hipStream_t st = P->ctx->stream;
+        HIPCHK(hipMemcpyAsync(host, scal, count * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return APX_OK;
+    }
+    // one leapfrog step of size v * step from src into dst; returns H at the new point
+    apx_status leap(const NPoint& dst, const NPoint& src, double v, double* H) {
+        const Plan& p = P->plan;
+        hipStream_t st = P->ctx->stream;
+        APXCHK(copy(dst, src));
+        HIPCHK(launch_hmc_matvec(p, F, dst.g, dst.r, -0.25 * v * step, st));
+        HIPCHK(launch_hmc_matvec(p, Ft, dst.r, dst.t, v * step, st));
+        APXCHK(grad_core(P, dst.t, data, weight, dst.g, chi2, 1));
+        HIPCHK(launch_hmc_matvec(p, F, dst.g, dst.r, -0.25 * v * step, st));
+        HIPCHK(launch_nuts_energy(p, chi2, dst.r, scal, st));
+        APXCHK(read(H, 1));
+        ++steps;
+        return APX_OK;
+    }
+    // (tp - tm) . F rm >= 0 and (tp - tm) . F rp >= 0
+    apx_status no_uturn(const NPoint& m, const NPoint& pp, bool* ok) {
+        const Plan& p = P->plan;
+        hipStream_t st = P->ctx->stream;
+        HIPCHK(launch_fill(vel_m, n, 0.0, st));
+        HIPCHK(launch_fill(vel_p, n, 0.0, st));
+        HIPCHK(launch_hmc_matvec(p, Ft, m.r, vel_m, 1.0, st));
+        HIPCHK(launch_hmc_matvec(p, Ft, pp.r, vel_p, 1.0, st));
+        HIPCHK(launch_nuts_uturn(p, m.t, pp.t, vel_m, vel_p, scal, st));
+        double d[2];
+        APXCHK(read(d, 2));
+        *ok = d[0] >= 0.0 && d[1] >= 0.0;
+        return APX_OK;
+    }
+    // Subtree of 2^j steps in direction v from src: its outer end, inner end and proposal
+    // (refs into level buffers), its count of slice points and its continue flag.
+    apx_status build(const NPoint& src, double v, int j, NPoint* o, NPoint* in, double** pr, int* nn, int* ss) {
+        if (j == 0) {
+            double H;
+            APXCHK(leap(outer[0], src, v, &H));
+            *nn = log_slice <= -H ? 1 : 0;
+            *ss = log_slice < -H + APX_NUTS_DELTA_MAX ? 1 : 0;
+            if (!*ss) divergent = 1;
+            *o = outer[0];
+            *in = outer[0];
+            *pr = outer[0].t;
+            return APX_OK;
+        }
+        NPoint o1, i1;
+        double* p1;
+        int n1, s1;
+        APXCHK(build(src, v, j - 1, &o1, &i1, &p1, &n1, &s1));
+        APXCHK(copy(inner[j], i1));
+        APXCHK(copy(outer[j], o1));
+        APXCHK(copy(prop[j], p1));
+        if (s1) {
+            NPoint o2, i2;
+            double* p2;
+            int n2, s2;
+            APXCHK(build(outer[j], v, j - 1, &o2, &i2, &p2, &n2, &s2));
+            if (draw() * (n1 + n2) < n2) APXCHK(copy(prop[j], p2));
+            APXCHK(copy(outer[j], o2));
+            bool ok;
+            APXCHK(v < 0 ? no_uturn(outer[j], inner[j], &ok) : no_uturn(inner[j], outer[j], &ok));
+            s1 = s2 && ok ? 1 : 0;
+            n1 += n2;
+        }
+        *o = outer[j];
+        *in = inner[j];
+        *pr = prop[j];
+        *nn = n1;
+        *ss = s1;
+        return APX_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+apx_status apx_nuts_run(apx_problem* P, const float* data, const float* weight, double* theta, const double* F,
+                        double step, int32_t max_depth, int32_t n_samples, const double* z, const double* u,
+                        double* samples, double* stats) {
+    APXCHK(ready(P));
+    if (!data || !weight || !par_ok(P, theta) || !par_ok(P, F) ||
+        (n_samples > 0 && (!par_ok(P, z) || !u || !par_ok(P, samples) || !stats)))
+        return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (max_depth < 1 || max_depth > APX_NUTS_MAX_DEPTH || n_samples < 0 || !(step > 0.0) || !std::isfinite(step))
+        return fail(P->ctx, APX_E_INVALID, "need 1 <= max_depth <= APX_NUTS_MAX_DEPTH, n_samples >= 0, step > 0");
+    if (n_samples == 0) return APX_OK;
+    const Plan& p = P->plan;
+    hipStream_t st = P->ctx->stream;
+    const long long n = P->n_par;
+    const long long nd = 1 + max_depth + (1LL << (max_depth + 1));
+    std::vector<double> uh((size_t)(nd * n_samples));
+    HIPCHK(hipMemcpyAsync(uh.data(), u, uh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    Nuts N{};
+    N.P = P;
+    N.data = data;
+    N.weight = weight;
+    N.F = F;
+    N.Ft = p.M;                                   // F^T (the Cholesky scratch is free here)
+    N.step = step;
+    N.n = n;
+    double* lvl = wsp<double>(P, "nuts_lvl");
+    for (int j = 0; j <= APX_NUTS_MAX_DEPTH; ++j) {
+        double* b = lvl + (long long)j * 7 * n;
+        N.outer[j] = NPoint{b, b + n, b + 2 * n};
+        N.inner[j] = NPoint{b + 3 * n, b + 4 * n, b + 5 * n};
+        N.prop[j] = b + 6 * n;
+    }
+    double* ed = wsp<double>(P, "nuts_edge");
+    const NPoint em{ed, ed + n, ed + 2 * n}, ep{ed + 3 * n, ed + 4 * n, ed + 5 * n};
+    N.vel_m = wsp<double>(P, "nuts_vel");
+    N.vel_p = N.vel_m + n;
+    N.scal = wsp<double>(P, "nuts_scal");
+    N.chi2 = wsp<double>(P, "hmc_c1");
+    HIPCHK(launch_hmc_transpose(p, F, p.M, st));
+    HIPCHK(launch_clear_trial_flags(p, st));
+    std::vector<double> sh((size_t)n_samples * 4);
+    for (long long i = 0; i < n_samples; ++i) {
+        N.u = uh.data() + i * nd;
+        N.k = 0;
+        N.steps = 0;
+        N.divergent = 0;
+        // start: theta with momentum z_i and its gradient (an out-of-domain first start
+        // raises the sticky flag)
+        APXCHK(N.copy(em.t, theta));
+        APXCHK(N.copy(em.r, z + i * n));
+        APXCHK(grad_core(P, em.t, data, weight, em.g, N.chi2, i == 0 ? 0 : 1));
+        HIPCHK(launch_nuts_energy(p, N.chi2, em.r, N.scal, st));
+        double H0;
+        APXCHK(N.read(&H0, 1));
+        APXCHK(N.copy(ep, em));
+        N.log_slice = std::log(N.draw()) - H0;
+        long long cnt = 1;
+        int s = 1, depth = 0;
+        while (s && depth < max_depth) {
+            const double v = N.draw() < 0.5 ? -1.0 : 1.0;
+            NPoint o, in;
+            double* pr;
+            int n1, s1;
+            APXCHK(N.build(v < 0 ? em : ep, v, depth, &o, &in, &pr, &n1, &s1));
+            APXCHK(N.copy(v < 0 ? em : ep, o));
+            if (s1 && N.draw() * (double)cnt < (double)n1) APXCHK(N.copy(theta, pr));
+            cnt += n1;
+            bool ok = false;
+            if (s1) APXCHK(N.no_uturn(em, ep, &ok));
+            s = s1 && ok ? 1 : 0;
+            ++depth;
+        }
+        APXCHK(N.copy(samples + i * n, theta));
+        sh[i * 4 + 0] = depth;
+        sh[i * 4 + 1] = N.steps;
+        sh[i * 4 + 2] = (double)cnt;
+        sh[i * 4 + 3] = N.divergent;
+    }
+    HIPCHK(hipMemcpyAsync(stats, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
     return APX_OK;
 }
 

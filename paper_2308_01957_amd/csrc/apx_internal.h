@@ -347,5 +347,11 @@ hipError_t launch_hmc_matvec(const Plan& p, const double* M, const double* v, do
                              hipStream_t st);
 hipError_t launch_hmc_begin(const Plan& p, const HmcIO& h, long long i, hipStream_t st);
 hipError_t launch_hmc_accept(const Plan& p, const HmcIO& h, long long i, hipStream_t st);
+hipError_t launch_clear_trial_flags(const Plan& p, hipStream_t st);
+// NUTS: out[0] = joint energy (+inf if a point left the domain; clears the flags)
+hipError_t launch_nuts_energy(const Plan& p, const double* chi2, const double* r, double* out, hipStream_t st);
+// NUTS: out[0..1] = (tp - tm) . vm, (tp - tm) . vp
+hipError_t launch_nuts_uturn(const Plan& p, const double* tm, const double* tp, const double* vm,
+                             const double* vp, double* out, hipStream_t st);
 
 }  // namespace apx

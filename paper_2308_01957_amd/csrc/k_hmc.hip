@@ -5,6 +5,8 @@
 //     r <- r - (eps/2) F^T grad U,   theta <- theta + eps F r,   r <- r - (eps/2) F^T grad U.
 // The gradient passes are the library's adjoint; these kernels are the small per-sub-problem
 // vector steps around them.  Each sub-problem is its own chain with its own Metropolis test.
+// The No-U-Turn sampler (the variant the paper's example runs) reuses the kick and drift;
+// its tree logic runs on the host between the energy and U-turn reductions below.
 // All sums run in a fixed order (bitwise reproducible).
 #include "apx_internal.h"
 
@@ -113,6 +115,79 @@ hipError_t launch_hmc_begin(const Plan& p, const HmcIO& h, long long i, hipStrea
 
 hipError_t launch_hmc_accept(const Plan& p, const HmcIO& h, long long i, hipStream_t st) {
     hipLaunchKernelGGL(k_hmc_accept, dim3(p.n_sub + 1), dim3(64), 0, st, p, h, i);
+    return hipGetLastError();
+}
+
+// NUTS energy of the joint chain: H = sum_s chi2_s / 2 + |r|^2 / 2 over the entries of
+// every sub-problem, +inf when any sub-problem's point left the domain (whose flags it
+// then clears).  One workgroup, fixed-order sums; the result goes to out[0].
+__global__ __launch_bounds__(256) void k_nuts_energy(Plan p, const double* __restrict__ chi2,
+                                                     const double* __restrict__ r, double* out) {
+    __shared__ double red[4];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    double a = 0.0;
+    for (int j = (int)threadIdx.x; j < p.n_par; j += 256)
+        if (p.par_sub[j] >= 0) a = fma(r[j], r[j], a);
+    for (int s = (int)threadIdx.x; s < p.n_sub; s += 256)
+        if (p.lmf[s].trial_bad) atomicOr(&bad, 1);
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double c = 0.0;
+        for (int s = 0; s < p.n_sub; ++s) c += chi2[s];
+        const double h = 0.5 * c + 0.5 * (((red[0] + red[1]) + red[2]) + red[3]);
+        out[0] = bad || !isfinite(h) ? __builtin_inf() : h;
+    }
+    __syncthreads();
+    for (int s = (int)threadIdx.x; s < p.n_sub; s += 256) p.lmf[s].trial_bad = 0;
+}
+
+// U-turn products of a trajectory with ends (tm, rm) and (tp, rp): out[0] = (tp - tm) . vm,
+// out[1] = (tp - tm) . vp, with the velocities vm = F rm, vp = F rp given.
+__global__ __launch_bounds__(256) void k_nuts_uturn(Plan p, const double* __restrict__ tm,
+                                                    const double* __restrict__ tp, const double* __restrict__ vm,
+                                                    const double* __restrict__ vp, double* out) {
+    __shared__ double red[4][2];
+    double a = 0.0, b = 0.0;
+    for (int j = (int)threadIdx.x; j < p.n_par; j += 256) {
+        if (p.par_sub[j] < 0) continue;
+        const double d = tp[j] - tm[j];
+        a = fma(d, vm[j], a);
+        b = fma(d, vp[j], b);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = a;
+        red[threadIdx.x >> 6][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) out[threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                           red[3][threadIdx.x];
+}
+
+__global__ void k_clear_trial_flags(Plan p) {
+    for (int s = (int)threadIdx.x; s < p.n_sub; s += blockDim.x) p.lmf[s].trial_bad = 0;
+}
+
+hipError_t launch_clear_trial_flags(const Plan& p, hipStream_t st) {
+    hipLaunchKernelGGL(k_clear_trial_flags, dim3(1), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_energy(const Plan& p, const double* chi2, const double* r, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_nuts_energy, dim3(1), dim3(256), 0, st, p, chi2, r, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_uturn(const Plan& p, const double* tm, const double* tp, const double* vm,
+                             const double* vp, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_nuts_uturn, dim3(1), dim3(256), 0, st, p, tm, tp, vm, vp, out);
     return hipGetLastError();
 }
 

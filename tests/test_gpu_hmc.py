@@ -160,3 +160,67 @@ def test_hmc_argument_checks(apx):
     for step, L in [(0.0, 3), (-1.0, 3), (float("nan"), 3), (0.1, 0)]:
         with pytest.raises(apx.ApxError):
             P.hmc(th, d, w, F, step, L, z, u)
+
+
+def test_nuts_chain_matches_the_oracle(apx):
+    """NUTS over the joint posterior of six cutouts, 3 transitions of step 0.3 from the
+    truth with the oracle's covariance factor: the same trees (depth, leapfrog steps, slice
+    points, divergences) and the same samples within 1e-4 of each posterior width."""
+    import torch
+    spec = cases.bright_cutouts()
+    P, d, w = _problem(apx, spec)
+    th0 = np.array(spec["theta_true"])
+    n_sub, n_par = len(spec["subs"]), spec["n_par"]
+    Fb = [oracle.covariance_factor(spec, th0, spec["data"], spec["weight"], s) for s in range(n_sub)]
+    Fflat = np.concatenate([f.ravel() for f in Fb])
+    Fd = np.zeros((n_par, n_par))
+    for (p0, n), f in zip(spec["subs"], Fb):
+        Fd[p0:p0 + n, p0:p0 + n] = f
+    depth, n_samples, eps = 6, 3, 0.3
+    rng = np.random.default_rng(4211)
+    z = rng.standard_normal((n_samples, n_par))
+    u = rng.uniform(size=(n_samples, oracle.nuts_draws_per_sample(depth)))
+    so, sto = oracle.nuts_chain(spec, th0, spec["data"], spec["weight"], Fd, eps, depth, z, u)
+    th = torch.tensor(th0, dtype=torch.float64, device=P.device)
+    sg, stg = P.nuts(th, d, w, Fflat, eps, depth, z, u)
+    P.check()
+    sg, stg = sg.cpu().numpy(), stg.cpu().numpy()
+    print("trees", stg.tolist(), flush=True)
+    assert np.array_equal(stg, sto), (stg, sto)
+    width = np.sqrt(np.diag(Fd @ Fd.T))
+    assert np.all(np.abs(sg - so) <= 1e-4 * width[None, :]), float(np.max(np.abs(sg - so) / width[None, :]))
+    assert np.array_equal(th.cpu().numpy(), sg[-1])
+
+
+def test_nuts_sky_only_chain_has_the_closed_form_posterior(apx):
+    """1500 NUTS transitions on the quadratic sky posterior N(s*, 1 / sum w): mean and
+    variance within 4 standard errors, no divergences."""
+    import torch
+    spec, s_star, sigma = _sky_only()
+    P, d, w = _problem(apx, spec)
+    F, _ = P.covariance_factor(np.array([s_star]), d, w)
+    n, depth = 1500, 6
+    rng = np.random.default_rng(99)
+    th = torch.tensor([s_star + 2 * sigma], dtype=torch.float64, device=P.device)
+    samples, stats = P.nuts(th, d, w, F, 0.5, depth, rng.standard_normal((n, 1)),
+                            rng.uniform(size=(n, oracle.nuts_draws_per_sample(depth))))
+    P.check()
+    x = samples.cpu().numpy()[50:, 0]
+    st = stats.cpu().numpy()
+    assert np.all(st[:, 3] == 0) and np.all(st[:, 0] >= 1)
+    m, v = x.mean(), x.var()
+    assert abs(m - s_star) < 4 * sigma / math.sqrt(x.size), (m, s_star, sigma)
+    assert abs(v / sigma ** 2 - 1.0) < 4 * math.sqrt(2.0 / x.size), v / sigma ** 2
+
+
+def test_nuts_argument_checks(apx):
+    import torch
+    spec = cases.bright_cutouts()
+    P, d, w = _problem(apx, spec)
+    th = torch.tensor(spec["theta_true"], dtype=torch.float64, device=P.device)
+    F = np.zeros(int(P.a_offsets[-1]))
+    z = np.zeros((1, spec["n_par"]))
+    for step, depth in [(0.0, 3), (0.1, 0), (0.1, 11)]:
+        u = np.full((1, 1 + depth + (1 << (depth + 1))), 0.5)
+        with pytest.raises(apx.ApxError):
+            P.nuts(th, d, w, F, step, depth, z, u)
