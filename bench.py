@@ -312,8 +312,8 @@ def run_adaptive(args, torch, apx, synth):
 def run_hmc(args, torch, apx, synth):
     """The Bayesian mock of the paper's sampling example: one Sersic galaxy, one star and the
     sky under a live Moffat PSF (11 free parameters), fitted by LM, then sampled with the LM
-    covariance as the inverse mass matrix: NUTS (20 untimed warm-up transitions, then
-    `steps` x 25 timed, as the paper's 20 + 250 at the default 10 steps) and plain HMC
+    covariance as the inverse mass matrix: NUTS (20 warm-up transitions adapting the step,
+    then `steps` x 25 timed, as the paper's 20 + 250 at the default 10 steps) and plain HMC
     (10 leapfrog steps per transition)."""
     spec = synth.live_psf(seed_id=9, H=128, W=128, n_star=1, n_sersic=1, P=25, logf_range=(2.0, 2.5),
                           logie_range=(0.0, 0.5))
@@ -326,13 +326,15 @@ def run_hmc(args, torch, apx, synth):
     rng = np.random.default_rng(20230801)
     n_warm, n_samp, n_par = 20, 25 * args.steps, spec["n_par"]
     z = torch.tensor(rng.standard_normal((n_warm + n_samp, n_par)), device=prob.device)
-    # NUTS
-    depth, eps_nuts = 8, 0.5
+    # NUTS: 20 warm-up transitions select the step (dual averaging to acceptance 0.8)
+    depth = 8
     nd = 1 + depth + (1 << (depth + 1))
     un = torch.tensor(rng.uniform(size=(n_warm + n_samp, nd)), device=prob.device)
     thn = th.clone()
-    prob.nuts(thn, dd, ww, F, eps_nuts, depth, z[:n_warm], un[:n_warm])
+    t0 = time.perf_counter()
+    eps_nuts = prob.nuts_warmup(thn, dd, ww, F, 1.0, depth, 0.8, z[:n_warm], un[:n_warm])
     torch.cuda.synchronize()
+    dt_warm = time.perf_counter() - t0
     t0 = time.perf_counter()
     _, nst = prob.nuts(thn, dd, ww, F, eps_nuts, depth, z[n_warm:], un[n_warm:])
     torch.cuda.synchronize()
@@ -355,13 +357,15 @@ def run_hmc(args, torch, apx, synth):
     _line({
         "metric": "NUTS transitions/s (LM covariance mass matrix) on the Bayesian mock",
         "workload": "hmc", "value": n_samp / dt_nuts, "unit": "NUTS samples/s", "ms_per_step": dt_nuts * 1e3 / n_samp,
-        "n_gpus": 1, "steps": n_samp, "nuts_mean_depth": float(nst[:, 0].mean()),
+        "n_gpus": 1, "steps": n_samp, "nuts_step": eps_nuts, "nuts_warmup_s": dt_warm,
+        "nuts_mean_depth": float(nst[:, 0].mean()),
         "nuts_leapfrog_per_sample": float(nst[:, 1].mean()), "nuts_divergent": int(nst[:, 3].sum()),
         "hmc_samples_per_s": n_samp / dt, "hmc_gradient_passes_per_s": n_samp * n_leap / dt, "hmc_accept_rate": acc,
         "hmc_kernel_ms_per_sample": {k: round(v[0] / n_samp, 4) for k, v in kt.items()},
         "paper_context": "NUTS, 20 warm-up + 250 samples of a 13-parameter mock in 738.5 s, hardware unstated",
         "config": {"workload": "128x128, 1 Sersic + 1 star + sky, live Moffat PSF 25x25 (n, R_d fitted), "
-                               "11 params; NUTS step 0.5, depth <= 8; HMC step 0.3, 10 leapfrog steps",
+                               "11 params; NUTS 20 warm-up (dual averaging, target 0.8) + 25 x steps, depth <= 8; "
+                               "HMC step 0.3, 10 leapfrog steps",
                    "n_par": spec["n_par"], "n_pix": prob.n_pix},
         "dtype": "f64 objective / f32 adjoint gradient", "data": "synthetic"})
     return 0

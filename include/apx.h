@@ -380,6 +380,21 @@ apx_status apx_nuts_run(apx_problem* p, const float* data, const float* weight, 
                         const double* F, double step, int32_t max_depth, int32_t n_samples,
                         const double* z, const double* u, double* samples, double* stats);
 
+/* Step-size warm-up of NUTS (§3.5: warm-up samples select the step before sampling):
+ * n_warmup transitions of apx_nuts_run (same z, u layout; theta advances) while dual
+ * averaging (Hoffman & Gelman) adapts the step on the acceptance statistic a_m = mean over
+ * the leaves of transition m's last doubling of min(1, exp(H0 - H)): with mu = log(10 step0),
+ * Hbar_m = (1 - 1/(m + t0)) Hbar_{m-1} + (target - a_m) / (m + t0), log step_m = mu -
+ * sqrt(m) / gamma Hbar_m, log stepbar_m = m^-kappa log step_m + (1 - m^-kappa) log
+ * stepbar_{m-1} (gamma, t0, kappa below).  step: HOST pointer, in: the first step, out:
+ * stepbar after the last transition.  target_accept in (0, 1).  Synchronous. */
+#define APX_NUTS_DA_GAMMA 0.05
+#define APX_NUTS_DA_T0    10.0
+#define APX_NUTS_DA_KAPPA 0.75
+apx_status apx_nuts_warmup(apx_problem* p, const float* data, const float* weight, double* theta,
+                           const double* F, double* step, int32_t max_depth, int32_t n_warmup,
+                           double target_accept, const double* z, const double* u);
+
 /* Vector-Jacobian product of the render (the reverse pass of the model of §2.3, the
  * same adjoint as apx_chi2_grad with the caller's seed in place of -2 w r):
  * grad_theta[k] = sum_i grad_model[i] * d model_i / d theta_k, i over every output pixel

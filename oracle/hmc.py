@@ -138,7 +138,9 @@ def nuts_transition(theta0, r0, F, U, grad_U, step, max_depth, u):
     (theta+ - theta-) . F r- < 0 or (theta+ - theta-) . F r+ < 0.  The proposal of a subtree
     is replaced by that of its second half with probability n'' / (n' + n''); that of the
     chain by a new doubling's with probability min(1, n' / n).  Returns (theta, stats) with
-    stats = (depth, leapfrog steps, points in the slice, divergent)."""
+    stats = (depth, leapfrog steps, points in the slice, divergent, alpha, n_alpha), where
+    alpha sums min(1, exp(H0 - H)) over the leaves of the last doubling and n_alpha counts
+    them (the acceptance statistic of the step-size warm-up)."""
     d = _Draws(u)
     theta0 = np.asarray(theta0, dtype=np.float64)
     r0 = np.asarray(r0, dtype=np.float64)
@@ -149,7 +151,7 @@ def nuts_transition(theta0, r0, F, U, grad_U, step, max_depth, u):
 
     H0 = H(theta0, r0)
     log_slice = math.log(d.next()) - H0
-    counters = {"steps": 0, "divergent": 0}
+    counters = {"steps": 0, "divergent": 0, "alpha": 0.0, "n_alpha": 0}
 
     def step1(t, r, g, v):
         r = r - 0.5 * v * step * (F.T @ g)
@@ -168,6 +170,8 @@ def nuts_transition(theta0, r0, F, U, grad_U, step, max_depth, u):
         if j == 0:
             t1, r1, g1 = step1(t, r, g, v)
             h = H(t1, r1)
+            counters["alpha"] += min(1.0, math.exp(H0 - h)) if math.isfinite(h) else 0.0
+            counters["n_alpha"] += 1
             n = 1 if log_slice <= -h else 0
             s = 1 if log_slice < -h + NUTS_DELTA_MAX else 0
             if not s:
@@ -193,6 +197,7 @@ def nuts_transition(theta0, r0, F, U, grad_U, step, max_depth, u):
     n, s, depth = 1, 1, 0
     while s and depth < max_depth:
         v = -1.0 if d.next() < 0.5 else 1.0
+        counters["alpha"], counters["n_alpha"] = 0.0, 0
         if v < 0:
             tm, rm, gm, _, _, _, prop, n1, s1 = build(tm, rm, gm, v, depth)
         else:
@@ -202,17 +207,13 @@ def nuts_transition(theta0, r0, F, U, grad_U, step, max_depth, u):
         n += n1
         s = s1 if no_uturn(tm, rm, tp, rp) else 0
         depth += 1
-    return theta, (depth, counters["steps"], n, counters["divergent"])
+    return theta, (depth, counters["steps"], n, counters["divergent"], counters["alpha"], counters["n_alpha"])
 
 
-def nuts_chain(spec, theta0, data, weight, F, step: float, max_depth: int, z, u):
-    """NUTS on the joint posterior of every sub-problem (one chain; U = sum chi^2 / 2) with
-    the inverse-mass factor F (n_par x n_par, block diagonal per sub-problem).  z:
-    [n_samples, n_par] standard normals (the momenta), u: [n_samples,
-    nuts_draws_per_sample(max_depth)] uniforms.  Returns (samples, stats [n_samples, 4])."""
+def _joint_energy(spec, data, weight):
+    """U(theta) = sum of the sub-problems' chi^2 / 2 (+inf outside the domain) and its
+    gradient -J^T W r per sub-problem (NaN outside the domain)."""
     from .core import chi2 as chi2_all
-
-    theta = np.array(theta0, dtype=np.float64)
     subs = spec["subs"]
 
     def U(t):
@@ -228,7 +229,24 @@ def nuts_chain(spec, theta0, data, weight, F, step: float, max_depth: int, z, u)
             _, gs, _ = jtwj(spec, t, data, weight, s)
             g[p0:p0 + npar] = -gs
         return g
+    return U, grad_U
 
+
+def nuts_warmup(spec, theta0, data, weight, F, step0: float, max_depth: int, target: float, z, u):
+    """The step-size warm-up of the paper's NUTS run (§3.5: warm-up samples select the step)
+    on the joint chi^2 posterior: returns (theta, adapted step, steps used)."""
+    U, grad_U = _joint_energy(spec, data, weight)
+    return nuts_warmup_core(theta0, F, U, grad_U, step0, max_depth, target,
+                            np.asarray(z, dtype=np.float64), np.asarray(u, dtype=np.float64))
+
+
+def nuts_chain(spec, theta0, data, weight, F, step: float, max_depth: int, z, u):
+    """NUTS on the joint posterior of every sub-problem (one chain; U = sum chi^2 / 2) with
+    the inverse-mass factor F (n_par x n_par, block diagonal per sub-problem).  z:
+    [n_samples, n_par] standard normals (the momenta), u: [n_samples,
+    nuts_draws_per_sample(max_depth)] uniforms.  Returns (samples, stats [n_samples, 4])."""
+    theta = np.array(theta0, dtype=np.float64)
+    U, grad_U = _joint_energy(spec, data, weight)
     z = np.asarray(z, dtype=np.float64)
     u = np.asarray(u, dtype=np.float64)
     samples = np.zeros((z.shape[0], theta.size))
@@ -236,5 +254,44 @@ def nuts_chain(spec, theta0, data, weight, F, step: float, max_depth: int, z, u)
     for i in range(z.shape[0]):
         theta, st = nuts_transition(theta, z[i], F, U, grad_U, step, max_depth, u[i])
         samples[i] = theta
-        stats[i] = st
+        stats[i] = st[:4]
     return samples, stats
+
+
+# dual-averaging constants of the step-size warm-up (Hoffman & Gelman's defaults)
+DA_GAMMA, DA_T0, DA_KAPPA = 0.05, 10.0, 0.75
+
+
+def dual_averaging(step0: float, target: float):
+    """Step sizes of the warm-up by dual averaging: with mu = log(10 step0), after warm-up
+    transition m (m = 1, 2, ...) with acceptance statistic a_m = alpha / n_alpha,
+    Hbar_m = (1 - 1/(m + t0)) Hbar_{m-1} + (target - a_m) / (m + t0),
+    log step_m = mu - sqrt(m) / gamma Hbar_m,
+    log stepbar_m = m^-kappa log step_m + (1 - m^-kappa) log stepbar_{m-1}.
+    Yields (step_m, stepbar_m) as the statistics arrive (a generator fed by `send`)."""
+    mu = math.log(10.0 * step0)
+    hbar, log_bar, m = 0.0, 0.0, 0
+    a = yield step0, step0
+    while True:
+        m += 1
+        hbar = (1.0 - 1.0 / (m + DA_T0)) * hbar + (target - a) / (m + DA_T0)
+        log_step = mu - math.sqrt(m) / DA_GAMMA * hbar
+        w = m ** (-DA_KAPPA)
+        log_bar = w * log_step + (1.0 - w) * log_bar
+        a = yield math.exp(log_step), math.exp(log_bar)
+
+
+def nuts_warmup_core(theta0, F, U, grad_U, step0, max_depth, target, z, u):
+    """len(z) warm-up transitions adapting the step (dual averaging on the acceptance
+    statistic of each transition's last doubling); returns (theta, the final averaged
+    step, the steps used)."""
+    gen = dual_averaging(step0, target)
+    step, bar = next(gen)
+    theta = np.asarray(theta0, dtype=np.float64)
+    used = []
+    for i in range(len(z)):
+        used.append(step)
+        theta, st = nuts_transition(theta, z[i], F, U, grad_U, step, max_depth, u[i])
+        a = st[4] / st[5] if st[5] > 0 else 0.0
+        step, bar = gen.send(a)
+    return theta, bar, used

@@ -31,7 +31,7 @@ EXPORTS = [
     "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_render_vjp", "apx_lm_init",
     "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
     "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_problem_tile_shapes", "apx_covariance",
-    "apx_covariance_factor", "apx_hmc_run", "apx_nuts_run",
+    "apx_covariance_factor", "apx_hmc_run", "apx_nuts_run", "apx_nuts_warmup",
 ]
 TILES_AUTOTUNE, TILES_MODEL, TILES_FIXED = 0, 1, 2
 TILE_SHAPES = [(32, 64), (16, 64), (32, 32), (16, 32)]       # output rows x cols per workgroup
@@ -141,6 +141,8 @@ def load_library(path: str = LIB_PATH):
         "apx_covariance_factor": ([vp, vp, vp, vp, vp, vp], i32),
         "apx_hmc_run": ([vp, vp, vp, vp, vp, ctypes.c_double, i32, i32, vp, vp, vp, vp], i32),
         "apx_nuts_run": ([vp, vp, vp, vp, vp, ctypes.c_double, i32, i32, vp, vp, vp, vp], i32),
+        "apx_nuts_warmup": ([vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), i32, i32, ctypes.c_double,
+                             vp, vp], i32),
         "apx_lm_init": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_step": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_run": ([vp, i32, vp, vp, vp, vp, i32], i32),
@@ -416,6 +418,26 @@ class Problem:
                                               z.data_ptr(), u.data_ptr(), samples.data_ptr(), stats.data_ptr()))
         self._leave()
         return samples, stats
+
+    def nuts_warmup(self, theta, data, weight, F, step0: float, max_depth: int, target: float, z, u) -> float:
+        """len(z) NUTS warm-up transitions from theta (advanced in place) adapting the step by
+        dual averaging toward the target acceptance; returns the adapted step."""
+        t = self.torch
+        z = self._dev(z, t.float64)
+        u = self._dev(u, t.float64)
+        F = self._dev(F, t.float64)
+        nd = 1 + int(max_depth) + (1 << (int(max_depth) + 1))
+        n = int(u.numel() // nd)
+        if u.numel() != n * nd or z.numel() != n * self.n_par:
+            raise ValueError("z must hold n x n_par and u n x (1 + d + 2^(d+1)) entries")
+        step = ctypes.c_double(float(step0))
+        self._enter(theta, data, weight, F, z, u)
+        with t.cuda.stream(self.stream):
+            self._check(self.lib.apx_nuts_warmup(self._prob, data.data_ptr(), weight.data_ptr(), theta.data_ptr(),
+                                                 F.data_ptr(), ctypes.byref(step), int(max_depth), n,
+                                                 float(target), z.data_ptr(), u.data_ptr()))
+        self._leave()
+        return float(step.value)
 
     def render_vjp(self, theta, grad_model, out=None):
         """sum_i grad_model[i] d model_i / d theta (FP64 [n_par]) by the adjoint pass."""

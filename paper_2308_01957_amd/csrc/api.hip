@@ -1918,8 +1918,10 @@ struct Nuts {
     double step;
     const double* u;          // this transition's uniforms (host)
     int k;                    // next uniform
-    double log_slice;
+    double log_slice, H0;
     int steps, divergent;
+    double alpha;             // sum of min(1, exp(H0 - H)) over the leaves of the last doubling
+    int n_alpha;
     NPoint outer[APX_NUTS_MAX_DEPTH + 1], inner[APX_NUTS_MAX_DEPTH + 1];
     double* prop[APX_NUTS_MAX_DEPTH + 1];
     double *vel_m, *vel_p, *scal, *chi2;
@@ -1977,6 +1979,8 @@ struct Nuts {
         if (j == 0) {
             double H;
             APXCHK(leap(outer[0], src, v, &H));
+            alpha += std::isfinite(H) ? std::min(1.0, std::exp(H0 - H)) : 0.0;
+            ++n_alpha;
             *nn = log_slice <= -H ? 1 : 0;
             *ss = log_slice < -H + APX_NUTS_DELTA_MAX ? 1 : 0;
             if (!*ss) divergent = 1;
@@ -2015,31 +2019,18 @@ struct Nuts {
 
 }  // namespace
 
-extern "C" {
-
-apx_status apx_nuts_run(apx_problem* P, const float* data, const float* weight, double* theta, const double* F,
-                        double step, int32_t max_depth, int32_t n_samples, const double* z, const double* u,
-                        double* samples, double* stats) {
-    APXCHK(ready(P));
-    if (!data || !weight || !par_ok(P, theta) || !par_ok(P, F) ||
-        (n_samples > 0 && (!par_ok(P, z) || !u || !par_ok(P, samples) || !stats)))
-        return fail(P->ctx, APX_E_INVALID, "null pointer");
-    if (max_depth < 1 || max_depth > APX_NUTS_MAX_DEPTH || n_samples < 0 || !(step > 0.0) || !std::isfinite(step))
-        return fail(P->ctx, APX_E_INVALID, "need 1 <= max_depth <= APX_NUTS_MAX_DEPTH, n_samples >= 0, step > 0");
-    if (n_samples == 0) return APX_OK;
+// Workspace views of the NUTS state; F^T goes to the LM's Cholesky scratch.
+static apx_status nuts_setup(apx_problem* P, Nuts& N, const float* data, const float* weight, const double* F,
+                             double step, NPoint& em, NPoint& ep) {
     const Plan& p = P->plan;
     hipStream_t st = P->ctx->stream;
     const long long n = P->n_par;
-    const long long nd = 1 + max_depth + (1LL << (max_depth + 1));
-    std::vector<double> uh((size_t)(nd * n_samples));
-    HIPCHK(hipMemcpyAsync(uh.data(), u, uh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    Nuts N{};
+    N = Nuts{};
     N.P = P;
     N.data = data;
     N.weight = weight;
     N.F = F;
-    N.Ft = p.M;                                   // F^T (the Cholesky scratch is free here)
+    N.Ft = p.M;
     N.step = step;
     N.n = n;
     double* lvl = wsp<double>(P, "nuts_lvl");
@@ -2050,53 +2041,140 @@ apx_status apx_nuts_run(apx_problem* P, const float* data, const float* weight, 
         N.prop[j] = b + 6 * n;
     }
     double* ed = wsp<double>(P, "nuts_edge");
-    const NPoint em{ed, ed + n, ed + 2 * n}, ep{ed + 3 * n, ed + 4 * n, ed + 5 * n};
+    em = NPoint{ed, ed + n, ed + 2 * n};
+    ep = NPoint{ed + 3 * n, ed + 4 * n, ed + 5 * n};
     N.vel_m = wsp<double>(P, "nuts_vel");
     N.vel_p = N.vel_m + n;
     N.scal = wsp<double>(P, "nuts_scal");
     N.chi2 = wsp<double>(P, "hmc_c1");
     HIPCHK(launch_hmc_transpose(p, F, p.M, st));
     HIPCHK(launch_clear_trial_flags(p, st));
+    return APX_OK;
+}
+
+// One transition from theta (updated in place to the new sample) with momentum z and the
+// host uniforms u; first: the start's domain violations raise the sticky flag.
+// st = (depth, leapfrog steps, slice points, divergent, alpha, n_alpha).
+static apx_status nuts_transition(Nuts& N, const NPoint& em, const NPoint& ep, double* theta, const double* z,
+                                  const double* u, int max_depth, bool first, double st[6]) {
+    apx_problem* P = N.P;
+    const Plan& p = P->plan;
+    N.u = u;
+    N.k = 0;
+    N.steps = 0;
+    N.divergent = 0;
+    N.alpha = 0.0;
+    N.n_alpha = 0;
+    APXCHK(N.copy(em.t, theta));
+    APXCHK(N.copy(em.r, z));
+    APXCHK(grad_core(P, em.t, N.data, N.weight, em.g, N.chi2, first ? 0 : 1));
+    HIPCHK(launch_nuts_energy(p, N.chi2, em.r, N.scal, P->ctx->stream));
+    APXCHK(N.read(&N.H0, 1));
+    APXCHK(N.copy(ep, em));
+    N.log_slice = std::log(N.draw()) - N.H0;
+    long long cnt = 1;
+    int s = 1, depth = 0;
+    while (s && depth < max_depth) {
+        const double v = N.draw() < 0.5 ? -1.0 : 1.0;
+        N.alpha = 0.0;
+        N.n_alpha = 0;
+        NPoint o, in;
+        double* pr;
+        int n1, s1;
+        APXCHK(N.build(v < 0 ? em : ep, v, depth, &o, &in, &pr, &n1, &s1));
+        APXCHK(N.copy(v < 0 ? em : ep, o));
+        if (s1 && N.draw() * (double)cnt < (double)n1) APXCHK(N.copy(theta, pr));
+        cnt += n1;
+        bool ok = false;
+        if (s1) APXCHK(N.no_uturn(em, ep, &ok));
+        s = s1 && ok ? 1 : 0;
+        ++depth;
+    }
+    st[0] = depth;
+    st[1] = N.steps;
+    st[2] = (double)cnt;
+    st[3] = N.divergent;
+    st[4] = N.alpha;
+    st[5] = N.n_alpha;
+    return APX_OK;
+}
+
+static apx_status nuts_args(apx_problem* P, const float* data, const float* weight, const double* theta,
+                            const double* F, double step, int32_t max_depth, int32_t n, const double* z,
+                            const double* u) {
+    APXCHK(ready(P));
+    if (!data || !weight || !par_ok(P, theta) || !par_ok(P, F) || (n > 0 && (!par_ok(P, z) || !u)))
+        return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (max_depth < 1 || max_depth > APX_NUTS_MAX_DEPTH || n < 0 || !(step > 0.0) || !std::isfinite(step))
+        return fail(P->ctx, APX_E_INVALID, "need 1 <= max_depth <= APX_NUTS_MAX_DEPTH, n >= 0, step > 0");
+    return APX_OK;
+}
+
+static apx_status host_uniforms(apx_problem* P, const double* u, long long count, std::vector<double>& uh) {
+    uh.resize((size_t)count);
+    HIPCHK(hipMemcpyAsync(uh.data(), u, uh.size() * sizeof(double), hipMemcpyDeviceToHost, P->ctx->stream));
+    HIPCHK(hipStreamSynchronize(P->ctx->stream));
+    return APX_OK;
+}
+
+extern "C" {
+
+apx_status apx_nuts_run(apx_problem* P, const float* data, const float* weight, double* theta, const double* F,
+                        double step, int32_t max_depth, int32_t n_samples, const double* z, const double* u,
+                        double* samples, double* stats) {
+    APXCHK(nuts_args(P, data, weight, theta, F, step, max_depth, n_samples, z, u));
+    if (n_samples > 0 && (!par_ok(P, samples) || !stats)) return fail(P->ctx, APX_E_INVALID, "null pointer");
+    if (n_samples == 0) return APX_OK;
+    hipStream_t st = P->ctx->stream;
+    const long long n = P->n_par;
+    const long long nd = 1 + max_depth + (1LL << (max_depth + 1));
+    std::vector<double> uh;
+    APXCHK(host_uniforms(P, u, nd * n_samples, uh));
+    Nuts N;
+    NPoint em, ep;
+    APXCHK(nuts_setup(P, N, data, weight, F, step, em, ep));
     std::vector<double> sh((size_t)n_samples * 4);
     for (long long i = 0; i < n_samples; ++i) {
-        N.u = uh.data() + i * nd;
-        N.k = 0;
-        N.steps = 0;
-        N.divergent = 0;
-        // start: theta with momentum z_i and its gradient (an out-of-domain first start
-        // raises the sticky flag)
-        APXCHK(N.copy(em.t, theta));
-        APXCHK(N.copy(em.r, z + i * n));
-        APXCHK(grad_core(P, em.t, data, weight, em.g, N.chi2, i == 0 ? 0 : 1));
-        HIPCHK(launch_nuts_energy(p, N.chi2, em.r, N.scal, st));
-        double H0;
-        APXCHK(N.read(&H0, 1));
-        APXCHK(N.copy(ep, em));
-        N.log_slice = std::log(N.draw()) - H0;
-        long long cnt = 1;
-        int s = 1, depth = 0;
-        while (s && depth < max_depth) {
-            const double v = N.draw() < 0.5 ? -1.0 : 1.0;
-            NPoint o, in;
-            double* pr;
-            int n1, s1;
-            APXCHK(N.build(v < 0 ? em : ep, v, depth, &o, &in, &pr, &n1, &s1));
-            APXCHK(N.copy(v < 0 ? em : ep, o));
-            if (s1 && N.draw() * (double)cnt < (double)n1) APXCHK(N.copy(theta, pr));
-            cnt += n1;
-            bool ok = false;
-            if (s1) APXCHK(N.no_uturn(em, ep, &ok));
-            s = s1 && ok ? 1 : 0;
-            ++depth;
-        }
+        double t6[6];
+        APXCHK(nuts_transition(N, em, ep, theta, z + i * n, uh.data() + i * nd, max_depth, i == 0, t6));
         APXCHK(N.copy(samples + i * n, theta));
-        sh[i * 4 + 0] = depth;
-        sh[i * 4 + 1] = N.steps;
-        sh[i * 4 + 2] = (double)cnt;
-        sh[i * 4 + 3] = N.divergent;
+        for (int q = 0; q < 4; ++q) sh[i * 4 + q] = t6[q];
     }
     HIPCHK(hipMemcpyAsync(stats, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
+    return APX_OK;
+}
+
+apx_status apx_nuts_warmup(apx_problem* P, const float* data, const float* weight, double* theta, const double* F,
+                           double* step, int32_t max_depth, int32_t n_warmup, double target_accept,
+                           const double* z, const double* u) {
+    if (!step) return fail(P ? P->ctx : nullptr, APX_E_INVALID, "null pointer");
+    APXCHK(nuts_args(P, data, weight, theta, F, *step, max_depth, n_warmup, z, u));
+    if (!(target_accept > 0.0 && target_accept < 1.0))
+        return fail(P->ctx, APX_E_INVALID, "target acceptance must be in (0, 1)");
+    if (n_warmup == 0) return APX_OK;
+    const long long n = P->n_par;
+    const long long nd = 1 + max_depth + (1LL << (max_depth + 1));
+    std::vector<double> uh;
+    APXCHK(host_uniforms(P, u, nd * n_warmup, uh));
+    Nuts N;
+    NPoint em, ep;
+    APXCHK(nuts_setup(P, N, data, weight, F, *step, em, ep));
+    // dual averaging of log step on the acceptance statistic
+    const double mu = std::log(10.0 * *step);
+    double hbar = 0.0, log_bar = 0.0;
+    for (long long i = 0; i < n_warmup; ++i) {
+        double t6[6];
+        APXCHK(nuts_transition(N, em, ep, theta, z + i * n, uh.data() + i * nd, max_depth, i == 0, t6));
+        const double a = t6[5] > 0 ? t6[4] / t6[5] : 0.0;
+        const double m = (double)(i + 1);
+        hbar = (1.0 - 1.0 / (m + APX_NUTS_DA_T0)) * hbar + (target_accept - a) / (m + APX_NUTS_DA_T0);
+        const double log_step = mu - std::sqrt(m) / APX_NUTS_DA_GAMMA * hbar;
+        const double w = std::pow(m, -APX_NUTS_DA_KAPPA);
+        log_bar = w * log_step + (1.0 - w) * log_bar;
+        N.step = std::exp(log_step);
+    }
+    *step = std::exp(log_bar);
     return APX_OK;
 }
 

@@ -224,3 +224,24 @@ def test_nuts_argument_checks(apx):
         u = np.full((1, 1 + depth + (1 << (depth + 1))), 0.5)
         with pytest.raises(apx.ApxError):
             P.nuts(th, d, w, F, step, depth, z, u)
+
+
+def test_nuts_warmup_matches_the_oracle(apx):
+    """30 warm-up transitions on the sky posterior from a step of 2.5 (whitened units):
+    the adapted step and the chain's state agree with the oracle's dual averaging."""
+    import torch
+    spec, s_star, sigma = _sky_only()
+    P, d, w = _problem(apx, spec)
+    Fo = np.array([[sigma]])
+    depth, n = 6, 30
+    rng = np.random.default_rng(101)
+    z = rng.standard_normal((n, 1))
+    u = rng.uniform(size=(n, oracle.nuts_draws_per_sample(depth)))
+    th0 = np.array([s_star + sigma])
+    to, step_o, _ = oracle.nuts_warmup(spec, th0, spec["data"], spec["weight"], Fo, 2.5, depth, 0.8, z, u)
+    th = torch.tensor(th0, dtype=torch.float64, device=P.device)
+    step_g = P.nuts_warmup(th, d, w, Fo.ravel(), 2.5, depth, 0.8, z, u)
+    P.check()
+    print("steps", step_g, step_o, flush=True)
+    assert math.isclose(step_g, step_o, rel_tol=1e-6), (step_g, step_o)
+    assert abs(float(th.cpu()[0]) - float(to[0])) <= 1e-6 * sigma

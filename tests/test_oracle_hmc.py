@@ -202,3 +202,47 @@ def test_planted_inverted_merge_test_fails_the_gaussian_pin(monkeypatch):
     monkeypatch.setattr(oracle.hmc, "_Draws", Stuck)
     with pytest.raises(AssertionError):
         test_nuts_samples_a_correlated_gaussian()
+
+
+def _accept_stat(F, U, G, step, n, seed, max_depth=8):
+    rng = np.random.default_rng(seed)
+    th = np.zeros(F.shape[0])
+    nd = oracle.nuts_draws_per_sample(max_depth)
+    a = []
+    for _ in range(n):
+        th, st = oracle.nuts_transition(th, rng.standard_normal(F.shape[0]), F, U, G, step, max_depth,
+                                        rng.uniform(size=nd))
+        a.append(st[4] / st[5])
+    return float(np.mean(a))
+
+
+@pytest.mark.parametrize("step0", [0.02, 4.0])
+def test_nuts_warmup_reaches_the_target_acceptance(step0):
+    """Dual averaging from a far too small or far too large step: 400 warm-up transitions
+    give a step whose mean acceptance statistic is near the target 0.8 (within 0.1: the
+    averaged step of dual averaging lands close to, not exactly on, the target)."""
+    Sigma, mu, U, G = _gauss2()
+    F = np.linalg.cholesky(Sigma) * 2.0          # a mass matrix off by a factor: the step must adapt
+    rng = np.random.default_rng(17)
+    nd = oracle.nuts_draws_per_sample(8)
+    _, step, used = oracle.nuts_warmup_core(np.zeros(2), F, U, G, step0, 8, 0.8,
+                                            rng.standard_normal((400, 2)), rng.uniform(size=(400, nd)))
+    assert used[0] == step0 and 0.05 < step < 2.0
+    assert abs(_accept_stat(F, U, G, step, 1500, 23) - 0.8) < 0.1
+
+
+def test_planted_sign_error_in_dual_averaging_fails(monkeypatch):
+    def bad(step0, target):
+        mu = math.log(10.0 * step0)
+        hbar, log_bar, m = 0.0, 0.0, 0
+        a = yield step0, step0
+        while True:
+            m += 1
+            hbar = (1.0 - 1.0 / (m + 10.0)) * hbar - (target - a) / (m + 10.0)     # planted sign
+            log_step = mu - math.sqrt(m) / 0.05 * hbar
+            w = m ** -0.75
+            log_bar = w * log_step + (1.0 - w) * log_bar
+            a = yield math.exp(min(log_step, 50.0)), math.exp(min(log_bar, 50.0))
+    monkeypatch.setattr(oracle.hmc, "dual_averaging", bad)
+    with pytest.raises(AssertionError):
+        test_nuts_warmup_reaches_the_target_acceptance(0.02)
