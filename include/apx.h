@@ -285,7 +285,11 @@ apx_status apx_problem_destroy(apx_problem* p);
 #define APX_TIME_CONV_ADJ   9     /* adjoint convolution                        */
 #define APX_TIME_GRAD       10    /* adjoint contraction with recomputed samples */
 #define APX_TIME_CLASSES    11
+/* Kernel timing with HIP events on the context stream (outside graph capture): enabled != 0
+ * records every class; set_timing_classes records only the classes in mask (bit 1 << class),
+ * which keeps the event overhead off the other launches.  Either call resets the records. */
 apx_status apx_problem_set_timing(apx_problem* p, int32_t enabled);
+apx_status apx_problem_set_timing_classes(apx_problem* p, uint32_t mask);
 apx_status apx_problem_timing(apx_problem* p, int32_t klass, double* total_ms, int64_t* launches);
 
 /* ------------------------------------------------------------------ hot path ---- */

@@ -22,7 +22,9 @@ What it computes, with the passage each step follows (section numbers of the pap
   convolution, which gives the same image.
 * Composite model (§2.1, §2.2): the sum of all components on the pre-convolution
   ("extended") grid, then a true 2-D convolution with the PSF stamp (§2.1.3, direct
-  mode), then a flat sky per image.
+  mode), then a flat sky per image.  An image whose PSF has a higher resolution than its
+  pixels (§2.1.3) is sampled and convolved on a grid of U x U sub-pixels per pixel and the
+  result is integrated (summed) onto its pixels (`render_grid`, `bin_pixels`).
 * Likelihood (§2.2, Eq. likelihood and Eq. chi2): chi2 = sum_i w_i (d_i - m_i)^2 with
   w = 1/sigma^2.  The paper's Eq. (chi2) carries a factor 1/2 (it is -log L); this
   oracle reports the conventional sum without it.
@@ -295,8 +297,38 @@ def point_pixels(im, comp, prm, with_grad=False):
     return val
 
 
+def render_grid(im) -> Dict:
+    """The grid an image's model is sampled and convolved on.  An image whose PSF has a
+    higher resolution than its pixels (§2.1.3: sampling and convolution then run at the
+    PSF's resolution and the result is integrated onto the image pixels) carries
+    "up" = U > 1: its render grid has U x U sub-pixels per pixel, fine pixel (yf, xf)
+    centred at pixel coordinates ((xf + 1/2)/U - 1/2, (yf + 1/2)/U - 1/2), so its
+    pixel -> sky map is the image's composed with that scaling (and its pixel area is the
+    image's over U^2); windows of its components and its PSF stamp are in fine pixels."""
+    U = int(im.get("up", 1))
+    if U == 1:
+        return im
+    a = np.asarray(im["affine"], dtype=np.float64)
+    o = (1.0 - U) / (2.0 * U)
+    fine = dict(im)
+    fine["H"], fine["W"] = U * im["H"], U * im["W"]
+    fine["affine"] = np.array([a[0] + (a[1] + a[2]) * o, a[1] / U, a[2] / U,
+                               a[3] + (a[4] + a[5]) * o, a[4] / U, a[5] / U])
+    fine["up"] = 1
+    return fine
+
+
+def bin_pixels(M: np.ndarray, U: int) -> np.ndarray:
+    """Integrate a render-grid image onto the image pixels: each pixel is the sum of its
+    U x U sub-pixels."""
+    if U == 1:
+        return M
+    H, W = M.shape[0] // U, M.shape[1] // U
+    return M.reshape(H, U, W, U).sum(axis=(1, 3))
+
+
 def comp_pixels(spec, comp, theta, with_grad=False):
-    im = spec["images"][comp["image"]]
+    im = render_grid(spec["images"][comp["image"]])
     prm = local_params(comp, theta)
     if comp["type"] == SERSIC:
         return sersic_pixels(im, comp, prm, spec["sampling"], with_grad)
@@ -324,8 +356,9 @@ def clipped(comp: Dict, im) -> Dict | None:
 
 
 def render_ext(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
-    """Sum of all components of image k on its extended grid [-c, H+c) x [-c, W+c)."""
-    im = spec["images"][k]
+    """Sum of all components of image k on the extended render grid [-c, H+c) x [-c, W+c)
+    (fine pixels for an image with a higher-resolution PSF)."""
+    im = render_grid(spec["images"][k])
     c = psf_half(im)
     S = np.zeros((im["H"] + 2 * c, im["W"] + 2 * c))
     for comp in spec["comps"]:
@@ -404,9 +437,11 @@ def psf_of(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
 
 
 def model_image(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
-    """Convolved model of image k plus its flat sky (the sky is not convolved)."""
+    """Convolved model of image k (integrated onto its pixels) plus its flat sky (the sky
+    is not convolved)."""
     im = spec["images"][k]
-    return convolve_valid(render_ext(spec, theta, k), psf_of(spec, theta, k)) + sky_value(im, theta)
+    M = convolve_valid(render_ext(spec, theta, k), psf_of(spec, theta, k))
+    return bin_pixels(M, int(im.get("up", 1))) + sky_value(im, theta)
 
 
 def images_of_sub(spec: Dict, sub: int) -> List[int]:
@@ -434,7 +469,9 @@ def jacobian_image(spec, theta, k, cols: Sequence[int] | None = None) -> np.ndar
     """dm/dtheta on image k, shape (H*W, n_par) (or only the listed columns):
     each column is the PSF convolution of the derivative of the pre-convolution image;
     the sky column is 1; tied parameters sum their contributions."""
-    im = spec["images"][k]
+    im0 = spec["images"][k]
+    U = int(im0.get("up", 1))
+    im = render_grid(im0)
     c = psf_half(im)
     H, W = im["H"], im["W"]
     n_par = spec["n_par"]
@@ -457,11 +494,11 @@ def jacobian_image(spec, theta, k, cols: Sequence[int] | None = None) -> np.ndar
                 dS[p] = np.zeros((H + 2 * c, W + 2 * c))
             dS[p][y0 + c:y1 + c, x0 + c:x1 + c] += g[loc]
     out_cols = list(range(n_par)) if cols is None else list(cols)
-    J = np.zeros((H * W, len(out_cols)))
+    J = np.zeros(((H // U) * (W // U), len(out_cols)))
     K = psf_of(spec, theta, k)
     for ci, p in enumerate(out_cols):
         if p in dS:
-            J[:, ci] = convolve_valid(dS[p], K).ravel()
+            J[:, ci] = bin_pixels(convolve_valid(dS[p], K), U).ravel()
         if im["sky_par"] == p:
             J[:, ci] += 1.0
     # live PSF: m = K(phi) * S + sky, so dm/dphi = (dK/dphi) * S
@@ -472,7 +509,7 @@ def jacobian_image(spec, theta, k, cols: Sequence[int] | None = None) -> np.ndar
         S = render_ext(spec, theta, k)
         for p, dK in zip(pm["par"], (dK_dn, dK_drd)):
             if p >= 0 and p in want:
-                J[:, out_cols.index(p)] += convolve_valid(S, dK).ravel()
+                J[:, out_cols.index(p)] += bin_pixels(convolve_valid(S, dK), U).ravel()
     return J
 
 

@@ -31,7 +31,7 @@ EXPORTS = [
     "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_render_vjp", "apx_lm_init",
     "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
     "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_problem_tile_shapes", "apx_covariance",
-    "apx_covariance_factor", "apx_hmc_run", "apx_nuts_run", "apx_nuts_warmup",
+    "apx_covariance_factor", "apx_hmc_run", "apx_nuts_run", "apx_nuts_warmup", "apx_problem_set_timing_classes",
 ]
 TILES_AUTOTUNE, TILES_MODEL, TILES_FIXED = 0, 1, 2
 TILE_SHAPES = [(32, 64), (16, 64), (32, 32), (16, 32)]       # output rows x cols per workgroup
@@ -147,6 +147,7 @@ def load_library(path: str = LIB_PATH):
         "apx_lm_step": ([vp, vp, vp, vp, vp], i32),
         "apx_lm_run": ([vp, i32, vp, vp, vp, vp, i32], i32),
         "apx_problem_set_timing": ([vp, i32], i32),
+        "apx_problem_set_timing_classes": ([vp, ctypes.c_uint32], i32),
         "apx_problem_timing": ([vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], i32),
         "apx_ctx_set_tiles": ([vp, i32], i32),
         "apx_ctx_tile_cost": ([vp, i32, i32, ctypes.POINTER(ctypes.c_double)], i32),
@@ -499,8 +500,15 @@ class Problem:
                                             theta.data_ptr(), state.data_ptr(), 1 if use_graph else 0))
         self._leave()
 
-    def set_timing(self, enabled: bool):
-        self._check(self.lib.apx_problem_set_timing(self._prob, 1 if enabled else 0))
+    def set_timing(self, enabled: bool, classes=None):
+        """Record kernel times (HIP events): every class, or only the named classes."""
+        if classes is None or not enabled:
+            self._check(self.lib.apx_problem_set_timing(self._prob, 1 if enabled else 0))
+        else:
+            mask = 0
+            for c in classes:
+                mask |= 1 << TIME_CLASSES.index(c)
+            self._check(self.lib.apx_problem_set_timing_classes(self._prob, mask))
 
     def timing(self) -> Dict[str, tuple]:
         """{class: (total_ms, launches)} since timing was enabled (synchronises)."""

@@ -114,6 +114,7 @@ struct apx_problem {
 
     // kernel timing
     bool timing = false;
+    uint32_t timing_mask = 0;        // classes recorded while timing
     bool capturing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -381,7 +382,7 @@ struct TimeScope {
 };
 
 TimeScope::TimeScope(apx_problem* P_, int k) : P(P_), klass(k) {
-    if (!P->timing || P->capturing) return;
+    if (!P->timing || P->capturing || !((P->timing_mask >> k) & 1u)) return;
     while (P->ev_pool.size() < P->ev_used + 2) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;
@@ -1508,13 +1509,18 @@ apx_status apx_problem_check(apx_problem* P) {
     return APX_OK;
 }
 
-apx_status apx_problem_set_timing(apx_problem* P, int32_t enabled) {
+apx_status apx_problem_set_timing_classes(apx_problem* P, uint32_t mask) {
     if (!P) return APX_E_INVALID;
     if (P->capturing) return fail(P->ctx, APX_E_INVALID, "timing cannot change during capture");
-    P->timing = enabled != 0;
+    P->timing_mask = mask & ((1u << APX_TIME_CLASSES) - 1u);
+    P->timing = P->timing_mask != 0;
     P->ev_used = 0;
     P->ev_recs.clear();
     return APX_OK;
+}
+
+apx_status apx_problem_set_timing(apx_problem* P, int32_t enabled) {
+    return apx_problem_set_timing_classes(P, enabled ? (1u << APX_TIME_CLASSES) - 1u : 0u);
 }
 
 apx_status apx_problem_timing(apx_problem* P, int32_t klass, double* total_ms, int64_t* launches) {

@@ -613,3 +613,81 @@ def test_planted_dropped_bn_term_fails_flux(monkeypatch):
     monkeypatch.setattr(oracle.core, "sersic_b_prime", lambda n, h=1e-5: 0.0)
     with pytest.raises(AssertionError):
         test_jacobian_matches_central_differences(None)
+
+
+# ------------------------------------------------------- higher-resolution PSF (§2.1.3)
+def _superres_spec(H, W, U, prm, psf, s=3, aff=None):
+    """One Sersic on an image whose PSF has U x U samples per pixel; the window covers the
+    whole fine extended grid."""
+    P = psf.shape[0]
+    c = (P - 1) // 2
+    spec = _render_spec(H, W, P, [_sersic_comp(prm, (-c, -c, U * H + c, U * W + c))], s=s, aff=aff, psf=psf)
+    spec["images"][0]["up"] = U
+    return spec
+
+
+def test_superres_delta_psf_equals_finer_nodes():
+    """U = 2 with a one-sample (delta) PSF and 3 x 3 midpoint nodes per fine pixel is the
+    6 x 6 midpoint rule on the image pixels: the sub-pixels and their nodes tile each pixel
+    exactly (including under a rotated, scaled map)."""
+    prm = [6.3, 5.1, 0.6, 0.7, 1.8, 2.5, 0.4]
+    aff = np.array([0.4, 0.93, -0.21, -0.3, 0.25, 1.04])
+    delta = np.ones((1, 1), np.float32)
+    sup = oracle.model_image(_superres_spec(12, 13, 2, prm, delta, s=3, aff=aff), np.zeros(0), 0)
+    ref = oracle.model_image(_render_spec(12, 13, 1, [_sersic_comp(prm, (0, 0, 12, 13))], s=6, aff=aff),
+                             np.zeros(0), 0)
+    assert sup.shape == (12, 13)
+    assert np.allclose(sup, ref, rtol=1e-12, atol=1e-15 * np.abs(ref).max())
+
+
+def test_superres_fine_shift_is_a_sub_pixel_shift():
+    """A fine stamp that moves light by one fine sample in +x (a true convolution with the
+    delta one sample right of the centre) equals the source moved by 1/U pixel in +x."""
+    U = 4
+    prm = [6.3, 5.1, 0.6, 0.7, 1.8, 2.5, 0.4]
+    K = np.zeros((3, 3), np.float32)
+    K[1, 2] = 1.0
+    sup = oracle.model_image(_superres_spec(12, 13, U, prm, K, s=2), np.zeros(0), 0)
+    moved = list(prm)
+    moved[0] += 1.0 / U
+    ref = oracle.model_image(_render_spec(12, 13, 1, [_sersic_comp(moved, (0, 0, 12, 13))], s=2 * U),
+                             np.zeros(0), 0)
+    assert np.allclose(sup, ref, rtol=1e-12, atol=1e-15 * np.abs(ref).max())
+
+
+def test_superres_binning_conserves_flux():
+    """U = 3, a random unit-sum fine stamp: the image total equals the convolved fine total
+    (binning and a unit-sum convolution both keep the flux of a source well inside)."""
+    rng = np.random.default_rng(31)
+    K = rng.random((7, 7))
+    K = (K / K.sum()).astype(np.float32)
+    K = K / K.astype(np.float64).sum()
+    prm = [10.2, 9.7, 0.8, 0.3, 0.5, 1.1, 0.0]        # a Gaussian profile: no flux near the edges
+    spec = _superres_spec(20, 20, 3, prm, K.astype(np.float64))
+    m = oracle.model_image(spec, np.zeros(0), 0)
+    S = oracle.render_ext(spec, np.zeros(0), 0)
+    assert math.isclose(m.sum(), S.sum() * float(np.asarray(K, np.float64).sum()), rel_tol=1e-9)
+
+
+def test_superres_jacobian_matches_central_differences():
+    """U = 2 (fine windows, fine asymmetric stamp, point source splatted on the fine grid):
+    the analytic columns, integrated onto the pixels, match central differences."""
+    spec, theta = _small_problem()
+    U = 2
+    im = spec["images"][0]
+    im["up"] = U
+    im["H"], im["W"] = 11, 10                              # fine grid 22 x 20 like the base case
+    spec["comps"][0]["box"] = (-2, -2, 24, 22)
+    spec["comps"][2]["fixed"][:2] = [7.2, 7.8]             # sky = pixel coordinates (identity map)
+    spec["comps"][2]["box"] = synth.point_window((7.2 + 0.5) * U - 0.5, (7.8 + 0.5) * U - 0.5, 22, 20, 5)
+    J = oracle.jacobian(spec, theta)
+    assert J.shape == (110, spec["n_par"])
+    for p in range(spec["n_par"]):
+        h = 1e-6 * max(abs(theta[p]), 0.1)
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = (oracle.model_image(spec, tp, 0) - oracle.model_image(spec, tm, 0)).ravel() / (2 * h)
+        scale = np.max(np.abs(J[:, p]))
+        assert scale > 0, p
+        assert np.max(np.abs(fd - J[:, p])) < 1e-7 * scale, p
