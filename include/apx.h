@@ -135,12 +135,20 @@ typedef int32_t apx_status;
 #define APX_LM_ATTEMPTS    4      /* Cholesky tries per iteration (lambda *= UP between) */
 #define APX_LM_DAMP_FLOOR  1e-12  /* D_kk = max(A_kk, floor * max A_kk)                */
 
+/* An image whose PSF has a higher resolution than its pixels (§2.1.3: sampling and
+ * convolution then run at the PSF's resolution and the result is integrated onto the
+ * image pixels) sets psf_up = U in {2, 4, 8}: its model is rendered on U x U sub-pixels
+ * per pixel (sub-pixel (yf, xf) centred at pixel coordinates ((xf + 1/2)/U - 1/2,
+ * (yf + 1/2)/U - 1/2)), convolved there with its stamp (P in sub-pixels) and summed over
+ * each pixel's U x U sub-pixels.  Its components' windows are then in sub-pixels
+ * (extended by c sub-pixels).  Such images always use direct convolution. */
 typedef struct apx_image_desc {
     int32_t H, W;          /* output grid                                        */
     int32_t P;             /* PSF side, odd, 1..63                               */
     int32_t sub;           /* sub-problem this image belongs to                  */
     int32_t sky_par;       /* theta index of the flat sky, -1 = fixed            */
-    int32_t reserved;
+    int32_t psf_up;        /* PSF samples per pixel per axis: 0 or 1 (same
+                              resolution), 2, 4 or 8                             */
     double  sky_fixed;     /* sky value when sky_par == -1                       */
     double  affine[6];     /* pixel -> sky map (see above)                       */
 } apx_image_desc;

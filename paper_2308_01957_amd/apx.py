@@ -41,7 +41,7 @@ TIME_CLASSES = ["prep", "render", "conv_fwd", "deriv", "conv_jcol", "pairs", "re
 
 class ImageDesc(ctypes.Structure):
     _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("P", ctypes.c_int32),
-                ("sub", ctypes.c_int32), ("sky_par", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sub", ctypes.c_int32), ("sky_par", ctypes.c_int32), ("psf_up", ctypes.c_int32),
                 ("sky_fixed", ctypes.c_double), ("affine", ctypes.c_double * 6)]
 
 
@@ -171,6 +171,7 @@ def _descs(spec: Dict):
         d.P = int(np.asarray(im["psf"]).shape[0])
         d.sub = int(im["sub"])
         d.sky_par = int(im["sky_par"])
+        d.psf_up = int(im.get("up", 1))          # PSF samples per pixel per axis
         d.sky_fixed = float(im["sky_fixed"])
         for q in range(6):
             d.affine[q] = float(im["affine"][q])

@@ -226,6 +226,7 @@ static bool tune_kernel(apx_ctx* C, int key, int P, std::array<double, 4>& us) {
     hipStream_t st = C->stream;
     DImage im{};
     im.H = im.W = TUNE_H; im.P = P; im.c = c; im.EH = im.EW = EH;
+    im.up = 1; im.Hc = im.Wc = TUNE_H;
     im.area = 1.0;
     if (hipMemcpy(base + o_img, &im, sizeof im, hipMemcpyHostToDevice) != hipSuccess) return false;
     Plan p{};
@@ -519,13 +520,21 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         if (id.sky_par >= 0 && !in_sub(id.sky_par, id.sub))
             return fail(C, APX_E_INVALID, "image " + std::to_string(k) + ": sky_par outside its sub-problem");
         if (id.sky_par < -1) return fail(C, APX_E_INVALID, "sky_par < -1");
+        const int U = id.psf_up <= 1 ? 1 : id.psf_up;
+        if (U != 1 && U != 2 && U != 4 && U != 8)
+            return fail(C, APX_E_UNSUPPORTED, "image " + std::to_string(k) + ": psf_up must be 1, 2, 4 or 8");
+        if ((long long)U * id.H > (1 << 24) || (long long)U * id.W > (1 << 24))
+            return fail(C, APX_E_UNSUPPORTED, "image " + std::to_string(k) + ": render grid too large");
         DImage im{};
-        im.H = id.H;
-        im.W = id.W;
+        im.up = U;
+        im.Hc = id.H;
+        im.Wc = id.W;
+        im.H = U * id.H;
+        im.W = U * id.W;
         im.P = id.P;
         im.c = (id.P - 1) / 2;
-        im.EH = id.H + 2 * im.c;
-        im.EW = id.W + 2 * im.c;
+        im.EH = im.H + 2 * im.c;
+        im.EW = im.W + 2 * im.c;
         im.sub = id.sub;
         im.sky_par = id.sky_par;
         im.sky_fixed = id.sky_fixed;
@@ -533,24 +542,34 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         im.ext_off = ext;
         im.psf_off = psfo;
         im.fft_off = -1;
-        if (d->conv_mode == APX_CONV_FFT && id.P >= APX_FFT_MIN_P) {
+        if (d->conv_mode == APX_CONV_FFT && id.P >= APX_FFT_MIN_P && U == 1) {
             im.fft_off = P->n_fft_spec;
             P->n_fft_spec += 2LL * FFT_T * FFT_T;
             ++P->n_fft_images;
         }
-        for (int q = 0; q < 6; ++q) im.aff[q] = id.affine[q];
-        const double det = id.affine[1] * id.affine[5] - id.affine[2] * id.affine[4];
+        // render-grid pixel -> sky: the image's map after pixel = (sub-pixel + 1/2) / U - 1/2
+        {
+            const double* a = id.affine;
+            const double o = (1.0 - U) / (2.0 * U);
+            im.aff[0] = a[0] + (a[1] + a[2]) * o;
+            im.aff[1] = a[1] / U;
+            im.aff[2] = a[2] / U;
+            im.aff[3] = a[3] + (a[4] + a[5]) * o;
+            im.aff[4] = a[4] / U;
+            im.aff[5] = a[5] / U;
+        }
+        const double det = im.aff[1] * im.aff[5] - im.aff[2] * im.aff[4];
         if (!std::isfinite(det) || det == 0.0) return fail(C, APX_E_INVALID, "singular affine map");
         im.area = std::fabs(det);
         // inverse: p = Ainv (u - t)
-        const double i11 = id.affine[5] / det, i12 = -id.affine[2] / det;
-        const double i21 = -id.affine[4] / det, i22 = id.affine[1] / det;
+        const double i11 = im.aff[5] / det, i12 = -im.aff[2] / det;
+        const double i21 = -im.aff[4] / det, i22 = im.aff[1] / det;
         im.inv[1] = i11;
         im.inv[2] = i12;
         im.inv[4] = i21;
         im.inv[5] = i22;
-        im.inv[0] = -(i11 * id.affine[0] + i12 * id.affine[3]);
-        im.inv[3] = -(i21 * id.affine[0] + i22 * id.affine[3]);
+        im.inv[0] = -(i11 * im.aff[0] + i12 * im.aff[3]);
+        im.inv[3] = -(i21 * im.aff[0] + i22 * im.aff[3]);
         P->images[k] = im;
         pix += (long long)id.H * id.W;
         ext += (long long)im.EH * im.EW;
@@ -708,12 +727,13 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             gr.ix0 = c0.box[1];
             gr.ih = c0.box[2] - c0.box[0];
             gr.iw = c0.box[3] - c0.box[1];
+            // output box on the render grid, then in image pixels (rounded outward)
             const int oy0 = std::max(0, c0.box[0] - im.c), ox0 = std::max(0, c0.box[1] - im.c);
             const int oy1 = std::min(im.H, c0.box[2] + im.c), ox1 = std::min(im.W, c0.box[3] + im.c);
-            gr.oy0 = oy0;
-            gr.ox0 = ox0;
-            gr.oh = std::max(0, oy1 - oy0);
-            gr.ow = std::max(0, ox1 - ox0);
+            gr.oy0 = oy0 / im.up;
+            gr.ox0 = ox0 / im.up;
+            gr.oh = oy1 > oy0 ? ceil_div(oy1, im.up) - gr.oy0 : 0;
+            gr.ow = ox1 > ox0 ? ceil_div(ox1, im.up) - gr.ox0 : 0;
             gr.comp_begin = (int)P->group_comps.size();
             gr.col_begin = (int)P->cols.size();
             int nc = 0;
@@ -751,7 +771,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             gr.type = GROUP_PSF;
             gr.sub = im.sub;
             gr.iy0 = -im.c; gr.ix0 = -im.c; gr.ih = im.EH; gr.iw = im.EW;
-            gr.oy0 = 0; gr.ox0 = 0; gr.oh = im.H; gr.ow = im.W;
+            gr.oy0 = 0; gr.ox0 = 0; gr.oh = im.Hc; gr.ow = im.Wc;
             gr.comp_begin = gr.comp_end = (int)P->group_comps.size();
             gr.col_begin = (int)P->cols.size();
             int nc = 0;
@@ -872,7 +892,9 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             jb.out_off = gr.j_off;
             jb.out_cs = (long long)gr.oh * gr.ow;
             jb.in_y0 = gr.iy0; jb.in_x0 = gr.ix0; jb.in_h = gr.ih; jb.in_w = gr.iw;
-            jb.out_y0 = gr.oy0; jb.out_x0 = gr.ox0; jb.out_h = gr.oh; jb.out_w = gr.ow;
+            // the job's output rectangle is on the render grid (whole pixels of sub-pixels)
+            jb.out_y0 = im.up * gr.oy0; jb.out_x0 = im.up * gr.ox0;
+            jb.out_h = im.up * gr.oh; jb.out_w = im.up * gr.ow;
             jb.image = gr.image;
             jb.group = g;
             const bool psfg = gr.type == GROUP_PSF;

@@ -46,16 +46,17 @@ constexpr int BN_COUNT = 2600;
 
 // Plan records (uploaded once into the workspace) -------------------------------
 struct DImage {
-    int H, W, P, c;
+    int H, W, P, c;           // render grid (sub-pixels when up > 1), stamp, half-width
     int EH, EW;               // extended grid (H+2c) x (W+2c)
+    int up, Hc, Wc, pad_up;   // sub-pixels per pixel per axis; the image's own pixel grid
     int sub, sky_par;
     double sky_fixed;
-    long long pix_off;        // first element in the pixel buffers
+    long long pix_off;        // first element in the pixel buffers (Hc x Wc pixels)
     long long ext_off;        // first element in the extended-grid buffers
     long long psf_off;        // first element of the stamp
-    double aff[6];            // pixel -> sky
-    double inv[6];            // sky -> pixel
-    double area;              // |det| of the linear part
+    double aff[6];            // render-grid pixel -> sky
+    double inv[6];            // sky -> render-grid pixel
+    double area;              // |det| of the linear part (render-grid pixel area)
     int live;                 // 1: the stamp is a live Moffat model rendered from theta
     int live_par[2];          // theta indices of (n, R_d), -1 = fixed
     int pad_live;
@@ -93,8 +94,9 @@ struct CompConst {
 
 struct DGroup {               // columns sharing one window on one image
     int image, type, ncols, sub;
-    int iy0, ix0, ih, iw;     // input box (window), extended-grid coords
-    int oy0, ox0, oh, ow;     // output box (window dilated by c, clipped to the image)
+    int iy0, ix0, ih, iw;     // input box (window), extended render-grid coords
+    int oy0, ox0, oh, ow;     // output box (window dilated by c, clipped to the image), in
+                              // image pixels (render-grid box / up, rounded outward)
     int comp_begin, comp_end; // into group_comps
     int col_begin;            // global id of column 0
     int tile_begin, ntiles;   // RT tiles of the input box (deriv / grad)

@@ -9,6 +9,9 @@
 // does useful FMAs at ~CV_R*P per (CV_R+P-1)/4 LDS instructions.  Each PSF row is summed
 // into a fresh partial before being added to the accumulator (error ~2P ulp, not P^2).
 //
+// On an image whose PSF has a higher resolution than its pixels the grid is of sub-pixels,
+// and the model and Jacobian epilogues first sum each pixel's sub-pixel outputs.
+//
 // Epilogues (template KIND):
 //   CONV_FWD  model + sky, optional model store, FP32 residual store, FP64 partials of
 //             sum w r^2, sum w r, sum w (chi^2 of Eq. chi2, sky gradient, sky-sky entry);
@@ -22,6 +25,18 @@
 #include "apx_internal.h"
 
 namespace apx {
+
+// Sum of each run of UU consecutive entries into the first CV_R / UU entries.
+template <int UU, typename T>
+__device__ __forceinline__ void bin_lane(T (&acc)[CV_R]) {
+#pragma unroll
+    for (int q = 0; q < CV_R / UU; ++q) {
+        T v = acc[q * UU];
+#pragma unroll
+        for (int i = 1; i < UU; ++i) v += acc[q * UU + i];
+        acc[q] = v;
+    }
+}
 
 __device__ __forceinline__ double conv_wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -70,7 +85,8 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
             const int y = iy_base + ly, x = ix_base + lx;
             T val = 0;
             if (e < LH * LW0 && y >= 0 && y < im.H && x >= 0 && x < im.W) {
-                const long long pix = im.pix_off + (long long)y * im.W + x;
+                // a pixel's seed reaches each of its sub-pixels (the adjoint of their sum)
+                const long long pix = im.pix_off + (long long)(y / im.up) * im.Wc + x / im.up;
                 val = io.seed ? io.seed[pix] : -2.f * io.weight[pix] * p.rbuf[pix];
             }
             v[q] = val;
@@ -134,21 +150,37 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
 
     // ---- epilogue
     const int y = oy0 + ty;
-    const bool yok = y < jb.out_y0 + jb.out_h;
     const int xb = ox0 + tx * CV_R;
     const int xend = jb.out_x0 + jb.out_w;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // Sub-pixel grids (up = U > 1, a power of two <= CV_R): sum each pixel's U x U outputs,
+    // U consecutive ones in a lane, then across the lanes of rows ty ^ 1 .. ty ^ (U - 1)
+    // (one wave holds 64 / LPR >= 8 rows; tiles and output boxes are whole pixels).  Lane
+    // rows with ty % U == 0 then hold CV_R / U pixel values each.
+    const int up = im.up;
+    if (KIND != CONV_ADJ && up > 1) {
+        if (up == 2) bin_lane<2>(acc);
+        else if (up == 4) bin_lane<4>(acc);
+        else bin_lane<8>(acc);
+        for (int k = 1; k < up; k <<= 1)
+#pragma unroll
+            for (int r = 0; r < CV_R; ++r) acc[r] += __shfl_xor(acc[r], k * LPR, 64);
+    }
+    const int nq = KIND == CONV_ADJ ? CV_R : CV_R / up;         // values per lane
+    const int sx = KIND == CONV_ADJ ? 1 : up;                   // render-grid step between them
+    const bool yok = y < jb.out_y0 + jb.out_h && (KIND == CONV_ADJ || (ty & (up - 1)) == 0);
+    const int yc = KIND == CONV_ADJ ? y : y / up;               // image pixel row
     if constexpr (KIND == CONV_FWD) {
         const T sky = (T)p.sky_val[jb.image];
         double c2 = 0.0, swr = 0.0, sw = 0.0;
         if (yok) {
-            const long long rowpix = im.pix_off + (long long)y * im.W;
+            const long long rowpix = im.pix_off + (long long)yc * im.Wc;
 #pragma unroll
             for (int r = 0; r < CV_R; ++r) {
-                const int x = xb + r;
-                if (x < xend) {
+                const int x = xb + r * sx;
+                if (r < nq && x < xend) {
                     const T m = acc[r] + sky;
-                    const long long pix = rowpix + x;
+                    const long long pix = rowpix + x / up;
                     if (io.out) io.out[pix] = (float)m;
                     if (io.data) {
                         const double w = (double)io.weight[pix];
@@ -179,16 +211,19 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
         float* __restrict__ out = io.out + jb.out_off + (long long)it.ch * jb.out_cs;
         double s1 = 0.0, s2 = 0.0;
         if (yok) {
-            const long long orow = (long long)(y - jb.out_y0) * jb.out_w - jb.out_x0;
-            const long long rowpix = im.pix_off + (long long)y * im.W;
+            // the column's plane is stored on the image pixels of the output box
+            const int ow = jb.out_w / up;
+            const long long orow = (long long)(yc - jb.out_y0 / up) * ow - jb.out_x0 / up;
+            const long long rowpix = im.pix_off + (long long)yc * im.Wc;
 #pragma unroll
             for (int r = 0; r < CV_R; ++r) {
-                const int x = xb + r;
-                if (x < xend) {
-                    out[orow + x] = acc[r];
+                const int x = xb + r * sx;
+                if (r < nq && x < xend) {
+                    const int xc = x / up;
+                    out[orow + xc] = acc[r];
                     if (io.weight) {
-                        const double wj = (double)io.weight[rowpix + x] * (double)acc[r];
-                        s1 += wj * (double)p.rbuf[rowpix + x];
+                        const double wj = (double)io.weight[rowpix + xc] * (double)acc[r];
+                        s1 += wj * (double)p.rbuf[rowpix + xc];
                         s2 += wj;
                     }
                 }

@@ -13,7 +13,8 @@
 // of the tile's largest values times log2 of the transform size.
 //
 // Same epilogues as the direct kernel: model + chi^2 partials (FP32 objective), Jacobian
-// columns + partials, adjoint.
+// columns + partials, adjoint.  Images with a higher-resolution PSF (a sub-pixel render
+// grid) are never planned here, so the render grid is the pixel grid.
 #include "apx_internal.h"
 
 namespace apx {
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
             if (itx >= 0) {
                 if constexpr (KIND == CONV_ADJ) {
                     if (y >= 0 && y < im.H && x >= 0 && x < im.W) {
-                        const long long pix = im.pix_off + (long long)y * im.W + x;
+                        const long long pix = im.pix_off + (long long)y * im.Wc + x;
                         val = io.seed ? io.seed[pix] : -2.f * io.weight[pix] * p.rbuf[pix];
                     }
                 } else {
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
                 const int dy = e / bw, dx = e - dy * bw;
                 const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
                 const float m = (h == 0 ? s.x : -s.y) * scale + sky;
-                const long long pix = im.pix_off + (long long)(oy + dy) * im.W + (ox + dx);
+                const long long pix = im.pix_off + (long long)(oy + dy) * im.Wc + (ox + dx);
                 if (io.out) io.out[pix] = m;
                 if (io.data) {
                     const double w = (double)io.weight[pix];
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
                 const int y = oy + dy, x = ox + dx;
                 out[(long long)(y - jb.out_y0) * jb.out_w + (x - jb.out_x0)] = v;
                 if (io.weight) {
-                    const long long pix = im.pix_off + (long long)y * im.W + x;
+                    const long long pix = im.pix_off + (long long)y * im.Wc + x;
                     const double wj = (double)io.weight[pix] * (double)v;
                     a0 += wj * (double)p.rbuf[pix];
                     a1 += wj;

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     const DGroup G = p.groups[pr.g];
     const DGroup Hh = p.groups[pr.h];
     const long long pix_off = p.images[pr.image].pix_off;
-    const int imW = p.images[pr.image].W;
+    const int imW = p.images[pr.image].Wc;          // image pixels (output boxes are in pixels)
     const long long gs = (long long)G.oh * G.ow, hs = (long long)Hh.oh * Hh.ow;
     const float* __restrict__ Jg = p.J + G.j_off;
     const float* __restrict__ Jh = p.J + Hh.j_off;
@@ -222,7 +222,7 @@ __global__ void k_jscatter(Plan p, const int* __restrict__ par_off, const int* _
     }
     const DImage& im = p.images[lo];
     const long long local = i - im.pix_off;
-    const int y = (int)(local / im.W), x = (int)(local - (long long)y * im.W);
+    const int y = (int)(local / im.Wc), x = (int)(local - (long long)y * im.Wc);
     float v = 0.f;
     for (int q = par_off[k]; q < par_off[k + 1]; ++q) {
         const DCol cl = p.cols[par_cols[q]];

@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void k_seed_part(Plan p, const float* __restri
     __shared__ double red[4];
     const int k = blockIdx.y, c = blockIdx.x;
     const DImage& im = p.images[k];
-    const long long npx = (long long)im.H * im.W;
+    const long long npx = (long long)im.Hc * im.Wc;
     double acc = 0.0;
     for (long long e = (long long)c * 256 + threadIdx.x; e < npx; e += (long long)SEED_BLOCKS * 256)
         acc += (double)seed[im.pix_off + e];

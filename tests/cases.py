@@ -185,3 +185,43 @@ def fft_fit():
     spec["conv_mode"] = 1
     spec["name"] = "fft_fit110x120_P25"
     return with_data(spec)
+
+
+def superres(U=2, H=38, W=44, seed=140, aff=None, P=11, fit=False):
+    """An image whose PSF has U x U samples per pixel: two Sersics (windows on the fine
+    grid, one cut), a point source and the sky; fine asymmetric-ish Moffat stamp P."""
+    rng = np.random.default_rng(seed)
+    Hf, Wf = U * H, U * W
+    psf = synth.moffat_psf(P, 1.2 * U, 2.8)
+    a = synth.IDENTITY_AFFINE.copy() if aff is None else np.asarray(aff, dtype=np.float64)
+    lie = (0.5, 1.5) if fit else (0.0, 1.0)
+    gals = [[0.45 * W + rng.uniform(-1, 1), 0.5 * H + rng.uniform(-1, 1), 0.65, 0.9, 1.6, 4.5, rng.uniform(*lie)],
+            [0.7 * W, 0.3 * H, 0.8, 2.1, 1.1, 3.0, rng.uniform(*lie)]]
+    theta, kinds, re_of, comps = [], [], [], []
+    c = (P - 1) // 2
+    boxes = [synth.full_window(Hf, Wf, P), (-c, U * 4, U * H - 3, Wf + c)]
+    for gi, g in enumerate(gals):
+        p0 = len(theta)
+        theta += g
+        kinds += [0, 1, 2, 3, 4, 5, 6]
+        re_of += [g[5]] * 7
+        comps.append(dict(type=0, image=0, box=boxes[gi], par=list(range(p0, p0 + 7)), fixed=[0.0] * 7))
+    # point source at sky position (ux, uy); its window on the fine grid
+    px, py = 0.25 * W + 0.37, 0.7 * H + 0.21                # image pixel position
+    ux, uy = a[0] + a[1] * px + a[2] * py, a[3] + a[4] * px + a[5] * py
+    theta.append(1.8 if fit else 1.4)
+    kinds.append(7)
+    re_of.append(1.0)
+    comps.append(dict(type=1, image=0, box=synth.point_window((px + 0.5) * U - 0.5, (py + 0.5) * U - 0.5, Hf, Wf, P),
+                      par=[-1, -1, len(theta) - 1, -1, -1, -1, -1], fixed=[ux, uy, 0, 0, 0, 0, 0]))
+    theta.append(0.05)
+    kinds.append(8)
+    re_of.append(1.0)
+    spec = {"name": f"superres_U{U}_{H}x{W}", "images": [dict(H=H, W=W, psf=psf, affine=a, sky_par=len(theta) - 1,
+                                                               sky_fixed=0.0, sub=0, up=U)],
+            "comps": comps, "subs": [(0, len(theta))], "sampling": dict(s=2, rule=0, mode=0, k=0.0),
+            "theta_true": theta, "kinds": kinds, "re_of": re_of}
+    synth._finish(spec)
+    spec["noise"] = [np.random.default_rng(seed + 1).standard_normal((H, W))]
+    spec["theta_init"] = synth.perturb(spec["theta_true"], spec["kinds"], spec["re_of"], np.random.default_rng(seed + 2))
+    return with_data(spec)
