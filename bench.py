@@ -302,6 +302,15 @@ def run_livepsf(args, torch, apx, synth):
                            "and scale, 243 params")
 
 
+def run_superres(args, torch, apx, synth):
+    spec = synth.with_psf_upsampling(synth.blend(seed_id=12, H=256, W=256, n_sersic=20, n_point=50, P=13),
+                                     U=2, P_fine=25)
+    return run_lm_workload(args, torch, apx, synth, spec, "superres",
+                           "256x256 blend (20 Sersic + 50 point sources + sky) through a PSF sampled 2x "
+                           "finer: 512x512 sub-pixel render and 25x25 sub-pixel Moffat, summed onto the "
+                           "pixels, 191 params")
+
+
 def run_adaptive(args, torch, apx, synth):
     spec = synth.blend(mode=synth.MODE_ADAPTIVE, k_re=1e-2)
     return run_lm_workload(args, torch, apx, synth, spec, "adaptive",
@@ -373,7 +382,7 @@ def run_hmc(args, torch, apx, synth):
 
 OTHER_WORKLOADS = {"cutouts": run_cutouts, "field": run_field, "multiband": run_multiband,
                    "single": run_single, "livepsf": run_livepsf, "adaptive": run_adaptive,
-                   "hmc": run_hmc}
+                   "hmc": run_hmc, "superres": run_superres}
 
 
 def tile_choice(prob):
@@ -436,7 +445,8 @@ def main():
     ap.add_argument("--conv", default="direct", choices=["direct", "fft"],
                     help="PSF convolution mode: direct (default) or FFT tiles for P >= 15")
     ap.add_argument("--workload", default="blend",
-                    choices=["blend", "cutouts", "field", "multiband", "single", "livepsf", "adaptive", "hmc"],
+                    choices=["blend", "cutouts", "field", "multiband", "single", "livepsf", "adaptive", "hmc",
+                             "superres"],
                     help="blend (default, the headline line); the others print their own line")
     args = ap.parse_args()
     CONV_MODE[0] = args.conv

@@ -535,3 +535,31 @@ def sub_spec(spec: Dict, sub: int) -> Dict:
     out["theta_init"] = spec["theta_init"][p0:p0 + n].copy()
     out["noise"] = [spec["noise"][k] for k in ks]
     return out
+
+
+def with_psf_upsampling(spec: Dict, U: int, P_fine: int, fwhm: float = 3.0, beta: float = 2.5) -> Dict:
+    """The same field observed through a PSF sampled U times finer than the pixels: each
+    image gets psf_up = U and a P_fine x P_fine Moffat stamp of FWHM `fwhm` pixels (U *
+    fwhm sub-pixels); component windows move to the sub-pixel grid (whole-image windows
+    stay whole-image, point-source supports follow their sub-pixel positions)."""
+    out = dict(spec)
+    out["images"], out["comps"] = [], []
+    for im in spec["images"]:
+        im2 = dict(im)
+        im2["up"] = U
+        im2["psf"] = moffat_psf(P_fine, fwhm * U, beta)
+        out["images"].append(im2)
+    for comp in spec["comps"]:
+        im = spec["images"][comp["image"]]
+        Hf, Wf = U * im["H"], U * im["W"]
+        c2 = dict(comp)
+        if comp["type"] == SERSIC:
+            c2["box"] = full_window(Hf, Wf, P_fine)
+        else:
+            a = np.asarray(im["affine"], dtype=np.float64)
+            A = np.array([[a[1], a[2]], [a[4], a[5]]])
+            px, py = np.linalg.solve(A, [comp["fixed"][0] - a[0], comp["fixed"][1] - a[3]])
+            c2["box"] = point_window((px + 0.5) * U - 0.5, (py + 0.5) * U - 0.5, Hf, Wf, P_fine)
+        out["comps"].append(c2)
+    out["name"] = f"{spec['name']}_up{U}_P{P_fine}"
+    return out
