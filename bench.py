@@ -178,6 +178,12 @@ def run_cutouts(args, torch, apx, synth):
         t_plain += time.perf_counter() - t0
         pp.close()
     plain = len(sample) * args.steps / t_plain
+    # parameter covariance of every cutout at the last iterate (one wave per cutout)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.covariance(th, dd, ww)
+    torch.cuda.synchronize()
+    cov_ms = (time.perf_counter() - t0) * 1e3
     mpix = _mpix(prob, spec, torch, 5)
     _line({
         "metric": "LM iters/s & Mpix/s rendered (fused adjoint+batched vs plain) at oracle rtol",
