@@ -569,6 +569,7 @@ def main():
                      "avg_launch_ms": avg_ms, "launches_with_work": j_phases,
                      "launches_total": jcol_launches,
                      "flop_per_launch": flop_per_phase},
+        "covariance_ms": cov_ms,
         "kernel_ms": {k: round(v[0], 4) for k, v in kt_all.items()},
         "kernel_ms_note": "per class over the K iterations, from a second fully instrumented pass",
     }

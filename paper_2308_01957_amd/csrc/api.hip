@@ -317,7 +317,9 @@ static std::array<double, 4> tile_costs(apx_ctx* C, int key, int P) {
     return cost;
 }
 
-// Tile shape of least estimated cost for an out_h x out_w output (ties: the lower index).
+// Tile shape of least estimated cost for an out_h x out_w output.  A shape must beat the
+// best lower-indexed (larger) one by more than 3 % to be taken: measured costs of
+// near-equal shapes wobble from run to run, and the larger tile re-reads less halo.
 static int choose_shape(apx_ctx* C, int key, int P, int out_h, int out_w) {
     if (C->tiles >= APX_TILES_FIXED && C->tiles < APX_TILES_FIXED + N_TILE_SHAPES) return C->tiles - APX_TILES_FIXED;
     if (out_h <= 0 || out_w <= 0) return 0;
@@ -326,7 +328,7 @@ static int choose_shape(apx_ctx* C, int key, int P, int out_h, int out_w) {
     double bc = 1e300;
     for (int s = 0; s < N_TILE_SHAPES; ++s) {
         const double v = (double)ceil_div(out_h, tile_th(s)) * ceil_div(out_w, tile_tw(s)) * cost[s];
-        if (v < bc) { bc = v; best = s; }
+        if (v < 0.97 * bc) { bc = v; best = s; }
     }
     return best;
 }
