@@ -459,7 +459,7 @@ def main():
     CONV_MODE[0] = args.conv
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(the fit of one field runs on one device); run with --gpus 1", file=sys.stderr)
         return 2
 
