@@ -25,6 +25,9 @@ What it computes, with the passage each step follows (section numbers of the pap
   mode), then a flat sky per image.  An image whose PSF has a higher resolution than its
   pixels (§2.1.3) is sampled and convolved on a grid of U x U sub-pixels per pixel and the
   result is integrated (summed) onto its pixels (`render_grid`, `bin_pixels`).
+* Sub-pixel re-centring (§2.1.3, optional): a Sersic is sampled with its centre moved to
+  the nearest pixel centre, convolved, and the convolved image is shifted back to the
+  true position by Lanczos or bilinear interpolation (`shifted_conv`).
 * Likelihood (§2.2, Eq. likelihood and Eq. chi2): chi2 = sum_i w_i (d_i - m_i)^2 with
   w = 1/sigma^2.  The paper's Eq. (chi2) carries a factor 1/2 (it is -log L); this
   oracle reports the conventional sum without it.
@@ -297,6 +300,118 @@ def point_pixels(im, comp, prm, with_grad=False):
     return val
 
 
+# ------------------------------------------------------------ sub-pixel re-centring
+# §2.1.3: with re-centring on, a Sersic component is sampled (and pixel-integrated) with its
+# centre moved to the centre of the nearest pixel, convolved with the PSF, and the convolved
+# image is then moved back to the true sub-pixel position by interpolation (Lanczos or
+# bilinear).  Point sources are bilinear splats already and are left as they are.
+SHIFT_NONE, SHIFT_BILINEAR, SHIFT_LANCZOS = 0, 1, 2
+
+
+def shift_setting(spec: Dict):
+    """(method, a): the re-centring interpolation and its half-width in pixels (1 for
+    bilinear, the order a for Lanczos), or (SHIFT_NONE, 0)."""
+    rc = spec.get("recentre")
+    if not rc or int(rc["method"]) == SHIFT_NONE:
+        return SHIFT_NONE, 0
+    m = int(rc["method"])
+    return m, (1 if m == SHIFT_BILINEAR else int(rc["a"]))
+
+
+def lanczos(x, a: int):
+    """Lanczos window of order a: sinc(x) sinc(x / a) for |x| < a, else 0 (normalised
+    sinc, sin(pi x) / (pi x))."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.where(np.abs(x) < a, np.sinc(x) * np.sinc(x / a), 0.0)
+
+
+def lanczos_prime(x, a: int):
+    """d/dx of the Lanczos window; sinc'(z) = (cos(pi z) - sinc(z)) / z, 0 at z = 0."""
+    x = np.asarray(x, dtype=np.float64)
+
+    def dsinc(z):
+        zs = np.where(z == 0.0, 1.0, z)
+        return np.where(z == 0.0, 0.0, (np.cos(np.pi * zs) - np.sinc(zs)) / zs)
+
+    return np.where(np.abs(x) < a, dsinc(x) * np.sinc(x / a) + np.sinc(x) * dsinc(x / a) / a, 0.0)
+
+
+def shift_taps(delta: float, method: int, a: int):
+    """Weights w[t + a], t = -a..a, that move a pixel-sampled image by delta pixels
+    (|delta| <= 1/2) along one axis, shifted(i) = sum_t w_t img(i - t) (the image read at
+    i - delta), and dw/d delta.  Bilinear: the two nearest samples (at delta = 0 the
+    derivative is the one from the right, delta -> 0+).  Lanczos: the window at t - delta,
+    normalised to unit sum so that the shift keeps the flux."""
+    t = np.arange(-a, a + 1, dtype=np.float64)
+    if method == SHIFT_BILINEAR:
+        w = np.maximum(0.0, 1.0 - np.abs(t - delta))
+        side = 1.0 if delta >= 0.0 else -1.0
+        dw = np.where(t == 0.0, -side, 0.0) + np.where(t == side, side, 0.0)
+        return w, dw
+    L = lanczos(t - delta, a)
+    dL = -lanczos_prime(t - delta, a)
+    N, dN = float(L.sum()), float(dL.sum())
+    return L / N, (dL * N - L * dN) / (N * N)
+
+
+def recentre_geometry(im, x0: float, y0: float):
+    """Nearest pixel centre of the sky position (x0, y0) on image im: returns the sky
+    position of that pixel centre, the offset delta = (pixel position) - (that centre)
+    in pixels (each in [-1/2, 1/2)), and d delta / d (x0, y0) (the inverse of the linear
+    part of the pixel -> sky map)."""
+    a = _affine(im)
+    A = np.array([[a[1], a[2]], [a[4], a[5]]])
+    px, py = np.linalg.solve(A, np.array([x0 - a[0], y0 - a[3]]))
+    nx, ny = math.floor(px + 0.5), math.floor(py + 0.5)
+    ux, uy = _sky_coords(a, float(nx), float(ny))
+    return (ux, uy), (px - nx, py - ny), np.linalg.inv(A)
+
+
+def recentred(spec: Dict, comp: Dict) -> bool:
+    return comp["type"] == SERSIC and shift_setting(spec)[0] != SHIFT_NONE
+
+
+def shifted_conv(Sc: np.ndarray, K: np.ndarray, wy: np.ndarray, wx: np.ndarray, a: int) -> np.ndarray:
+    """The paper's order for one re-centred component: the true convolution K * S'
+    (S' on the extended grid, zero beyond it) taken on the image grown by a pixels on
+    every side, then the interpolation shift back onto the image:
+    out(i) = sum_t wy[ty] wx[tx] (K * S')(i - t)."""
+    Mp = convolve_valid(np.pad(Sc, a), K)             # image coords -a .. H+a
+    H, W = Mp.shape[0] - 2 * a, Mp.shape[1] - 2 * a
+    out = np.zeros((H, W))
+    for jy in range(2 * a + 1):
+        for jx in range(2 * a + 1):
+            ty, tx = jy - a, jx - a
+            out += wy[jy] * wx[jx] * Mp[a - ty:a - ty + H, a - tx:a - tx + W]
+    return out
+
+
+def recentred_parts(spec: Dict, comp: Dict, theta: np.ndarray, with_grad: bool = False):
+    """One re-centred Sersic on the extended grid of its image: S' (sampled with the
+    centre at the nearest pixel centre), the x and y taps (and their delta-derivatives)
+    and d delta / d (x0, y0); with_grad adds dS'/dtheta_k (k = q, PA, n, Re, Ie; S' does
+    not move with x0 and y0, whose derivative comes through the taps alone)."""
+    im = render_grid(spec["images"][comp["image"]])
+    c = psf_half(im)
+    method, a = shift_setting(spec)
+    prm = local_params(comp, theta)
+    (ux, uy), (dx, dy), dd = recentre_geometry(im, prm[0], prm[1])
+    prm_c = [ux, uy] + prm[2:]
+    y0, x0, y1, x1 = comp["box"]
+    Sc = np.zeros((im["H"] + 2 * c, im["W"] + 2 * c))
+    r = sersic_pixels(im, comp, prm_c, spec["sampling"], with_grad)
+    wx, dwx = shift_taps(dx, method, a)
+    wy, dwy = shift_taps(dy, method, a)
+    if not with_grad:
+        Sc[y0 + c:y1 + c, x0 + c:x1 + c] = r
+        return Sc, (wy, wx, dwy, dwx), dd
+    Sc[y0 + c:y1 + c, x0 + c:x1 + c] = r[0]
+    G = np.zeros((7,) + Sc.shape)
+    G[:, y0 + c:y1 + c, x0 + c:x1 + c] = r[1]
+    G[0] = G[1] = 0.0
+    return Sc, (wy, wx, dwy, dwx), dd, G
+
+
 def render_grid(im) -> Dict:
     """The grid an image's model is sampled and convolved on.  An image whose PSF has a
     higher resolution than its pixels (§2.1.3: sampling and convolution then run at the
@@ -357,12 +472,13 @@ def clipped(comp: Dict, im) -> Dict | None:
 
 def render_ext(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
     """Sum of all components of image k on the extended render grid [-c, H+c) x [-c, W+c)
-    (fine pixels for an image with a higher-resolution PSF)."""
+    (fine pixels for an image with a higher-resolution PSF); re-centred components are
+    left out (they are convolved one by one, `model_conv`)."""
     im = render_grid(spec["images"][k])
     c = psf_half(im)
     S = np.zeros((im["H"] + 2 * c, im["W"] + 2 * c))
     for comp in spec["comps"]:
-        if comp["image"] != k:
+        if comp["image"] != k or recentred(spec, comp):
             continue
         comp = clipped(comp, im)
         if comp is None:
@@ -436,12 +552,39 @@ def psf_of(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
     return moffat_stamp(n, rd, np.asarray(im["psf"]).shape[0])
 
 
+def recentred_comps(spec: Dict, k: int):
+    """The re-centred components of image k, windows cut to its extended grid."""
+    im = render_grid(spec["images"][k])
+    out = []
+    for comp in spec["comps"]:
+        if comp["image"] == k and recentred(spec, comp):
+            comp = clipped(comp, im)
+            if comp is not None:
+                out.append(comp)
+    return out
+
+
+def model_conv(spec: Dict, theta: np.ndarray, k: int, K: np.ndarray) -> np.ndarray:
+    """Image k's components convolved with the stamp K, on its render grid: the sum of
+    the ordinary components convolved at once, plus every re-centred component
+    convolved and shifted back on its own (`shifted_conv`)."""
+    M = convolve_valid(render_ext(spec, theta, k), K)
+    a = shift_setting(spec)[1]
+    for comp in recentred_comps(spec, k):
+        Sc, (wy, wx, _, _), _ = recentred_parts(spec, comp, theta)
+        M += shifted_conv(Sc, K, wy, wx, a)
+    return M
+
+
 def model_image(spec: Dict, theta: np.ndarray, k: int) -> np.ndarray:
     """Convolved model of image k (integrated onto its pixels) plus its flat sky (the sky
     is not convolved)."""
     im = spec["images"][k]
-    M = convolve_valid(render_ext(spec, theta, k), psf_of(spec, theta, k))
-    return bin_pixels(M, int(im.get("up", 1))) + sky_value(im, theta)
+    U = int(im.get("up", 1))
+    if U > 1 and shift_setting(spec)[0] != SHIFT_NONE:
+        raise ValueError("re-centring is defined on image pixels; a higher-resolution PSF replaces it")
+    M = model_conv(spec, theta, k, psf_of(spec, theta, k))
+    return bin_pixels(M, U) + sky_value(im, theta)
 
 
 def images_of_sub(spec: Dict, sub: int) -> List[int]:
@@ -475,10 +618,12 @@ def jacobian_image(spec, theta, k, cols: Sequence[int] | None = None) -> np.ndar
     c = psf_half(im)
     H, W = im["H"], im["W"]
     n_par = spec["n_par"]
+    if U > 1 and shift_setting(spec)[0] != SHIFT_NONE:
+        raise ValueError("re-centring is defined on image pixels; a higher-resolution PSF replaces it")
     want = set(range(n_par)) if cols is None else set(cols)
     dS = {}
     for comp in spec["comps"]:
-        if comp["image"] != k:
+        if comp["image"] != k or recentred(spec, comp):
             continue
         comp = clipped(comp, im)
         if comp is None:
@@ -501,15 +646,31 @@ def jacobian_image(spec, theta, k, cols: Sequence[int] | None = None) -> np.ndar
             J[:, ci] = bin_pixels(convolve_valid(dS[p], K), U).ravel()
         if im["sky_par"] == p:
             J[:, ci] += 1.0
+    # re-centred components: m_c = T(delta) * (K * S'); the shape parameters move S', the
+    # centre moves only delta (by d delta / d(x0, y0)), i.e. the taps
+    a = shift_setting(spec)[1]
+    for comp in recentred_comps(spec, k):
+        if not any(p >= 0 and p in want for p in comp["par"]):
+            continue
+        Sc, (wy, wx, dwy, dwx), dd, G = recentred_parts(spec, comp, theta, with_grad=True)
+        for loc, p in enumerate(comp["par"]):
+            if p < 0 or p not in want:
+                continue
+            if loc < 2:
+                Mx = shifted_conv(Sc, K, wy, dwx, a)          # d / d delta_x
+                My = shifted_conv(Sc, K, dwy, wx, a)          # d / d delta_y
+                col = dd[0, loc] * Mx + dd[1, loc] * My
+            else:
+                col = shifted_conv(G[loc], K, wy, wx, a)
+            J[:, out_cols.index(p)] += col.ravel()
     # live PSF: m = K(phi) * S + sky, so dm/dphi = (dK/dphi) * S
     pm = psf_model_of(spec, k)
     if pm is not None and any(p >= 0 and p in want for p in pm["par"]):
         n, rd = psf_params(pm, theta)
         _, dK_dn, dK_drd = moffat_stamp(n, rd, np.asarray(im["psf"]).shape[0], with_grad=True)
-        S = render_ext(spec, theta, k)
         for p, dK in zip(pm["par"], (dK_dn, dK_drd)):
             if p >= 0 and p in want:
-                J[:, out_cols.index(p)] += bin_pixels(convolve_valid(S, dK), U).ravel()
+                J[:, out_cols.index(p)] += bin_pixels(model_conv(spec, theta, k, dK), U).ravel()
     return J
 
 

@@ -563,3 +563,15 @@ def with_psf_upsampling(spec: Dict, U: int, P_fine: int, fwhm: float = 3.0, beta
         out["comps"].append(c2)
     out["name"] = f"{spec['name']}_up{U}_P{P_fine}"
     return out
+
+
+SHIFT_NONE, SHIFT_BILINEAR, SHIFT_LANCZOS = 0, 1, 2
+
+
+def with_recentring(spec: Dict, method: int, a: int = 3) -> Dict:
+    """The same workload with sub-pixel re-centring of its Sersic components (§2.1.3):
+    `method` SHIFT_BILINEAR or SHIFT_LANCZOS of order `a`."""
+    out = dict(spec)
+    out["recentre"] = {"method": int(method), "a": int(a)}
+    out["name"] = f"{spec['name']}_shift{method}a{a}"
+    return out
