@@ -125,6 +125,25 @@ typedef int32_t apx_status;
 #define APX_CONV_FFT    1
 #define APX_FFT_MIN_P   15
 
+/* Sub-pixel re-centring (§2.1.3).  With shift != APX_SHIFT_NONE every Sersic component
+ * is sampled (and pixel-integrated) with its centre moved to the centre of the nearest
+ * pixel of its image, n = floor(p + 1/2) for its pixel position p, and the convolved
+ * image is moved back by delta = p - n (each axis in [-1/2, 1/2)) by interpolation:
+ * m_c(i) = sum_t w_y(t_y) w_x(t_x) (K * S'_c)(i - t), |t| <= a per axis, with
+ *   APX_SHIFT_BILINEAR: a = 1, the two nearest samples (1 - |delta|, |delta|);
+ *   APX_SHIFT_LANCZOS:  a = shift_a in [2, APX_SHIFT_MAX_A], weights
+ *                       sinc(t - delta) sinc((t - delta)/a), normalised to unit sum.
+ * The derivatives in x0, y0 come through delta alone (d delta / d(x0, y0) is the inverse
+ * of the image's linear map; the bilinear one is taken from the right at delta = 0).
+ * Point sources (already bilinear splats) are not moved.  The library applies the shift
+ * before the convolution (it commutes with it), so a component's support grows by a
+ * pixels on every side (clipped to the extended grid).  Not with APX_MODE_ADAPTIVE, nor
+ * with psf_up > 1 (a higher-resolution PSF is the alternative the paper gives). */
+#define APX_SHIFT_NONE     0
+#define APX_SHIFT_BILINEAR 1
+#define APX_SHIFT_LANCZOS  2
+#define APX_SHIFT_MAX_A    5
+
 /* LM constants (§2.5 gives the method, not the constants; these are fixed here). */
 #define APX_LM_LAMBDA0     1e-2
 #define APX_LM_UP          11.0
@@ -194,6 +213,8 @@ typedef struct apx_problem_desc {
     int32_t n_psf_models;           /* live PSF models (0: every stamp is fixed)     */
     int32_t conv_mode;              /* APX_CONV_DIRECT (default) or APX_CONV_FFT     */
     const apx_psf_model_desc* psf_models;   /* host, [n_psf_models]                 */
+    int32_t shift;                  /* APX_SHIFT_* sub-pixel re-centring (0 = none)   */
+    int32_t shift_a;                /* Lanczos order a (APX_SHIFT_LANCZOS only)      */
 } apx_problem_desc;
 
 /* Per-sub-problem LM state, device memory, [n_sub] entries (apx_lm_init fills it). */

@@ -23,6 +23,7 @@ APX_OK, APX_E_INVALID, APX_E_HIP, APX_E_NONFINITE, APX_E_WORKSPACE, APX_E_UNSUPP
     0, -1, -2, -3, -4, -5, -6
 OBJECTIVE_FP64, OBJECTIVE_FP32 = 0, 1
 CONV_DIRECT, CONV_FFT = 0, 1            # spec["conv_mode"]
+SHIFT_NONE, SHIFT_BILINEAR, SHIFT_LANCZOS = 0, 1, 2   # spec["recentre"]["method"]
 
 EXPORTS = [
     "apx_version", "apx_status_string", "apx_ctx_create", "apx_ctx_set_stream", "apx_ctx_destroy",
@@ -64,7 +65,16 @@ class ProblemDesc(ctypes.Structure):
                 ("s", ctypes.c_int32), ("rule", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("objective", ctypes.c_int32), ("k_re", ctypes.c_double),
                 ("n_psf_models", ctypes.c_int32), ("conv_mode", ctypes.c_int32),
-                ("psf_models", ctypes.POINTER(PsfModelDesc))]
+                ("psf_models", ctypes.POINTER(PsfModelDesc)),
+                ("shift", ctypes.c_int32), ("shift_a", ctypes.c_int32)]
+
+
+def _shift(spec: Dict):
+    """(method, Lanczos order) of the spec's sub-pixel re-centring."""
+    rc = spec.get("recentre")
+    if not rc:
+        return SHIFT_NONE, 0
+    return int(rc["method"]), int(rc.get("a", 0))
 
 
 PSF_MOFFAT = 0
@@ -222,7 +232,7 @@ class Problem:
                            idesc, cdesc, sp, ctypes.c_void_p(self.psf.data_ptr()),
                            int(sampling["s"]), int(sampling["rule"]), int(sampling["mode"]),
                            int(objective), float(sampling.get("k", 0.0)), npm,
-                           int(spec.get("conv_mode", CONV_DIRECT)), pms)
+                           int(spec.get("conv_mode", CONV_DIRECT)), pms, *_shift(spec))
         self._keep = (idesc, cdesc, sp, desc, pms)
         self._prob = ctypes.c_void_p()
         self._check(self.lib.apx_problem_create(self._ctx, ctypes.byref(desc), ctypes.byref(self._prob)))
@@ -560,7 +570,7 @@ class Plan:
         desc = ProblemDesc(len(spec["images"]), len(spec["comps"]), int(spec["n_par"]), len(spec["subs"]),
                            idesc, cdesc, sp, None, int(sampling["s"]), int(sampling["rule"]),
                            int(sampling["mode"]), int(objective), float(sampling.get("k", 0.0)), npm,
-                           int(spec.get("conv_mode", CONV_DIRECT)), pms)
+                           int(spec.get("conv_mode", CONV_DIRECT)), pms, *_shift(spec))
         self._keep = (idesc, cdesc, sp, desc, pms)
         self._prob = ctypes.c_void_p()
         st = self.lib.apx_problem_create(self._ctx, ctypes.byref(desc), ctypes.byref(self._prob))

@@ -50,6 +50,7 @@ struct apx_problem {
     apx_ctx* ctx = nullptr;
     int n_images = 0, n_comps = 0, n_par = 0, n_sub = 0;
     int s = 3, rule = 0, mode = 0, objective = 0, conv_mode = 0;
+    int shift = 0, shift_a = 0;                   // re-centring method, interpolation half-width
     double k_re = 0.0;
     const float* psf = nullptr;
 
@@ -434,6 +435,14 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         return fail(C, APX_E_INVALID, "unknown objective precision");
     if (d->conv_mode != APX_CONV_DIRECT && d->conv_mode != APX_CONV_FFT)
         return fail(C, APX_E_INVALID, "unknown convolution mode");
+    if (d->shift != APX_SHIFT_NONE && d->shift != APX_SHIFT_BILINEAR && d->shift != APX_SHIFT_LANCZOS)
+        return fail(C, APX_E_INVALID, "unknown re-centring method");
+    if (d->shift == APX_SHIFT_LANCZOS && (d->shift_a < 2 || d->shift_a > APX_SHIFT_MAX_A))
+        return fail(C, APX_E_UNSUPPORTED, "Lanczos order must be in 2..5");
+    if (d->shift != APX_SHIFT_NONE && d->mode == APX_MODE_ADAPTIVE)
+        return fail(C, APX_E_UNSUPPORTED, "re-centring with adaptive integration");
+    P->shift = d->shift;
+    P->shift_a = d->shift == APX_SHIFT_NONE ? 0 : (d->shift == APX_SHIFT_BILINEAR ? 1 : d->shift_a);
 
     // nodes (adaptive mode: its 3 x 3 Gauss-Legendre level; the other levels use agl)
     if (d->mode == APX_MODE_ADAPTIVE) {
@@ -525,6 +534,8 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         const int U = id.psf_up <= 1 ? 1 : id.psf_up;
         if (U != 1 && U != 2 && U != 4 && U != 8)
             return fail(C, APX_E_UNSUPPORTED, "image " + std::to_string(k) + ": psf_up must be 1, 2, 4 or 8");
+        if (U != 1 && d->shift != APX_SHIFT_NONE)
+            return fail(C, APX_E_UNSUPPORTED, "re-centring with a higher-resolution PSF");
         if ((long long)U * id.H > (1 << 24) || (long long)U * id.W > (1 << 24))
             return fail(C, APX_E_UNSUPPORTED, "image " + std::to_string(k) + ": render grid too large");
         DImage im{};
@@ -640,7 +651,16 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         int y0 = std::max(cd.box[0], -im.c), x0 = std::max(cd.box[1], -im.c);
         int y1 = std::min(cd.box[2], im.H + im.c), x1 = std::min(cd.box[3], im.W + im.c);
         if (y1 <= y0 || x1 <= x0) { y0 = x0 = y1 = x1 = 0; }
-        c.box[0] = y0; c.box[1] = x0; c.box[2] = y1; c.box[3] = x1;
+        c.box[0] = c.sbox[0] = y0; c.box[1] = c.sbox[1] = x0;
+        c.box[2] = c.sbox[2] = y1; c.box[3] = c.sbox[3] = x1;
+        if (cd.type == APX_SERSIC && P->shift != APX_SHIFT_NONE && y1 > y0) {
+            // the shifted component reaches shift_a pixels beyond where it is sampled
+            const int a = P->shift_a;
+            c.box[0] = std::max(y0 - a, -im.c);
+            c.box[1] = std::max(x0 - a, -im.c);
+            c.box[2] = std::min(y1 + a, im.H + im.c);
+            c.box[3] = std::min(x1 + a, im.W + im.c);
+        }
         P->comps[i] = c;
     }
 
@@ -1198,6 +1218,7 @@ static void layout(apx_problem* P) {
     ws_take<int>(P, "acount", 1);
     // buffers
     ws_take<CompConst>(P, "cc", P->comps.size());
+    ws_take<double>(P, "stap", P->shift != APX_SHIFT_NONE ? STAP_STRIDE * P->comps.size() : 0);
     ws_take<float>(P, "S", P->n_ext);
     ws_take<double>(P, "S64", P->objective == APX_OBJECTIVE_FP64 ? P->n_ext : 0);
     ws_take<float>(P, "Abar", P->n_ext);
@@ -1434,6 +1455,8 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.rule = P->rule;
     p.mode = P->mode;
     p.objective = P->objective;
+    p.shift = P->shift;
+    p.shift_a = P->shift_a;
     p.k_re = P->k_re;
     for (int k = 0; k < MAX_NODES_1D; ++k) {
         p.node_o[k] = k < (int)P->node_o.size() ? P->node_o[k] : 0.f;
@@ -1456,6 +1479,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.gtiles = wsp<RTile>(P, "gtiles");
     p.n_gtiles = (int)P->gtiles.size();
     p.cc = wsp<CompConst>(P, "cc");
+    p.stap = wsp<double>(P, "stap");
     p.S = wsp<float>(P, "S");
     p.S64 = wsp<double>(P, "S64");
     p.Abar = wsp<float>(P, "Abar");

@@ -39,6 +39,10 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
     const int x = b % N_XCD, q = n / N_XCD, r = n % N_XCD;
     return x * q + (x < r ? x : r) + b / N_XCD;
 }
+// Sub-pixel re-centring taps per component (written by k_prep): wx, wy, dwx/d delta_x,
+// dwy/d delta_y, each SHIFT_NT entries indexed by t + a (t = -a..a)
+constexpr int SHIFT_NT = 2 * APX_SHIFT_MAX_A + 1;
+constexpr int STAP_STRIDE = 4 * SHIFT_NT;
 // b_n table: cubic Hermite nodes (b, db/dn) on [BN_N0, BN_N0 + (BN_COUNT-1)/BN_INV_H]
 constexpr double BN_N0 = 0.35;
 constexpr double BN_INV_H = 256.0;
@@ -67,7 +71,10 @@ struct DImage {
 
 struct DComp {
     int type, image;
-    int box[4];               // clipped window y0, x0, y1, x1 (extended-grid coords)
+    int box[4];               // clipped window y0, x0, y1, x1 (extended-grid coords); with
+                              // re-centring, the support of the shifted component (sbox
+                              // grown by the interpolation half-width, clipped)
+    int sbox[4];              // where the component is sampled (the clipped window)
     int par[7];
     int group;                // Jacobian group, -1 when the component has no free parameter
     int col[7];               // column of local parameter k inside its group, -1 = fixed
@@ -148,6 +155,7 @@ struct LMFlags {
 struct Plan {
     int n_images, n_comps, n_par, n_sub, n_groups, n_cols;
     int s, rule, mode, objective;
+    int shift, shift_a;       // re-centring: APX_SHIFT_*, interpolation half-width a (0: none)
     double k_re;
     float node_o[MAX_NODES_1D], node_w[MAX_NODES_1D];
     double node_od[MAX_NODES_1D], node_wd[MAX_NODES_1D];
@@ -173,6 +181,7 @@ struct Plan {
 
     // buffers
     CompConst* cc;
+    double* stap;             // [n_comps * STAP_STRIDE] re-centring taps (shift != 0)
     float* S;                 // extended grid (render, FP32 objective)
     double* S64;              // extended grid (render, FP64 objective)
     float* Abar;              // extended grid adjoint

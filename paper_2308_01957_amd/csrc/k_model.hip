@@ -32,6 +32,41 @@ __device__ void sersic_bn_table(const double* tab, double n, double& b, double& 
          (3 * t2 - 2 * t) * d1;
 }
 
+// ------------------------------------------------------------------- re-centring taps
+// Weights that move a pixel-sampled image by delta (|delta| <= 1/2) along one axis,
+// shifted(i) = sum_t w[t + a] img(i - t), and their derivatives in delta (§2.1.3).
+// Bilinear: the two nearest samples (derivative from the right at delta = 0).  Lanczos of
+// order a: sinc(t - delta) sinc((t - delta) / a) (normalised sinc), divided by its sum.
+__device__ __forceinline__ double nsinc(double x) { return x == 0.0 ? 1.0 : sinpi(x) / (M_PI * x); }
+__device__ __forceinline__ double nsinc_d(double x) { return x == 0.0 ? 0.0 : (cospi(x) - nsinc(x)) / x; }
+
+__device__ void shift_taps(int method, int a, double delta, double* w, double* dw) {
+    if (method == APX_SHIFT_BILINEAR) {
+        const double side = delta >= 0.0 ? 1.0 : -1.0;
+        for (int j = 0; j < 3; ++j) {
+            const double t = (double)(j - 1);
+            w[j] = fmax(0.0, 1.0 - fabs(t - delta));
+            dw[j] = (t == 0.0 ? -side : 0.0) + (t == side ? side : 0.0);
+        }
+        return;
+    }
+    double N = 0.0, dN = 0.0;
+    for (int j = 0; j <= 2 * a; ++j) {
+        const double x = (double)(j - a) - delta;
+        const bool in = fabs(x) < (double)a;
+        const double L = in ? nsinc(x) * nsinc(x / a) : 0.0;
+        const double dL = in ? -(nsinc_d(x) * nsinc(x / a) + nsinc(x) * nsinc_d(x / a) / a) : 0.0;
+        w[j] = L;
+        dw[j] = dL;
+        N += L;
+        dN += dL;
+    }
+    for (int j = 0; j <= 2 * a; ++j) {
+        dw[j] = (dw[j] * N - w[j] * dN) / (N * N);
+        w[j] = w[j] / N;
+    }
+}
+
 // ------------------------------------------------------------------------- prep
 __global__ void k_prep(Plan p, const double* __restrict__ theta, int lm_trial) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,6 +120,18 @@ __global__ void k_prep(Plan p, const double* __restrict__ theta, int lm_trial) {
             c.n = (float)n;
             c.re = (float)re;
             c.q = (float)q;
+            if (p.shift != APX_SHIFT_NONE) {
+                // sample with the centre at the nearest pixel centre n; the taps move the
+                // result back by delta = (pixel position) - n
+                const double px = im.inv[0] + im.inv[1] * c.x0 + im.inv[2] * c.y0;
+                const double py = im.inv[3] + im.inv[4] * c.x0 + im.inv[5] * c.y0;
+                const double nx = floor(px + 0.5), ny = floor(py + 0.5);
+                c.x0 = im.aff[0] + im.aff[1] * nx + im.aff[2] * ny;
+                c.y0 = im.aff[3] + im.aff[4] * nx + im.aff[5] * ny;
+                double* tp = p.stap + (long long)i * STAP_STRIDE;
+                shift_taps(p.shift, p.shift_a, px - nx, tp, tp + 2 * SHIFT_NT);
+                shift_taps(p.shift, p.shift_a, py - ny, tp + SHIFT_NT, tp + 3 * SHIFT_NT);
+            }
         }
     } else {
         // point source: sky position -> pixel position of its image
@@ -97,6 +144,8 @@ __global__ void k_prep(Plan p, const double* __restrict__ theta, int lm_trial) {
         c.F = (float)c.F64;
     }
     c.valid = valid ? 1 : 0;
+    if (cp.type == APX_SERSIC && p.shift != APX_SHIFT_NONE && !valid)
+        for (int j = 0; j < STAP_STRIDE; ++j) p.stap[(long long)i * STAP_STRIDE + j] = 0.0;
     p.cc[i] = c;
     if (!valid) {
         if (lm_trial) atomicOr(&p.lmf[cp.sub].trial_bad, 1);
@@ -296,15 +345,95 @@ __device__ __forceinline__ double point_weight(const CompConst& c, int y, int x)
     return wx * wy;
 }
 
+// ------------------------------------------------------------- re-centred tiles
+// A re-centred Sersic (§2.1.3) enters the pre-convolution grid as T * S': S' sampled with
+// the centre at the nearest pixel centre, T the separable interpolation taps (the shift
+// commutes with the PSF convolution).  A workgroup owning an RT_Y x RT_X tile with origin
+// (y0, x0) samples S' once over the tile grown by a on every side into LDS (zero outside
+// the sampled window sbox), then every pixel sums its (2a+1)^2 taps from LDS.
+constexpr int SH_H = RT_Y + 2 * APX_SHIFT_MAX_A, SH_W = RT_X + 2 * APX_SHIFT_MAX_A;
+
+// Stage NPL planes of f(ry, rx, out[NPL]) over the grown tile: sh[q][hy * (RT_X + 2a) + hx].
+template <int NPL, typename T, typename F>
+__device__ __forceinline__ void stage_halo(const Plan& p, const DComp& cp, int y0, int x0, T (*sh)[SH_H * SH_W],
+                                           F&& f) {
+    const int a = p.shift_a, HW = RT_X + 2 * a, n = (RT_Y + 2 * a) * HW;
+    for (int e = (int)threadIdx.x; e < n; e += 256) {
+        const int hy = e / HW, hx = e - hy * HW;
+        const int ry = y0 - a + hy, rx = x0 - a + hx;
+        T v[NPL];
+        for (int q = 0; q < NPL; ++q) v[q] = (T)0;
+        if (ry >= cp.sbox[0] && ry < cp.sbox[2] && rx >= cp.sbox[1] && rx < cp.sbox[3]) f(ry, rx, v);
+        for (int q = 0; q < NPL; ++q) sh[q][e] = v[q];
+    }
+}
+
+// sum_t wy[ty] wx[tx] plane(ly - ty, lx - tx) for the pixel (ly, lx) of the tile; the taps
+// (same for the whole block) are read from the component's tap table.
+template <typename T>
+__device__ __forceinline__ T tap_sum(const T* plane, int a, int ly, int lx, const double* wy,
+                                     const double* wx) {
+    const int HW = RT_X + 2 * a;
+    T out = (T)0;
+    for (int jy = 0; jy <= 2 * a; ++jy) {
+        const T* row = plane + (ly + 2 * a - jy) * HW + lx + 2 * a;
+        T acc = (T)0;
+        for (int jx = 0; jx <= 2 * a; ++jx) acc = fma((T)wx[jx], row[-jx], acc);
+        out = fma((T)wy[jy], acc, out);
+    }
+    return out;
+}
+
+// tap table of component ci: wx, wy, dwx, dwy (SHIFT_NT each)
+__device__ __forceinline__ const double* taps_of(const Plan& p, int ci) {
+    return p.stap + (long long)ci * STAP_STRIDE;
+}
+
+// The 7 pre-convolution derivative values (before the area factor is applied: it is in
+// the staged planes) of a re-centred Sersic at pixel (ly, lx) of a tile whose grown
+// origin is (y0 - a, x0 - a): d/d(q, PA, n, Re, log Ie) are T * dS'/dtheta; x0 and y0 move
+// only delta, d/d x0 = inv1 (dT/d delta_x * S') + inv4 (dT/d delta_y * S') (and inv2,
+// inv5 for y0), S' = (d/d log Ie plane) / ln 10.  Every thread of the block calls it.
+__device__ void shifted_derivs(const Plan& p, int ci, const CompConst& c, const DComp& cp, const DImage& im,
+                               int y0, int x0, int ly, int lx, bool want, float (*sh)[SH_H * SH_W],
+                               float out[7]) {
+    stage_halo<5, float>(p, cp, y0, x0, sh, [&](int ry, int rx, float* v) {
+        const double ucx = im.aff[0] + im.aff[1] * rx + im.aff[2] * ry;
+        const double ucy = im.aff[3] + im.aff[4] * rx + im.aff[5] * ry;
+        float acc[7];
+        sersic_pixel_grad(p, c, im, cp, ry, rx, ucx, ucy, acc);
+        const float area = (float)im.area;
+        for (int q = 0; q < 5; ++q) v[q] = acc[q + 2] * area;
+    });
+    __syncthreads();
+    for (int q = 0; q < 7; ++q) out[q] = 0.f;
+    if (want) {
+        const double* tp = taps_of(p, ci);
+        const double *wx = tp, *wy = tp + SHIFT_NT, *dwx = tp + 2 * SHIFT_NT, *dwy = tp + 3 * SHIFT_NT;
+        const int a = p.shift_a;
+        for (int q = 0; q < 5; ++q) out[q + 2] = tap_sum(sh[q], a, ly, lx, wy, wx);
+        const float inv_ln10 = 1.f / LN10F;
+        const float mx = tap_sum(sh[4], a, ly, lx, wy, dwx) * inv_ln10;
+        const float my = tap_sum(sh[4], a, ly, lx, dwy, wx) * inv_ln10;
+        out[0] = (float)im.inv[1] * mx + (float)im.inv[4] * my;
+        out[1] = (float)im.inv[2] * mx + (float)im.inv[5] * my;
+    }
+    __syncthreads();
+}
+
 // ----------------------------------------------------------------------- render
 // S (extended grid) = sum of all components whose window holds the pixel.
+// SHIFT: the problem re-centres its Sersics (a separate instantiation keeps the plain
+// kernels' register and LDS budgets)
+template <bool SHIFT>
 __global__ __launch_bounds__(256) void k_render(Plan p, int skip_mode, const apx_lm_state* lm) {
+    __shared__ float sh[1][SHIFT ? SH_H * SH_W : 1];
     const RTile t = p.rtiles[blockIdx.x];
     const DImage& im = p.images[t.a];
     if (sub_skipped(p, im.sub, skip_mode, lm)) return;
-    const int y = t.y0 + (int)threadIdx.x / RT_X;
-    const int x = t.x0 + (int)threadIdx.x % RT_X;
-    if (y >= im.H + im.c || x >= im.W + im.c) return;
+    const int ly = (int)threadIdx.x / RT_X, lx = (int)threadIdx.x % RT_X;
+    const int y = t.y0 + ly, x = t.x0 + lx;
+    const bool inside = y < im.H + im.c && x < im.W + im.c;
     const double ucx = im.aff[0] + im.aff[1] * x + im.aff[2] * y;
     const double ucy = im.aff[3] + im.aff[4] * x + im.aff[5] * y;
     double sum = 0.0;
@@ -312,20 +441,41 @@ __global__ __launch_bounds__(256) void k_render(Plan p, int skip_mode, const apx
     for (int k = kb; k < ke; ++k) {
         const int ci = p.rtile_comps[k];
         const DComp& cp = p.comps[ci];
-        if (y < cp.box[0] || y >= cp.box[2] || x < cp.box[1] || x >= cp.box[3]) continue;
+        const bool inbox = inside && y >= cp.box[0] && y < cp.box[2] && x >= cp.box[1] && x < cp.box[3];
         const CompConst& c = p.cc[ci];
-        if (!c.valid) { sum += __builtin_nan(""); continue; }
+        if (!c.valid) {
+            if (inbox) sum += __builtin_nan("");
+            continue;
+        }
+        if constexpr (SHIFT) if (cp.type == APX_SERSIC) {      // block-uniform
+            stage_halo<1, float>(p, cp, t.y0, t.x0, sh, [&](int ry, int rx, float* v) {
+                const double rcx = im.aff[0] + im.aff[1] * rx + im.aff[2] * ry;
+                const double rcy = im.aff[3] + im.aff[4] * rx + im.aff[5] * ry;
+                v[0] = (float)((double)sersic_pixel(p, c, im, rcx, rcy) * im.area);
+            });
+            __syncthreads();
+            if (inbox) {
+                const double* tp = taps_of(p, ci);
+                sum += (double)tap_sum(sh[0], p.shift_a, ly, lx, tp + SHIFT_NT, tp);
+            }
+            __syncthreads();
+            continue;
+        }
+        if (!inbox) continue;
         if (cp.type == APX_SERSIC)
             sum += (p.mode == APX_MODE_ADAPTIVE ? p.aval[adapt_index(cp, y, x)]
                                                 : (double)sersic_pixel(p, c, im, ucx, ucy)) * im.area;
         else sum += (double)c.F * point_weight(c, y, x);
     }
-    p.S[im.ext_off + (long long)(y + im.c) * im.EW + (x + im.c)] = (float)sum;
+    if (inside) p.S[im.ext_off + (long long)(y + im.c) * im.EW + (x + im.c)] = (float)sum;
 }
 
 hipError_t launch_render_mode(const Plan& p, int skip_mode, const apx_lm_state* lm, hipStream_t st) {
     if (p.n_rtiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_render, dim3(p.n_rtiles), dim3(256), 0, st, p, skip_mode, lm);
+    if (p.shift != APX_SHIFT_NONE)
+        hipLaunchKernelGGL(k_render<true>, dim3(p.n_rtiles), dim3(256), 0, st, p, skip_mode, lm);
+    else
+        hipLaunchKernelGGL(k_render<false>, dim3(p.n_rtiles), dim3(256), 0, st, p, skip_mode, lm);
     return hipGetLastError();
 }
 
@@ -351,13 +501,15 @@ __device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst&
     return sum;
 }
 
+template <bool SHIFT>
 __global__ __launch_bounds__(256) void k_render64(Plan p, int skip_mode, const apx_lm_state* lm) {
+    __shared__ double sh[1][SHIFT ? SH_H * SH_W : 1];
     const RTile t = p.rtiles[blockIdx.x];
     const DImage& im = p.images[t.a];
     if (sub_skipped(p, im.sub, skip_mode, lm)) return;
-    const int y = t.y0 + (int)threadIdx.x / RT_X;
-    const int x = t.x0 + (int)threadIdx.x % RT_X;
-    if (y >= im.H + im.c || x >= im.W + im.c) return;
+    const int ly = (int)threadIdx.x / RT_X, lx = (int)threadIdx.x % RT_X;
+    const int y = t.y0 + ly, x = t.x0 + lx;
+    const bool inside = y < im.H + im.c && x < im.W + im.c;
     const double ucx = im.aff[0] + im.aff[1] * x + im.aff[2] * y;
     const double ucy = im.aff[3] + im.aff[4] * x + im.aff[5] * y;
     double sum = 0.0;
@@ -365,34 +517,57 @@ __global__ __launch_bounds__(256) void k_render64(Plan p, int skip_mode, const a
     for (int k = kb; k < ke; ++k) {
         const int ci = p.rtile_comps[k];
         const DComp& cp = p.comps[ci];
-        if (y < cp.box[0] || y >= cp.box[2] || x < cp.box[1] || x >= cp.box[3]) continue;
+        const bool inbox = inside && y >= cp.box[0] && y < cp.box[2] && x >= cp.box[1] && x < cp.box[3];
         const CompConst& c = p.cc[ci];
-        if (!c.valid) { sum += __builtin_nan(""); continue; }
+        if (!c.valid) {
+            if (inbox) sum += __builtin_nan("");
+            continue;
+        }
+        if constexpr (SHIFT) if (cp.type == APX_SERSIC) {      // block-uniform
+            stage_halo<1, double>(p, cp, t.y0, t.x0, sh, [&](int ry, int rx, double* v) {
+                const double rcx = im.aff[0] + im.aff[1] * rx + im.aff[2] * ry;
+                const double rcy = im.aff[3] + im.aff[4] * rx + im.aff[5] * ry;
+                v[0] = sersic_pixel64(p, c, im, rcx, rcy) * im.area;
+            });
+            __syncthreads();
+            if (inbox) {
+                const double* tp = taps_of(p, ci);
+                sum += tap_sum(sh[0], p.shift_a, ly, lx, tp + SHIFT_NT, tp);
+            }
+            __syncthreads();
+            continue;
+        }
+        if (!inbox) continue;
         if (cp.type == APX_SERSIC)
             sum += (p.mode == APX_MODE_ADAPTIVE ? p.aval[adapt_index(cp, y, x)]
                                                 : sersic_pixel64(p, c, im, ucx, ucy)) * im.area;
         else sum += (double)c.F64 * point_weight(c, y, x);
     }
-    p.S64[im.ext_off + (long long)(y + im.c) * im.EW + (x + im.c)] = sum;
+    if (inside) p.S64[im.ext_off + (long long)(y + im.c) * im.EW + (x + im.c)] = sum;
 }
 
 hipError_t launch_render64(const Plan& p, int skip_mode, const apx_lm_state* lm, hipStream_t st) {
     if (p.n_rtiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_render64, dim3(p.n_rtiles), dim3(256), 0, st, p, skip_mode, lm);
+    if (p.shift != APX_SHIFT_NONE)
+        hipLaunchKernelGGL(k_render64<true>, dim3(p.n_rtiles), dim3(256), 0, st, p, skip_mode, lm);
+    else
+        hipLaunchKernelGGL(k_render64<false>, dim3(p.n_rtiles), dim3(256), 0, st, p, skip_mode, lm);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ derivative images
 // D[col] over the group's input box: the pixel-integrated derivative of each free
 // parameter of each component of the group (pre-convolution).
+template <bool SHIFT>
 __global__ __launch_bounds__(256) void k_deriv(Plan p, const apx_lm_state* lm) {
+    __shared__ float sh[5][SHIFT ? SH_H * SH_W : 1];
     const RTile t = p.gtiles[blockIdx.x];
     const DGroup& gr = p.groups[t.a];
     if (lm && lm[gr.sub].need_jac == 0) return;
     const DImage& im = p.images[gr.image];
-    const int ly = t.y0 + (int)threadIdx.x / RT_X;
-    const int lx = t.x0 + (int)threadIdx.x % RT_X;
-    if (ly >= gr.ih || lx >= gr.iw) return;
+    const int ty = (int)threadIdx.x / RT_X, tx = (int)threadIdx.x % RT_X;
+    const int ly = t.y0 + ty, lx = t.x0 + tx;
+    const bool inside = ly < gr.ih && lx < gr.iw;
     const int y = gr.iy0 + ly, x = gr.ix0 + lx;
     const double ucx = im.aff[0] + im.aff[1] * x + im.aff[2] * y;
     const double ucy = im.aff[3] + im.aff[4] * x + im.aff[5] * y;
@@ -402,6 +577,15 @@ __global__ __launch_bounds__(256) void k_deriv(Plan p, const apx_lm_state* lm) {
         const int ci = p.group_comps[k];
         const DComp& cp = p.comps[ci];
         const CompConst& c = p.cc[ci];
+        if constexpr (SHIFT) if (cp.type == APX_SERSIC) {      // block-uniform
+            float acc[7];
+            shifted_derivs(p, ci, c, cp, im, gr.iy0 + t.y0, gr.ix0 + t.x0, ty, tx, inside, sh, acc);
+            if (inside)
+                for (int q = 0; q < 7; ++q)
+                    if (cp.col[q] >= 0) Dg[cp.col[q] * plane] = acc[q];
+            continue;
+        }
+        if (!inside) continue;
         if (cp.type == APX_SERSIC) {
             float acc[7];
             sersic_pixel_grad(p, c, im, cp, y, x, ucx, ucy, acc);
@@ -416,7 +600,10 @@ __global__ __launch_bounds__(256) void k_deriv(Plan p, const apx_lm_state* lm) {
 
 hipError_t launch_deriv(const Plan& p, const apx_lm_state* lm, hipStream_t st) {
     if (p.n_gtiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_deriv, dim3(p.n_gtiles), dim3(256), 0, st, p, lm);
+    if (p.shift != APX_SHIFT_NONE)
+        hipLaunchKernelGGL(k_deriv<true>, dim3(p.n_gtiles), dim3(256), 0, st, p, lm);
+    else
+        hipLaunchKernelGGL(k_deriv<false>, dim3(p.n_gtiles), dim3(256), 0, st, p, lm);
     return hipGetLastError();
 }
 
@@ -427,8 +614,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // grad_part[col][tile] = sum over the tile of Abar * dS/dtheta_col (recomputed).
+template <bool SHIFT>
 __global__ __launch_bounds__(256) void k_grad_tiles(Plan p) {
     __shared__ double red[4][7];
+    __shared__ float sh[5][SHIFT ? SH_H * SH_W : 1];
     const RTile t = p.gtiles[blockIdx.x];
     const DGroup& gr = p.groups[t.a];
     const DImage& im = p.images[gr.image];
@@ -447,7 +636,12 @@ __global__ __launch_bounds__(256) void k_grad_tiles(Plan p) {
         const DComp& cp = p.comps[ci];
         const CompConst& c = p.cc[ci];
         double v[7];
-        if (cp.type == APX_SERSIC) {
+        if (SHIFT && cp.type == APX_SERSIC) {      // block-uniform
+            float acc[7];
+            if constexpr (SHIFT)
+                shifted_derivs(p, ci, c, cp, im, gr.iy0 + t.y0, gr.ix0 + t.x0, ly - t.y0, lx - t.x0, inside, sh, acc);
+            for (int q = 0; q < 7; ++q) v[q] = (double)acc[q] * (double)abar;
+        } else if (cp.type == APX_SERSIC) {
             float acc[7];
             if (inside) sersic_pixel_grad(p, c, im, cp, y, x, ucx, ucy, acc);
             else for (int q = 0; q < 7; ++q) acc[q] = 0.f;
@@ -473,7 +667,10 @@ __global__ __launch_bounds__(256) void k_grad_tiles(Plan p) {
 
 hipError_t launch_grad_tiles(const Plan& p, hipStream_t st) {
     if (p.n_gtiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_tiles, dim3(p.n_gtiles), dim3(256), 0, st, p);
+    if (p.shift != APX_SHIFT_NONE)
+        hipLaunchKernelGGL(k_grad_tiles<true>, dim3(p.n_gtiles), dim3(256), 0, st, p);
+    else
+        hipLaunchKernelGGL(k_grad_tiles<false>, dim3(p.n_gtiles), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 

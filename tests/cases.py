@@ -225,3 +225,37 @@ def superres(U=2, H=38, W=44, seed=140, aff=None, P=11, fit=False):
     spec["noise"] = [np.random.default_rng(seed + 1).standard_normal((H, W))]
     spec["theta_init"] = synth.perturb(spec["theta_true"], spec["kinds"], spec["re_of"], np.random.default_rng(seed + 2))
     return with_data(spec)
+
+
+def recentred_blend(method, a=3):
+    """The ragged 75 x 93 blend of `small_blend` (partial windows, point sources, asymmetric
+    9 x 9 PSF, s = 3 within 2 Re) with sub-pixel re-centring of its Sersics."""
+    rng = np.random.default_rng(21)
+    spec = synth.blend(seed_id=102, H=75, W=93, n_sersic=3, n_point=4, P=9,
+                       psf=synth.asymmetric_psf(9, rng))
+    spec["comps"][1]["box"] = (5, -4, 60, 70)
+    spec["comps"][2]["box"] = (-4, 20, 79, 97)
+    return with_data(synth.with_recentring(spec, method, a))
+
+
+def recentred_affine_pair(method=synth.SHIFT_LANCZOS, a=3):
+    """`affine_pair` (two rotated, scaled images, tied shapes, Gauss-Legendre 4 x 4) with
+    re-centring: each image moves each Sersic to its own nearest pixel centre."""
+    return with_data(synth.with_recentring(affine_pair(), method, a))
+
+
+def recentred_fft(method=synth.SHIFT_LANCZOS, a=3):
+    """`fft_blend` (P = 25, FFT-mode convolution) with re-centring."""
+    return with_data(synth.with_recentring(fft_blend(), method, a))
+
+
+def recentred_live_psf(method=synth.SHIFT_LANCZOS, a=2):
+    """`live_psf_small` (live Moffat PSF with free n, R_d) with re-centring."""
+    return with_data(synth.with_recentring(live_psf_small(), method, a))
+
+
+def recentred_fit(method=synth.SHIFT_LANCZOS, a=3):
+    """A 64 x 70 blend of three bright Sersics, two point sources and the sky (P = 9) that
+    the LM settles, with re-centring."""
+    spec = synth.blend(seed_id=160, H=64, W=70, n_sersic=3, n_point=2, P=9, logie_range=(0.5, 1.5))
+    return with_data(synth.with_recentring(spec, method, a))

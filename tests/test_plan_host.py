@@ -146,3 +146,39 @@ def test_unknown_conv_mode_is_rejected(apx):
     spec["conv_mode"] = 7
     with pytest.raises(apx.ApxError):
         apx.Plan(spec)
+
+
+@pytest.mark.parametrize("rc,up,mode,status", [
+    ({"method": 3, "a": 3}, 1, 1, -1),             # unknown re-centring method
+    ({"method": 2, "a": 1}, 1, 1, -5),             # Lanczos order below 2
+    ({"method": 2, "a": 6}, 1, 1, -5),             # Lanczos order above the table
+    ({"method": 1, "a": 0}, 1, 2, -5),             # with adaptive integration
+    ({"method": 2, "a": 3}, 2, 1, -5),             # with a higher-resolution PSF
+])
+def test_recentring_descriptors(apx, rc, up, mode, status):
+    spec = copy.deepcopy(_small())
+    spec["recentre"] = rc
+    spec["sampling"] = dict(s=3, rule=0, mode=mode, k=2.0 if mode == 1 else 0.01)
+    if up > 1:
+        spec = synth.with_psf_upsampling(spec, up, 9)
+    with pytest.raises(apx.ApxError) as e:
+        apx.Plan(spec)
+    assert e.value.status == status
+
+
+def test_recentring_grows_windows_by_the_taps(apx):
+    """A re-centred Sersic's shifted image reaches a pixels beyond where it is sampled:
+    its Jacobian output box grows by a on every side (clipped to the image)."""
+    base = _small()
+    win = (8, 10, 20, 30)                         # inside the 40 x 52 image, away from edges
+    for c in base["comps"]:
+        if c["type"] == 0:
+            c["box"] = win
+    n0 = apx.Plan(base).n_jac
+    for rc, a in [({"method": 1, "a": 0}, 1), ({"method": 2, "a": 3}, 3), ({"method": 2, "a": 5}, 5)]:
+        spec = copy.deepcopy(base)
+        spec["recentre"] = rc
+        n = apx.Plan(spec).n_jac
+        h, w = win[2] - win[0] + 6, win[3] - win[1] + 6          # output box: window + c
+        grown = min(40, win[2] + 3 + a) - max(0, win[0] - 3 - a), min(52, win[3] + 3 + a) - max(0, win[1] - 3 - a)
+        assert n - n0 == 14 * (grown[0] * grown[1] - h * w)
