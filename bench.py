@@ -318,6 +318,13 @@ def run_superres(args, torch, apx, synth):
                            "pixels, 191 params")
 
 
+def run_recentre(args, torch, apx, synth):
+    spec = synth.with_recentring(synth.blend(), synth.SHIFT_LANCZOS, 3)
+    return run_lm_workload(args, torch, apx, synth, spec, "recentre",
+                           "512x512, 50 Sersic + 200 point sources + sky, Moffat 25x25, Sersics sampled at "
+                           "the nearest pixel centre and moved back by Lanczos-3 interpolation, 551 params")
+
+
 def run_adaptive(args, torch, apx, synth):
     spec = synth.blend(mode=synth.MODE_ADAPTIVE, k_re=1e-2)
     return run_lm_workload(args, torch, apx, synth, spec, "adaptive",
@@ -389,7 +396,7 @@ def run_hmc(args, torch, apx, synth):
 
 OTHER_WORKLOADS = {"cutouts": run_cutouts, "field": run_field, "multiband": run_multiband,
                    "single": run_single, "livepsf": run_livepsf, "adaptive": run_adaptive,
-                   "hmc": run_hmc, "superres": run_superres}
+                   "hmc": run_hmc, "superres": run_superres, "recentre": run_recentre}
 
 
 def tile_choice(prob):
@@ -453,7 +460,7 @@ def main():
                     help="PSF convolution mode: direct (default) or FFT tiles for P >= 15")
     ap.add_argument("--workload", default="blend",
                     choices=["blend", "cutouts", "field", "multiband", "single", "livepsf", "adaptive", "hmc",
-                             "superres"],
+                             "superres", "recentre"],
                     help="blend (default, the headline line); the others print their own line")
     args = ap.parse_args()
     CONV_MODE[0] = args.conv

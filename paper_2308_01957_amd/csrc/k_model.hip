@@ -353,11 +353,14 @@ __device__ __forceinline__ double point_weight(const CompConst& c, int y, int x)
 // the sampled window sbox), then every pixel sums its (2a+1)^2 taps from LDS.
 constexpr int SH_H = RT_Y + 2 * APX_SHIFT_MAX_A, SH_W = RT_X + 2 * APX_SHIFT_MAX_A;
 
-// Stage NPL planes of f(ry, rx, out[NPL]) over the grown tile: sh[q][hy * (RT_X + 2a) + hx].
+// Stage NPL planes of f(ry, rx, out[NPL]) over the grown tile, sh[q][hy * (RT_X + 2a) + hx],
+// and the component's taps into tw (wx, wy, dwx, dwy; SHIFT_NT each).  The caller
+// synchronises before reading them.
 template <int NPL, typename T, typename F>
-__device__ __forceinline__ void stage_halo(const Plan& p, const DComp& cp, int y0, int x0, T (*sh)[SH_H * SH_W],
-                                           F&& f) {
+__device__ __forceinline__ void stage_halo(const Plan& p, int ci, const DComp& cp, int y0, int x0,
+                                           T (*sh)[SH_H * SH_W], T* tw, F&& f) {
     const int a = p.shift_a, HW = RT_X + 2 * a, n = (RT_Y + 2 * a) * HW;
+    if (threadIdx.x < STAP_STRIDE) tw[threadIdx.x] = (T)p.stap[(long long)ci * STAP_STRIDE + threadIdx.x];
     for (int e = (int)threadIdx.x; e < n; e += 256) {
         const int hy = e / HW, hx = e - hy * HW;
         const int ry = y0 - a + hy, rx = x0 - a + hx;
@@ -368,36 +371,44 @@ __device__ __forceinline__ void stage_halo(const Plan& p, const DComp& cp, int y
     }
 }
 
-// sum_t wy[ty] wx[tx] plane(ly - ty, lx - tx) for the pixel (ly, lx) of the tile; the taps
-// (same for the whole block) are read from the component's tap table.
-template <typename T>
-__device__ __forceinline__ T tap_sum(const T* plane, int a, int ly, int lx, const double* wy,
-                                     const double* wx) {
-    const int HW = RT_X + 2 * a;
+// sum_t wy[ty] wx[tx] plane(ly - ty, lx - tx) for the pixel (ly, lx) of the tile (taps in
+// LDS, the same for every thread); unrolled per half-width A.
+template <int A, typename T>
+__device__ __forceinline__ T tap_sum_a(const T* plane, int ly, int lx, const T* wy, const T* wx) {
+    constexpr int HW = RT_X + 2 * A;
+    const T* base = plane + (ly + 2 * A) * HW + lx + 2 * A;
     T out = (T)0;
-    for (int jy = 0; jy <= 2 * a; ++jy) {
-        const T* row = plane + (ly + 2 * a - jy) * HW + lx + 2 * a;
+#pragma unroll
+    for (int jy = 0; jy <= 2 * A; ++jy) {
+        const T* row = base - jy * HW;
         T acc = (T)0;
-        for (int jx = 0; jx <= 2 * a; ++jx) acc = fma((T)wx[jx], row[-jx], acc);
-        out = fma((T)wy[jy], acc, out);
+#pragma unroll
+        for (int jx = 0; jx <= 2 * A; ++jx) acc = fma(wx[jx], row[-jx], acc);
+        out = fma(wy[jy], acc, out);
     }
     return out;
 }
 
-// tap table of component ci: wx, wy, dwx, dwy (SHIFT_NT each)
-__device__ __forceinline__ const double* taps_of(const Plan& p, int ci) {
-    return p.stap + (long long)ci * STAP_STRIDE;
+template <typename T>
+__device__ __forceinline__ T tap_sum(const T* plane, int a, int ly, int lx, const T* wy, const T* wx) {
+    switch (a) {
+        case 1: return tap_sum_a<1>(plane, ly, lx, wy, wx);
+        case 2: return tap_sum_a<2>(plane, ly, lx, wy, wx);
+        case 3: return tap_sum_a<3>(plane, ly, lx, wy, wx);
+        case 4: return tap_sum_a<4>(plane, ly, lx, wy, wx);
+        default: return tap_sum_a<5>(plane, ly, lx, wy, wx);
+    }
 }
 
-// The 7 pre-convolution derivative values (before the area factor is applied: it is in
-// the staged planes) of a re-centred Sersic at pixel (ly, lx) of a tile whose grown
-// origin is (y0 - a, x0 - a): d/d(q, PA, n, Re, log Ie) are T * dS'/dtheta; x0 and y0 move
-// only delta, d/d x0 = inv1 (dT/d delta_x * S') + inv4 (dT/d delta_y * S') (and inv2,
-// inv5 for y0), S' = (d/d log Ie plane) / ln 10.  Every thread of the block calls it.
+// The 7 pre-convolution derivative values (area included: it is in the staged planes) of
+// a re-centred Sersic at pixel (ly, lx) of a tile whose origin is (y0, x0):
+// d/d(q, PA, n, Re, log Ie) are T * dS'/dtheta; x0 and y0 move only delta, so
+// d/d x0 = inv1 (dT/d delta_x * S') + inv4 (dT/d delta_y * S') (inv2, inv5 for y0), with
+// S' = (d/d log Ie plane) / ln 10.  Every thread of the block calls it.
 __device__ void shifted_derivs(const Plan& p, int ci, const CompConst& c, const DComp& cp, const DImage& im,
                                int y0, int x0, int ly, int lx, bool want, float (*sh)[SH_H * SH_W],
-                               float out[7]) {
-    stage_halo<5, float>(p, cp, y0, x0, sh, [&](int ry, int rx, float* v) {
+                               float* tw, float out[7]) {
+    stage_halo<5, float>(p, ci, cp, y0, x0, sh, tw, [&](int ry, int rx, float* v) {
         const double ucx = im.aff[0] + im.aff[1] * rx + im.aff[2] * ry;
         const double ucy = im.aff[3] + im.aff[4] * rx + im.aff[5] * ry;
         float acc[7];
@@ -408,8 +419,7 @@ __device__ void shifted_derivs(const Plan& p, int ci, const CompConst& c, const 
     __syncthreads();
     for (int q = 0; q < 7; ++q) out[q] = 0.f;
     if (want) {
-        const double* tp = taps_of(p, ci);
-        const double *wx = tp, *wy = tp + SHIFT_NT, *dwx = tp + 2 * SHIFT_NT, *dwy = tp + 3 * SHIFT_NT;
+        const float *wx = tw, *wy = tw + SHIFT_NT, *dwx = tw + 2 * SHIFT_NT, *dwy = tw + 3 * SHIFT_NT;
         const int a = p.shift_a;
         for (int q = 0; q < 5; ++q) out[q + 2] = tap_sum(sh[q], a, ly, lx, wy, wx);
         const float inv_ln10 = 1.f / LN10F;
@@ -428,6 +438,7 @@ __device__ void shifted_derivs(const Plan& p, int ci, const CompConst& c, const 
 template <bool SHIFT>
 __global__ __launch_bounds__(256) void k_render(Plan p, int skip_mode, const apx_lm_state* lm) {
     __shared__ float sh[1][SHIFT ? SH_H * SH_W : 1];
+    __shared__ float tw[SHIFT ? STAP_STRIDE : 1];
     const RTile t = p.rtiles[blockIdx.x];
     const DImage& im = p.images[t.a];
     if (sub_skipped(p, im.sub, skip_mode, lm)) return;
@@ -448,16 +459,13 @@ __global__ __launch_bounds__(256) void k_render(Plan p, int skip_mode, const apx
             continue;
         }
         if constexpr (SHIFT) if (cp.type == APX_SERSIC) {      // block-uniform
-            stage_halo<1, float>(p, cp, t.y0, t.x0, sh, [&](int ry, int rx, float* v) {
+            stage_halo<1, float>(p, ci, cp, t.y0, t.x0, sh, tw, [&](int ry, int rx, float* v) {
                 const double rcx = im.aff[0] + im.aff[1] * rx + im.aff[2] * ry;
                 const double rcy = im.aff[3] + im.aff[4] * rx + im.aff[5] * ry;
                 v[0] = (float)((double)sersic_pixel(p, c, im, rcx, rcy) * im.area);
             });
             __syncthreads();
-            if (inbox) {
-                const double* tp = taps_of(p, ci);
-                sum += (double)tap_sum(sh[0], p.shift_a, ly, lx, tp + SHIFT_NT, tp);
-            }
+            if (inbox) sum += (double)tap_sum(sh[0], p.shift_a, ly, lx, tw + SHIFT_NT, tw);
             __syncthreads();
             continue;
         }
@@ -504,6 +512,7 @@ __device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst&
 template <bool SHIFT>
 __global__ __launch_bounds__(256) void k_render64(Plan p, int skip_mode, const apx_lm_state* lm) {
     __shared__ double sh[1][SHIFT ? SH_H * SH_W : 1];
+    __shared__ double tw[SHIFT ? STAP_STRIDE : 1];
     const RTile t = p.rtiles[blockIdx.x];
     const DImage& im = p.images[t.a];
     if (sub_skipped(p, im.sub, skip_mode, lm)) return;
@@ -524,16 +533,13 @@ __global__ __launch_bounds__(256) void k_render64(Plan p, int skip_mode, const a
             continue;
         }
         if constexpr (SHIFT) if (cp.type == APX_SERSIC) {      // block-uniform
-            stage_halo<1, double>(p, cp, t.y0, t.x0, sh, [&](int ry, int rx, double* v) {
+            stage_halo<1, double>(p, ci, cp, t.y0, t.x0, sh, tw, [&](int ry, int rx, double* v) {
                 const double rcx = im.aff[0] + im.aff[1] * rx + im.aff[2] * ry;
                 const double rcy = im.aff[3] + im.aff[4] * rx + im.aff[5] * ry;
                 v[0] = sersic_pixel64(p, c, im, rcx, rcy) * im.area;
             });
             __syncthreads();
-            if (inbox) {
-                const double* tp = taps_of(p, ci);
-                sum += tap_sum(sh[0], p.shift_a, ly, lx, tp + SHIFT_NT, tp);
-            }
+            if (inbox) sum += tap_sum(sh[0], p.shift_a, ly, lx, tw + SHIFT_NT, tw);
             __syncthreads();
             continue;
         }
@@ -561,6 +567,7 @@ hipError_t launch_render64(const Plan& p, int skip_mode, const apx_lm_state* lm,
 template <bool SHIFT>
 __global__ __launch_bounds__(256) void k_deriv(Plan p, const apx_lm_state* lm) {
     __shared__ float sh[5][SHIFT ? SH_H * SH_W : 1];
+    __shared__ float tw[SHIFT ? STAP_STRIDE : 1];
     const RTile t = p.gtiles[blockIdx.x];
     const DGroup& gr = p.groups[t.a];
     if (lm && lm[gr.sub].need_jac == 0) return;
@@ -579,7 +586,7 @@ __global__ __launch_bounds__(256) void k_deriv(Plan p, const apx_lm_state* lm) {
         const CompConst& c = p.cc[ci];
         if constexpr (SHIFT) if (cp.type == APX_SERSIC) {      // block-uniform
             float acc[7];
-            shifted_derivs(p, ci, c, cp, im, gr.iy0 + t.y0, gr.ix0 + t.x0, ty, tx, inside, sh, acc);
+            shifted_derivs(p, ci, c, cp, im, gr.iy0 + t.y0, gr.ix0 + t.x0, ty, tx, inside, sh, tw, acc);
             if (inside)
                 for (int q = 0; q < 7; ++q)
                     if (cp.col[q] >= 0) Dg[cp.col[q] * plane] = acc[q];
@@ -618,6 +625,7 @@ template <bool SHIFT>
 __global__ __launch_bounds__(256) void k_grad_tiles(Plan p) {
     __shared__ double red[4][7];
     __shared__ float sh[5][SHIFT ? SH_H * SH_W : 1];
+    __shared__ float tw[SHIFT ? STAP_STRIDE : 1];
     const RTile t = p.gtiles[blockIdx.x];
     const DGroup& gr = p.groups[t.a];
     const DImage& im = p.images[gr.image];
@@ -639,7 +647,8 @@ __global__ __launch_bounds__(256) void k_grad_tiles(Plan p) {
         if (SHIFT && cp.type == APX_SERSIC) {      // block-uniform
             float acc[7];
             if constexpr (SHIFT)
-                shifted_derivs(p, ci, c, cp, im, gr.iy0 + t.y0, gr.ix0 + t.x0, ly - t.y0, lx - t.x0, inside, sh, acc);
+                shifted_derivs(p, ci, c, cp, im, gr.iy0 + t.y0, gr.ix0 + t.x0, ly - t.y0, lx - t.x0, inside, sh, tw,
+                               acc);
             for (int q = 0; q < 7; ++q) v[q] = (double)acc[q] * (double)abar;
         } else if (cp.type == APX_SERSIC) {
             float acc[7];
