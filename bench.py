@@ -410,9 +410,11 @@ def prob_tile_shapes():
     return apx.TILE_SHAPES
 
 
-def counted_traffic(kernel):
+def counted_traffic(kernel, jac_tiles):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when there is none or the kernel's sources changed after the counters were taken."""
+    when there is none, the kernel's sources changed after the counters were taken, or this
+    run's Jacobian jobs took other tile shapes than the counted run's (the halo re-reads, and
+    so the bytes, depend on the shape)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "conv_jcol_blend512_hbm_counters.md")
     if not os.path.exists(path):
@@ -428,6 +430,8 @@ def counted_traffic(kernel):
     for src in kv["sources"].split():
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if h.hexdigest() != kv.get("sources_sha256"):
+        return None
+    if "jacobian_tiles" not in kv or json.loads(kv["jacobian_tiles"]) != jac_tiles:
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -592,7 +596,8 @@ def main():
         "mpix_per_s": mpix,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": counted_traffic(f"k_conv<{P_psf},JCOL>"), "traffic_unit": "bytes/launch",
+                     "traffic": counted_traffic(f"k_conv<{P_psf},JCOL>", tile_choice(prob)["jacobian"]),
+                     "traffic_unit": "bytes/launch",
                      "kernel": f"k_conv<{P_psf},JCOL>",
                      "avg_launch_ms": avg_ms, "launches_with_work": j_phases,
                      "launches_total": jcol_launches,
