@@ -345,6 +345,27 @@ __device__ __forceinline__ double point_weight(const CompConst& c, int y, int x)
     return wx * wy;
 }
 
+// The same pixel integral in double precision throughout (FP64 log2/exp2), for the
+// objective path: chi^2 differences of the LM gain ratio are resolved far below FP32
+// rounding.
+__device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst& c, const DImage& im,
+                                                 double ucx, double ucy) {
+    const double dxc = ucx - c.x0, dyc = ucy - c.y0;
+    if (p.mode == APX_MODE_WITHIN_K_RE && !within_kre(c, ucx, ucy)) return sersic_I64(c, dxc, dyc);
+    double sum = 0.0;
+    for (int ky = 0; ky < p.s; ++ky) {
+        const double oy = p.node_od[ky];
+        double row = 0.0;
+        for (int kx = 0; kx < p.s; ++kx) {
+            const double ox = p.node_od[kx];
+            row += p.node_wd[kx] * sersic_I64(c, dxc + im.aff[1] * ox + im.aff[2] * oy,
+                                              dyc + im.aff[4] * ox + im.aff[5] * oy);
+        }
+        sum += p.node_wd[ky] * row;
+    }
+    return sum;
+}
+
 // ------------------------------------------------------------- re-centred tiles
 // A re-centred Sersic (§2.1.3) enters the pre-convolution grid as T * S': S' sampled with
 // the centre at the nearest pixel centre, T the separable interpolation taps (the shift
@@ -431,6 +452,23 @@ __device__ void shifted_derivs(const Plan& p, int ci, const CompConst& c, const 
     __syncthreads();
 }
 
+// Pixel value T * S' (area included) of a re-centred Sersic at pixel (ly, lx) of the render
+// tile with origin (y0, x0); 0 where !want.  Every thread of the block calls it.
+template <typename T>
+__device__ T shifted_pixel(const Plan& p, int ci, const CompConst& c, const DComp& cp, const DImage& im, int y0,
+                           int x0, int ly, int lx, bool want, T (*sh)[SH_H * SH_W], T* tw) {
+    stage_halo<1, T>(p, ci, cp, y0, x0, sh, tw, [&](int ry, int rx, T* v) {
+        const double rcx = im.aff[0] + im.aff[1] * rx + im.aff[2] * ry;
+        const double rcy = im.aff[3] + im.aff[4] * rx + im.aff[5] * ry;
+        if constexpr (sizeof(T) == 8) v[0] = sersic_pixel64(p, c, im, rcx, rcy) * im.area;
+        else v[0] = (float)((double)sersic_pixel(p, c, im, rcx, rcy) * im.area);
+    });
+    __syncthreads();
+    const T out = want ? tap_sum(sh[0], p.shift_a, ly, lx, tw + SHIFT_NT, tw) : (T)0;
+    __syncthreads();
+    return out;
+}
+
 // ----------------------------------------------------------------------- render
 // S (extended grid) = sum of all components whose window holds the pixel.
 // SHIFT: the problem re-centres its Sersics (a separate instantiation keeps the plain
@@ -458,15 +496,8 @@ __global__ __launch_bounds__(256) void k_render(Plan p, int skip_mode, const apx
             if (inbox) sum += __builtin_nan("");
             continue;
         }
-        if constexpr (SHIFT) if (cp.type == APX_SERSIC) {      // block-uniform
-            stage_halo<1, float>(p, ci, cp, t.y0, t.x0, sh, tw, [&](int ry, int rx, float* v) {
-                const double rcx = im.aff[0] + im.aff[1] * rx + im.aff[2] * ry;
-                const double rcy = im.aff[3] + im.aff[4] * rx + im.aff[5] * ry;
-                v[0] = (float)((double)sersic_pixel(p, c, im, rcx, rcy) * im.area);
-            });
-            __syncthreads();
-            if (inbox) sum += (double)tap_sum(sh[0], p.shift_a, ly, lx, tw + SHIFT_NT, tw);
-            __syncthreads();
+        if (SHIFT && cp.type == APX_SERSIC) {      // block-uniform
+            if constexpr (SHIFT) sum += (double)shifted_pixel<float>(p, ci, c, cp, im, t.y0, t.x0, ly, lx, inbox, sh, tw);
             continue;
         }
         if (!inbox) continue;
@@ -488,27 +519,7 @@ hipError_t launch_render_mode(const Plan& p, int skip_mode, const apx_lm_state* 
 }
 
 // ------------------------------------------------------------- FP64 render
-// The same pixel integral in double precision throughout (FP64 log2/exp2), for the
-// objective path: chi^2 differences of the LM gain ratio are resolved far below FP32
-// rounding.
-__device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst& c, const DImage& im,
-                                                 double ucx, double ucy) {
-    const double dxc = ucx - c.x0, dyc = ucy - c.y0;
-    if (p.mode == APX_MODE_WITHIN_K_RE && !within_kre(c, ucx, ucy)) return sersic_I64(c, dxc, dyc);
-    double sum = 0.0;
-    for (int ky = 0; ky < p.s; ++ky) {
-        const double oy = p.node_od[ky];
-        double row = 0.0;
-        for (int kx = 0; kx < p.s; ++kx) {
-            const double ox = p.node_od[kx];
-            row += p.node_wd[kx] * sersic_I64(c, dxc + im.aff[1] * ox + im.aff[2] * oy,
-                                              dyc + im.aff[4] * ox + im.aff[5] * oy);
-        }
-        sum += p.node_wd[ky] * row;
-    }
-    return sum;
-}
-
+// S64 (extended grid, FP64): the objective path's render.
 template <bool SHIFT>
 __global__ __launch_bounds__(256) void k_render64(Plan p, int skip_mode, const apx_lm_state* lm) {
     __shared__ double sh[1][SHIFT ? SH_H * SH_W : 1];
@@ -532,15 +543,8 @@ __global__ __launch_bounds__(256) void k_render64(Plan p, int skip_mode, const a
             if (inbox) sum += __builtin_nan("");
             continue;
         }
-        if constexpr (SHIFT) if (cp.type == APX_SERSIC) {      // block-uniform
-            stage_halo<1, double>(p, ci, cp, t.y0, t.x0, sh, tw, [&](int ry, int rx, double* v) {
-                const double rcx = im.aff[0] + im.aff[1] * rx + im.aff[2] * ry;
-                const double rcy = im.aff[3] + im.aff[4] * rx + im.aff[5] * ry;
-                v[0] = sersic_pixel64(p, c, im, rcx, rcy) * im.area;
-            });
-            __syncthreads();
-            if (inbox) sum += tap_sum(sh[0], p.shift_a, ly, lx, tw + SHIFT_NT, tw);
-            __syncthreads();
+        if (SHIFT && cp.type == APX_SERSIC) {      // block-uniform
+            if constexpr (SHIFT) sum += shifted_pixel<double>(p, ci, c, cp, im, t.y0, t.x0, ly, lx, inbox, sh, tw);
             continue;
         }
         if (!inbox) continue;
@@ -584,9 +588,10 @@ __global__ __launch_bounds__(256) void k_deriv(Plan p, const apx_lm_state* lm) {
         const int ci = p.group_comps[k];
         const DComp& cp = p.comps[ci];
         const CompConst& c = p.cc[ci];
-        if constexpr (SHIFT) if (cp.type == APX_SERSIC) {      // block-uniform
-            float acc[7];
-            shifted_derivs(p, ci, c, cp, im, gr.iy0 + t.y0, gr.ix0 + t.x0, ty, tx, inside, sh, tw, acc);
+        if (SHIFT && cp.type == APX_SERSIC) {      // block-uniform
+            float acc[7] = {};
+            if constexpr (SHIFT)
+                shifted_derivs(p, ci, c, cp, im, gr.iy0 + t.y0, gr.ix0 + t.x0, ty, tx, inside, sh, tw, acc);
             if (inside)
                 for (int q = 0; q < 7; ++q)
                     if (cp.col[q] >= 0) Dg[cp.col[q] * plane] = acc[q];
@@ -645,7 +650,7 @@ __global__ __launch_bounds__(256) void k_grad_tiles(Plan p) {
         const CompConst& c = p.cc[ci];
         double v[7];
         if (SHIFT && cp.type == APX_SERSIC) {      // block-uniform
-            float acc[7];
+            float acc[7] = {};
             if constexpr (SHIFT)
                 shifted_derivs(p, ci, c, cp, im, gr.iy0 + t.y0, gr.ix0 + t.x0, ly - t.y0, lx - t.x0, inside, sh, tw,
                                acc);

@@ -186,3 +186,66 @@ def test_all_parameters_fixed(apx):
     c2o = float(np.sum(c2o)) if np.ndim(c2o) else float(c2o)
     assert math.isclose(c2, c2o, rel_tol=1e-6)
     P.check()
+
+
+def test_nonfinite_data_or_weight_is_reported(apx):
+    """A NaN in the data or an infinite weight makes chi^2 non-finite: the call itself
+    succeeds (nothing is checked on the host inside the hot path) and the device flag
+    surfaces as APX_E_NONFINITE at the next check; the flag is then cleared."""
+    psf = synth.gaussian_psf(7, 1.2)
+    spec = _spec("nonfinite", 26, 30, psf, [[13.0, 12.5, 0.6, 1.0, 2.0, 3.5, 0.2]])
+    P = apx.Problem(spec)
+    th = spec["theta_init"]
+    d0, w0 = spec["data"][0].copy(), spec["weight"][0].copy()
+    for d_, w_ in [(d0.copy(), w0), (d0, w0.copy())]:
+        if d_ is not d0:
+            d_[5, 7] = np.nan
+        else:
+            w_[11, 3] = np.inf
+        P.chi2(th, P.pixels([d_]), P.pixels([w_]))
+        with pytest.raises(apx.ApxError) as e:
+            P.check()
+        assert e.value.status == apx.APX_E_NONFINITE
+    c2 = float(P.chi2(th, P.pixels([d0]), P.pixels([w0])).cpu()[0])
+    assert math.isfinite(c2)
+    P.check()
+
+
+def test_zero_effect_parameters_never_stop_the_lm(apx):
+    """A galaxy whose window misses the image has all-zero Jacobian columns, so J^T W J is
+    singular; the damping floor (D_kk >= 1e-12 max D) keeps A + lambda D positive definite,
+    the LM runs without error, the dead parameters do not move and the live galaxy's fit
+    matches the oracle's."""
+    psf = synth.gaussian_psf(7, 1.2)
+    gals = [[12.3, 10.8, 0.7, 0.5, 1.5, 3.0, 0.9], [60.0, 70.0, 0.7, 0.5, 1.5, 3.0, 0.4]]
+    boxes = [synth.full_window(24, 28, 7), (80, 90, 100, 110)]
+    spec = _spec("dead_params", 24, 28, psf, gals, boxes=boxes)
+    th0 = spec["theta_true"].copy()
+    th0[:7] = synth.perturb(th0, spec["kinds"], spec["re_of"], np.random.default_rng(93))[:7]
+    P = apx.Problem(spec)
+    d, w = P.pixels(spec["data"]), P.pixels(spec["weight"])
+    th, st = P.lm_init(th0, d, w)
+    P.lm_run(25, d, w, th, st)
+    P.check()
+    tg = th.cpu().numpy()
+    assert np.array_equal(tg[7:14], th0[7:14])
+    to, _ = oracle.lm_fit(spec, th0, spec["data"], spec["weight"], 25)
+    live = list(range(7)) + [14]
+    assert np.all(np.abs(tg[live] - to[live]) <= 1e-6 * (np.abs(to[live]) + spec["scale"][live]))
+    assert int(P.lm_state(st)["n_accept"][0]) > 0
+
+
+def test_masked_image_lm_step_is_a_no_op(apx):
+    """w = 0 everywhere: A = 0 and D = 0, so every Cholesky attempt fails; the step is
+    dropped (theta unchanged, lambda raised, retries counted) and no error is raised."""
+    psf = synth.gaussian_psf(7, 1.2)
+    spec = _spec("masked_lm", 26, 30, psf, [[13.0, 12.5, 0.6, 1.0, 2.0, 3.5, 0.2]])
+    P = apx.Problem(spec)
+    d = P.pixels(spec["data"])
+    w = P.pixels([np.zeros_like(spec["weight"][0])])
+    th, st = P.lm_init(spec["theta_init"], d, w)
+    P.lm_run(2, d, w, th, st)
+    P.check()
+    assert np.array_equal(th.cpu().numpy(), spec["theta_init"])
+    s = P.lm_state(st)
+    assert int(s["n_accept"][0]) == 0 and int(s["n_chol_retry"][0]) > 0
