@@ -194,7 +194,7 @@ def run_cutouts(args, torch, apx, synth):
         "plain_sample_cutouts": len(sample), "steps": args.steps, "n_gpus": 1,
         "mpix_per_s": mpix,
         "covariance_ms": cov_ms,
-        "fft_mode": fft_mode, "accepted_mean": float(np.mean(stt["n_accept"])),
+        "accepted_mean": float(np.mean(stt["n_accept"])),
         "tile_shapes": tile_choice(prob),
         "config": {"workload": "4096 cutouts, side 32-256 px log-uniform, 1-5 Sersic + sky each, "
                                "Gaussian/Moffat PSF 15-31 px, 3x3 nodes",

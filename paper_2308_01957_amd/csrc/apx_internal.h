@@ -87,6 +87,7 @@ struct DComp {
 struct CompConst {
     double x0, y0;            // Sersic centre (sky frame); point: pixel position
     double cs_d, sn_d, q_d;   // FP64 copies for the within-k-Re test
+    double iq_d;              // 1 / q (FP64 profile)
     double kre;               // k * Re
     double h_d, A_d, B_d;     // t = exp2(g log2 R^2 - h), I = exp2(A - B t)
     double g_d;               // 0.5 / n

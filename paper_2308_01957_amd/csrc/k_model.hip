@@ -89,7 +89,7 @@ __global__ void k_prep(Plan p, const double* __restrict__ theta, int lm_trial) {
         finite = finite && isfinite(v[k]);
     }
     CompConst c;
-    c.x0 = c.y0 = c.cs_d = c.sn_d = c.q_d = c.kre = c.h_d = c.A_d = c.B_d = c.g_d = 0.0;
+    c.x0 = c.y0 = c.cs_d = c.sn_d = c.q_d = c.iq_d = c.kre = c.h_d = c.A_d = c.B_d = c.g_d = 0.0;
     c.cs = c.sn = c.iq = c.g = c.b = c.bp = c.n = c.re = c.q = c.F = 0.f;
     c.pad = 0;
     c.F64 = 0.0;
@@ -106,6 +106,7 @@ __global__ void k_prep(Plan p, const double* __restrict__ theta, int lm_trial) {
             c.cs_d = cos(pa);
             c.sn_d = sin(pa);
             c.q_d = q;
+            c.iq_d = 1.0 / q;
             c.kre = p.k_re * re;
             c.h_d = log2(re) / n;
             c.A_d = lie * 3.3219280948873622 + b * log2e;

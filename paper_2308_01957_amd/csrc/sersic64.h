@@ -8,12 +8,67 @@
 
 namespace apx {
 
+// FP64 2^x and log2(x) for the profile, from their series (a few ulp; the profile needs
+// FP64-level smoothness in theta, not correctly rounded results).
+//   2^x: x = n + f with n the nearest integer (f exact, |f| <= 1/2), 2^f = e^(f ln 2) by its
+//   Taylor series to degree 13 (next term < 5e-18), then scaled by 2^n.  Arguments are
+//   clamped to [-1100, 1100] first (results underflow to 0 / overflow to inf as they
+//   should); NaN propagates.
+//   log2(x), x positive and normal: x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m =
+//   2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...), s = (m - 1) / (m + 1), |s| <= 0.1716, to
+//   s^21 (next term < 3e-17 relative); 1/(m + 1) is the hardware reciprocal refined by two
+//   Newton steps.
+struct Exp2Series {
+    double c[14];
+    constexpr Exp2Series() : c() {
+        c[0] = 1.0;
+        for (int k = 1; k < 14; ++k) c[k] = c[k - 1] * 0.6931471805599453094 / k;
+    }
+};
+struct AtanhSeries {
+    double q[11];
+    constexpr AtanhSeries() : q() {
+        for (int k = 0; k < 11; ++k) q[k] = 1.0 / (2 * k + 1);
+    }
+};
+
+__device__ __forceinline__ double exp2_d(double x) {
+    constexpr Exp2Series S;
+    x = x < -1100.0 ? -1100.0 : (x > 1100.0 ? 1100.0 : x);
+    const double n = rint(x);
+    const double f = x - n;
+    double p = S.c[13];
+#pragma unroll
+    for (int k = 12; k >= 0; --k) p = fma(p, f, S.c[k]);
+    return ldexp(p, (int)n);
+}
+
+__device__ __forceinline__ double log2_d(double x) {
+    constexpr AtanhSeries S;
+    double m = __builtin_amdgcn_frexp_mant(x);          // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(x);
+    if (m < 0.70710678118654752440) {
+        m += m;
+        e -= 1;
+    }
+    const double d = m + 1.0;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    const double s = (m - 1.0) * r;
+    const double z = s * s;
+    double q = S.q[10];
+#pragma unroll
+    for (int k = 9; k >= 0; --k) q = fma(q, z, S.q[k]);
+    return fma(2.0 * s * q, 1.4426950408889634074, (double)e);
+}
+
 __device__ __forceinline__ double sersic_I64(const CompConst& c, double dx, double dy) {
     const double xp = dx * c.cs_d + dy * c.sn_d;
-    const double yq = (-dx * c.sn_d + dy * c.cs_d) / c.q_d;
+    const double yq = (-dx * c.sn_d + dy * c.cs_d) * c.iq_d;
     const double R2 = fmax(xp * xp + yq * yq, 1e-12);
-    const double t = exp2(c.g_d * log2(R2) - c.h_d);
-    return exp2(c.A_d - c.B_d * t);
+    const double t = exp2_d(c.g_d * log2_d(R2) - c.h_d);
+    return exp2_d(c.A_d - c.B_d * t);
 }
 
 // Adds wgt * I and wgt * dI/dtheta_k (k = x0, y0, q, PA, n, Re, log10 Ie) into val, acc.
@@ -21,14 +76,14 @@ __device__ __forceinline__ void sersic_dI64(const CompConst& c, double dx, doubl
                                             double& val, double acc[7]) {
     const double xp = dx * c.cs_d + dy * c.sn_d;
     const double yp = -dx * c.sn_d + dy * c.cs_d;
-    const double iq = 1.0 / c.q_d;
+    const double iq = c.iq_d;
     const double yq = yp * iq;
     double R2 = xp * xp + yq * yq;
     const bool floored = R2 < 1e-12;
     R2 = floored ? 1e-12 : R2;
-    const double lt = c.g_d * log2(R2) - c.h_d;
-    const double t = exp2(lt);
-    const double I = exp2(c.A_d - c.B_d * t) * wgt;
+    const double lt = c.g_d * log2_d(R2) - c.h_d;
+    const double t = exp2_d(lt);
+    const double I = exp2_d(c.A_d - c.B_d * t) * wgt;
     const double inv_n = 2.0 * c.g_d;
     const double b = c.B_d * 0.69314718055994531;   // B = b log2 e
     const double G = floored ? 0.0 : -I * b * t * inv_n / R2;   // (dI/dR) / R

@@ -259,3 +259,19 @@ def recentred_fit(method=synth.SHIFT_LANCZOS, a=3):
     the LM settles, with re-centring."""
     spec = synth.blend(seed_id=160, H=64, W=70, n_sersic=3, n_point=2, P=9, logie_range=(0.5, 1.5))
     return with_data(synth.with_recentring(spec, method, a))
+
+
+def fit_tolerance(spec, theta):
+    """Per-parameter bound for comparing two converged fits at the oracle's optimum theta:
+    1e-6 (|theta_k| + scale_k), or 1e-5 of the posterior width sigma_k =
+    sqrt((J^T W J)^-1)_kk where that is larger.  An FP64 chi^2 of N terms carries ~1e-15
+    relative rounding, so its minimum fixes theta_k only to about sigma_k sqrt(2e-15 chi^2)
+    (1.6e-7 for a cutout's sky with sigma 0.15 at chi^2 = 564); two exact LMs may stop
+    anywhere inside that."""
+    sigma = np.zeros(spec["n_par"])
+    for s, (p0, n) in enumerate(spec["subs"]):
+        if n == 0:
+            continue
+        A, _, _ = oracle.jtwj(spec, theta, spec["data"], spec["weight"], s)
+        sigma[p0:p0 + n] = np.sqrt(np.abs(np.diag(np.linalg.inv(A))))
+    return np.maximum(1e-6 * (np.abs(theta) + spec["scale"]), 1e-5 * sigma)
