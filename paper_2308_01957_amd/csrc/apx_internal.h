@@ -150,6 +150,7 @@ struct LMFlags {
     int trial_bad;            // trial parameters outside the domain
     int skip;                 // 1: sub-problem skips the current render/phase
     int subst_fail;           // a substitution hand-off wait ran out this iteration
+    int rhs_folded;           // the forward substitution ran inside the first factorisation
 };
 
 // Launch-time views of the workspace ----------------------------------------------

@@ -324,9 +324,12 @@ __global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
     if (threadIdx.x == 0) {
         p.lmf[s].chol_fail = 0;
         p.lmf[s].subst_fail = 0;
+        p.lmf[s].rhs_folded = 0;
     }
 }
 
+// M = A + lambda D, and the working right-hand side yvec = J^T W r that the first
+// factorisation attempt turns into y = L^-1 g as it goes.
 __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
     const DSub sb = p.subs[s];
     const int n = sb.n;
@@ -336,15 +339,20 @@ __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
          e += (long long)gridDim.x * blockDim.x) {
         const int i = (int)(e / n), j = (int)(e - (long long)i * n);
         double v = p.A[sb.a_off + e];
-        if (i == j) v += lam * p.Ddiag[sb.p0 + i];
+        if (i == j) {
+            v += lam * p.Ddiag[sb.p0 + i];
+            p.yvec[sb.p0 + i] = p.gvec[sb.p0 + i];
+        }
         p.M[sb.a_off + e] = v;
     }
 }
 
 // Block column k: every workgroup factors the diagonal block (redundantly, blocked on
 // FP64 MFMA); workgroup 0 stores it and reports a failed pivot, workgroup b > 0 solves row
-// block k+b (X L_kk^T = M_rk).
-__global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
+// block k+b (X L_kk^T = M_rk).  With fold, workgroup 0 also finishes block k of the forward
+// substitution: the trailing updates have already taken sum_{c<k} L_kc y_c off the right-
+// hand side, so y_k = L_kk^-1 yvec_k (64 column steps on wave 0, by readlane broadcasts).
+__global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk, int fold) {
     __shared__ double L[CHOL_NB][CHOL_NB + 1];
     __shared__ double X[CHOL_NB][CHOL_NB + 1];
     __shared__ double col[CHOL_NB], invd[CHOL_NB];
@@ -369,6 +377,17 @@ __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk) {
         for (int e = t; e < nb * nb; e += 256) {
             const int i = e / nb, j = e - (e / nb) * nb;
             if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[i][j];
+        }
+        if (fold && t < 64) {
+            double* y = p.yvec + sb.p0 + kb;
+            double yi = t < nb ? y[t] : 0.0;
+#pragma unroll
+            for (int j = 0; j < CHOL_NB; ++j) {
+                const double yj = lane_bcast(yi, j) * invd[j];
+                if (t == j) yi = yj;
+                else if (t > j) yi = fma(-L[t][j], yj, yi);
+            }
+            if (t < nb) y[t] = yi;
         }
         return;
     }
@@ -421,7 +440,10 @@ __device__ void chol_update_block(double* Mg, int n, int ri, int rj, int kc, boo
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, int nblk) {
+// With fold, the workgroup of each diagonal block (i, i) also takes L_ik y_k off row block
+// i of the right-hand side (L_ik is its staged Li; 4 threads per row, 16 products each,
+// summed in a fixed order).
+__global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, int nblk, int fold) {
     __shared__ double Li[CHOL_NB][CHOL_NB + 1], Lj[CHOL_NB][CHOL_NB + 1];
     if (p.lmf[s].chol_fail) return;
     const DSub sb = p.subs[s];
@@ -429,8 +451,22 @@ __global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, in
     int e = blockIdx.x, bi = 0;
     while (e >= bi + 1) { e -= bi + 1; ++bi; }
     const int bj = e;
-    chol_update_block(p.M + sb.a_off, sb.n, (kblk + 1 + bi) * CHOL_NB, (kblk + 1 + bj) * CHOL_NB,
-                      kblk * CHOL_NB, bi == bj, Li, Lj);
+    const int ri = (kblk + 1 + bi) * CHOL_NB, kc = kblk * CHOL_NB;
+    chol_update_block(p.M + sb.a_off, sb.n, ri, (kblk + 1 + bj) * CHOL_NB, kc, bi == bj, Li, Lj);
+    if (fold && bi == bj) {
+        const int n = sb.n, ni = min(CHOL_NB, n - ri), nk = min(CHOL_NB, n - kc);
+        const int r = threadIdx.x >> 2, qq = threadIdx.x & 3;
+        const double* yk = p.yvec + sb.p0 + kc;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = 16 * qq + q;
+            if (c < nk) acc = fma(Li[r][c], yk[c], acc);
+        }
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (qq == 0 && r < ni) p.yvec[sb.p0 + ri + r] -= acc;
+    }
     (void)nblk;
 }
 
@@ -445,7 +481,10 @@ void k_chol_retry(Plan p, int s, apx_lm_state* lm) {
     __shared__ int bad;
     const int t = threadIdx.x;
     if (!p.lmf[s].chol_fail) {
-        if (t == 0) p.lmf[s].chol_done = 1;
+        if (t == 0) {
+            p.lmf[s].chol_done = 1;
+            p.lmf[s].rhs_folded = 1;
+        }
         return;
     }
     const DSub sb = p.subs[s];
@@ -531,10 +570,12 @@ __device__ __forceinline__ void subst_publish(int* f, int lane) {
     if (lane == 0) __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Runs only when the factor came from the fallback workgroup (the first attempt folds the
+// forward substitution into its panels and updates).
 __global__ __launch_bounds__(256) void k_subst_fwd(Plan p, int s) {
     __shared__ double Lb[CHOL_NB][CHOL_NB + 1];
     __shared__ double rhs[CHOL_NB];
-    if (!p.lmf[s].chol_done) return;
+    if (!p.lmf[s].chol_done || p.lmf[s].rhs_folded) return;
     const DSub sb = p.subs[s];
     const int n = sb.n, b = blockIdx.x;
     const int t = threadIdx.x, lane = t & 63;
@@ -670,9 +711,9 @@ hipError_t launch_chol_reset(const Plan& p, int s, hipStream_t st) {
 hipError_t launch_chol_blocks(const Plan& p, int s, int n, hipStream_t st) {
     const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
     for (int k = 0; k < nblk; ++k) {
-        hipLaunchKernelGGL(k_chol_panel, dim3(nblk - k), dim3(256), 0, st, p, s, k);
+        hipLaunchKernelGGL(k_chol_panel, dim3(nblk - k), dim3(256), 0, st, p, s, k, 0);
         const int T = nblk - k - 1;
-        if (T > 0) hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk);
+        if (T > 0) hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk, 0);
     }
     return hipGetLastError();
 }
@@ -685,9 +726,9 @@ hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipS
     if (fb > 4096) fb = 4096;
     hipLaunchKernelGGL(k_chol_fill, dim3((unsigned)fb), dim3(256), 0, st, p, s, lm);
     for (int k = 0; k < nblk; ++k) {
-        hipLaunchKernelGGL(k_chol_panel, dim3(nblk - k), dim3(256), 0, st, p, s, k);
+        hipLaunchKernelGGL(k_chol_panel, dim3(nblk - k), dim3(256), 0, st, p, s, k, 1);
         const int T = nblk - k - 1;
-        if (T > 0) hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk);
+        if (T > 0) hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk, 1);
     }
     hipLaunchKernelGGL(k_chol_retry, dim3(1), dim3(256), 0, st, p, s, lm);
     hipLaunchKernelGGL(k_subst_fwd, dim3(nblk), dim3(256), 0, st, p, s);
