@@ -507,6 +507,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         sb.a_off = aoff;
         sb.large = n > SMALL_N ? 1 : 0;
         sb.flag_off = P->n_sflag;
+        sb.diag_idx = sb.large ? (int)P->large_subs.size() : -1;
         if (sb.large) P->n_sflag += 2 * ((n + CHOL_NB - 1) / CHOL_NB);
         aoff += (long long)n * n;
         P->subs[s] = sb;
@@ -1246,6 +1247,7 @@ static void layout(apx_problem* P) {
     ws_take<double>(P, "theta_trial", P->n_par);
     ws_take<LMFlags>(P, "lmf", P->n_sub);
     ws_take<int>(P, "sflag", std::max(1, P->n_sflag));
+    ws_take<double>(P, "chol_diag", (size_t)CHOL_NB * CHOL_NB * P->large_subs.size());
     ws_take<int>(P, "sticky", 1);
     ws_take<double>(P, "sky_val", P->n_images);
     ws_take<double>(P, "seed_part", 64LL * P->n_images);
@@ -1507,6 +1509,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.theta_trial = wsp<double>(P, "theta_trial");
     p.lmf = wsp<LMFlags>(P, "lmf");
     p.sflag = wsp<int>(P, "sflag");
+    p.chol_diag = wsp<double>(P, "chol_diag");
     p.sticky = wsp<int>(P, "sticky");
     p.sky_val = wsp<double>(P, "sky_val");
     p.par_sub = wsp<int>(P, "par_sub");

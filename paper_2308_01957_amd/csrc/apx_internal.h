@@ -141,7 +141,12 @@ constexpr int ADAPT_CHUNK = 256;
 struct AChunk { int comp, start; };
 struct ARef { int comp, idx; };
 
-struct DSub { int p0, n; long long a_off; int large, flag_off; };   // flag_off: 2 x blocks of sflag
+struct DSub {
+    int p0, n;
+    long long a_off;
+    int large, flag_off;      // flag_off: 2 x blocks of sflag
+    int diag_idx, pad;        // large: slot in chol_diag (the latest factored diagonal block)
+};
 
 // Per-sub-problem LM scratch flags
 struct LMFlags {
@@ -206,6 +211,7 @@ struct Plan {
     double* theta_trial;      // [n_par]
     LMFlags* lmf;             // [n_sub]
     int* sflag;               // substitution hand-off flags (per large sub: forward, backward blocks)
+    double* chol_diag;        // per large sub: a factored diagonal block on its way into M
     int* sticky;              // device error flags
     double* sky_val;          // [n_images] sky of each image at the current theta
     const int* par_sub;       // [n_par] sub-problem of each theta index (-1: none)

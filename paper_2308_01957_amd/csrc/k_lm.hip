@@ -349,7 +349,9 @@ __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
 
 // Block column k: every workgroup factors the diagonal block (redundantly, blocked on
 // FP64 MFMA); workgroup 0 stores it and reports a failed pivot, workgroup b > 0 solves row
-// block k+b (X L_kk^T = M_rk).  With fold, workgroup 0 also finishes block k of the forward
+// block k+b (X L_kk^T = M_rk).  The factored diagonal block goes to the sub-problem's
+// chol_diag slot, not into M, because the other workgroups of the launch are still reading
+// that block of M (the next step copies it into M).  With fold, workgroup 0 also finishes block k of the forward
 // substitution: the trailing updates have already taken sum_{c<k} L_kc y_c off the right-
 // hand side, so y_k = L_kk^-1 yvec_k (64 column steps on wave 0, by readlane broadcasts).
 __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk, int fold) {
@@ -374,9 +376,10 @@ __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk, int
         return;
     }
     if (blockIdx.x == 0) {
+        double* DF = p.chol_diag + (long long)sb.diag_idx * CHOL_NB * CHOL_NB;
         for (int e = t; e < nb * nb; e += 256) {
             const int i = e / nb, j = e - (e / nb) * nb;
-            if (j <= i) Mg[(long long)(kb + i) * n + kb + j] = L[i][j];
+            if (j <= i) DF[i * CHOL_NB + j] = L[i][j];
         }
         if (fold && t < 64) {
             double* y = p.yvec + sb.p0 + kb;
@@ -398,18 +401,13 @@ __global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk, int
     }
 }
 
-// Trailing update M_ij -= L_ik L_jk^T of one 64 x 64 block pair on FP64 MFMA: both
-// 64 x 64 panels are staged in LDS, each wave accumulates a 32 x 32 quadrant as 2 x 2
-// tiles of v_mfma_f64_16x16x4 (D[i][j] in lane j + 16 (i % 4), register i / 4).
-__device__ void chol_update_block(double* Mg, int n, int ri, int rj, int kc, bool diag,
-                                  double (*Li)[CHOL_NB + 1], double (*Lj)[CHOL_NB + 1]) {
-    const int ni = min(CHOL_NB, n - ri), nj = min(CHOL_NB, n - rj), nk = min(CHOL_NB, n - kc);
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    stage_block(Mg, n, ri, kc, ni, nk, Li, false);
-    stage_block(Mg, n, rj, kc, nj, nk, Lj, false);
-    __syncthreads();
+// L_ik L_jk^T for one 64 x 64 block pair on FP64 MFMA from the panels staged in LDS: each
+// wave accumulates a 32 x 32 quadrant as 2 x 2 tiles of v_mfma_f64_16x16x4 (D[i][j] in
+// lane j + 16 (i % 4), register i / 4 of tile [(i % 32) / 16][(j % 32) / 16]).
+__device__ __forceinline__ void trail_product(const double (*Li)[CHOL_NB + 1], const double (*Lj)[CHOL_NB + 1],
+                                              chol_d4 (&acc)[2][2]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int wr = wv >> 1, wc = wv & 1;
-    chol_d4 acc[2][2];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -427,6 +425,40 @@ __device__ void chol_update_block(double* Mg, int n, int ri, int rj, int kc, boo
             for (int q = 0; q < 2; ++q)
                 acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[q], acc[m][q], 0, 0, 0);
     }
+}
+
+// X -= L_ik L_jk^T on the entries i < ni, j < nj (and j <= i when diag) of an LDS block;
+// the caller synchronises before and after.
+__device__ __forceinline__ void trail_update_lds(double (*X)[CHOL_NB + 1], const double (*Li)[CHOL_NB + 1],
+                                                 const double (*Lj)[CHOL_NB + 1], int ni, int nj, bool diag) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wr = wv >> 1, wc = wv & 1;
+    chol_d4 acc[2][2];
+    trail_product(Li, Lj, acc);
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = wr * 32 + m * 16 + (lane >> 4) + 4 * v;
+                const int j = wc * 32 + q * 16 + (lane & 15);
+                if (i < ni && j < nj && (!diag || j <= i)) X[i][j] -= acc[m][q][v];
+            }
+}
+
+// Trailing update M_ij -= L_ik L_jk^T of one 64 x 64 block pair in global memory: both
+// 64 x 64 panels are staged in LDS and multiplied on FP64 MFMA.
+__device__ void chol_update_block(double* Mg, int n, int ri, int rj, int kc, bool diag,
+                                  double (*Li)[CHOL_NB + 1], double (*Lj)[CHOL_NB + 1]) {
+    const int ni = min(CHOL_NB, n - ri), nj = min(CHOL_NB, n - rj), nk = min(CHOL_NB, n - kc);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    stage_block(Mg, n, ri, kc, ni, nk, Li, false);
+    stage_block(Mg, n, rj, kc, nj, nk, Lj, false);
+    __syncthreads();
+    const int wr = wv >> 1, wc = wv & 1;
+    chol_d4 acc[2][2];
+    trail_product(Li, Lj, acc);
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -440,34 +472,113 @@ __device__ void chol_update_block(double* Mg, int n, int ri, int rj, int kc, boo
     __syncthreads();
 }
 
-// With fold, the workgroup of each diagonal block (i, i) also takes L_ik y_k off row block
-// i of the right-hand side (L_ik is its staged Li; 4 threads per row, 16 products each,
-// summed in a fixed order).
-__global__ __launch_bounds__(256) void k_chol_update(Plan p, int s, int kblk, int nblk, int fold) {
-    __shared__ double Li[CHOL_NB][CHOL_NB + 1], Lj[CHOL_NB][CHOL_NB + 1];
+// rhs rows of block i: yvec_i -= L_ik y_k (L_ik staged in Li; 4 threads per row, 16 products
+// each, summed in a fixed order).  Every thread calls it.
+__device__ __forceinline__ void fold_rhs(Plan& p, const DSub& sb, int ri, int kc, const double (*Li)[CHOL_NB + 1]) {
+    const int n = sb.n, ni = min(CHOL_NB, n - ri), nk = min(CHOL_NB, n - kc);
+    const int r = threadIdx.x >> 2, qq = threadIdx.x & 3;
+    const double* yk = p.yvec + sb.p0 + kc;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int c = 16 * qq + q;
+        if (c < nk) acc = fma(Li[r][c], yk[c], acc);
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (qq == 0 && r < ni) p.yvec[sb.p0 + ri + r] -= acc;
+}
+
+// One step of the right-looking factorisation with look-ahead: the trailing update of
+// block column k fused with the panel of block column k+1, so that a block of the next
+// panel is factored the moment it is up to date instead of after the whole update.
+// Workgroup (bi, bj), bj <= bi, owns block (k+1+bi, k+1+bj) and brings it up to date in LDS
+// (X = M - L_ik L_jk^T).  Blocks right of column k+1 are written back.  Block (k+1, k+1) is
+// factored (and, with fold, y_{k+1} solved); every other block of column k+1 updates its
+// own copy of that diagonal block with the same arithmetic, factors it (bitwise the same
+// factor), and solves its row block against it (X L_{k+1,k+1}^T = X).  The arithmetic of
+// every entry is that of the separate panel and update kernels.  Since the lower blocks read
+// block (k+1, k+1) of M while its owner factors it, the factor goes to the chol_diag slot and
+// reaches M in the next step (whose workgroups do not read that block), or directly in the
+// last step, which has no other workgroup.
+__global__ __launch_bounds__(256) void k_chol_step(Plan p, int s, int kblk, int fold) {
+    __shared__ double Li[CHOL_NB][CHOL_NB + 1];     // L_ik, then the diagonal block copy
+    __shared__ double Lj[CHOL_NB][CHOL_NB + 1];     // L_jk
+    __shared__ double X[CHOL_NB][CHOL_NB + 1];      // the block being brought up to date
+    __shared__ double col[CHOL_NB], invd[CHOL_NB];
+    __shared__ int bad;
     if (p.lmf[s].chol_fail) return;
     const DSub sb = p.subs[s];
-    // block index -> (bi, bj), bj <= bi, both after kblk
+    const int n = sb.n;
+    double* Mg = p.M + sb.a_off;
     int e = blockIdx.x, bi = 0;
     while (e >= bi + 1) { e -= bi + 1; ++bi; }
     const int bj = e;
-    const int ri = (kblk + 1 + bi) * CHOL_NB, kc = kblk * CHOL_NB;
-    chol_update_block(p.M + sb.a_off, sb.n, ri, (kblk + 1 + bj) * CHOL_NB, kc, bi == bj, Li, Lj);
-    if (fold && bi == bj) {
-        const int n = sb.n, ni = min(CHOL_NB, n - ri), nk = min(CHOL_NB, n - kc);
-        const int r = threadIdx.x >> 2, qq = threadIdx.x & 3;
-        const double* yk = p.yvec + sb.p0 + kc;
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int c = 16 * qq + q;
-            if (c < nk) acc = fma(Li[r][c], yk[c], acc);
+    const int t = threadIdx.x;
+    const int kc = kblk * CHOL_NB, r1 = (kblk + 1) * CHOL_NB;
+    const int ri = r1 + bi * CHOL_NB, rj = r1 + bj * CHOL_NB;
+    const int ni = min(CHOL_NB, n - ri), nj = min(CHOL_NB, n - rj), nk = min(CHOL_NB, n - kc);
+    const bool diag = bi == bj;
+    double* DF = p.chol_diag + (long long)sb.diag_idx * CHOL_NB * CHOL_NB;
+    if (blockIdx.x == 0)                             // L_kk (factored by the previous launch) into M
+        for (int q = t; q < nk * nk; q += 256) {
+            const int i = q / nk, j = q - (q / nk) * nk;
+            if (j <= i) Mg[(long long)(kc + i) * n + kc + j] = DF[i * CHOL_NB + j];
         }
-        acc += __shfl_xor(acc, 1, 64);
-        acc += __shfl_xor(acc, 2, 64);
-        if (qq == 0 && r < ni) p.yvec[sb.p0 + ri + r] -= acc;
+    stage_block(Mg, n, ri, kc, ni, nk, Li, false);
+    stage_block(Mg, n, rj, kc, nj, nk, Lj, false);
+    stage_block(Mg, n, ri, rj, ni, nj, X, diag);
+    __syncthreads();
+    trail_update_lds(X, Li, Lj, ni, nj, diag);
+    __syncthreads();
+    if (fold && diag) fold_rhs(p, sb, ri, kc, Li);
+    if (bj > 0) {                                    // not in the next panel: write back
+        for (int q = t; q < ni * nj; q += 256) {
+            const int i = q / nj, j = q - (q / nj) * nj;
+            if (!diag || j <= i) Mg[(long long)(ri + i) * n + rj + j] = X[i][j];
+        }
+        return;
     }
-    (void)nblk;
+    if (bi == 0) {                                   // the next diagonal block itself
+        if (!factor_diag_blocked(X, col, invd, &bad)) {
+            if (t == 0) p.lmf[s].chol_fail = 1;
+            return;
+        }
+        const bool last = gridDim.x == 1;
+        for (int q = t; q < ni * ni; q += 256) {
+            const int i = q / ni, j = q - (q / ni) * ni;
+            if (j > i) continue;
+            if (last) Mg[(long long)(ri + i) * n + ri + j] = X[i][j];
+            else DF[i * CHOL_NB + j] = X[i][j];
+        }
+        if (fold) {
+            __syncthreads();                          // the rhs of block k+1 (fold_rhs above)
+            if (t < 64) {
+                double* y = p.yvec + sb.p0 + ri;
+                double yi = t < ni ? y[t] : 0.0;
+#pragma unroll
+                for (int j = 0; j < CHOL_NB; ++j) {
+                    const double yj = lane_bcast(yi, j) * invd[j];
+                    if (t == j) yi = yj;
+                    else if (t > j) yi = fma(-X[t][j], yj, yi);
+                }
+                if (t < ni) y[t] = yi;
+            }
+        }
+        return;
+    }
+    // a lower block of the next panel: its own copy of the up-to-date diagonal block
+    // (Lj holds L_{k+1,k} here, since bj = 0)
+    stage_block(Mg, n, r1, r1, nj, nj, Li, true);
+    __syncthreads();
+    trail_update_lds(Li, Lj, Lj, nj, nj, true);
+    __syncthreads();
+    if (!factor_diag_blocked(Li, col, invd, &bad)) return;
+    trsm_blocked(X, Li, invd);
+    for (int q = t; q < ni * nj; q += 256) {
+        const int i = q / nj, j = q - (q / nj) * nj;
+        Mg[(long long)(ri + i) * n + rj + j] = X[i][j];
+    }
 }
 
 // Retries: if the first attempt failed, raise lambda and refactor with this single
@@ -710,10 +821,10 @@ hipError_t launch_chol_reset(const Plan& p, int s, hipStream_t st) {
 
 hipError_t launch_chol_blocks(const Plan& p, int s, int n, hipStream_t st) {
     const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
-    for (int k = 0; k < nblk; ++k) {
-        hipLaunchKernelGGL(k_chol_panel, dim3(nblk - k), dim3(256), 0, st, p, s, k, 0);
+    hipLaunchKernelGGL(k_chol_panel, dim3(nblk), dim3(256), 0, st, p, s, 0, 0);
+    for (int k = 0; k + 1 < nblk; ++k) {
         const int T = nblk - k - 1;
-        if (T > 0) hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk, 0);
+        hipLaunchKernelGGL(k_chol_step, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, 0);
     }
     return hipGetLastError();
 }
@@ -725,10 +836,10 @@ hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipS
     long long fb = (nn + 255) / 256;
     if (fb > 4096) fb = 4096;
     hipLaunchKernelGGL(k_chol_fill, dim3((unsigned)fb), dim3(256), 0, st, p, s, lm);
-    for (int k = 0; k < nblk; ++k) {
-        hipLaunchKernelGGL(k_chol_panel, dim3(nblk - k), dim3(256), 0, st, p, s, k, 1);
+    hipLaunchKernelGGL(k_chol_panel, dim3(nblk), dim3(256), 0, st, p, s, 0, 1);
+    for (int k = 0; k + 1 < nblk; ++k) {
         const int T = nblk - k - 1;
-        if (T > 0) hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, nblk, 1);
+        hipLaunchKernelGGL(k_chol_step, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, 1);
     }
     hipLaunchKernelGGL(k_chol_retry, dim3(1), dim3(256), 0, st, p, s, lm);
     hipLaunchKernelGGL(k_subst_fwd, dim3(nblk), dim3(256), 0, st, p, s);

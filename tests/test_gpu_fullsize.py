@@ -216,10 +216,44 @@ def test_cutouts_sampled_render_and_early_lm(apx):
 
 
 # ------------------------------------------------------------ multiband 6 x 2048^2
-def test_multiband_patches_and_tied_gradient(apx):
+@pytest.fixture(scope="module")
+def multiband(apx):
     spec = synth.multiband()
     print("[case] multiband full size", flush=True)
     P, data, weight, dd, ww = _problem(apx, spec, [None] * len(spec["images"]))
+    return spec, P, data, weight, dd, ww
+
+
+def test_multiband_lm_step_solves_the_damped_system(apx, multiband):
+    """The 2706-parameter system (43 blocks: the factorisation's steps launch up to 903
+    workgroups, several per CU slot, so blocks of one step run at different times): the
+    step of the first accepted iteration satisfies (A + lambda D) h = g with the device's
+    own A and g."""
+    spec, P, data, weight, dd, ww = multiband
+    n = spec["n_par"]
+    th0 = spec["theta_init"]
+    A, g, _ = P.jtwj(th0, dd, ww)
+    A = A.cpu().numpy().reshape(n, n)
+    g = g.cpu().numpy()
+    th, st = P.lm_init(th0, dd, ww)
+    for it in range(10):
+        P.lm_step(dd, ww, th, st)
+        s = P.lm_state(st)[0]
+        if s["accepted"]:
+            break
+    P.check()
+    assert s["accepted"] == 1 and s["n_chol_retry"] == 0
+    lam_used = s["lambda"] * oracle.LM_DOWN
+    assert lam_used == pytest.approx(oracle.LM_LAMBDA0 * oracle.LM_UP ** it, rel=1e-14)
+    D = np.maximum(np.diag(A), oracle.LM_DAMP_FLOOR * np.max(np.diag(A)))
+    h = th.cpu().numpy() - th0
+    res = (A + lam_used * np.diag(D)) @ h - g
+    assert np.linalg.norm(res) <= 1e-8 * np.linalg.norm(g)
+    assert s["pred"] == pytest.approx(float(h @ (lam_used * D * h + g)), rel=1e-9)
+
+
+def test_multiband_patches_and_tied_gradient(apx, multiband):
+    spec, P, data, weight, dd, ww = multiband
     th = spec["theta_init"]
     m = P.split(P.render(th))
     g = 17
