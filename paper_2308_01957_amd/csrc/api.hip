@@ -1239,15 +1239,16 @@ static void layout(apx_problem* P) {
     ws_take<double>(P, "grad_part", P->n_gradpart);
     ws_take<double>(P, "asrc", P->asrc_img + 3LL * P->n_images);
     ws_take<double>(P, "A", P->a_total);
-    ws_take<double>(P, "M", P->a_total);
+    ws_take<double>(P, "M", 2 * P->a_total);
     ws_take<double>(P, "gvec", P->n_par);
     ws_take<double>(P, "Ddiag", P->n_par);
-    ws_take<double>(P, "hvec", P->n_par);
-    ws_take<double>(P, "yvec", P->n_par);
+    ws_take<double>(P, "hvec", 2 * P->n_par);
+    ws_take<double>(P, "yvec", 2 * P->n_par);
     ws_take<double>(P, "theta_trial", P->n_par);
-    ws_take<LMFlags>(P, "lmf", P->n_sub);
-    ws_take<int>(P, "sflag", std::max(1, P->n_sflag));
-    ws_take<double>(P, "chol_diag", (size_t)CHOL_NB * CHOL_NB * P->large_subs.size());
+    ws_take<LMFlags>(P, "lmf", 2 * P->n_sub);
+    ws_take<int>(P, "sflag", std::max(1, 2 * P->n_sflag));
+    ws_take<double>(P, "chol_diag", 2 * (size_t)CHOL_NB * CHOL_NB * P->large_subs.size());
+    ws_take<LMSpec>(P, "spec", P->n_sub);
     ws_take<int>(P, "sticky", 1);
     ws_take<double>(P, "sky_val", P->n_images);
     ws_take<double>(P, "seed_part", 64LL * P->n_images);
@@ -1510,6 +1511,10 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.lmf = wsp<LMFlags>(P, "lmf");
     p.sflag = wsp<int>(P, "sflag");
     p.chol_diag = wsp<double>(P, "chol_diag");
+    p.spec = wsp<LMSpec>(P, "spec");
+    p.a_total = P->a_total;
+    p.n_sflag = P->n_sflag;
+    p.n_large = (int)P->large_subs.size();
     p.sticky = wsp<int>(P, "sticky");
     p.sky_val = wsp<double>(P, "sky_val");
     p.par_sub = wsp<int>(P, "par_sub");
@@ -1533,7 +1538,8 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     P->chi2_sub = wsp<double>(P, "chi2_sub");
     P->chi2_trial = wsp<double>(P, "chi2_trial");
     HIPCHK(hipMemsetAsync(p.sticky, 0, sizeof(int), P->ctx->stream));
-    HIPCHK(hipMemsetAsync(p.lmf, 0, sizeof(LMFlags) * P->n_sub, P->ctx->stream));
+    HIPCHK(hipMemsetAsync(p.lmf, 0, sizeof(LMFlags) * 2 * P->n_sub, P->ctx->stream));
+    HIPCHK(hipMemsetAsync(p.spec, 0, sizeof(LMSpec) * P->n_sub, P->ctx->stream));
     P->bound = true;
     return APX_OK;
 }
@@ -2333,6 +2339,7 @@ static apx_status lm_step_enqueue(apx_problem* P, const float* data, const float
     {
         TimeScope ts(P, APX_TIME_LM);
         HIPCHK(launch_lm_begin(p, state, st));
+        if (!P->large_subs.empty()) HIPCHK(launch_lm_adopt(p, state, st));
     }
     // normal equations at theta for sub-problems whose last step was accepted
     APXCHK(prep(P, theta, 0, 2, state, 1));

@@ -156,6 +156,18 @@ struct LMFlags {
     int skip;                 // 1: sub-problem skips the current render/phase
     int subst_fail;           // a substitution hand-off wait ran out this iteration
     int rhs_folded;           // the forward substitution ran inside the first factorisation
+    int adopted;              // this iteration's step is the one solved ahead (see LMSpec)
+};
+
+// Step solved ahead (large sub-problems): while an iteration factors A + lambda D, the same
+// launches also factor A + lambda' D with lambda' = min(UP lambda, max), the damping the next
+// iteration starts from if this trial is rejected (same A, same D).  The next iteration
+// adopts that solution, with its retries, instead of solving again.
+struct LMSpec {
+    double lam_start;         // lambda' the solve started from
+    double lam_final;         // lambda after its own retries
+    double pred;              // h^T (lambda D h + g) of its step
+    int valid, done, retries, pad;
 };
 
 // Launch-time views of the workspace ----------------------------------------------
@@ -212,6 +224,9 @@ struct Plan {
     LMFlags* lmf;             // [n_sub]
     int* sflag;               // substitution hand-off flags (per large sub: forward, backward blocks)
     double* chol_diag;        // per large sub: a factored diagonal block on its way into M
+    LMSpec* spec;             // [n_sub] the step solved ahead
+    long long a_total;        // entries of M per copy (the solve-ahead copy follows)
+    int n_sflag, n_large;     // per copy: substitution flags, large sub-problems
     int* sticky;              // device error flags
     double* sky_val;          // [n_images] sky of each image at the current theta
     const int* par_sub;       // [n_par] sub-problem of each theta index (-1: none)
@@ -240,6 +255,22 @@ constexpr int FLAG_DOMAIN = 1, FLAG_NONFINITE = 2, FLAG_STALL = 4;
 // live Moffat PSF domain
 constexpr double PSF_N_MIN = 0.2, PSF_N_MAX = 20.0, PSF_RD_MIN = 0.05, PSF_RD_MAX = 1e3;
 constexpr int GROUP_PSF = 2;                   // DGroup.type of the live-PSF columns of an image
+
+// The buffers of the damped solve for copy `which` (0: this iteration's lambda, 1: the
+// solve-ahead lambda'): M, yvec, hvec, the hand-off flags, the factorisation flags and the
+// diagonal-block slots of copy 1 follow those of copy 0.
+__device__ __forceinline__ Plan solve_view(const Plan& p, int which) {
+    Plan q = p;
+    if (which) {
+        q.M += p.a_total;
+        q.yvec += p.n_par;
+        q.hvec += p.n_par;
+        q.sflag += p.n_sflag;
+        q.lmf += p.n_sub;
+        q.chol_diag += (long long)p.n_large * CHOL_NB * CHOL_NB;
+    }
+    return q;
+}
 
 // skip_mode of the launchers: 0 none, 1 sub-problems without a valid trial (the trial
 // render), 2 sub-problems that keep their Jacobian (lm[sub].need_jac == 0)
@@ -327,6 +358,8 @@ hipError_t launch_chi2_check(const double* chi2, int n, int* sticky, hipStream_t
 
 // k_lm.hip
 hipError_t launch_lm_begin(const Plan& p, apx_lm_state* lm, hipStream_t st);
+// large sub-problems whose step was solved ahead take it (step, pred, lambda, retries)
+hipError_t launch_lm_adopt(const Plan& p, apx_lm_state* lm, hipStream_t st);
 hipError_t launch_lm_init(const Plan& p, const double* chi2_sub, apx_lm_state* lm, hipStream_t st);
 hipError_t launch_chol_small(const Plan& p, const int* small_subs, int n_small, int nmax,
                              apx_lm_state* lm, hipStream_t st);

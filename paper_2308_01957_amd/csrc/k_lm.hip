@@ -16,7 +16,10 @@ __device__ __forceinline__ double lm_wave_max(double v) {
     return v;
 }
 
-__global__ void k_lm_begin(Plan p) {
+// Start of an iteration: clear the per-iteration flags of both solve copies and decide
+// whether a large sub-problem takes the step solved ahead: the same A (its last trial was
+// rejected, so no new normal equations) and the lambda that solve started from.
+__global__ void k_lm_begin(Plan p, const apx_lm_state* lm) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= p.n_sub) return;
     LMFlags f;
@@ -24,12 +27,40 @@ __global__ void k_lm_begin(Plan p) {
     f.chol_fail = 0;
     f.trial_bad = 0;
     f.skip = 0;
+    f.subst_fail = 0;
+    f.rhs_folded = 0;
+    f.adopted = 0;
+    p.lmf[p.n_sub + s] = f;
+    const LMSpec sp = p.spec[s];
+    f.adopted = p.subs[s].large && sp.valid && lm[s].need_jac == 0 && lm[s].lambda == sp.lam_start;
     p.lmf[s] = f;
 }
 
 hipError_t launch_lm_begin(const Plan& p, apx_lm_state* lm, hipStream_t st) {
-    (void)lm;
-    hipLaunchKernelGGL(k_lm_begin, dim3((p.n_sub + 255) / 256), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_lm_begin, dim3((p.n_sub + 255) / 256), dim3(256), 0, st, p, lm);
+    return hipGetLastError();
+}
+
+// One wave per sub-problem: an adopting sub-problem takes the step, its predicted decrease,
+// lambda and retry count from the solve made ahead (exactly what solving now would give:
+// same A, D, g and starting lambda, same kernels); the record is used up.
+__global__ __launch_bounds__(64) void k_lm_adopt(Plan p, apx_lm_state* lm) {
+    const int s = blockIdx.x;
+    if (!p.lmf[s].adopted) return;
+    const DSub sb = p.subs[s];
+    for (int i = (int)threadIdx.x; i < sb.n; i += 64) p.hvec[sb.p0 + i] = p.hvec[p.n_par + sb.p0 + i];
+    if (threadIdx.x == 0) {
+        const LMSpec sp = p.spec[s];
+        lm[s].pred = sp.pred;
+        lm[s].lambda = sp.lam_final;
+        lm[s].n_chol_retry += sp.retries;
+        p.lmf[s].chol_done = sp.done;
+        p.spec[s].valid = 0;
+    }
+}
+
+hipError_t launch_lm_adopt(const Plan& p, apx_lm_state* lm, hipStream_t st) {
+    hipLaunchKernelGGL(k_lm_adopt, dim3(p.n_sub), dim3(64), 0, st, p, lm);
     return hipGetLastError();
 }
 
@@ -49,6 +80,7 @@ __global__ void k_lm_init(Plan p, const double* chi2_sub, apx_lm_state* lm) {
     st.n_chol_retry = 0;
     st.status = isfinite(st.chi2) ? APX_OK : APX_E_NONFINITE;
     lm[s] = st;
+    p.spec[s].valid = 0;
 }
 
 hipError_t launch_lm_init(const Plan& p, const double* chi2_sub, apx_lm_state* lm, hipStream_t st) {
@@ -306,8 +338,10 @@ __device__ __forceinline__ void stage_block(const double* Mg, int n, int r0, int
 }
 
 __global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
-    // one block: damping diagonal D from the diagonal of A and its maximum
+    // one block: damping diagonal D from the diagonal of A and its maximum; clears the
+    // flags of copy 0 (and, in the LM, of the solve-ahead copy 1)
     __shared__ double red[4];
+    if (lm && p.lmf[s].adopted) return;
     const DSub sb = p.subs[s];
     const int n = sb.n;
     const double* A = p.A + sb.a_off;
@@ -320,20 +354,29 @@ __global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
     for (int i = threadIdx.x; i < n; i += blockDim.x)
         p.Ddiag[sb.p0 + i] = fmax(A[(long long)i * n + i], APX_LM_DAMP_FLOOR * dmax);
     const int nflag = 2 * ((n + CHOL_NB - 1) / CHOL_NB);
-    for (int i = threadIdx.x; i < nflag; i += blockDim.x) p.sflag[sb.flag_off + i] = 0;
-    if (threadIdx.x == 0) {
-        p.lmf[s].chol_fail = 0;
-        p.lmf[s].subst_fail = 0;
-        p.lmf[s].rhs_folded = 0;
+    for (int w = 0; w < (lm ? 2 : 1); ++w) {
+        const Plan q = solve_view(p, w);
+        for (int i = threadIdx.x; i < nflag; i += blockDim.x) q.sflag[sb.flag_off + i] = 0;
+        if (threadIdx.x == 0) {
+            q.lmf[s].chol_fail = 0;
+            q.lmf[s].subst_fail = 0;
+            q.lmf[s].rhs_folded = 0;
+        }
     }
 }
 
 // M = A + lambda D, and the working right-hand side yvec = J^T W r that the first
 // factorisation attempt turns into y = L^-1 g as it goes.
+// Copy 0 (blockIdx.y = 0) takes this iteration's lambda, copy 1 the solve-ahead
+// lambda' = min(UP lambda, max).
 __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
+    if (p.lmf[s].adopted) return;
+    const int which = blockIdx.y;
+    const Plan q = solve_view(p, which);
     const DSub sb = p.subs[s];
     const int n = sb.n;
-    const double lam = lm[s].lambda;
+    const double lam = which ? fmin(lm[s].lambda * APX_LM_UP, APX_LM_LAMBDA_MAX) : lm[s].lambda;
+    if (which && blockIdx.x == 0 && threadIdx.x == 0) p.spec[s].lam_start = lam;
     const long long nn = (long long)n * n;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
          e += (long long)gridDim.x * blockDim.x) {
@@ -341,9 +384,9 @@ __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
         double v = p.A[sb.a_off + e];
         if (i == j) {
             v += lam * p.Ddiag[sb.p0 + i];
-            p.yvec[sb.p0 + i] = p.gvec[sb.p0 + i];
+            q.yvec[sb.p0 + i] = p.gvec[sb.p0 + i];
         }
-        p.M[sb.a_off + e] = v;
+        q.M[sb.a_off + e] = v;
     }
 }
 
@@ -354,7 +397,9 @@ __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
 // that block of M (the next step copies it into M).  With fold, workgroup 0 also finishes block k of the forward
 // substitution: the trailing updates have already taken sum_{c<k} L_kc y_c off the right-
 // hand side, so y_k = L_kk^-1 yvec_k (64 column steps on wave 0, by readlane broadcasts).
-__global__ __launch_bounds__(256) void k_chol_panel(Plan p, int s, int kblk, int fold) {
+__global__ __launch_bounds__(256) void k_chol_panel(Plan p0, int s, int kblk, int fold) {
+    if (fold && p0.lmf[s].adopted) return;          // fold: the LM's solve (blockIdx.y = copy)
+    const Plan p = solve_view(p0, blockIdx.y);
     __shared__ double L[CHOL_NB][CHOL_NB + 1];
     __shared__ double X[CHOL_NB][CHOL_NB + 1];
     __shared__ double col[CHOL_NB], invd[CHOL_NB];
@@ -474,7 +519,7 @@ __device__ void chol_update_block(double* Mg, int n, int ri, int rj, int kc, boo
 
 // rhs rows of block i: yvec_i -= L_ik y_k (L_ik staged in Li; 4 threads per row, 16 products
 // each, summed in a fixed order).  Every thread calls it.
-__device__ __forceinline__ void fold_rhs(Plan& p, const DSub& sb, int ri, int kc, const double (*Li)[CHOL_NB + 1]) {
+__device__ __forceinline__ void fold_rhs(const Plan& p, const DSub& sb, int ri, int kc, const double (*Li)[CHOL_NB + 1]) {
     const int n = sb.n, ni = min(CHOL_NB, n - ri), nk = min(CHOL_NB, n - kc);
     const int r = threadIdx.x >> 2, qq = threadIdx.x & 3;
     const double* yk = p.yvec + sb.p0 + kc;
@@ -501,12 +546,14 @@ __device__ __forceinline__ void fold_rhs(Plan& p, const DSub& sb, int ri, int kc
 // block (k+1, k+1) of M while its owner factors it, the factor goes to the chol_diag slot and
 // reaches M in the next step (whose workgroups do not read that block), or directly in the
 // last step, which has no other workgroup.
-__global__ __launch_bounds__(256) void k_chol_step(Plan p, int s, int kblk, int fold) {
+__global__ __launch_bounds__(256) void k_chol_step(Plan p0, int s, int kblk, int fold) {
     __shared__ double Li[CHOL_NB][CHOL_NB + 1];     // L_ik, then the diagonal block copy
     __shared__ double Lj[CHOL_NB][CHOL_NB + 1];     // L_jk
     __shared__ double X[CHOL_NB][CHOL_NB + 1];      // the block being brought up to date
     __shared__ double col[CHOL_NB], invd[CHOL_NB];
     __shared__ int bad;
+    if (fold && p0.lmf[s].adopted) return;
+    const Plan p = solve_view(p0, blockIdx.y);
     if (p.lmf[s].chol_fail) return;
     const DSub sb = p.subs[s];
     const int n = sb.n;
@@ -583,18 +630,27 @@ __global__ __launch_bounds__(256) void k_chol_step(Plan p, int s, int kblk, int 
 
 // Retries: if the first attempt failed, raise lambda and refactor with this single
 // workgroup (up to APX_LM_ATTEMPTS - 1 more times).  Otherwise mark success and exit.
+// blockIdx.y = copy: copy 0 updates the LM state, copy 1 the solve-ahead record.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void k_chol_retry(Plan p, int s, apx_lm_state* lm) {
+void k_chol_retry(Plan p0, int s, apx_lm_state* lm) {
     __shared__ double L[CHOL_NB][CHOL_NB + 1];
     __shared__ double X[CHOL_NB][CHOL_NB + 1];
     __shared__ double Li[CHOL_NB][CHOL_NB + 1], Lj[CHOL_NB][CHOL_NB + 1];
     __shared__ double col[CHOL_NB], invd[CHOL_NB];
     __shared__ int bad;
+    if (p0.lmf[s].adopted) return;
+    const int which = blockIdx.y;
+    const Plan p = solve_view(p0, which);
     const int t = threadIdx.x;
+    const double lam0 = which ? p0.spec[s].lam_start : lm[s].lambda;
     if (!p.lmf[s].chol_fail) {
         if (t == 0) {
             p.lmf[s].chol_done = 1;
             p.lmf[s].rhs_folded = 1;
+            if (which) {
+                p0.spec[s].lam_final = lam0;
+                p0.spec[s].retries = 0;
+            }
         }
         return;
     }
@@ -602,7 +658,7 @@ void k_chol_retry(Plan p, int s, apx_lm_state* lm) {
     const int n = sb.n;
     double* Mg = p.M + sb.a_off;
     const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
-    double lam = lm[s].lambda;
+    double lam = lam0;
     int done = 0, retries = 1;                      // the failed first attempt
     for (int att = 1; att < APX_LM_ATTEMPTS && !done; ++att) {
         lam = fmin(lam * APX_LM_UP, APX_LM_LAMBDA_MAX);
@@ -642,8 +698,15 @@ void k_chol_retry(Plan p, int s, apx_lm_state* lm) {
         if (ok) done = 1;
     }
     if (t == 0) {
-        lm[s].lambda = done ? lam : fmin(lam * APX_LM_UP, APX_LM_LAMBDA_MAX);
-        lm[s].n_chol_retry += done ? retries - 1 : retries;
+        const double lam_out = done ? lam : fmin(lam * APX_LM_UP, APX_LM_LAMBDA_MAX);
+        const int retry_out = done ? retries - 1 : retries;
+        if (which) {
+            p0.spec[s].lam_final = lam_out;
+            p0.spec[s].retries = retry_out;
+        } else {
+            lm[s].lambda = lam_out;
+            lm[s].n_chol_retry += retry_out;
+        }
         p.lmf[s].chol_done = done;
     }
 }
@@ -683,9 +746,11 @@ __device__ __forceinline__ void subst_publish(int* f, int lane) {
 
 // Runs only when the factor came from the fallback workgroup (the first attempt folds the
 // forward substitution into its panels and updates).
-__global__ __launch_bounds__(256) void k_subst_fwd(Plan p, int s) {
+__global__ __launch_bounds__(256) void k_subst_fwd(Plan p0, int s) {
     __shared__ double Lb[CHOL_NB][CHOL_NB + 1];
     __shared__ double rhs[CHOL_NB];
+    if (p0.lmf[s].adopted) return;
+    Plan p = solve_view(p0, blockIdx.y);
     if (!p.lmf[s].chol_done || p.lmf[s].rhs_folded) return;
     const DSub sb = p.subs[s];
     const int n = sb.n, b = blockIdx.x;
@@ -736,9 +801,11 @@ __global__ __launch_bounds__(256) void k_subst_fwd(Plan p, int s) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_subst_bwd(Plan p, int s) {
+__global__ __launch_bounds__(256) void k_subst_bwd(Plan p0, int s) {
     __shared__ double Lb[CHOL_NB][CHOL_NB + 1];
     __shared__ double part[4][CHOL_NB];
+    if (p0.lmf[s].adopted) return;
+    Plan p = solve_view(p0, blockIdx.y);
     if (!p.lmf[s].chol_done) return;
     const DSub sb = p.subs[s];
     const int n = sb.n, nblk = (n + CHOL_NB - 1) / CHOL_NB;
@@ -789,13 +856,17 @@ __global__ __launch_bounds__(256) void k_subst_bwd(Plan p, int s) {
 }
 
 // h = y, pred = h^T (lambda D h + g); zeros when the factorisation or a hand-off failed.
-__global__ __launch_bounds__(256) void k_subst_finish(Plan p, int s, apx_lm_state* lm) {
+// blockIdx.y = copy: copy 1 fills the solve-ahead record (step in its hvec copy).
+__global__ __launch_bounds__(256) void k_subst_finish(Plan p0, int s, apx_lm_state* lm) {
     __shared__ double red[4];
+    if (p0.lmf[s].adopted) return;
+    const int which = blockIdx.y;
+    const Plan p = solve_view(p0, which);
     const DSub sb = p.subs[s];
     const int n = sb.n;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const bool done = p.lmf[s].chol_done != 0 && p.lmf[s].subst_fail == 0;
-    const double lam = lm[s].lambda;
+    const double lam = which ? p0.spec[s].lam_final : lm[s].lambda;
     double v = 0.0;
     for (int i = t; i < n; i += 256) {
         const double h = done ? p.yvec[sb.p0 + i] : 0.0;
@@ -806,7 +877,14 @@ __global__ __launch_bounds__(256) void k_subst_finish(Plan p, int s, apx_lm_stat
     if (lane == 0) red[wv] = v;
     __syncthreads();
     if (t == 0) {
-        lm[s].pred = done ? ((red[0] + red[1]) + red[2]) + red[3] : 0.0;
+        const double pred = done ? ((red[0] + red[1]) + red[2]) + red[3] : 0.0;
+        if (which) {
+            p0.spec[s].pred = pred;
+            p0.spec[s].done = done ? 1 : 0;
+            p0.spec[s].valid = 1;
+        } else {
+            lm[s].pred = pred;
+        }
         if (!done) p.lmf[s].chol_done = 0;
     }
 }
@@ -835,16 +913,17 @@ hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipS
     const long long nn = (long long)n * n;
     long long fb = (nn + 255) / 256;
     if (fb > 4096) fb = 4096;
-    hipLaunchKernelGGL(k_chol_fill, dim3((unsigned)fb), dim3(256), 0, st, p, s, lm);
-    hipLaunchKernelGGL(k_chol_panel, dim3(nblk), dim3(256), 0, st, p, s, 0, 1);
+    // y = 2 copies: this iteration's lambda and the solve-ahead lambda'
+    hipLaunchKernelGGL(k_chol_fill, dim3((unsigned)fb, 2), dim3(256), 0, st, p, s, lm);
+    hipLaunchKernelGGL(k_chol_panel, dim3(nblk, 2), dim3(256), 0, st, p, s, 0, 1);
     for (int k = 0; k + 1 < nblk; ++k) {
         const int T = nblk - k - 1;
-        hipLaunchKernelGGL(k_chol_step, dim3(T * (T + 1) / 2), dim3(256), 0, st, p, s, k, 1);
+        hipLaunchKernelGGL(k_chol_step, dim3(T * (T + 1) / 2, 2), dim3(256), 0, st, p, s, k, 1);
     }
-    hipLaunchKernelGGL(k_chol_retry, dim3(1), dim3(256), 0, st, p, s, lm);
-    hipLaunchKernelGGL(k_subst_fwd, dim3(nblk), dim3(256), 0, st, p, s);
-    hipLaunchKernelGGL(k_subst_bwd, dim3(nblk), dim3(256), 0, st, p, s);
-    hipLaunchKernelGGL(k_subst_finish, dim3(1), dim3(256), 0, st, p, s, lm);
+    hipLaunchKernelGGL(k_chol_retry, dim3(1, 2), dim3(256), 0, st, p, s, lm);
+    hipLaunchKernelGGL(k_subst_fwd, dim3(nblk, 2), dim3(256), 0, st, p, s);
+    hipLaunchKernelGGL(k_subst_bwd, dim3(nblk, 2), dim3(256), 0, st, p, s);
+    hipLaunchKernelGGL(k_subst_finish, dim3(1, 2), dim3(256), 0, st, p, s, lm);
     return hipGetLastError();
 }
 
@@ -898,6 +977,9 @@ __global__ void k_lm_accept(Plan p, const double* __restrict__ chi2_trial, doubl
         st.need_jac = accept;
         if (accept) st.n_accept += 1; else st.n_reject += 1;
         lm[s] = st;
+        // a step solved ahead stays usable only after a rejection of a solved trial (same A,
+        // lambda raised exactly once)
+        if (accept || !f.chol_done) p.spec[s].valid = 0;
         acc_flag = accept;
     }
     __syncthreads();

@@ -320,6 +320,40 @@ def _early(apx, name, iters):
         assert np.all(np.abs(tg - to) <= 1e-5 * (np.abs(to) + spec["scale"])), n_iter
 
 
+def test_step_solved_ahead_equals_a_fresh_solve(apx):
+    """After a rejected trial the next iteration takes the step solved ahead (same A, lambda
+    raised once).  A fresh problem that forms A at the same theta and solves at that lambda
+    in its first iteration takes bitwise the same step (and reports the same lambda and
+    predicted decrease)."""
+    import torch
+    spec = get("large_sub")
+    assert spec["n_par"] > 64
+    P, d, w = problem(apx, spec)
+    th, st = P.lm_init(spec["theta_init"], d, w)
+    for _ in range(30):
+        P.lm_step(d, w, th, st)
+        s = P.lm_state(st)[0]
+        if not s["accepted"] and not math.isnan(s["chi2_trial"]):
+            break
+    else:
+        pytest.skip("no rejected solved trial in 30 iterations")
+    th_rej, st_rej = th.clone(), P.lm_state(st).copy()
+    P.lm_step(d, w, th, st)                               # adopts the step solved ahead
+    s_a = P.lm_state(st)[0]
+    Q, dq, wq = problem(apx, spec)
+    th_q, st_q = Q.lm_init(th_rej.cpu().numpy(), dq, wq)
+    s0 = Q.lm_state(st_q).copy()
+    s0["lambda"] = st_rej["lambda"]
+    st_q.copy_(torch.from_numpy(np.frombuffer(s0.tobytes(), dtype=np.uint8).copy()).to(st_q.device))
+    Q.lm_step(dq, wq, th_q, st_q)                         # forms A at theta, solves at lambda
+    s_q = Q.lm_state(st_q)[0]
+    P.check()
+    Q.check()
+    assert torch.equal(th.cpu(), th_q.cpu())
+    assert s_a["lambda"] == s_q["lambda"] and s_a["pred"] == s_q["pred"]
+    assert s_a["accepted"] == s_q["accepted"] and s_a["chi2_trial"] == s_q["chi2_trial"]
+
+
 def test_lm_graph_replay_matches_eager(apx):
     spec = get("few_cutouts")
     P, d, w = problem(apx, spec)
