@@ -57,23 +57,33 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     const long long colA = (long long)(a0 + i0) * gs - G.ox0, stepA = (long long)DI * gs;
     const long long colB = (long long)(b0 + i0) * hs - Hh.ox0, stepB = (long long)DI * hs;
     const int nva = G.ncols - a0 - i0, nvb = Hh.ncols - b0 - i0;   // element q valid: DI q < nv
+    const long long lastA = (long long)(G.ncols - 1) * gs - G.ox0;   // a column that exists
+    const long long lastB = (long long)(Hh.ncols - 1) * hs - Hh.ox0;
 
     const int nxs = (pr.x1 - pr.x0 + KC - 1) / KC;
     const int n_stage = (it.r1 - it.r0) * nxs;
     // two stages of global loads in flight (register ring): the loads of stage s+2 are
     // issued while the MFMAs consume stages s and s+1
     float ra0[PER], rb0[PER], rw0 = 0.f, ra1[PER], rb1[PER], rw1 = 0.f;
+    // every load is issued unconditionally (a lane past the box or past the last column
+    // reads a valid entry and zeroes it afterwards), so the 2 PER + 1 loads of a stage go
+    // out back to back instead of one branch each
     auto fetch = [&](int st, float (&ra)[PER], float (&rb)[PER], float& rw) {
         const int row = it.r0 + st / nxs;
         const int x = pr.x0 + (st - (st / nxs) * nxs) * KC + kq;
-        const long long grow = (long long)(row - G.oy0) * G.ow + x;
-        const long long hrow = (long long)(row - Hh.oy0) * Hh.ow + x;
         const bool in = x < pr.x1;
-        rw = in ? weight[pix_off + (long long)row * imW + x] : 0.f;
+        const int xc = in ? x : pr.x1 - 1;
+        const long long grow = (long long)(row - G.oy0) * G.ow + xc;
+        const long long hrow = (long long)(row - Hh.oy0) * Hh.ow + xc;
+        const float wv = weight[pix_off + (long long)row * imW + xc];
+        rw = in ? wv : 0.f;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            ra[q] = (in && DI * q < nva) ? Jg[colA + q * stepA + grow] : 0.f;
-            rb[q] = (in && DI * q < nvb) ? Jh[colB + q * stepB + hrow] : 0.f;
+            const bool va = DI * q < nva, vb = DI * q < nvb;
+            const float a = Jg[(va ? colA + q * stepA : lastA) + grow];
+            const float b = Jh[(vb ? colB + q * stepB : lastB) + hrow];
+            ra[q] = (in && va) ? a : 0.f;
+            rb[q] = (in && vb) ? b : 0.f;
         }
     };
     auto stage = [&](const float (&ra)[PER], const float (&rb)[PER], float rw) {
