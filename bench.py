@@ -515,6 +515,16 @@ def main():
     prob.set_timing(False)
     state = prob.lm_state(st)[0]
     prob.check()
+    # context: the same K iterations as replays of one captured iteration (HIP graph)
+    th_g, st_g = prob.lm_init(spec["theta_init"], dd, ww)
+    prob.lm_run(1, dd, ww, th_g, st_g, use_graph=True)
+    prob.lm_init(spec["theta_init"], dd, ww, theta_out=th_g, state_out=st_g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.lm_run(args.steps, dd, ww, th_g, st_g, use_graph=True)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    assert torch.equal(th_g, th), "graph replay and eager iterations differ"
     # the per-class breakdown from a second, fully instrumented pass over the same iterations
     th2, st2 = prob.lm_init(spec["theta_init"], dd, ww)
     prob.set_timing(True)
@@ -603,6 +613,7 @@ def main():
                      "launches_total": jcol_launches,
                      "flop_per_launch": flop_per_phase},
         "covariance_ms": cov_ms,
+        "graph_ms_per_step": graph_ms,
         "fft_mode": fft_mode,
         "kernel_ms": {k: round(v[0], 4) for k, v in kt_all.items()},
         "kernel_ms_note": "per class over the K iterations, from a second fully instrumented pass",

@@ -301,7 +301,10 @@ apx_status apx_problem_destroy(apx_problem* p);
 /* Kernel timing (tracing aid).  When enabled, every launch group of the hot path is
  * bracketed by HIP events recorded on the context stream; apx_problem_timing()
  * synchronises and returns the summed duration and launch count of one class since
- * the last enable.  Not usable while a graph is being captured (APX_E_INVALID). */
+ * the last enable.  With apx_lm_run(use_graph = 1) the events are captured into the
+ * iteration's graph (a graph captured under another set of classes is captured again)
+ * and every replay records into fresh events.  The classes cannot change during a
+ * capture (APX_E_INVALID). */
 #define APX_TIME_PREP       0
 #define APX_TIME_RENDER     1     /* pre-convolution render (objective path)   */
 #define APX_TIME_CONV_FWD   2     /* model convolution + chi^2 partials         */
@@ -314,9 +317,9 @@ apx_status apx_problem_destroy(apx_problem* p);
 #define APX_TIME_CONV_ADJ   9     /* adjoint convolution                        */
 #define APX_TIME_GRAD       10    /* adjoint contraction with recomputed samples */
 #define APX_TIME_CLASSES    11
-/* Kernel timing with HIP events on the context stream (outside graph capture): enabled != 0
- * records every class; set_timing_classes records only the classes in mask (bit 1 << class),
- * which keeps the event overhead off the other launches.  Either call resets the records. */
+/* Kernel timing with HIP events on the context stream: enabled != 0 records every class;
+ * set_timing_classes records only the classes in mask (bit 1 << class), which keeps the
+ * event overhead off the other launches.  Either call resets the records. */
 apx_status apx_problem_set_timing(apx_problem* p, int32_t enabled);
 apx_status apx_problem_set_timing_classes(apx_problem* p, uint32_t mask);
 apx_status apx_problem_timing(apx_problem* p, int32_t klass, double* total_ms, int64_t* launches);

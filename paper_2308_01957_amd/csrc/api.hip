@@ -120,11 +120,17 @@ struct apx_problem {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> ev_recs;   // (class, index of start event)
+    // timing inside a captured LM iteration: the events recorded during capture become
+    // event-record nodes; each replay points them at fresh events of ev_pool
+    struct CapMark { int klass; hipEvent_t ev[2]; hipGraphNode_t node[2]; };
+    std::vector<CapMark> cap_marks;
+    std::string cap_error;                       // first failure of a mark during capture
 
     // graph cache for apx_lm_run
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     const void* gkey[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint32_t gmask = 0;                          // timing classes captured into the graph
 };
 
 // ------------------------------------------------------------------------ helpers
@@ -385,8 +391,44 @@ struct TimeScope {
     ~TimeScope();
 };
 
+// During capture: an event-record node appended to the captured work by hand (a plain
+// event record inside a capture is only a dependency marker); the node's event is a
+// placeholder that every replay replaces.  Returns false (and notes why) on any failure.
+static bool capture_mark(apx_problem* P, hipEvent_t ev, hipGraphNode_t* node) {
+    hipStream_t st = P->ctx->stream;
+    hipStreamCaptureStatus cs;
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t nd = 0;
+    hipError_t e = hipStreamGetCaptureInfo_v2(st, &cs, &id, &g, &deps, &nd);
+    if (e == hipSuccess && cs != hipStreamCaptureStatusActive) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = hipGraphAddEventRecordNode(node, g, deps, nd, ev);
+    if (e == hipSuccess) e = hipStreamUpdateCaptureDependencies(st, node, 1, hipStreamSetCaptureDependencies);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (P->cap_error.empty()) P->cap_error = std::string("timing mark in capture: ") + hipGetErrorString(e);
+        return false;
+    }
+    return true;
+}
+
 TimeScope::TimeScope(apx_problem* P_, int k) : P(P_), klass(k) {
-    if (!P->timing || P->capturing || !((P->timing_mask >> k) & 1u)) return;
+    if (!P->timing || !((P->timing_mask >> k) & 1u)) return;
+    if (P->capturing) {
+        apx_problem::CapMark m{};
+        m.klass = k;
+        if (hipEventCreate(&m.ev[0]) != hipSuccess) { P->cap_error = "timing: event creation"; return; }
+        if (hipEventCreate(&m.ev[1]) != hipSuccess) {
+            hipEventDestroy(m.ev[0]);
+            P->cap_error = "timing: event creation";
+            return;
+        }
+        P->cap_marks.push_back(m);
+        idx = P->cap_marks.size() - 1;
+        capture_mark(P, m.ev[0], &P->cap_marks[idx].node[0]);
+        return;
+    }
     while (P->ev_pool.size() < P->ev_used + 2) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;
@@ -398,8 +440,40 @@ TimeScope::TimeScope(apx_problem* P_, int k) : P(P_), klass(k) {
 }
 TimeScope::~TimeScope() {
     if (idx == (size_t)-1) return;
+    if (P->capturing) {
+        capture_mark(P, P->cap_marks[idx].ev[1], &P->cap_marks[idx].node[1]);
+        return;
+    }
     hipEventRecord(P->ev_pool[idx + 1], P->ctx->stream);
     P->ev_recs.emplace_back(klass, idx);
+}
+
+static void drop_graph(apx_problem* P) {
+    if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+    if (P->graph) { hipGraphDestroy(P->graph); P->graph = nullptr; }
+    for (auto& m : P->cap_marks) {
+        hipEventDestroy(m.ev[0]);
+        hipEventDestroy(m.ev[1]);
+    }
+    P->cap_marks.clear();
+    P->cap_error.clear();
+}
+
+// Before a replay: fresh events of the pool for every timing mark of the graph.
+static apx_status arm_mark_nodes(apx_problem* P) {
+    for (const auto& m : P->cap_marks) {
+        while (P->ev_pool.size() < P->ev_used + 2) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            P->ev_pool.push_back(e);
+        }
+        const size_t idx = P->ev_used;
+        P->ev_used += 2;
+        HIPCHK(hipGraphExecEventRecordNodeSetEvent(P->gexec, m.node[0], P->ev_pool[idx]));
+        HIPCHK(hipGraphExecEventRecordNodeSetEvent(P->gexec, m.node[1], P->ev_pool[idx + 1]));
+        P->ev_recs.emplace_back(m.klass, idx);
+    }
+    return APX_OK;
 }
 
 
@@ -1599,9 +1673,9 @@ apx_status apx_problem_timing(apx_problem* P, int32_t klass, double* total_ms, i
 
 apx_status apx_problem_destroy(apx_problem* P) {
     if (!P) return APX_OK;
+    if (P->ctx && P->ctx->stream) hipStreamSynchronize(P->ctx->stream);
+    drop_graph(P);
     for (hipEvent_t e : P->ev_pool) hipEventDestroy(e);
-    if (P->gexec) hipGraphExecDestroy(P->gexec);
-    if (P->graph) hipGraphDestroy(P->graph);
     delete P;
     return APX_OK;
 }
@@ -2382,23 +2456,36 @@ apx_status apx_lm_run(apx_problem* P, int32_t n_iter, const float* data, const f
     hipStream_t st = P->ctx->stream;
     if (!st) return fail(P->ctx, APX_E_INVALID, "graph capture needs a non-default stream");
     const void* key[4] = {data, weight, theta, state};
-    if (!P->gexec || std::memcmp(key, P->gkey, sizeof(key)) != 0) {
-        if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
-        if (P->graph) { hipGraphDestroy(P->graph); P->graph = nullptr; }
-        if (P->timing) return fail(P->ctx, APX_E_INVALID, "disable timing before graph capture");
+    const uint32_t mask = P->timing ? P->timing_mask : 0u;
+    if (!P->gexec || std::memcmp(key, P->gkey, sizeof(key)) != 0 || mask != P->gmask) {
+        drop_graph(P);
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         P->capturing = true;
         apx_status s = lm_step_enqueue(P, data, weight, theta, state);
         P->capturing = false;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(st, &g);
-        if (s != APX_OK) { if (g) hipGraphDestroy(g); return s; }
-        if (e != hipSuccess) return fail(P->ctx, APX_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+        if (s != APX_OK) {
+            if (g) hipGraphDestroy(g);
+            std::string m = P->cap_error;
+            drop_graph(P);
+            return m.empty() ? s : fail(P->ctx, APX_E_HIP, m + " (then: " + P->ctx->err + ")");
+        }
+        if (e != hipSuccess) { drop_graph(P); return fail(P->ctx, APX_E_HIP, std::string("capture: ") + hipGetErrorString(e)); }
         P->graph = g;
+        if (!P->cap_error.empty()) {
+            std::string m = P->cap_error;
+            drop_graph(P);
+            return fail(P->ctx, APX_E_HIP, m);
+        }
         HIPCHK(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0));
         std::memcpy(P->gkey, key, sizeof(key));
+        P->gmask = mask;
     }
-    for (int i = 0; i < n_iter; ++i) HIPCHK(hipGraphLaunch(P->gexec, st));
+    for (int i = 0; i < n_iter; ++i) {
+        if (mask) APXCHK(arm_mark_nodes(P));
+        HIPCHK(hipGraphLaunch(P->gexec, st));
+    }
     return APX_OK;
 }
 

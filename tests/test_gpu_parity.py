@@ -366,6 +366,37 @@ def test_lm_graph_replay_matches_eager(apx):
     assert np.array_equal(st1.cpu().numpy(), st2.cpu().numpy())
 
 
+def test_timing_inside_graph_replays(apx):
+    """HIP events captured into the iteration's graph: every replay records the same
+    launch groups as the eager iteration, with positive durations, and capturing under a
+    set of timing classes leaves the results unchanged."""
+    spec = get("small_blend")
+    P, d, w = problem(apx, spec)
+    th1, st1 = P.lm_init(spec["theta_init"], d, w)
+    P.set_timing(True)
+    P.lm_run(3, d, w, th1, st1, use_graph=False)
+    eager = P.timing()
+    th2, st2 = P.lm_init(spec["theta_init"], d, w)
+    P.set_timing(True)
+    P.lm_run(1, d, w, th2, st2, use_graph=True)
+    P.lm_run(2, d, w, th2, st2, use_graph=True)
+    graph = P.timing()
+    P.set_timing(True, classes=["conv_jcol"])         # another class set: captured again
+    P.lm_run(2, d, w, th2, st2, use_graph=True)
+    only = P.timing()
+    P.set_timing(False)
+    P.check()
+    th3, st3 = P.lm_init(spec["theta_init"], d, w)
+    P.lm_run(5, d, w, th3, st3, use_graph=False)
+    for k, (ms, n) in eager.items():
+        assert graph[k][1] == n, (k, graph[k], n)
+        assert n == 0 or graph[k][0] > 0.0, k
+    assert only["conv_jcol"][1] == 2 * eager["conv_jcol"][1] // 3 > 0
+    assert all(n == 0 for k, (_, n) in only.items() if k != "conv_jcol")
+    assert np.array_equal(th2.cpu().numpy(), th3.cpu().numpy())
+    assert np.array_equal(st2.cpu().numpy(), st3.cpu().numpy())
+
+
 def test_results_are_bitwise_reproducible(apx):
     spec = get("small_blend")
     P, d, w = problem(apx, spec)
