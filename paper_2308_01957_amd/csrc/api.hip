@@ -23,6 +23,7 @@ struct apx_ctx {
     std::map<int, std::array<double, 4>> tile_us;       // (kernel, P) -> measured us per tile
     void* tune_mem = nullptr;                           // autotuner scratch (allocated once)
     size_t tune_bytes = 0;
+    int pair_slots = 0;                                 // resident k_pair<64> workgroups
 };
 
 namespace {
@@ -327,6 +328,25 @@ static std::array<double, 4> tile_costs(apx_ctx* C, int key, int P) {
 // Tile shape of least estimated cost for an out_h x out_w output.  A shape must beat the
 // best lower-indexed (larger) one by more than 3 % to be taken: measured costs of
 // near-equal shapes wobble from run to run, and the larger tile re-reads less halo.
+// Workgroups of the 64-wide J^T W J tile kernel resident on the whole device at once; a
+// plan-only context takes gfx950's (256 compute units, 3 per unit at the kernel's 134
+// registers per lane).
+static int pair_slots(apx_ctx* C) {
+    if (C->pair_slots > 0) return C->pair_slots;
+    int per_cu = 3, n_cu = 256;
+    if (C->device >= 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, C->device) == hipSuccess && v > 0)
+            n_cu = v;
+        else
+            (void)hipGetLastError();
+        const int b = pair_blocks_per_cu(64);
+        if (b > 0) per_cu = b;
+    }
+    C->pair_slots = per_cu * n_cu;
+    return C->pair_slots;
+}
+
 static int choose_shape(apx_ctx* C, int key, int P, int out_h, int out_w) {
     if (C->tiles >= APX_TILES_FIXED && C->tiles < APX_TILES_FIXED + N_TILE_SHAPES) return C->tiles - APX_TILES_FIXED;
     if (out_h <= 0 || out_w <= 0) return 0;
@@ -1043,12 +1063,36 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         }
     }
 
-    // pairs of groups on one image whose output boxes intersect
+    // pairs of groups on one image whose output boxes intersect.  A pair's box is cut
+    // into K-slices of whole LDS stages (KC pixels of one row).  Narrow pairs (16-wide
+    // tiles) take slices of about 4096 pixels.  The 64-wide tile pairs share the grid in
+    // proportion to their work, so their items fill the resident workgroups of the chip
+    // about once (no second, partly empty wave of workgroups); each item still gets at
+    // least 32 stages.
     {
+        struct Wide { int pi, na, nb, tri, stages; };
+        std::vector<Wide> wide;
+        long long outoff = 0;
+        auto tile_pairs = [](int na, int nb, int tri) { return tri ? na * (na + 1) / 2 : na * nb; };
+        // K-slices outermost: the tile pairs that run together read the same rows of J
+        auto add_pair_items = [&](int pi, int na, int nb, bool tri, int stages, int per, int tm) {
+            for (int s0 = 0; s0 < stages; s0 += per)
+                for (int ta = 0; ta < na; ++ta)
+                    for (int tb = tri ? ta : 0; tb < nb; ++tb) {
+                        PairItem it{};
+                        it.pair = pi;
+                        it.ta = ta;
+                        it.tb = tb;
+                        it.s0 = s0;
+                        it.s1 = std::min(stages, s0 + per);
+                        it.out_off = outoff;
+                        outoff += (long long)tm * tm;
+                        (tm == 64 ? P->pitems64 : P->pitems16).push_back(it);
+                    }
+        };
         std::vector<std::vector<int>> by_img(d->n_images);
         for (int g = 0; g < n_groups; ++g)
             if (P->groups[g].oh > 0 && P->groups[g].ow > 0) by_img[P->groups[g].image].push_back(g);
-        long long outoff = 0;
         for (int k = 0; k < d->n_images; ++k) {
             const auto& gl = by_img[k];
             for (size_t a = 0; a < gl.size(); ++a)
@@ -1063,24 +1107,24 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
                     P->pairs.push_back(pr);
                     const int tm = (std::min(G.ncols, H.ncols) >= 48) ? 64 : 16;
                     const int na = ceil_div(G.ncols, tm), nb = ceil_div(H.ncols, tm);
-                    const int rows = y1 - y0, width = x1 - x0;
-                    const int kc_w = ceil_div(width, PAIR_KC) * PAIR_KC;
-                    const int rows_per = std::max(1, ceil_div(4096, kc_w));
-                    // K-slices outermost: the tiles that run together read the same rows of J
-                    for (int r0 = 0; r0 < rows; r0 += rows_per)
-                        for (int ta = 0; ta < na; ++ta)
-                            for (int tb = (gl[a] == gl[b] ? ta : 0); tb < nb; ++tb) {
-                                PairItem it{};
-                                it.pair = pi;
-                                it.ta = ta;
-                                it.tb = tb;
-                                it.r0 = y0 + r0;
-                                it.r1 = y0 + std::min(rows, r0 + rows_per);
-                                it.out_off = outoff;
-                                outoff += (long long)tm * tm;
-                                (tm == 64 ? P->pitems64 : P->pitems16).push_back(it);
-                            }
+                    const int stages = (y1 - y0) * ceil_div(x1 - x0, PAIR_KC);
+                    const bool tri = gl[a] == gl[b];
+                    if (tm == 64) {
+                        wide.push_back({pi, na, nb, tri ? 1 : 0, stages});
+                        continue;
+                    }
+                    add_pair_items(pi, na, nb, tri, stages, std::max(1, 4096 / PAIR_KC), 16);
                 }
+        }
+        long long work = 0;
+        for (const Wide& w : wide) work += (long long)tile_pairs(w.na, w.nb, w.tri) * w.stages;
+        const long long slots = pair_slots(P->ctx);
+        for (const Wide& w : wide) {
+            const int tp = tile_pairs(w.na, w.nb, w.tri);
+            const double share = (double)slots * tp * w.stages / (double)std::max(1LL, work);
+            int slices = std::max(1, (int)(share / tp));
+            slices = std::min(slices, std::max(1, w.stages / 32));
+            add_pair_items(w.pi, w.na, w.nb, w.tri, w.stages, ceil_div(w.stages, slices), 64);
         }
         P->n_pairpart = outoff;
     }

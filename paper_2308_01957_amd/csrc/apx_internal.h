@@ -133,7 +133,9 @@ struct DPair {
     int g, h, image, sub;
     int y0, x0, y1, x1;       // intersection of the two output boxes
 };
-struct PairItem { int pair, ta, tb, r0, r1, pad; long long out_off; };
+// one tile pair over stages [s0, s1) of the pair's box (stage s: row y0 + s / nxs, pixels
+// x0 + (s % nxs) KC ... of that row, nxs = ceil((x1 - x0) / KC))
+struct PairItem { int pair, ta, tb, s0, s1, pad; long long out_off; };
 
 // Adaptive integration: the Sersic windows cut into chunks of up to ADAPT_CHUNK pixels
 // (row-major window order); a pixel that needs sub-pixels is appended to the refine list.
@@ -328,6 +330,8 @@ hipError_t launch_fft_stamps(const Plan& p, int live_only, hipStream_t st);
 
 // k_jtwj.hip
 struct PairLaunch { const DPair* pairs; const PairItem* items; int n_items; int tm; };
+// Workgroups of k_pair<tm> resident per compute unit (0 if the runtime cannot say).
+int pair_blocks_per_cu(int tm);
 hipError_t launch_pairs(const Plan& p, const PairLaunch& L, const float* weight,
                         const apx_lm_state* lm, hipStream_t st);
 struct SegSum {

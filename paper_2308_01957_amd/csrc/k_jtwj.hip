@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     const long long lastB = (long long)(Hh.ncols - 1) * hs - Hh.ox0;
 
     const int nxs = (pr.x1 - pr.x0 + KC - 1) / KC;
-    const int n_stage = (it.r1 - it.r0) * nxs;
+    const int n_stage = it.s1 - it.s0;
     // two stages of global loads in flight (register ring): the loads of stage s+2 are
     // issued while the MFMAs consume stages s and s+1
     float ra0[PER], rb0[PER], rw0 = 0.f, ra1[PER], rb1[PER], rw1 = 0.f;
@@ -69,8 +69,9 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     // reads a valid entry and zeroes it afterwards), so the 2 PER + 1 loads of a stage go
     // out back to back instead of one branch each
     auto fetch = [&](int st, float (&ra)[PER], float (&rb)[PER], float& rw) {
-        const int row = it.r0 + st / nxs;
-        const int x = pr.x0 + (st - (st / nxs) * nxs) * KC + kq;
+        const int gs_ = it.s0 + st;
+        const int row = pr.y0 + gs_ / nxs;
+        const int x = pr.x0 + (gs_ - (gs_ / nxs) * nxs) * KC + kq;
         const bool in = x < pr.x1;
         const int xc = in ? x : pr.x1 - 1;
         const long long grow = (long long)(row - G.oy0) * G.ow + xc;
@@ -157,6 +158,17 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
         const int t = threadIdx.x;
         out[t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
     }
+}
+
+int pair_blocks_per_cu(int tm) {
+    int nb = 0;
+    const hipError_t e = tm == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair<64>, 256, 0)
+                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair<16>, 256, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
 }
 
 hipError_t launch_pairs(const Plan& p, const PairLaunch& L, const float* weight,
