@@ -462,6 +462,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also launch three plain copy kernels of MIB MiB (read MIB, write MIB) "
                          "after the timed region, to calibrate HBM byte counters")
+    ap.add_argument("--tile-costs-out", metavar="JSON",
+                    help="blend: write the autotuner's measured tile costs to JSON")
+    ap.add_argument("--tile-costs-in", metavar="JSON",
+                    help="blend: take the tile costs from JSON instead of timing them (the same "
+                         "tile shapes as the run that wrote it, e.g. under a counter profiler)")
     ap.add_argument("--conv", default="direct", choices=["direct", "fft"],
                     help="PSF convolution mode: direct (default) or FFT tiles for P >= 15")
     ap.add_argument("--workload", default="blend",
@@ -490,7 +495,13 @@ def main():
     img = spec["images"][0]
     P_psf = img["psf"].shape[0]
     print(f"[bench] workload {spec['name']}: {spec['n_par']} parameters", file=sys.stderr, flush=True)
-    prob = apx.Problem(_conv(args, spec))
+    costs = None
+    if args.tile_costs_in:
+        costs = {(int(k), P_psf): v for k, v in json.load(open(args.tile_costs_in)).items()}
+    prob = apx.Problem(_conv(args, spec), tile_costs=costs)
+    if args.tile_costs_out:
+        table = {k: prob.tile_cost(k, P_psf) for k in range(4)}
+        json.dump({k: v for k, v in table.items() if v is not None}, open(args.tile_costs_out, "w"))
     m_true = prob.split(prob.render(spec["theta_true"]))[0].astype(np.float64)
     prob.check()
     d, w = synth.make_data(m_true, spec["noise"][0])

@@ -268,6 +268,12 @@ apx_status apx_ctx_set_tiles(apx_ctx* ctx, int32_t policy);
  * `kernel` (0 model FP32, 1 Jacobian columns, 2 adjoint, 3 model FP64) at PSF size P, as
  * timed by the autotuner; APX_E_INVALID when that pair has not been timed. */
 apx_status apx_ctx_tile_cost(const apx_ctx* ctx, int32_t kernel, int32_t P, double* us);
+
+/* Set that table entry (us[4], positive and finite) instead of timing it: under
+ * APX_TILES_AUTOTUNE, problems created afterwards take their shapes from it.  Replays another
+ * run's choices, e.g. under a profiler that perturbs the timings.  APX_E_INVALID for a bad
+ * kernel, an even or out-of-range P, or a bad cost. */
+apx_status apx_ctx_set_tile_cost(apx_ctx* ctx, int32_t kernel, int32_t P, const double* us);
 apx_status apx_ctx_destroy(apx_ctx* ctx);
 const char* apx_last_error(const apx_ctx* ctx);
 

@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Dict, List, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
@@ -31,7 +31,7 @@ EXPORTS = [
     "apx_problem_bind_workspace", "apx_problem_sizes", "apx_problem_check", "apx_problem_destroy",
     "apx_render", "apx_chi2", "apx_jacobian", "apx_jtwj", "apx_chi2_grad", "apx_render_vjp", "apx_lm_init",
     "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
-    "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_problem_tile_shapes", "apx_covariance",
+    "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_ctx_set_tile_cost", "apx_problem_tile_shapes", "apx_covariance",
     "apx_covariance_factor", "apx_hmc_run", "apx_nuts_run", "apx_nuts_warmup", "apx_problem_set_timing_classes",
 ]
 TILES_AUTOTUNE, TILES_MODEL, TILES_FIXED = 0, 1, 2
@@ -161,6 +161,7 @@ def load_library(path: str = LIB_PATH):
         "apx_problem_timing": ([vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], i32),
         "apx_ctx_set_tiles": ([vp, i32], i32),
         "apx_ctx_tile_cost": ([vp, i32, i32, ctypes.POINTER(ctypes.c_double)], i32),
+        "apx_ctx_set_tile_cost": ([vp, i32, i32, ctypes.POINTER(ctypes.c_double)], i32),
         "apx_problem_tile_shapes": ([vp, i32, ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
@@ -204,7 +205,10 @@ def _descs(spec: Dict):
 class Problem:
     """A model/fit problem bound to one GPU: descriptor, workspace and stream."""
 
-    def __init__(self, spec: Dict, device: int = 0, objective: int = 0, tiles: int = TILES_AUTOTUNE):
+    def __init__(self, spec: Dict, device: int = 0, objective: int = 0, tiles: int = TILES_AUTOTUNE,
+                 tile_costs: Optional[Dict] = None):
+        """tile_costs: {(kernel, P): [us per tile of each shape]} entries of the autotuner's
+        table to use instead of timing them (as read back by tile_cost())."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("apx needs a ROCm GPU; none is visible")
@@ -225,6 +229,9 @@ class Problem:
         self._check(self.lib.apx_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream),
                                             ctypes.byref(self._ctx)), ctx=False)
         self._check(self.lib.apx_ctx_set_tiles(self._ctx, int(tiles)))
+        for (kernel, P), us in (tile_costs or {}).items():
+            arr = (ctypes.c_double * 4)(*[float(u) for u in us])
+            self._check(self.lib.apx_ctx_set_tile_cost(self._ctx, int(kernel), int(P), arr))
         idesc, cdesc, sp = _descs(spec)
         sampling = spec["sampling"]
         npm, pms = _psf_models(spec)

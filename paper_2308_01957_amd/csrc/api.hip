@@ -1465,6 +1465,18 @@ apx_status apx_ctx_tile_cost(const apx_ctx* ctx, int32_t kernel, int32_t P, doub
     return APX_OK;
 }
 
+apx_status apx_ctx_set_tile_cost(apx_ctx* ctx, int32_t kernel, int32_t P, const double* us) {
+    if (!ctx || !us || kernel < 0 || kernel > 3 || P < 1 || P > APX_MAX_PSF || (P & 1) == 0)
+        return APX_E_INVALID;
+    std::array<double, 4> cost;
+    for (int s = 0; s < N_TILE_SHAPES; ++s) {
+        if (!(us[s] > 0.0) || !std::isfinite(us[s])) return APX_E_INVALID;
+        cost[s] = us[s];
+    }
+    ctx->tile_us[kernel * 64 + P] = cost;
+    return APX_OK;
+}
+
 const char* apx_last_error(const apx_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 apx_status apx_problem_create(apx_ctx* ctx, const apx_problem_desc* desc, apx_problem** out) {

@@ -249,3 +249,24 @@ def test_masked_image_lm_step_is_a_no_op(apx):
     assert np.array_equal(th.cpu().numpy(), spec["theta_init"])
     s = P.lm_state(st)
     assert int(s["n_accept"][0]) == 0 and int(s["n_chol_retry"][0]) > 0
+
+
+def test_given_tile_costs_replace_the_timing(apx):
+    """Tile costs handed to the context (as a profiled run replays an earlier run's table)
+    decide the shapes: 16 x 32 made cheapest takes every job, and the Jacobian keeps its
+    parity with the oracle."""
+    spec = cases.small_blend()
+    Pk = int(np.asarray(spec["images"][0]["psf"]).shape[0])
+    costs = {(k, Pk): [100.0, 100.0, 100.0, 1.0] for k in range(4)}
+    print(f"[case] {spec['name']} tile costs", flush=True)
+    P = apx.Problem(spec, tile_costs=costs)
+    for kind in range(3):
+        counts = P.tile_shapes(kind)
+        assert counts[3] == sum(counts[:4]) > 0, (kind, counts)
+    assert P.tile_cost(1, Pk) == [100.0, 100.0, 100.0, 1.0]
+    th = spec["theta_init"]
+    J = P.jacobian(th).cpu().numpy().T.astype(np.float64)
+    Jo = oracle.jacobian(spec, th)
+    scale = np.maximum(np.max(np.abs(Jo), axis=0), 1e-30)
+    assert np.all(np.max(np.abs(J - Jo), axis=0) <= 3e-5 * scale)
+    P.check()

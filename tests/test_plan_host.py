@@ -182,3 +182,26 @@ def test_recentring_grows_windows_by_the_taps(apx):
         h, w = win[2] - win[0] + 6, win[3] - win[1] + 6          # output box: window + c
         grown = min(40, win[2] + 3 + a) - max(0, win[0] - 3 - a), min(52, win[3] + 3 + a) - max(0, win[1] - 3 - a)
         assert n - n0 == 14 * (grown[0] * grown[1] - h * w)
+
+
+def test_tile_cost_table_can_be_set_and_read_back(apx):
+    """A host context stores autotuner table entries given to it and rejects bad ones."""
+    import ctypes
+    lib = apx.load_library()
+    ctx = ctypes.c_void_p()
+    assert lib.apx_ctx_create(-1, None, ctypes.byref(ctx)) == apx.APX_OK
+    try:
+        us = (ctypes.c_double * 4)(3.0, 2.5, 2.0, 1.25)
+        out = (ctypes.c_double * 4)()
+        assert lib.apx_ctx_tile_cost(ctx, 1, 25, out) != apx.APX_OK        # not timed yet
+        assert lib.apx_ctx_set_tile_cost(ctx, 1, 25, us) == apx.APX_OK
+        assert lib.apx_ctx_tile_cost(ctx, 1, 25, out) == apx.APX_OK
+        assert list(out) == [3.0, 2.5, 2.0, 1.25]
+        for kernel, P in [(4, 25), (-1, 25), (1, 24), (1, 0), (1, 65)]:
+            assert lib.apx_ctx_set_tile_cost(ctx, kernel, P, us) != apx.APX_OK, (kernel, P)
+        for bad in (0.0, -1.0, float("nan"), float("inf")):
+            b = (ctypes.c_double * 4)(1.0, bad, 1.0, 1.0)
+            assert lib.apx_ctx_set_tile_cost(ctx, 1, 25, b) != apx.APX_OK, bad
+        assert lib.apx_ctx_tile_cost(ctx, 1, 25, out) == apx.APX_OK and list(out) == [3.0, 2.5, 2.0, 1.25]
+    finally:
+        lib.apx_ctx_destroy(ctx)
