@@ -33,6 +33,18 @@ def small_blend():
     return with_data(spec)
 
 
+def wide_groups():
+    """Two Sersic groups wide enough for the 64-column J^T W J tiles on one 70x80 image:
+    12 Sersics on the full window (84 columns: a full 64-column block and a ragged one) and
+    8 on a shared partial window (56 columns), plus point sources and sky; each wide group
+    meets itself and the other one on the 64-column tile path."""
+    spec = synth.blend(seed_id=131, H=70, W=80, n_sersic=20, n_point=2, P=7)
+    for q in range(12, 20):
+        spec["comps"][q]["box"] = (6, 9, 62, 70)
+    spec["name"] = "wide_groups70x80"
+    return with_data(spec)
+
+
 def affine_pair():
     """Two images with rotated/scaled/shifted pixel->sky maps, different PSF sizes,
     two Sersics with tied shape parameters and per-image brightness and sky,

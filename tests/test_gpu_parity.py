@@ -27,6 +27,7 @@ SPECS = {
     "single64": cases.single64,
     "few_cutouts": cases.few_cutouts,
     "large_sub": cases.large_sub,
+    "wide_groups": cases.wide_groups,
 }
 _CACHE = {}
 
