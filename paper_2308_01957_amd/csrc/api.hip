@@ -1829,17 +1829,16 @@ static apx_status fwd_chi2(apx_problem* P, const double* theta, const float* dat
     APXCHK(run_conv(P, CONV_FWD, io));
     if (data) {
         TimeScope ts(P, APX_TIME_REDUCE);
-        for (int q = 0; q < 3; ++q) {
-            SegSum a = segsum_base();
+        {
+            SegSum a = segsum_base();               // sum w r^2, sum w r, sum w per image
             a.src = p.fwd_part;
             a.stride = 3;
-            a.comp = q;
+            a.ncomp = 3;
             a.seg = wsp<int>(P, "img_seg");
             a.idx = wsp<int>(P, "img_idx");
             a.n_seg = P->n_images;
             a.out = p.img_sum;
             a.ostride = 3;
-            a.ocomp = q;
             HIPCHK(launch_segsum(a, st));
         }
         if (chi2_out) {
@@ -1879,19 +1878,16 @@ static apx_status psf_columns(apx_problem* P, const float* weight, int skip_mode
 static apx_status col_sums(apx_problem* P) {
     const Plan& p = P->plan;
     TimeScope ts(P, APX_TIME_REDUCE);
-    for (int q = 0; q < 2; ++q) {
-        SegSum a = segsum_base();
-        a.src = p.jcol_part;
-        a.stride = 2;
-        a.comp = q;
-        a.seg = wsp<int>(P, "col_seg");
-        a.idx = wsp<int>(P, "col_idx");
-        a.n_seg = (int)P->cols.size();
-        a.out = p.col_sum;
-        a.ostride = 2;
-        a.ocomp = q;
-        HIPCHK(launch_segsum(a, P->ctx->stream));
-    }
+    SegSum a = segsum_base();                       // sum w r J, sum w J per column
+    a.src = p.jcol_part;
+    a.stride = 2;
+    a.ncomp = 2;
+    a.seg = wsp<int>(P, "col_seg");
+    a.idx = wsp<int>(P, "col_idx");
+    a.n_seg = (int)P->cols.size();
+    a.out = p.col_sum;
+    a.ostride = 2;
+    HIPCHK(launch_segsum(a, P->ctx->stream));
     return APX_OK;
 }
 

@@ -341,6 +341,7 @@ struct SegSum {
     double* out; int ostride, ocomp;
     double scale;
     const int* seg_sub; const apx_lm_state* lm;
+    int ncomp;                                // components comp .. comp + ncomp - 1 (0: one)
 };
 hipError_t launch_segsum(const SegSum& a, hipStream_t st);
 struct AsmA {

@@ -184,25 +184,30 @@ hipError_t launch_pairs(const Plan& p, const PairLaunch& L, const float* weight,
 // out[s*ostride + ocomp] = scale * sum_k wts[k] * src[(idx ? idx[k] : k) * stride + comp],
 // k in [seg[s], seg[s+1]).  One wave per segment: lane l sums entries l, l+64, ... in
 // order, then a fixed butterfly combines the lanes -- the same order on every run.
-// Segments of sub-problems that keep their Jacobian are skipped when lm is given.
+// Segments of sub-problems that keep their Jacobian are skipped when lm is given.  With
+// ncomp > 1 one launch sums components comp + q into ocomp + q (q < ncomp), one wave per
+// (segment, component), each in the same order as a launch of its own.
 __global__ __launch_bounds__(256) void k_segsum(SegSum a) {
-    const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nc = a.ncomp > 1 ? a.ncomp : 1;
+    const int sf = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (s >= a.n_seg) return;
+    if (sf >= a.n_seg * nc) return;
+    const int s = sf / nc, q = sf - s * nc;
     if (a.lm && a.seg_sub && a.lm[a.seg_sub[s]].need_jac == 0) return;
     double acc = 0.0;
     for (int k = a.seg[s] + lane; k < a.seg[s + 1]; k += 64) {
         const long long j = a.idx ? (long long)a.idx[k] : (long long)k;
-        const double v = a.src[j * a.stride + a.comp];
+        const double v = a.src[j * a.stride + a.comp + q];
         acc += a.wts ? a.wts[k] * v : v;
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) a.out[(long long)s * a.ostride + a.ocomp] = acc * a.scale;
+    if (lane == 0) a.out[(long long)s * a.ostride + a.ocomp + q] = acc * a.scale;
 }
 
 hipError_t launch_segsum(const SegSum& a, hipStream_t st) {
-    if (a.n_seg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_segsum, dim3((a.n_seg + 3) / 4), dim3(256), 0, st, a);
+    const long long n = (long long)a.n_seg * (a.ncomp > 1 ? a.ncomp : 1);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_segsum, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
