@@ -2464,8 +2464,8 @@ static apx_status lm_step_enqueue(apx_problem* P, const float* data, const float
     hipStream_t st = P->ctx->stream;
     {
         TimeScope ts(P, APX_TIME_LM);
-        HIPCHK(launch_lm_begin(p, state, st));
-        if (!P->large_subs.empty()) HIPCHK(launch_lm_adopt(p, state, st));
+        if (P->large_subs.empty()) HIPCHK(launch_lm_begin(p, state, st));
+        else HIPCHK(launch_lm_begin_adopt(p, state, st));
     }
     // normal equations at theta for sub-problems whose last step was accepted
     APXCHK(prep(P, theta, 0, 2, state, 1));

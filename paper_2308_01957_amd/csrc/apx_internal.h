@@ -364,7 +364,7 @@ hipError_t launch_chi2_check(const double* chi2, int n, int* sticky, hipStream_t
 // k_lm.hip
 hipError_t launch_lm_begin(const Plan& p, apx_lm_state* lm, hipStream_t st);
 // large sub-problems whose step was solved ahead take it (step, pred, lambda, retries)
-hipError_t launch_lm_adopt(const Plan& p, apx_lm_state* lm, hipStream_t st);
+hipError_t launch_lm_begin_adopt(const Plan& p, apx_lm_state* lm, hipStream_t st);
 hipError_t launch_lm_init(const Plan& p, const double* chi2_sub, apx_lm_state* lm, hipStream_t st);
 hipError_t launch_chol_small(const Plan& p, const int* small_subs, int n_small, int nmax,
                              apx_lm_state* lm, hipStream_t st);

@@ -41,12 +41,31 @@ hipError_t launch_lm_begin(const Plan& p, apx_lm_state* lm, hipStream_t st) {
     return hipGetLastError();
 }
 
-// One wave per sub-problem: an adopting sub-problem takes the step, its predicted decrease,
-// lambda and retry count from the solve made ahead (exactly what solving now would give:
-// same A, D, g and starting lambda, same kernels); the record is used up.
-__global__ __launch_bounds__(64) void k_lm_adopt(Plan p, apx_lm_state* lm) {
+// k_lm_begin, then adoption, in one launch with one wave per sub-problem (for problems with
+// a large sub-problem, whose solves are made ahead): lane 0 sets the flags as k_lm_begin does;
+// an adopting sub-problem then takes the step, its predicted decrease, lambda and retry
+// count from the solve made ahead (exactly what solving now would give: same A, D, g and
+// starting lambda, same kernels), and the record is used up.
+__global__ __launch_bounds__(64) void k_lm_begin_adopt(Plan p, apx_lm_state* lm) {
     const int s = blockIdx.x;
-    if (!p.lmf[s].adopted) return;
+    int adopted = 0;
+    if (threadIdx.x == 0) {
+        LMFlags f;
+        f.chol_done = 0;
+        f.chol_fail = 0;
+        f.trial_bad = 0;
+        f.skip = 0;
+        f.subst_fail = 0;
+        f.rhs_folded = 0;
+        f.adopted = 0;
+        p.lmf[p.n_sub + s] = f;
+        const LMSpec sp = p.spec[s];
+        f.adopted = p.subs[s].large && sp.valid && lm[s].need_jac == 0 && lm[s].lambda == sp.lam_start;
+        p.lmf[s] = f;
+        adopted = f.adopted;
+    }
+    adopted = __shfl(adopted, 0, 64);
+    if (!adopted) return;
     const DSub sb = p.subs[s];
     for (int i = (int)threadIdx.x; i < sb.n; i += 64) p.hvec[sb.p0 + i] = p.hvec[p.n_par + sb.p0 + i];
     if (threadIdx.x == 0) {
@@ -59,8 +78,8 @@ __global__ __launch_bounds__(64) void k_lm_adopt(Plan p, apx_lm_state* lm) {
     }
 }
 
-hipError_t launch_lm_adopt(const Plan& p, apx_lm_state* lm, hipStream_t st) {
-    hipLaunchKernelGGL(k_lm_adopt, dim3(p.n_sub), dim3(64), 0, st, p, lm);
+hipError_t launch_lm_begin_adopt(const Plan& p, apx_lm_state* lm, hipStream_t st) {
+    hipLaunchKernelGGL(k_lm_begin_adopt, dim3(p.n_sub), dim3(64), 0, st, p, lm);
     return hipGetLastError();
 }
 
@@ -368,22 +387,45 @@ __global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
 // M = A + lambda D, and the working right-hand side yvec = J^T W r that the first
 // factorisation attempt turns into y = L^-1 g as it goes.
 // Copy 0 (blockIdx.y = 0) takes this iteration's lambda, copy 1 the solve-ahead
-// lambda' = min(UP lambda, max).
+// lambda' = min(UP lambda, max).  The damping diagonal D (the diagonal of A, floored at
+// APX_LM_DAMP_FLOOR times its maximum) is formed by every block from the diagonal of A, the
+// same values k_chol_damp stores; block 0 of each copy also stores D (copy 0) and clears
+// that copy's flags, which k_chol_damp does for the other solves.
 __global__ void k_chol_fill(Plan p, int s, apx_lm_state* lm) {
+    __shared__ double red[4];
     if (p.lmf[s].adopted) return;
     const int which = blockIdx.y;
     const Plan q = solve_view(p, which);
     const DSub sb = p.subs[s];
     const int n = sb.n;
+    const double* A = p.A + sb.a_off;
+    double m = -1e308;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, A[(long long)i * n + i]);
+    m = lm_wave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    const double dfloor = APX_LM_DAMP_FLOOR * fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (blockIdx.x == 0) {
+        if (which == 0)
+            for (int i = threadIdx.x; i < n; i += blockDim.x)
+                p.Ddiag[sb.p0 + i] = fmax(A[(long long)i * n + i], dfloor);
+        const int nflag = 2 * ((n + CHOL_NB - 1) / CHOL_NB);
+        for (int i = threadIdx.x; i < nflag; i += blockDim.x) q.sflag[sb.flag_off + i] = 0;
+        if (threadIdx.x == 0) {
+            q.lmf[s].chol_fail = 0;
+            q.lmf[s].subst_fail = 0;
+            q.lmf[s].rhs_folded = 0;
+        }
+    }
     const double lam = which ? fmin(lm[s].lambda * APX_LM_UP, APX_LM_LAMBDA_MAX) : lm[s].lambda;
     if (which && blockIdx.x == 0 && threadIdx.x == 0) p.spec[s].lam_start = lam;
     const long long nn = (long long)n * n;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
          e += (long long)gridDim.x * blockDim.x) {
         const int i = (int)(e / n), j = (int)(e - (long long)i * n);
-        double v = p.A[sb.a_off + e];
+        double v = A[e];
         if (i == j) {
-            v += lam * p.Ddiag[sb.p0 + i];
+            v += lam * fmax(v, dfloor);
             q.yvec[sb.p0 + i] = p.gvec[sb.p0 + i];
         }
         q.M[sb.a_off + e] = v;
@@ -909,7 +951,6 @@ hipError_t launch_chol_blocks(const Plan& p, int s, int n, hipStream_t st) {
 
 hipError_t launch_chol_large(const Plan& p, int s, int n, apx_lm_state* lm, hipStream_t st) {
     const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
-    hipLaunchKernelGGL(k_chol_damp, dim3(1), dim3(256), 0, st, p, s, lm);
     const long long nn = (long long)n * n;
     long long fb = (nn + 255) / 256;
     if (fb > 4096) fb = 4096;
