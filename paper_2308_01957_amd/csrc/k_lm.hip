@@ -358,7 +358,8 @@ __device__ __forceinline__ void stage_block(const double* Mg, int n, int r0, int
 
 __global__ void k_chol_damp(Plan p, int s, apx_lm_state* lm) {
     // one block: damping diagonal D from the diagonal of A and its maximum; clears the
-    // flags of copy 0 (and, in the LM, of the solve-ahead copy 1)
+    // flags of copy 0 (and, given lm, of the solve-ahead copy 1).  The LM's large solves
+    // form D inside k_chol_fill instead; this kernel serves the covariance factorisation.
     __shared__ double red[4];
     if (lm && p.lmf[s].adopted) return;
     const DSub sb = p.subs[s];
