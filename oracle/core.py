@@ -240,6 +240,17 @@ def adaptive_pixels(im, comp, prm, tol, with_grad=False):
     return val
 
 
+def within_k_re(ux, uy, prm, k):
+    """Pixels whose centre (sky position ux, uy) lies strictly inside the isophote of
+    elliptical radius k Re (§2.1.2: the first, cheap pass at the pixel centre; the fine
+    nodes only where the profile is steep)."""
+    x0, y0, q, pa = prm[0], prm[1], prm[2], prm[3]
+    dx, dy = ux - x0, uy - y0
+    xp = dx * math.cos(pa) + dy * math.sin(pa)
+    yp = -dx * math.sin(pa) + dy * math.cos(pa)
+    return np.sqrt(xp * xp + (yp / q) ** 2) < k * prm[5]
+
+
 def sersic_pixels(im, comp, prm, sampling, with_grad=False):
     """Pixel-integrated Sersic (area x weighted node mean) over the component window;
     returns the value on the window and, if asked, the 7 derivative images."""
@@ -266,11 +277,7 @@ def sersic_pixels(im, comp, prm, sampling, with_grad=False):
     if mode == MODE_WITHIN_K_RE:
         # the centre alone outside k Re (pixel-centre elliptical radius, strict <)
         ux, uy = _sky_coords(a, xx, yy)
-        x0, y0, q, pa = prm[0], prm[1], prm[2], prm[3]
-        dx, dy = ux - x0, uy - y0
-        xp = dx * math.cos(pa) + dy * math.sin(pa)
-        yp = -dx * math.sin(pa) + dy * math.cos(pa)
-        inside = np.sqrt(xp * xp + (yp / q) ** 2) < sampling["k"] * prm[5]
+        inside = within_k_re(ux, uy, prm, sampling["k"])
         r = sersic_profile(ux, uy, prm, b, with_grad, bp)
         if with_grad:
             val = np.where(inside, val, r[0])
@@ -751,6 +758,12 @@ def cholesky_or_none(M: np.ndarray):
     return L
 
 
+def lm_predicted_decrease(h, lam, D, g) -> float:
+    """chi2 decrease the linearised model predicts for the step h of (A + lam D) h = g:
+    2 h.g - h.A.h, which the normal equations turn into h.(lam D h + g)."""
+    return float(h @ (lam * D * h + g))
+
+
 def lm_fit_sub(spec, theta0, data, weight, sub: int, n_iter: int):
     """n_iter LM iterations on one sub-problem; returns (theta, history).
 
@@ -788,7 +801,7 @@ def lm_fit_sub(spec, theta0, data, weight, sub: int, n_iter: int):
         h = np.linalg.solve(L.T, y)
         trial = theta.copy()
         trial[p0:p0 + npar] += h
-        pred = float(h @ (lam * D * h + g))
+        pred = lm_predicted_decrease(h, lam, D, g)
         if in_domain(spec, trial, sub):
             c2t = chi2_images(spec, trial, data, weight, ks)
             rho = (c2 - c2t) / pred if pred != 0.0 else float("nan")

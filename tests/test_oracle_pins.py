@@ -691,3 +691,159 @@ def test_superres_jacobian_matches_central_differences():
         scale = np.max(np.abs(J[:, p]))
         assert scale > 0, p
         assert np.max(np.abs(fd - J[:, p])) < 1e-7 * scale, p
+
+
+# ------------------------------------------- 3 x 3 nodes within k Re, centre elsewhere
+def _profile_scalar(x, y, x0, y0, q, pa, b, n, re, ie):
+    """Sersic profile at one point, written out with the elliptical radius as the quadratic
+    form d^T M d, M = R^T diag(1, 1/q^2) R for the rotation R by PA (b from the table)."""
+    c, s = math.cos(pa), math.sin(pa)
+    M = np.array([[c * c + s * s / q ** 2, c * s - c * s / q ** 2],
+                  [c * s - c * s / q ** 2, s * s + c * c / q ** 2]])
+    d = np.array([x - x0, y - y0])
+    R2 = float(d @ M @ d)
+    R = max(math.sqrt(R2), 1e-6)          # the cusp's radius floor (reading: R >= 1e-6 px)
+    return ie * math.exp(-b * ((R / re) ** (1.0 / n) - 1.0)), R2
+
+
+def _within_kre_reference(H, W, prm, k, s=3):
+    """Plain loop over pixels: s x s midpoint mean where the centre's elliptical radius is
+    below k Re, the centre value elsewhere (the first-pass midpoint of §2.1.2)."""
+    x0, y0, q, pa, n, re, lie = prm
+    b = {row[0]: row[1] for row in _read_table("sersic_bn_erlang.txt")}[n]
+    ref = np.zeros((H, W))
+    inside = np.zeros((H, W), bool)
+    offs = [(k_ + 0.5) / s - 0.5 for k_ in range(s)]
+    for i in range(H):
+        for j in range(W):
+            vc, R2 = _profile_scalar(j, i, x0, y0, q, pa, b, n, re, 10.0 ** lie)
+            if R2 < (k * re) ** 2:
+                inside[i, j] = True
+                ref[i, j] = sum(_profile_scalar(j + ox, i + oy, x0, y0, q, pa, b, n, re, 10.0 ** lie)[0]
+                                for oy in offs for ox in offs) / (s * s)
+            else:
+                ref[i, j] = vc
+    return ref, inside
+
+
+def _within_kre_render(H, W, prm, k):
+    spec = _render_spec(H, W, 1, [_sersic_comp(prm, (0, 0, H, W))], s=3, mode=oracle.MODE_WITHIN_K_RE, k=k)
+    return oracle.model_image(spec, np.zeros(0), 0)
+
+
+def test_within_k_re_sampling_matches_pixel_loop():
+    """q < 1 and a rotated major axis: pixels whose centres straddle 2 Re take the 3 x 3
+    node mean inside (strict <) and the centre value outside; checked against a plain
+    loop over pixels, with some pixels on each side of the isophote."""
+    H, W, prm = 16, 18, (8.3, 7.6, 0.45, 0.7, 1.0, 2.5, 0.3)
+    ref, inside = _within_kre_reference(H, W, prm, 2.0)
+    assert 10 < inside.sum() < H * W - 10
+    m = _within_kre_render(H, W, prm, 2.0)
+    assert np.allclose(m, ref, rtol=1e-13, atol=0)
+    # the inside and outside rules differ by far more than the tolerance on the boundary
+    ring = inside & ~np.roll(inside, 1, 0)
+    assert np.all(np.abs(ref[ring] - _within_kre_reference(H, W, prm, 1e-9)[0][ring]) > 1e-6 * ref[ring])
+
+
+def test_within_k_re_threshold_is_strict():
+    """PA = 0: pixel centres exactly 2 Re from the centre along the major axis have R = 5
+    exactly and take the centre value."""
+    H, W, prm = 15, 19, (8.0, 7.0, 0.5, 0.0, 2.0, 2.5, 0.1)
+    ref, inside = _within_kre_reference(H, W, prm, 2.0)
+    assert not inside[7, 13] and not inside[7, 3] and inside[7, 12]
+    m = _within_kre_render(H, W, prm, 2.0)
+    assert np.allclose(m, ref, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("mistake", ["circular", "inverted", "non_strict", "pa_sign"])
+def test_planted_within_k_re_mistakes_fail(monkeypatch, mistake):
+    """A circular radius, an inverted mask, <= for <, or the position angle taken clockwise
+    in the inside test each fail one of the two pins above."""
+    orig = oracle.core.within_k_re
+
+    def bad(ux, uy, prm, k):
+        x0, y0, q, pa = prm[0], prm[1], prm[2], prm[3]
+        if mistake == "circular":
+            return np.hypot(ux - x0, uy - y0) < k * prm[5]
+        if mistake == "inverted":
+            return ~orig(ux, uy, prm, k)
+        if mistake == "pa_sign":
+            return orig(ux, uy, (x0, y0, q, -pa) + tuple(prm[4:]), k)
+        dx, dy = ux - x0, uy - y0
+        xp = dx * math.cos(pa) + dy * math.sin(pa)
+        yp = -dx * math.sin(pa) + dy * math.cos(pa)
+        return np.sqrt(xp * xp + (yp / q) ** 2) <= k * prm[5]
+    monkeypatch.setattr(oracle.core, "within_k_re", bad)
+    with pytest.raises(AssertionError):
+        test_within_k_re_sampling_matches_pixel_loop()
+        test_within_k_re_threshold_is_strict()
+
+
+# ------------------------------------------------------------ LM gain ratio (§2.5)
+def _sky_only_problem():
+    spec, theta = _small_problem()
+    m = oracle.model_image(spec, theta, 0)
+    d, w = synth.make_data(m, np.random.default_rng(4).standard_normal(m.shape), np.float64)
+    for c in spec["comps"]:
+        c["fixed"] = oracle.local_params(c, theta)
+        c["par"] = [-1] * 7
+    spec["subs"] = [(15, 1)]
+    t0 = theta.copy()
+    t0[15] = 0.2
+    return spec, t0, d, w
+
+
+def test_lm_gain_ratio_is_one_for_a_linear_model():
+    """With only the sky free the model is linear in theta, so chi^2 is exactly the
+    quadratic the LM linearises and the measured decrease equals the predicted one: the
+    gain ratio of the first trial is 1 (to rounding)."""
+    spec, t0, d, w = _sky_only_problem()
+    _, hist = oracle.lm_fit(spec, t0, [d], [w], 1)
+    rec = hist[0][0]
+    assert rec["accepted"] and abs(rec["rho"] - 1.0) <= 1e-9, rec
+
+
+def test_lm_predicted_decrease_is_the_quadratic_model_decrease():
+    """On the nonlinear 16-parameter problem the predicted decrease of each trial equals
+    2 h.g - h.A.h for the step h solved afresh by numpy from (A + lambda D) h = g (the
+    decrease of the linearised chi^2), and rho = (chi2 - chi2_trial) / pred.  The
+    iterates are replayed from the history with those steps."""
+    spec, theta = _small_problem()
+    m = oracle.model_image(spec, theta, 0)
+    d, w = synth.make_data(m, np.random.default_rng(8).standard_normal(m.shape), np.float64)
+    t0 = theta.copy()
+    t0[[0, 5, 9]] += [0.3, 0.4, 0.05]
+    _, hist = oracle.lm_fit(spec, t0, [d], [w], 8)
+    th = t0.copy()
+    seen = 0
+    for it, rec in enumerate(hist[0]):
+        A, g, c2 = oracle.jtwj(spec, th, [d], [w])
+        D = np.maximum(np.diag(A), oracle.LM_DAMP_FLOOR * np.max(np.diag(A)))
+        h = np.linalg.solve(A + rec["lam"] * np.diag(D), g)
+        pred = 2.0 * h @ g - h @ A @ h
+        assert rec["pred"] == pytest.approx(pred, rel=1e-9), it
+        if oracle.in_domain(spec, th + h, 0):
+            c2t = oracle.chi2(spec, th + h, [d], [w])[0]
+            assert rec["rho"] == pytest.approx((c2 - c2t) / pred, rel=1e-7, abs=1e-9), it
+            seen += 1
+        if rec["accepted"]:
+            th = th + h
+    assert seen >= 4
+
+
+def test_planted_gain_ratio_denominator_fails(monkeypatch):
+    """Predicting the decrease as h.g (the lambda D h term dropped) breaks both pins."""
+    monkeypatch.setattr(oracle.core, "lm_predicted_decrease", lambda h, lam, D, g: float(h @ g))
+    with pytest.raises(AssertionError):
+        test_lm_gain_ratio_is_one_for_a_linear_model()
+    with pytest.raises(AssertionError):
+        test_lm_predicted_decrease_is_the_quadratic_model_decrease()
+
+
+def test_golden_fixtures_are_what_their_script_writes():
+    """The stored fixtures are reproduced exactly by tests/golden/make_golden.py."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(GOLD, "make_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    assert mod.main(check=True) == 0
