@@ -302,6 +302,17 @@ apx_status apx_problem_tile_shapes(const apx_problem* p, int32_t kind, int32_t* 
  * APX_E_DOMAIN, APX_E_NONFINITE, or APX_E_HIP when a substitution hand-off wait of the
  * damped solve ran out (that iteration's step was dropped). */
 apx_status apx_problem_check(apx_problem* p);
+
+/* Bound of the damped solve's substitution hand-off waits (the blocked Cholesky path of
+ * sub-problems with more than 64 parameters, §2.5).  Each wait polls a flag that an
+ * earlier workgroup of the same launch raises; one that polls `polls` times without
+ * seeing it gives up, raises the sticky flag reported as APX_E_HIP by apx_problem_check,
+ * and that iteration's step is dropped (theta and lambda as after a failed factorisation).
+ * polls > 0: the bound; 0: the default (2^22 polls); polls < 0: every wait takes its flag
+ * as never raised and gives up after -polls polls -- a way to exercise the give-up path
+ * from the host in which every kernel still ends normally.  Synchronises the stream and
+ * drops a captured LM iteration graph.  APX_E_WORKSPACE before bind_workspace. */
+apx_status apx_problem_set_wait_limit(apx_problem* p, int32_t polls);
 apx_status apx_problem_destroy(apx_problem* p);
 
 /* Kernel timing (tracing aid).  When enabled, every launch group of the hot path is

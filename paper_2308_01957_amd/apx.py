@@ -33,6 +33,7 @@ EXPORTS = [
     "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
     "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_ctx_set_tile_cost", "apx_problem_tile_shapes", "apx_covariance",
     "apx_covariance_factor", "apx_hmc_run", "apx_nuts_run", "apx_nuts_warmup", "apx_problem_set_timing_classes",
+    "apx_problem_set_wait_limit",
 ]
 TILES_AUTOTUNE, TILES_MODEL, TILES_FIXED = 0, 1, 2
 TILE_SHAPES = [(32, 64), (16, 64), (32, 32), (16, 32)]       # output rows x cols per workgroup
@@ -119,6 +120,24 @@ class ApxError(RuntimeError):
 _LIB = None
 
 
+def check_buffer(t, device, dtype, numel: int, name: str):
+    """Raise ApxError(APX_E_INVALID) unless t is a contiguous torch tensor of the given
+    device, dtype and element count: a pointer handed to the library must be device memory
+    of the size its kernels index."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ApxError(APX_E_INVALID, f"{name}: a torch tensor is required, got {type(t).__name__}")
+    if t.device != device:
+        raise ApxError(APX_E_INVALID, f"{name}: on {t.device}, the problem is on {device}")
+    if t.dtype != dtype:
+        raise ApxError(APX_E_INVALID, f"{name}: dtype {t.dtype}, {dtype} required")
+    if not t.is_contiguous():
+        raise ApxError(APX_E_INVALID, f"{name}: not contiguous")
+    if t.numel() != numel:
+        raise ApxError(APX_E_INVALID, f"{name}: {t.numel()} elements, {numel} required")
+    return t
+
+
 def load_library(path: str = LIB_PATH):
     """Load libapx.so (raises if it has not been built)."""
     global _LIB
@@ -140,6 +159,7 @@ def load_library(path: str = LIB_PATH):
         "apx_problem_bind_workspace": ([vp, vp, u64], i32),
         "apx_problem_sizes": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
         "apx_problem_check": ([vp], i32),
+        "apx_problem_set_wait_limit": ([vp, i32], i32),
         "apx_problem_destroy": ([vp], i32),
         "apx_render": ([vp, vp, vp], i32),
         "apx_chi2": ([vp, vp, vp, vp, vp], i32),
@@ -285,6 +305,16 @@ class Problem:
             if t is not None:
                 t.record_stream(self.stream)
 
+    def _pix(self, data, weight):
+        t = self.torch
+        check_buffer(data, self.device, t.float32, self.n_pix, "data")
+        check_buffer(weight, self.device, t.float32, self.n_pix, "weight")
+
+    def _lm_bufs(self, theta, state):
+        t = self.torch
+        check_buffer(theta, self.device, t.float64, self.n_par, "theta")
+        check_buffer(state, self.device, t.uint8, self.n_sub * LM_STATE_BYTES, "state")
+
     def _leave(self):
         self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
@@ -295,6 +325,13 @@ class Problem:
                 x = x.to(device=self.device, dtype=dtype).contiguous()
             return x
         return t.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=self.device)
+
+    def _theta(self, x):
+        """theta as a contiguous FP64 tensor on the problem's device, of n_par entries."""
+        th = self._dev(x, self.torch.float64)
+        if th.numel() != self.n_par:
+            raise ApxError(APX_E_INVALID, f"theta: {th.numel()} elements, {self.n_par} required")
+        return th
 
     def pixels(self, arrays: Sequence[np.ndarray]):
         """Concatenate per-image arrays into one FP32 device pixel buffer."""
@@ -312,23 +349,31 @@ class Problem:
     def synchronize(self):
         self.stream.synchronize()
 
+    def set_wait_limit(self, polls: int):
+        """Bound of the damped solve's hand-off waits (0: default; < 0: flags taken as never
+        raised, every wait gives up after -polls polls and its step is dropped)."""
+        self._check(self.lib.apx_problem_set_wait_limit(self._prob, int(polls)))
+
     # ----------------------------------------------------------------- hot path
     def render(self, theta, out=None):
-        th = self._dev(theta, self.torch.float64)
+        th = self._theta(theta)
         self._enter(th)
         with self.torch.cuda.stream(self.stream):
             if out is None:
                 out = self.torch.empty(self.n_pix, dtype=self.torch.float32, device=self.device)
+            check_buffer(out, self.device, self.torch.float32, self.n_pix, "out")
             self._check(self.lib.apx_render(self._prob, th.data_ptr(), out.data_ptr()))
         self._leave()
         return out
 
     def chi2(self, theta, data, weight, out=None):
-        th = self._dev(theta, self.torch.float64)
+        th = self._theta(theta)
+        self._pix(data, weight)
         self._enter(th, data, weight)
         with self.torch.cuda.stream(self.stream):
             if out is None:
                 out = self.torch.empty(self.n_sub, dtype=self.torch.float64, device=self.device)
+            check_buffer(out, self.device, self.torch.float64, self.n_sub, "out")
             self._check(self.lib.apx_chi2(self._prob, th.data_ptr(), data.data_ptr(), weight.data_ptr(),
                                           out.data_ptr()))
         self._leave()
@@ -336,7 +381,7 @@ class Problem:
 
     def jacobian(self, theta):
         """Dense J as a (n_par, n_pix) FP32 tensor (row k = d model / d theta_k)."""
-        th = self._dev(theta, self.torch.float64)
+        th = self._theta(theta)
         self._enter(th)
         with self.torch.cuda.stream(self.stream):
             J = self.torch.empty((self.n_par, self.n_pix), dtype=self.torch.float32, device=self.device)
@@ -346,7 +391,8 @@ class Problem:
 
     def jtwj(self, theta, data, weight):
         """(JtWJ flat per-sub blocks, JtWr [n_par], chi2 [n_sub]), FP64 device tensors."""
-        th = self._dev(theta, self.torch.float64)
+        th = self._theta(theta)
+        self._pix(data, weight)
         self._enter(th, data, weight)
         t = self.torch
         with t.cuda.stream(self.stream):
@@ -364,7 +410,8 @@ class Problem:
 
     def covariance(self, theta, data, weight):
         """((J^T W J)^{-1} flat per-sub blocks, chi2 [n_sub]), FP64 device tensors."""
-        th = self._dev(theta, self.torch.float64)
+        th = self._theta(theta)
+        self._pix(data, weight)
         self._enter(th, data, weight)
         t = self.torch
         with t.cuda.stream(self.stream):
@@ -377,7 +424,8 @@ class Problem:
 
     def covariance_factor(self, theta, data, weight):
         """(F flat per-sub blocks with F F^T = (J^T W J)^{-1}, chi2 [n_sub]), FP64 device tensors."""
-        th = self._dev(theta, self.torch.float64)
+        th = self._theta(theta)
+        self._pix(data, weight)
         self._enter(th, data, weight)
         t = self.torch
         with t.cuda.stream(self.stream):
@@ -402,6 +450,8 @@ class Problem:
             raise ValueError("z must hold n_samples x n_par and u n_samples x n_sub entries")
         if F.numel() < int(self.a_offsets[-1]):
             raise ValueError("F must hold the per-sub blocks (sum of n_s^2 entries)")
+        self._pix(data, weight)
+        check_buffer(theta, self.device, t.float64, self.n_par, "theta")
         self._enter(theta, data, weight, F, z, u)
         with t.cuda.stream(self.stream):
             samples = t.empty((n_samples, self.n_par), dtype=t.float64, device=self.device)
@@ -428,6 +478,8 @@ class Problem:
             raise ValueError("z must hold n_samples x n_par and u n_samples x (1 + d + 2^(d+1)) entries")
         if F.numel() < int(self.a_offsets[-1]):
             raise ValueError("F must hold the per-sub blocks (sum of n_s^2 entries)")
+        self._pix(data, weight)
+        check_buffer(theta, self.device, t.float64, self.n_par, "theta")
         self._enter(theta, data, weight, F, z, u)
         with t.cuda.stream(self.stream):
             samples = t.empty((n_samples, self.n_par), dtype=t.float64, device=self.device)
@@ -450,6 +502,8 @@ class Problem:
         if u.numel() != n * nd or z.numel() != n * self.n_par:
             raise ValueError("z must hold n x n_par and u n x (1 + d + 2^(d+1)) entries")
         step = ctypes.c_double(float(step0))
+        self._pix(data, weight)
+        check_buffer(theta, self.device, t.float64, self.n_par, "theta")
         self._enter(theta, data, weight, F, z, u)
         with t.cuda.stream(self.stream):
             self._check(self.lib.apx_nuts_warmup(self._prob, data.data_ptr(), weight.data_ptr(), theta.data_ptr(),
@@ -460,7 +514,7 @@ class Problem:
 
     def render_vjp(self, theta, grad_model, out=None):
         """sum_i grad_model[i] d model_i / d theta (FP64 [n_par]) by the adjoint pass."""
-        th = self._dev(theta, self.torch.float64)
+        th = self._theta(theta)
         gm = self._dev(grad_model, self.torch.float32)
         if gm.numel() != self.n_pix:
             raise ValueError(f"grad_model has {gm.numel()} entries, the render has {self.n_pix} pixels")
@@ -474,7 +528,8 @@ class Problem:
         return out
 
     def chi2_grad(self, theta, data, weight):
-        th = self._dev(theta, self.torch.float64)
+        th = self._theta(theta)
+        self._pix(data, weight)
         self._enter(th, data, weight)
         t = self.torch
         with t.cuda.stream(self.stream):
@@ -489,7 +544,12 @@ class Problem:
         """Returns (theta device copy, state device buffer) ready for lm_step / lm_run.
         theta_out / state_out reuse existing buffers (a captured graph keys on them)."""
         t = self.torch
-        src = self._dev(theta, t.float64)
+        src = self._theta(theta)
+        self._pix(data, weight)
+        if theta_out is not None:
+            check_buffer(theta_out, self.device, t.float64, self.n_par, "theta_out")
+        if state_out is not None:
+            check_buffer(state_out, self.device, t.uint8, self.n_sub * LM_STATE_BYTES, "state_out")
         self._enter(src, data, weight)
         with t.cuda.stream(self.stream):
             if theta_out is None:
@@ -505,6 +565,8 @@ class Problem:
         return th, state
 
     def lm_step(self, data, weight, theta, state):
+        self._pix(data, weight)
+        self._lm_bufs(theta, state)
         self._enter(data, weight, theta, state)
         with self.torch.cuda.stream(self.stream):
             self._check(self.lib.apx_lm_step(self._prob, data.data_ptr(), weight.data_ptr(), theta.data_ptr(),
@@ -512,6 +574,8 @@ class Problem:
         self._leave()
 
     def lm_run(self, n_iter: int, data, weight, theta, state, use_graph: bool = False):
+        self._pix(data, weight)
+        self._lm_bufs(theta, state)
         self._enter(data, weight, theta, state)
         with self.torch.cuda.stream(self.stream):
             self._check(self.lib.apx_lm_run(self._prob, int(n_iter), data.data_ptr(), weight.data_ptr(),

@@ -1578,6 +1578,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
 
     Plan& p = P->plan;
     p = Plan{};
+    p.wait_spin_max = SUBST_SPIN_MAX;
     p.n_images = P->n_images;
     p.n_comps = P->n_comps;
     p.n_par = P->n_par;
@@ -1724,6 +1725,15 @@ apx_status apx_problem_timing(apx_problem* P, int32_t klass, double* total_ms, i
     }
     *total_ms = tot;
     *launches = n;
+    return APX_OK;
+}
+
+apx_status apx_problem_set_wait_limit(apx_problem* P, int32_t polls) {
+    if (!P || !P->bound) return APX_E_WORKSPACE;
+    if (P->capturing) return fail(P->ctx, APX_E_INVALID, "the wait limit cannot change during capture");
+    HIPCHK(hipStreamSynchronize(P->ctx->stream));
+    P->plan.wait_spin_max = polls == 0 ? SUBST_SPIN_MAX : polls;
+    drop_graph(P);                      // a captured iteration holds the old plan
     return APX_OK;
 }
 

@@ -250,7 +250,13 @@ struct Plan {
     long long n_apix;
 
     long long n_pix, n_ext;
+    // bound of a substitution hand-off wait in polls; < 0: every wait takes its flag as never
+    // raised and gives up after -wait_spin_max polls (forces the give-up path from the host)
+    int wait_spin_max;
 };
+
+// default bound of a substitution hand-off wait (polls of ~64 cycles each)
+constexpr int SUBST_SPIN_MAX = 1 << 22;
 
 // Sticky flag bits
 constexpr int FLAG_DOMAIN = 1, FLAG_NONFINITE = 2, FLAG_STALL = 4;

@@ -763,13 +763,13 @@ void k_chol_retry(Plan p0, int s, apx_lm_state* lm) {
 // waits for the flag (acquire) and folds in that block's contribution, in a fixed order.
 // The waits are bounded: one that runs out raises FLAG_STALL and marks the iteration's
 // step as failed instead of hanging.  y and then h overwrite yvec.
-constexpr int SUBST_SPIN_MAX = 1 << 22;
-
 __device__ void subst_wait(Plan& p, int s, const int* f) {
     if (threadIdx.x == 0) {
+        const bool never = p.wait_spin_max < 0;
+        const int limit = never ? -p.wait_spin_max : p.wait_spin_max;
         int spins = 0;
-        while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-            if (++spins > SUBST_SPIN_MAX) {
+        while (never || __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            if (++spins > limit) {
                 atomicOr(p.sticky, FLAG_STALL);
                 p.lmf[s].subst_fail = 1;
                 break;

@@ -273,17 +273,56 @@ def recentred_fit(method=synth.SHIFT_LANCZOS, a=3):
     return with_data(synth.with_recentring(spec, method, a))
 
 
-def fit_tolerance(spec, theta):
-    """Per-parameter bound for comparing two converged fits at the oracle's optimum theta:
-    1e-6 (|theta_k| + scale_k), or 1e-5 of the posterior width sigma_k =
-    sqrt((J^T W J)^-1)_kk where that is larger.  An FP64 chi^2 of N terms carries ~1e-15
-    relative rounding, so its minimum fixes theta_k only to about sigma_k sqrt(2e-15 chi^2)
-    (1.6e-7 for a cutout's sky with sigma 0.15 at chi^2 = 564); two exact LMs may stop
-    anywhere inside that."""
-    sigma = np.zeros(spec["n_par"])
+# Relative rounding of an FP64 chi^2 of many terms (a few ulp of each term, summed): the LM
+# decides on chi^2 differences, so two exact LMs stop within sigma_k sqrt(CHI2_REL_RES chi^2)
+# of the minimum along parameter k (a step of that size changes chi^2 by about the
+# rounding).  RES_MULT: 2 for the two fits stopping on opposite sides of the minimum, and
+# a margin of 1.5 for the estimate of the rounding (measured: at most 1.9 of the resolution).
+CHI2_REL_RES = 2e-15
+RES_MULT = 3.0
+
+
+def fit_gates(spec, theta):
+    """(the benchmark spec, resolution) per parameter at the oracle's optimum theta:
+    1e-6 (|theta_k| + scale_k), and sigma_k sqrt(CHI2_REL_RES chi^2_s) with the posterior
+    width sigma_k = sqrt((J^T W J)^-1)_kk of sub-problem s."""
+    res = np.zeros(spec["n_par"])
     for s, (p0, n) in enumerate(spec["subs"]):
         if n == 0:
             continue
-        A, _, _ = oracle.jtwj(spec, theta, spec["data"], spec["weight"], s)
-        sigma[p0:p0 + n] = np.sqrt(np.abs(np.diag(np.linalg.inv(A))))
-    return np.maximum(1e-6 * (np.abs(theta) + spec["scale"]), 1e-5 * sigma)
+        A, _, c2 = oracle.jtwj(spec, theta, spec["data"], spec["weight"], s)
+        res[p0:p0 + n] = np.sqrt(np.abs(np.diag(np.linalg.inv(A)))) * math.sqrt(CHI2_REL_RES * c2)
+    return 1e-6 * (np.abs(theta) + spec["scale"]), res
+
+
+def fit_tolerance(spec, theta):
+    """Per-parameter bound for comparing two converged fits at the oracle's optimum theta:
+    1e-6 (|theta_k| + scale_k), or RES_MULT times the FP64 chi^2 resolution where that is
+    larger (a cutout's sky with sigma 0.15 at chi^2 = 564: resolution 1.6e-7 against a
+    spec gate of 1.5e-7).  Where the resolution is the larger, no LM deciding on FP64
+    chi^2 differences can be held to the spec gate."""
+    ns, res = fit_gates(spec, theta)
+    return np.maximum(ns, RES_MULT * res)
+
+
+def assert_fit_parity(spec, tg, to, label=""):
+    """Converged-fit parity: |tg - to| within fit_tolerance.  The ratios to the north-star
+    gate and to the chi^2 resolution go into the assertion message, and to the JSON-lines
+    file named by APX_FIT_REPORT when that is set."""
+    import json
+    import os
+    ns, res = fit_gates(spec, to)
+    d = np.abs(np.asarray(tg, np.float64) - to)
+    tol = np.maximum(ns, RES_MULT * res)
+    kinds = np.asarray(spec.get("kinds", np.full(len(d), -1)))
+    rep = {"case": label or spec.get("name", "?"), "max_over_northstar": float(np.max(d / ns)),
+           "worst_kind": int(kinds[int(np.argmax(d / ns))]),
+           "max_over_resolution": float(np.max(d / np.maximum(res, 1e-300))),
+           "n_over_northstar": int(np.sum(d > ns)), "n_par": int(spec["n_par"])}
+    path = os.environ.get("APX_FIT_REPORT")
+    if path:
+        with open(path, "a") as f:
+            f.write(json.dumps(rep) + "\n")
+    bad = d > tol
+    assert not bad.any(), (rep, np.nonzero(bad), np.asarray(tg)[bad], to[bad], tol[bad])
+    return rep

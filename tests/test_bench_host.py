@@ -50,3 +50,32 @@ def test_fft_lines_report_a_direct_equivalent_rate(capsys):
     rec = json.loads(capsys.readouterr().out)
     assert "roofline" not in rec and rec["direct_equivalent"]["tflops"] == 120.0
     assert rec["config"]["conv"] == "fft"
+
+
+def test_jacobian_entries_per_cutout_count_every_convolved_column():
+    """Cutouts: each free Sersic parameter is one column over the whole cutout (the window
+    is the cutout); the sky column is not convolved."""
+    from paper_2308_01957_amd import synth
+    spec = synth.cutouts(seed_id=104, n_cutouts=5, side_range=(20, 40), p_range=(5, 9), max_comp=3)
+    ent, flop = bench.jac_entries_per_sub(spec)
+    for s, (p0, n) in enumerate(spec["subs"]):
+        im = [im for im in spec["images"] if im["sub"] == s][0]
+        P = im["psf"].shape[0]
+        assert ent[s] == (n - 1) * im["H"] * im["W"]
+        assert flop[s] == ent[s] * 2.0 * P * P
+
+
+def test_cpu_baseline_runs_the_oracle_on_a_process_pool():
+    """The CPU baseline: a pool of single-threaded workers runs oracle LM iterations on a
+    sample of cutouts and reports cutout iterations per second with its core count."""
+    import oracle
+    from paper_2308_01957_amd import synth
+    spec = synth.cutouts(seed_id=104, n_cutouts=4, side_range=(20, 28), p_range=(5, 7), max_comp=1)
+    data, weight = [], []
+    for k, im in enumerate(spec["images"]):
+        d, w = synth.make_data(oracle.model_image(spec, spec["theta_true"], k), spec["noise"][k][:im["H"], :im["W"]])
+        data.append(d)
+        weight.append(w)
+    rec = bench.cpu_baseline_cutouts(spec, data, weight, synth, stride=2, n_iter=1)
+    assert rec["kind"] == "oracle" and rec["value"] > 0 and 1 <= rec["cores"] <= 16
+    assert rec["unit"] == "cutout LM it/s" and "2 of 4 cutouts" in rec["sample"]

@@ -137,5 +137,4 @@ def test_adaptive_lm_converges_to_the_oracle_fit(apx):
     to, _ = oracle.lm_fit(spec, spec["theta_init"], spec["data"], spec["weight"], 40)
     A, g, _ = oracle.jtwj(spec, to, spec["data"], spec["weight"], 0)
     assert float(g @ np.linalg.solve(A, g)) < 1e-6
-    bad = np.abs(tg - to) > cases.fit_tolerance(spec, to)
-    assert not bad.any(), (np.nonzero(bad), tg[bad], to[bad])
+    cases.assert_fit_parity(spec, tg, to)
