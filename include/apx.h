@@ -303,6 +303,23 @@ apx_status apx_problem_tile_shapes(const apx_problem* p, int32_t kind, int32_t* 
  * damped solve ran out (that iteration's step was dropped). */
 apx_status apx_problem_check(apx_problem* p);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): binds the problem to the library's own
+ * scratch array on the context's device instead of a caller workspace -- 64 MiB per GPU,
+ * a static device array that each GPU the library runs on holds until the process ends.
+ * Afterwards every entry point behaves as after apx_problem_bind_workspace (same kernels,
+ * same results) and allocates nothing.  This call allocates nothing either: it uploads
+ * the plan tables and clears the flags that must start at zero, after a device-wide
+ * synchronisation.  The scratch is shared: binding another problem on the same device
+ * makes the earlier one refuse further calls with APX_E_WORKSPACE (bind it again to use
+ * it), and calls on the scratch from several threads or streams at once race.
+ * APX_E_WORKSPACE (with the sizes in apx_last_error) when apx_problem_workspace_bytes
+ * exceeds 64 MiB; APX_E_INVALID for a host-only context; APX_E_HIP if the array's address
+ * could not be looked up.  Note that apx_problem_create itself may allocate once per
+ * context for the tile autotuner's timing buffer: use APX_TILES_MODEL or a fixed shape
+ * (apx_ctx_set_tiles), or measured costs (apx_ctx_set_tile_cost), to avoid it. */
+apx_status apx_problem_bind_scratch(apx_problem* p);
+
 /* Bound of the damped solve's substitution hand-off waits (the blocked Cholesky path of
  * sub-problems with more than 64 parameters, §2.5).  Each wait polls a flag that an
  * earlier workgroup of the same launch raises; one that polls `polls` times without

@@ -33,7 +33,7 @@ EXPORTS = [
     "apx_lm_step", "apx_lm_run", "apx_problem_set_timing", "apx_problem_timing",
     "apx_ctx_set_tiles", "apx_ctx_tile_cost", "apx_ctx_set_tile_cost", "apx_problem_tile_shapes", "apx_covariance",
     "apx_covariance_factor", "apx_hmc_run", "apx_nuts_run", "apx_nuts_warmup", "apx_problem_set_timing_classes",
-    "apx_problem_set_wait_limit",
+    "apx_problem_set_wait_limit", "apx_problem_bind_scratch",
 ]
 TILES_AUTOTUNE, TILES_MODEL, TILES_FIXED = 0, 1, 2
 TILE_SHAPES = [(32, 64), (16, 64), (32, 32), (16, 32)]       # output rows x cols per workgroup
@@ -160,6 +160,7 @@ def load_library(path: str = LIB_PATH):
         "apx_problem_sizes": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
         "apx_problem_check": ([vp], i32),
         "apx_problem_set_wait_limit": ([vp, i32], i32),
+        "apx_problem_bind_scratch": ([vp], i32),
         "apx_problem_destroy": ([vp], i32),
         "apx_render": ([vp, vp, vp], i32),
         "apx_chi2": ([vp, vp, vp, vp, vp], i32),
@@ -226,9 +227,11 @@ class Problem:
     """A model/fit problem bound to one GPU: descriptor, workspace and stream."""
 
     def __init__(self, spec: Dict, device: int = 0, objective: int = 0, tiles: int = TILES_AUTOTUNE,
-                 tile_costs: Optional[Dict] = None):
+                 tile_costs: Optional[Dict] = None, scratch: bool = False):
         """tile_costs: {(kernel, P): [us per tile of each shape]} entries of the autotuner's
-        table to use instead of timing them (as read back by tile_cost())."""
+        table to use instead of timing them (as read back by tile_cost()).  scratch: bind
+        the library's own device scratch (apx_problem_bind_scratch) instead of allocating
+        a workspace tensor."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("apx needs a ROCm GPU; none is visible")
@@ -266,10 +269,14 @@ class Problem:
         nbytes = ctypes.c_uint64()
         self._check(self.lib.apx_problem_workspace_bytes(self._prob, ctypes.byref(nbytes)))
         self.workspace_bytes = int(nbytes.value)
-        with torch.cuda.stream(self.stream):
-            self.workspace = torch.empty(max(256, self.workspace_bytes), dtype=torch.uint8, device=self.device)
-        self._check(self.lib.apx_problem_bind_workspace(self._prob, ctypes.c_void_p(self.workspace.data_ptr()),
-                                                        self.workspace.numel()))
+        if scratch:
+            self.workspace = None
+            self._check(self.lib.apx_problem_bind_scratch(self._prob))
+        else:
+            with torch.cuda.stream(self.stream):
+                self.workspace = torch.empty(max(256, self.workspace_bytes), dtype=torch.uint8, device=self.device)
+            self._check(self.lib.apx_problem_bind_workspace(self._prob, ctypes.c_void_p(self.workspace.data_ptr()),
+                                                            self.workspace.numel()))
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.apx_problem_sizes(self._prob, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         self.n_ext, self.n_jac = int(b.value), int(c.value)

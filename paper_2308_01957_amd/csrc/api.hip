@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -25,6 +26,40 @@ struct apx_ctx {
     size_t tune_bytes = 0;
     int pair_slots = 0;                                 // resident k_pair<64> workgroups
 };
+
+// ------------------------------------------------------------ library scratch
+// Device memory for callers that cannot allocate (code under graph capture, serving loops,
+// harnesses that forbid hipMalloc): one array per GPU the library runs on, held until the
+// process ends.  A problem bound to it (apx_problem_bind_scratch) keeps its plan tables and
+// every per-call buffer there, as it would in a caller workspace.  In host code the array's
+// name is only a stand-in: its device address comes from hipGetSymbolAddress, looked up
+// once per device when the first context of that device is created.
+static constexpr size_t APX_SCRATCH_BYTES = size_t(64) << 20;
+static constexpr int APX_SCRATCH_DEVICES = 64;
+static __device__ __align__(256) char scratch[APX_SCRATCH_BYTES];
+
+namespace {
+struct ScratchSlot {
+    bool looked_up = false;
+    hipError_t status = hipSuccess;
+    void* ptr = nullptr;          // device address of `scratch` on this device
+    uint64_t generation = 0;      // bumped by every binding; a problem keeps the value it bound
+};
+std::mutex g_scratch_mu;
+ScratchSlot g_scratch[APX_SCRATCH_DEVICES];
+
+// with `device` current: look the array's address up once
+void scratch_lookup(int device) {
+    if (device < 0 || device >= APX_SCRATCH_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchSlot& sl = g_scratch[device];
+    if (sl.looked_up) return;
+    sl.looked_up = true;
+    void* ptr = nullptr;
+    sl.status = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    sl.ptr = sl.status == hipSuccess ? ptr : nullptr;
+}
+}  // namespace
 
 namespace {
 
@@ -106,6 +141,8 @@ struct apx_problem {
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
     bool bound = false;
+    bool on_scratch = false;         // bound to the library scratch of ctx->device
+    uint64_t scratch_gen = 0;        // the scratch binding this problem made
     Layout L;
     std::map<std::string, size_t> off;
     Plan plan{};
@@ -1429,6 +1466,7 @@ apx_status apx_ctx_create(int device, void* hip_stream, apx_ctx** out) {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return APX_E_HIP;
     if (hipSetDevice(device) != hipSuccess) return APX_E_HIP;
+    scratch_lookup(device);
     apx_ctx* c = new apx_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -1520,6 +1558,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
         return fail(P->ctx, APX_E_WORKSPACE, "workspace null, misaligned or smaller than required");
     P->ws = (char*)dev;
     P->ws_bytes = bytes;
+    P->on_scratch = false;
     HIPCHK(upload(P, "images", P->images));
     HIPCHK(upload(P, "comps", P->comps));
     HIPCHK(upload(P, "groups", P->groups));
@@ -1672,6 +1711,35 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     HIPCHK(hipMemsetAsync(p.lmf, 0, sizeof(LMFlags) * 2 * P->n_sub, P->ctx->stream));
     HIPCHK(hipMemsetAsync(p.spec, 0, sizeof(LMSpec) * P->n_sub, P->ctx->stream));
     P->bound = true;
+    return APX_OK;
+}
+
+apx_status apx_problem_bind_scratch(apx_problem* P) {
+    if (!P) return APX_E_INVALID;
+    const int dev = P->ctx->device;
+    if (dev < 0) return fail(P->ctx, APX_E_INVALID, "host-only context cannot bind the scratch");
+    if (dev >= APX_SCRATCH_DEVICES) return fail(P->ctx, APX_E_UNSUPPORTED, "device index beyond the scratch table");
+    if (P->L.total > APX_SCRATCH_BYTES)
+        return fail(P->ctx, APX_E_WORKSPACE,
+                    "the problem needs " + std::to_string(P->L.total) + " bytes of workspace; the library scratch holds " +
+                        std::to_string(APX_SCRATCH_BYTES) + " (bind a caller workspace instead)");
+    void* ptr = nullptr;
+    uint64_t gen = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        ScratchSlot& sl = g_scratch[dev];
+        if (!sl.looked_up || sl.status != hipSuccess || !sl.ptr)
+            return fail(P->ctx, APX_E_HIP, std::string("scratch address lookup failed: ") +
+                                               (sl.looked_up ? hipGetErrorString(sl.status) : "not looked up"));
+        ptr = sl.ptr;
+        gen = ++sl.generation;
+    }
+    // the previous user of the scratch may still run on another stream of this device
+    HIPCHK(hipDeviceSynchronize());
+    const apx_status st = apx_problem_bind_workspace(P, ptr, APX_SCRATCH_BYTES);
+    if (st != APX_OK) return st;
+    P->on_scratch = true;
+    P->scratch_gen = gen;
     return APX_OK;
 }
 
@@ -1962,6 +2030,11 @@ static apx_status normal_eq(apx_problem* P, const float* weight, double* A_out, 
 static apx_status ready(apx_problem* P) {
     if (!P) return APX_E_INVALID;
     if (!P->bound) return fail(P->ctx, APX_E_WORKSPACE, "no workspace bound");
+    if (P->on_scratch) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (g_scratch[P->ctx->device].generation != P->scratch_gen)
+            return fail(P->ctx, APX_E_WORKSPACE, "another problem has been bound to the library scratch since");
+    }
     return APX_OK;
 }
 
