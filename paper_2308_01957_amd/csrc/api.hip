@@ -129,6 +129,7 @@ struct apx_problem {
     std::vector<float> node_o, node_w;
     std::vector<double> node_od, node_wd;
     std::vector<double> bn_tab;
+    std::vector<double> ptab;                     // FP64 render: 2^x / log2 table
     std::vector<double> agl;                      // adaptive: GL 3/5/7 offsets and weights
     std::vector<AChunk> achunks;
     std::vector<int> acomp_chunk;
@@ -429,6 +430,19 @@ static double sersic_bn_host(double n) {
     return b;
 }
 
+// The FP64 render's 2^x / log2 table (layout in sersic64.h), in extended precision and
+// rounded once.
+static void build_pow2_table(std::vector<double>& tab) {
+    tab.resize(PTAB_N);
+    for (int j = 0; j < 64; ++j) {
+        tab[j] = (double)exp2l((long double)j / 64.0L);
+        const long double c = 0.5L + ((long double)j + 0.5L) / 128.0L;
+        const double r = (double)(1.0L / c);
+        tab[64 + j] = r;
+        tab[128 + j] = (double)(-log2l((long double)r));
+    }
+}
+
 static void build_bn_table(std::vector<double>& tab) {
     tab.resize(2 * BN_COUNT);
     const double hd = 1e-5;
@@ -613,6 +627,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     }
 
     build_bn_table(P->bn_tab);
+    build_pow2_table(P->ptab);
     if (d->conv_mode == APX_CONV_FFT)
         for (int m = 0; m < FFT_T; ++m) {
             const double a = -2.0 * M_PI * m / FFT_T;
@@ -1360,6 +1375,7 @@ static void layout(apx_problem* P) {
     ws_take<int>(P, "par_sky", P->par_sky.size());
     ws_take<int>(P, "small_subs", P->small_subs.size());
     ws_take<double>(P, "bn_tab", P->bn_tab.size());
+    ws_take<double>(P, "ptab", P->ptab.size());
     ws_take<double>(P, "agl", P->agl.size());
     ws_take<AChunk>(P, "achunks", P->achunks.size());
     ws_take<int>(P, "acomp_chunk", P->acomp_chunk.size());
@@ -1606,6 +1622,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     HIPCHK(upload(P, "par_sky", P->par_sky));
     HIPCHK(upload(P, "small_subs", P->small_subs));
     HIPCHK(upload(P, "bn_tab", P->bn_tab));
+    HIPCHK(upload(P, "ptab", P->ptab));
     HIPCHK(upload(P, "agl", P->agl));
     HIPCHK(upload(P, "fft_tw", P->fft_tw));
     HIPCHK(upload(P, "fwd_pairs", P->fwd_pairs));
@@ -1689,6 +1706,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.sky_val = wsp<double>(P, "sky_val");
     p.par_sub = wsp<int>(P, "par_sub");
     p.bn_tab = wsp<double>(P, "bn_tab");
+    p.ptab = wsp<double>(P, "ptab");
     p.agl = wsp<double>(P, "agl");
     p.achunks = wsp<AChunk>(P, "achunks");
     p.n_achunks = (int)P->achunks.size();

@@ -233,6 +233,7 @@ struct Plan {
     double* sky_val;          // [n_images] sky of each image at the current theta
     const int* par_sub;       // [n_par] sub-problem of each theta index (-1: none)
     const double* bn_tab;     // [2 * BN_COUNT]: b_n, db_n/dn at the table nodes
+    const double* ptab;       // [PTAB_N]: the FP64 render's 2^x / log2 table (sersic64.h)
 
     // adaptive integration (mode APX_MODE_ADAPTIVE, tolerance k_re)
     const double* agl;        // Gauss-Legendre offsets / weights on [-1/2, 1/2]: o3 w3 o5 w5 o7 w7
@@ -254,6 +255,9 @@ struct Plan {
     // raised and gives up after -wait_spin_max polls (forces the give-up path from the host)
     int wait_spin_max;
 };
+
+// entries of the FP64 render's 2^x / log2 table (layout in sersic64.h)
+constexpr int PTAB_N = 192;
 
 // default bound of a substitution hand-off wait (polls of ~64 cycles each)
 constexpr int SUBST_SPIN_MAX = 1 << 22;

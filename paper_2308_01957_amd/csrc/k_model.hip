@@ -349,22 +349,28 @@ __device__ __forceinline__ double point_weight(const CompConst& c, int y, int x)
 // The same pixel integral in double precision throughout (FP64 log2/exp2), for the
 // objective path: chi^2 differences of the LM gain ratio are resolved far below FP32
 // rounding.
+// tab: the 2^x / log2 table in LDS (PTAB_N doubles)
 __device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst& c, const DImage& im,
-                                                 double ucx, double ucy) {
+                                                 double ucx, double ucy, const double* __restrict__ tab) {
     const double dxc = ucx - c.x0, dyc = ucy - c.y0;
-    if (p.mode == APX_MODE_WITHIN_K_RE && !within_kre(c, ucx, ucy)) return sersic_I64(c, dxc, dyc);
+    if (p.mode == APX_MODE_WITHIN_K_RE && !within_kre(c, ucx, ucy)) return sersic_I64_t(c, dxc, dyc, tab);
     double sum = 0.0;
     for (int ky = 0; ky < p.s; ++ky) {
         const double oy = p.node_od[ky];
         double row = 0.0;
         for (int kx = 0; kx < p.s; ++kx) {
             const double ox = p.node_od[kx];
-            row += p.node_wd[kx] * sersic_I64(c, dxc + im.aff[1] * ox + im.aff[2] * oy,
-                                              dyc + im.aff[4] * ox + im.aff[5] * oy);
+            row += p.node_wd[kx] * sersic_I64_t(c, dxc + im.aff[1] * ox + im.aff[2] * oy,
+                                                dyc + im.aff[4] * ox + im.aff[5] * oy, tab);
         }
         sum += p.node_wd[ky] * row;
     }
     return sum;
+}
+
+// Stage the 2^x / log2 table into LDS (the caller synchronises before use).
+__device__ __forceinline__ void stage_ptab(const Plan& p, double* sh) {
+    for (int k = (int)threadIdx.x; k < PTAB_N; k += (int)blockDim.x) sh[k] = p.ptab[k];
 }
 
 // ------------------------------------------------------------- re-centred tiles
@@ -457,11 +463,12 @@ __device__ void shifted_derivs(const Plan& p, int ci, const CompConst& c, const 
 // tile with origin (y0, x0); 0 where !want.  Every thread of the block calls it.
 template <typename T>
 __device__ T shifted_pixel(const Plan& p, int ci, const CompConst& c, const DComp& cp, const DImage& im, int y0,
-                           int x0, int ly, int lx, bool want, T (*sh)[SH_H * SH_W], T* tw) {
+                           int x0, int ly, int lx, bool want, T (*sh)[SH_H * SH_W], T* tw,
+                           const double* __restrict__ tab = nullptr) {
     stage_halo<1, T>(p, ci, cp, y0, x0, sh, tw, [&](int ry, int rx, T* v) {
         const double rcx = im.aff[0] + im.aff[1] * rx + im.aff[2] * ry;
         const double rcy = im.aff[3] + im.aff[4] * rx + im.aff[5] * ry;
-        if constexpr (sizeof(T) == 8) v[0] = sersic_pixel64(p, c, im, rcx, rcy) * im.area;
+        if constexpr (sizeof(T) == 8) v[0] = sersic_pixel64(p, c, im, rcx, rcy, tab) * im.area;
         else v[0] = (float)((double)sersic_pixel(p, c, im, rcx, rcy) * im.area);
     });
     __syncthreads();
@@ -525,9 +532,12 @@ template <bool SHIFT>
 __global__ __launch_bounds__(256) void k_render64(Plan p, int skip_mode, const apx_lm_state* lm) {
     __shared__ double sh[1][SHIFT ? SH_H * SH_W : 1];
     __shared__ double tw[SHIFT ? STAP_STRIDE : 1];
+    __shared__ double ptab[PTAB_N];
     const RTile t = p.rtiles[blockIdx.x];
     const DImage& im = p.images[t.a];
     if (sub_skipped(p, im.sub, skip_mode, lm)) return;
+    stage_ptab(p, ptab);
+    __syncthreads();
     const int ly = (int)threadIdx.x / RT_X, lx = (int)threadIdx.x % RT_X;
     const int y = t.y0 + ly, x = t.x0 + lx;
     const bool inside = y < im.H + im.c && x < im.W + im.c;
@@ -545,13 +555,13 @@ __global__ __launch_bounds__(256) void k_render64(Plan p, int skip_mode, const a
             continue;
         }
         if (SHIFT && cp.type == APX_SERSIC) {      // block-uniform
-            if constexpr (SHIFT) sum += shifted_pixel<double>(p, ci, c, cp, im, t.y0, t.x0, ly, lx, inbox, sh, tw);
+            if constexpr (SHIFT) sum += shifted_pixel<double>(p, ci, c, cp, im, t.y0, t.x0, ly, lx, inbox, sh, tw, ptab);
             continue;
         }
         if (!inbox) continue;
         if (cp.type == APX_SERSIC)
             sum += (p.mode == APX_MODE_ADAPTIVE ? p.aval[adapt_index(cp, y, x)]
-                                                : sersic_pixel64(p, c, im, ucx, ucy)) * im.area;
+                                                : sersic_pixel64(p, c, im, ucx, ucy, ptab)) * im.area;
         else sum += (double)c.F64 * point_weight(c, y, x);
     }
     if (inside) p.S64[im.ext_off + (long long)(y + im.c) * im.EW + (x + im.c)] = sum;
