@@ -256,8 +256,10 @@ __device__ __forceinline__ void sersic_dI(const CompConst& c, float dx, float dy
     const float t = fast_exp2(lt);
     const float I = fast_exp2((float)fma(-c.B_d, (double)t, c.A_d)) * wgt;
     const float inv_n = 2.f * c.g;
-    // dI/dR divided by R
-    const float G = floored ? 0.f : -I * c.b * t * inv_n / R2;
+    // dI/dR divided by R (hardware reciprocals, 1 ulp: these derivative images feed the
+    // FP32 Jacobian and adjoint, held to 3e-5 of each column's scale)
+    const float bt = I * c.b * t * inv_n;
+    const float G = floored ? 0.f : -bt * __builtin_amdgcn_rcpf(R2);
     const float dxp = G * xp;                 // dI/dx'
     const float dyp = G * yq * c.iq;          // dI/dy' = G y' / q^2
     acc[0] += -c.cs * dxp + c.sn * dyp;
@@ -265,7 +267,7 @@ __device__ __forceinline__ void sersic_dI(const CompConst& c, float dx, float dy
     acc[2] += -G * yq * yq * c.iq;            // dR/dq = -y'^2 / (q^3 R)
     acc[3] += G * xp * yp * (1.f - c.iq * c.iq);
     acc[4] += I * (c.bp * (1.f - t) + c.b * t * lt * LN2F * inv_n);
-    acc[5] += I * c.b * t * inv_n / c.re;
+    acc[5] += bt * __builtin_amdgcn_rcpf(c.re);
     acc[6] += I * LN10F;
 }
 
