@@ -566,7 +566,7 @@ OTHER_WORKLOADS = {"field": run_field, "multiband": run_multiband,
 
 def tile_choice(prob):
     """Convolution jobs per tile shape (rows x cols) as the autotuner chose them."""
-    names = ["%dx%d" % t for t in prob_tile_shapes()] + ["fft"]
+    names = ["%dx%d" % t for t in prob_tile_shapes()] + ["fft", "sep"]
     return {kind: dict(zip(names, prob.tile_shapes(k))) for k, kind in enumerate(["model", "jacobian", "adjoint"])}
 
 

@@ -124,6 +124,13 @@ typedef int32_t apx_status;
 #define APX_CONV_DIRECT 0
 #define APX_CONV_FFT    1
 #define APX_FFT_MIN_P   15
+/* APX_CONV_DIRECT also runs the Jacobian-column convolutions of an image whose stamp is
+ * the outer product of two vectors (rank one to FP32 rounding: K_uv = a_u b_v, e.g. a
+ * Gaussian) as two 1-D passes, 2 P multiply-adds per output per pass instead of P^2; the
+ * result is the same convolution to FP32 rounding.  The stamp is read back when the problem
+ * is created.  The objective (model) convolution stays 2-D.  APX_CONV_DIRECT_2D keeps
+ * every convolution 2-D. */
+#define APX_CONV_DIRECT_2D 2
 
 /* Sub-pixel re-centring (§2.1.3).  With shift != APX_SHIFT_NONE every Sersic component
  * is sampled (and pixel-integrated) with its centre moved to the centre of the nearest
@@ -211,7 +218,7 @@ typedef struct apx_problem_desc {
     double  k_re;                   /* k of APX_MODE_WITHIN_K_RE; tol of
                                        APX_MODE_ADAPTIVE                             */
     int32_t n_psf_models;           /* live PSF models (0: every stamp is fixed)     */
-    int32_t conv_mode;              /* APX_CONV_DIRECT (default) or APX_CONV_FFT     */
+    int32_t conv_mode;              /* APX_CONV_DIRECT (default), APX_CONV_FFT or APX_CONV_DIRECT_2D */
     const apx_psf_model_desc* psf_models;   /* host, [n_psf_models]                 */
     int32_t shift;                  /* APX_SHIFT_* sub-pixel re-centring (0 = none)   */
     int32_t shift_a;                /* Lanczos order a (APX_SHIFT_LANCZOS only)      */
@@ -294,8 +301,8 @@ apx_status apx_problem_bind_workspace(apx_problem* p, void* dev, uint64_t bytes)
 apx_status apx_problem_sizes(const apx_problem* p, int64_t* n_pix, int64_t* n_ext, int64_t* n_jac);
 
 /* Convolution jobs of `kind` (0 model, 1 Jacobian columns, 2 adjoint) per tile shape:
- * counts[s] for s = 0..3 (see apx_ctx_set_tiles), counts[4] = jobs in FFT mode.  counts
- * must hold 5 entries. */
+ * counts[s] for s = 0..3 (see apx_ctx_set_tiles), counts[4] = jobs in FFT mode, counts[5]
+ * = jobs run as two 1-D passes (rank-one stamps).  counts must hold 6 entries. */
 apx_status apx_problem_tile_shapes(const apx_problem* p, int32_t kind, int32_t* counts);
 
 /* Synchronise the stream and return the sticky device flag, then clear it: APX_OK,
@@ -350,7 +357,8 @@ apx_status apx_problem_destroy(apx_problem* p);
 #define APX_TIME_LM         8     /* trial, accept and state kernels            */
 #define APX_TIME_CONV_ADJ   9     /* adjoint convolution                        */
 #define APX_TIME_GRAD       10    /* adjoint contraction with recomputed samples */
-#define APX_TIME_CLASSES    11
+#define APX_TIME_CONV_SEP   11    /* Jacobian-column convolutions as two 1-D passes (rank-one stamps) */
+#define APX_TIME_CLASSES    12
 /* Kernel timing with HIP events on the context stream: enabled != 0 records every class;
  * set_timing_classes records only the classes in mask (bit 1 << class), which keeps the
  * event overhead off the other launches.  Either call resets the records. */

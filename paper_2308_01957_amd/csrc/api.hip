@@ -130,6 +130,7 @@ struct apx_problem {
     std::vector<double> node_od, node_wd;
     std::vector<double> bn_tab;
     std::vector<double> ptab;                     // FP64 render: 2^x / log2 table
+    std::vector<float> psf_sep;                   // factors of rank-one stamps (a, then b)
     std::vector<double> agl;                      // adaptive: GL 3/5/7 offsets and weights
     std::vector<AChunk> achunks;
     std::vector<int> acomp_chunk;
@@ -578,7 +579,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         return fail(C, APX_E_INVALID, "adaptive tolerance (k_re) must be > 0");
     if (d->objective != APX_OBJECTIVE_FP64 && d->objective != APX_OBJECTIVE_FP32)
         return fail(C, APX_E_INVALID, "unknown objective precision");
-    if (d->conv_mode != APX_CONV_DIRECT && d->conv_mode != APX_CONV_FFT)
+    if (d->conv_mode != APX_CONV_DIRECT && d->conv_mode != APX_CONV_FFT && d->conv_mode != APX_CONV_DIRECT_2D)
         return fail(C, APX_E_INVALID, "unknown convolution mode");
     if (d->shift != APX_SHIFT_NONE && d->shift != APX_SHIFT_BILINEAR && d->shift != APX_SHIFT_LANCZOS)
         return fail(C, APX_E_INVALID, "unknown re-centring method");
@@ -761,6 +762,43 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         im.live = 1;
         im.live_off = P->n_live;
         P->n_live += 3LL * im.P * im.P;
+    }
+
+    // rank-one stamps: K_uv = a_u b_v to FP32 rounding (a Gaussian, for one), whose
+    // Jacobian-column convolutions run as two 1-D passes.  With the largest entry at
+    // (u0, v0): a_u = K_u,v0 and b_v = K_u0,v / K_u0,v0; every entry must be reproduced to
+    // 4e-7 of itself (three FP32 roundings of exact products) plus 1e-9 of the largest.
+    for (int k = 0; k < d->n_images; ++k) P->images[k].sep_off = -1;
+    P->psf_sep.clear();
+    if (d->conv_mode == APX_CONV_DIRECT && C->device >= 0 && P->n_psf > 0) {
+        std::vector<float> h((size_t)P->n_psf);
+        if (hipMemcpy(h.data(), d->psf, (size_t)P->n_psf * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(C, APX_E_HIP, "reading the stamps back");
+        for (int k = 0; k < d->n_images; ++k) {
+            DImage& im = P->images[k];
+            if (im.live || im.up != 1 || im.P < 3) continue;
+            const int Pk = im.P;
+            const float* K = h.data() + im.psf_off;
+            int u0 = 0, v0 = 0;
+            double kmax = 0.0;
+            for (int u = 0; u < Pk; ++u)
+                for (int v = 0; v < Pk; ++v)
+                    if (std::fabs((double)K[u * Pk + v]) > kmax) { kmax = std::fabs((double)K[u * Pk + v]); u0 = u; v0 = v; }
+            if (!(kmax > 0.0) || !std::isfinite(kmax)) continue;
+            std::vector<double> a(Pk), b(Pk);
+            for (int u = 0; u < Pk; ++u) a[u] = K[u * Pk + v0];
+            for (int v = 0; v < Pk; ++v) b[v] = (double)K[u0 * Pk + v] / (double)K[u0 * Pk + v0];
+            bool ok = true;
+            for (int u = 0; u < Pk && ok; ++u)
+                for (int v = 0; v < Pk && ok; ++v) {
+                    const double kv = K[u * Pk + v];
+                    ok = std::isfinite(kv) && std::fabs(kv - a[u] * b[v]) <= 4e-7 * std::fabs(kv) + 1e-9 * kmax;
+                }
+            if (!ok) continue;
+            im.sep_off = (long long)P->psf_sep.size();
+            for (int u = 0; u < Pk; ++u) P->psf_sep.push_back((float)a[u]);
+            for (int v = 0; v < Pk; ++v) P->psf_sep.push_back((float)b[v]);
+        }
     }
 
     // components
@@ -980,7 +1018,9 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         for (size_t j = 0; j < jobs.size(); ++j) {
             const bool fft = pairs && P->images[jobs[j].image].fft_off >= 0 && jobs[j].out_h >= 32 &&
                              jobs[j].out_w >= 32;
-            jobs[j].shape = fft ? SHAPE_FFT : choose_shape(C, key, jobP[j], jobs[j].out_h, jobs[j].out_w);
+            const bool sep = kind == CONV_JCOL && P->images[jobs[j].image].sep_off >= 0;
+            jobs[j].shape = fft ? SHAPE_FFT
+                          : sep ? SHAPE_SEP : choose_shape(C, key, jobP[j], jobs[j].out_h, jobs[j].out_w);
         }
         std::vector<int> order(jobs.size());
         for (size_t i = 0; i < jobs.size(); ++i) order[i] = (int)i;
@@ -1376,6 +1416,7 @@ static void layout(apx_problem* P) {
     ws_take<int>(P, "small_subs", P->small_subs.size());
     ws_take<double>(P, "bn_tab", P->bn_tab.size());
     ws_take<double>(P, "ptab", P->ptab.size());
+    ws_take<float>(P, "psf_sep", P->psf_sep.size());
     ws_take<double>(P, "agl", P->agl.size());
     ws_take<AChunk>(P, "achunks", P->achunks.size());
     ws_take<int>(P, "acomp_chunk", P->acomp_chunk.size());
@@ -1623,6 +1664,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     HIPCHK(upload(P, "small_subs", P->small_subs));
     HIPCHK(upload(P, "bn_tab", P->bn_tab));
     HIPCHK(upload(P, "ptab", P->ptab));
+    HIPCHK(upload(P, "psf_sep", P->psf_sep));
     HIPCHK(upload(P, "agl", P->agl));
     HIPCHK(upload(P, "fft_tw", P->fft_tw));
     HIPCHK(upload(P, "fwd_pairs", P->fwd_pairs));
@@ -1707,6 +1749,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     p.par_sub = wsp<int>(P, "par_sub");
     p.bn_tab = wsp<double>(P, "bn_tab");
     p.ptab = wsp<double>(P, "ptab");
+    p.psf_sep = wsp<float>(P, "psf_sep");
     p.agl = wsp<double>(P, "agl");
     p.achunks = wsp<AChunk>(P, "achunks");
     p.n_achunks = (int)P->achunks.size();
@@ -1764,7 +1807,7 @@ apx_status apx_problem_bind_scratch(apx_problem* P) {
 apx_status apx_problem_tile_shapes(const apx_problem* P, int32_t kind, int32_t* counts) {
     if (!P || !counts || kind < 0 || kind > 2) return APX_E_INVALID;
     const std::vector<ConvJob>& jobs = kind == 0 ? P->fwd_jobs : kind == 1 ? P->jcol_jobs : P->adj_jobs;
-    for (int s = 0; s <= SHAPE_FFT; ++s) counts[s] = 0;
+    for (int s = 0; s <= SHAPE_SEP; ++s) counts[s] = 0;
     for (const ConvJob& jb : jobs)
         if (jb.out_h > 0 && jb.out_w > 0) counts[jb.shape] += 1;
     return APX_OK;
@@ -1848,9 +1891,14 @@ static apx_status run_conv(apx_problem* P, int kind, const ConvIO& io) {
                     : (kind == CONV_JCOL || kind == CONV_JCOL_PSF) ? APX_TIME_CONV_JCOL : APX_TIME_CONV_ADJ;
     const char* pn = kind == CONV_FWD ? "fwd_pairs" : kind == CONV_JCOL ? "jcol_pairs" : "adj_pairs";
     for (const PRange& r : *ranges) {
-        TimeScope ts(P, klass);
+        TimeScope ts(P, r.shape == SHAPE_SEP ? APX_TIME_CONV_SEP : klass);
         ConvLaunch L{wsp<ConvJob>(P, jn), wsp<ConvItem>(P, inn), r.begin, r.count, r.P, r.shape, nullptr,
                      r.pair_begin, r.pair_count};
+        if (r.shape == SHAPE_SEP) {
+            hipError_t e = launch_conv_sep(p, L, io, st);
+            if (e != hipSuccess) return fail(P->ctx, APX_E_HIP, std::string("separable conv launch: ") + hipGetErrorString(e));
+            continue;
+        }
         if (r.shape == SHAPE_FFT) {
             L.pairs = wsp<int2>(P, pn);
             hipError_t e = launch_conv_fft(p, kind, L, io, st);

@@ -27,8 +27,16 @@ constexpr int N_XCD = 8;                       // accelerator dies, each with it
 // SHAPE_FFT, whose output blocks are (FFT_T - P + 1)^2
 constexpr int FFT_T = 128;
 constexpr int SHAPE_FFT = N_TILE_SHAPES;
-__host__ __device__ constexpr int shape_th(int s, int P) { return s == SHAPE_FFT ? FFT_T - P + 1 : tile_th(s); }
-__host__ __device__ constexpr int shape_tw(int s, int P) { return s == SHAPE_FFT ? FFT_T - P + 1 : tile_tw(s); }
+// a Jacobian-column job on an image with a rank-one stamp: two 1-D passes over SEP_TH x
+// SEP_TW output tiles
+constexpr int SHAPE_SEP = N_TILE_SHAPES + 1;
+constexpr int SEP_TH = 32, SEP_TW = 64;
+__host__ __device__ constexpr int shape_th(int s, int P) {
+    return s == SHAPE_FFT ? FFT_T - P + 1 : (s == SHAPE_SEP ? SEP_TH : tile_th(s));
+}
+__host__ __device__ constexpr int shape_tw(int s, int P) {
+    return s == SHAPE_FFT ? FFT_T - P + 1 : (s == SHAPE_SEP ? SEP_TW : tile_tw(s));
+}
 
 // Workgroups of a launch are dealt to the XCDs round-robin (block b to XCD b % 8).
 // Block b takes logical item xcd_item(b, n): every XCD then owns a contiguous range of
@@ -67,6 +75,7 @@ struct DImage {
     double live_fixed[2];
     long long live_off;       // into psf_live: K, dK/dn, dK/dR_d (3 P^2 floats)
     long long fft_off;        // FFT mode: into fft_spec (2 slots of FFT_T^2), -1 = none
+    long long sep_off;        // rank-one stamp K_uv = a_u b_v: into psf_sep (a, then b), -1 = none
 };
 
 struct DComp {
@@ -234,6 +243,7 @@ struct Plan {
     const int* par_sub;       // [n_par] sub-problem of each theta index (-1: none)
     const double* bn_tab;     // [2 * BN_COUNT]: b_n, db_n/dn at the table nodes
     const double* ptab;       // [PTAB_N]: the FP64 render's 2^x / log2 table (sersic64.h)
+    const float* psf_sep;     // factors of rank-one stamps (2 P per such image)
 
     // adaptive integration (mode APX_MODE_ADAPTIVE, tolerance k_re)
     const double* agl;        // Gauss-Legendre offsets / weights on [-1/2, 1/2]: o3 w3 o5 w5 o7 w7
@@ -334,6 +344,8 @@ hipError_t launch_conv_fwd(const Plan& p, const ConvLaunch& L, const ConvIO& io,
 hipError_t launch_conv_fwd64(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
 hipError_t launch_conv_jcol(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
 hipError_t launch_conv_adj(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
+// Jacobian-column convolution as two 1-D passes (jobs of shape SHAPE_SEP)
+hipError_t launch_conv_sep(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
 // k_conv_fft.hip: FFT mode (kinds FWD with the FP32 objective, JCOL, ADJ)
 hipError_t launch_conv_fft(const Plan& p, int kind, const ConvLaunch& L, const ConvIO& io, hipStream_t st);
 hipError_t launch_fft_stamps(const Plan& p, int live_only, hipStream_t st);

@@ -263,6 +263,147 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
     }
 }
 
+// Jacobian-column convolution with a rank-one stamp K_UV = a_U b_V (jobs of shape
+// SHAPE_SEP) as two 1-D passes over an SEP_TH x SEP_TW output tile, 256 threads: the input
+// tile with its P - 1 halo is staged in LDS as for the 2-D kernel; the row pass convolves
+// every staged row with b into a second LDS buffer (the tile rows plus the vertical halo);
+// the column pass convolves that with a, each lane making CV_R consecutive outputs of one
+// column, and the epilogue is that of the 2-D kernel's JCOL (column store, FP64 partials
+// of sum w r J and sum w J per item).  2 (P + P (TH + P - 1) / TH) multiply-adds per output
+// instead of 2 P^2.
+template <int P>
+__global__ __launch_bounds__(256) void k_conv_sep(Plan p, const ConvJob* __restrict__ jobs,
+                                                  const ConvItem* __restrict__ items, int item_begin,
+                                                  ConvIO io) {
+    constexpr int TH = SEP_TH, TW = SEP_TW, NT = 256;
+    constexpr int c = (P - 1) / 2;
+    constexpr int LPR = TW / CV_R;                  // lanes per output row
+    constexpr int NW = NT / 64;
+    static_assert(TH * TW / CV_R == NT && TH == CV_R * (NT / TW), "one lane per CV_R outputs of a column");
+    constexpr int LH = TH + P - 1;
+    constexpr int LW0 = TW + P - 1;
+    constexpr int LW = (LW0 + 3) & ~3;
+    __shared__ __attribute__((aligned(16))) float tile[LH * LW];
+    __shared__ __attribute__((aligned(16))) float hb[LH * TW];
+    __shared__ double red[NW][2];
+
+    const int item_idx = item_begin + (int)blockIdx.x;
+    const ConvItem it = items[item_idx];
+    const ConvJob jb = jobs[it.job];
+    const DImage& im = p.images[jb.image];
+    if (io.skip_mode == 1) {
+        if (p.lmf[im.sub].chol_done == 0 || p.lmf[im.sub].trial_bad != 0) return;
+    } else if (io.skip_mode == 2) {
+        if (io.lm[im.sub].need_jac == 0) return;
+    }
+    const int oy0 = jb.out_y0 + it.ty * TH;
+    const int ox0 = jb.out_x0 + it.tx * TW;
+    const int iy_base = oy0 - c, ix_base = ox0 - c;
+
+    // ---- stage the input tile (zero outside the input rectangle)
+    constexpr int NE = (LH * LW0 + NT - 1) / NT;
+    {
+        const float* __restrict__ in = (jb.in_src ? io.in_s : io.in) + jb.in_off + (long long)it.ch * jb.in_cs;
+        const int iy1 = jb.in_y0 + jb.in_h, ix1 = jb.in_x0 + jb.in_w;
+        float v[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int e = threadIdx.x + NT * q;
+            const int ly = e / LW0, lx = e - ly * LW0;
+            const int y = iy_base + ly, x = ix_base + lx;
+            float val = 0.f;
+            if (e < LH * LW0 && y >= jb.in_y0 && y < iy1 && x >= jb.in_x0 && x < ix1)
+                val = in[(long long)(y - jb.in_y0) * jb.in_w + (x - jb.in_x0)];
+            v[q] = val;
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int e = threadIdx.x + NT * q;
+            if (e < LH * LW0) {
+                const int ly = e / LW0, lx = e - ly * LW0;
+                tile[ly * LW + lx] = v[q];
+            }
+        }
+    }
+    __syncthreads();
+
+    const float* __restrict__ fa = p.psf_sep + im.sep_off;       // a_U (rows)
+    const float* __restrict__ fb = fa + P;                       // b_V (columns)
+    // ---- row pass: hb[r][x] = sum_V b_V tile[r][x + P - 1 - V], r < LH, x < TW
+    for (int task = (int)threadIdx.x; task < LH * LPR; task += NT) {
+        const int r = task / LPR, g = task - r * LPR;
+        const float* row = tile + r * LW + g * CV_R;
+        float sw[CV_R + P - 1];
+#pragma unroll
+        for (int k = 0; k < CV_R + P - 1; ++k) sw[k] = row[k];
+        float part[CV_R];
+#pragma unroll
+        for (int q = 0; q < CV_R; ++q) part[q] = 0.f;
+#pragma unroll
+        for (int V = 0; V < P; ++V) {
+            const float kv = fb[V];
+#pragma unroll
+            for (int q = 0; q < CV_R; ++q) part[q] = fmaf(kv, sw[q + P - 1 - V], part[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < CV_R; ++q) hb[r * TW + g * CV_R + q] = part[q];
+    }
+    __syncthreads();
+
+    // ---- column pass: out[y][x] = sum_U a_U hb[y + P - 1 - U][x]; each lane makes CV_R
+    // consecutive outputs of one column from a register window down that column (lanes of
+    // a wave take consecutive columns: conflict-free LDS reads, coalesced stores)
+    const int cx = (int)threadIdx.x % TW, rb = (int)threadIdx.x / TW;      // column, row block
+    float acc[CV_R];
+    {
+        float sw[CV_R + P - 1];
+#pragma unroll
+        for (int k = 0; k < CV_R + P - 1; ++k) sw[k] = hb[(rb * CV_R + k) * TW + cx];
+#pragma unroll
+        for (int q = 0; q < CV_R; ++q) acc[q] = 0.f;
+#pragma unroll
+        for (int U = 0; U < P; ++U) {
+            const float ka = fa[U];
+#pragma unroll
+            for (int q = 0; q < CV_R; ++q) acc[q] = fmaf(ka, sw[q + P - 1 - U], acc[q]);
+        }
+    }
+
+    // ---- epilogue (the JCOL epilogue of the 2-D kernel on a pixel grid)
+    const int x = ox0 + cx;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float* __restrict__ out = io.out + jb.out_off + (long long)it.ch * jb.out_cs;
+    double s1 = 0.0, s2 = 0.0;
+    if (x < jb.out_x0 + jb.out_w) {
+#pragma unroll
+        for (int q = 0; q < CV_R; ++q) {
+            const int y = oy0 + rb * CV_R + q;
+            if (y < jb.out_y0 + jb.out_h) {
+                const long long rowpix = im.pix_off + (long long)y * im.Wc;
+                out[(long long)(y - jb.out_y0) * jb.out_w + (x - jb.out_x0)] = acc[q];
+                if (io.weight) {
+                    const double wj = (double)io.weight[rowpix + x] * (double)acc[q];
+                    s1 += wj * (double)p.rbuf[rowpix + x];
+                    s2 += wj;
+                }
+            }
+        }
+    }
+    if (io.weight) {
+        s1 = conv_wave_sum(s1);
+        s2 = conv_wave_sum(s2);
+        if (lane == 0) { red[wv][0] = s1; red[wv][1] = s2; }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            const int q = threadIdx.x;
+            double sum = red[0][q];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) sum += red[w][q];
+            io.part[(long long)item_idx * 2 + q] = sum;
+        }
+    }
+}
+
 #define APX_FOR_EACH_P(X)                                                                     \
     X(1) X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29)     \
     X(31) X(33) X(35) X(37) X(39) X(41) X(43) X(45) X(47) X(49) X(51) X(53) X(55) X(57)      \
@@ -276,6 +417,22 @@ hipError_t launch_conv_shape(const Plan& p, const ConvLaunch& L, const ConvIO& i
     case PP:                                                                                 \
         hipLaunchKernelGGL((k_conv<PP, KIND, T, TH, TW>), grid, block, 0, st, p, L.jobs,     \
                            L.items, L.item_begin, io);                                      \
+        break;
+        APX_FOR_EACH_P(APX_CASE)
+#undef APX_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+inline hipError_t launch_conv_sep_impl(const Plan& p, const ConvLaunch& L, const ConvIO& io, hipStream_t st) {
+    if (L.item_count <= 0) return hipSuccess;
+    dim3 grid(L.item_count), block(256);
+    switch (L.P) {
+#define APX_CASE(PP)                                                                                   \
+    case PP:                                                                                           \
+        hipLaunchKernelGGL((k_conv_sep<PP>), grid, block, 0, st, p, L.jobs, L.items, L.item_begin, io); \
         break;
         APX_FOR_EACH_P(APX_CASE)
 #undef APX_CASE

@@ -98,6 +98,17 @@ def asymmetric_psf(P: int, rng: np.random.Generator) -> np.ndarray:
     return (k / k.sum()).astype(np.float32)
 
 
+def separable_psf(P: int) -> np.ndarray:
+    """A positive, lopsided stamp that is the outer product of two different vectors
+    (a_u b_v: rank one, rows and columns distinguishable), unit sum, stored FP32."""
+    c = (P - 1) // 2
+    v = np.arange(-c, c + 1, dtype=np.float64)
+    a = np.exp(-(v - 0.7) ** 2 / (2 * 1.3 ** 2))
+    b = np.exp(-(v + 0.4) ** 2 / (2 * 2.1 ** 2)) * (1.0 + 0.1 * v / c)
+    k = np.outer(a, b)
+    return (k / k.sum()).astype(np.float32)
+
+
 # -------------------------------------------------------------------------- helpers
 IDENTITY_AFFINE = np.array([0.0, 1.0, 0.0, 0.0, 0.0, 1.0])
 

@@ -208,8 +208,9 @@ def test_every_tile_shape_keeps_parity(apx, name, shape):
 
 def test_autotuner_times_every_shape(apx):
     """The default policy times the four shapes of each convolution kernel the problem
-    needs and the planner's choice is the cheapest estimate for each job."""
-    spec = get("few_cutouts")
+    needs and the planner's choice is the cheapest estimate for each job (every convolution
+    2-D here: rank-one stamps would take the two-pass Jacobian kernel, which is not tuned)."""
+    spec = dict(get("few_cutouts"), conv_mode=apx.CONV_DIRECT_2D)
     P, _, _ = problem(apx, spec)
     Ps = sorted({int(im["psf"].shape[0]) for im in spec["images"]})
     for Pk in Ps:

@@ -94,7 +94,7 @@ def test_model_tile_policy_prefers_tiles_that_fit_the_output(apx):
     narrower tiles where they cut the padding of a 40-pixel-wide window."""
     big = synth.single(1, H=512, W=512, P=11)
     pl = apx.Plan(big, tiles=apx.TILES_MODEL)
-    assert pl.tile_shapes(0) == [1, 0, 0, 0, 0]
+    assert pl.tile_shapes(0) == [1, 0, 0, 0, 0, 0]
     pl.close()
     small = synth.single(1, H=40, W=40, P=11)
     pl = apx.Plan(small, tiles=apx.TILES_MODEL)
