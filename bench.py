@@ -17,7 +17,9 @@ rendered by the library itself, Gaussian noise of variance model + 0.01^2.
 The dominant kernel class (the Jacobian-column convolutions) is timed live with HIP events
 on the library's stream inside the replayed graphs; its roofline fraction is its
 algorithmic FLOP rate (2 P^2 FLOP per Jacobian entry of the cutouts that form a Jacobian
-in that iteration) over the FP32 VALU peak.  The CPU baseline is the FP64 test oracle run
+in that iteration, for the cutouts whose stamp is not rank one) over the FP32 VALU peak;
+rank-one stamps (the Gaussian PSFs) take two 1-D passes, reported beside it, as is the value
+with every convolution 2-D.  The CPU baseline is the FP64 test oracle run
 on a sample of the cutouts by a process pool, one thread per worker.  The 512 x 512 blend
 (50 Sersic + 200 point sources, 551 parameters in one fit) is reported beside it.
 """
@@ -216,6 +218,30 @@ def jac_entries_per_sub(spec):
     return ent, flop
 
 
+def rank_one_images(spec, conv_mode):
+    """Images whose Jacobian columns the library convolves as two 1-D passes: the stamp is
+    a_u b_v to FP32 rounding (the library's own test, repeated here: with the largest entry
+    at (u0, v0), a_u = K[u, v0], b_v = K[u0, v] / K[u0, v0], every entry within 4e-7 of
+    itself plus 1e-9 of the largest), not live, not sub-pixel, in direct mode."""
+    out = set()
+    if conv_mode != 0:
+        return out
+    live = {int(m["image"]) for m in spec.get("psf_models", [])}
+    for k, im in enumerate(spec["images"]):
+        K = np.asarray(im["psf"], np.float32).astype(np.float64)
+        if k in live or int(im.get("up", 1)) != 1 or K.shape[0] < 3:
+            continue
+        u0, v0 = np.unravel_index(int(np.argmax(np.abs(K))), K.shape)
+        kmax = abs(K[u0, v0])
+        if not kmax > 0:
+            continue
+        a = K[:, v0]
+        b = K[u0, :] / K[u0, v0]
+        if np.all(np.abs(K - np.outer(a, b)) <= 4e-7 * np.abs(K) + 1e-9 * kmax):
+            out.add(k)
+    return out
+
+
 def run_cutouts(args, torch, apx, synth):
     """4096 independent cutouts: the batched LM (every kernel over all cutouts, one HIP
     graph replay per iteration) against the plain per-cutout path (one problem per
@@ -233,26 +259,36 @@ def run_cutouts(args, torch, apx, synth):
     dd, ww = prob.pixels(data), prob.pixels(weight)
     ent, flop_sub = jac_entries_per_sub(spec)
     assert int(ent.sum()) == prob.n_jac, (ent.sum(), prob.n_jac)
+    # cutouts whose stamp is rank one take the two-pass Jacobian kernel: the 2-D class's
+    # algorithmic work counts only the others
+    sep_img = rank_one_images(spec, spec.get("conv_mode", 0))
+    assert prob.tile_shapes(1)[5] == len(sep_img), (prob.tile_shapes(1), len(sep_img))
+    sep_sub = np.zeros(n_sub, bool)
+    for k in sep_img:
+        sep_sub[spec["images"][k]["sub"]] = True
+    flop_2d_sub = np.where(sep_sub, 0.0, flop_sub)
+    ent_sep_sub = np.where(sep_sub, ent, 0.0)
 
     # eager pass over the same iterations, one at a time: which cutouts form a Jacobian in
     # each iteration (need_jac), for the algorithmic FLOP count of the Jacobian phases
     th_e, st_e = prob.lm_init(spec["theta_init"], dd, ww)
-    flop_jac = 0.0
+    flop_jac = ent_sep = 0.0
     for _ in range(args.steps):
         need = prob.lm_state(st_e)["need_jac"] != 0
-        flop_jac += float(flop_sub[need].sum())
+        flop_jac += float(flop_2d_sub[need].sum())
+        ent_sep += float(ent_sep_sub[need].sum())
         prob.lm_step(dd, ww, th_e, st_e)
     prob.check()
     torch.cuda.synchronize()
-    print(f"[bench] eager pass done ({flop_jac / 1e12:.2f} TFLOP of Jacobian convolutions)", file=sys.stderr,
-          flush=True)
+    print(f"[bench] eager pass done ({flop_jac / 1e12:.2f} TFLOP of 2-D Jacobian convolutions, "
+          f"{ent_sep / 1e9:.2f} G entries by two passes)", file=sys.stderr, flush=True)
 
     # warm-up: captures the iteration graph with HIP events around the Jacobian convolutions
     th, st = prob.lm_init(spec["theta_init"], dd, ww)
-    prob.set_timing(True, classes=["conv_jcol"])
+    prob.set_timing(True, classes=["conv_jcol", "conv_sep"])
     prob.lm_run(max(1, args.warmup), dd, ww, th, st, use_graph=True)
     prob.timing()
-    prob.set_timing(True, classes=["conv_jcol"])     # clears the records, keeps the graph
+    prob.set_timing(True, classes=["conv_jcol", "conv_sep"])     # clears the records, keeps the graph
     prob.lm_init(spec["theta_init"], dd, ww, theta_out=th, state_out=st)
     torch.cuda.synchronize()
 
@@ -270,6 +306,7 @@ def run_cutouts(args, torch, apx, synth):
     print(f"[bench] {args.steps} batched iterations in {t_graph * 1e3:.1f} ms (graph = eager: {same})",
           file=sys.stderr, flush=True)
     jcol_ms, jcol_launches = kt["conv_jcol"]
+    sep_ms, _ = kt["conv_sep"]
     achieved = flop_jac / (jcol_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
 
     # eager batched, the same iterations
@@ -279,6 +316,22 @@ def run_cutouts(args, torch, apx, synth):
     prob.lm_run(args.steps, dd, ww, th2, st2, use_graph=False)
     torch.cuda.synchronize()
     t_eager = time.perf_counter() - t0
+
+    # context: the same K iterations with every convolution 2-D (no two-pass Jacobians)
+    value_2d = None
+    if not args.no_2d_context:
+        spec2 = dict(spec, conv_mode=apx.CONV_DIRECT_2D)
+        q2 = apx.Problem(spec2)
+        t2, s2 = q2.lm_init(spec["theta_init"], dd, ww)
+        q2.lm_run(1, dd, ww, t2, s2, use_graph=True)
+        q2.lm_init(spec["theta_init"], dd, ww, theta_out=t2, state_out=s2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q2.lm_run(args.steps, dd, ww, t2, s2, use_graph=True)
+        torch.cuda.synchronize()
+        value_2d = n_sub * args.steps / (time.perf_counter() - t0)
+        q2.check()
+        q2.close()
 
     # plain path on a sample of cutouts: one problem per cutout, K eager iterations with
     # device-side control and one synchronisation at the end; also with a host read of the
@@ -341,9 +394,13 @@ def run_cutouts(args, torch, apx, synth):
         "mpix_per_s": mpix,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
-                     "kernel": "k_conv<P,JCOL> (all PSF sizes and tile shapes of a Jacobian phase)",
+                     "kernel": "k_conv<P,JCOL> (2-D Jacobian-column convolutions: all PSF sizes and tile "
+                               "shapes of a phase, cutouts whose stamp is not rank one)",
                      "ms_per_phase": jcol_ms / max(1, args.steps), "flop_per_phase": flop_jac / max(1, args.steps),
                      "launch_groups": jcol_launches},
+        "two_pass_jacobian": {"kernel": "k_conv_sep<P> (rank-one stamps)", "ms_per_phase": sep_ms / max(1, args.steps),
+                              "entries_per_phase": ent_sep / max(1, args.steps), "images": len(sep_img)},
+        "value_all_2d_convolutions": value_2d,
         "covariance_ms": cov_ms,
         "accepted_mean": float(np.mean(stt["n_accept"])),
         "tile_shapes": tile_choice(prob),
@@ -638,6 +695,8 @@ def main():
                     help="cutouts (default, the headline line, with the blend beside it); the others print "
                          "their own line")
     ap.add_argument("--no-blend", action="store_true", help="cutouts: leave out the blend beside the headline")
+    ap.add_argument("--no-2d-context", action="store_true",
+                    help="cutouts: leave out the same iterations with every convolution 2-D")
     args = ap.parse_args()
     CONV_MODE[0] = args.conv
     world = int(os.environ.get("WORLD_SIZE", "1"))

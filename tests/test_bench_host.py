@@ -79,3 +79,18 @@ def test_cpu_baseline_runs_the_oracle_on_a_process_pool():
     rec = bench.cpu_baseline_cutouts(spec, data, weight, synth, stride=2, n_iter=1)
     assert rec["kind"] == "oracle" and rec["value"] > 0 and 1 <= rec["cores"] <= 16
     assert rec["unit"] == "cutout LM it/s" and "2 of 4 cutouts" in rec["sample"]
+
+
+def test_rank_one_images_follow_the_library_rule():
+    """The bench's copy of the rank-one test: Gaussian and outer-product stamps qualify,
+    Moffat and asymmetric ones do not; FFT or 2-D mode and live images never do."""
+    import numpy as np
+    from paper_2308_01957_amd import synth
+    rng = np.random.default_rng(0)
+    psfs = [synth.gaussian_psf(15, 2.0), synth.separable_psf(9), synth.moffat_psf(11, 3.0, 2.5),
+            synth.asymmetric_psf(9, rng)]
+    spec = {"images": [dict(psf=k) for k in psfs], "psf_models": []}
+    assert bench.rank_one_images(spec, 0) == {0, 1}
+    assert bench.rank_one_images(spec, 1) == set() and bench.rank_one_images(spec, 2) == set()
+    spec["psf_models"] = [dict(image=0)]
+    assert bench.rank_one_images(spec, 0) == {1}
