@@ -110,6 +110,8 @@ struct apx_problem {
     bool has_live_cols = false;                   // some live PSF has a free parameter
     std::vector<DPair> pairs;
     std::vector<PairItem> pitems64, pitems16;
+    std::vector<PairItem> gitems;                 // 4 x 4-block Gram items, sorted by tile count
+    int gram_begin[GRAM4_MAX_T + 2] = {};         // items of tile count t: [gram_begin[t], gram_begin[t + 1])
     // reduction tables
     std::vector<int> img_seg, img_idx;            // FWD items of each image
     std::vector<int> col_seg, col_idx;            // JCOL items of each column
@@ -1164,6 +1166,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     {
         struct Wide { int pi, na, nb, tri, stages; };
         std::vector<Wide> wide;
+        std::vector<std::vector<PairItem>> gram_items(GRAM4_MAX_T + 1);
         long long outoff = 0;
         auto tile_pairs = [](int na, int nb, int tri) { return tri ? na * (na + 1) / 2 : na * nb; };
         // K-slices outermost: the tile pairs that run together read the same rows of J
@@ -1201,6 +1204,20 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
                     const int na = ceil_div(G.ncols, tm), nb = ceil_div(H.ncols, tm);
                     const int stages = (y1 - y0) * ceil_div(x1 - x0, PAIR_KC);
                     const bool tri = gl[a] == gl[b];
+                    if (tri && G.ncols <= 4 * GRAM4_MAX_T) {
+                        // a narrow group with itself: 4 x 4 blocks (k_gram4), K-slices of ~4096 px
+                        const int nt = ceil_div(G.ncols, 4);
+                        const int per = std::max(1, 4096 / PAIR_KC);
+                        for (int s0 = 0; s0 < stages; s0 += per) {
+                            PairItem it{};
+                            it.pair = pi;
+                            it.ta = nt;
+                            it.s0 = s0;
+                            it.s1 = std::min(stages, s0 + per);
+                            gram_items[nt].push_back(it);
+                        }
+                        continue;
+                    }
                     if (tm == 64) {
                         wide.push_back({pi, na, nb, tri ? 1 : 0, stages});
                         continue;
@@ -1218,6 +1235,16 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             slices = std::min(slices, std::max(1, w.stages / 32));
             add_pair_items(w.pi, w.na, w.nb, w.tri, w.stages, ceil_div(w.stages, slices), 64);
         }
+        P->gitems.clear();
+        for (int t = 0; t <= GRAM4_MAX_T; ++t) {
+            P->gram_begin[t] = (int)P->gitems.size();
+            for (PairItem it : gram_items[t]) {
+                it.out_off = outoff;
+                outoff += (long long)16 * t * (t + 1) / 2;
+                P->gitems.push_back(it);
+            }
+        }
+        P->gram_begin[GRAM4_MAX_T + 1] = (int)P->gitems.size();
         P->n_pairpart = outoff;
     }
     P->asrc_col = P->n_pairpart;
@@ -1264,9 +1291,27 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
                 }
             }
         };
-        // keep item order: 64-tiles then 16-tiles, each in item order
+        // keep item order: 64-tiles, 16-tiles, then 4 x 4-block Gram items, each in item order
         add_items_tm(P->pitems64, 64);
         add_items_tm(P->pitems16, 16);
+        for (const PairItem& it : P->gitems) {
+            const DPair& pr = P->pairs[it.pair];
+            const DGroup& G = P->groups[pr.g];
+            int q = 0;
+            for (int ta = 0; ta < it.ta; ++ta)
+                for (int tb = ta; tb < it.ta; ++tb, ++q)
+                    for (int i = 0; i < 4; ++i) {
+                        const int ci = 4 * ta + i;
+                        if (ci >= G.ncols) break;
+                        for (int j = 0; j < 4; ++j) {
+                            const int cj = 4 * tb + j;
+                            if (cj >= G.ncols) break;
+                            if (ci > cj) continue;
+                            const int pp = P->cols[G.col_begin + ci].par, qq = P->cols[G.col_begin + cj].par;
+                            add(pp, qq, it.out_off + (long long)q * 16 + i * 4 + j, (pp == qq && ci != cj) ? 2 : 1);
+                        }
+                    }
+        }
         for (int k = 0; k < d->n_images; ++k) {
             const DImage& im = P->images[k];
             if (im.sky_par < 0) continue;
@@ -1389,6 +1434,7 @@ static void layout(apx_problem* P) {
     ws_take<DPair>(P, "pairs", P->pairs.size());
     ws_take<PairItem>(P, "pitems64", P->pitems64.size());
     ws_take<PairItem>(P, "pitems16", P->pitems16.size());
+    ws_take<PairItem>(P, "gitems", P->gitems.size());
     ws_take<int>(P, "img_seg", P->img_seg.size());
     ws_take<int>(P, "img_idx", P->img_idx.size());
     ws_take<int>(P, "col_seg", P->col_seg.size());
@@ -1637,6 +1683,7 @@ apx_status apx_problem_bind_workspace(apx_problem* P, void* dev, uint64_t bytes)
     HIPCHK(upload(P, "pairs", P->pairs));
     HIPCHK(upload(P, "pitems64", P->pitems64));
     HIPCHK(upload(P, "pitems16", P->pitems16));
+    HIPCHK(upload(P, "gitems", P->gitems));
     HIPCHK(upload(P, "img_seg", P->img_seg));
     HIPCHK(upload(P, "img_idx", P->img_idx));
     HIPCHK(upload(P, "col_seg", P->col_seg));
@@ -2066,6 +2113,12 @@ static apx_status normal_eq(apx_problem* P, const float* weight, double* A_out, 
         TimeScope ts(P, APX_TIME_PAIRS);
         HIPCHK(launch_pairs(p, L64, weight, lm, st));
         HIPCHK(launch_pairs(p, L16, weight, lm, st));
+        for (int t = 1; t <= GRAM4_MAX_T; ++t) {
+            const int b = P->gram_begin[t], n = P->gram_begin[t + 1] - b;
+            if (n <= 0) continue;
+            PairLaunch G4{wsp<DPair>(P, "pairs"), wsp<PairItem>(P, "gitems") + b, n, t};
+            HIPCHK(launch_gram4(p, G4, weight, lm, st));
+        }
     }
     TimeScope ts(P, APX_TIME_REDUCE);
     AsmA a{};

@@ -145,6 +145,10 @@ struct DPair {
 // one tile pair over stages [s0, s1) of the pair's box (stage s: row y0 + s / nxs, pixels
 // x0 + (s % nxs) KC ... of that row, nxs = ceil((x1 - x0) / KC))
 struct PairItem { int pair, ta, tb, s0, s1, pad; long long out_off; };
+// The J^T W J of a narrow group with itself (at most GRAM4_MAX_T tiles of 4 columns) over one
+// K-slice, by 4 x 4 FP64 MFMA blocks: item.ta = the group's 4-column tiles; the partial is
+// every tile pair (a <= b, row-major over the upper triangle) as a 4 x 4 block.
+constexpr int GRAM4_MAX_T = 9;
 
 // Adaptive integration: the Sersic windows cut into chunks of up to ADAPT_CHUNK pixels
 // (row-major window order); a pixel that needs sub-pixels is appended to the refine list.
@@ -355,6 +359,9 @@ struct PairLaunch { const DPair* pairs; const PairItem* items; int n_items; int 
 // Workgroups of k_pair<tm> resident per compute unit (0 if the runtime cannot say).
 int pair_blocks_per_cu(int tm);
 hipError_t launch_pairs(const Plan& p, const PairLaunch& L, const float* weight,
+                        const apx_lm_state* lm, hipStream_t st);
+// L.items: Gram items with L.tm = the number of 4-column tiles (1..GRAM4_MAX_T)
+hipError_t launch_gram4(const Plan& p, const PairLaunch& L, const float* weight,
                         const apx_lm_state* lm, hipStream_t st);
 struct SegSum {
     const double* src; int stride, comp;

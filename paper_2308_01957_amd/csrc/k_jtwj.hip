@@ -160,6 +160,104 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     }
 }
 
+// J^T W J of a narrow group (NT tiles of 4 columns, at most 36 columns) with itself over one
+// K-slice, on v_mfma_f64_4x4x4f64: the instruction holds four independent 4 x 4 x 4 products
+// (blocks), block b of lanes 16 k + 4 b + i (A[i][k], B[k][j] at lane 16 k + 4 b + j, D[i][j] at
+// lane 16 i + 4 b + j; measured on gfx950).  Lane L takes pixel L / 4 of a 16-pixel chunk and
+// column L % 4 of a tile, so one instruction contracts 16 pixels of one 4 x 4 tile pair, and
+// the tiles are loaded straight from J into registers (each reused by every pair it is in).
+// Waves take every fourth 32-pixel stage of the slice; at the end each wave folds its four
+// blocks (lanes xor 4, xor 8) and the four waves are added in order.  Against 16 x 16 tiles
+// this pads a group of 7k columns to a multiple of 4, not 16.
+template <int NT>
+__global__ __launch_bounds__(256) void k_gram4(Plan p, const DPair* __restrict__ pairs,
+                                               const PairItem* __restrict__ items, int n_items,
+                                               const float* __restrict__ weight, const apx_lm_state* lm) {
+    constexpr int NP = NT * (NT + 1) / 2;
+    constexpr int KC = PAIR_KC;
+    const PairItem it = items[xcd_item((int)blockIdx.x, n_items)];
+    const DPair pr = pairs[it.pair];
+    if (lm && lm[pr.sub].need_jac == 0) return;
+    const DGroup G = p.groups[pr.g];
+    const long long pix_off = p.images[pr.image].pix_off;
+    const int imW = p.images[pr.image].Wc;
+    const long long gs = (long long)G.oh * G.ow;
+    const float* __restrict__ Jg = p.J + G.j_off;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 3, pxl = lane >> 2;       // column within a tile, pixel within a chunk
+    const long long lastA = (long long)(G.ncols - 1) * gs - G.ox0;
+    long long coff[NT];
+    bool cval[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int ca = 4 * t + col;
+        cval[t] = ca < G.ncols;
+        coff[t] = cval[t] ? (long long)ca * gs - G.ox0 : lastA;
+    }
+    double acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+    const int nxs = (pr.x1 - pr.x0 + KC - 1) / KC;
+    for (int st = it.s0 + wv; st < it.s1; st += 4) {
+        const int row = pr.y0 + st / nxs;
+        const int xs = pr.x0 + (st - (st / nxs) * nxs) * KC;
+#pragma unroll
+        for (int h = 0; h < KC / 16; ++h) {
+            const int x = xs + 16 * h + pxl;
+            const bool in = x < pr.x1;
+            const int xc = in ? x : pr.x1 - 1;
+            const long long grow = (long long)(row - G.oy0) * G.ow + xc;
+            const float wf = weight[pix_off + (long long)row * imW + xc];
+            const double w = in ? (double)wf : 0.0;
+            double b[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const float v = Jg[coff[t] + grow];
+                b[t] = (in && cval[t]) ? (double)v : 0.0;
+            }
+            int q = 0;
+#pragma unroll
+            for (int ta = 0; ta < NT; ++ta) {
+                const double a = b[ta] * w;
+#pragma unroll
+                for (int tb = ta; tb < NT; ++tb, ++q)
+                    acc[q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b[tb], acc[q], 0, 0, 0);
+            }
+        }
+    }
+    // fold the four blocks of each wave, then the four waves in order
+    __shared__ double red[4][NP * 16];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        double v = acc[q];
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        // lanes with block 0 (lane % 16 < 4) hold D[i][j] at lane 16 i + j
+        if ((lane & 12) == 0) red[wv][q * 16 + (lane >> 4) * 4 + (lane & 3)] = v;
+    }
+    __syncthreads();
+    double* out = p.pair_part + it.out_off;
+    for (int e = (int)threadIdx.x; e < NP * 16; e += 256)
+        out[e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+}
+
+hipError_t launch_gram4(const Plan& p, const PairLaunch& L, const float* weight,
+                        const apx_lm_state* lm, hipStream_t st) {
+    if (L.n_items <= 0) return hipSuccess;
+    dim3 grid(L.n_items), block(256);
+    switch (L.tm) {
+#define APX_G4(T)                                                                                       \
+    case T:                                                                                             \
+        hipLaunchKernelGGL(k_gram4<T>, grid, block, 0, st, p, L.pairs, L.items, L.n_items, weight, lm); \
+        break;
+        APX_G4(1) APX_G4(2) APX_G4(3) APX_G4(4) APX_G4(5) APX_G4(6) APX_G4(7) APX_G4(8) APX_G4(9)
+#undef APX_G4
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 int pair_blocks_per_cu(int tm) {
     int nb = 0;
     const hipError_t e = tm == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair<64>, 256, 0)
