@@ -483,8 +483,13 @@ apx_status apx_nuts_warmup(apx_problem* p, const float* data, const float* weigh
 apx_status apx_render_vjp(apx_problem* p, const double* theta, const float* grad_model,
                           double* grad_theta);
 
-/* Initialise the LM state of every sub-problem at theta (lambda = LM_LAMBDA0,
- * chi2 and residual at theta). */
+/* Initialise the Levenberg-Marquardt state of every sub-problem at theta (§2.5: the fit
+ * starts from the initial parameters with a small damping): lambda = 1e-2, chi2 and the
+ * residual at theta (the objective path), need_jac = 1 so the first apx_lm_step forms the
+ * normal equations, counters zeroed.  theta: device FP64 [n_par], read only (copy it into
+ * the buffer the iterations update); data, weight: device FP32 [n_pix]; state: device,
+ * [n_sub] apx_lm_state, overwritten.  Out-of-domain theta raises the sticky APX_E_DOMAIN
+ * flag (apx_problem_check).  Asynchronous on the context stream. */
 apx_status apx_lm_init(apx_problem* p, const double* theta, const float* data,
                        const float* weight, apx_lm_state* state);
 
@@ -495,8 +500,13 @@ apx_status apx_lm_init(apx_problem* p, const double* theta, const float* data,
 apx_status apx_lm_step(apx_problem* p, const float* data, const float* weight,
                        double* theta, apx_lm_state* state);
 
-/* n_iter LM iterations.  use_graph != 0 captures one iteration into a HIP graph on
- * first use (per data/weight/theta/state pointer set) and replays it. */
+/* n_iter Levenberg-Marquardt iterations (§2.5), each exactly apx_lm_step, and for many
+ * sub-problems the batching of many small models in one problem (§3.2).  use_graph != 0
+ * captures one iteration into a HIP graph on first use (per data / weight / theta / state
+ * pointer set and timing classes) and replays it n_iter times: no host work per iteration,
+ * results bitwise those of eager iterations.  Buffers as in apx_lm_step (theta and state
+ * updated in place on the device); n_iter >= 0, else APX_E_INVALID; a graph needs a
+ * non-default context stream (APX_E_INVALID otherwise).  Asynchronous. */
 apx_status apx_lm_run(apx_problem* p, int32_t n_iter, const float* data,
                       const float* weight, double* theta, apx_lm_state* state,
                       int32_t use_graph);
