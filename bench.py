@@ -196,7 +196,89 @@ def _mpix(prob, spec, torch, reps):
     return prob.n_pix * reps / (time.perf_counter() - t0) / 1e6
 
 
-def jac_entries_per_sub(spec):
+def calls_per_launch_count(prob, th, dd, ww):
+    """Timed launches of the objective convolution per objective evaluation and of the
+    adjoint convolution per gradient evaluation (one per (P, tile shape) range), read from
+    one timed call of each."""
+    prob.set_timing(True, classes=["conv_fwd", "conv_adj"])
+    prob.chi2(th, dd, ww)
+    n_fwd = prob.timing()["conv_fwd"][1]
+    prob.set_timing(True, classes=["conv_fwd", "conv_adj"])
+    prob.chi2_grad(th, dd, ww)
+    n_adj = prob.timing()["conv_adj"][1]
+    prob.set_timing(False)
+    return max(1, n_fwd), max(1, n_adj)
+
+
+def class_rooflines(spec, prob, kt, phases, per_call=(1, 1), n_obj=None):
+    """Roofline of each timed kernel class that has an algorithmic count, over a timed
+    region with `phases` Jacobian phases (kt: {class: (ms, launches)}; per_call: launches
+    per objective and per gradient evaluation, which count the evaluations when every
+    launch does its work; n_obj: the objective evaluations that did work, where some
+    launches find nothing to do):
+    2-D Jacobian convolutions (2 P^2 per Jacobian entry of images whose stamp is not rank
+    one, and 2 P^2 per image pixel for each live-PSF parameter column; FP32 vector peak),
+    the objective convolution (2 P^2 per image pixel per evaluation; FP64 or FP32 vector
+    peak), the adjoint convolution (2 P^2 per image pixel per gradient; FP32 vector peak),
+    the J^T W J tiles (2 FLOP per pixel and upper-triangle column pair of each pair of
+    column groups that meet; FP64 MFMA peak).  Returns (dominant of those by time, all)."""
+    conv_mode = spec.get("conv_mode", 0)
+    sep = rank_one_images(spec, conv_mode)
+    ent, flop = jac_entries_per_sub(spec, exclude_images=sep)
+    fp64 = prob.objective == 0
+    img_flop = [2.0 * np.asarray(im["psf"]).shape[0] ** 2 * int(im.get("up", 1)) ** 2 * im["H"] * im["W"]
+                for im in spec["images"]]
+    fwd = sum(img_flop)
+    psf_cols = sum(img_flop[int(m["image"])] * sum(1 for q in m["par"] if q >= 0)
+                   for m in spec.get("psf_models", []))
+    # column groups: the free parameters of one component share one output window
+    groups = []
+    for c in spec["comps"]:
+        n = sum(1 for q in c["par"] if q >= 0)
+        if n:
+            groups.append((c["image"], output_window(c, spec["images"][c["image"]]), n))
+    pair_flop = 0.0
+    for a in range(len(groups)):
+        for b in range(a, len(groups)):
+            (ia, wa, na), (ib, wb, nb) = groups[a], groups[b]
+            if ia != ib:
+                continue
+            npix = max(0, min(wa[2], wb[2]) - max(wa[0], wb[0])) * max(0, min(wa[3], wb[3]) - max(wa[1], wb[1]))
+            pair_flop += 2.0 * npix * (na * (na + 1) / 2 if a == b else na * nb)
+    n_fwd = kt.get("conv_fwd", (0.0, 0))[1] / per_call[0] if n_obj is None else n_obj
+    n_adj = kt.get("conv_adj", (0.0, 0))[1] / per_call[1]
+    models = {"pairs": (pair_flop * phases, PEAK_FP64_TFLOPS, "k_pair / k_gram4 (FP64 MFMA)")}
+    if conv_mode == 0:       # the direct-convolution counts do not price an FFT convolution
+        models["conv_jcol"] = ((float(flop.sum()) + psf_cols) * phases, PEAK_FP32_VALU_TFLOPS,
+                               "k_conv<P,JCOL> (2-D)")
+        models["conv_fwd"] = (fwd * n_fwd, PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_VALU_TFLOPS,
+                              "k_conv<P,FWD,%s>" % ("double" if fp64 else "float"))
+        models["conv_adj"] = (fwd * n_adj, PEAK_FP32_VALU_TFLOPS, "k_conv<P,ADJ>")
+    out = {}
+    for cls, (fl, peak, name) in models.items():
+        ms = kt.get(cls, (0.0, 0))[0]
+        if ms <= 0 or fl <= 0:
+            continue
+        ach = fl / (ms * 1e-3) / 1e12
+        out[cls] = {"bound": "alu" if cls != "pairs" else "mfma", "kernel": name, "achieved": ach, "peak": peak,
+                    "unit": "TFLOP/s", "frac": ach / peak, "ms_total": ms, "traffic": None}
+    dom = max(out, key=lambda k: out[k]["ms_total"]) if out else None
+    return (out[dom] if dom else None), out
+
+
+def output_window(c, im):
+    """Output pixels [y0, x0, y1, x1) a component's Jacobian columns reach: its window
+    grown by the PSF half-width, cut to the image, in output (coarse) pixels."""
+    P = np.asarray(im["psf"]).shape[0]
+    up = int(im.get("up", 1))
+    h = (P - 1) // 2
+    y0, x0, y1, x1 = c["box"]
+    oy0, ox0 = max(0, y0 - h) // up, max(0, x0 - h) // up
+    oy1, ox1 = min(up * im["H"], y1 + h), min(up * im["W"], x1 + h)
+    return oy0, ox0, -(-oy1 // up), -(-ox1 // up)
+
+
+def jac_entries_per_sub(spec, exclude_images=()):
     """Jacobian entries (output pixels of every convolved column) of each sub-problem:
     a free parameter of a Sersic or point source is one column over the output pixels its
     window reaches (the window grown by the PSF half-width, cut to the image); the sky
@@ -204,14 +286,13 @@ def jac_entries_per_sub(spec):
     ent = np.zeros(len(spec["subs"]))
     flop = np.zeros(len(spec["subs"]))
     for c in spec["comps"]:
+        if c["image"] in exclude_images:
+            continue
         im = spec["images"][c["image"]]
         P = np.asarray(im["psf"]).shape[0]
         up = int(im.get("up", 1))
-        h = (P - 1) // 2
-        y0, x0, y1, x1 = c["box"]
-        oy0, ox0 = max(0, y0 - h) // up, max(0, x0 - h) // up
-        oy1, ox1 = min(up * im["H"], y1 + h), min(up * im["W"], x1 + h)
-        npix = max(0, -(-oy1 // up) - oy0) * max(0, -(-ox1 // up) - ox0)
+        oy0, ox0, oy1, ox1 = output_window(c, im)
+        npix = max(0, oy1 - oy0) * max(0, ox1 - ox0)
         ncol = sum(1 for q in c["par"] if q >= 0)
         ent[im["sub"]] += ncol * npix
         flop[im["sub"]] += ncol * npix * 2.0 * P * P * up * up
@@ -492,6 +573,16 @@ def run_lm_workload(args, torch, apx, synth, spec, label, desc):
     th, st = prob.lm_init(spec["theta_init"], dd, ww)
     prob.lm_run(args.warmup, dd, ww, th, st)
     torch.cuda.synchronize()
+    # eager pass over the same iterations, one at a time: the Jacobian phases (need_jac on
+    # entry) and the trials whose objective was evaluated (finite chi2_trial; a failed
+    # Cholesky or an out-of-domain trial skips the objective convolution)
+    th, st = prob.lm_init(spec["theta_init"], dd, ww)
+    phases = n_obj = 0
+    for _ in range(args.steps):
+        phases += int(prob.lm_state(st)["need_jac"][0] != 0)
+        prob.lm_step(dd, ww, th, st)
+        n_obj += int(np.isfinite(prob.lm_state(st)["chi2_trial"][0]))
+    prob.check()
     th, st = prob.lm_init(spec["theta_init"], dd, ww)
     torch.cuda.synchronize()
     prob.set_timing(True)
@@ -502,11 +593,15 @@ def run_lm_workload(args, torch, apx, synth, spec, label, desc):
     kt = prob.timing()
     prob.set_timing(False)
     stt = prob.lm_state(st)
+    dominant, per_class = class_rooflines(_conv(args, spec), prob, kt, phases, n_obj=n_obj)
+    top = max(kt, key=lambda k: kt[k][0])
     _line({
         "metric": "LM iters/s & Mpix/s rendered (fused adjoint+batched vs plain) at oracle rtol",
         "workload": label, "value": args.steps / dt, "unit": "LM it/s", "ms_per_step": dt * 1e3 / args.steps,
         "n_gpus": 1, "steps": args.steps, "mpix_per_s": _mpix(prob, spec, torch, 10),
         "accepted": int(stt["n_accept"][0]),
+        "roofline": dominant, "roofline_per_class": per_class, "top_class": top,
+        "jacobian_phases": phases, "objective_evaluations": n_obj,
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
         "tile_shapes": tile_choice(prob),
         "config": {"workload": desc, "n_par": spec["n_par"], "n_pix": prob.n_pix},
@@ -599,6 +694,8 @@ def run_hmc(args, torch, apx, synth):
     prob.set_timing(False)
     prob.check()
     acc = float(stats[:, 0, 0].mean().cpu())
+    dominant, per_class = class_rooflines(_conv(args, spec), prob, kt, 0, calls_per_launch_count(prob, th, dd, ww))
+    top = max(kt, key=lambda k: kt[k][0])
     _line({
         "metric": "NUTS transitions/s (LM covariance mass matrix) on the Bayesian mock",
         "workload": "hmc", "value": n_samp / dt_nuts, "unit": "NUTS samples/s", "ms_per_step": dt_nuts * 1e3 / n_samp,
@@ -607,6 +704,8 @@ def run_hmc(args, torch, apx, synth):
         "nuts_leapfrog_per_sample": float(nst[:, 1].mean()), "nuts_divergent": int(nst[:, 3].sum()),
         "hmc_samples_per_s": n_samp / dt, "hmc_gradient_passes_per_s": n_samp * n_leap / dt, "hmc_accept_rate": acc,
         "hmc_kernel_ms_per_sample": {k: round(v[0] / n_samp, 4) for k, v in kt.items()},
+        "roofline": dominant, "roofline_per_class": per_class, "top_class": top,
+        "roofline_note": "classes of the timed plain-HMC transitions (NUTS runs the same kernels)",
         "paper_context": "NUTS, 20 warm-up + 250 samples of a 13-parameter mock in 738.5 s, hardware unstated",
         "config": {"workload": "128x128, 1 Sersic + 1 star + sky, live Moffat PSF 25x25 (n, R_d fitted), "
                                "11 params; NUTS 20 warm-up (dual averaging, target 0.8) + 25 x steps, depth <= 8; "

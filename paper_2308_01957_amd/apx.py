@@ -242,6 +242,7 @@ class Problem:
         self.stream = torch.cuda.Stream(device=self.device)
         self.n_par = int(spec["n_par"])
         self.n_sub = len(spec["subs"])
+        self.objective = int(objective)
         self.shapes = [(int(im["H"]), int(im["W"])) for im in spec["images"]]
         self.offsets = np.concatenate([[0], np.cumsum([h * w for h, w in self.shapes])]).astype(np.int64)
         self.n_pix = int(self.offsets[-1])

@@ -94,3 +94,33 @@ def test_rank_one_images_follow_the_library_rule():
     assert bench.rank_one_images(spec, 1) == set() and bench.rank_one_images(spec, 2) == set()
     spec["psf_models"] = [dict(image=0)]
     assert bench.rank_one_images(spec, 0) == {1}
+
+
+def test_class_rooflines_count_by_hand():
+    """Per-class algorithmic FLOP of a two-component image worked out by hand: windows grown
+    by the PSF half-width and cut to the image, J^T W J pairs over the windows' overlap,
+    objective and adjoint convolutions per evaluation; FFT mode prices only the pairs."""
+    import numpy as np
+
+    class _Prob:
+        objective = 0
+    K = np.array([[0.0, 1.0, 0.0], [1.0, 2.0, 1.0], [0.0, 1.0, 0.5]])
+    spec = {"images": [dict(H=10, W=12, psf=K, sub=0)], "subs": [(0, 5)], "psf_models": [],
+            "comps": [dict(image=0, box=(2, 3, 6, 8), par=[0, 1, 2]),
+                      dict(image=0, box=(5, 6, 10, 12), par=[3, -1, 4])]}
+    assert bench.rank_one_images(spec, 0) == set()
+    kt = {"conv_jcol": (2.0, 4), "pairs": (1.0, 4), "conv_fwd": (0.5, 6), "conv_adj": (0.25, 2), "render": (9.0, 6)}
+    dom, per = bench.class_rooflines(spec, _Prob(), kt, phases=3, per_call=(2, 1))
+    flop = {k: v["achieved"] * 1e12 * v["ms_total"] * 1e-3 for k, v in per.items()}
+    # windows (1,2,7,9) and (4,5,10,12): 42 pixels each, overlap 3 x 4 = 12
+    assert np.isclose(flop["conv_jcol"], 3 * (3 * 42 + 2 * 42) * 2 * 9)
+    assert np.isclose(flop["pairs"], 3 * (2 * 42 * 6 + 2 * 42 * 3 + 2 * 12 * 3 * 2))
+    assert np.isclose(flop["conv_fwd"], 3 * 2 * 9 * 120)       # 6 launches, 2 per evaluation
+    assert np.isclose(flop["conv_adj"], 2 * 2 * 9 * 120)
+    assert per["conv_fwd"]["peak"] == bench.PEAK_FP64_TFLOPS and per["conv_jcol"]["peak"] == bench.PEAK_FP32_VALU_TFLOPS
+    assert dom is per["conv_jcol"] and "render" not in per
+    _, per = bench.class_rooflines(spec, _Prob(), kt, phases=3, per_call=(2, 1), n_obj=1)   # 2 launches idle
+    assert np.isclose(per["conv_fwd"]["achieved"] * 1e12 * 0.5e-3, 2 * 9 * 120)
+    spec["conv_mode"] = 1
+    _, per = bench.class_rooflines(spec, _Prob(), kt, phases=3)
+    assert set(per) == {"pairs"}
