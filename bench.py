@@ -342,7 +342,7 @@ def run_cutouts(args, torch, apx, synth):
     assert int(ent.sum()) == prob.n_jac, (ent.sum(), prob.n_jac)
     # cutouts whose stamp is rank one take the two-pass Jacobian kernel: the 2-D class's
     # algorithmic work counts only the others
-    sep_img = rank_one_images(spec, spec.get("conv_mode", 0))
+    sep_img = rank_one_images(spec, 1 if args.conv == "fft" else spec.get("conv_mode", 0))
     assert prob.tile_shapes(1)[5] == len(sep_img), (prob.tile_shapes(1), len(sep_img))
     sep_sub = np.zeros(n_sub, bool)
     for k in sep_img:
