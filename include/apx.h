@@ -450,8 +450,12 @@ apx_status apx_hmc_run(apx_problem* p, const float* data, const float* weight, d
  * stops at max_depth doublings (1..APX_NUTS_MAX_DEPTH).  theta: device [n_par], in: start,
  * out: last sample.  samples: device FP64 [n_samples * n_par].  stats: device FP64
  * [n_samples * 4] = (depth, leapfrog steps, points in the slice, divergent).  The tree
- * logic runs on the host between device reductions (one synchronisation per leapfrog step
- * and per U-turn test); returns after the last transition.  Uses the LM's Cholesky scratch. */
+ * state lives on the device: each doubling is issued as one fixed sequence of launches
+ * (every leaf, merge and U-turn test of a tree of that depth, acting only while the tree has
+ * not stopped; a leaf after a stop re-runs the gradient pass on the last point and changes
+ * nothing), and the host reads the tree state once per doubling to decide whether to double
+ * again.  u is read on the device and, for the directions, once on the host.  Returns after
+ * the last transition.  Uses the LM's Cholesky scratch. */
 #define APX_NUTS_MAX_DEPTH 10
 #define APX_NUTS_DELTA_MAX 1000.0
 apx_status apx_nuts_run(apx_problem* p, const float* data, const float* weight, double* theta,

@@ -1524,7 +1524,7 @@ static void layout(apx_problem* P) {
     ws_take<double>(P, "nuts_lvl", (size_t)(APX_NUTS_MAX_DEPTH + 1) * 7 * P->n_par);
     ws_take<double>(P, "nuts_edge", 6 * (size_t)P->n_par);
     ws_take<double>(P, "nuts_vel", 2 * (size_t)P->n_par);
-    ws_take<double>(P, "nuts_scal", 4);
+    ws_take<double>(P, "nuts_dev", (sizeof(NutsDev) + sizeof(double) - 1) / sizeof(double));
     (void)n_cols;
 }
 
@@ -2302,109 +2302,80 @@ namespace {
 // A point of a NUTS trajectory: theta, whitened momentum, d chi2 / d theta (device vectors).
 struct NPoint { double *t, *r, *g; };
 
+static NutsCopy copies(std::initializer_list<std::pair<double*, const double*>> l) {
+    NutsCopy c{};
+    for (const auto& e : l) {
+        c.dst[c.n] = e.first;
+        c.src[c.n] = e.second;
+        ++c.n;
+    }
+    return c;
+}
+static NutsCopy copy3(const NPoint& d, const NPoint& s) { return copies({{d.t, s.t}, {d.r, s.r}, {d.g, s.g}}); }
+
+// The slice-sampling NUTS of one chain.  The tree of a doubling is walked on the host in a
+// fixed order (the recursion of Hoffman & Gelman: a subtree of depth j is its first half,
+// then, unless that stopped, its second half, a draw between their proposals and a U-turn
+// test of its ends); every step is a launch that acts only if the tree has not stopped
+// (NutsDev), so the host waits once per doubling.  Leaves after a stop still run the
+// gradient pass, on the last point computed, and change nothing.
 struct Nuts {
     apx_problem* P;
     const float *data, *weight;
     const double *F, *Ft;
     double step;
-    const double* u;          // this transition's uniforms (host)
-    int k;                    // next uniform
-    double log_slice, H0;
-    int steps, divergent;
-    double alpha;             // sum of min(1, exp(H0 - H)) over the leaves of the last doubling
-    int n_alpha;
+    const double* u;          // this transition's uniforms (device)
+    const double* uh;         // the same, host copy (the doubling directions)
     NPoint outer[APX_NUTS_MAX_DEPTH + 1], inner[APX_NUTS_MAX_DEPTH + 1];
     double* prop[APX_NUTS_MAX_DEPTH + 1];
-    double *vel_m, *vel_p, *scal, *chi2;
+    double *vel_m, *vel_p, *chi2;
+    NutsDev* dev;
+    NutsDev host;             // as read after the last doubling
     long long n;
 
-    double draw() { return u[k++]; }
-
-    apx_status copy(double* dst, const double* src) {
-        if (dst == src || n == 0) return APX_OK;
-        hipError_t e = hipMemcpyAsync(dst, src, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, P->ctx->stream);
-        return e == hipSuccess ? APX_OK : fail(P->ctx, APX_E_HIP, "NUTS copy");
-    }
-    apx_status copy(const NPoint& d, const NPoint& s) {
-        APXCHK(copy(d.t, s.t));
-        APXCHK(copy(d.r, s.r));
-        return copy(d.g, s.g);
-    }
-    apx_status read(double* host, int count) {
-        hipStream_t st = P->ctx->stream;
-        HIPCHK(hipMemcpyAsync(host, scal, count * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        return APX_OK;
-    }
-    // one leapfrog step of size v * step from src into dst; returns H at the new point
-    apx_status leap(const NPoint& dst, const NPoint& src, double v, double* H) {
+    // one leapfrog step of size v * step from src into outer[0]
+    apx_status leaf(const NPoint& src, double v) {
         const Plan& p = P->plan;
         hipStream_t st = P->ctx->stream;
-        APXCHK(copy(dst, src));
-        HIPCHK(launch_hmc_matvec(p, F, dst.g, dst.r, -0.25 * v * step, st));
-        HIPCHK(launch_hmc_matvec(p, Ft, dst.r, dst.t, v * step, st));
+        const NPoint& dst = outer[0];
+        const int* stop = &dev->stop;
+        HIPCHK(launch_nuts_copy(stop, 0, copy3(dst, src), n, st));
+        HIPCHK(launch_hmc_matvec(p, F, dst.g, dst.r, -0.25 * v * step, st, stop));
+        HIPCHK(launch_hmc_matvec(p, Ft, dst.r, dst.t, v * step, st, stop));
         APXCHK(grad_core(P, dst.t, data, weight, dst.g, chi2, 1));
-        HIPCHK(launch_hmc_matvec(p, F, dst.g, dst.r, -0.25 * v * step, st));
-        HIPCHK(launch_nuts_energy(p, chi2, dst.r, scal, st));
-        APXCHK(read(H, 1));
-        ++steps;
+        HIPCHK(launch_hmc_matvec(p, F, dst.g, dst.r, -0.25 * v * step, st, stop));
+        HIPCHK(launch_nuts_leaf(p, dev, chi2, dst.r, st));
         return APX_OK;
     }
-    // (tp - tm) . F rm >= 0 and (tp - tm) . F rp >= 0
-    apx_status no_uturn(const NPoint& m, const NPoint& pp, bool* ok) {
+    // U-turn test of the trajectory (m, pp) when *flag == want
+    apx_status uturn(const NPoint& m, const NPoint& pp, const int* flag, int want) {
         const Plan& p = P->plan;
         hipStream_t st = P->ctx->stream;
         HIPCHK(launch_fill(vel_m, n, 0.0, st));
         HIPCHK(launch_fill(vel_p, n, 0.0, st));
         HIPCHK(launch_hmc_matvec(p, Ft, m.r, vel_m, 1.0, st));
         HIPCHK(launch_hmc_matvec(p, Ft, pp.r, vel_p, 1.0, st));
-        HIPCHK(launch_nuts_uturn(p, m.t, pp.t, vel_m, vel_p, scal, st));
-        double d[2];
-        APXCHK(read(d, 2));
-        *ok = d[0] >= 0.0 && d[1] >= 0.0;
+        HIPCHK(launch_nuts_uturn(p, m.t, pp.t, vel_m, vel_p, dev, flag, want, st));
         return APX_OK;
     }
-    // Subtree of 2^j steps in direction v from src: its outer end, inner end and proposal
-    // (refs into level buffers), its count of slice points and its continue flag.
-    apx_status build(const NPoint& src, double v, int j, NPoint* o, NPoint* in, double** pr, int* nn, int* ss) {
-        if (j == 0) {
-            double H;
-            APXCHK(leap(outer[0], src, v, &H));
-            alpha += std::isfinite(H) ? std::min(1.0, std::exp(H0 - H)) : 0.0;
-            ++n_alpha;
-            *nn = log_slice <= -H ? 1 : 0;
-            *ss = log_slice < -H + APX_NUTS_DELTA_MAX ? 1 : 0;
-            if (!*ss) divergent = 1;
-            *o = outer[0];
-            *in = outer[0];
-            *pr = outer[0].t;
-            return APX_OK;
-        }
-        NPoint o1, i1;
-        double* p1;
-        int n1, s1;
-        APXCHK(build(src, v, j - 1, &o1, &i1, &p1, &n1, &s1));
-        APXCHK(copy(inner[j], i1));
-        APXCHK(copy(outer[j], o1));
-        APXCHK(copy(prop[j], p1));
-        if (s1) {
-            NPoint o2, i2;
-            double* p2;
-            int n2, s2;
-            APXCHK(build(outer[j], v, j - 1, &o2, &i2, &p2, &n2, &s2));
-            if (draw() * (n1 + n2) < n2) APXCHK(copy(prop[j], p2));
-            APXCHK(copy(outer[j], o2));
-            bool ok;
-            APXCHK(v < 0 ? no_uturn(outer[j], inner[j], &ok) : no_uturn(inner[j], outer[j], &ok));
-            s1 = s2 && ok ? 1 : 0;
-            n1 += n2;
-        }
-        *o = outer[j];
-        *in = inner[j];
-        *pr = prop[j];
-        *nn = n1;
-        *ss = s1;
-        return APX_OK;
+    // ends and proposal of the subtree of depth j (outer[0] for a leaf)
+    NPoint outer_of(int j) const { return outer[j]; }
+    NPoint inner_of(int j) const { return j == 0 ? outer[0] : inner[j]; }
+    double* prop_of(int j) const { return j == 0 ? outer[0].t : prop[j]; }
+
+    // Subtree of 2^j steps in direction v from src, entered when *entry != 0.
+    apx_status build(const NPoint& src, double v, int j, const int* entry) {
+        if (j == 0) return leaf(src, v);
+        hipStream_t st = P->ctx->stream;
+        APXCHK(build(src, v, j - 1, entry));
+        const NPoint i1 = inner_of(j - 1), o1 = outer_of(j - 1);
+        const NutsCopy keep = copies({{inner[j].t, i1.t}, {inner[j].r, i1.r}, {inner[j].g, i1.g},
+                                      {outer[j].t, o1.t}, {outer[j].r, o1.r}, {outer[j].g, o1.g},
+                                      {prop[j], prop_of(j - 1)}});
+        HIPCHK(launch_nuts_level(dev, j, entry, keep, n, st));
+        APXCHK(build(outer[j], v, j - 1, &dev->gate[j]));
+        HIPCHK(launch_nuts_merge(dev, j, u, copies({{prop[j], prop_of(j - 1)}}), copy3(outer[j], outer_of(j - 1)), n, st));
+        return v < 0 ? uturn(outer[j], inner[j], &dev->gate[j], 1) : uturn(inner[j], outer[j], &dev->gate[j], 1);
     }
 };
 
@@ -2436,7 +2407,7 @@ static apx_status nuts_setup(apx_problem* P, Nuts& N, const float* data, const f
     ep = NPoint{ed + 3 * n, ed + 4 * n, ed + 5 * n};
     N.vel_m = wsp<double>(P, "nuts_vel");
     N.vel_p = N.vel_m + n;
-    N.scal = wsp<double>(P, "nuts_scal");
+    N.dev = (NutsDev*)wsp<double>(P, "nuts_dev");
     N.chi2 = wsp<double>(P, "hmc_c1");
     HIPCHK(launch_hmc_transpose(p, F, p.M, st));
     HIPCHK(launch_clear_trial_flags(p, st));
@@ -2444,49 +2415,45 @@ static apx_status nuts_setup(apx_problem* P, Nuts& N, const float* data, const f
 }
 
 // One transition from theta (updated in place to the new sample) with momentum z and the
-// host uniforms u; first: the start's domain violations raise the sticky flag.
-// st = (depth, leapfrog steps, slice points, divergent, alpha, n_alpha).
+// uniforms u (device) / uh (host copy); first: the start's domain violations raise the
+// sticky flag.  st = (depth, leapfrog steps, slice points, divergent, alpha, n_alpha).
 static apx_status nuts_transition(Nuts& N, const NPoint& em, const NPoint& ep, double* theta, const double* z,
-                                  const double* u, int max_depth, bool first, double st[6]) {
+                                  const double* u, const double* uh, int max_depth, bool first, double st[6]) {
     apx_problem* P = N.P;
     const Plan& p = P->plan;
+    hipStream_t s = P->ctx->stream;
+    const long long n = N.n;
     N.u = u;
-    N.k = 0;
-    N.steps = 0;
-    N.divergent = 0;
-    N.alpha = 0.0;
-    N.n_alpha = 0;
-    APXCHK(N.copy(em.t, theta));
-    APXCHK(N.copy(em.r, z));
+    N.uh = uh;
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(em.t, theta, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(em.r, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
     APXCHK(grad_core(P, em.t, N.data, N.weight, em.g, N.chi2, first ? 0 : 1));
-    HIPCHK(launch_nuts_energy(p, N.chi2, em.r, N.scal, P->ctx->stream));
-    APXCHK(N.read(&N.H0, 1));
-    APXCHK(N.copy(ep, em));
-    N.log_slice = std::log(N.draw()) - N.H0;
-    long long cnt = 1;
-    int s = 1, depth = 0;
-    while (s && depth < max_depth) {
-        const double v = N.draw() < 0.5 ? -1.0 : 1.0;
-        N.alpha = 0.0;
-        N.n_alpha = 0;
-        NPoint o, in;
-        double* pr;
-        int n1, s1;
-        APXCHK(N.build(v < 0 ? em : ep, v, depth, &o, &in, &pr, &n1, &s1));
-        APXCHK(N.copy(v < 0 ? em : ep, o));
-        if (s1 && N.draw() * (double)cnt < (double)n1) APXCHK(N.copy(theta, pr));
-        cnt += n1;
-        bool ok = false;
-        if (s1) APXCHK(N.no_uturn(em, ep, &ok));
-        s = s1 && ok ? 1 : 0;
+    HIPCHK(launch_nuts_start(p, N.dev, N.chi2, em.r, u, s));
+    HIPCHK(launch_nuts_copy(nullptr, 0, copy3(ep, em), n, s));
+    int k = 1, depth = 0;
+    bool go = true;
+    while (go && depth < max_depth) {
+        const double v = uh[k] < 0.5 ? -1.0 : 1.0;
+        HIPCHK(launch_nuts_doubling(N.dev, s));
+        const NPoint& edge = v < 0 ? em : ep;
+        APXCHK(N.build(edge, v, depth, &N.dev->one));
+        HIPCHK(launch_nuts_top(N.dev, depth, u, copy3(edge, N.outer_of(depth)),
+                               copies({{theta, N.prop_of(depth)}}), n, s));
+        APXCHK(N.uturn(em, ep, &N.dev->stop, 0));
+        HIPCHK(hipMemcpyAsync(&N.host, N.dev, sizeof(NutsDev), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        go = N.host.stop == 0;
+        k = N.host.k;
         ++depth;
     }
     st[0] = depth;
-    st[1] = N.steps;
-    st[2] = (double)cnt;
-    st[3] = N.divergent;
-    st[4] = N.alpha;
-    st[5] = N.n_alpha;
+    st[1] = N.host.steps;
+    st[2] = (double)N.host.cnt;
+    st[3] = N.host.divergent;
+    st[4] = N.host.alpha;
+    st[5] = N.host.n_alpha;
     return APX_OK;
 }
 
@@ -2527,8 +2494,9 @@ apx_status apx_nuts_run(apx_problem* P, const float* data, const float* weight, 
     std::vector<double> sh((size_t)n_samples * 4);
     for (long long i = 0; i < n_samples; ++i) {
         double t6[6];
-        APXCHK(nuts_transition(N, em, ep, theta, z + i * n, uh.data() + i * nd, max_depth, i == 0, t6));
-        APXCHK(N.copy(samples + i * n, theta));
+        APXCHK(nuts_transition(N, em, ep, theta, z + i * n, u + i * nd, uh.data() + i * nd, max_depth, i == 0, t6));
+        if (n > 0)
+            HIPCHK(hipMemcpyAsync(samples + i * n, theta, n * sizeof(double), hipMemcpyDeviceToDevice, st));
         for (int q = 0; q < 4; ++q) sh[i * 4 + q] = t6[q];
     }
     HIPCHK(hipMemcpyAsync(stats, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, st));
@@ -2556,7 +2524,7 @@ apx_status apx_nuts_warmup(apx_problem* P, const float* data, const float* weigh
     double hbar = 0.0, log_bar = 0.0;
     for (long long i = 0; i < n_warmup; ++i) {
         double t6[6];
-        APXCHK(nuts_transition(N, em, ep, theta, z + i * n, uh.data() + i * nd, max_depth, i == 0, t6));
+        APXCHK(nuts_transition(N, em, ep, theta, z + i * n, u + i * nd, uh.data() + i * nd, max_depth, i == 0, t6));
         const double a = t6[5] > 0 ? t6[4] / t6[5] : 0.0;
         const double m = (double)(i + 1);
         hbar = (1.0 - 1.0 / (m + APX_NUTS_DA_T0)) * hbar + (target_accept - a) / (m + APX_NUTS_DA_T0);

@@ -428,16 +428,62 @@ struct HmcIO {
     double* stats;            // [n_samples * n_sub * 3]: accepted, H0, H1
 };
 hipError_t launch_hmc_transpose(const Plan& p, const double* F, double* Ft, hipStream_t st);
-// out[j] += coef * (M_s^T v_s)[j - p0_s] for every theta index j of sub-problem s
+// out[j] += coef * (M_s^T v_s)[j - p0_s] for every theta index j of sub-problem s; nothing
+// when skip is given and *skip != 0
 hipError_t launch_hmc_matvec(const Plan& p, const double* M, const double* v, double* out, double coef,
-                             hipStream_t st);
+                             hipStream_t st, const int* skip = nullptr);
 hipError_t launch_hmc_begin(const Plan& p, const HmcIO& h, long long i, hipStream_t st);
 hipError_t launch_hmc_accept(const Plan& p, const HmcIO& h, long long i, hipStream_t st);
 hipError_t launch_clear_trial_flags(const Plan& p, hipStream_t st);
-// NUTS: out[0] = joint energy (+inf if a point left the domain; clears the flags)
-hipError_t launch_nuts_energy(const Plan& p, const double* chi2, const double* r, double* out, hipStream_t st);
-// NUTS: out[0..1] = (tp - tm) . vm, (tp - tm) . vp
+
+// NUTS tree state of one transition on the device.  The host issues the launches of a whole
+// doubling (every leaf, subtree merge and U-turn test of a tree of that depth) without
+// waiting; the kernels act only where the tree in progress has not stopped, and the host
+// reads this struct once per doubling to decide whether to double again.
+struct NutsDev {
+    double log_slice;                       // log u0 - H0
+    double H0;                              // energy at the start of the transition
+    double alpha;                           // sum of min(1, exp(H0 - H)) over the doubling's leaves
+    long long cnt;                          // points in the slice, whole trajectory
+    long long c[APX_NUTS_MAX_DEPTH + 1];    // points in the slice of the subtree in progress, by level
+    int gate[APX_NUTS_MAX_DEPTH + 1];       // level j: its second half was built
+    int stop;                               // the doubling in progress stopped (divergence or U-turn)
+    int one;                                // 1: the entry flag of a doubling's tree
+    int take;                               // the last merge took its second half's proposal
+    int accept;                             // the last doubling's proposal became the sample
+    int k;                                  // next uniform of the transition
+    int steps, divergent, n_alpha;
+};
+// Up to 7 device vectors of n_par doubles copied dst[i] <- src[i] under one condition.
+struct NutsCopy {
+    double* dst[7];
+    const double* src[7];
+    int n;
+};
+// H0 and the slice from the start point (chi2 [n_sub], momenta r), k = 1, counters cleared
+hipError_t launch_nuts_start(const Plan& p, NutsDev* d, const double* chi2, const double* r, const double* u,
+                             hipStream_t st);
+// a doubling begins: its direction draw is consumed, stop and the acceptance statistic cleared
+hipError_t launch_nuts_doubling(NutsDev* d, hipStream_t st);
+// the copies when *flag == want
+hipError_t launch_nuts_copy(const int* flag, int want, const NutsCopy& c, long long n, hipStream_t st);
+// a leaf's energy (clears the domain flags) and, unless stopped, its slice count and tests
+hipError_t launch_nuts_leaf(const Plan& p, NutsDev* d, const double* chi2, const double* r, hipStream_t st);
+// level j after its first half: when *entry, copies (inner, outer, proposal) and c[j] = c[j-1];
+// gate[j] = !stop
+hipError_t launch_nuts_level(NutsDev* d, int j, const int* entry, const NutsCopy& c, long long n, hipStream_t st);
+// level j after its second half, when gate[j]: draw, proposal (copies `prop` when taken),
+// c[j] += c[j-1], outer end (copies `outer`)
+hipError_t launch_nuts_merge(NutsDev* d, int j, const double* u, const NutsCopy& prop, const NutsCopy& outer,
+                             long long n, hipStream_t st);
+// end of a doubling of depth `depth`: the trajectory's end (copies `edge`), and unless
+// stopped the draw that may make the doubling's proposal the sample (copies `sample`);
+// cnt += c[depth]
+hipError_t launch_nuts_top(NutsDev* d, int depth, const double* u, const NutsCopy& edge, const NutsCopy& sample,
+                           long long n, hipStream_t st);
+// U-turn test of ends (tm, rm), (tp, rp) with velocities vm = F rm, vp = F rp: when
+// *flag == want and (tp - tm) . vm < 0 or (tp - tm) . vp < 0, stop
 hipError_t launch_nuts_uturn(const Plan& p, const double* tm, const double* tp, const double* vm,
-                             const double* vp, double* out, hipStream_t st);
+                             const double* vp, NutsDev* d, const int* flag, int want, hipStream_t st);
 
 }  // namespace apx

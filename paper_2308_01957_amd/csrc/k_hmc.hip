@@ -6,7 +6,8 @@
 // The gradient passes are the library's adjoint; these kernels are the small per-sub-problem
 // vector steps around them.  Each sub-problem is its own chain with its own Metropolis test.
 // The No-U-Turn sampler (the variant the paper's example runs) reuses the kick and drift;
-// its tree logic runs on the host between the energy and U-turn reductions below.
+// its tree state lives on the device (NutsDev): the host launches every step of a doubling
+// and the kernels below take the tree's decisions, so a doubling needs one host read.
 // All sums run in a fixed order (bitwise reproducible).
 #include "apx_internal.h"
 
@@ -26,9 +27,9 @@ __global__ void k_hmc_transpose(Plan p, const double* __restrict__ F, double* __
 // One thread per theta index j of a sub-problem (local index i): out[j] += coef * sum_k M[k][i] v[k].
 // With M = F this is F^T v (the kick), with M = F^T it is F v (the drift).
 __global__ void k_hmc_matvec(Plan p, const double* __restrict__ M, const double* __restrict__ v,
-                             double* __restrict__ out, double coef) {
+                             double* __restrict__ out, double coef, const int* skip) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= p.n_par) return;
+    if (j >= p.n_par || (skip && *skip)) return;
     const int s = p.par_sub[j];
     if (s < 0) return;
     const DSub sb = p.subs[s];
@@ -102,9 +103,9 @@ hipError_t launch_hmc_transpose(const Plan& p, const double* F, double* Ft, hipS
 }
 
 hipError_t launch_hmc_matvec(const Plan& p, const double* M, const double* v, double* out, double coef,
-                             hipStream_t st) {
+                             hipStream_t st, const int* skip) {
     if (p.n_par == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hmc_matvec, dim3((p.n_par + 255) / 256), dim3(256), 0, st, p, M, v, out, coef);
+    hipLaunchKernelGGL(k_hmc_matvec, dim3((p.n_par + 255) / 256), dim3(256), 0, st, p, M, v, out, coef, skip);
     return hipGetLastError();
 }
 
@@ -119,10 +120,10 @@ hipError_t launch_hmc_accept(const Plan& p, const HmcIO& h, long long i, hipStre
 }
 
 // NUTS energy of the joint chain: H = sum_s chi2_s / 2 + |r|^2 / 2 over the entries of
-// every sub-problem, +inf when any sub-problem's point left the domain (whose flags it
-// then clears).  One workgroup, fixed-order sums; the result goes to out[0].
-__global__ __launch_bounds__(256) void k_nuts_energy(Plan p, const double* __restrict__ chi2,
-                                                     const double* __restrict__ r, double* out) {
+// every sub-problem, +inf when any sub-problem's point left the domain (whose flags it then
+// clears).  Called by all 256 threads of one workgroup; fixed-order sums; the result is
+// valid in thread 0.
+__device__ double nuts_energy(const Plan& p, const double* __restrict__ chi2, const double* __restrict__ r) {
     __shared__ double red[4];
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0;
@@ -135,28 +136,130 @@ __global__ __launch_bounds__(256) void k_nuts_energy(Plan p, const double* __res
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
     __syncthreads();
+    double h = 0.0;
     if (threadIdx.x == 0) {
         double c = 0.0;
         for (int s = 0; s < p.n_sub; ++s) c += chi2[s];
-        const double h = 0.5 * c + 0.5 * (((red[0] + red[1]) + red[2]) + red[3]);
-        out[0] = bad || !isfinite(h) ? __builtin_inf() : h;
+        h = 0.5 * c + 0.5 * (((red[0] + red[1]) + red[2]) + red[3]);
+        if (bad || !isfinite(h)) h = __builtin_inf();
     }
     __syncthreads();
     for (int s = (int)threadIdx.x; s < p.n_sub; s += 256) p.lmf[s].trial_bad = 0;
+    return h;
 }
 
-// U-turn products of a trajectory with ends (tm, rm) and (tp, rp): out[0] = (tp - tm) . vm,
-// out[1] = (tp - tm) . vp, with the velocities vm = F rm, vp = F rp given.
+__global__ __launch_bounds__(256) void k_nuts_start(Plan p, NutsDev* d, const double* __restrict__ chi2,
+                                                    const double* __restrict__ r, const double* __restrict__ u) {
+    const double h = nuts_energy(p, chi2, r);
+    if (threadIdx.x == 0) {
+        d->H0 = h;
+        d->log_slice = log(u[0]) - h;
+        d->k = 1;
+        d->cnt = 1;
+        d->steps = 0;
+        d->divergent = 0;
+        d->alpha = 0.0;
+        d->n_alpha = 0;
+        d->stop = 0;
+        d->one = 1;
+        d->take = 0;
+        d->accept = 0;
+    }
+}
+
+__global__ void k_nuts_doubling(NutsDev* d) {
+    if (threadIdx.x == 0) {
+        d->k += 1;                          // the direction (the host read it from the same slot)
+        d->stop = 0;
+        d->alpha = 0.0;
+        d->n_alpha = 0;
+    }
+}
+
+__device__ __forceinline__ void nuts_copy_all(const NutsCopy& c, long long n) {
+    for (int v = 0; v < c.n; ++v)
+        for (long long e = threadIdx.x; e < n; e += blockDim.x) c.dst[v][e] = c.src[v][e];
+}
+
+__global__ __launch_bounds__(256) void k_nuts_copy(const int* flag, int want, NutsCopy c, long long n) {
+    if (flag && *flag != want) return;
+    nuts_copy_all(c, n);
+}
+
+// A leaf: point in the slice when log_slice <= -H; the doubling stops (divergent) when
+// log_slice >= -H + APX_NUTS_DELTA_MAX.
+__global__ __launch_bounds__(256) void k_nuts_leaf(Plan p, NutsDev* d, const double* __restrict__ chi2,
+                                                   const double* __restrict__ r) {
+    const double h = nuts_energy(p, chi2, r);
+    if (threadIdx.x == 0 && !d->stop) {
+        d->alpha += isfinite(h) ? fmin(1.0, exp(d->H0 - h)) : 0.0;
+        d->n_alpha += 1;
+        d->c[0] = d->log_slice <= -h ? 1 : 0;
+        if (!(d->log_slice < -h + APX_NUTS_DELTA_MAX)) {
+            d->divergent = 1;
+            d->stop = 1;
+        }
+        d->steps += 1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_nuts_level(NutsDev* d, int j, const int* entry, NutsCopy c, long long n) {
+    const bool in = *entry != 0;
+    if (threadIdx.x == 0) {
+        if (in) d->c[j] = d->c[j - 1];
+        d->gate[j] = d->stop ? 0 : 1;
+    }
+    if (in) nuts_copy_all(c, n);
+}
+
+__global__ __launch_bounds__(256) void k_nuts_merge(NutsDev* d, int j, const double* __restrict__ u, NutsCopy prop,
+                                                    NutsCopy outer, long long n) {
+    __shared__ int g, t;
+    if (threadIdx.x == 0) {
+        g = d->gate[j];
+        t = 0;
+        if (g) {
+            const long long n1 = d->c[j], n2 = d->c[j - 1];
+            t = u[d->k] * (double)(n1 + n2) < (double)n2 ? 1 : 0;
+            d->k += 1;
+            d->c[j] = n1 + n2;
+        }
+        d->take = t;
+    }
+    __syncthreads();
+    if (t) nuts_copy_all(prop, n);
+    if (g) nuts_copy_all(outer, n);
+}
+
+__global__ __launch_bounds__(256) void k_nuts_top(NutsDev* d, int depth, const double* __restrict__ u, NutsCopy edge,
+                                                  NutsCopy sample, long long n) {
+    __shared__ int acc;
+    nuts_copy_all(edge, n);
+    if (threadIdx.x == 0) {
+        acc = 0;
+        if (!d->stop) {
+            acc = u[d->k] * (double)d->cnt < (double)d->c[depth] ? 1 : 0;
+            d->k += 1;
+        }
+        d->cnt += d->c[depth];
+        d->accept = acc;
+    }
+    __syncthreads();
+    if (acc) nuts_copy_all(sample, n);
+}
+
 __global__ __launch_bounds__(256) void k_nuts_uturn(Plan p, const double* __restrict__ tm,
                                                     const double* __restrict__ tp, const double* __restrict__ vm,
-                                                    const double* __restrict__ vp, double* out) {
+                                                    const double* __restrict__ vp, NutsDev* d, const int* flag,
+                                                    int want) {
     __shared__ double red[4][2];
+    if (*flag != want) return;                // uniform across the workgroup
     double a = 0.0, b = 0.0;
     for (int j = (int)threadIdx.x; j < p.n_par; j += 256) {
         if (p.par_sub[j] < 0) continue;
-        const double d = tp[j] - tm[j];
-        a = fma(d, vm[j], a);
-        b = fma(d, vp[j], b);
+        const double dd = tp[j] - tm[j];
+        a = fma(dd, vm[j], a);
+        b = fma(dd, vp[j], b);
     }
     for (int o = 32; o > 0; o >>= 1) {
         a += __shfl_xor(a, o, 64);
@@ -167,8 +270,11 @@ __global__ __launch_bounds__(256) void k_nuts_uturn(Plan p, const double* __rest
         red[threadIdx.x >> 6][1] = b;
     }
     __syncthreads();
-    if (threadIdx.x < 2) out[threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
-                                           red[3][threadIdx.x];
+    if (threadIdx.x == 0) {
+        const double ua = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+        const double ub = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+        if (!(ua >= 0.0 && ub >= 0.0)) d->stop = 1;
+    }
 }
 
 __global__ void k_clear_trial_flags(Plan p) {
@@ -180,14 +286,47 @@ hipError_t launch_clear_trial_flags(const Plan& p, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_nuts_energy(const Plan& p, const double* chi2, const double* r, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_nuts_energy, dim3(1), dim3(256), 0, st, p, chi2, r, out);
+hipError_t launch_nuts_start(const Plan& p, NutsDev* d, const double* chi2, const double* r, const double* u,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_nuts_start, dim3(1), dim3(256), 0, st, p, d, chi2, r, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_doubling(NutsDev* d, hipStream_t st) {
+    hipLaunchKernelGGL(k_nuts_doubling, dim3(1), dim3(64), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_copy(const int* flag, int want, const NutsCopy& c, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_nuts_copy, dim3(1), dim3(256), 0, st, flag, want, c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_leaf(const Plan& p, NutsDev* d, const double* chi2, const double* r, hipStream_t st) {
+    hipLaunchKernelGGL(k_nuts_leaf, dim3(1), dim3(256), 0, st, p, d, chi2, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_level(NutsDev* d, int j, const int* entry, const NutsCopy& c, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_nuts_level, dim3(1), dim3(256), 0, st, d, j, entry, c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_merge(NutsDev* d, int j, const double* u, const NutsCopy& prop, const NutsCopy& outer,
+                             long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_nuts_merge, dim3(1), dim3(256), 0, st, d, j, u, prop, outer, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_top(NutsDev* d, int depth, const double* u, const NutsCopy& edge, const NutsCopy& sample,
+                           long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_nuts_top, dim3(1), dim3(256), 0, st, d, depth, u, edge, sample, n);
     return hipGetLastError();
 }
 
 hipError_t launch_nuts_uturn(const Plan& p, const double* tm, const double* tp, const double* vm,
-                             const double* vp, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_nuts_uturn, dim3(1), dim3(256), 0, st, p, tm, tp, vm, vp, out);
+                             const double* vp, NutsDev* d, const int* flag, int want, hipStream_t st) {
+    hipLaunchKernelGGL(k_nuts_uturn, dim3(1), dim3(256), 0, st, p, tm, tp, vm, vp, d, flag, want);
     return hipGetLastError();
 }
 
