@@ -7,13 +7,18 @@
 // staged in LDS and contracted with v_mfma_f64_16x16x4_f64; every tile of every
 // K-slice is written to its own slot and summed later in a fixed order, so the result
 // does not depend on scheduling.
+#include <type_traits>
+
 #include "apx_internal.h"
 
 namespace apx {
 
 typedef double apx_d4 __attribute__((ext_vector_type(4)));
 
-// TM = 64: 4 waves as 2 x 2 blocks of 32 x 32 (2 x 2 MFMA tiles each).
+// TM = 64: the tile's 16 x 16 blocks that hold needed entries (a block is skipped when its
+// rows or its columns lie past the group's last column, or, on a diagonal tile of a group
+// with itself, when it lies wholly below the diagonal) are dealt to the 4 waves in turn,
+// at most 4 blocks (MFMA accumulators) each.
 // TM = 16: 4 waves share one 16 x 16 tile and split each LDS stage along K.
 // Stages of KC = PAIR_KC pixels (one row segment of the box intersection) are software
 // pipelined two deep: the global loads of stages s+1 and s+2 are in flight while the
@@ -26,7 +31,7 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
                                               const apx_lm_state* lm) {
     constexpr int KC = PAIR_KC;
     constexpr int PER = TM * KC / 256;              // elements of A (and of B) per thread
-    constexpr int NB = TM >= 64 ? TM / 32 : 1;
+    constexpr int NB = TM >= 64 ? 2 : 1;            // accumulators: NB x NB per wave
     __shared__ double As[TM][KC + 1];
     __shared__ double Bs[TM][KC + 1];
     const PairItem it = items[xcd_item((int)blockIdx.x, (int)gridDim.x)];
@@ -43,7 +48,25 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     const float* __restrict__ Jh = p.J + Hh.j_off;
     const int a0 = it.ta * TM, b0 = it.tb * TM;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int wr = TM >= 64 ? (wv >> 1) : 0, wc = TM >= 64 ? (wv & 1) : 0;
+    // TM = 64: this wave's blocks s < nbk, row block (blk >> 4 s) & 3, column block
+    // (blk >> (4 s + 2)) & 3
+    int blk = 0, nbk = 0;
+    if constexpr (TM >= 64) {
+        const int rows = G.ncols - a0, cols = Hh.ncols - b0;
+        const bool diag = pr.g == pr.h && it.ta == it.tb;
+        int k = 0;
+        for (int m = 0; m < 4; ++m)
+            for (int n = 0; n < 4; ++n) {
+                if (16 * m >= rows || 16 * n >= cols || (diag && m > n)) continue;
+                if ((k & 3) == wv) {
+                    blk |= (m | (n << 2)) << (4 * nbk);
+                    ++nbk;
+                }
+                ++k;
+            }
+    }
+    auto bm = [&](int q) { return (blk >> (4 * q)) & 3; };
+    auto bn = [&](int q) { return (blk >> (4 * q + 2)) & 3; };
     apx_d4 acc[NB][NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a)
@@ -97,18 +120,35 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     };
     auto compute = [&]() {
         if constexpr (TM >= 64) {
+            // one branch per stage on the wave's block count; inside, the LDS reads of a
+            // K step are all issued before its MFMAs
+            // a wave with fewer than 4 blocks spreads each over 4 / NS accumulators (K steps
+            // dealt in turn), so it still has 4 independent MFMA chains
+            auto run = [&](auto ns) {
+                constexpr int NS = decltype(ns)::value;
+                constexpr int R = NS == 1 ? 4 : NS == 2 ? 2 : 1;
 #pragma unroll
-            for (int kk = 0; kk < KC; kk += 4) {
-                double av[NB], bv[NB];
+                for (int kk = 0; kk < KC; kk += 4) {
+                    const int rr = (kk / 4) % R;
+                    double av[NS], bv[NS];
 #pragma unroll
-                for (int m = 0; m < NB; ++m) av[m] = As[wr * (TM / 2) + m * 16 + (lane & 15)][kk + (lane >> 4)];
+                    for (int q = 0; q < NS; ++q) {
+                        av[q] = As[bm(q) * 16 + (lane & 15)][kk + (lane >> 4)];
+                        bv[q] = Bs[bn(q) * 16 + (lane & 15)][kk + (lane >> 4)];
+                    }
 #pragma unroll
-                for (int n = 0; n < NB; ++n) bv[n] = Bs[wc * (TM / 2) + n * 16 + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-                for (int m = 0; m < NB; ++m)
-#pragma unroll
-                    for (int n = 0; n < NB; ++n)
-                        acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
+                    for (int q = 0; q < NS; ++q) {
+                        const int c = q * R + rr;
+                        acc[c >> 1][c & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc[c >> 1][c & 1], 0, 0, 0);
+                    }
+                }
+            };
+            switch (nbk) {
+                case 4: run(std::integral_constant<int, 4>{}); break;
+                case 3: run(std::integral_constant<int, 3>{}); break;
+                case 2: run(std::integral_constant<int, 2>{}); break;
+                case 1: run(std::integral_constant<int, 1>{}); break;
+                default: break;
             }
         } else {
 #pragma unroll
@@ -138,17 +178,31 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
 
     double* out = p.pair_part + it.out_off;
     if constexpr (TM >= 64) {
+        // blocks no wave holds are left unwritten: the assembly reads none of their entries.
+        // A block's R accumulators are added in order.
+        auto emit = [&](auto ns) {
+            constexpr int NS = decltype(ns)::value;
+            constexpr int R = NS == 1 ? 4 : NS == 2 ? 2 : 1;
 #pragma unroll
-        for (int m = 0; m < NB; ++m)
-#pragma unroll
-            for (int n = 0; n < NB; ++n)
+            for (int q = 0; q < NS; ++q)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
+                    double sum = acc[(q * R) >> 1][(q * R) & 1][v];
+#pragma unroll
+                    for (int r = 1; r < R; ++r) sum += acc[(q * R + r) >> 1][(q * R + r) & 1][v];
                     // v_mfma_f64_16x16x4: D[i][j] sits in lane j + 16 (i % 4), register i / 4
-                    const int i = wr * (TM / 2) + m * 16 + (lane >> 4) + 4 * v;
-                    const int j = wc * (TM / 2) + n * 16 + (lane & 15);
-                    out[i * TM + j] = acc[m][n][v];
+                    const int i = bm(q) * 16 + (lane >> 4) + 4 * v;
+                    const int j = bn(q) * 16 + (lane & 15);
+                    out[i * TM + j] = sum;
                 }
+        };
+        switch (nbk) {
+            case 4: emit(std::integral_constant<int, 4>{}); break;
+            case 3: emit(std::integral_constant<int, 3>{}); break;
+            case 2: emit(std::integral_constant<int, 2>{}); break;
+            case 1: emit(std::integral_constant<int, 1>{}); break;
+            default: break;
+        }
     } else {
         // reduce the four K-slices in a fixed order
         __shared__ double red[4][256];
