@@ -148,11 +148,15 @@ def cpu_baseline_cutouts(spec, data, weight, synth, stride=16, n_iter=2):
     }
 
 
+CONV_MODES = {"direct": 0, "fft": 1, "auto": 3}
+
+
 def _conv(args, spec):
-    """The workload spec with the convolution mode asked for on the command line."""
-    if args.conv == "fft":
+    """The workload spec with the convolution mode asked for on the command line (direct:
+    the spec's own)."""
+    if args.conv in ("fft", "auto"):
         spec = dict(spec)
-        spec["conv_mode"] = 1
+        spec["conv_mode"] = CONV_MODES[args.conv]
     return spec
 
 
@@ -299,13 +303,61 @@ def jac_entries_per_sub(spec, exclude_images=()):
     return ent, flop
 
 
+TILE_HW = [(32, 64), (16, 64), (32, 32), (16, 32)]   # the library's four direct tile shapes
+AUTO_FFT_PAIR_COST = 6.7e6                            # APX_AUTO_FFT_PAIR_COST
+
+
+def auto_fft_job(P, h, w, nch):
+    """The library's automatic-mode rule for one job of nch channels with an h x w output:
+    FFT tiles when ceil(nch blocks / 2) transform pairs cost less than the cheapest direct
+    tiling by the operation-count model."""
+    def tile_model(th, tw):
+        return th * tw * (P * P + 10.0) + 8.0 * (th + P - 1) * (tw + P - 1) + 3000.0
+    direct = min(-(-h // th) * -(-w // tw) * tile_model(th, tw) for th, tw in TILE_HW)
+    B = 129 - P
+    blocks = -(-h // B) * -(-w // B)
+    return ((nch * blocks + 1) // 2) * AUTO_FFT_PAIR_COST < direct * nch
+
+
+def auto_fft_groups(spec, rank_one, cost=True):
+    """Jacobian-column jobs that run on FFT tiles in automatic mode, as (image, box, columns):
+    the library's column groups (Sersic components of one image with the same box share one;
+    each point source has its own) on images with a fixed stamp of P >= 15 that is not rank
+    one (`rank_one`: the images the library found rank one), no sub-pixel grid, an output
+    box of at least 32 x 32, and FFT priced below direct (auto_fft_job).  cost=False: every
+    such job (the FFT mode's rule; pass no rank-one images there)."""
+    live = {int(m["image"]) for m in spec.get("psf_models", [])}
+    groups, order = {}, []
+    for i, c in enumerate(spec["comps"]):
+        n = sum(1 for q in c["par"] if q >= 0)
+        if n == 0 or c["box"][2] <= c["box"][0]:
+            continue
+        key = (c["image"], tuple(c["box"])) if int(c["type"]) == 0 else ("point", i)
+        if key not in groups:
+            groups[key] = [c["image"], c, 0]
+            order.append(key)
+        groups[key][2] += n
+    out = []
+    for key in order:
+        k, c, nch = groups[key]
+        im = spec["images"][k]
+        P = np.asarray(im["psf"]).shape[0]
+        if k in live or k in rank_one or int(im.get("up", 1)) != 1 or P < 15:
+            continue
+        y0, x0, y1, x1 = output_window(c, im)
+        h, w = y1 - y0, x1 - x0
+        if h >= 32 and w >= 32 and (not cost or auto_fft_job(P, h, w, nch)):
+            out.append((k, tuple(c["box"]), nch))
+    return out
+
+
 def rank_one_images(spec, conv_mode):
     """Images whose Jacobian columns the library convolves as two 1-D passes: the stamp is
     a_u b_v to FP32 rounding (the library's own test, repeated here: with the largest entry
     at (u0, v0), a_u = K[u, v0], b_v = K[u0, v] / K[u0, v0], every entry within 4e-7 of
-    itself plus 1e-9 of the largest), not live, not sub-pixel, in direct mode."""
+    itself plus 1e-9 of the largest), not live, not sub-pixel, in direct or automatic mode."""
     out = set()
-    if conv_mode != 0:
+    if conv_mode not in (0, 3):
         return out
     live = {int(m["image"]) for m in spec.get("psf_models", [])}
     for k, im in enumerate(spec["images"]):
@@ -340,36 +392,48 @@ def run_cutouts(args, torch, apx, synth):
     dd, ww = prob.pixels(data), prob.pixels(weight)
     ent, flop_sub = jac_entries_per_sub(spec)
     assert int(ent.sum()) == prob.n_jac, (ent.sum(), prob.n_jac)
-    # cutouts whose stamp is rank one take the two-pass Jacobian kernel: the 2-D class's
-    # algorithmic work counts only the others
-    sep_img = rank_one_images(spec, 1 if args.conv == "fft" else spec.get("conv_mode", 0))
+    # cutouts whose stamp is rank one take the two-pass Jacobian kernel, and in automatic
+    # (or FFT) mode some take FFT tiles: the 2-D class's algorithmic work counts only the
+    # others (the bench repeats the library's rules and checks it planned the same jobs)
+    mode = _conv(args, spec).get("conv_mode", 0)
+    sep_img = rank_one_images(spec, mode)
     assert prob.tile_shapes(1)[5] == len(sep_img), (prob.tile_shapes(1), len(sep_img))
+    fft_jobs = auto_fft_groups(spec, sep_img, cost=mode == 3) if mode in (1, 3) else []
+    assert prob.tile_shapes(1)[4] == len(fft_jobs), (prob.tile_shapes(1), len(fft_jobs))
     sep_sub = np.zeros(n_sub, bool)
     for k in sep_img:
         sep_sub[spec["images"][k]["sub"]] = True
-    flop_2d_sub = np.where(sep_sub, 0.0, flop_sub)
+    fft_flop_sub = np.zeros(n_sub)
+    for k, box, nch in fft_jobs:
+        im = spec["images"][k]
+        y0, x0, y1, x1 = output_window({"box": box}, im)
+        fft_flop_sub[im["sub"]] += nch * (y1 - y0) * (x1 - x0) * 2.0 * np.asarray(im["psf"]).shape[0] ** 2
+    flop_2d_sub = np.where(sep_sub, 0.0, flop_sub - fft_flop_sub)
     ent_sep_sub = np.where(sep_sub, ent, 0.0)
 
     # eager pass over the same iterations, one at a time: which cutouts form a Jacobian in
     # each iteration (need_jac), for the algorithmic FLOP count of the Jacobian phases
     th_e, st_e = prob.lm_init(spec["theta_init"], dd, ww)
-    flop_jac = ent_sep = 0.0
+    flop_jac = ent_sep = flop_fft = 0.0
     for _ in range(args.steps):
         need = prob.lm_state(st_e)["need_jac"] != 0
         flop_jac += float(flop_2d_sub[need].sum())
         ent_sep += float(ent_sep_sub[need].sum())
+        flop_fft += float(fft_flop_sub[need].sum())
         prob.lm_step(dd, ww, th_e, st_e)
     prob.check()
     torch.cuda.synchronize()
     print(f"[bench] eager pass done ({flop_jac / 1e12:.2f} TFLOP of 2-D Jacobian convolutions, "
-          f"{ent_sep / 1e9:.2f} G entries by two passes)", file=sys.stderr, flush=True)
+          f"{ent_sep / 1e9:.2f} G entries by two passes, {len(fft_jobs)} jobs on FFT tiles)",
+          file=sys.stderr, flush=True)
 
     # warm-up: captures the iteration graph with HIP events around the Jacobian convolutions
+    jclasses = ["conv_jcol", "conv_sep", "conv_fft"]
     th, st = prob.lm_init(spec["theta_init"], dd, ww)
-    prob.set_timing(True, classes=["conv_jcol", "conv_sep"])
+    prob.set_timing(True, classes=jclasses)
     prob.lm_run(max(1, args.warmup), dd, ww, th, st, use_graph=True)
     prob.timing()
-    prob.set_timing(True, classes=["conv_jcol", "conv_sep"])     # clears the records, keeps the graph
+    prob.set_timing(True, classes=jclasses)     # clears the records, keeps the graph
     prob.lm_init(spec["theta_init"], dd, ww, theta_out=th, state_out=st)
     torch.cuda.synchronize()
 
@@ -388,7 +452,11 @@ def run_cutouts(args, torch, apx, synth):
           file=sys.stderr, flush=True)
     jcol_ms, jcol_launches = kt["conv_jcol"]
     sep_ms, _ = kt["conv_sep"]
+    fft_ms, _ = kt["conv_fft"]
     achieved = flop_jac / (jcol_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
+    if mode == 1:            # FFT mode: the Jacobian runs on FFT tiles (direct-equivalent rate)
+        jcol_ms, flop_jac = fft_ms, flop_fft
+        achieved = flop_jac / (jcol_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
 
     # eager batched, the same iterations
     th2, st2 = prob.lm_init(spec["theta_init"], dd, ww)
@@ -398,21 +466,28 @@ def run_cutouts(args, torch, apx, synth):
     torch.cuda.synchronize()
     t_eager = time.perf_counter() - t0
 
-    # context: the same K iterations with every convolution 2-D (no two-pass Jacobians)
-    value_2d = None
+    # context: the same K iterations with every convolution direct (rank-one stamps by two
+    # passes, no FFT tiles), and with every convolution 2-D
+    context = {}
     if not args.no_2d_context:
-        spec2 = dict(spec, conv_mode=apx.CONV_DIRECT_2D)
-        q2 = apx.Problem(spec2)
-        t2, s2 = q2.lm_init(spec["theta_init"], dd, ww)
-        q2.lm_run(1, dd, ww, t2, s2, use_graph=True)
-        q2.lm_init(spec["theta_init"], dd, ww, theta_out=t2, state_out=s2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        q2.lm_run(args.steps, dd, ww, t2, s2, use_graph=True)
-        torch.cuda.synchronize()
-        value_2d = n_sub * args.steps / (time.perf_counter() - t0)
-        q2.check()
-        q2.close()
+        modes = [("all_2d_convolutions", apx.CONV_DIRECT_2D)]
+        if mode == apx.CONV_AUTO:
+            modes.insert(0, ("direct_mode", apx.CONV_DIRECT))
+        elif mode == apx.CONV_DIRECT:
+            modes.insert(0, ("auto_mode", apx.CONV_AUTO))
+        for name, m in modes:
+            q2 = apx.Problem(dict(spec, conv_mode=m))
+            t2, s2 = q2.lm_init(spec["theta_init"], dd, ww)
+            q2.lm_run(1, dd, ww, t2, s2, use_graph=True)
+            q2.lm_init(spec["theta_init"], dd, ww, theta_out=t2, state_out=s2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            q2.lm_run(args.steps, dd, ww, t2, s2, use_graph=True)
+            torch.cuda.synchronize()
+            context[name] = n_sub * args.steps / (time.perf_counter() - t0)
+            q2.check()
+            q2.close()
+            print(f"[bench] context {name}: {context[name]:.0f} cutout LM it/s", file=sys.stderr, flush=True)
 
     # plain path on a sample of cutouts: one problem per cutout, K eager iterations with
     # device-side control and one synchronisation at the end; also with a host read of the
@@ -464,6 +539,7 @@ def run_cutouts(args, torch, apx, synth):
         "data": "synthetic (seeded; noise-free model rendered by the library, Gaussian noise)",
         "config": {"workload": "4096 cutouts, side 32-256 px log-uniform, 1-5 Sersic + sky each, "
                                "Gaussian/Moffat PSF 15-31 px, 3x3 nodes, batched LM with graph replay",
+                   "conv": {0: "direct", 1: "fft", 2: "direct_2d", 3: "auto"}[mode],
                    "n_sub": n_sub, "n_par": spec["n_par"], "n_pix": prob.n_pix, "n_jac": prob.n_jac,
                    "plan_s": t_plan, "generate_s": t_gen},
         "batch_it_per_s": args.steps / t_graph,
@@ -476,12 +552,18 @@ def run_cutouts(args, torch, apx, synth):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
                      "kernel": "k_conv<P,JCOL> (2-D Jacobian-column convolutions: all PSF sizes and tile "
-                               "shapes of a phase, cutouts whose stamp is not rank one)",
+                               "shapes of a phase, cutouts whose stamp is not rank one and whose job stays "
+                               "on direct tiles)",
                      "ms_per_phase": jcol_ms / max(1, args.steps), "flop_per_phase": flop_jac / max(1, args.steps),
                      "launch_groups": jcol_launches},
         "two_pass_jacobian": {"kernel": "k_conv_sep<P> (rank-one stamps)", "ms_per_phase": sep_ms / max(1, args.steps),
                               "entries_per_phase": ent_sep / max(1, args.steps), "images": len(sep_img)},
-        "value_all_2d_convolutions": value_2d,
+        "fft_jacobian": {"kernel": "k_conv_fft<JCOL> (128x128 overlap-save tiles)", "jobs": len(fft_jobs),
+                         "ms_per_phase": fft_ms / max(1, args.steps),
+                         "direct_equivalent_tflops": flop_fft / (fft_ms * 1e-3) / 1e12 if fft_ms > 0 else None,
+                         "note": "2 P^2 per Jacobian entry of these jobs over their FFT time: the rate a direct "
+                                 "convolution would need to match them"},
+        "context_cutout_it_per_s": context,
         "covariance_ms": cov_ms,
         "accepted_mean": float(np.mean(stt["n_accept"])),
         "tile_shapes": tile_choice(prob),
@@ -786,8 +868,9 @@ def main():
     ap.add_argument("--tile-costs-in", metavar="JSON",
                     help="blend: take the tile costs from JSON instead of timing them (the same "
                          "tile shapes as the run that wrote it, e.g. under a counter profiler)")
-    ap.add_argument("--conv", default="direct", choices=["direct", "fft"],
-                    help="PSF convolution mode: direct (default) or FFT tiles for P >= 15")
+    ap.add_argument("--conv", default=None, choices=["direct", "fft", "auto"],
+                    help="PSF convolution mode: direct (default), FFT tiles for P >= 15, or auto (FFT tiles "
+                         "per job where the library's cost model prices them below direct)")
     ap.add_argument("--workload", default="cutouts",
                     choices=["cutouts", "blend", "field", "multiband", "single", "livepsf", "adaptive", "hmc",
                              "superres", "recentre"],
@@ -795,8 +878,11 @@ def main():
                          "their own line")
     ap.add_argument("--no-blend", action="store_true", help="cutouts: leave out the blend beside the headline")
     ap.add_argument("--no-2d-context", action="store_true",
-                    help="cutouts: leave out the same iterations with every convolution 2-D")
+                    help="cutouts: leave out the same iterations in the other convolution modes (automatic, "
+                         "every convolution 2-D)")
     args = ap.parse_args()
+    if args.conv is None:
+        args.conv = "direct"
     CONV_MODE[0] = args.conv
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -824,9 +910,12 @@ def main():
 
     rec, spec, data, weight = run_cutouts(args, torch, apx, synth)
     if not args.no_blend:
-        b, _, _, _ = run_blend(args, torch, apx, synth, with_fft=False)
+        # the blend beside the headline runs its direct convolutions (the counted kernel)
+        b, _, _, _ = run_blend(argparse.Namespace(**dict(vars(args), conv="direct")), torch, apx, synth,
+                               with_fft=False)
         rec["blend"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "mpix_per_s", "roofline", "graph_ms_per_step")}
         rec["blend"]["workload"] = b["config"]["workload"]
+        rec["blend"]["conv"] = "direct"
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a sample of cutouts (process pool)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline_cutouts(spec, data, weight, synth)

@@ -131,6 +131,17 @@ typedef int32_t apx_status;
  * is created.  The objective (model) convolution stays 2-D.  APX_CONV_DIRECT_2D keeps
  * every convolution 2-D. */
 #define APX_CONV_DIRECT_2D 2
+/* APX_CONV_AUTO: as APX_CONV_DIRECT (rank-one stamps by two 1-D passes), and a job of the
+ * FP32 kinds (Jacobian columns, adjoint, the FP32 objective's model) on an image with a
+ * fixed stamp of P >= APX_FFT_MIN_P that is not rank one, no sub-pixel grid and an output
+ * box of at least 32 x 32 runs as FFT tiles (as in APX_CONV_FFT) when an operation-count
+ * model prices them below its direct tiles: with nch channels of an h x w output, blocks =
+ * ceil(h / (129 - P)) ceil(w / (129 - P)), FFT cost = ceil(nch blocks / 2)
+ * APX_AUTO_FFT_PAIR_COST, direct cost = nch min over the four tile shapes (TH x TW) of
+ * ceil(h / TH) ceil(w / TW) (TH TW (P^2 + 10) + 8 (TH + P - 1)(TW + P - 1) + 3000); FFT
+ * when strictly cheaper.  The choice depends on the geometry only, not on timings. */
+#define APX_CONV_AUTO 3
+#define APX_AUTO_FFT_PAIR_COST 6.7e6
 
 /* Sub-pixel re-centring (§2.1.3).  With shift != APX_SHIFT_NONE every Sersic component
  * is sampled (and pixel-integrated) with its centre moved to the centre of the nearest
@@ -218,7 +229,7 @@ typedef struct apx_problem_desc {
     double  k_re;                   /* k of APX_MODE_WITHIN_K_RE; tol of
                                        APX_MODE_ADAPTIVE                             */
     int32_t n_psf_models;           /* live PSF models (0: every stamp is fixed)     */
-    int32_t conv_mode;              /* APX_CONV_DIRECT (default), APX_CONV_FFT or APX_CONV_DIRECT_2D */
+    int32_t conv_mode;              /* APX_CONV_DIRECT (default), APX_CONV_FFT, APX_CONV_DIRECT_2D or APX_CONV_AUTO */
     const apx_psf_model_desc* psf_models;   /* host, [n_psf_models]                 */
     int32_t shift;                  /* APX_SHIFT_* sub-pixel re-centring (0 = none)   */
     int32_t shift_a;                /* Lanczos order a (APX_SHIFT_LANCZOS only)      */
@@ -358,7 +369,8 @@ apx_status apx_problem_destroy(apx_problem* p);
 #define APX_TIME_CONV_ADJ   9     /* adjoint convolution                        */
 #define APX_TIME_GRAD       10    /* adjoint contraction with recomputed samples */
 #define APX_TIME_CONV_SEP   11    /* Jacobian-column convolutions as two 1-D passes (rank-one stamps) */
-#define APX_TIME_CLASSES    12
+#define APX_TIME_CONV_FFT   12    /* convolutions on FFT tiles (any kind)        */
+#define APX_TIME_CLASSES    13
 /* Kernel timing with HIP events on the context stream: enabled != 0 records every class;
  * set_timing_classes records only the classes in mask (bit 1 << class), which keeps the
  * event overhead off the other launches.  Either call resets the records. */

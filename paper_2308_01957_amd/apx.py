@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libapx.so")
 APX_OK, APX_E_INVALID, APX_E_HIP, APX_E_NONFINITE, APX_E_WORKSPACE, APX_E_UNSUPPORTED, APX_E_DOMAIN = \
     0, -1, -2, -3, -4, -5, -6
 OBJECTIVE_FP64, OBJECTIVE_FP32 = 0, 1
-CONV_DIRECT, CONV_FFT, CONV_DIRECT_2D = 0, 1, 2     # spec["conv_mode"]
+CONV_DIRECT, CONV_FFT, CONV_DIRECT_2D, CONV_AUTO = 0, 1, 2, 3     # spec["conv_mode"]
 SHIFT_NONE, SHIFT_BILINEAR, SHIFT_LANCZOS = 0, 1, 2   # spec["recentre"]["method"]
 
 EXPORTS = [
@@ -38,7 +38,7 @@ EXPORTS = [
 TILES_AUTOTUNE, TILES_MODEL, TILES_FIXED = 0, 1, 2
 TILE_SHAPES = [(32, 64), (16, 64), (32, 32), (16, 32)]       # output rows x cols per workgroup
 TIME_CLASSES = ["prep", "render", "conv_fwd", "deriv", "conv_jcol", "pairs", "reduce", "solve",
-                "lm", "conv_adj", "grad", "conv_sep"]
+                "lm", "conv_adj", "grad", "conv_sep", "conv_fft"]
 
 
 class ImageDesc(ctypes.Structure):

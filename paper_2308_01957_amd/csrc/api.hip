@@ -366,9 +366,23 @@ static std::array<double, 4> tile_costs(apx_ctx* C, int key, int P) {
     return cost;
 }
 
-// Tile shape of least estimated cost for an out_h x out_w output.  A shape must beat the
-// best lower-indexed (larger) one by more than 3 % to be taken: measured costs of
-// near-equal shapes wobble from run to run, and the larger tile re-reads less halo.
+// Automatic mode: a job of nch channels with an out_h x out_w output takes FFT tiles when
+// its pairs of 128 x 128 transforms (ceil(nch * blocks / 2), blocks of (129 - P)^2 outputs)
+// cost less than its direct tiles of the cheapest shape, both by the operation-count model
+// (tile_model) with one transform pair at APX_AUTO_FFT_PAIR_COST units (measured on MI355X:
+// a pair takes about as long as 5.0 direct 32 x 64 tiles at P = 25, 3.3 at P = 31).  The
+// model, not the autotuner's timings, decides, so the choice and the results do not depend
+// on timing noise.
+static bool auto_fft(int P, int out_h, int out_w, int nch) {
+    double direct = 1e300;
+    for (int s = 0; s < N_TILE_SHAPES; ++s)
+        direct = std::min(direct, (double)ceil_div(out_h, tile_th(s)) * ceil_div(out_w, tile_tw(s)) * tile_model(P, s));
+    const int B = FFT_T - P + 1;
+    const long long blocks = (long long)ceil_div(out_h, B) * ceil_div(out_w, B);
+    const double fft = (double)((nch * blocks + 1) / 2) * APX_AUTO_FFT_PAIR_COST;
+    return fft < direct * nch;
+}
+
 // Workgroups of the 64-wide J^T W J tile kernel resident on the whole device at once; a
 // plan-only context takes gfx950's (256 compute units, 3 per unit at the kernel's 134
 // registers per lane).
@@ -388,6 +402,9 @@ static int pair_slots(apx_ctx* C) {
     return C->pair_slots;
 }
 
+// Tile shape of least estimated cost for an out_h x out_w output.  A shape must beat the
+// best lower-indexed (larger) one by more than 3 % to be taken: measured costs of
+// near-equal shapes wobble from run to run, and the larger tile re-reads less halo.
 static int choose_shape(apx_ctx* C, int key, int P, int out_h, int out_w) {
     if (C->tiles >= APX_TILES_FIXED && C->tiles < APX_TILES_FIXED + N_TILE_SHAPES) return C->tiles - APX_TILES_FIXED;
     if (out_h <= 0 || out_w <= 0) return 0;
@@ -581,7 +598,8 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         return fail(C, APX_E_INVALID, "adaptive tolerance (k_re) must be > 0");
     if (d->objective != APX_OBJECTIVE_FP64 && d->objective != APX_OBJECTIVE_FP32)
         return fail(C, APX_E_INVALID, "unknown objective precision");
-    if (d->conv_mode != APX_CONV_DIRECT && d->conv_mode != APX_CONV_FFT && d->conv_mode != APX_CONV_DIRECT_2D)
+    if (d->conv_mode != APX_CONV_DIRECT && d->conv_mode != APX_CONV_FFT && d->conv_mode != APX_CONV_DIRECT_2D &&
+        d->conv_mode != APX_CONV_AUTO)
         return fail(C, APX_E_INVALID, "unknown convolution mode");
     if (d->shift != APX_SHIFT_NONE && d->shift != APX_SHIFT_BILINEAR && d->shift != APX_SHIFT_LANCZOS)
         return fail(C, APX_E_INVALID, "unknown re-centring method");
@@ -631,7 +649,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
 
     build_bn_table(P->bn_tab);
     build_pow2_table(P->ptab);
-    if (d->conv_mode == APX_CONV_FFT)
+    if (d->conv_mode == APX_CONV_FFT || d->conv_mode == APX_CONV_AUTO)
         for (int m = 0; m < FFT_T; ++m) {
             const double a = -2.0 * M_PI * m / FFT_T;
             P->fft_tw.push_back((float)std::cos(a));
@@ -772,7 +790,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     // 4e-7 of itself (three FP32 roundings of exact products) plus 1e-9 of the largest.
     for (int k = 0; k < d->n_images; ++k) P->images[k].sep_off = -1;
     P->psf_sep.clear();
-    if (d->conv_mode == APX_CONV_DIRECT && C->device >= 0 && P->n_psf > 0) {
+    if ((d->conv_mode == APX_CONV_DIRECT || d->conv_mode == APX_CONV_AUTO) && C->device >= 0 && P->n_psf > 0) {
         std::vector<float> h((size_t)P->n_psf);
         if (hipMemcpy(h.data(), d->psf, (size_t)P->n_psf * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
             return fail(C, APX_E_HIP, "reading the stamps back");
@@ -1009,8 +1027,11 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     // convolution jobs and items, sorted by (PSF size, tile shape): one launch per pair.
     // Each job takes the tile shape of least estimated cost (choose_shape).
     // In FFT mode, jobs of the FP32 kinds on images with spectra and outputs of at least
-    // 32 x 32 take the FFT shape; the items of each FFT range are paired (two per complex
-    // transform) when they share the image, and so the stamp.
+    // 32 x 32 take the FFT shape; in automatic mode, such a job (on an image with a fixed,
+    // not rank-one stamp at P >= APX_FFT_MIN_P) takes it when the cost model prices its
+    // transforms below its direct tiles (auto_fft), and its image gets spectra.  The items
+    // of each FFT range are paired (two per complex transform) when they share the image,
+    // and so the stamp.
     auto add_items = [&](int kind, std::vector<ConvJob>& jobs, std::vector<ConvItem>& items,
                          std::vector<PRange>& ranges, const std::vector<int>& jobP,
                          const std::vector<int>& nch, std::vector<int>* job_item_begin,
@@ -1018,9 +1039,19 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         const int key = kind == CONV_JCOL ? TUNE_JCOL : kind == CONV_ADJ ? TUNE_ADJ
                       : P->objective == APX_OBJECTIVE_FP64 ? TUNE_FWD64 : TUNE_FWD32;
         for (size_t j = 0; j < jobs.size(); ++j) {
-            const bool fft = pairs && P->images[jobs[j].image].fft_off >= 0 && jobs[j].out_h >= 32 &&
-                             jobs[j].out_w >= 32;
-            const bool sep = kind == CONV_JCOL && P->images[jobs[j].image].sep_off >= 0;
+            DImage& im = P->images[jobs[j].image];
+            const bool big = jobs[j].out_h >= 32 && jobs[j].out_w >= 32;
+            const bool sep = kind == CONV_JCOL && im.sep_off >= 0;
+            bool fft = pairs && big && P->conv_mode == APX_CONV_FFT && im.fft_off >= 0;
+            if (pairs && big && !sep && P->conv_mode == APX_CONV_AUTO && !im.live && im.up == 1 &&
+                im.P >= APX_FFT_MIN_P && nch[j] > 0 && auto_fft(jobP[j], jobs[j].out_h, jobs[j].out_w, nch[j])) {
+                fft = true;
+                if (im.fft_off < 0) {
+                    im.fft_off = P->n_fft_spec;
+                    P->n_fft_spec += 2LL * FFT_T * FFT_T;
+                    ++P->n_fft_images;
+                }
+            }
             jobs[j].shape = fft ? SHAPE_FFT
                           : sep ? SHAPE_SEP : choose_shape(C, key, jobP[j], jobs[j].out_h, jobs[j].out_w);
         }
@@ -1938,7 +1969,7 @@ static apx_status run_conv(apx_problem* P, int kind, const ConvIO& io) {
                     : (kind == CONV_JCOL || kind == CONV_JCOL_PSF) ? APX_TIME_CONV_JCOL : APX_TIME_CONV_ADJ;
     const char* pn = kind == CONV_FWD ? "fwd_pairs" : kind == CONV_JCOL ? "jcol_pairs" : "adj_pairs";
     for (const PRange& r : *ranges) {
-        TimeScope ts(P, r.shape == SHAPE_SEP ? APX_TIME_CONV_SEP : klass);
+        TimeScope ts(P, r.shape == SHAPE_SEP ? APX_TIME_CONV_SEP : r.shape == SHAPE_FFT ? APX_TIME_CONV_FFT : klass);
         ConvLaunch L{wsp<ConvJob>(P, jn), wsp<ConvItem>(P, inn), r.begin, r.count, r.P, r.shape, nullptr,
                      r.pair_begin, r.pair_count};
         if (r.shape == SHAPE_SEP) {

@@ -124,3 +124,29 @@ def test_class_rooflines_count_by_hand():
     spec["conv_mode"] = 1
     _, per = bench.class_rooflines(spec, _Prob(), kt, phases=3)
     assert set(per) == {"pairs"}
+
+
+def test_auto_fft_choice_matches_the_library_plan():
+    """The bench's copy of the automatic mode's FFT-or-direct rule picks the same number of
+    FFT Jacobian jobs as the library's plan (host-only context: no stamp is read back, so
+    none counts as rank one), on cutouts of 32-256 px and on the blended field (one wide
+    Sersic group, small point-source windows)."""
+    from paper_2308_01957_amd import apx, synth
+    for spec in (synth.cutouts(seed_id=104, n_cutouts=300), synth.blend()):
+        spec = dict(spec, conv_mode=apx.CONV_AUTO)
+        plan = apx.Plan(spec)
+        n_fft = plan.tile_shapes(1)[4]
+        plan.close()
+        groups = bench.auto_fft_groups(spec, rank_one=set())
+        assert n_fft == len(groups) and n_fft > 0, (n_fft, len(groups))
+
+
+def test_auto_fft_rule_by_hand():
+    """Worked cases of the rule: a 256 x 256 job of 21 columns at P = 31 takes FFT tiles
+    (9 blocks of 98^2 per column, 95 transform pairs at 6.7e6 against 21 x 32 tiles of
+    32 x 64 at 2.04e6); a 40 x 40 job at P = 15 stays direct (one 115^2 block per column)."""
+    assert bench.auto_fft_job(31, 256, 256, 21)
+    assert not bench.auto_fft_job(15, 40, 40, 7)
+    P = 31
+    direct = 21 * 32 * (32 * 64 * (P * P + 10.0) + 8.0 * (32 + P - 1) * (64 + P - 1) + 3000.0)
+    assert ((21 * 9 + 1) // 2) * bench.AUTO_FFT_PAIR_COST < direct

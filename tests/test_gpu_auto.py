@@ -1,0 +1,112 @@
+"""Automatic convolution mode (a job takes FFT tiles where the library's cost model prices
+them below direct tiles; rank-one stamps keep the two-pass kernel) through the C ABI
+against the FP64 oracle, which convolves directly: the plan, Jacobian columns, J^T W J,
+the chi^2 gradient and the render VJP, graph replay against eager launches, and a
+converged batched fit."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import cases
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2308_01957_amd import apx as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def spec():
+    return cases.auto_cutouts()
+
+
+def _problem(apx, spec, **kw):
+    print(f"[case] {spec['name']}", flush=True)
+    P = apx.Problem(spec, **kw)
+    return P, P.pixels(spec["data"]), P.pixels(spec["weight"])
+
+
+def test_auto_plan_mixes_fft_two_pass_and_direct(apx, spec):
+    """The library plans the jobs the documented rule picks: the rank-one stamps on the
+    two-pass kernel, the FFT-priced jobs on FFT tiles (as many as the rule's copy in the
+    bench finds), the rest on direct tiles."""
+    P, _, _ = _problem(apx, spec)
+    shapes = P.tile_shapes(1)
+    sep = bench.rank_one_images(spec, 3)
+    fft = bench.auto_fft_groups(spec, sep)
+    assert shapes[5] == len(sep) >= 1
+    assert shapes[4] == len(fft) >= 1
+    assert sum(shapes[:4]) >= 1
+    P.check()
+
+
+def test_auto_jacobian_normal_equations_gradient_vjp(apx, spec):
+    P, d, w = _problem(apx, spec)
+    th = spec["theta_init"]
+    J = P.jacobian(th).cpu().numpy().T.astype(np.float64)
+    Jo = oracle.jacobian(spec, th)
+    scale = np.maximum(np.max(np.abs(Jo), axis=0), 1e-30)
+    err = np.max(np.abs(J - Jo), axis=0) / scale
+    assert np.all(err <= 3e-5), (int(np.argmax(err)), float(np.max(err)))
+    A, g, _ = P.jtwj(th, d, w)
+    A = A.cpu().numpy()
+    g = g.cpu().numpy()
+    for s, (p0, n) in enumerate(spec["subs"]):
+        Ao, go, c2o = oracle.jtwj(spec, th, spec["data"], spec["weight"], s)
+        As = A[P.a_offsets[s]:P.a_offsets[s + 1]].reshape(n, n)
+        sd = np.sqrt(np.diag(Ao))
+        assert np.all(np.abs(As - Ao) <= 1e-4 * np.outer(sd, sd)), s
+        assert np.all(np.abs(g[p0:p0 + n] - go) <= 1e-4 * sd * math.sqrt(c2o)), s
+    gr, _ = P.chi2_grad(th, d, w)
+    gro = oracle.chi2_grad(spec, th, spec["data"], spec["weight"])
+    r, wv = oracle.residual(spec, th, spec["data"], spec["weight"], list(range(len(spec["images"]))))
+    tol = 1e-4 * np.maximum(np.abs(gro), 2.0 * (np.abs(wv * r) @ np.abs(Jo)))
+    assert np.all(np.abs(gr.cpu().numpy() - gro) <= tol), float(np.max(np.abs(gr.cpu().numpy() - gro) / tol))
+    seed = np.random.default_rng(133).standard_normal(P.n_pix).astype(np.float32)
+    v = P.render_vjp(th, seed).cpu().numpy()
+    s64 = seed.astype(np.float64)
+    vo = s64 @ Jo
+    tolv = 1e-4 * np.maximum(np.abs(vo), np.abs(s64) @ np.abs(Jo))
+    assert np.all(np.abs(v - vo) <= tolv), float(np.max(np.abs(v - vo) / tolv))
+    P.check()
+
+
+def test_auto_graph_replay_equals_eager(apx, spec):
+    """Five batched iterations replayed from the captured graph land on the same bits as
+    five eager iterations."""
+    import torch
+    P, d, w = _problem(apx, spec)
+    th1, st1 = P.lm_init(spec["theta_init"], d, w)
+    P.lm_run(5, d, w, th1, st1, use_graph=True)
+    th2, st2 = P.lm_init(spec["theta_init"], d, w)
+    P.lm_run(5, d, w, th2, st2, use_graph=False)
+    P.check()
+    assert torch.equal(th1, th2)
+
+
+def test_auto_lm_converges_to_the_oracle_fit(apx):
+    spec = cases.auto_fit()
+    P, d, w = _problem(apx, spec)
+    shapes = P.tile_shapes(1)
+    assert shapes[4] >= 1 and shapes[5] >= 1 and sum(shapes[:4]) >= 1, shapes
+    th, st = P.lm_init(spec["theta_init"], d, w)
+    P.lm_run(30, d, w, th, st)
+    P.check()
+    tg = th.cpu().numpy()
+    to, _ = oracle.lm_fit(spec, spec["theta_init"], spec["data"], spec["weight"], 30)
+    for s, (p0, n) in enumerate(spec["subs"]):
+        A, g, _ = oracle.jtwj(spec, to, spec["data"], spec["weight"], s)
+        assert float(g @ np.linalg.solve(A, g)) < 1e-6, ("oracle not converged", s)
+    cases.assert_fit_parity(spec, tg, to, spec["name"])
