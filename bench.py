@@ -235,20 +235,7 @@ def class_rooflines(spec, prob, kt, phases, per_call=(1, 1), n_obj=None):
     fwd = sum(img_flop)
     psf_cols = sum(img_flop[int(m["image"])] * sum(1 for q in m["par"] if q >= 0)
                    for m in spec.get("psf_models", []))
-    # column groups: the free parameters of one component share one output window
-    groups = []
-    for c in spec["comps"]:
-        n = sum(1 for q in c["par"] if q >= 0)
-        if n:
-            groups.append((c["image"], output_window(c, spec["images"][c["image"]]), n))
-    pair_flop = 0.0
-    for a in range(len(groups)):
-        for b in range(a, len(groups)):
-            (ia, wa, na), (ib, wb, nb) = groups[a], groups[b]
-            if ia != ib:
-                continue
-            npix = max(0, min(wa[2], wb[2]) - max(wa[0], wb[0])) * max(0, min(wa[3], wb[3]) - max(wa[1], wb[1]))
-            pair_flop += 2.0 * npix * (na * (na + 1) / 2 if a == b else na * nb)
+    pair_flop = float(pair_flop_per_sub(spec).sum())
     n_fwd = kt.get("conv_fwd", (0.0, 0))[1] / per_call[0] if n_obj is None else n_obj
     n_adj = kt.get("conv_adj", (0.0, 0))[1] / per_call[1]
     models = {"pairs": (pair_flop * phases, PEAK_FP64_TFLOPS, "k_pair / k_gram4 (FP64 MFMA)")}
@@ -268,6 +255,53 @@ def class_rooflines(spec, prob, kt, phases, per_call=(1, 1), n_obj=None):
                     "unit": "TFLOP/s", "frac": ach / peak, "ms_total": ms, "traffic": None}
     dom = max(out, key=lambda k: out[k]["ms_total"]) if out else None
     return (out[dom] if dom else None), out
+
+
+def pair_flop_per_sub(spec):
+    """J^T W J work of each sub-problem: 2 FLOP per pixel and column pair of the upper
+    triangle, over the overlap of the output windows of every pair of column groups on one
+    image (a component's free parameters form a group; the algorithmic count, whatever
+    the tiles pad)."""
+    groups = []
+    for c in spec["comps"]:
+        n = sum(1 for q in c["par"] if q >= 0)
+        if n:
+            groups.append((c["image"], output_window(c, spec["images"][c["image"]]), n))
+    out = np.zeros(len(spec["subs"]))
+    for a in range(len(groups)):
+        for b in range(a, len(groups)):
+            (ia, wa, na), (ib, wb, nb) = groups[a], groups[b]
+            if ia != ib:
+                continue
+            npix = max(0, min(wa[2], wb[2]) - max(wa[0], wb[0])) * max(0, min(wa[3], wb[3]) - max(wa[1], wb[1]))
+            out[spec["images"][ia]["sub"]] += 2.0 * npix * (na * (na + 1) / 2 if a == b else na * nb)
+    return out
+
+
+RENDER64_FLOP_PER_NODE = 84.0   # 54 FP64 operations per Sersic node, 30 of them FMAs (2 FLOP)
+
+
+def objective_flop_per_sub(spec):
+    """Per sub-problem, one trial objective evaluation: (FP64 render, FP64 convolution).
+    Render: RENDER64_FLOP_PER_NODE per node, s^2 nodes per pixel of each Sersic window on
+    the extended grid (uniform sampling); convolution: 2 P^2 per image pixel."""
+    smp = spec["sampling"]
+    assert int(smp["mode"]) == 0, "node counts are exact for uniform sampling only"
+    nodes = int(smp["s"]) ** 2
+    ren = np.zeros(len(spec["subs"]))
+    fwd = np.zeros(len(spec["subs"]))
+    for im in spec["images"]:
+        P = np.asarray(im["psf"]).shape[0]
+        fwd[im["sub"]] += 2.0 * P * P * im["H"] * im["W"]
+    for c in spec["comps"]:
+        if int(c["type"]) != 0:
+            continue
+        im = spec["images"][c["image"]]
+        h = (np.asarray(im["psf"]).shape[0] - 1) // 2
+        y0, x0, y1, x1 = c["box"]
+        npix = max(0, min(y1, im["H"] + h) - max(y0, -h)) * max(0, min(x1, im["W"] + h) - max(x0, -h))
+        ren[im["sub"]] += npix * nodes * RENDER64_FLOP_PER_NODE
+    return ren, fwd
 
 
 def output_window(c, im):
@@ -413,14 +447,20 @@ def run_cutouts(args, torch, apx, synth):
 
     # eager pass over the same iterations, one at a time: which cutouts form a Jacobian in
     # each iteration (need_jac), for the algorithmic FLOP count of the Jacobian phases
+    ren_sub, fwd_sub = objective_flop_per_sub(spec)
+    pair_sub = pair_flop_per_sub(spec)
     th_e, st_e = prob.lm_init(spec["theta_init"], dd, ww)
-    flop_jac = ent_sep = flop_fft = 0.0
+    flop_jac = ent_sep = flop_fft = flop_ren = flop_fwd = flop_pair = 0.0
     for _ in range(args.steps):
         need = prob.lm_state(st_e)["need_jac"] != 0
         flop_jac += float(flop_2d_sub[need].sum())
         ent_sep += float(ent_sep_sub[need].sum())
         flop_fft += float(fft_flop_sub[need].sum())
+        flop_pair += float(pair_sub[need].sum())
         prob.lm_step(dd, ww, th_e, st_e)
+        ev = np.isfinite(prob.lm_state(st_e)["chi2_trial"])     # trials whose objective ran
+        flop_ren += float(ren_sub[ev].sum())
+        flop_fwd += float(fwd_sub[ev].sum())
     prob.check()
     torch.cuda.synchronize()
     print(f"[bench] eager pass done ({flop_jac / 1e12:.2f} TFLOP of 2-D Jacobian convolutions, "
@@ -454,6 +494,8 @@ def run_cutouts(args, torch, apx, synth):
     sep_ms, _ = kt["conv_sep"]
     fft_ms, _ = kt["conv_fft"]
     achieved = flop_jac / (jcol_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
+
+
     if mode == 1:            # FFT mode: the Jacobian runs on FFT tiles (direct-equivalent rate)
         jcol_ms, flop_jac = fft_ms, flop_fft
         achieved = flop_jac / (jcol_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
@@ -465,6 +507,29 @@ def run_cutouts(args, torch, apx, synth):
     prob.lm_run(args.steps, dd, ww, th2, st2, use_graph=False)
     torch.cuda.synchronize()
     t_eager = time.perf_counter() - t0
+
+    # the other kernel classes, from a second instrumented graph pass over the same
+    # iterations (their event marks stay out of the timed replays)
+    oclasses = ["render", "conv_fwd", "pairs"]
+    prob.set_timing(True, classes=oclasses)
+    prob.lm_init(spec["theta_init"], dd, ww, theta_out=th2, state_out=st2)
+    prob.lm_run(1, dd, ww, th2, st2, use_graph=True)            # captures with the new marks
+    prob.set_timing(True, classes=oclasses)
+    prob.lm_init(spec["theta_init"], dd, ww, theta_out=th2, state_out=st2)
+    prob.lm_run(args.steps, dd, ww, th2, st2, use_graph=True)
+    ko = prob.timing()
+    prob.set_timing(False)
+
+    def cls_roof(flop, ms, peak, kernel, bound="alu"):
+        ach = flop / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        return {"bound": bound, "kernel": kernel, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "ms_per_step": ms / max(1, args.steps), "traffic": None}
+    per_class = {
+        "render": cls_roof(flop_ren, ko["render"][0], PEAK_FP64_TFLOPS,
+                           "k_render64 (FP64 trial render; %g FLOP per Sersic node)" % RENDER64_FLOP_PER_NODE),
+        "conv_fwd": cls_roof(flop_fwd, ko["conv_fwd"][0], PEAK_FP64_TFLOPS, "k_conv<P,FWD,double> (FP64 objective)"),
+        "pairs": cls_roof(flop_pair, ko["pairs"][0], PEAK_FP64_TFLOPS, "k_gram4 / k_pair (FP64 MFMA)", "mfma"),
+    }
 
     # context: the same K iterations with every convolution direct (rank-one stamps by two
     # passes, no FFT tiles), and with every convolution 2-D
@@ -556,6 +621,8 @@ def run_cutouts(args, torch, apx, synth):
                                "on direct tiles)",
                      "ms_per_phase": jcol_ms / max(1, args.steps), "flop_per_phase": flop_jac / max(1, args.steps),
                      "launch_groups": jcol_launches},
+        "roofline_per_class": per_class,
+        "roofline_per_class_note": "other kernel classes of the same iterations, timed in a second graph pass",
         "two_pass_jacobian": {"kernel": "k_conv_sep<P> (rank-one stamps)", "ms_per_phase": sep_ms / max(1, args.steps),
                               "entries_per_phase": ent_sep / max(1, args.steps), "images": len(sep_img)},
         "fft_jacobian": {"kernel": "k_conv_fft<JCOL> (128x128 overlap-save tiles)", "jobs": len(fft_jobs),

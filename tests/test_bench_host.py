@@ -150,3 +150,18 @@ def test_auto_fft_rule_by_hand():
     P = 31
     direct = 21 * 32 * (32 * 64 * (P * P + 10.0) + 8.0 * (32 + P - 1) * (64 + P - 1) + 3000.0)
     assert ((21 * 9 + 1) // 2) * bench.AUTO_FFT_PAIR_COST < direct
+
+
+def test_objective_flop_by_hand():
+    """Trial objective work of a one-image sub-problem: a Sersic window (-3, -3, 5, 20) cut
+    to the extended grid [-1, 11) x [-1, 13) of a 10 x 12 image with P = 3 holds 6 x 14
+    pixels of 9 nodes; a point source adds no render work; the convolution is 2 P^2 per
+    image pixel."""
+    import numpy as np
+    spec = {"images": [dict(H=10, W=12, psf=np.ones((3, 3)), sub=0)], "subs": [(0, 8)],
+            "sampling": dict(s=3, rule=0, mode=0, k=0.0),
+            "comps": [dict(type=0, image=0, box=(-3, -3, 5, 20), par=[0, 1, 2, 3, 4, 5, 6]),
+                      dict(type=1, image=0, box=(2, 2, 6, 6), par=[7, -1, -1])]}
+    ren, fwd = bench.objective_flop_per_sub(spec)
+    assert ren[0] == 6 * 14 * 9 * bench.RENDER64_FLOP_PER_NODE
+    assert fwd[0] == 2 * 9 * 120
