@@ -417,8 +417,12 @@ def run_cutouts(args, torch, apx, synth):
     spec = synth.cutouts()
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    prob = apx.Problem(_conv(args, spec))
+    Ps = [np.asarray(im["psf"]).shape[0] for im in spec["images"]]
+    costs = load_tile_costs(args.tile_costs_in) if args.tile_costs_in else None
+    prob = apx.Problem(_conv(args, spec), tile_costs=costs)
     t_plan = time.perf_counter() - t0
+    if args.tile_costs_out:
+        save_tile_costs(prob, Ps, args.tile_costs_out)
     n_sub = len(spec["subs"])
     print(f"[bench] cutouts: {n_sub} sub-problems, {prob.n_pix / 1e6:.1f} Mpix, "
           f"plan {t_plan:.1f} s, workspace {prob.workspace_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
@@ -596,6 +600,18 @@ def run_cutouts(args, torch, apx, synth):
     torch.cuda.synchronize()
     cov_ms = (time.perf_counter() - t0) * 1e3
     mpix = _mpix(prob, spec, torch, 5)
+    # HBM bytes of the 2-D class: the counted bytes per algorithmic FLOP of the counter
+    # summary (same kernel sources, same tile shapes) times this run's FLOP per phase
+    # (the autotuner's choice among 2047 jobs varies a little from run to run; the counted
+    # run's tile mix is reported beside this run's)
+    traffic, traffic_note = None, None
+    if mode == 0:
+        kv = counted_record("conv_jcol_cutouts4096_hbm_counters.md", "k_conv<P,JCOL> (2-D, cutouts)")
+        if kv is not None:
+            traffic = float(kv["bytes_per_flop"]) * flop_jac / max(1, args.steps)
+            traffic_note = {"bytes_per_flop": float(kv["bytes_per_flop"]),
+                            "counted_tiles": json.loads(kv["jacobian_tiles"]),
+                            "this_run_tiles": tile_choice(prob)["jacobian"]}
     rec = {
         "metric": "LM iters/s & Mpix/s rendered (fused adjoint+batched vs plain) at oracle rtol",
         "value": batched, "unit": "cutout LM it/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -615,7 +631,8 @@ def run_cutouts(args, torch, apx, synth):
         "plain_vs_batched_max_dtheta": plain_dev,
         "mpix_per_s": mpix,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic, "traffic_unit": "bytes/phase",
+                     "traffic_from": traffic_note,
                      "kernel": "k_conv<P,JCOL> (2-D Jacobian-column convolutions: all PSF sizes and tile "
                                "shapes of a phase, cutouts whose stamp is not rank one and whose job stays "
                                "on direct tiles)",
@@ -623,6 +640,7 @@ def run_cutouts(args, torch, apx, synth):
                      "launch_groups": jcol_launches},
         "roofline_per_class": per_class,
         "roofline_per_class_note": "other kernel classes of the same iterations, timed in a second graph pass",
+        "eager_pass_flop_2d": flop_jac,
         "two_pass_jacobian": {"kernel": "k_conv_sep<P> (rank-one stamps)", "ms_per_phase": sep_ms / max(1, args.steps),
                               "entries_per_phase": ent_sep / max(1, args.steps), "images": len(sep_img)},
         "fft_jacobian": {"kernel": "k_conv_fft<JCOL> (128x128 overlap-save tiles)", "jobs": len(fft_jobs),
@@ -883,13 +901,14 @@ def prob_tile_shapes():
     return apx.TILE_SHAPES
 
 
-def counted_traffic(kernel, jac_tiles):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when there is none, the kernel's sources changed after the counters were taken, or this
-    run's Jacobian jobs took other tile shapes than the counted run's (the halo re-reads, and
-    so the bytes, depend on the shape)."""
+def counted_record(name, kernel, jac_tiles=None):
+    """The machine-readable block of the committed rocprofv3 counter summary
+    profiles/<name>, or None when there is none, it covers another kernel, the kernel's
+    sources changed after the counters were taken, or (jac_tiles given) this run's Jacobian
+    jobs took other tile shapes than the counted run's (the halo re-reads, and so the bytes,
+    depend on the shape)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "conv_jcol_blend512_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -904,9 +923,26 @@ def counted_traffic(kernel, jac_tiles):
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if h.hexdigest() != kv.get("sources_sha256"):
         return None
-    if "jacobian_tiles" not in kv or json.loads(kv["jacobian_tiles"]) != jac_tiles:
+    if "jacobian_tiles" not in kv or (jac_tiles is not None and json.loads(kv["jacobian_tiles"]) != jac_tiles):
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return kv
+
+
+def counted_traffic(kernel, jac_tiles):
+    """HBM bytes per launch of the blend's Jacobian convolution (counter summary of the
+    blend), or None (counted_record)."""
+    kv = counted_record("conv_jcol_blend512_hbm_counters.md", kernel, jac_tiles)
+    return None if kv is None else float(kv["traffic_bytes_per_launch"])
+
+
+def load_tile_costs(path):
+    """Autotuner table written by --tile-costs-out: {(kernel, P): [us per tile]}."""
+    return {tuple(int(v) for v in k.split(",")): c for k, c in json.load(open(path)).items()}
+
+
+def save_tile_costs(prob, Ps, path):
+    table = {f"{k},{P}": prob.tile_cost(k, P) for k in range(4) for P in sorted(set(Ps))}
+    json.dump({k: v for k, v in table.items() if v is not None}, open(path, "w"))
 
 
 def copy_calibration(args, torch):
@@ -934,10 +970,10 @@ def main():
                     help="also launch three plain copy kernels of MIB MiB (read MIB, write MIB) "
                          "after the timed region, to calibrate HBM byte counters")
     ap.add_argument("--tile-costs-out", metavar="JSON",
-                    help="blend: write the autotuner's measured tile costs to JSON")
+                    help="cutouts or blend: write the autotuner's measured tile costs to JSON")
     ap.add_argument("--tile-costs-in", metavar="JSON",
-                    help="blend: take the tile costs from JSON instead of timing them (the same "
-                         "tile shapes as the run that wrote it, e.g. under a counter profiler)")
+                    help="cutouts or blend: take the tile costs from JSON instead of timing them (the "
+                         "same tile shapes as the run that wrote it, e.g. under a counter profiler)")
     ap.add_argument("--conv", default=None, choices=["direct", "fft", "auto"],
                     help="PSF convolution mode: direct (default), FFT tiles for P >= 15, or auto (FFT tiles "
                          "per job where the library's cost model prices them below direct)")
@@ -1005,11 +1041,10 @@ def run_blend(args, torch, apx, synth, with_fft=True):
     print(f"[bench] workload {spec['name']}: {spec['n_par']} parameters", file=sys.stderr, flush=True)
     costs = None
     if args.tile_costs_in:
-        costs = {(int(k), P_psf): v for k, v in json.load(open(args.tile_costs_in)).items()}
+        costs = load_tile_costs(args.tile_costs_in)
     prob = apx.Problem(_conv(args, spec), tile_costs=costs)
     if args.tile_costs_out:
-        table = {k: prob.tile_cost(k, P_psf) for k in range(4)}
-        json.dump({k: v for k, v in table.items() if v is not None}, open(args.tile_costs_out, "w"))
+        save_tile_costs(prob, [P_psf], args.tile_costs_out)
     m_true = prob.split(prob.render(spec["theta_true"]))[0].astype(np.float64)
     prob.check()
     d, w = synth.make_data(m_true, spec["noise"][0])
