@@ -278,7 +278,7 @@ def pair_flop_per_sub(spec):
     return out
 
 
-RENDER64_FLOP_PER_NODE = 84.0   # 54 FP64 operations per Sersic node, 30 of them FMAs (2 FLOP)
+RENDER64_FLOP_PER_NODE = 73.0   # 47 FP64 operations per Sersic node, 26 of them FMAs (2 FLOP)
 
 
 def objective_flop_per_sub(spec):

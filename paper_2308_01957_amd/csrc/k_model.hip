@@ -352,18 +352,29 @@ __device__ __forceinline__ double point_weight(const CompConst& c, int y, int x)
 // objective path: chi^2 differences of the LM gain ratio are resolved far below FP32
 // rounding.
 // tab: the 2^x / log2 table in LDS (PTAB_N doubles)
+// The nodes of a pixel in the component's frame: the node at pixel offset (ox, oy) sits at
+// (xp, yq) = (xp0 + ox ax + oy bx, yq0 + ox ay + oy by), with (xp0, yq0) the pixel centre's
+// rotated and 1/q-scaled offset and (ax, ay), (bx, by) the images of the pixel axes (the
+// affine map's columns rotated and scaled the same way): two FMAs per node instead of
+// mapping and rotating every node.
 __device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst& c, const DImage& im,
                                                  double ucx, double ucy, const double* __restrict__ tab) {
     const double dxc = ucx - c.x0, dyc = ucy - c.y0;
     if (p.mode == APX_MODE_WITHIN_K_RE && !within_kre(c, ucx, ucy)) return sersic_I64_t(c, dxc, dyc, tab);
+    const double xp0 = dxc * c.cs_d + dyc * c.sn_d;
+    const double yq0 = (-dxc * c.sn_d + dyc * c.cs_d) * c.iq_d;
+    const double ax = im.aff[1] * c.cs_d + im.aff[4] * c.sn_d;
+    const double bx = im.aff[2] * c.cs_d + im.aff[5] * c.sn_d;
+    const double ay = (-im.aff[1] * c.sn_d + im.aff[4] * c.cs_d) * c.iq_d;
+    const double by = (-im.aff[2] * c.sn_d + im.aff[5] * c.cs_d) * c.iq_d;
     double sum = 0.0;
     for (int ky = 0; ky < p.s; ++ky) {
         const double oy = p.node_od[ky];
+        const double xr = fma(oy, bx, xp0), yr = fma(oy, by, yq0);
         double row = 0.0;
         for (int kx = 0; kx < p.s; ++kx) {
             const double ox = p.node_od[kx];
-            row += p.node_wd[kx] * sersic_I64_t(c, dxc + im.aff[1] * ox + im.aff[2] * oy,
-                                                dyc + im.aff[4] * ox + im.aff[5] * oy, tab);
+            row += p.node_wd[kx] * sersic_I64_r(c, fma(ox, ax, xr), fma(ox, ay, yr), tab);
         }
         sum += p.node_wd[ky] * row;
     }

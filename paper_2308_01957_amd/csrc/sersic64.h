@@ -105,13 +105,19 @@ __device__ __forceinline__ double log2_t(double x, const double* __restrict__ ta
     return fma(q * u, 1.4426950408889634074, tab[128 + j] + (double)e);
 }
 
+// I at a point given in the component's frame (xp along the major axis, yq = yp / q).
+__device__ __forceinline__ double sersic_I64_r(const CompConst& c, double xp, double yq,
+                                               const double* __restrict__ tab) {
+    const double R2 = fmax(xp * xp + yq * yq, 1e-12);
+    const double t = exp2_t(c.g_d * log2_t(R2, tab) - c.h_d, tab);
+    return exp2_t(c.A_d - c.B_d * t, tab);
+}
+
 __device__ __forceinline__ double sersic_I64_t(const CompConst& c, double dx, double dy,
                                                const double* __restrict__ tab) {
     const double xp = dx * c.cs_d + dy * c.sn_d;
     const double yq = (-dx * c.sn_d + dy * c.cs_d) * c.iq_d;
-    const double R2 = fmax(xp * xp + yq * yq, 1e-12);
-    const double t = exp2_t(c.g_d * log2_t(R2, tab) - c.h_d, tab);
-    return exp2_t(c.A_d - c.B_d * t, tab);
+    return sersic_I64_r(c, xp, yq, tab);
 }
 
 __device__ __forceinline__ double sersic_I64(const CompConst& c, double dx, double dy) {
