@@ -244,10 +244,8 @@ __device__ __forceinline__ float sersic_I(const CompConst& c, float dx, float dy
 }
 
 // Adds wgt * dI/dtheta_k (k = x0, y0, q, PA, n, Re, log10 Ie) into acc.
-__device__ __forceinline__ void sersic_dI(const CompConst& c, float dx, float dy, float wgt,
-                                          float acc[7]) {
-    const float xp = fmaf(dx, c.cs, dy * c.sn);
-    const float yp = fmaf(dy, c.cs, -dx * c.sn);
+// ... at a point given in the component's frame (xp along the major axis, yp across it)
+__device__ __forceinline__ void sersic_dI_r(const CompConst& c, float xp, float yp, float wgt, float acc[7]) {
     const float yq = yp * c.iq;
     float R2 = fmaf(xp, xp, yq * yq);
     const bool floored = R2 < 1e-12f;
@@ -269,6 +267,11 @@ __device__ __forceinline__ void sersic_dI(const CompConst& c, float dx, float dy
     acc[4] += I * (c.bp * (1.f - t) + c.b * t * lt * LN2F * inv_n);
     acc[5] += bt * __builtin_amdgcn_rcpf(c.re);
     acc[6] += I * LN10F;
+}
+
+__device__ __forceinline__ void sersic_dI(const CompConst& c, float dx, float dy, float wgt,
+                                          float acc[7]) {
+    sersic_dI_r(c, fmaf(dx, c.cs, dy * c.sn), fmaf(dy, c.cs, -dx * c.sn), wgt, acc);
 }
 
 struct NodeSet {
@@ -331,13 +334,18 @@ __device__ __forceinline__ void sersic_pixel_grad(const Plan& p, const CompConst
             return;
         }
     }
+    // the nodes in the component's frame: (xp, yp) = (xp0 + ox ax + oy bx, yp0 + ox ay + oy by)
+    // with (ax, ay), (bx, by) the pixel axes mapped and rotated once
     const float a1 = (float)im.aff[1], a2 = (float)im.aff[2], a4 = (float)im.aff[4], a5 = (float)im.aff[5];
+    const float xp0 = fmaf(dxc, c.cs, dyc * c.sn), yp0 = fmaf(dyc, c.cs, -dxc * c.sn);
+    const float ax = fmaf(a1, c.cs, a4 * c.sn), ay = fmaf(a4, c.cs, -a1 * c.sn);
+    const float bx = fmaf(a2, c.cs, a5 * c.sn), by = fmaf(a5, c.cs, -a2 * c.sn);
     for (int ky = 0; ky < p.s; ++ky) {
         const float oy = p.node_o[ky];
+        const float xr = fmaf(oy, bx, xp0), yr = fmaf(oy, by, yp0);
         for (int kx = 0; kx < p.s; ++kx) {
             const float ox = p.node_o[kx];
-            sersic_dI(c, dxc + fmaf(a1, ox, a2 * oy), dyc + fmaf(a4, ox, a5 * oy),
-                      p.node_w[kx] * p.node_w[ky], acc);
+            sersic_dI_r(c, fmaf(ox, ax, xr), fmaf(ox, ay, yr), p.node_w[kx] * p.node_w[ky], acc);
         }
     }
 }
