@@ -236,9 +236,10 @@ def class_rooflines(spec, prob, kt, phases, per_call=(1, 1), n_obj=None):
     psf_cols = sum(img_flop[int(m["image"])] * sum(1 for q in m["par"] if q >= 0)
                    for m in spec.get("psf_models", []))
     pair_flop = float(pair_flop_per_sub(spec).sum())
+    pair_bytes = float(pair_bytes_per_sub(spec).sum())
     n_fwd = kt.get("conv_fwd", (0.0, 0))[1] / per_call[0] if n_obj is None else n_obj
     n_adj = kt.get("conv_adj", (0.0, 0))[1] / per_call[1]
-    models = {"pairs": (pair_flop * phases, PEAK_FP64_TFLOPS, "k_pair / k_gram4 (FP64 MFMA)")}
+    models = {}
     if conv_mode == 0:       # the direct-convolution counts do not price an FFT convolution
         models["conv_jcol"] = ((float(flop.sum()) + psf_cols) * phases, PEAK_FP32_VALU_TFLOPS,
                                "k_conv<P,JCOL> (2-D)")
@@ -246,12 +247,16 @@ def class_rooflines(spec, prob, kt, phases, per_call=(1, 1), n_obj=None):
                               "k_conv<P,FWD,%s>" % ("double" if fp64 else "float"))
         models["conv_adj"] = (fwd * n_adj, PEAK_FP32_VALU_TFLOPS, "k_conv<P,ADJ>")
     out = {}
+    ms_p = kt.get("pairs", (0.0, 0))[0]
+    if ms_p > 0 and pair_flop > 0:
+        out["pairs"] = dict(pair_roof(pair_flop * phases, pair_bytes * phases, ms_p, "k_pair / k_gram4 (FP64 MFMA)"),
+                            ms_total=ms_p, traffic=None)
     for cls, (fl, peak, name) in models.items():
         ms = kt.get(cls, (0.0, 0))[0]
         if ms <= 0 or fl <= 0:
             continue
         ach = fl / (ms * 1e-3) / 1e12
-        out[cls] = {"bound": "alu" if cls != "pairs" else "mfma", "kernel": name, "achieved": ach, "peak": peak,
+        out[cls] = {"bound": "alu", "kernel": name, "achieved": ach, "peak": peak,
                     "unit": "TFLOP/s", "frac": ach / peak, "ms_total": ms, "traffic": None}
     dom = max(out, key=lambda k: out[k]["ms_total"]) if out else None
     return (out[dom] if dom else None), out
@@ -276,6 +281,37 @@ def pair_flop_per_sub(spec):
             npix = max(0, min(wa[2], wb[2]) - max(wa[0], wb[0])) * max(0, min(wa[3], wb[3]) - max(wa[1], wb[1]))
             out[spec["images"][ia]["sub"]] += 2.0 * npix * (na * (na + 1) / 2 if a == b else na * nb)
     return out
+
+
+def pair_bytes_per_sub(spec):
+    """Algorithmic HBM bytes of each sub-problem's J^T W J: every stored Jacobian entry and
+    every weight of the output windows read once (4 B each)."""
+    ent, _ = jac_entries_per_sub(spec)
+    px = np.zeros(len(spec["subs"]))
+    seen = set()
+    for c in spec["comps"]:
+        im = spec["images"][c["image"]]
+        key = (c["image"], output_window(c, im))
+        if key in seen or not any(q >= 0 for q in c["par"]):
+            continue
+        seen.add(key)
+        y0, x0, y1, x1 = key[1]
+        px[im["sub"]] += max(0, y1 - y0) * max(0, x1 - x0)
+    return 4.0 * (ent + px)
+
+
+def pair_roof(flop, nbytes, ms, kernel):
+    """Roofline of the J^T W J class: bound by whichever of the FP64 MFMA peak and the HBM
+    bandwidth its algorithmic FLOP and bytes take longer on; frac against that roof."""
+    hbm = nbytes / (PEAK_HBM_GBS * 1e9) > flop / (PEAK_FP64_TFLOPS * 1e12)
+    sec = ms * 1e-3
+    if hbm:
+        ach = nbytes / sec / 1e9 if sec > 0 else 0.0
+        return {"bound": "hbm", "kernel": kernel, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes": nbytes, "flop": flop}
+    ach = flop / sec / 1e12 if sec > 0 else 0.0
+    return {"bound": "mfma", "kernel": kernel, "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP64_TFLOPS, "algorithmic_bytes": nbytes, "flop": flop}
 
 
 RENDER64_FLOP_PER_NODE = 73.0   # 47 FP64 operations per Sersic node, 26 of them FMAs (2 FLOP)
@@ -453,14 +489,16 @@ def run_cutouts(args, torch, apx, synth):
     # each iteration (need_jac), for the algorithmic FLOP count of the Jacobian phases
     ren_sub, fwd_sub = objective_flop_per_sub(spec)
     pair_sub = pair_flop_per_sub(spec)
+    pbyte_sub = pair_bytes_per_sub(spec)
     th_e, st_e = prob.lm_init(spec["theta_init"], dd, ww)
-    flop_jac = ent_sep = flop_fft = flop_ren = flop_fwd = flop_pair = 0.0
+    flop_jac = ent_sep = flop_fft = flop_ren = flop_fwd = flop_pair = byte_pair = 0.0
     for _ in range(args.steps):
         need = prob.lm_state(st_e)["need_jac"] != 0
         flop_jac += float(flop_2d_sub[need].sum())
         ent_sep += float(ent_sep_sub[need].sum())
         flop_fft += float(fft_flop_sub[need].sum())
         flop_pair += float(pair_sub[need].sum())
+        byte_pair += float(pbyte_sub[need].sum())
         prob.lm_step(dd, ww, th_e, st_e)
         ev = np.isfinite(prob.lm_state(st_e)["chi2_trial"])     # trials whose objective ran
         flop_ren += float(ren_sub[ev].sum())
@@ -540,7 +578,8 @@ def run_cutouts(args, torch, apx, synth):
                            "k_render64 (FP64 trial render; %g FLOP per Sersic node)" % RENDER64_FLOP_PER_NODE,
                            timed=True),
         "conv_fwd": cls_roof(flop_fwd, ko["conv_fwd"][0], PEAK_FP64_TFLOPS, "k_conv<P,FWD,double> (FP64 objective)"),
-        "pairs": cls_roof(flop_pair, ko["pairs"][0], PEAK_FP64_TFLOPS, "k_gram4 / k_pair (FP64 MFMA)", "mfma"),
+        "pairs": dict(pair_roof(flop_pair, byte_pair, ko["pairs"][0], "k_gram4 / k_pair (FP64 MFMA)"),
+                      ms_per_step=ko["pairs"][0] / max(1, args.steps), traffic=None, timed_region=False),
     }
     per_class["conv_jcol"].update({"ms_per_phase": jcol_ms / max(1, args.steps),
                                    "flop_per_phase": flop_jac / max(1, args.steps), "launch_groups": jcol_launches})
