@@ -252,32 +252,50 @@ __global__ __launch_bounds__(256) void k_gram4(Plan p, const DPair* __restrict__
 #pragma unroll
     for (int q = 0; q < NP; ++q) acc[q] = 0.0;
     const int nxs = (pr.x1 - pr.x0 + KC - 1) / KC;
-    for (int st = it.s0 + wv; st < it.s1; st += 4) {
+    // the wave's 16-pixel chunks, in order: chunk h of stages it.s0 + wv, + 4, + 8, ...; the
+    // loads of the next chunk are issued before the MFMAs of the current one
+    constexpr int NH = KC / 16;
+    auto fetch = [&](int st, int h, float (&bv)[NT], float& wf, bool& in) {
         const int row = pr.y0 + st / nxs;
-        const int xs = pr.x0 + (st - (st / nxs) * nxs) * KC;
+        const int x = pr.x0 + (st - (st / nxs) * nxs) * KC + 16 * h + pxl;
+        in = x < pr.x1;
+        const int xc = in ? x : pr.x1 - 1;
+        const long long grow = (long long)(row - G.oy0) * G.ow + xc;
+        wf = weight[pix_off + (long long)row * imW + xc];
 #pragma unroll
-        for (int h = 0; h < KC / 16; ++h) {
-            const int x = xs + 16 * h + pxl;
-            const bool in = x < pr.x1;
-            const int xc = in ? x : pr.x1 - 1;
-            const long long grow = (long long)(row - G.oy0) * G.ow + xc;
-            const float wf = weight[pix_off + (long long)row * imW + xc];
-            const double w = in ? (double)wf : 0.0;
-            double b[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const float v = Jg[coff[t] + grow];
-                b[t] = (in && cval[t]) ? (double)v : 0.0;
-            }
-            int q = 0;
-#pragma unroll
-            for (int ta = 0; ta < NT; ++ta) {
-                const double a = b[ta] * w;
-#pragma unroll
-                for (int tb = ta; tb < NT; ++tb, ++q)
-                    acc[q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b[tb], acc[q], 0, 0, 0);
-            }
+        for (int t = 0; t < NT; ++t) bv[t] = Jg[coff[t] + grow];
+    };
+    float bc[NT], wc = 0.f;
+    bool inc = false;
+    int st = it.s0 + wv, h = 0;
+    if (st < it.s1) fetch(st, 0, bc, wc, inc);
+    while (st < it.s1) {
+        int st2 = st, h2 = h + 1;
+        if (h2 == NH) {
+            h2 = 0;
+            st2 += 4;
         }
+        float bn[NT], wn = 0.f;
+        bool inn = false;
+        if (st2 < it.s1) fetch(st2, h2, bn, wn, inn);
+        const double w = inc ? (double)wc : 0.0;
+        double b[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) b[t] = (inc && cval[t]) ? (double)bc[t] : 0.0;
+        int q = 0;
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta) {
+            const double a = b[ta] * w;
+#pragma unroll
+            for (int tb = ta; tb < NT; ++tb, ++q)
+                acc[q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b[tb], acc[q], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bc[t] = bn[t];
+        wc = wn;
+        inc = inn;
+        st = st2;
+        h = h2;
     }
     // fold the four blocks of each wave, then the four waves in order
     __shared__ double red[4][NP * 16];
