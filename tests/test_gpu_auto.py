@@ -110,3 +110,21 @@ def test_auto_lm_converges_to_the_oracle_fit(apx):
         A, g, _ = oracle.jtwj(spec, to, spec["data"], spec["weight"], s)
         assert float(g @ np.linalg.solve(A, g)) < 1e-6, ("oracle not converged", s)
     cases.assert_fit_parity(spec, tg, to, spec["name"])
+
+
+def test_auto_fp32_objective_model(apx, spec):
+    """FP32 objective in the automatic mode: the model convolution itself is a job of the
+    FP32 kinds and takes FFT tiles where the rule prices them cheaper."""
+    P, d, w = _problem(apx, spec, objective=1)
+    assert P.tile_shapes(0)[4] >= 1, P.tile_shapes(0)
+    th = spec["theta_init"]
+    m = P.split(P.render(th))
+    for k in range(len(spec["images"])):
+        mo = oracle.model_image(spec, th, k)
+        mk = m[k].astype(np.float64)
+        tol = 1e-5 * np.abs(mo) + 1e-6 * np.max(np.abs(mo))
+        assert np.all(np.abs(mk - mo) <= tol), (k, float(np.max(np.abs(mk - mo) / tol)))
+    c2 = P.chi2(th, d, w).cpu().numpy()
+    c2o = oracle.chi2(spec, th, spec["data"], spec["weight"])
+    assert np.allclose(c2, c2o, rtol=1e-4), (c2, c2o)
+    P.check()
