@@ -40,9 +40,10 @@ __host__ __device__ constexpr int shape_tw(int s, int P) {
 
 // Workgroups of a launch are dealt to the XCDs round-robin (block b to XCD b % 8).
 // Block b takes logical item xcd_item(b, n): every XCD then owns a contiguous range of
-// items, so items that run at the same time on one XCD (neighbouring convolution tiles,
-// the tile pairs of one pixel slice) share their global reads in that XCD's L2.  The map
-// is a bijection on [0, n) for every n.
+// items, so items that run at the same time on one XCD (neighbouring convolution tiles, the
+// columns of one group, which read the same weights and residuals in their epilogues, the
+// tile pairs of one pixel slice) share their global reads in that XCD's L2.  The map is a
+// bijection on [0, n) for every n.
 __device__ __forceinline__ int xcd_item(int b, int n) {
     const int x = b % N_XCD, q = n / N_XCD, r = n % N_XCD;
     return x * q + (x < r ? x : r) + b / N_XCD;
