@@ -183,6 +183,18 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
         double c2 = 0.0, swr = 0.0, sw = 0.0;
         if (yok) {
             const long long rowpix = im.pix_off + (long long)yc * im.Wc;
+            // the row's weights and data first: their loads overlap instead of following
+            // one another
+            float wv[CV_R], dv[CV_R];
+#pragma unroll
+            for (int r = 0; r < CV_R; ++r) {
+                const int x = xb + r * sx;
+                wv[r] = dv[r] = 0.f;
+                if (io.data && r < nq && x < xend) {
+                    wv[r] = io.weight[rowpix + x / up];
+                    dv[r] = io.data[rowpix + x / up];
+                }
+            }
 #pragma unroll
             for (int r = 0; r < CV_R; ++r) {
                 const int x = xb + r * sx;
@@ -191,8 +203,8 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
                     const long long pix = rowpix + x / up;
                     if (io.out) io.out[pix] = (float)m;
                     if (io.data) {
-                        const double w = (double)io.weight[pix];
-                        const double rr = (double)io.data[pix] - (double)m;
+                        const double w = (double)wv[r];
+                        const double rr = (double)dv[r] - (double)m;
                         c2 += w * rr * rr;
                         swr += w * rr;
                         sw += w;
@@ -223,6 +235,16 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
             const int ow = jb.out_w / up;
             const long long orow = (long long)(yc - jb.out_y0 / up) * ow - jb.out_x0 / up;
             const long long rowpix = im.pix_off + (long long)yc * im.Wc;
+            float wv[CV_R], rv[CV_R];                   // loads first, as above
+#pragma unroll
+            for (int r = 0; r < CV_R; ++r) {
+                const int x = xb + r * sx;
+                wv[r] = rv[r] = 0.f;
+                if (io.weight && r < nq && x < xend) {
+                    wv[r] = io.weight[rowpix + x / up];
+                    rv[r] = p.rbuf[rowpix + x / up];
+                }
+            }
 #pragma unroll
             for (int r = 0; r < CV_R; ++r) {
                 const int x = xb + r * sx;
@@ -230,8 +252,8 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
                     const int xc = x / up;
                     out[orow + xc] = acc[r];
                     if (io.weight) {
-                        const double wj = (double)io.weight[rowpix + xc] * (double)acc[r];
-                        s1 += wj * (double)p.rbuf[rowpix + xc];
+                        const double wj = (double)wv[r] * (double)acc[r];
+                        s1 += wj * (double)rv[r];
                         s2 += wj;
                     }
                 }
@@ -375,15 +397,27 @@ __global__ __launch_bounds__(256) void k_conv_sep(Plan p, const ConvJob* __restr
     float* __restrict__ out = io.out + jb.out_off + (long long)it.ch * jb.out_cs;
     double s1 = 0.0, s2 = 0.0;
     if (x < jb.out_x0 + jb.out_w) {
+        // the column's weights and residuals first: their loads overlap instead of following
+        // one another
+        float wv[CV_R], rv[CV_R];
+#pragma unroll
+        for (int q = 0; q < CV_R; ++q) {
+            const int y = oy0 + rb * CV_R + q;
+            wv[q] = rv[q] = 0.f;
+            if (io.weight && y < jb.out_y0 + jb.out_h) {
+                const long long pix = im.pix_off + (long long)y * im.Wc + x;
+                wv[q] = io.weight[pix];
+                rv[q] = p.rbuf[pix];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < CV_R; ++q) {
             const int y = oy0 + rb * CV_R + q;
             if (y < jb.out_y0 + jb.out_h) {
-                const long long rowpix = im.pix_off + (long long)y * im.Wc;
                 out[(long long)(y - jb.out_y0) * jb.out_w + (x - jb.out_x0)] = acc[q];
                 if (io.weight) {
-                    const double wj = (double)io.weight[rowpix + x] * (double)acc[q];
-                    s1 += wj * (double)p.rbuf[rowpix + x];
+                    const double wj = (double)wv[q] * (double)acc[q];
+                    s1 += wj * (double)rv[q];
                     s2 += wj;
                 }
             }

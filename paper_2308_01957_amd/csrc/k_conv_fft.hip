@@ -22,6 +22,7 @@ namespace apx {
 constexpr int FT = FFT_T;                 // 128
 constexpr int FTP = FT + 1;               // padded LDS row
 constexpr int FFT_THREADS = 1024;
+constexpr int EPI_B = 4;                  // epilogue elements per thread whose loads go out together
 static_assert(FT == 128, "the 16 x 8 decomposition below is for 128-point transforms");
 
 struct cf { float x, y; };
@@ -191,7 +192,13 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
     load_twiddles(p, tw);
     const int P = im.P, c = (P - 1) / 2, V = FT - P + 1;
 
-    // ---- stage both halves: element (ly, lx) = input (oy - c + ly, ox - c + lx)
+    // ---- stage both halves: element (ly, lx) = input (oy - c + ly, ox - c + lx).  Every
+    // thread issues all its global loads (NPT per half) before its first LDS store, so their
+    // latencies overlap instead of following one another.
+    constexpr int NPT = FT * FT / FFT_THREADS;
+    static_assert(NPT * FFT_THREADS == FT * FT, "whole elements per thread");
+    float hv[2][NPT];
+#pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int itx = half_item[h];
         const ConvItem it = items[itx < 0 ? pr.x : itx];
@@ -200,36 +207,70 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
         const float* in = nullptr;
         if constexpr (KIND != CONV_ADJ) in = io.in + jb.in_off + (long long)it.ch * jb.in_cs;
         const int iy1 = jb.in_y0 + jb.in_h, ix1 = jb.in_x0 + jb.in_w;
-        for (int e = threadIdx.x; e < FT * FT; e += FFT_THREADS) {
-            const int ly = e >> 7, lx = e & 127;
-            const int y = iy_base + ly, x = ix_base + lx;
-            float val = 0.f;
-            if (itx >= 0) {
-                if constexpr (KIND == CONV_ADJ) {
-                    if (y >= 0 && y < im.H && x >= 0 && x < im.W) {
-                        const long long pix = im.pix_off + (long long)y * im.Wc + x;
-                        val = io.seed ? io.seed[pix] : -2.f * io.weight[pix] * p.rbuf[pix];
+        // offsets within one image or one input plane fit in 32 bits
+        if constexpr (KIND == CONV_ADJ) {
+            // the seed, or -2 w r, on the image (zero elsewhere)
+            const float* wimg = io.weight + im.pix_off;
+            const float* rimg = p.rbuf + im.pix_off;
+            const float* simg = io.seed ? io.seed + im.pix_off : nullptr;
+            float rv[NPT];
+            unsigned okm = 0;
+#pragma unroll
+            for (int q = 0; q < NPT; ++q) {
+                const int e = (int)threadIdx.x + FFT_THREADS * q;
+                const int y = iy_base + (e >> 7), x = ix_base + (e & 127);
+                const bool ok = itx >= 0 && y >= 0 && y < im.H && x >= 0 && x < im.W;
+                const int pix = y * im.Wc + x;
+                hv[h][q] = 0.f;
+                rv[q] = 0.f;
+                if (ok) {
+                    okm |= 1u << q;
+                    if (simg) {
+                        hv[h][q] = simg[pix];
+                    } else {
+                        hv[h][q] = wimg[pix];
+                        rv[q] = rimg[pix];
                     }
-                } else {
-                    if (y >= jb.in_y0 && y < iy1 && x >= jb.in_x0 && x < ix1)
-                        val = in[(long long)(y - jb.in_y0) * jb.in_w + (x - jb.in_x0)];
                 }
             }
-            cf& s = sm[ly * FTP + lx];
-            if (h == 0) s.x = val;
-            else s.y = val;
+            if (!simg) {
+#pragma unroll
+                for (int q = 0; q < NPT; ++q)
+                    if ((okm >> q) & 1u) hv[h][q] = -2.f * hv[h][q] * rv[q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NPT; ++q) {
+                const int e = (int)threadIdx.x + FFT_THREADS * q;
+                const int y = iy_base + (e >> 7), x = ix_base + (e & 127);
+                float val = 0.f;
+                if (itx >= 0 && y >= jb.in_y0 && y < iy1 && x >= jb.in_x0 && x < ix1)
+                    val = in[(y - jb.in_y0) * jb.in_w + (x - jb.in_x0)];
+                hv[h][q] = val;
+            }
         }
     }
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        const int e = (int)threadIdx.x + FFT_THREADS * q;
+        sm[(e >> 7) * FTP + (e & 127)] = {hv[0][q], hv[1][q]};
+    }
+    // the stamp spectrum's values for this thread's elements, loaded now so that their
+    // latency hides behind the forward transform
+    const int slot = KIND == CONV_ADJ ? 1 : 0;
+    const float2* Kf = p.fft_spec + im.fft_off + (long long)slot * FT * FT;
+    float2 kv[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) kv[q] = Kf[(int)threadIdx.x + FFT_THREADS * q];
     __syncthreads();
     fft2d(sm, tw);
 
     // ---- times the stamp spectrum, conjugated for the inverse
-    const int slot = KIND == CONV_ADJ ? 1 : 0;
-    const float2* Kf = p.fft_spec + im.fft_off + (long long)slot * FT * FT;
-    for (int e = threadIdx.x; e < FT * FT; e += FFT_THREADS) {
-        const float2 kv = Kf[e];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        const int e = (int)threadIdx.x + FFT_THREADS * q;
         cf& s = sm[(e >> 7) * FTP + (e & 127)];
-        const cf m = cmul(s, {kv.x, kv.y});
+        const cf m = cmul(s, {kv[q].x, kv[q].y});
         s = {m.x, -m.y};
     }
     __syncthreads();
@@ -248,19 +289,36 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         if constexpr (KIND == CONV_FWD) {
             const float sky = (float)p.sky_val[jb.image];
-            for (int e = threadIdx.x; e < bh * bw; e += FFT_THREADS) {
-                const int dy = e / bw, dx = e - dy * bw;
-                const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
-                const float m = (h == 0 ? s.x : -s.y) * scale + sky;
-                const long long pix = im.pix_off + (long long)(oy + dy) * im.Wc + (ox + dx);
-                if (io.out) io.out[pix] = m;
-                if (io.data) {
-                    const double w = (double)io.weight[pix];
-                    const double rr = (double)io.data[pix] - (double)m;
-                    a0 += w * rr * rr;
-                    a1 += w * rr;
-                    a2 += w;
-                    p.rbuf[pix] = (float)rr;
+            for (int e0 = threadIdx.x; e0 < bh * bw; e0 += EPI_B * FFT_THREADS) {
+                float wv[EPI_B], dv[EPI_B];
+#pragma unroll
+                for (int u = 0; u < EPI_B; ++u) {          // the batch's loads first
+                    const int e = e0 + u * FFT_THREADS;
+                    wv[u] = dv[u] = 0.f;
+                    if (io.data && e < bh * bw) {
+                        const int dy = e / bw, dx = e - dy * bw;
+                        const long long pix = im.pix_off + (long long)(oy + dy) * im.Wc + (ox + dx);
+                        wv[u] = io.weight[pix];
+                        dv[u] = io.data[pix];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < EPI_B; ++u) {
+                    const int e = e0 + u * FFT_THREADS;
+                    if (e >= bh * bw) break;
+                    const int dy = e / bw, dx = e - dy * bw;
+                    const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
+                    const float m = (h == 0 ? s.x : -s.y) * scale + sky;
+                    const long long pix = im.pix_off + (long long)(oy + dy) * im.Wc + (ox + dx);
+                    if (io.out) io.out[pix] = m;
+                    if (io.data) {
+                        const double w = (double)wv[u];
+                        const double rr = (double)dv[u] - (double)m;
+                        a0 += w * rr * rr;
+                        a1 += w * rr;
+                        a2 += w;
+                        p.rbuf[pix] = (float)rr;
+                    }
                 }
             }
             if (io.data) {
@@ -275,17 +333,33 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
             }
         } else if constexpr (KIND == CONV_JCOL) {
             float* __restrict__ out = io.out + jb.out_off + (long long)it.ch * jb.out_cs;
-            for (int e = threadIdx.x; e < bh * bw; e += FFT_THREADS) {
-                const int dy = e / bw, dx = e - dy * bw;
-                const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
-                const float v = (h == 0 ? s.x : -s.y) * scale;
-                const int y = oy + dy, x = ox + dx;
-                out[(long long)(y - jb.out_y0) * jb.out_w + (x - jb.out_x0)] = v;
-                if (io.weight) {
-                    const long long pix = im.pix_off + (long long)y * im.Wc + x;
-                    const double wj = (double)io.weight[pix] * (double)v;
-                    a0 += wj * (double)p.rbuf[pix];
-                    a1 += wj;
+            for (int e0 = threadIdx.x; e0 < bh * bw; e0 += EPI_B * FFT_THREADS) {
+                float wv[EPI_B], rv[EPI_B];
+#pragma unroll
+                for (int u = 0; u < EPI_B; ++u) {          // the batch's loads first
+                    const int e = e0 + u * FFT_THREADS;
+                    wv[u] = rv[u] = 0.f;
+                    if (io.weight && e < bh * bw) {
+                        const int dy = e / bw, dx = e - dy * bw;
+                        const long long pix = im.pix_off + (long long)(oy + dy) * im.Wc + (ox + dx);
+                        wv[u] = io.weight[pix];
+                        rv[u] = p.rbuf[pix];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < EPI_B; ++u) {
+                    const int e = e0 + u * FFT_THREADS;
+                    if (e >= bh * bw) break;
+                    const int dy = e / bw, dx = e - dy * bw;
+                    const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
+                    const float v = (h == 0 ? s.x : -s.y) * scale;
+                    const int y = oy + dy, x = ox + dx;
+                    out[(long long)(y - jb.out_y0) * jb.out_w + (x - jb.out_x0)] = v;
+                    if (io.weight) {
+                        const double wj = (double)wv[u] * (double)v;
+                        a0 += wj * (double)rv[u];
+                        a1 += wj;
+                    }
                 }
             }
             if (io.weight) {
