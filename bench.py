@@ -374,7 +374,27 @@ def jac_entries_per_sub(spec, exclude_images=()):
 
 
 TILE_HW = [(32, 64), (16, 64), (32, 32), (16, 32)]   # the library's four direct tile shapes
-AUTO_FFT_PAIR_COST = 6.7e6                            # APX_AUTO_FFT_PAIR_COST
+# One FFT-tile item pair: a forward and an inverse 128 x 128 complex transform at the
+# conventional 5 N log2 N operations each (N = 128^2), and the spectrum product (6 per element)
+FFT_N = 128 * 128
+FFT_PAIR_FLOP = 2 * 5 * FFT_N * 14 + 6 * FFT_N
+
+
+def fft_pairs_per_sub(spec, fft_jobs):
+    """Transform pairs of the FFT-tile Jacobian jobs per sub-problem: each job has nch
+    channels of ceil(h / (129 - P)) ceil(w / (129 - P)) output blocks, and the items of one
+    image ride two per transform (its jobs' items are consecutive in the launch)."""
+    items = {}
+    for k, box, nch in fft_jobs:
+        im = spec["images"][k]
+        B = 129 - np.asarray(im["psf"]).shape[0]
+        y0, x0, y1, x1 = output_window({"box": box}, im)
+        items[k] = items.get(k, 0) + nch * (-(-(y1 - y0) // B)) * (-(-(x1 - x0) // B))
+    out = np.zeros(len(spec["subs"]))
+    for k, n in items.items():
+        out[spec["images"][k]["sub"]] += (n + 1) // 2
+    return out
+AUTO_FFT_PAIR_COST = 1.0e6                            # APX_AUTO_FFT_PAIR_COST
 
 
 def auto_fft_job(P, h, w, nch):
@@ -483,6 +503,7 @@ def run_cutouts(args, torch, apx, synth):
         y0, x0, y1, x1 = output_window({"box": box}, im)
         fft_flop_sub[im["sub"]] += nch * (y1 - y0) * (x1 - x0) * 2.0 * np.asarray(im["psf"]).shape[0] ** 2
     flop_2d_sub = np.where(sep_sub, 0.0, flop_sub - fft_flop_sub)
+    fft_pair_sub = fft_pairs_per_sub(spec, fft_jobs)
     ent_sep_sub = np.where(sep_sub, ent, 0.0)
 
     # eager pass over the same iterations, one at a time: which cutouts form a Jacobian in
@@ -491,12 +512,13 @@ def run_cutouts(args, torch, apx, synth):
     pair_sub = pair_flop_per_sub(spec)
     pbyte_sub = pair_bytes_per_sub(spec)
     th_e, st_e = prob.lm_init(spec["theta_init"], dd, ww)
-    flop_jac = ent_sep = flop_fft = flop_ren = flop_fwd = flop_pair = byte_pair = 0.0
+    flop_jac = ent_sep = flop_fft = flop_ren = flop_fwd = flop_pair = byte_pair = pairs_fft = 0.0
     for _ in range(args.steps):
         need = prob.lm_state(st_e)["need_jac"] != 0
         flop_jac += float(flop_2d_sub[need].sum())
         ent_sep += float(ent_sep_sub[need].sum())
         flop_fft += float(fft_flop_sub[need].sum())
+        pairs_fft += float(fft_pair_sub[need].sum())
         flop_pair += float(pair_sub[need].sum())
         byte_pair += float(pbyte_sub[need].sum())
         prob.lm_step(dd, ww, th_e, st_e)
@@ -577,15 +599,19 @@ def run_cutouts(args, torch, apx, synth):
         "render": cls_roof(flop_ren, kt["render"][0], PEAK_FP64_TFLOPS,
                            "k_render64 (FP64 trial render; %g FLOP per Sersic node)" % RENDER64_FLOP_PER_NODE,
                            timed=True),
+        "conv_fft": cls_roof(pairs_fft * FFT_PAIR_FLOP, fft_ms, PEAK_FP32_VALU_TFLOPS,
+                             "k_conv_fft<JCOL> (FFT-tile Jacobian convolutions; 5 N log2 N per 128^2 "
+                             "transform, two transforms and the spectrum product per item pair)", timed=True),
         "conv_fwd": cls_roof(flop_fwd, ko["conv_fwd"][0], PEAK_FP64_TFLOPS, "k_conv<P,FWD,double> (FP64 objective)"),
         "pairs": dict(pair_roof(flop_pair, byte_pair, ko["pairs"][0], "k_gram4 / k_pair (FP64 MFMA)"),
                       ms_per_step=ko["pairs"][0] / max(1, args.steps), traffic=None, timed_region=False),
     }
     per_class["conv_jcol"].update({"ms_per_phase": jcol_ms / max(1, args.steps),
                                    "flop_per_phase": flop_jac / max(1, args.steps), "launch_groups": jcol_launches})
-    # the dominant class: the larger of the two timed in the timed region (every other class
+    per_class["conv_fft"].update({"pairs_per_phase": pairs_fft / max(1, args.steps), "jobs": len(fft_jobs)})
+    # the dominant class: the largest of those timed in the timed region (every other class
     # takes less time)
-    dom = max(("conv_jcol", "render"), key=lambda k: per_class[k]["ms_per_step"])
+    dom = max(("conv_jcol", "render", "conv_fft"), key=lambda k: per_class[k]["ms_per_step"])
     if mode == 1:            # FFT mode reports the Jacobian's direct-equivalent rate
         dom = "conv_jcol"
 

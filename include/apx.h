@@ -141,7 +141,7 @@ typedef int32_t apx_status;
  * ceil(h / TH) ceil(w / TW) (TH TW (P^2 + 10) + 8 (TH + P - 1)(TW + P - 1) + 3000); FFT
  * when strictly cheaper.  The choice depends on the geometry only, not on timings. */
 #define APX_CONV_AUTO 3
-#define APX_AUTO_FFT_PAIR_COST 6.7e6
+#define APX_AUTO_FFT_PAIR_COST 1.0e6
 
 /* Sub-pixel re-centring (§2.1.3).  With shift != APX_SHIFT_NONE every Sersic component
  * is sampled (and pixel-integrated) with its centre moved to the centre of the nearest

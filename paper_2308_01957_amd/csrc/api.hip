@@ -369,10 +369,12 @@ static std::array<double, 4> tile_costs(apx_ctx* C, int key, int P) {
 // Automatic mode: a job of nch channels with an out_h x out_w output takes FFT tiles when
 // its pairs of 128 x 128 transforms (ceil(nch * blocks / 2), blocks of (129 - P)^2 outputs)
 // cost less than its direct tiles of the cheapest shape, both by the operation-count model
-// (tile_model) with one transform pair at APX_AUTO_FFT_PAIR_COST units (measured on MI355X:
-// a pair takes about as long as 5.0 direct 32 x 64 tiles at P = 25, 3.3 at P = 31).  The
-// model, not the autotuner's timings, decides, so the choice and the results do not depend
-// on timing noise.
+// (tile_model) with one transform pair at APX_AUTO_FFT_PAIR_COST units.  Calibrated on
+// MI355X: over a full Jacobian phase of 4096 cutouts a pair takes as long as 4.7e6 units of
+// direct tiles on average, but the whole LM iteration is fastest near 1e6, where all but the
+// smallest jobs take FFT tiles: the direct launches left behind are small and bound by their
+// latency, not by their operation count.  The model, not the autotuner's timings, decides,
+// so the choice and the results do not depend on timing noise.
 static bool auto_fft(int P, int out_h, int out_w, int nch) {
     double direct = 1e300;
     for (int s = 0; s < N_TILE_SHAPES; ++s)

@@ -38,15 +38,20 @@ __host__ __device__ constexpr int shape_tw(int s, int P) {
     return s == SHAPE_FFT ? FFT_T - P + 1 : (s == SHAPE_SEP ? SEP_TW : tile_tw(s));
 }
 
-// Workgroups of a launch are dealt to the XCDs round-robin (block b to XCD b % 8).
-// Block b takes logical item xcd_item(b, n): every XCD then owns a contiguous range of
-// items, so items that run at the same time on one XCD (neighbouring convolution tiles, the
-// columns of one group, which read the same weights and residuals in their epilogues, the
-// tile pairs of one pixel slice) share their global reads in that XCD's L2.  The map is a
-// bijection on [0, n) for every n.
-__device__ __forceinline__ int xcd_item(int b, int n) {
-    const int x = b % N_XCD, q = n / N_XCD, r = n % N_XCD;
-    return x * q + (x < r ? x : r) + b / N_XCD;
+// Workgroups of a launch are dealt to the XCDs round-robin (block b to XCD b % 8), each
+// with its own L2.  Block b takes logical item xcd_chunk_item(b, n): runs of XCD_CHUNK
+// consecutive items go to the XCDs in turn (run k to XCD k % 8), so a run's items (the
+// columns of one group, the tile pairs of one pixel slice) share their global reads in one
+// L2, while items that exit early (sub-problems that skip a phase) spread over the XCDs at
+// the grain of one run.  (Giving each XCD one contiguous eighth of the items shares more,
+// but left XCDs idle when the skipped sub-problems bunched up: 25 % slower LM iterations.)
+// The last n mod (8 XCD_CHUNK) items keep their order.  A bijection on [0, n) for every n.
+constexpr int XCD_CHUNK = 8;
+__device__ __forceinline__ int xcd_chunk_item(int b, int n) {
+    const int full = n / (N_XCD * XCD_CHUNK);
+    if (b >= full * N_XCD * XCD_CHUNK) return b;
+    const int x = b % N_XCD, s = b / N_XCD;
+    return ((s / XCD_CHUNK) * N_XCD + x) * XCD_CHUNK + s % XCD_CHUNK;
 }
 // Sub-pixel re-centring taps per component (written by k_prep): wx, wy, dwx/d delta_x,
 // dwy/d delta_y, each SHIFT_NT entries indexed by t + a (t = -a..a)

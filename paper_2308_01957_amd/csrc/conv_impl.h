@@ -60,7 +60,7 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
     __shared__ __attribute__((aligned(16))) T tile[LH * LW];
     __shared__ double red[NW][3];
 
-    const int item_idx = item_begin + xcd_item((int)blockIdx.x, (int)gridDim.x);
+    const int item_idx = item_begin + xcd_chunk_item((int)blockIdx.x, (int)gridDim.x);
     const ConvItem it = items[item_idx];
     const ConvJob jb = jobs[it.job];
     const DImage& im = p.images[jb.image];
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void k_conv_sep(Plan p, const ConvJob* __restr
     __shared__ __attribute__((aligned(16))) float hb[LH * TW];
     __shared__ double red[NW][2];
 
-    const int item_idx = item_begin + xcd_item((int)blockIdx.x, (int)gridDim.x);
+    const int item_idx = item_begin + xcd_chunk_item((int)blockIdx.x, (int)gridDim.x);
     const ConvItem it = items[item_idx];
     const ConvJob jb = jobs[it.job];
     const DImage& im = p.images[jb.image];

@@ -180,7 +180,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
     __shared__ cf sm[FT * FTP];
     __shared__ cf tw[FT];
     __shared__ double red[FFT_THREADS / 64];
-    const int2 pr = pairs[pair_begin + xcd_item((int)blockIdx.x, (int)gridDim.x)];
+    const int2 pr = pairs[pair_begin + xcd_chunk_item((int)blockIdx.x, (int)gridDim.x)];
     const int half_item[2] = {pr.x, pr.y};
     const ConvJob jb0 = jobs[items[pr.x].job];
     const DImage& im = p.images[jb0.image];

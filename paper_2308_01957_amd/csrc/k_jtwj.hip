@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     constexpr int NB = TM >= 64 ? 2 : 1;            // accumulators: NB x NB per wave
     __shared__ double As[TM][KC + 1];
     __shared__ double Bs[TM][KC + 1];
-    const PairItem it = items[xcd_item((int)blockIdx.x, (int)gridDim.x)];
+    const PairItem it = items[xcd_chunk_item((int)blockIdx.x, (int)gridDim.x)];
     const DPair pr = pairs[it.pair];
     if (lm && lm[pr.sub].need_jac == 0) return;
     // by value: the fields live in registers for the whole loop (no reloads through the
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_gram4(Plan p, const DPair* __restrict__
                                                const float* __restrict__ weight, const apx_lm_state* lm) {
     constexpr int NP = NT * (NT + 1) / 2;
     constexpr int KC = PAIR_KC;
-    const PairItem it = items[xcd_item((int)blockIdx.x, n_items)];
+    const PairItem it = items[xcd_chunk_item((int)blockIdx.x, n_items)];
     const DPair pr = pairs[it.pair];
     if (lm && lm[pr.sub].need_jac == 0) return;
     const DGroup G = p.groups[pr.g];

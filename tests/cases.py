@@ -329,10 +329,10 @@ def assert_fit_parity(spec, tg, to, label=""):
 
 
 def auto_cutouts():
-    """Automatic convolution mode on six cutouts of 56-160 px, P = 21-31, 1-3 Sersics each:
+    """Automatic convolution mode on six cutouts of 27-92 px, P = 21-29, 1-3 Sersics each:
     three Jacobian jobs priced cheaper on FFT tiles, one rank-one (Gaussian) stamp on the
-    two-pass kernel, two jobs on direct 2-D tiles."""
-    spec = synth.cutouts(seed_id=160, n_cutouts=6, side_range=(56, 160), p_range=(21, 31), max_comp=3)
+    two-pass kernel, two jobs on direct 2-D tiles (windows under 32 px)."""
+    spec = synth.cutouts(seed_id=160, n_cutouts=6, side_range=(24, 160), p_range=(21, 31), max_comp=3)
     spec["conv_mode"] = 3
     spec["name"] = "auto_cutouts6"
     return with_data(spec)
@@ -340,7 +340,7 @@ def auto_cutouts():
 
 def auto_fit():
     """Six bright single-Sersic cutouts of 64-160 px (P = 21-31) that the batched LM settles
-    in automatic convolution mode (FFT, two-pass and direct Jacobian jobs)."""
+    in automatic convolution mode (FFT and two-pass Jacobian jobs)."""
     spec = synth.cutouts(seed_id=171, n_cutouts=6, side_range=(64, 160), p_range=(21, 31), max_comp=1,
                          logie_range=(0.5, 1.5))
     spec["conv_mode"] = 3

@@ -147,13 +147,39 @@ def test_auto_fft_choice_matches_the_library_plan():
 
 def test_auto_fft_rule_by_hand():
     """Worked cases of the rule: a 256 x 256 job of 21 columns at P = 31 takes FFT tiles
-    (9 blocks of 98^2 per column, 95 transform pairs at 6.7e6 against 21 x 32 tiles of
-    32 x 64 at 2.04e6); a 40 x 40 job at P = 15 stays direct (one 115^2 block per column)."""
+    (9 blocks of 98^2 per column, 95 transform pairs at 1.0e6 against 21 x 32 tiles of
+    32 x 64 at 2.04e6 units); so does a 40 x 40 job of 7 columns at P = 15 (4 pairs against
+    7 x 3 tiles of 16 x 64 at 262360 units); a 32 x 32 job of one column at P = 15 stays
+    direct (one pair against one 32 x 32 tile at 260568 units)."""
     assert bench.auto_fft_job(31, 256, 256, 21)
-    assert not bench.auto_fft_job(15, 40, 40, 7)
+    assert bench.auto_fft_job(15, 40, 40, 7)
+    assert not bench.auto_fft_job(15, 32, 32, 1)
+    P = 15
+    assert 4 * bench.AUTO_FFT_PAIR_COST < 7 * 3 * (16 * 64 * (P * P + 10.0) + 8.0 * (16 + P - 1) * (64 + P - 1) + 3000.0)
+    assert 1 * bench.AUTO_FFT_PAIR_COST > 32 * 32 * (P * P + 10.0) + 8.0 * (32 + P - 1) * (32 + P - 1) + 3000.0
     P = 31
     direct = 21 * 32 * (32 * 64 * (P * P + 10.0) + 8.0 * (32 + P - 1) * (64 + P - 1) + 3000.0)
     assert ((21 * 9 + 1) // 2) * bench.AUTO_FFT_PAIR_COST < direct
+
+
+def test_fft_pairs_by_hand():
+    """Transform pairs of FFT-tile jobs: on a 200 x 200 image with P = 29 (blocks of 100^2
+    outputs) two jobs of 7 columns whose windows grow to 100 x 100 have 7 items each; the
+    image's 14 items ride two per transform: 7 pairs (not 4 + 4 job by job).  A 7-column job
+    reaching 114 x 78 pixels has 2 blocks per column (14 items); a second image's lone item
+    is a pair of its own."""
+    import numpy as np
+    spec = {"images": [dict(H=200, W=200, psf=np.ones((29, 29)), sub=0), dict(H=60, W=60, psf=np.ones((29, 29)), sub=1),
+                       dict(H=200, W=200, psf=np.ones((29, 29)), sub=2)],
+            "subs": [(0, 14), (14, 1), (15, 7)]}
+    jobs = [(0, (14, 14, 86, 86), 7), (0, (114, 114, 186, 186), 7), (1, (10, 10, 40, 40), 1),
+            (2, (100, 20, 200, 70), 7)]
+    assert bench.output_window({"box": jobs[0][1]}, spec["images"][0]) == (0, 0, 100, 100)
+    assert bench.output_window({"box": jobs[1][1]}, spec["images"][0]) == (100, 100, 200, 200)
+    assert bench.output_window({"box": jobs[3][1]}, spec["images"][2]) == (86, 6, 200, 84)
+    pairs = bench.fft_pairs_per_sub(spec, jobs)
+    assert list(pairs) == [7, 1, 7]
+    assert bench.FFT_PAIR_FLOP == 2 * 5 * 16384 * 14 + 6 * 16384
 
 
 def test_objective_flop_by_hand():
