@@ -71,44 +71,54 @@ __device__ __forceinline__ void dft_reg(cf (&x)[N]) {
 
 // 128-point forward FFTs of all 128 lines of the LDS tile; rows (dir 0: element e of line
 // l at l * FTP + e) or columns (dir 1: at e * FTP + l).  tw[m] = exp(-2 pi i m / 128).
-__device__ __forceinline__ void fft_lines(cf* sm, const cf* tw, int dir) {
+// Lanes of a wave take 64 consecutive lines at one position: with the odd row pitch FTP the
+// 64 addresses of every LDS access fall in distinct banks (two per bank for 8-byte
+// elements), for rows and columns alike.
+//
+// Pass A, in place: thread (line, n2), n2 < 8: 16-point DFT over n1 of x[n2 + 8 n1], times
+// W^(n2 k1).
+__device__ __forceinline__ void pass_a(cf* sm, const cf* tw, int dir) {
     const int t = threadIdx.x;
     const int ls = dir == 0 ? FTP : 1, es = dir == 0 ? 1 : FTP;
-    // Lanes of a wave take 64 consecutive lines at one position: with the odd row pitch FTP
-    // the 64 addresses of every LDS access fall in distinct banks (two per bank for 8-byte
-    // elements), for rows and columns alike.
-    {   // pass A: thread (line, n2), n2 < 8: 16-point DFT over n1 of x[n2 + 8 n1], times W^(n2 k1)
-        const int line = t & 127;
-        const int n2 = t >> 7;
-        cf* base = sm + line * ls;
-        cf x[16];
+    const int line = t & 127;
+    const int n2 = t >> 7;
+    cf* base = sm + line * ls;
+    cf x[16];
 #pragma unroll
-        for (int n1 = 0; n1 < 16; ++n1) x[n1] = base[(n2 + 8 * n1) * es];
-        dft_reg<16>(x);
+    for (int n1 = 0; n1 < 16; ++n1) x[n1] = base[(n2 + 8 * n1) * es];
+    dft_reg<16>(x);
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) base[(n2 + 8 * k1) * es] = cmul(x[k1], tw[(n2 * k1) & 127]);
+    for (int k1 = 0; k1 < 16; ++k1) base[(n2 + 8 * k1) * es] = cmul(x[k1], tw[(n2 * k1) & 127]);
+}
+// Pass B's inputs: thread (line, k1) for two k1 (k1 = t / 128 + 8 h, line = t mod 128); the
+// 8-point DFT over n2 of x[h] then gives X[k1 + 16 k2], k2 < 8.
+__device__ __forceinline__ void pass_b_load(const cf* sm, int dir, cf (&x)[2][8], int (&line)[2], int (&k1)[2]) {
+    const int t = threadIdx.x;
+    const int ls = dir == 0 ? FTP : 1, es = dir == 0 ? 1 : FTP;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int u = t + FFT_THREADS * h;                 // 0 .. 2047
+        line[h] = u & 127;
+        k1[h] = u >> 7;
+        const cf* base = sm + line[h] * ls;
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) x[h][n2] = base[(n2 + 8 * k1[h]) * es];
     }
+}
+__device__ __forceinline__ void fft_lines(cf* sm, const cf* tw, int dir) {
+    const int ls = dir == 0 ? FTP : 1, es = dir == 0 ? 1 : FTP;
+    pass_a(sm, tw, dir);
     __syncthreads();
-    {   // pass B: thread (line, k1) for two k1: 8-point DFT over n2 -> X[k1 + 16 k2]
-        cf x[2][8];
-        int line[2], k1[2];
+    cf x[2][8];
+    int line[2], k1[2];
+    pass_b_load(sm, dir, x, line, k1);
+    __syncthreads();
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int u = t + FFT_THREADS * h;                 // 0 .. 2047
-            line[h] = u & 127;
-            k1[h] = u >> 7;
-            const cf* base = sm + line[h] * ls;
+    for (int h = 0; h < 2; ++h) {
+        dft_reg<8>(x[h]);
+        cf* base = sm + line[h] * ls;
 #pragma unroll
-            for (int n2 = 0; n2 < 8; ++n2) x[h][n2] = base[(n2 + 8 * k1[h]) * es];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            dft_reg<8>(x[h]);
-            cf* base = sm + line[h] * ls;
-#pragma unroll
-            for (int k2 = 0; k2 < 8; ++k2) base[(k1[h] + 16 * k2) * es] = x[h][k2];
-        }
+        for (int k2 = 0; k2 < 8; ++k2) base[(k1[h] + 16 * k2) * es] = x[h][k2];
     }
     __syncthreads();
 }
@@ -255,25 +265,40 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
         const int e = (int)threadIdx.x + FFT_THREADS * q;
         sm[(e >> 7) * FTP + (e & 127)] = {hv[0][q], hv[1][q]};
     }
-    // the stamp spectrum's values for this thread's elements, loaded now so that their
-    // latency hides behind the forward transform
+    // the stamp spectrum at the elements this thread takes in the last pass of the forward
+    // transform (the column pass B: column t mod 128 at rows t / 128 + 8 h + 16 k2), loaded
+    // now so that their latency hides behind the transform
     const int slot = KIND == CONV_ADJ ? 1 : 0;
     const float2* Kf = p.fft_spec + im.fft_off + (long long)slot * FT * FT;
-    float2 kv[NPT];
+    float2 kv[2][8];
 #pragma unroll
-    for (int q = 0; q < NPT; ++q) kv[q] = Kf[(int)threadIdx.x + FFT_THREADS * q];
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2)
+            kv[h][k2] = Kf[((int)(threadIdx.x >> 7) + 8 * h + 16 * k2) * FT + (int)(threadIdx.x & 127)];
     __syncthreads();
-    fft2d(sm, tw);
 
-    // ---- times the stamp spectrum, conjugated for the inverse
+    // ---- forward transform: rows, then columns, whose results are multiplied by the stamp
+    // spectrum and conjugated for the inverse as they are stored
+    fft_lines(sm, tw, 0);
+    {
+        pass_a(sm, tw, 1);
+        __syncthreads();
+        cf x[2][8];
+        int line[2], k1[2];
+        pass_b_load(sm, 1, x, line, k1);
+        __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NPT; ++q) {
-        const int e = (int)threadIdx.x + FFT_THREADS * q;
-        cf& s = sm[(e >> 7) * FTP + (e & 127)];
-        const cf m = cmul(s, {kv[q].x, kv[q].y});
-        s = {m.x, -m.y};
+        for (int h = 0; h < 2; ++h) {
+            dft_reg<8>(x[h]);
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) {
+                const cf m = cmul(x[h][k2], {kv[h][k2].x, kv[h][k2].y});
+                sm[(k1[h] + 16 * k2) * FTP + line[h]] = {m.x, -m.y};
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     fft2d(sm, tw);
     const float scale = 1.f / (float)(FT * FT);     // real part of the inverse: x / N, imaginary: -y / N
 
