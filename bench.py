@@ -680,22 +680,16 @@ def run_cutouts(args, torch, apx, synth):
     torch.cuda.synchronize()
     cov_ms = (time.perf_counter() - t0) * 1e3
     mpix = _mpix(prob, spec, torch, 5)
-    # HBM bytes of the 2-D class: the counted bytes per algorithmic FLOP of the counter
-    # summary (same kernel sources, same tile shapes) times this run's FLOP per phase
-    # (the autotuner's choice among 2047 jobs varies a little from run to run; the counted
-    # run's tile mix is reported beside this run's)
-    if mode == 0:
-        kv = counted_record("conv_jcol_cutouts4096_hbm_counters.md", "k_conv<P,JCOL> (2-D, cutouts)")
-        if kv is not None:
-            per_class["conv_jcol"]["traffic"] = float(kv["bytes_per_flop"]) * flop_jac / max(1, args.steps)
-            per_class["conv_jcol"]["traffic_unit"] = "bytes/phase"
-            per_class["conv_jcol"]["traffic_from"] = {
-                "bytes_per_flop": float(kv["bytes_per_flop"]), "counted_tiles": json.loads(kv["jacobian_tiles"]),
-                "this_run_tiles": tile_choice(prob)["jacobian"]}
     kv = counted_record("render64_cutouts4096_hbm_counters.md", "k_render64 (cutouts)")
     if kv is not None:
         per_class["render"]["traffic"] = float(kv["bytes_per_flop"]) * flop_ren / max(1, args.steps)
         per_class["render"]["traffic_unit"] = "bytes/step"
+    # HBM bytes of the FFT-tile class: the counted bytes per transform pair of the counter
+    # summary (same kernel sources) times this run's pairs per step
+    kv = counted_record("conv_fft_cutouts4096_hbm_counters.md", "k_conv_fft<JCOL> (cutouts)")
+    if kv is not None and mode == 3:
+        per_class["conv_fft"]["traffic"] = float(kv["bytes_per_pair"]) * pairs_fft / max(1, args.steps)
+        per_class["conv_fft"]["traffic_unit"] = "bytes/step"
     roof = dict(per_class[dom])
     roof["class"] = dom
     rec = {

@@ -198,10 +198,11 @@ def test_objective_flop_by_hand():
 
 
 def test_cutouts_counted_traffic_follows_the_kernel_sources():
-    """The headline's HBM bytes per algorithmic FLOP come from the committed counter summary
-    only while the convolution kernel's sources hash to the recorded value."""
+    """The headline's HBM bytes per transform pair of its dominant class come from the
+    committed counter summary only while the FFT kernel's sources hash to the recorded
+    value."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "conv_jcol_cutouts4096_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", "conv_fft_cutouts4096_hbm_counters.md")
     kv = {}
     for line in open(path):
         if ":" in line and not line.startswith("|"):
@@ -210,11 +211,11 @@ def test_cutouts_counted_traffic_follows_the_kernel_sources():
     h = hashlib.sha256()
     for src in kv["sources"].split():
         h.update(open(os.path.join(ROOT, src), "rb").read())
-    got = bench.counted_record("conv_jcol_cutouts4096_hbm_counters.md", kv["kernel"])
+    got = bench.counted_record("conv_fft_cutouts4096_hbm_counters.md", kv["kernel"])
     if h.hexdigest() == kv["sources_sha256"]:
-        assert got is not None and float(got["bytes_per_flop"]) > 0
-        assert abs(float(got["bytes_per_flop"]) * float(got["flop"]) -
+        assert got is not None and float(got["bytes_per_pair"]) > 0
+        assert abs(float(got["bytes_per_pair"]) * float(got["pairs"]) -
                    float(got["read_bytes"]) - float(got["write_bytes"])) < 1e-5 * float(got["read_bytes"])
     else:
         assert got is None
-    assert bench.counted_record("conv_jcol_cutouts4096_hbm_counters.md", "k_conv<99,JCOL>") is None
+    assert bench.counted_record("conv_fft_cutouts4096_hbm_counters.md", "k_conv_fft<ADJ>") is None
