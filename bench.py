@@ -262,11 +262,38 @@ def class_rooflines(spec, prob, kt, phases, per_call=(1, 1), n_obj=None):
     return (out[dom] if dom else None), out
 
 
+GRAM4_MAX_COLS = 36          # column groups up to this width take the 4 x 4-block Gram kernel
+
+
+def gram_part_groups(spec):
+    """Column groups as the library forms them (the Sersic components of one image with the
+    same box share one, each point source has its own) that the 4 x 4-block Gram kernel
+    forms with themselves, and which therefore also take their columns' J^T W r and sum w J
+    there: (image, output window, columns) of groups of at most GRAM4_MAX_COLS columns."""
+    groups, order = {}, []
+    for i, c in enumerate(spec["comps"]):
+        n = sum(1 for q in c["par"] if q >= 0)
+        if n == 0:
+            continue
+        key = (c["image"], tuple(c["box"])) if int(c.get("type", 0)) == 0 else ("point", i)
+        if key not in groups:
+            groups[key] = [c["image"], output_window(c, spec["images"][c["image"]]), 0]
+            order.append(key)
+        groups[key][2] += n
+    out = []
+    for key in order:
+        k, w, n = groups[key]
+        if w[2] > w[0] and w[3] > w[1] and n <= GRAM4_MAX_COLS:
+            out.append((k, w, n))
+    return out
+
+
 def pair_flop_per_sub(spec):
     """J^T W J work of each sub-problem: 2 FLOP per pixel and column pair of the upper
     triangle, over the overlap of the output windows of every pair of column groups on one
     image (a component's free parameters form a group; the algorithmic count, whatever
-    the tiles pad)."""
+    the tiles pad); and, for the groups whose J^T W r and sum w J the Gram kernel forms
+    (gram_part_groups), 4 FLOP per Jacobian entry (w J, its product with r and two sums)."""
     groups = []
     for c in spec["comps"]:
         n = sum(1 for q in c["par"] if q >= 0)
@@ -280,12 +307,15 @@ def pair_flop_per_sub(spec):
                 continue
             npix = max(0, min(wa[2], wb[2]) - max(wa[0], wb[0])) * max(0, min(wa[3], wb[3]) - max(wa[1], wb[1]))
             out[spec["images"][ia]["sub"]] += 2.0 * npix * (na * (na + 1) / 2 if a == b else na * nb)
+    for k, w, n in gram_part_groups(spec):
+        out[spec["images"][k]["sub"]] += 4.0 * n * (w[2] - w[0]) * (w[3] - w[1])
     return out
 
 
 def pair_bytes_per_sub(spec):
     """Algorithmic HBM bytes of each sub-problem's J^T W J: every stored Jacobian entry and
-    every weight of the output windows read once (4 B each)."""
+    every weight of the output windows read once (4 B each), and the residual of each pixel
+    of the windows whose J^T W r the Gram kernel forms."""
     ent, _ = jac_entries_per_sub(spec)
     px = np.zeros(len(spec["subs"]))
     seen = set()
@@ -297,6 +327,8 @@ def pair_bytes_per_sub(spec):
         seen.add(key)
         y0, x0, y1, x1 = key[1]
         px[im["sub"]] += max(0, y1 - y0) * max(0, x1 - x0)
+    for k, w, n in gram_part_groups(spec):
+        px[spec["images"][k]["sub"]] += (w[2] - w[0]) * (w[3] - w[1])
     return 4.0 * (ent + px)
 
 

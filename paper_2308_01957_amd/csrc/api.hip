@@ -1025,6 +1025,13 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     }
     const int n_cols = (int)P->cols.size();
     const int n_groups = (int)P->groups.size();
+    // groups whose columns' J^T W r (sum w r J) and sum w J (the sky row of J^T W J) come from
+    // the 4 x 4-block Gram kernel, which forms their self-pair and reads each pixel's weight
+    // anyway, instead of from the convolution epilogues
+    auto gram_part = [&](int g) {
+        const DGroup& gr = P->groups[g];
+        return gr.type != GROUP_PSF && gr.oh > 0 && gr.ow > 0 && gr.ncols > 0 && gr.ncols <= 4 * GRAM4_MAX_T;
+    };
 
     // convolution jobs and items, sorted by (PSF size, tile shape): one launch per pair.
     // Each job takes the tile shape of least estimated cost (choose_shape).
@@ -1141,6 +1148,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             jb.out_h = im.up * gr.oh; jb.out_w = im.up * gr.ow;
             jb.image = gr.image;
             jb.group = g;
+            jb.gram_part = gram_part(g) ? 1 : 0;
             const bool psfg = gr.type == GROUP_PSF;
             P->jcol_jobs.push_back(jb);
             jp.push_back(im.P);
@@ -1183,7 +1191,8 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             // partials of the PSF list follow those of the main list in jcol_part
             const int first = pj >= 0 ? n_main_items + psf_item_begin[pj] : jcol_item_begin[g];
             for (int ch = 0; ch < gr.ncols; ++ch) {
-                for (int q = 0; q < per; ++q) P->col_idx.push_back(first + ch * per + q);
+                if (!gram_part(g))        // (the others' partials come from k_gram4)
+                    for (int q = 0; q < per; ++q) P->col_idx.push_back(first + ch * per + q);
                 P->col_seg.push_back((int)P->col_idx.size());
                 P->gcol_seg.push_back((int)(gr.gp_off + (long long)(ch + 1) * gr.ntiles));
             }
@@ -1273,7 +1282,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             P->gram_begin[t] = (int)P->gitems.size();
             for (PairItem it : gram_items[t]) {
                 it.out_off = outoff;
-                outoff += (long long)16 * t * (t + 1) / 2;
+                outoff += (long long)16 * (t * (t + 1) / 2 + t);     // tile pairs, then J^T W [r 1]
                 P->gitems.push_back(it);
             }
         }
@@ -1283,6 +1292,19 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     P->asrc_col = P->n_pairpart;
     P->asrc_gcol = P->asrc_col + 2LL * n_cols;
     P->asrc_img = P->asrc_gcol + n_cols;
+    if (P->asrc_img + 3LL * d->n_images > (long long)INT32_MAX)   // J^T W r sources are 32-bit indices
+        return fail(C, APX_E_INVALID, "problem too large: J^T W J partials exceed 2^31 entries");
+
+    // the 4 x 4-block Gram items of each group, and where each holds a column's J^T W r
+    // (comp 0) and sum w J (comp 1) over its K-slice: after the item's t (t + 1) / 2 tile-pair
+    // blocks, block ta = ci / 4 of the item's J^T W [r 1], entry (ci mod 4, comp)
+    std::vector<std::vector<int>> group_gitems(n_groups);
+    for (int i = 0; i < (int)P->gitems.size(); ++i) group_gitems[P->pairs[P->gitems[i].pair].g].push_back(i);
+    auto gram_src = [&](int gi, int ci, int comp) {
+        const PairItem& it = P->gitems[gi];
+        const int t = it.ta;
+        return it.out_off + 16LL * (t * (t + 1) / 2 + ci / 4) + 4 * (ci % 4) + comp;
+    };
 
     // A assembly: sources per upper entry (sub, a <= b) in a fixed order
     {
@@ -1351,8 +1373,13 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             for (int g = 0; g < n_groups; ++g) {
                 const DGroup& gr = P->groups[g];
                 if (gr.image != k || gr.oh <= 0 || gr.ow <= 0) continue;
-                for (int ch = 0; ch < gr.ncols; ++ch)
-                    add(im.sky_par, P->cols[gr.col_begin + ch].par, P->asrc_col + 2LL * (gr.col_begin + ch) + 1, 1);
+                for (int ch = 0; ch < gr.ncols; ++ch) {
+                    if (gram_part(g)) {
+                        for (int gi : group_gitems[g]) add(im.sky_par, P->cols[gr.col_begin + ch].par, gram_src(gi, ch, 1), 1);
+                    } else {
+                        add(im.sky_par, P->cols[gr.col_begin + ch].par, P->asrc_col + 2LL * (gr.col_begin + ch) + 1, 1);
+                    }
+                }
             }
             add(im.sky_par, im.sky_par, P->asrc_img + 3LL * k + 2, 1);
         }
@@ -1394,8 +1421,14 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         P->par_sky_off.assign(1, 0);
         for (int p = 0; p < d->n_par; ++p) {
             for (int c : pc[p]) {
-                const DGroup& gr = P->groups[P->cols[c].group];
-                if (gr.oh > 0 && gr.ow > 0) {
+                const int g = P->cols[c].group;
+                const DGroup& gr = P->groups[g];
+                if (gram_part(g)) {
+                    for (int gi : group_gitems[g]) {
+                        P->g_idx.push_back((int)gram_src(gi, c - gr.col_begin, 0));
+                        P->g_w.push_back(1.0);
+                    }
+                } else if (gr.oh > 0 && gr.ow > 0) {
                     P->g_idx.push_back((int)(P->asrc_col + 2LL * c));
                     P->g_w.push_back(1.0);
                 }

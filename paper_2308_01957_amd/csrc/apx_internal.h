@@ -140,7 +140,8 @@ struct ConvJob {
     int in_src;                               // input: 0 derivative images, 1 the model S
     int kslot[2];                             // stamp of channel 0 / 1 on live-PSF images:
                                               // 0 K, 1 dK/dn, 2 dK/dR_d
-    int pad_job;
+    int gram_part;                            // 1: the columns' sum w r J and sum w J come
+                                              // from k_gram4; the epilogue skips them
 };
 struct ConvItem { int job, ch, ty, tx; };
 

@@ -230,6 +230,7 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
     } else if constexpr (KIND == CONV_JCOL) {
         float* __restrict__ out = io.out + jb.out_off + (long long)it.ch * jb.out_cs;
         double s1 = 0.0, s2 = 0.0;
+        const bool epart = io.weight && !jb.gram_part;       // sum w r J and sum w J here
         if (yok) {
             // the column's plane is stored on the image pixels of the output box
             const int ow = jb.out_w / up;
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
             for (int r = 0; r < CV_R; ++r) {
                 const int x = xb + r * sx;
                 wv[r] = rv[r] = 0.f;
-                if (io.weight && r < nq && x < xend) {
+                if (epart && r < nq && x < xend) {
                     wv[r] = io.weight[rowpix + x / up];
                     rv[r] = p.rbuf[rowpix + x / up];
                 }
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
                 if (r < nq && x < xend) {
                     const int xc = x / up;
                     out[orow + xc] = acc[r];
-                    if (io.weight) {
+                    if (epart) {
                         const double wj = (double)wv[r] * (double)acc[r];
                         s1 += wj * (double)rv[r];
                         s2 += wj;
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
                 }
             }
         }
-        if (io.weight) {
+        if (epart) {
             s1 = conv_wave_sum(s1);
             s2 = conv_wave_sum(s2);
             if (lane == 0) { red[wv][0] = s1; red[wv][1] = s2; }
@@ -396,6 +397,7 @@ __global__ __launch_bounds__(256) void k_conv_sep(Plan p, const ConvJob* __restr
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float* __restrict__ out = io.out + jb.out_off + (long long)it.ch * jb.out_cs;
     double s1 = 0.0, s2 = 0.0;
+    const bool epart = io.weight && !jb.gram_part;           // sum w r J and sum w J here
     if (x < jb.out_x0 + jb.out_w) {
         // the column's weights and residuals first: their loads overlap instead of following
         // one another
@@ -404,7 +406,7 @@ __global__ __launch_bounds__(256) void k_conv_sep(Plan p, const ConvJob* __restr
         for (int q = 0; q < CV_R; ++q) {
             const int y = oy0 + rb * CV_R + q;
             wv[q] = rv[q] = 0.f;
-            if (io.weight && y < jb.out_y0 + jb.out_h) {
+            if (epart && y < jb.out_y0 + jb.out_h) {
                 const long long pix = im.pix_off + (long long)y * im.Wc + x;
                 wv[q] = io.weight[pix];
                 rv[q] = p.rbuf[pix];
@@ -415,7 +417,7 @@ __global__ __launch_bounds__(256) void k_conv_sep(Plan p, const ConvJob* __restr
             const int y = oy0 + rb * CV_R + q;
             if (y < jb.out_y0 + jb.out_h) {
                 out[(long long)(y - jb.out_y0) * jb.out_w + (x - jb.out_x0)] = acc[q];
-                if (io.weight) {
+                if (epart) {
                     const double wj = (double)wv[q] * (double)acc[q];
                     s1 += wj * (double)rv[q];
                     s2 += wj;
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(256) void k_conv_sep(Plan p, const ConvJob* __restr
             }
         }
     }
-    if (io.weight) {
+    if (epart) {
         s1 = conv_wave_sum(s1);
         s2 = conv_wave_sum(s2);
         if (lane == 0) { red[wv][0] = s1; red[wv][1] = s2; }

@@ -358,13 +358,14 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
             }
         } else if constexpr (KIND == CONV_JCOL) {
             float* __restrict__ out = io.out + jb.out_off + (long long)it.ch * jb.out_cs;
+            const bool epart = io.weight && !jb.gram_part;   // sum w r J and sum w J here
             for (int e0 = threadIdx.x; e0 < bh * bw; e0 += EPI_B * FFT_THREADS) {
                 float wv[EPI_B], rv[EPI_B];
 #pragma unroll
                 for (int u = 0; u < EPI_B; ++u) {          // the batch's loads first
                     const int e = e0 + u * FFT_THREADS;
                     wv[u] = rv[u] = 0.f;
-                    if (io.weight && e < bh * bw) {
+                    if (epart && e < bh * bw) {
                         const int dy = e / bw, dx = e - dy * bw;
                         const long long pix = im.pix_off + (long long)(oy + dy) * im.Wc + (ox + dx);
                         wv[u] = io.weight[pix];
@@ -380,14 +381,14 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
                     const float v = (h == 0 ? s.x : -s.y) * scale;
                     const int y = oy + dy, x = ox + dx;
                     out[(long long)(y - jb.out_y0) * jb.out_w + (x - jb.out_x0)] = v;
-                    if (io.weight) {
+                    if (epart) {
                         const double wj = (double)wv[u] * (double)v;
                         a0 += wj * (double)rv[u];
                         a1 += wj;
                     }
                 }
             }
-            if (io.weight) {
+            if (epart) {
                 a0 = fft_block_sum(a0, red);
                 a1 = fft_block_sum(a1, red);
                 if (threadIdx.x == 0) {

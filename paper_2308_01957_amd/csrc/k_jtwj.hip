@@ -222,7 +222,9 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
 // the tiles are loaded straight from J into registers (each reused by every pair it is in).
 // Waves take every fourth 32-pixel stage of the slice; at the end each wave folds its four
 // blocks (lanes xor 4, xor 8) and the four waves are added in order.  Against 16 x 16 tiles
-// this pads a group of 7k columns to a multiple of 4, not 16.
+// this pads a group of 7k columns to a multiple of 4, not 16.  Each tile is also contracted
+// with [r 1 0 0] (the pixel's residual, a one), giving the columns' J^T W r and sum w J (the
+// sky row of J^T W J) over the slice in NT more blocks, after the tile pairs.
 template <int NT>
 __global__ __launch_bounds__(256) void k_gram4(Plan p, const DPair* __restrict__ pairs,
                                                const PairItem* __restrict__ items, int n_items,
@@ -248,37 +250,42 @@ __global__ __launch_bounds__(256) void k_gram4(Plan p, const DPair* __restrict__
         cval[t] = ca < G.ncols;
         coff[t] = cval[t] ? (long long)ca * gs - G.ox0 : lastA;
     }
-    double acc[NP];
+    double acc[NP], acx[NT];
 #pragma unroll
     for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acx[t] = 0.0;
     const int nxs = (pr.x1 - pr.x0 + KC - 1) / KC;
     // the wave's 16-pixel chunks, in order: chunk h of stages it.s0 + wv, + 4, + 8, ...; the
     // loads of the next chunk are issued before the MFMAs of the current one
     constexpr int NH = KC / 16;
-    auto fetch = [&](int st, int h, float (&bv)[NT], float& wf, bool& in) {
+    auto fetch = [&](int st, int h, float (&bv)[NT], float& wf, float& rf, bool& in) {
         const int row = pr.y0 + st / nxs;
         const int x = pr.x0 + (st - (st / nxs) * nxs) * KC + 16 * h + pxl;
         in = x < pr.x1;
         const int xc = in ? x : pr.x1 - 1;
         const long long grow = (long long)(row - G.oy0) * G.ow + xc;
-        wf = weight[pix_off + (long long)row * imW + xc];
+        const long long pix = pix_off + (long long)row * imW + xc;
+        wf = weight[pix];
+        rf = p.rbuf[pix];
 #pragma unroll
         for (int t = 0; t < NT; ++t) bv[t] = Jg[coff[t] + grow];
     };
-    float bc[NT], wc = 0.f;
+    float bc[NT], wc = 0.f, rc = 0.f;
     bool inc = false;
     int st = it.s0 + wv, h = 0;
-    if (st < it.s1) fetch(st, 0, bc, wc, inc);
+    if (st < it.s1) fetch(st, 0, bc, wc, rc, inc);
     while (st < it.s1) {
         int st2 = st, h2 = h + 1;
         if (h2 == NH) {
             h2 = 0;
             st2 += 4;
         }
-        float bn[NT], wn = 0.f;
+        float bn[NT], wn = 0.f, rn = 0.f;
         bool inn = false;
-        if (st2 < it.s1) fetch(st2, h2, bn, wn, inn);
+        if (st2 < it.s1) fetch(st2, h2, bn, wn, rn, inn);
         const double w = inc ? (double)wc : 0.0;
+        const double vx = col == 0 ? (double)rc : (col == 1 ? 1.0 : 0.0);     // [r 1 0 0]
         double b[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) b[t] = (inc && cval[t]) ? (double)bc[t] : 0.0;
@@ -289,19 +296,21 @@ __global__ __launch_bounds__(256) void k_gram4(Plan p, const DPair* __restrict__
 #pragma unroll
             for (int tb = ta; tb < NT; ++tb, ++q)
                 acc[q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b[tb], acc[q], 0, 0, 0);
+            acx[ta] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, vx, acx[ta], 0, 0, 0);
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) bc[t] = bn[t];
         wc = wn;
+        rc = rn;
         inc = inn;
         st = st2;
         h = h2;
     }
     // fold the four blocks of each wave, then the four waves in order
-    __shared__ double red[4][NP * 16];
+    __shared__ double red[4][(NP + NT) * 16];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-        double v = acc[q];
+    for (int q = 0; q < NP + NT; ++q) {
+        double v = q < NP ? acc[q] : acx[q - NP];
         v += __shfl_xor(v, 4, 64);
         v += __shfl_xor(v, 8, 64);
         // lanes with block 0 (lane % 16 < 4) hold D[i][j] at lane 16 i + j
@@ -309,7 +318,7 @@ __global__ __launch_bounds__(256) void k_gram4(Plan p, const DPair* __restrict__
     }
     __syncthreads();
     double* out = p.pair_part + it.out_off;
-    for (int e = (int)threadIdx.x; e < NP * 16; e += 256)
+    for (int e = (int)threadIdx.x; e < (NP + NT) * 16; e += 256)
         out[e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
