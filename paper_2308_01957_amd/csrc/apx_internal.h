@@ -46,6 +46,12 @@ __host__ __device__ constexpr int shape_tw(int s, int P) {
 // the grain of one run.  (Giving each XCD one contiguous eighth of the items shares more,
 // but left XCDs idle when the skipped sub-problems bunched up: 25 % slower LM iterations.)
 // The last n mod (8 XCD_CHUNK) items keep their order.  A bijection on [0, n) for every n.
+// xcd_item(b, n) gives each XCD one contiguous range of items instead, for launches where a
+// group of items that must share an L2 is longer than a run and no item skips.
+__device__ __forceinline__ int xcd_item(int b, int n) {
+    const int x = b % N_XCD, q = n / N_XCD, r = n % N_XCD;
+    return x * q + (x < r ? x : r) + b / N_XCD;
+}
 constexpr int XCD_CHUNK = 8;
 __device__ __forceinline__ int xcd_chunk_item(int b, int n) {
     const int full = n / (N_XCD * XCD_CHUNK);

@@ -34,7 +34,11 @@ __global__ __launch_bounds__(256) void k_pair(Plan p, const DPair* __restrict__ 
     constexpr int NB = TM >= 64 ? 2 : 1;            // accumulators: NB x NB per wave
     __shared__ double As[TM][KC + 1];
     __shared__ double Bs[TM][KC + 1];
-    const PairItem it = items[xcd_chunk_item((int)blockIdx.x, (int)gridDim.x)];
+    // the 64-wide tile pairs of one K-slice (up to 21 for a 350-column group) share its rows
+    // of J in one L2 when each XCD takes a contiguous range of items (in runs of 8 they read
+    // J 3.3x over from HBM); the narrow ones, of cutouts that may skip, go in runs
+    const PairItem it = items[TM >= 64 ? xcd_item((int)blockIdx.x, (int)gridDim.x)
+                                       : xcd_chunk_item((int)blockIdx.x, (int)gridDim.x)];
     const DPair pr = pairs[it.pair];
     if (lm && lm[pr.sub].need_jac == 0) return;
     // by value: the fields live in registers for the whole loop (no reloads through the
