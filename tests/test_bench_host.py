@@ -183,6 +183,32 @@ def test_fft_pairs_by_hand():
     assert bench.FFT_PAIR_FLOP == 2 * 5 * 16384 * 14 + 6 * 16384
 
 
+def test_gram_part_groups_follow_the_library_grouping():
+    """Groups whose J^T W r comes from the 4 x 4-block Gram kernel: the Sersic components of
+    one image with the same box form one group (6 of 7 columns = 42 columns: too wide, its
+    partials stay in the convolution epilogues); a lone Sersic (7 columns) and each point
+    source (its own group) qualify; a component without free parameters forms none."""
+    import numpy as np
+    im = dict(H=40, W=40, psf=np.ones((5, 5)), sub=0)
+    box = (4, 4, 30, 30)
+    comps = [dict(type=0, image=0, box=box, par=list(range(7 * i, 7 * i + 7))) for i in range(6)]
+    comps.append(dict(type=0, image=0, box=(1, 1, 12, 12), par=list(range(42, 49))))
+    comps.append(dict(type=1, image=0, box=(20, 20, 24, 24), par=[49, 50, 51]))
+    comps.append(dict(type=1, image=0, box=(20, 20, 24, 24), par=[52, -1, -1]))
+    comps.append(dict(type=0, image=0, box=(2, 2, 8, 8), par=[-1] * 7))
+    spec = {"images": [im], "subs": [(0, 53)], "comps": comps}
+    got = bench.gram_part_groups(spec)
+    assert [(n, w) for _, w, n in got] == [(7, (0, 0, 14, 14)), (3, (18, 18, 26, 26)), (1, (18, 18, 26, 26))]
+    # the wide group alone: its Gram only (no J^T W r work counted in the pairs class)
+    base = bench.pair_flop_per_sub(dict(spec, comps=comps[:6]))
+    assert np.isclose(base[0], 2 * 30 * 30 * (42 * 43 / 2))
+    # bytes: every entry, the weights of each distinct window once (the two point sources
+    # share theirs), and the residuals of each group whose J^T W r the Gram kernel forms
+    ent, _ = bench.jac_entries_per_sub(spec)
+    assert np.isclose(bench.pair_bytes_per_sub(spec)[0],
+                      4 * (ent[0] + (30 * 30 + 14 * 14 + 8 * 8) + (14 * 14 + 8 * 8 + 8 * 8)))
+
+
 def test_objective_flop_by_hand():
     """Trial objective work of a one-image sub-problem: a Sersic window (-3, -3, 5, 20) cut
     to the extended grid [-1, 11) x [-1, 13) of a 10 x 12 image with P = 3 holds 6 x 14
