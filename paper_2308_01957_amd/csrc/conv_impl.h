@@ -15,7 +15,8 @@
 // Epilogues (template KIND):
 //   CONV_FWD  model + sky, optional model store, FP32 residual store, FP64 partials of
 //             sum w r^2, sum w r, sum w (chi^2 of Eq. chi2, sky gradient, sky-sky entry);
-//   CONV_JCOL Jacobian column store, FP64 partials of sum w r J, sum w J;
+//   CONV_JCOL Jacobian column store, FP64 partials of sum w r J, sum w J (only for jobs
+//             without gram_part: the 4 x 4-block Gram kernel forms them for the others);
 //   CONV_ADJ  input is -2 w r staged from the residual (the adjoint seed of chi^2), or a
 //             given seed (vector-Jacobian product of the render), PSF flipped,
 //             output is dchi2/dS on the extended grid.
@@ -291,8 +292,8 @@ __global__ __launch_bounds__(TH * TW / CV_R) void k_conv(Plan p, const ConvJob* 
 // tile with its P - 1 halo is staged in LDS as for the 2-D kernel; the row pass convolves
 // every staged row with b into a second LDS buffer (the tile rows plus the vertical halo);
 // the column pass convolves that with a, each lane making CV_R consecutive outputs of one
-// column, and the epilogue is that of the 2-D kernel's JCOL (column store, FP64 partials
-// of sum w r J and sum w J per item).  2 (P + P (TH + P - 1) / TH) multiply-adds per output
+// column, and the epilogue is that of the 2-D kernel's JCOL (column store, and the FP64
+// partials of sum w r J and sum w J per item unless the job's gram_part is set).  2 (P + P (TH + P - 1) / TH) multiply-adds per output
 // instead of 2 P^2.
 template <int P>
 __global__ __launch_bounds__(256) void k_conv_sep(Plan p, const ConvJob* __restrict__ jobs,

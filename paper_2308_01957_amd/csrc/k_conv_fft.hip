@@ -13,7 +13,7 @@
 // of the tile's largest values times log2 of the transform size.
 //
 // Same epilogues as the direct kernel: model + chi^2 partials (FP32 objective), Jacobian
-// columns + partials, adjoint.  Images with a higher-resolution PSF (a sub-pixel render
+// columns (+ partials unless the job's gram_part is set), adjoint.  Images with a higher-resolution PSF (a sub-pixel render
 // grid) are never planned here, so the render grid is the pixel grid.
 #include "apx_internal.h"
 
