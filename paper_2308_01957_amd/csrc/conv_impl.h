@@ -365,7 +365,10 @@ __global__ __launch_bounds__(256) void k_conv_sep(Plan p, const ConvJob* __restr
         for (int q = 0; q < CV_R; ++q) part[q] = 0.f;
 #pragma unroll
         for (int V = 0; V < P; ++V) {
-            const float kv = fb[V];
+            // the factor (a scalar load) moves into a VGPR, one v_mov per CV_R FMAs, so that
+            // the FMAs of two waves issue together (as in the 2-D kernel)
+            float kv;
+            asm("v_mov_b32 %0, %1" : "=v"(kv) : "s"(fb[V]));
 #pragma unroll
             for (int q = 0; q < CV_R; ++q) part[q] = fmaf(kv, sw[q + P - 1 - V], part[q]);
         }
@@ -387,7 +390,8 @@ __global__ __launch_bounds__(256) void k_conv_sep(Plan p, const ConvJob* __restr
         for (int q = 0; q < CV_R; ++q) acc[q] = 0.f;
 #pragma unroll
         for (int U = 0; U < P; ++U) {
-            const float ka = fa[U];
+            float ka;
+            asm("v_mov_b32 %0, %1" : "=v"(ka) : "s"(fa[U]));
 #pragma unroll
             for (int q = 0; q < CV_R; ++q) acc[q] = fmaf(ka, sw[q + P - 1 - U], acc[q]);
         }
