@@ -38,6 +38,19 @@ __device__ __forceinline__ cf w16(int m) {
     return {cs[m & 15], -sn[m & 15]};
 }
 
+// a * exp(-2 pi i m / 16).  The quarter turns are a swap and sign changes: a general complex
+// product with the constants 1 and 0 would still cost its multiplies by zero, which IEEE
+// arithmetic does not let the compiler drop (same values either way, up to the sign of zeros).
+// m is a constant once the callers' loops are unrolled, so the branches fold away.
+__device__ __forceinline__ cf mul_w16(cf a, int m) {
+    m &= 15;
+    if (m == 0) return a;
+    if (m == 4) return {a.y, -a.x};
+    if (m == 8) return {-a.x, -a.y};
+    if (m == 12) return {-a.y, a.x};
+    return cmul(a, w16(m));
+}
+
 __host__ __device__ constexpr int bitrev(int v, int bits) {
     int r = 0;
     for (int b = 0; b < bits; ++b) r |= ((v >> b) & 1) << (bits - 1 - b);
@@ -60,8 +73,7 @@ __device__ __forceinline__ void dft_reg(cf (&x)[N]) {
         for (int i = 0; i < N; i += len) {
 #pragma unroll
             for (int k = 0; k < len / 2; ++k) {
-                const cf w = w16(k * (16 / len));
-                const cf u = x[i + k], v = cmul(x[i + k + len / 2], w);
+                const cf u = x[i + k], v = mul_w16(x[i + k + len / 2], k * (16 / len));
                 x[i + k] = cadd(u, v);
                 x[i + k + len / 2] = csub(u, v);
             }
@@ -88,7 +100,7 @@ __device__ __forceinline__ void pass_a(cf* sm, const cf* tw, int dir) {
     for (int n1 = 0; n1 < 16; ++n1) x[n1] = base[(n2 + 8 * n1) * es];
     dft_reg<16>(x);
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) base[(n2 + 8 * k1) * es] = cmul(x[k1], tw[(n2 * k1) & 127]);
+    for (int k1 = 0; k1 < 16; ++k1) base[(n2 + 8 * k1) * es] = k1 == 0 ? x[0] : cmul(x[k1], tw[(n2 * k1) & 127]);
 }
 // Pass B's inputs: thread (line, k1) for two k1 (k1 = t / 128 + 8 h, line = t mod 128); the
 // 8-point DFT over n2 of x[h] then gives X[k1 + 16 k2], k2 < 8.
