@@ -314,7 +314,11 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
     fft2d(sm, tw);
     const float scale = 1.f / (float)(FT * FT);     // real part of the inverse: x / N, imaginary: -y / N
 
-    // ---- epilogues, one half at a time
+    // ---- epilogues, one half at a time.  A thread takes the block's elements
+    // threadIdx.x + k FFT_THREADS in row-major order; it steps their (row, column) by the
+    // quotient and remainder of FFT_THREADS by the block width instead of dividing for each.
+    const long long pix_off = im.pix_off;
+    const int Wc = im.Wc;
     for (int h = 0; h < 2; ++h) {
         const int itx = half_item[h];
         if (itx < 0) break;                          // uniform across the block
@@ -323,38 +327,52 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
         const int oy = jb.out_y0 + it.ty * V, ox = jb.out_x0 + it.tx * V;
         const int yend = min(oy + V, jb.out_y0 + jb.out_h), xend = min(ox + V, jb.out_x0 + jb.out_w);
         const int bh = yend - oy, bw = xend - ox;
+        if (bh <= 0 || bw <= 0) continue;           // uniform; planned blocks are never empty
+        const int sq = FFT_THREADS / bw, sr = FFT_THREADS - sq * bw;
+        int ey = (int)threadIdx.x / bw, ex = (int)threadIdx.x - ey * bw;
+        // offsets within one image or one output plane fit in 32 bits
+        const int orow = oy - jb.out_y0, ocol = ox - jb.out_x0;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         if constexpr (KIND == CONV_FWD) {
             const float sky = (float)p.sky_val[jb.image];
-            for (int e0 = threadIdx.x; e0 < bh * bw; e0 += EPI_B * FFT_THREADS) {
+            const float* wimg = io.data ? io.weight + pix_off : nullptr;
+            const float* dimg = io.data ? io.data + pix_off : nullptr;
+            float* oimg = io.out ? io.out + pix_off : nullptr;
+            float* rimg = p.rbuf + pix_off;
+            while (ey < bh) {
+                int yy[EPI_B], xx[EPI_B];
                 float wv[EPI_B], dv[EPI_B];
 #pragma unroll
+                for (int u = 0; u < EPI_B; ++u) {
+                    yy[u] = ey;
+                    xx[u] = ex;
+                    ex += sr;
+                    ey += sq;
+                    if (ex >= bw) { ex -= bw; ++ey; }
+                }
+#pragma unroll
                 for (int u = 0; u < EPI_B; ++u) {          // the batch's loads first
-                    const int e = e0 + u * FFT_THREADS;
                     wv[u] = dv[u] = 0.f;
-                    if (io.data && e < bh * bw) {
-                        const int dy = e / bw, dx = e - dy * bw;
-                        const long long pix = im.pix_off + (long long)(oy + dy) * im.Wc + (ox + dx);
-                        wv[u] = io.weight[pix];
-                        dv[u] = io.data[pix];
+                    if (wimg && yy[u] < bh) {
+                        const int pix = (oy + yy[u]) * Wc + ox + xx[u];
+                        wv[u] = wimg[pix];
+                        dv[u] = dimg[pix];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < EPI_B; ++u) {
-                    const int e = e0 + u * FFT_THREADS;
-                    if (e >= bh * bw) break;
-                    const int dy = e / bw, dx = e - dy * bw;
-                    const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
+                    if (yy[u] >= bh) break;
+                    const cf s = sm[(yy[u] + 2 * c) * FTP + xx[u] + 2 * c];
                     const float m = (h == 0 ? s.x : -s.y) * scale + sky;
-                    const long long pix = im.pix_off + (long long)(oy + dy) * im.Wc + (ox + dx);
-                    if (io.out) io.out[pix] = m;
-                    if (io.data) {
+                    const int pix = (oy + yy[u]) * Wc + ox + xx[u];
+                    if (oimg) oimg[pix] = m;
+                    if (wimg) {
                         const double w = (double)wv[u];
                         const double rr = (double)dv[u] - (double)m;
                         a0 += w * rr * rr;
                         a1 += w * rr;
                         a2 += w;
-                        p.rbuf[pix] = (float)rr;
+                        rimg[pix] = (float)rr;
                     }
                 }
             }
@@ -371,28 +389,34 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
         } else if constexpr (KIND == CONV_JCOL) {
             float* __restrict__ out = io.out + jb.out_off + (long long)it.ch * jb.out_cs;
             const bool epart = io.weight && !jb.gram_part;   // sum w r J and sum w J here
-            for (int e0 = threadIdx.x; e0 < bh * bw; e0 += EPI_B * FFT_THREADS) {
+            const float* wimg = io.weight + pix_off;
+            const float* rimg = p.rbuf + pix_off;
+            while (ey < bh) {
+                int yy[EPI_B], xx[EPI_B];
                 float wv[EPI_B], rv[EPI_B];
 #pragma unroll
+                for (int u = 0; u < EPI_B; ++u) {
+                    yy[u] = ey;
+                    xx[u] = ex;
+                    ex += sr;
+                    ey += sq;
+                    if (ex >= bw) { ex -= bw; ++ey; }
+                }
+#pragma unroll
                 for (int u = 0; u < EPI_B; ++u) {          // the batch's loads first
-                    const int e = e0 + u * FFT_THREADS;
                     wv[u] = rv[u] = 0.f;
-                    if (epart && e < bh * bw) {
-                        const int dy = e / bw, dx = e - dy * bw;
-                        const long long pix = im.pix_off + (long long)(oy + dy) * im.Wc + (ox + dx);
-                        wv[u] = io.weight[pix];
-                        rv[u] = p.rbuf[pix];
+                    if (epart && yy[u] < bh) {
+                        const int pix = (oy + yy[u]) * Wc + ox + xx[u];
+                        wv[u] = wimg[pix];
+                        rv[u] = rimg[pix];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < EPI_B; ++u) {
-                    const int e = e0 + u * FFT_THREADS;
-                    if (e >= bh * bw) break;
-                    const int dy = e / bw, dx = e - dy * bw;
-                    const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
+                    if (yy[u] >= bh) break;
+                    const cf s = sm[(yy[u] + 2 * c) * FTP + xx[u] + 2 * c];
                     const float v = (h == 0 ? s.x : -s.y) * scale;
-                    const int y = oy + dy, x = ox + dx;
-                    out[(long long)(y - jb.out_y0) * jb.out_w + (x - jb.out_x0)] = v;
+                    out[(orow + yy[u]) * jb.out_w + ocol + xx[u]] = v;
                     if (epart) {
                         const double wj = (double)wv[u] * (double)v;
                         a0 += wj * (double)rv[u];
@@ -410,11 +434,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob*
             }
         } else {
             float* __restrict__ out = io.out + jb.out_off;
-            for (int e = threadIdx.x; e < bh * bw; e += FFT_THREADS) {
-                const int dy = e / bw, dx = e - dy * bw;
-                const cf s = sm[(dy + 2 * c) * FTP + dx + 2 * c];
-                out[(long long)(oy + dy - jb.out_y0) * jb.out_w + (ox + dx - jb.out_x0)] =
-                    (h == 0 ? s.x : -s.y) * scale;
+            while (ey < bh) {
+                const cf s = sm[(ey + 2 * c) * FTP + ex + 2 * c];
+                out[(orow + ey) * jb.out_w + ocol + ex] = (h == 0 ? s.x : -s.y) * scale;
+                ex += sr;
+                ey += sq;
+                if (ex >= bw) { ex -= bw; ++ey; }
             }
         }
     }
