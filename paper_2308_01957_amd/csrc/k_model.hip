@@ -375,6 +375,7 @@ __device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst&
     const double bx = im.aff[2] * c.cs_d + im.aff[5] * c.sn_d;
     const double ay = (-im.aff[1] * c.sn_d + im.aff[4] * c.cs_d) * c.iq_d;
     const double by = (-im.aff[2] * c.sn_d + im.aff[5] * c.cs_d) * c.iq_d;
+    const Poly64Regs rg = poly64_regs(c);
     double sum = 0.0;
     for (int ky = 0; ky < p.s; ++ky) {
         const double oy = p.node_od[ky];
@@ -382,7 +383,7 @@ __device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst&
         double row = 0.0;
         for (int kx = 0; kx < p.s; ++kx) {
             const double ox = p.node_od[kx];
-            row += p.node_wd[kx] * sersic_I64_r(c, fma(ox, ax, xr), fma(ox, ay, yr), tab);
+            row += p.node_wd[kx] * sersic_I64_r(c, fma(ox, ax, xr), fma(ox, ay, yr), tab, rg);
         }
         sum += p.node_wd[ky] * row;
     }

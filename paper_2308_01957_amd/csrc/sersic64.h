@@ -71,35 +71,67 @@ __device__ __forceinline__ double log2_d(double x) {
 //              intervals that cut [1/2, 1);
 //   [128, 192) -log2(r_j).
 //   2^x: n = rint(64 x), f = x - n/64 (exact, |f| <= 1/128), 2^x = 2^(n >> 6) 2^((n & 63)/64)
-//   e^(f ln 2), the last by its Taylor series to degree 5 (next term < 4e-17).
+//   e^(f ln 2), the last by its Taylor series to degree 5 (next term < 4e-17).  x is first
+//   clamped to [-1100, 1100] (results underflow to 0 / overflow to inf) by a max and a min,
+//   which map a NaN argument to -1100; the callers' arguments are finite (the profile's
+//   constants are checked before any pixel is rendered).
 //   log2(x) = e + log2(m) for x = m 2^e, m in [1/2, 1): with j the interval of m (the top
 //   six mantissa bits), u = m r_j - 1 (one rounding, |u| < 0.0079) and log2(m) = -log2(r_j)
 //   + ln(1 + u) log2(e), ln(1 + u) by its series to u^7 (next term < 2e-18).
-__device__ __forceinline__ double exp2_t(double x, const double* __restrict__ tab) {
+//
+// A VALU instruction reads at most one SGPR operand, and the compiler turns FMAs into the
+// two-address v_fmac_f64 with a fresh copy of a constant addend at every node.  The node
+// loop's FMAs are therefore written out (fma_vvs, fma_svv: the operand kinds in order) with
+// their constants in SGPRs or, where an FMA needs two, in the VGPR copies of Poly64Regs,
+// which are made once per component before the loop.  Same operations in the same order as
+// the plain fma() calls: the same results.
+constexpr double EXP2_C5 = 0.6931471805599453094 * 0.6931471805599453094 * 0.6931471805599453094 *
+                           0.6931471805599453094 * 0.6931471805599453094 / 120.0;
+constexpr double EXP2_C4 = 0.6931471805599453094 * 0.6931471805599453094 * 0.6931471805599453094 *
+                           0.6931471805599453094 / 24.0;
+struct Poly64Regs { double e4, l6, h, A; };            // EXP2_C4, -1/6, the component's h and A
+__device__ __forceinline__ double vcopy64(double s) {
+    double v;
+    asm("v_mov_b64 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+__device__ __forceinline__ Poly64Regs poly64_regs(const CompConst& c) {
+    return {vcopy64(EXP2_C4), vcopy64(-1.0 / 6.0), vcopy64(c.h_d), vcopy64(c.A_d)};
+}
+__device__ __forceinline__ double fma_vvs(double a, double b, double cs) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(cs));
+    return r;
+}
+__device__ __forceinline__ double fma_svv(double as, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "s"(as), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ double exp2_t(double x, const double* __restrict__ tab, const Poly64Regs& rg) {
     constexpr double L = 0.6931471805599453094;
-    x = x < -1100.0 ? -1100.0 : (x > 1100.0 ? 1100.0 : x);
+    x = __builtin_fmin(__builtin_fmax(x, -1100.0), 1100.0);
     const double nd = rint(x * 64.0);
     const double f = fma(nd, -0.015625, x);
     const int n = (int)nd;
-    double p = L * L * L * L * L / 120.0;
-    p = fma(p, f, L * L * L * L / 24.0);
-    p = fma(p, f, L * L * L / 6.0);
-    p = fma(p, f, L * L / 2.0);
-    p = fma(p, f, L);
+    double p = fma_svv(EXP2_C5, f, rg.e4);
+    p = fma_vvs(p, f, L * L * L / 6.0);
+    p = fma_vvs(p, f, L * L / 2.0);
+    p = fma_vvs(p, f, L);
     p = fma(p, f, 1.0);
     return ldexp(tab[n & 63] * p, n >> 6);
 }
 
-__device__ __forceinline__ double log2_t(double x, const double* __restrict__ tab) {
+__device__ __forceinline__ double log2_t(double x, const double* __restrict__ tab, const Poly64Regs& rg) {
     const double m = __builtin_amdgcn_frexp_mant(x);          // [1/2, 1)
     const int e = __builtin_amdgcn_frexp_exp(x);
     const int j = (__double2hiint(m) >> 14) & 63;
     const double u = fma(m, tab[64 + j], -1.0);
-    double q = 1.0 / 7.0;
-    q = fma(q, u, -1.0 / 6.0);
-    q = fma(q, u, 1.0 / 5.0);
-    q = fma(q, u, -1.0 / 4.0);
-    q = fma(q, u, 1.0 / 3.0);
+    double q = fma_svv(1.0 / 7.0, u, rg.l6);
+    q = fma_vvs(q, u, 1.0 / 5.0);
+    q = fma_vvs(q, u, -1.0 / 4.0);
+    q = fma_vvs(q, u, 1.0 / 3.0);
     q = fma(q, u, -0.5);
     q = fma(q, u, 1.0);
     return fma(q * u, 1.4426950408889634074, tab[128 + j] + (double)e);
@@ -107,17 +139,17 @@ __device__ __forceinline__ double log2_t(double x, const double* __restrict__ ta
 
 // I at a point given in the component's frame (xp along the major axis, yq = yp / q).
 __device__ __forceinline__ double sersic_I64_r(const CompConst& c, double xp, double yq,
-                                               const double* __restrict__ tab) {
+                                               const double* __restrict__ tab, const Poly64Regs& rg) {
     const double R2 = fmax(xp * xp + yq * yq, 1e-12);
-    const double t = exp2_t(c.g_d * log2_t(R2, tab) - c.h_d, tab);
-    return exp2_t(c.A_d - c.B_d * t, tab);
+    const double t = exp2_t(fma(c.g_d, log2_t(R2, tab, rg), -rg.h), tab, rg);
+    return exp2_t(fma(-c.B_d, t, rg.A), tab, rg);
 }
 
 __device__ __forceinline__ double sersic_I64_t(const CompConst& c, double dx, double dy,
                                                const double* __restrict__ tab) {
     const double xp = dx * c.cs_d + dy * c.sn_d;
     const double yq = (-dx * c.sn_d + dy * c.cs_d) * c.iq_d;
-    return sersic_I64_r(c, xp, yq, tab);
+    return sersic_I64_r(c, xp, yq, tab, poly64_regs(c));
 }
 
 __device__ __forceinline__ double sersic_I64(const CompConst& c, double dx, double dy) {
