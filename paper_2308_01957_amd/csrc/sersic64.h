@@ -71,10 +71,12 @@ __device__ __forceinline__ double log2_d(double x) {
 //              intervals that cut [1/2, 1);
 //   [128, 192) -log2(r_j).
 //   2^x: n = rint(64 x), f = x - n/64 (exact, |f| <= 1/128), 2^x = 2^(n >> 6) 2^((n & 63)/64)
-//   e^(f ln 2), the last by its Taylor series to degree 5 (next term < 4e-17).  x is first
-//   clamped to [-1100, 1100] (results underflow to 0 / overflow to inf) by a max and a min,
-//   which map a NaN argument to -1100; the callers' arguments are finite (the profile's
-//   constants are checked before any pixel is rendered).
+//   e^(f ln 2), the last by its Taylor series to degree 5 (next term < 4e-17).  With CLAMP, x
+//   is first clamped to [-1100, 1100] (results underflow to 0 / overflow to inf) by a max and
+//   a min, which map a NaN argument to -1100; the callers' arguments are finite (the
+//   profile's constants are checked before any pixel is rendered).  Without it |x| must stay
+//   below 2^24 (n fits an int): the argument g log2(R^2) - h of t does, as |g| <= 1/0.72 and
+//   |h| < 37 for a valid component and |log2 R^2| <= 1024 (R^2 finite, floored at 1e-12).
 //   log2(x) = e + log2(m) for x = m 2^e, m in [1/2, 1): with j the interval of m (the top
 //   six mantissa bits), u = m r_j - 1 (one rounding, |u| < 0.0079) and log2(m) = -log2(r_j)
 //   + ln(1 + u) log2(e), ln(1 + u) by its series to u^7 (next term < 2e-18).
@@ -109,9 +111,10 @@ __device__ __forceinline__ double fma_svv(double as, double b, double c) {
     return r;
 }
 
+template <bool CLAMP>
 __device__ __forceinline__ double exp2_t(double x, const double* __restrict__ tab, const Poly64Regs& rg) {
     constexpr double L = 0.6931471805599453094;
-    x = __builtin_fmin(__builtin_fmax(x, -1100.0), 1100.0);
+    if constexpr (CLAMP) x = __builtin_fmin(__builtin_fmax(x, -1100.0), 1100.0);
     const double nd = rint(x * 64.0);
     const double f = fma(nd, -0.015625, x);
     const int n = (int)nd;
@@ -141,8 +144,8 @@ __device__ __forceinline__ double log2_t(double x, const double* __restrict__ ta
 __device__ __forceinline__ double sersic_I64_r(const CompConst& c, double xp, double yq,
                                                const double* __restrict__ tab, const Poly64Regs& rg) {
     const double R2 = fmax(xp * xp + yq * yq, 1e-12);
-    const double t = exp2_t(fma(c.g_d, log2_t(R2, tab, rg), -rg.h), tab, rg);
-    return exp2_t(fma(-c.B_d, t, rg.A), tab, rg);
+    const double t = exp2_t<false>(fma(c.g_d, log2_t(R2, tab, rg), -rg.h), tab, rg);
+    return exp2_t<true>(fma(-c.B_d, t, rg.A), tab, rg);
 }
 
 __device__ __forceinline__ double sersic_I64_t(const CompConst& c, double dx, double dy,
