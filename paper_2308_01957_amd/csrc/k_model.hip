@@ -377,6 +377,22 @@ __device__ __forceinline__ double sersic_pixel64(const Plan& p, const CompConst&
     const double by = (-im.aff[2] * c.sn_d + im.aff[5] * c.cs_d) * c.iq_d;
     const Poly64Regs rg = poly64_regs(c);
     double sum = 0.0;
+    if (p.s == 3) {
+        // the usual 3 x 3 rule, unrolled with its nodes and weights loaded once (the same
+        // operations in the same order as the loop below)
+        const double od[3] = {p.node_od[0], p.node_od[1], p.node_od[2]};
+        const double wd[3] = {p.node_wd[0], p.node_wd[1], p.node_wd[2]};
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            const double xr = fma(od[ky], bx, xp0), yr = fma(od[ky], by, yq0);
+            double row = 0.0;
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx)
+                row += wd[kx] * sersic_I64_r(c, fma(od[kx], ax, xr), fma(od[kx], ay, yr), tab, rg);
+            sum += wd[ky] * row;
+        }
+        return sum;
+    }
     for (int ky = 0; ky < p.s; ++ky) {
         const double oy = p.node_od[ky];
         const double xr = fma(oy, bx, xp0), yr = fma(oy, by, yq0);
