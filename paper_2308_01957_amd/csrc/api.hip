@@ -1033,7 +1033,10 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         return gr.type != GROUP_PSF && gr.oh > 0 && gr.ow > 0 && gr.ncols > 0 && gr.ncols <= 4 * GRAM4_MAX_T;
     };
 
-    // convolution jobs and items, sorted by (PSF size, tile shape): one launch per pair.
+    // convolution jobs and items, sorted by (PSF size, tile shape): one launch per pair,
+    // except that the FFT-tile items of every PSF size form one range and one launch (the
+    // FFT kernel takes P at run time, so one grid keeps the chip full to its end instead of
+    // leaving a partly filled last round per PSF size).
     // Each job takes the tile shape of least estimated cost (choose_shape).
     // In FFT mode, jobs of the FP32 kinds on images with spectra and outputs of at least
     // 32 x 32 take the FFT shape; in automatic mode, such a job (on an image with a fixed,
@@ -1066,7 +1069,10 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
         }
         std::vector<int> order(jobs.size());
         for (size_t i = 0; i < jobs.size(); ++i) order[i] = (int)i;
+        // FFT jobs sort after every direct and two-pass job, by PSF size among themselves
+        auto fft_key = [&](int a) { return jobs[a].shape == SHAPE_FFT ? 1 : 0; };
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            if (fft_key(a) != fft_key(b)) return fft_key(a) < fft_key(b);
             return jobP[a] != jobP[b] ? jobP[a] < jobP[b] : jobs[a].shape < jobs[b].shape;
         });
         if (job_item_begin) job_item_begin->assign(jobs.size(), 0);
@@ -1081,10 +1087,12 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
                     for (int tx = 0; tx < nx; ++tx) items.push_back(ConvItem{j, ch, ty, tx});
             const int cnt = (int)items.size() - b;
             if (cnt == 0) continue;
-            if (!ranges.empty() && ranges.back().P == jobP[j] && ranges.back().shape == jb.shape)
+            const bool same = !ranges.empty() && ranges.back().shape == jb.shape &&
+                              (jb.shape == SHAPE_FFT || ranges.back().P == jobP[j]);
+            if (same)
                 ranges.back().count += cnt;
             else
-                ranges.push_back(PRange{jobP[j], jb.shape, b, cnt, 0, 0});
+                ranges.push_back(PRange{jb.shape == SHAPE_FFT ? 0 : jobP[j], jb.shape, b, cnt, 0, 0});
         }
         if (!pairs) return;
         for (PRange& r : ranges) {
