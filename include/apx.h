@@ -265,8 +265,9 @@ apx_status apx_ctx_set_stream(apx_ctx* ctx, void* hip_stream);
 
 /* Output tile shapes of the direct convolution (§2.1.3).  Every convolution job (an image,
  * or the Jacobian columns of one window) is cut into workgroup tiles of one of four shapes:
- * 0 = 32 x 64, 1 = 16 x 64, 2 = 32 x 32, 3 = 16 x 32 output pixels; a job takes the shape of
- * least estimated cost (tiles needed x cost of one tile) for its output size.  The policy
+ * 0 = 32 x 64, 1 = 16 x 64, 2 = 32 x 32, 3 = 16 x 32 output pixels; the direct jobs of one
+ * kind at one PSF size take the one shape of least estimated cost (tiles needed x cost of
+ * one tile, summed over those jobs), so that each PSF size is one launch.  The policy
  * holds for problems created after the call:
  *   APX_TILES_AUTOTUNE (default): on a device context, the first problem that needs a
  *     convolution kernel at a PSF size times all four shapes of it on a synthetic
