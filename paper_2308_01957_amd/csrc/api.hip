@@ -101,7 +101,7 @@ struct apx_problem {
     std::vector<ConvJob> fwd_jobs, jcol_jobs, adj_jobs, psf_jobs;
     std::vector<ConvItem> fwd_items, jcol_items, adj_items, psf_items;
     std::vector<PRange> fwd_ranges, jcol_ranges, adj_ranges, psf_ranges;
-    std::vector<int2> fwd_pairs, jcol_pairs, adj_pairs;    // FFT mode: items per transform
+    std::vector<int4> fwd_pairs, jcol_pairs, adj_pairs;    // FFT mode: items per transform (+ sub-problem)
     long long n_fft_spec = 0;                     // FFT mode: stamp spectra (complex entries)
     int n_fft_images = 0;
     bool fft_fixed_ready = false;                 // spectra of fixed stamps computed
@@ -1056,7 +1056,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
     auto add_items = [&](int kind, std::vector<ConvJob>& jobs, std::vector<ConvItem>& items,
                          std::vector<PRange>& ranges, const std::vector<int>& jobP,
                          const std::vector<int>& nch, std::vector<int>* job_item_begin,
-                         std::vector<int2>* pairs) {
+                         std::vector<int4>* pairs) {
         const int key = kind == CONV_JCOL ? TUNE_JCOL : kind == CONV_ADJ ? TUNE_ADJ
                       : P->objective == APX_OBJECTIVE_FP64 ? TUNE_FWD64 : TUNE_FWD32;
         for (size_t j = 0; j < jobs.size(); ++j) {
@@ -1125,7 +1125,7 @@ static apx_status build_plan(apx_problem* P, const apx_problem_desc* d) {
             for (int i = r.begin; i < r.begin + r.count;) {
                 const bool two = i + 1 < r.begin + r.count &&
                                  jobs[items[i].job].image == jobs[items[i + 1].job].image;
-                pairs->push_back(make_int2(i, two ? i + 1 : -1));
+                pairs->push_back(make_int4(i, two ? i + 1 : -1, P->images[jobs[items[i].job].image].sub, 0));
                 i += two ? 2 : 1;
             }
             r.pair_count = (int)pairs->size() - r.pair_begin;
@@ -1589,9 +1589,9 @@ static void layout(apx_problem* P) {
     ws_take<double>(P, "psf64", P->n_psf);
     ws_take<float2>(P, "fft_spec", P->n_fft_spec);
     ws_take<float>(P, "fft_tw", P->fft_tw.size());
-    ws_take<int2>(P, "fwd_pairs", P->fwd_pairs.size());
-    ws_take<int2>(P, "jcol_pairs", P->jcol_pairs.size());
-    ws_take<int2>(P, "adj_pairs", P->adj_pairs.size());
+    ws_take<int4>(P, "fwd_pairs", P->fwd_pairs.size());
+    ws_take<int4>(P, "jcol_pairs", P->jcol_pairs.size());
+    ws_take<int4>(P, "adj_pairs", P->adj_pairs.size());
     ws_take<double>(P, "grad_part", P->n_gradpart);
     ws_take<double>(P, "asrc", P->asrc_img + 3LL * P->n_images);
     ws_take<double>(P, "A", P->a_total);
@@ -2045,7 +2045,7 @@ static apx_status run_conv(apx_problem* P, int kind, const ConvIO& io) {
             continue;
         }
         if (r.shape == SHAPE_FFT) {
-            L.pairs = wsp<int2>(P, pn);
+            L.pairs = wsp<int4>(P, pn);
             hipError_t e = launch_conv_fft(p, kind, L, io, st);
             if (e != hipSuccess) return fail(P->ctx, APX_E_HIP, std::string("FFT conv launch: ") + hipGetErrorString(e));
             continue;

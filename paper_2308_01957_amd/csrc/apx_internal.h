@@ -342,7 +342,7 @@ struct ConvLaunch {
     const ConvJob* jobs;
     const ConvItem* items;
     int item_begin, item_count, P, shape;
-    const int2* pairs;        // FFT mode: items sharing one transform (second -1 = none)
+    const int4* pairs;        // FFT mode: items sharing one transform (second -1 = none), their sub-problem
     int pair_begin, pair_count;
 };
 struct ConvIO {

@@ -197,20 +197,22 @@ __device__ __forceinline__ double fft_block_sum(double v, double* red) {
 template <int KIND>
 __global__ __launch_bounds__(FFT_THREADS) void k_conv_fft(Plan p, const ConvJob* __restrict__ jobs,
                                                           const ConvItem* __restrict__ items,
-                                                          const int2* __restrict__ pairs, int pair_begin,
+                                                          const int4* __restrict__ pairs, int pair_begin,
                                                           ConvIO io) {
     __shared__ cf sm[FT * FTP];
     __shared__ cf tw[FT];
     __shared__ double red[FFT_THREADS / 64];
-    const int2 pr = pairs[pair_begin + xcd_chunk_item((int)blockIdx.x, (int)gridDim.x)];
+    // the pair carries its sub-problem, so a pair whose sub-problem skips this phase exits
+    // after two dependent loads instead of five (items, job, image first)
+    const int4 pr = pairs[pair_begin + xcd_chunk_item((int)blockIdx.x, (int)gridDim.x)];
+    if (io.skip_mode == 1) {
+        if (p.lmf[pr.z].chol_done == 0 || p.lmf[pr.z].trial_bad != 0) return;
+    } else if (io.skip_mode == 2) {
+        if (io.lm[pr.z].need_jac == 0) return;
+    }
     const int half_item[2] = {pr.x, pr.y};
     const ConvJob jb0 = jobs[items[pr.x].job];
     const DImage& im = p.images[jb0.image];
-    if (io.skip_mode == 1) {
-        if (p.lmf[im.sub].chol_done == 0 || p.lmf[im.sub].trial_bad != 0) return;
-    } else if (io.skip_mode == 2) {
-        if (io.lm[im.sub].need_jac == 0) return;
-    }
     load_twiddles(p, tw);
     const int P = im.P, c = (P - 1) / 2, V = FT - P + 1;
 
