@@ -563,9 +563,11 @@ def run_cutouts(args, torch, apx, synth):
           f"{ent_sep / 1e9:.2f} G entries by two passes, {len(fft_jobs)} jobs on FFT tiles)",
           file=sys.stderr, flush=True)
 
-    # warm-up: captures the iteration graph with HIP events around the trial render and the
-    # Jacobian convolutions (the classes that can be the largest)
-    jclasses = ["render", "conv_jcol", "conv_sep", "conv_fft"]
+    # warm-up: captures the iteration graph with HIP events around the two classes that can
+    # be the largest (the trial render, and the FFT-tile or the 2-D Jacobian convolutions);
+    # every event mark costs the replay ~12 us, so the other classes are timed in a second
+    # graph pass below and their marks stay out of the timed region
+    jclasses = ["render", "conv_fft" if mode in (1, 3) else "conv_jcol"]
     th, st = prob.lm_init(spec["theta_init"], dd, ww)
     prob.set_timing(True, classes=jclasses)
     prob.lm_run(max(1, args.warmup), dd, ww, th, st, use_graph=True)
@@ -587,15 +589,6 @@ def run_cutouts(args, torch, apx, synth):
     batched = n_sub * args.steps / t_graph
     print(f"[bench] {args.steps} batched iterations in {t_graph * 1e3:.1f} ms (graph = eager: {same})",
           file=sys.stderr, flush=True)
-    jcol_ms, jcol_launches = kt["conv_jcol"]
-    sep_ms, _ = kt["conv_sep"]
-    fft_ms, _ = kt["conv_fft"]
-    achieved = flop_jac / (jcol_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
-
-
-    if mode == 1:            # FFT mode: the Jacobian runs on FFT tiles (direct-equivalent rate)
-        jcol_ms, flop_jac = fft_ms, flop_fft
-        achieved = flop_jac / (jcol_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
 
     # eager batched, the same iterations
     th2, st2 = prob.lm_init(spec["theta_init"], dd, ww)
@@ -607,7 +600,7 @@ def run_cutouts(args, torch, apx, synth):
 
     # the other kernel classes, from a second instrumented graph pass over the same
     # iterations (their event marks stay out of the timed replays)
-    oclasses = ["conv_fwd", "pairs"]
+    oclasses = ["conv_fwd", "pairs"] + [c for c in ("conv_jcol", "conv_sep", "conv_fft") if c not in jclasses]
     prob.set_timing(True, classes=oclasses)
     prob.lm_init(spec["theta_init"], dd, ww, theta_out=th2, state_out=st2)
     prob.lm_run(1, dd, ww, th2, st2, use_graph=True)            # captures with the new marks
@@ -617,6 +610,14 @@ def run_cutouts(args, torch, apx, synth):
     prob.lm_run(args.steps, dd, ww, th2, st2, use_graph=True)
     ko = prob.timing()
     prob.set_timing(False)
+    kk = {c: (kt[c] if c in jclasses else ko[c]) for c in kt}
+    jcol_ms, jcol_launches = kk["conv_jcol"]
+    sep_ms, _ = kk["conv_sep"]
+    fft_ms, _ = kk["conv_fft"]
+    achieved = flop_jac / (jcol_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
+    if mode == 1:            # FFT mode: the Jacobian runs on FFT tiles (direct-equivalent rate)
+        jcol_ms, flop_jac = fft_ms, flop_fft
+        achieved = flop_jac / (jcol_ms * 1e-3) / 1e12 if jcol_ms > 0 else 0.0
 
     def cls_roof(flop, ms, peak, kernel, bound="alu", timed=False):
         ach = flop / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
@@ -627,13 +628,14 @@ def run_cutouts(args, torch, apx, synth):
         "conv_jcol": cls_roof(flop_jac, jcol_ms, PEAK_FP32_VALU_TFLOPS,
                               "k_conv<P,JCOL> (2-D Jacobian-column convolutions: all PSF sizes and tile shapes "
                               "of a phase, cutouts whose stamp is not rank one and whose job stays on direct "
-                              "tiles)", timed=True),
+                              "tiles)", timed="conv_jcol" in jclasses or mode == 1),
         "render": cls_roof(flop_ren, kt["render"][0], PEAK_FP64_TFLOPS,
                            "k_render64 (FP64 trial render; %g FLOP per Sersic node)" % RENDER64_FLOP_PER_NODE,
                            timed=True),
         "conv_fft": cls_roof(pairs_fft * FFT_PAIR_FLOP, fft_ms, PEAK_FP32_VALU_TFLOPS,
                              "k_conv_fft<JCOL> (FFT-tile Jacobian convolutions; 5 N log2 N per 128^2 "
-                             "transform, two transforms and the spectrum product per item pair)", timed=True),
+                             "transform, two transforms and the spectrum product per item pair)",
+                             timed="conv_fft" in jclasses),
         "conv_fwd": cls_roof(flop_fwd, ko["conv_fwd"][0], PEAK_FP64_TFLOPS, "k_conv<P,FWD,double> (FP64 objective)"),
         "pairs": dict(pair_roof(flop_pair, byte_pair, ko["pairs"][0], "k_gram4 / k_pair (FP64 MFMA)"),
                       ms_per_step=ko["pairs"][0] / max(1, args.steps), traffic=None, timed_region=False),
@@ -641,9 +643,11 @@ def run_cutouts(args, torch, apx, synth):
     per_class["conv_jcol"].update({"ms_per_phase": jcol_ms / max(1, args.steps),
                                    "flop_per_phase": flop_jac / max(1, args.steps), "launch_groups": jcol_launches})
     per_class["conv_fft"].update({"pairs_per_phase": pairs_fft / max(1, args.steps), "jobs": len(fft_jobs)})
-    # the dominant class: the largest of those timed in the timed region (every other class
-    # takes less time)
-    dom = max(("conv_jcol", "render", "conv_fft"), key=lambda k: per_class[k]["ms_per_step"])
+    # the dominant class: the larger of the two timed in the timed region; the record says
+    # whether every class timed in the second pass took less time
+    dom = max((c for c in ("conv_jcol", "render", "conv_fft") if c in jclasses),
+              key=lambda k: per_class[k]["ms_per_step"])
+    dom_is_largest = all(v["ms_per_step"] <= per_class[dom]["ms_per_step"] for v in per_class.values())
     if mode == 1:            # FFT mode reports the Jacobian's direct-equivalent rate
         dom = "conv_jcol"
 
@@ -724,6 +728,7 @@ def run_cutouts(args, torch, apx, synth):
         per_class["conv_fft"]["traffic_unit"] = "bytes/step"
     roof = dict(per_class[dom])
     roof["class"] = dom
+    roof["largest_class"] = dom_is_largest
     rec = {
         "metric": "LM iters/s & Mpix/s rendered (fused adjoint+batched vs plain) at oracle rtol",
         "value": batched, "unit": "cutout LM it/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
