@@ -205,3 +205,17 @@ def test_tile_cost_table_can_be_set_and_read_back(apx):
         assert lib.apx_ctx_tile_cost(ctx, 1, 25, out) == apx.APX_OK and list(out) == [3.0, 2.5, 2.0, 1.25]
     finally:
         lib.apx_ctx_destroy(ctx)
+
+
+def test_direct_jobs_of_one_psf_size_share_one_tile_shape(apx):
+    """A batch of cutouts of 32-256 px at one PSF size: every direct job of a kind takes the
+    one shape of least cost summed over the batch (one launch per PSF size), although the
+    operation-count model would give the small cutouts narrower tiles one by one."""
+    spec = synth.cutouts(seed_id=7, n_cutouts=40, p_range=(21, 21))
+    assert len({np.asarray(im["psf"]).shape[0] for im in spec["images"]}) == 1
+    pl = apx.Plan(dict(spec, conv_mode=apx.CONV_DIRECT_2D), tiles=apx.TILES_MODEL)
+    for kind in range(3):
+        counts = pl.tile_shapes(kind)
+        assert sum(1 for c in counts[:4] if c > 0) == 1, (kind, counts)
+    assert sum(pl.tile_shapes(0)[:4]) == len(spec["images"])
+    pl.close()
