@@ -105,6 +105,7 @@ struct apx_problem {
     long long n_fft_spec = 0;                     // FFT mode: stamp spectra (complex entries)
     int n_fft_images = 0;
     bool fft_fixed_ready = false;                 // spectra of fixed stamps computed
+    int fft_live = -1;                            // images with spectra of live stamps (-1: not counted yet)
     std::vector<float> fft_tw;                    // exp(-2 pi i m / FFT_T) as (re, im)
     long long n_live = 0;                         // floats of live-PSF stamps (3 P^2 each)
     bool has_live_cols = false;                   // some live PSF has a free parameter
@@ -2082,7 +2083,12 @@ static apx_status prep(apx_problem* P, const double* theta, int lm_trial, int sk
     {
         TimeScope ts(P, APX_TIME_PREP);
         HIPCHK(launch_prep(p, theta, lm_trial, st));
-        if (P->n_fft_images > 0) {               // stamp spectra: live stamps per theta, fixed once
+        if (P->fft_live < 0) {
+            P->fft_live = 0;
+            for (const DImage& im : P->images) P->fft_live += im.fft_off >= 0 && im.live ? 1 : 0;
+        }
+        // stamp spectra: live stamps per theta, fixed once (no launch once only fixed ones remain)
+        if (P->n_fft_images > 0 && (!P->fft_fixed_ready || P->fft_live > 0)) {
             HIPCHK(launch_fft_stamps(p, P->fft_fixed_ready ? 1 : 0, st));
             P->fft_fixed_ready = true;
         }
